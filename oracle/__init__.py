@@ -1,0 +1,272 @@
+"""FP64 CPU oracle of the probe update and probe query (TEST INFRASTRUCTURE).
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this package.  It wraps ``liborc.so`` (built from
+``irf_oracle.c`` by ``oracle/build.py``) with ctypes and keeps all state in
+numpy float64 arrays owned by Python.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional
+
+import numpy as np
+
+from . import build as _build
+
+OFF, SLEEPING, NEWLY_AWAKE, NEWLY_VIGILANT, AWAKE, VIGILANT = 0, 1, 2, 3, 4, 5
+F_GRAZE, F_TIE, F_NEARMISS, F_EDGEON, F_SHADOW = 1, 2, 4, 8, 16
+CAGE = 16
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        _lib = C.CDLL(_build.LIB)
+        _declare(_lib)
+    return _lib
+
+
+class Hit(C.Structure):
+    _fields_ = [("tri", C.c_int32), ("flags", C.c_int32), ("t", C.c_double), ("bmin", C.c_double)]
+
+
+class RayRecord(C.Structure):
+    _fields_ = [("tri", C.c_int32), ("flags", C.c_int32), ("t", C.c_double), ("rgb", C.c_double * 3),
+                ("d", C.c_double), ("vis", C.c_uint32), ("n_cage", C.c_int32),
+                ("cage", C.c_int32 * CAGE), ("kappa", C.c_double * 3)]
+
+
+RECORD_DTYPE = np.dtype([("tri", np.int32), ("flags", np.int32), ("t", np.float64), ("rgb", np.float64, 3),
+                         ("d", np.float64), ("vis", np.uint32), ("n_cage", np.int32),
+                         ("cage", np.int32, CAGE), ("kappa", np.float64, 3)], align=True)
+assert RECORD_DTYPE.itemsize == C.sizeof(RayRecord)
+HIT_DTYPE = np.dtype([("tri", np.int32), ("flags", np.int32), ("t", np.float64), ("bmin", np.float64)], align=True)
+
+
+class Lights(C.Structure):
+    _fields_ = [("n_dir", C.c_int32), ("dir_to_light", C.c_void_p), ("dir_irradiance", C.c_void_p),
+                ("n_point", C.c_int32), ("point_pos", C.c_void_p), ("point_intensity", C.c_void_p),
+                ("sky", C.c_float * 3)]
+
+
+class VolumeStruct(C.Structure):
+    _fields_ = [("origin", C.c_float * 3), ("spacing", C.c_float * 3), ("counts", C.c_int32 * 3),
+                ("rays", C.c_int32), ("alpha_irr", C.c_float), ("alpha_dist", C.c_float),
+                ("cos_power", C.c_float), ("bias", C.c_float), ("dmax", C.c_float), ("cheb_power", C.c_int32),
+                ("irr", C.c_void_p), ("dist", C.c_void_p), ("states", C.c_void_p), ("offsets", C.c_void_p)]
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _declare(L):
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_void_p
+    L.orc_scene_create.restype = vp
+    L.orc_scene_create.argtypes = [vp, i64, vp, i64, vp, vp, vp, vp, i32]
+    L.orc_scene_free.argtypes = [vp]
+    L.orc_scene_bvh_nodes.restype = i64
+    L.orc_scene_bvh_nodes.argtypes = [vp]
+    for name in ("orc_oct_encode", "orc_oct_decode"):
+        getattr(L, name).argtypes = [dp, dp]
+    L.orc_texel_direction.argtypes = [i32, i32, i32, dp]
+    L.orc_border_source.argtypes = [i32, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.orc_sample_tile.argtypes = [dp, i32, i32, dp, dp]
+    L.orc_sf_direction.argtypes = [i32, i32, vp, dp]
+    L.orc_trace_batch.argtypes = [vp, i64, dp, dp, i32, i32, vp]
+    L.orc_blend_probe.argtypes = [i32, dp, dp, dp, C.c_double, C.c_double, C.c_double, dp, dp]
+    L.orc_query_batch.argtypes = [vp, i32, i64, vp, vp, vp, dp, dp]
+    L.orc_classify.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
+    L.orc_state_step.argtypes = [vp, vp, i32]
+    L.orc_update_frame.restype = i64
+    L.orc_update_frame.argtypes = [vp, vp, vp, i32, vp, vp, i64]
+    L.orc_shade_ray.argtypes = [vp, vp, vp, i32, dp, dp, C.c_double, vp]
+
+
+# ---------------------------------------------------------------- wrappers
+
+
+def _d(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a if shape is None else a.reshape(shape)
+
+
+def oct_encode(v) -> np.ndarray:
+    v = _d(v, 3)
+    p = np.zeros(2)
+    lib().orc_oct_encode(_p(v), _p(p))
+    return p
+
+
+def oct_decode(p) -> np.ndarray:
+    p = _d(p, 2)
+    v = np.zeros(3)
+    lib().orc_oct_decode(_p(p), _p(v))
+    return v
+
+
+def texel_direction(m: int, x: int, y: int) -> np.ndarray:
+    v = np.zeros(3)
+    lib().orc_texel_direction(m, x, y, _p(v))
+    return v
+
+
+def border_source(m: int, x: int, y: int):
+    sx, sy = C.c_int32(), C.c_int32()
+    lib().orc_border_source(m, x, y, C.byref(sx), C.byref(sy))
+    return sx.value, sy.value
+
+
+def sample_tile(tile: np.ndarray, v) -> np.ndarray:
+    tile = _d(tile)
+    m, nch = tile.shape[0], tile.shape[2]
+    out = np.zeros(nch)
+    lib().orc_sample_tile(_p(tile), m, nch, _p(_d(v, 3)), _p(out))
+    return out
+
+
+def sf_directions(n: int, R) -> np.ndarray:
+    R = np.ascontiguousarray(R, dtype=np.float32).reshape(9)
+    out = np.zeros((n, 3))
+    for i in range(n):
+        lib().orc_sf_direction(i, n, _p(R), _p(out[i]))
+    return out
+
+
+def blend_probe(omega, rgb, d, cos_power, alpha_irr, alpha_dist, irr_tile, dist_tile):
+    """In-place blend of one probe's tiles ([8,8,3] and [16,16,2] float64)."""
+    omega, rgb, d = _d(omega), _d(rgb), _d(d)
+    assert irr_tile.dtype == np.float64 and irr_tile.flags.c_contiguous
+    assert dist_tile.dtype == np.float64 and dist_tile.flags.c_contiguous
+    lib().orc_blend_probe(len(d), _p(omega), _p(rgb), _p(d), cos_power, alpha_irr, alpha_dist,
+                          _p(irr_tile), _p(dist_tile))
+
+
+class Scene:
+    """Oracle-side copy of a scene (FP64 triangles plus the oracle's own
+    median-split BVH, an exact accelerator)."""
+
+    def __init__(self, scene):
+        self._keep = [np.ascontiguousarray(x) for x in (scene.vertices, scene.indices, scene.tri_material,
+                                                        scene.tri_object, scene.albedo, scene.emission)]
+        v, i, m, o, a, e = self._keep
+        self.n_triangles = int(i.shape[0])
+        self.handle = lib().orc_scene_create(_p(v), v.shape[0], _p(i), i.shape[0], _p(m), _p(o),
+                                             _p(a), _p(e), a.shape[0])
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.orc_scene_free(self.handle)
+            self.handle = None
+
+    def trace(self, origins, dirs, static_only=False, brute=False) -> np.ndarray:
+        o = _d(origins).reshape(-1, 3)
+        d = _d(dirs).reshape(-1, 3)
+        hits = np.zeros(o.shape[0], dtype=HIT_DTYPE)
+        lib().orc_trace_batch(self.handle, o.shape[0], _p(o), _p(d), int(static_only), int(brute), _p(hits))
+        return hits
+
+
+def make_lights(lights) -> Lights:
+    L = Lights()
+    keep = [np.ascontiguousarray(x, dtype=np.float32) for x in
+            (lights.dir_to_light, lights.dir_irradiance, lights.point_pos, lights.point_intensity)]
+    L.n_dir = keep[0].shape[0]
+    L.dir_to_light, L.dir_irradiance = _p(keep[0]), _p(keep[1])
+    L.n_point = keep[2].shape[0]
+    L.point_pos, L.point_intensity = _p(keep[2]), _p(keep[3])
+    for c in range(3):
+        L.sky[c] = float(lights.sky[c])
+    L._keep = keep
+    return L
+
+
+class Volume:
+    """Oracle volume: FP64 atlases irr[P,8,8,3], dist[P,16,16,2], uint8
+    states[P], float32 offsets[P,3]."""
+
+    def __init__(self, desc, states=None):
+        self.desc = desc
+        P = desc.n_probes
+        self.irr = np.zeros((P, 8, 8, 3))
+        self.dist = np.zeros((P, 16, 16, 2))
+        self.states = np.full(P, NEWLY_VIGILANT if states is None else 0, dtype=np.uint8)
+        if states is not None:
+            self.states[:] = states
+        self.offsets = np.zeros((P, 3), dtype=np.float32)
+
+    def struct(self) -> VolumeStruct:
+        d = self.desc
+        s = VolumeStruct()
+        for a in range(3):
+            s.origin[a] = d.origin[a]
+            s.spacing[a] = d.spacing[a]
+            s.counts[a] = d.counts[a]
+        s.rays = d.rays_per_probe
+        s.alpha_irr, s.alpha_dist = d.hysteresis_irr, d.hysteresis_dist
+        s.cos_power, s.bias = d.cos_power, d.self_shadow_bias
+        s.dmax = d.resolved_max_distance()
+        s.cheb_power = d.cheb_power
+        for arr in (self.irr, self.dist, self.states, self.offsets):
+            assert arr.flags.c_contiguous
+        s.irr, s.dist, s.states, s.offsets = _p(self.irr), _p(self.dist), _p(self.states), _p(self.offsets)
+        return s
+
+
+def _vol_array(vols: List[Volume]):
+    arr = (VolumeStruct * max(1, len(vols)))()
+    for i, v in enumerate(vols):
+        arr[i] = v.struct()
+    return arr
+
+
+def classify(scene: Scene, vols: List[Volume], rotations: np.ndarray):
+    R = np.ascontiguousarray(rotations, dtype=np.float32).reshape(-1, 9)
+    total = sum(v.desc.n_probes for v in vols)
+    n_back = np.zeros(total, np.int32)
+    n_flag = np.zeros(total, np.int32)
+    t_front = np.zeros(total)
+    arr = _vol_array(vols)
+    lib().orc_classify(scene.handle, arr, len(vols), _p(R), R.shape[0], _p(n_back), _p(n_flag), _p(t_front))
+    return n_back, n_flag, t_front
+
+
+def state_step(scene: Scene, vols: List[Volume]):
+    lib().orc_state_step(scene.handle, _vol_array(vols), len(vols))
+
+
+def update_frame(scene: Scene, lights, vols: List[Volume], R, records: bool = True):
+    R = np.ascontiguousarray(R, dtype=np.float32).reshape(9)
+    L = make_lights(lights)
+    # states change inside; the number of active probes is known after the
+    # state step, so size the record buffer for every probe
+    cap = sum(v.desc.n_probes * v.desc.rays_per_probe for v in vols) if records else 0
+    rec = np.zeros(cap, dtype=RECORD_DTYPE)
+    arr = _vol_array(vols)
+    n = lib().orc_update_frame(scene.handle, C.byref(L), arr, len(vols), _p(R),
+                               _p(rec) if records else None, cap)
+    return rec[:n] if records else None
+
+
+def query(vols: List[Volume], pos, nrm, view):
+    pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
+    nrm = np.ascontiguousarray(nrm, dtype=np.float32).reshape(-1, 3)
+    view = np.ascontiguousarray(view, dtype=np.float32).reshape(-1, 3)
+    out = np.zeros((pos.shape[0], 3))
+    kap = np.zeros((pos.shape[0], 3))
+    lib().orc_query_batch(_vol_array(vols), len(vols), pos.shape[0], _p(pos), _p(nrm), _p(view), _p(out), _p(kap))
+    return out, kap
+
+
+def shade_ray(scene: Scene, lights, vols: List[Volume], o, w, dmax) -> np.ndarray:
+    L = make_lights(lights)
+    rec = np.zeros(1, dtype=RECORD_DTYPE)
+    lib().orc_shade_ray(scene.handle, C.byref(L), _vol_array(vols), len(vols), _p(_d(o, 3)), _p(_d(w, 3)),
+                        float(dmax), _p(rec))
+    return rec[0]

@@ -1,0 +1,940 @@
+/*
+ * FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY (see irf_oracle.h).
+ *
+ * Paper: Majercik, Marrs, Spjut, McGuire, "Scaling Probe-Based Real-Time
+ * Dynamic Global Illumination for Production" (JCGT / arXiv 2009.10796).
+ * Sections are cited by title:
+ *   "Overview of the algorithm"   -> Build/Init, Probe Query, Probe Update,
+ *                                    and the hysteresis update equation (Eq. U)
+ *   "Self-shadow bias ..."         -> Eq. 1 and the backface-ray rule
+ *   "Probe States"                 -> states, full initialization algorithm
+ *   "Multiple Probe Volumes"       -> cascade blending
+ * Readings where the paper is silent follow the published base method
+ * (DDGI, Majercik et al. 2019) and are listed in the design notes.
+ *
+ * Plain, unblocked loops: every function follows the definition it cites.
+ */
+#include "irf_oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define EPS_B 1e-4   /* barycentric margin for flags */
+#define EPS_T 1e-6   /* relative distance margin for flags */
+#define U32 (1.0 / 16777216.0)
+
+/* ------------------------------------------------------------------ vec3 */
+static inline double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+static inline void sub3(const double a[3], const double b[3], double r[3]) {
+  r[0] = a[0] - b[0]; r[1] = a[1] - b[1]; r[2] = a[2] - b[2];
+}
+static inline void cross3(const double a[3], const double b[3], double r[3]) {
+  r[0] = a[1] * b[2] - a[2] * b[1];
+  r[1] = a[2] * b[0] - a[0] * b[2];
+  r[2] = a[0] * b[1] - a[1] * b[0];
+}
+static inline double len3(const double a[3]) { return sqrt(dot3(a, a)); }
+static inline void normalize3(double a[3]) {
+  double l = len3(a);
+  if (l > 0) { a[0] /= l; a[1] /= l; a[2] /= l; }
+  else { a[0] = a[1] = a[2] = 0; }
+}
+static inline double clampd(double x, double lo, double hi) { return x < lo ? lo : (x > hi ? hi : x); }
+static inline double signnz(double x) { return x >= 0.0 ? 1.0 : -1.0; }
+
+/* ------------------------------------------------------------------ scene */
+typedef struct {
+  double lo[3], hi[3];
+  int32_t left, right;  /* children, -1 for leaves */
+  int32_t first, count; /* range in s->order for leaves */
+} onode;
+
+struct orc_scene {
+  int64_t nt;
+  double* v;          /* [T][3][3] triangle vertices */
+  int32_t* material;  /* [T] */
+  int32_t* object;    /* [T] */
+  int32_t nm;
+  double* albedo;     /* [M][3] */
+  double* emission;   /* [M][3] */
+  int32_t* order;     /* triangle ids in leaf order */
+  onode* nodes;
+  int64_t nnodes, cap;
+  int32_t nobj;       /* number of dynamic objects (ids 1..nobj) */
+  double* obj_lo;     /* [nobj+1][3] */
+  double* obj_hi;
+};
+
+static const double* tri_v(const orc_scene* s, int64_t t, int k) { return s->v + (t * 3 + k) * 3; }
+
+static void tri_box(const orc_scene* s, int32_t t, double lo[3], double hi[3]) {
+  /* triangle bounds inflated so that every point within EPS_B (barycentric)
+     of the triangle is inside; the flag pass relies on it */
+  double e = 0;
+  for (int k = 0; k < 3; k++) {
+    double d[3];
+    sub3(tri_v(s, t, (k + 1) % 3), tri_v(s, t, k), d);
+    double l = len3(d);
+    if (l > e) e = l;
+  }
+  e = 4.0 * EPS_B * e + 1e-9;
+  for (int a = 0; a < 3; a++) {
+    lo[a] = INFINITY; hi[a] = -INFINITY;
+    for (int k = 0; k < 3; k++) {
+      double x = tri_v(s, t, k)[a];
+      if (x < lo[a]) lo[a] = x;
+      if (x > hi[a]) hi[a] = x;
+    }
+    lo[a] -= e; hi[a] += e;
+  }
+}
+
+static int32_t new_node(orc_scene* s) {
+  if (s->nnodes == s->cap) {
+    s->cap = s->cap ? s->cap * 2 : 1024;
+    s->nodes = (onode*)realloc(s->nodes, (size_t)s->cap * sizeof(onode));
+  }
+  return (int32_t)s->nnodes++;
+}
+
+static double* g_cent; /* build-time centroid table, used by the comparator */
+static int g_axis;
+static int cmp_cent(const void* a, const void* b) {
+  double ca = g_cent[*(const int32_t*)a * 3 + g_axis];
+  double cb = g_cent[*(const int32_t*)b * 3 + g_axis];
+  if (ca < cb) return -1;
+  if (ca > cb) return 1;
+  return (*(const int32_t*)a) - (*(const int32_t*)b);
+}
+
+/* median split on the widest centroid axis; exact accelerator only */
+static int32_t build(orc_scene* s, int32_t first, int32_t count) {
+  int32_t id = new_node(s);
+  onode n;
+  for (int a = 0; a < 3; a++) { n.lo[a] = INFINITY; n.hi[a] = -INFINITY; }
+  double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int32_t i = first; i < first + count; i++) {
+    double lo[3], hi[3];
+    int32_t t = s->order[i];
+    tri_box(s, t, lo, hi);
+    for (int a = 0; a < 3; a++) {
+      if (lo[a] < n.lo[a]) n.lo[a] = lo[a];
+      if (hi[a] > n.hi[a]) n.hi[a] = hi[a];
+      double c = g_cent[t * 3 + a];
+      if (c < clo[a]) clo[a] = c;
+      if (c > chi[a]) chi[a] = c;
+    }
+  }
+  n.left = n.right = -1;
+  n.first = first;
+  n.count = count;
+  if (count > 4) {
+    int axis = 0;
+    for (int a = 1; a < 3; a++)
+      if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+    g_axis = axis;
+    qsort(s->order + first, (size_t)count, sizeof(int32_t), cmp_cent);
+    int32_t half = count / 2;
+    n.left = build(s, first, half);
+    n.right = build(s, first + half, count - half);
+    n.count = 0;
+  }
+  s->nodes[id] = n;
+  return id;
+}
+
+orc_scene* orc_scene_create(const float* vertices, int64_t n_vertices, const uint32_t* indices,
+                            int64_t n_tris, const uint32_t* tri_material, const uint32_t* tri_object,
+                            const float* albedo, const float* emission, int32_t n_materials) {
+  (void)n_vertices;
+  orc_scene* s = (orc_scene*)calloc(1, sizeof(orc_scene));
+  s->nt = n_tris;
+  s->v = (double*)malloc(sizeof(double) * 9 * (size_t)(n_tris ? n_tris : 1));
+  s->material = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_tris ? n_tris : 1));
+  s->object = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_tris ? n_tris : 1));
+  s->order = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_tris ? n_tris : 1));
+  s->nobj = 0;
+  for (int64_t t = 0; t < n_tris; t++) {
+    for (int k = 0; k < 3; k++)
+      for (int a = 0; a < 3; a++) s->v[(t * 3 + k) * 3 + a] = (double)vertices[(size_t)indices[t * 3 + k] * 3 + a];
+    s->material[t] = (int32_t)tri_material[t];
+    s->object[t] = tri_object ? (int32_t)tri_object[t] : 0;
+    if (s->object[t] > s->nobj) s->nobj = s->object[t];
+    s->order[t] = (int32_t)t;
+  }
+  s->nm = n_materials;
+  s->albedo = (double*)malloc(sizeof(double) * 3 * (size_t)(n_materials ? n_materials : 1));
+  s->emission = (double*)malloc(sizeof(double) * 3 * (size_t)(n_materials ? n_materials : 1));
+  for (int32_t m = 0; m < 3 * n_materials; m++) {
+    s->albedo[m] = albedo[m];
+    s->emission[m] = emission[m];
+  }
+  s->obj_lo = (double*)malloc(sizeof(double) * 3 * (size_t)(s->nobj + 1));
+  s->obj_hi = (double*)malloc(sizeof(double) * 3 * (size_t)(s->nobj + 1));
+  for (int32_t o = 0; o <= s->nobj; o++)
+    for (int a = 0; a < 3; a++) { s->obj_lo[o * 3 + a] = INFINITY; s->obj_hi[o * 3 + a] = -INFINITY; }
+  for (int64_t t = 0; t < n_tris; t++) {
+    int32_t o = s->object[t];
+    for (int k = 0; k < 3; k++)
+      for (int a = 0; a < 3; a++) {
+        double x = tri_v(s, t, k)[a];
+        if (x < s->obj_lo[o * 3 + a]) s->obj_lo[o * 3 + a] = x;
+        if (x > s->obj_hi[o * 3 + a]) s->obj_hi[o * 3 + a] = x;
+      }
+  }
+  if (n_tris > 0) {
+    g_cent = (double*)malloc(sizeof(double) * 3 * (size_t)n_tris);
+    for (int64_t t = 0; t < n_tris; t++)
+      for (int a = 0; a < 3; a++)
+        g_cent[t * 3 + a] = (tri_v(s, t, 0)[a] + tri_v(s, t, 1)[a] + tri_v(s, t, 2)[a]) / 3.0;
+    build(s, 0, (int32_t)n_tris);
+    free(g_cent);
+    g_cent = NULL;
+  }
+  return s;
+}
+
+void orc_scene_free(orc_scene* s) {
+  if (!s) return;
+  free(s->v); free(s->material); free(s->object); free(s->order); free(s->nodes);
+  free(s->albedo); free(s->emission); free(s->obj_lo); free(s->obj_hi);
+  free(s);
+}
+
+int64_t orc_scene_bvh_nodes(const orc_scene* s) { return s->nnodes; }
+
+/* ---------------------------------------------------------- intersection */
+/* Plane intersection of ray o + t d with triangle t (Moller-Trumbore):
+   returns 0 if the ray is parallel to the plane, else t and the three
+   barycentric coordinates (negative outside the triangle). */
+static int plane_hit(const orc_scene* s, int32_t tri, const double o[3], const double d[3],
+                     double* t, double* bmin) {
+  const double *v0 = tri_v(s, tri, 0), *v1 = tri_v(s, tri, 1), *v2 = tri_v(s, tri, 2);
+  double e1[3], e2[3], p[3], q[3], sv[3];
+  sub3(v1, v0, e1);
+  sub3(v2, v0, e2);
+  cross3(d, e2, p);
+  double det = dot3(e1, p);
+  if (det == 0.0) return 0;
+  double inv = 1.0 / det;
+  sub3(o, v0, sv);
+  double u = dot3(sv, p) * inv;
+  cross3(sv, e1, q);
+  double v = dot3(d, q) * inv;
+  *t = dot3(e2, q) * inv;
+  double b0 = 1.0 - u - v;
+  double m = b0 < u ? b0 : u;
+  *bmin = m < v ? m : v;
+  return 1;
+}
+
+static int box_hit(const onode* n, const double o[3], const double d[3], double tmax) {
+  double t0 = 0.0, t1 = tmax;
+  for (int a = 0; a < 3; a++) {
+    if (d[a] == 0.0) {
+      if (o[a] < n->lo[a] || o[a] > n->hi[a]) return 0;
+      continue;
+    }
+    double ta = (n->lo[a] - o[a]) / d[a], tb = (n->hi[a] - o[a]) / d[a];
+    if (ta > tb) { double x = ta; ta = tb; tb = x; }
+    if (ta > t0) t0 = ta;
+    if (tb < t1) t1 = tb;
+    if (t0 > t1) return 0;
+  }
+  return 1;
+}
+
+static int skip_tri(const orc_scene* s, int32_t t, int32_t static_only) {
+  return static_only && s->object[t] != 0;
+}
+
+/* Visits every leaf triangle whose (inflated) box meets the ray within
+   [0, *tlim]; the callback may shrink *tlim. brute: visit all triangles. */
+typedef void (*visit_fn)(const orc_scene* s, int32_t tri, const double o[3], const double d[3],
+                         void* ctx, double* tlim);
+
+static void traverse(const orc_scene* s, const double o[3], const double d[3], double* tlim,
+                     int32_t static_only, int brute, visit_fn f, void* ctx) {
+  if (s->nt == 0) return;
+  if (brute) {
+    for (int64_t t = 0; t < s->nt; t++)
+      if (!skip_tri(s, (int32_t)t, static_only)) f(s, (int32_t)t, o, d, ctx, tlim);
+    return;
+  }
+  int32_t stack[256];
+  int sp = 0;
+  stack[sp++] = 0;
+  while (sp) {
+    const onode* n = &s->nodes[stack[--sp]];
+    double lim = isinf(*tlim) ? INFINITY : *tlim * (1.0 + 4.0 * EPS_T) + 1e-12;
+    if (!box_hit(n, o, d, lim)) continue;
+    if (n->left < 0) {
+      for (int32_t i = n->first; i < n->first + n->count; i++) {
+        int32_t t = s->order[i];
+        if (!skip_tri(s, t, static_only)) f(s, t, o, d, ctx, tlim);
+      }
+    } else {
+      stack[sp++] = n->left;
+      stack[sp++] = n->right;
+    }
+  }
+}
+
+typedef struct { double t; int32_t tri; } closest_ctx;
+
+static void visit_closest(const orc_scene* s, int32_t tri, const double o[3], const double d[3],
+                          void* vctx, double* tlim) {
+  closest_ctx* c = (closest_ctx*)vctx;
+  double t, bmin;
+  if (!plane_hit(s, tri, o, d, &t, &bmin)) return;
+  if (!(t > 0.0) || bmin < 0.0) return;
+  if (t < c->t || (t == c->t && tri < c->tri)) {
+    c->t = t;
+    c->tri = tri;
+    *tlim = t;
+  }
+}
+
+typedef struct { double t; int32_t tri; int32_t flags; } flag_ctx;
+
+static void visit_flags(const orc_scene* s, int32_t tri, const double o[3], const double d[3],
+                        void* vctx, double* tlim) {
+  (void)tlim;
+  flag_ctx* c = (flag_ctx*)vctx;
+  if (tri == c->tri) return;
+  double t, bmin;
+  if (!plane_hit(s, tri, o, d, &t, &bmin)) return;
+  if (!(t > 0.0)) return;
+  if (c->tri >= 0 && t > c->t * (1.0 + EPS_T)) return;
+  if (bmin >= 0.0) {
+    if (c->tri >= 0 && fabs(t - c->t) <= EPS_T * c->t) c->flags |= ORC_F_TIE;
+  } else if (bmin > -EPS_B) {
+    c->flags |= ORC_F_NEARMISS;
+  }
+}
+
+static void trace_impl(const orc_scene* s, const double o[3], const double d[3], int32_t static_only,
+                       int brute, orc_hit* hit) {
+  closest_ctx c = {INFINITY, -1};
+  double tlim = INFINITY;
+  traverse(s, o, d, &tlim, static_only, brute, visit_closest, &c);
+  flag_ctx f = {c.t, c.tri, 0};
+  double tl2 = c.tri >= 0 ? c.t : INFINITY;
+  traverse(s, o, d, &tl2, static_only, brute, visit_flags, &f);
+  hit->tri = c.tri;
+  hit->t = c.t;
+  hit->bmin = 0.0;
+  hit->flags = f.flags;
+  if (c.tri >= 0) {
+    double t, bmin;
+    plane_hit(s, c.tri, o, d, &t, &bmin);
+    hit->bmin = bmin;
+    if (bmin < EPS_B) hit->flags |= ORC_F_GRAZE;
+    double e1[3], e2[3], n[3];
+    sub3(tri_v(s, c.tri, 1), tri_v(s, c.tri, 0), e1);
+    sub3(tri_v(s, c.tri, 2), tri_v(s, c.tri, 0), e2);
+    cross3(e1, e2, n);
+    if (fabs(dot3(n, d)) < 1e-5 * len3(n) * len3(d)) hit->flags |= ORC_F_EDGEON;
+  }
+}
+
+void orc_trace(const orc_scene* s, const double o[3], const double d[3], int32_t static_only, orc_hit* hit) {
+  trace_impl(s, o, d, static_only, 0, hit);
+}
+void orc_trace_brute(const orc_scene* s, const double o[3], const double d[3], int32_t static_only,
+                     orc_hit* hit) {
+  trace_impl(s, o, d, static_only, 1, hit);
+}
+void orc_trace_batch(const orc_scene* s, int64_t n, const double* o, const double* d,
+                     int32_t static_only, int32_t brute, orc_hit* hits) {
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; i++) trace_impl(s, o + 3 * i, d + 3 * i, static_only, brute, &hits[i]);
+}
+
+/* Shadow ray: is any triangle (either side) hit at 0 < t < tmax?  ambiguous
+   is set when a float32 tracer could decide otherwise. */
+typedef struct { double tmax; int occ; int robust; int amb; } shadow_ctx;
+
+static void visit_shadow(const orc_scene* s, int32_t tri, const double o[3], const double d[3],
+                         void* vctx, double* tlim) {
+  shadow_ctx* c = (shadow_ctx*)vctx;
+  if (c->robust) return;
+  double t, bmin;
+  if (!plane_hit(s, tri, o, d, &t, &bmin)) return;
+  if (!(t > -EPS_T)) return;
+  double hi = isinf(c->tmax) ? INFINITY : c->tmax * (1.0 + EPS_T);
+  if (t > hi) return;
+  double lo_amb = isinf(c->tmax) ? INFINITY : c->tmax * (1.0 - EPS_T);
+  int inside = bmin >= 0.0 && t > 0.0 && t < c->tmax;
+  if (inside) c->occ = 1;
+  if (inside && bmin >= EPS_B && t < lo_amb && t > EPS_T) {
+    c->robust = 1;
+    *tlim = 0.0; /* stop: the decision is settled */
+    return;
+  }
+  if (fabs(bmin) < EPS_B || (bmin >= 0.0 && (t >= lo_amb || t <= EPS_T))) c->amb = 1;
+}
+
+static int occluded(const orc_scene* s, const double o[3], const double d[3], double tmax, int* amb) {
+  shadow_ctx c = {tmax, 0, 0, 0};
+  double tlim = tmax;
+  traverse(s, o, d, &tlim, 0, 0, visit_shadow, &c);
+  *amb = c.robust ? 0 : c.amb;
+  return c.occ;
+}
+
+/* -------------------------------------------------------------- octahedral */
+/* Octahedral map of the unit sphere onto [-1,1]^2 (Cigolle et al. 2014),
+   used for the probe tiles (Section "Probe Representation" and Table 2). */
+void orc_oct_encode(const double v[3], double p[2]) {
+  double l1 = fabs(v[0]) + fabs(v[1]) + fabs(v[2]);
+  double x = v[0] / l1, y = v[1] / l1;
+  if (v[2] < 0.0) {
+    double nx = (1.0 - fabs(y)) * signnz(x);
+    double ny = (1.0 - fabs(x)) * signnz(y);
+    x = nx;
+    y = ny;
+  }
+  p[0] = x;
+  p[1] = y;
+}
+
+void orc_oct_decode(const double p[2], double v[3]) {
+  double x = p[0], y = p[1];
+  double z = 1.0 - fabs(x) - fabs(y);
+  if (z < 0.0) {
+    double nx = (1.0 - fabs(y)) * signnz(x);
+    double ny = (1.0 - fabs(x)) * signnz(y);
+    x = nx;
+    y = ny;
+  }
+  v[0] = x; v[1] = y; v[2] = z;
+  normalize3(v);
+}
+
+/* interior cell (x, y) of an m x m tile covers [-1,1]^2 in k = m-2 cells */
+void orc_texel_direction(int32_t m, int32_t x, int32_t y, double v[3]) {
+  int32_t k = m - 2;
+  double p[2] = {2.0 * ((x - 1) + 0.5) / k - 1.0, 2.0 * ((y - 1) + 0.5) / k - 1.0};
+  orc_oct_decode(p, v);
+}
+
+/* The one-texel border repeats the cell across the octahedral seam: the
+   edge p_y = -1 folds onto itself mirrored in x (and likewise for the other
+   edges); corners take the diagonally opposite interior corner. */
+void orc_border_source(int32_t m, int32_t x, int32_t y, int32_t* sx, int32_t* sy) {
+  int32_t k = m - 2;
+  int bx = (x == 0 || x == k + 1), by = (y == 0 || y == k + 1);
+  if (bx && by) {
+    *sx = (x == 0) ? k : 1;
+    *sy = (y == 0) ? k : 1;
+  } else if (by) {
+    *sx = k + 1 - x;
+    *sy = (y == 0) ? 1 : k;
+  } else if (bx) {
+    *sx = (x == 0) ? 1 : k;
+    *sy = k + 1 - y;
+  } else {
+    *sx = x;
+    *sy = y;
+  }
+}
+
+void orc_sample_tile(const double* tile, int32_t m, int32_t nch, const double v[3], double* out) {
+  int32_t k = m - 2;
+  double p[2];
+  orc_oct_encode(v, p);
+  double cx = 1.0 + (0.5 * p[0] + 0.5) * k - 0.5;
+  double cy = 1.0 + (0.5 * p[1] + 0.5) * k - 0.5;
+  int32_t x0 = (int32_t)floor(cx), y0 = (int32_t)floor(cy);
+  if (x0 < 0) x0 = 0;
+  if (x0 > k) x0 = k;
+  if (y0 < 0) y0 = 0;
+  if (y0 > k) y0 = k;
+  double fx = clampd(cx - x0, 0.0, 1.0), fy = clampd(cy - y0, 0.0, 1.0);
+  for (int c = 0; c < nch; c++) {
+    double a = tile[(y0 * m + x0) * nch + c], b = tile[(y0 * m + x0 + 1) * nch + c];
+    double cc = tile[((y0 + 1) * m + x0) * nch + c], dd = tile[((y0 + 1) * m + x0 + 1) * nch + c];
+    out[c] = (1 - fy) * ((1 - fx) * a + fx * b) + fy * ((1 - fx) * cc + fx * dd);
+  }
+}
+
+/* -------------------------------------------------------------------- rays */
+/* Spherical Fibonacci point i of n (Keinert et al. 2015), rotated by the
+   frame's random rotation (Section "Probe Update"). */
+void orc_sf_direction(int32_t i, int32_t n, const float R[9], double out[3]) {
+  const double phi = (1.0 + sqrt(5.0)) / 2.0;
+  double z = 1.0 - (2.0 * i + 1.0) / n;
+  double r = sqrt(fmax(0.0, 1.0 - z * z));
+  double f = (double)i * phi;
+  double a = 2.0 * M_PI * (f - floor(f));
+  double sf[3] = {r * cos(a), r * sin(a), z};
+  for (int row = 0; row < 3; row++)
+    out[row] = (double)R[row * 3 + 0] * sf[0] + (double)R[row * 3 + 1] * sf[1] + (double)R[row * 3 + 2] * sf[2];
+}
+
+/* ------------------------------------------------------------------- blend */
+/* Eq. U with the normalisation that makes it the weighted *average* the text
+   describes: texel' = a*texel + (1-a) * sum(w L) / sum(w), w = max(0, n.w)
+   for irradiance and max(0, n.w)^p for mean distance and distance^2.  The
+   border is copied from the blended interior afterwards. */
+void orc_blend_probe(int32_t n, const double* omega, const double* rgb, const double* d,
+                     double cos_power, double alpha_irr, double alpha_dist,
+                     double* irr, double* dist) {
+  for (int32_t y = 1; y <= 6; y++)
+    for (int32_t x = 1; x <= 6; x++) {
+      double nt[3], W = 0, acc[3] = {0, 0, 0};
+      orc_texel_direction(8, x, y, nt);
+      for (int32_t r = 0; r < n; r++) {
+        double w = fmax(0.0, dot3(nt, omega + 3 * r));
+        W += w;
+        for (int c = 0; c < 3; c++) acc[c] += w * rgb[3 * r + c];
+      }
+      if (W > 0.0)
+        for (int c = 0; c < 3; c++) {
+          double* t = &irr[(y * 8 + x) * 3 + c];
+          *t = alpha_irr * (*t) + (1.0 - alpha_irr) * (acc[c] / W);
+        }
+    }
+  for (int32_t y = 1; y <= 14; y++)
+    for (int32_t x = 1; x <= 14; x++) {
+      double nt[3], W = 0, m1 = 0, m2 = 0;
+      orc_texel_direction(16, x, y, nt);
+      for (int32_t r = 0; r < n; r++) {
+        double w = pow(fmax(0.0, dot3(nt, omega + 3 * r)), cos_power);
+        W += w;
+        m1 += w * d[r];
+        m2 += w * d[r] * d[r];
+      }
+      if (W > 0.0) {
+        double* t = &dist[(y * 16 + x) * 2];
+        t[0] = alpha_dist * t[0] + (1.0 - alpha_dist) * (m1 / W);
+        t[1] = alpha_dist * t[1] + (1.0 - alpha_dist) * (m2 / W);
+      }
+    }
+  for (int32_t y = 0; y < 8; y++)
+    for (int32_t x = 0; x < 8; x++) {
+      int32_t sx, sy;
+      orc_border_source(8, x, y, &sx, &sy);
+      if (sx != x || sy != y)
+        for (int c = 0; c < 3; c++) irr[(y * 8 + x) * 3 + c] = irr[(sy * 8 + sx) * 3 + c];
+    }
+  for (int32_t y = 0; y < 16; y++)
+    for (int32_t x = 0; x < 16; x++) {
+      int32_t sx, sy;
+      orc_border_source(16, x, y, &sx, &sy);
+      if (sx != x || sy != y)
+        for (int c = 0; c < 2; c++) dist[(y * 16 + x) * 2 + c] = dist[(sy * 16 + sx) * 2 + c];
+    }
+}
+
+/* ------------------------------------------------------------------- query */
+static int64_t vol_probes(const orc_volume* V) { return (int64_t)V->counts[0] * V->counts[1] * V->counts[2]; }
+
+static void probe_position(const orc_volume* V, int64_t q, double P[3]) {
+  int64_t i = q % V->counts[0], j = (q / V->counts[0]) % V->counts[1], k = q / ((int64_t)V->counts[0] * V->counts[1]);
+  int64_t g[3] = {i, j, k};
+  for (int a = 0; a < 3; a++) {
+    P[a] = (double)V->origin[a] + (double)g[a] * (double)V->spacing[a];
+    if (V->offsets) P[a] += (double)V->offsets[q * 3 + a];
+  }
+}
+
+static int sampled_state(uint8_t s) { return s == ORC_AWAKE || s == ORC_VIGILANT; }
+
+/* Section "Probe Query": the 8 probes of the cage around X, each weighted by
+   trilinear x backface x visibility; the visibility test (one-sided
+   Chebyshev on the mean/mean^2 distance texels) is taken at X moved by the
+   self-shadow bias of Eq. 1.  Result: normalised weighted sum of the
+   irradiance texels sampled in direction n.  kap receives the absolute
+   sensitivity of the result to float32 rounding (units of 2^-24). */
+static void volume_query(const orc_volume* V, int64_t base, const double X[3], const double n[3],
+                         const double wo[3], double out[3], double kap[3], int32_t* cage, int32_t* ncage) {
+  double u[3], f[3];
+  int64_t g[3];
+  double D = fmin((double)V->spacing[0], fmin((double)V->spacing[1], (double)V->spacing[2]));
+  double Xb[3];
+  for (int a = 0; a < 3; a++) {
+    u[a] = (X[a] - (double)V->origin[a]) / (double)V->spacing[a];
+    double fl = floor(u[a]);
+    g[a] = (int64_t)clampd(fl, 0.0, (double)(V->counts[a] - 2));
+    f[a] = clampd(u[a] - (double)g[a], 0.0, 1.0);
+    Xb[a] = X[a] + (0.2 * n[a] + 0.8 * wo[a]) * (0.75 * D) * (double)V->bias;
+  }
+  double w[8], e[8][3], sens[8];
+  int32_t ids[8];
+  double W = 0;
+  int used = 0;
+  for (int c = 0; c < 8; c++) {
+    int cb[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+    int64_t q = (g[0] + cb[0]) + (int64_t)V->counts[0] * ((g[1] + cb[1]) + (int64_t)V->counts[1] * (g[2] + cb[2]));
+    if (!sampled_state(V->states[q])) continue;
+    double wt = 1.0;
+    for (int a = 0; a < 3; a++) wt *= cb[a] ? f[a] : 1.0 - f[a];
+    double P[3], toP[3];
+    probe_position(V, q, P);
+    sub3(P, X, toP);
+    normalize3(toP);
+    double h = (1.0 + dot3(n, toP)) * 0.5;
+    double wb = h * h + 0.2;
+    double z[3];
+    sub3(Xb, P, z);
+    double r = len3(z);
+    double wv = 1.0, s = 8.0;
+    if (r > 0.0) {
+      double zd[3] = {z[0] / r, z[1] / r, z[2] / r}, mm[2];
+      orc_sample_tile(V->dist + q * 16 * 16 * 2, 16, 2, zd, mm);
+      if (r > mm[0]) {
+        double var = fmax(mm[1] - mm[0] * mm[0], 0.0);
+        double dl = r - mm[0];
+        double ch = var / (var + dl * dl);
+        wv = pow(ch, (double)V->cheb_power);
+        /* relative float32 sensitivity of the Chebyshev weight (units of u):
+           cancellation in mu2 - mu^2 and in r - mu, incl. bilinear position */
+        double sp = 32.0 * (fabs(mm[0]) + r);
+        double sv = 32.0 * (fabs(mm[1]) + 2.0 * mm[0] * mm[0] + sp * fabs(mm[0]));
+        if (var > 0.0)
+          s += V->cheb_power * ((1.0 - ch) * sv / var + 2.0 * (1.0 - ch) * sp / dl);
+        else
+          s = INFINITY; /* zero variance: float32 rounding decides the weight */
+      }
+    }
+    ids[used] = (int32_t)(base + q);
+    w[used] = wt * wb * wv;
+    sens[used] = s;
+    orc_sample_tile(V->irr + q * 8 * 8 * 3, 8, 3, n, e[used]);
+    W += w[used];
+    used++;
+  }
+  for (int c = 0; c < 3; c++) { out[c] = 0.0; kap[c] = 0.0; }
+  if (ncage) *ncage = 0;
+  if (!(W > 0.0)) {
+    /* no visible probe: float32 may find tiny positive weights */
+    for (int i = 0; i < used; i++)
+      for (int c = 0; c < 3; c++) kap[c] = fmax(kap[c], fabs(e[i][c]) / U32);
+    return;
+  }
+  for (int i = 0; i < used; i++)
+    for (int c = 0; c < 3; c++) out[c] += w[i] * e[i][c];
+  for (int c = 0; c < 3; c++) out[c] /= W;
+  for (int i = 0; i < used; i++) {
+    for (int c = 0; c < 3; c++) {
+      double dv = fabs(e[i][c] - out[c]);
+      double term = isinf(sens[i]) ? (dv > 0 ? dv / U32 : 0.0) : (w[i] / W) * dv * sens[i];
+      kap[c] += term + (w[i] / W) * 16.0 * fabs(e[i][c]);
+    }
+    if (w[i] > 0.0 && cage && ncage && *ncage < 8) cage[(*ncage)++] = ids[i];
+  }
+}
+
+/* Section "Multiple Probe Volumes": volumes are visited from most to least
+   dense; a volume's weight falls linearly from 1 to 0 across its last grid
+   cell on every axis (product over axes); weights accumulate until they
+   reach 1; the sparsest volume takes whatever weight remains. */
+void orc_query(const orc_volume* vols, int32_t nvol, const double X[3], const double n[3],
+               const double wo[3], double out[3], double kappa[3], int32_t* cage, int32_t* n_cage) {
+  double Wt = 0.0;
+  int64_t base = 0;
+  for (int c = 0; c < 3; c++) { out[c] = 0.0; kappa[c] = 0.0; }
+  if (n_cage) *n_cage = 0;
+  for (int32_t v = 0; v < nvol; v++) {
+    const orc_volume* V = &vols[v];
+    if (Wt >= 1.0) break;
+    double wv = 1.0;
+    for (int a = 0; a < 3; a++) {
+      double u = (X[a] - (double)V->origin[a]) / (double)V->spacing[a];
+      wv *= clampd(fmin(u, (double)(V->counts[a] - 1) - u), 0.0, 1.0);
+    }
+    double wuse = (v == nvol - 1) ? 1.0 - Wt : fmin(wv, 1.0 - Wt);
+    if (wuse > 0.0) {
+      double ev[3], kv[3];
+      int32_t cg[8], nc = 0;
+      volume_query(V, base, X, n, wo, ev, kv, cg, &nc);
+      for (int c = 0; c < 3; c++) {
+        out[c] += wuse * ev[c];
+        kappa[c] += wuse * kv[c] + 4.0 * fabs(wuse * ev[c]);
+      }
+      if (cage && n_cage)
+        for (int i = 0; i < nc && *n_cage < ORC_CAGE; i++) cage[(*n_cage)++] = cg[i];
+      Wt += wuse;
+    }
+    base += vol_probes(V);
+  }
+}
+
+void orc_query_batch(const orc_volume* vols, int32_t nvol, int64_t nq, const float* pos,
+                     const float* nrm, const float* view, double* out, double* kappa) {
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t i = 0; i < nq; i++) {
+    double X[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+    double n[3] = {nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]};
+    double w[3] = {view[3 * i], view[3 * i + 1], view[3 * i + 2]};
+    orc_query(vols, nvol, X, n, w, out + 3 * i, kappa + 3 * i, NULL, NULL);
+  }
+}
+
+/* ----------------------------------------------------------------- shading */
+/* Section "Probe Update" (hit shading) and the backface rule of the
+   self-shadow-bias section: a miss sees the sky at the distance clamp; a
+   backface records radiance 0 and 20 % of its distance; a front face is
+   shaded Lambertian with shadowed direct light, its emission and the
+   previous frame's probe irradiance at the hit. */
+void orc_shade_ray(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol,
+                   const double o[3], const double w[3], double dmax, orc_ray_record* rec) {
+  orc_hit h;
+  orc_trace(s, o, w, 0, &h);
+  memset(rec, 0, sizeof(*rec));
+  for (int i = 0; i < ORC_CAGE; i++) rec->cage[i] = -1;
+  rec->tri = h.tri;
+  rec->t = h.t;
+  rec->flags = h.flags;
+  if (h.tri < 0) {
+    for (int c = 0; c < 3; c++) rec->rgb[c] = L->sky[c];
+    rec->d = dmax;
+    return;
+  }
+  double e1[3], e2[3], ng[3];
+  sub3(tri_v(s, h.tri, 1), tri_v(s, h.tri, 0), e1);
+  sub3(tri_v(s, h.tri, 2), tri_v(s, h.tri, 0), e2);
+  cross3(e1, e2, ng);
+  normalize3(ng);
+  if (dot3(w, ng) > 0.0) {
+    rec->d = fmin(0.2 * h.t, dmax);
+    return;
+  }
+  rec->d = fmin(h.t, dmax);
+  double X[3], wo[3] = {-w[0], -w[1], -w[2]};
+  for (int a = 0; a < 3; a++) X[a] = o[a] + h.t * w[a];
+  int32_t m = s->material[h.tri];
+  double direct[3] = {0, 0, 0};
+  double xmax = fmax(fabs(X[0]), fmax(fabs(X[1]), fabs(X[2])));
+  double eps = 1e-4 * fmax(1.0, xmax);
+  double Xs[3] = {X[0] + eps * ng[0], X[1] + eps * ng[1], X[2] + eps * ng[2]};
+  int32_t li = 0;
+  for (int32_t l = 0; l < L->n_dir; l++, li++) {
+    double dl[3] = {L->dir_to_light[3 * l], L->dir_to_light[3 * l + 1], L->dir_to_light[3 * l + 2]};
+    double c = dot3(ng, dl);
+    if (c <= 0.0) continue;
+    int amb = 0;
+    if (!occluded(s, Xs, dl, INFINITY, &amb)) {
+      rec->vis |= 1u << li;
+      for (int k = 0; k < 3; k++) direct[k] += (double)L->dir_irradiance[3 * l + k] * c;
+    }
+    if (amb) rec->flags |= ORC_F_SHADOW;
+  }
+  for (int32_t l = 0; l < L->n_point; l++, li++) {
+    double u[3] = {L->point_pos[3 * l] - Xs[0], L->point_pos[3 * l + 1] - Xs[1], L->point_pos[3 * l + 2] - Xs[2]};
+    double dist = len3(u);
+    if (!(dist > 0.0)) continue;
+    double uh[3] = {u[0] / dist, u[1] / dist, u[2] / dist};
+    double c = dot3(ng, uh);
+    if (c <= 0.0) continue;
+    int amb = 0;
+    if (!occluded(s, Xs, uh, dist * (1.0 - 1e-6), &amb)) {
+      rec->vis |= 1u << li;
+      for (int k = 0; k < 3; k++) direct[k] += (double)L->point_intensity[3 * l + k] * c / (dist * dist);
+    }
+    if (amb) rec->flags |= ORC_F_SHADOW;
+  }
+  double ind[3] = {0, 0, 0}, kq[3] = {0, 0, 0};
+  if (nvol > 0) orc_query(vols, nvol, X, ng, wo, ind, kq, rec->cage, &rec->n_cage);
+  for (int k = 0; k < 3; k++) {
+    double alb = s->albedo[m * 3 + k];
+    rec->rgb[k] = s->emission[m * 3 + k] + alb * (direct[k] / M_PI + ind[k]);
+    rec->kappa[k] = alb * (kq[k] + 16.0 * direct[k] / M_PI) + 8.0 * fabs(rec->rgb[k]);
+  }
+}
+
+/* ----------------------------------------------------------------- states */
+static void expanded_object_boxes(const orc_scene* s, const orc_volume* V, double* lo, double* hi) {
+  double D = fmin((double)V->spacing[0], fmin((double)V->spacing[1], (double)V->spacing[2]));
+  double bias = 0.75 * D * (double)V->bias;
+  for (int32_t o = 1; o <= s->nobj; o++)
+    for (int a = 0; a < 3; a++) {
+      lo[o * 3 + a] = s->obj_lo[o * 3 + a] - ((double)V->spacing[a] + bias);
+      hi[o * 3 + a] = s->obj_hi[o * 3 + a] + ((double)V->spacing[a] + bias);
+    }
+}
+
+static int inside_any(const orc_scene* s, const double* lo, const double* hi, const double P[3]) {
+  for (int32_t o = 1; o <= s->nobj; o++) {
+    if (isinf(s->obj_lo[o * 3])) continue;
+    int in = 1;
+    for (int a = 0; a < 3; a++) in &= (P[a] >= lo[o * 3 + a] && P[a] <= hi[o * 3 + a]);
+    if (in) return 1;
+  }
+  return 0;
+}
+
+/* Section "Full Probe Initialization Algorithm", steps 1-2: distance-only
+   rays against static geometry; a probe that sees more than 25 % backfaces
+   is inside geometry (Off); a front face closer than the probe spacing makes
+   it Newly Vigilant, otherwise it sleeps; sleeping probes inside the box of
+   a dynamic object (grown by one cell and the self-shadow bias) become Newly
+   Awake. */
+void orc_classify(const orc_scene* s, orc_volume* vols, int32_t nvol, const float* rotations,
+                  int32_t K, int32_t* n_back, int32_t* n_flagged, double* t_front) {
+  int64_t base = 0;
+  for (int32_t v = 0; v < nvol; v++) {
+    orc_volume* V = &vols[v];
+    int64_t P = vol_probes(V);
+    double* lo = (double*)malloc(sizeof(double) * 3 * (size_t)(s->nobj + 1));
+    double* hi = (double*)malloc(sizeof(double) * 3 * (size_t)(s->nobj + 1));
+    expanded_object_boxes(s, V, lo, hi);
+    double smax = fmax((double)V->spacing[0], fmax((double)V->spacing[1], (double)V->spacing[2]));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < P; q++) {
+      double Pq[3];
+      probe_position(V, q, Pq);
+      int32_t back = 0, flagged = 0;
+      double tf = INFINITY;
+      for (int32_t k = 0; k < K; k++)
+        for (int32_t r = 0; r < V->rays; r++) {
+          double w[3];
+          orc_sf_direction(r, V->rays, rotations + 9 * k, w);
+          orc_hit h;
+          orc_trace(s, Pq, w, 1, &h);
+          if (h.flags) flagged++;
+          if (h.tri < 0) continue;
+          double e1[3], e2[3], ng[3];
+          sub3(tri_v(s, h.tri, 1), tri_v(s, h.tri, 0), e1);
+          sub3(tri_v(s, h.tri, 2), tri_v(s, h.tri, 0), e2);
+          cross3(e1, e2, ng);
+          if (dot3(w, ng) > 0.0) back++;
+          else if (h.t < tf) tf = h.t;
+        }
+      uint8_t st;
+      if ((double)back / ((double)K * V->rays) > 0.25) st = ORC_OFF;
+      else if (tf < smax) st = ORC_NEWLY_VIGILANT;
+      else st = ORC_SLEEPING;
+      if (st == ORC_SLEEPING && inside_any(s, lo, hi, Pq)) st = ORC_NEWLY_AWAKE;
+      V->states[q] = st;
+      if (n_back) n_back[base + q] = back;
+      if (n_flagged) n_flagged[base + q] = flagged;
+      if (t_front) t_front[base + q] = tf;
+    }
+    free(lo);
+    free(hi);
+    base += P;
+  }
+}
+
+/* Per-frame state step: sleeping probes near a dynamic object wake (Newly
+   Awake); awake probes no longer near any dynamic object go back to sleep. */
+void orc_state_step(const orc_scene* s, orc_volume* vols, int32_t nvol) {
+  for (int32_t v = 0; v < nvol; v++) {
+    orc_volume* V = &vols[v];
+    double* lo = (double*)malloc(sizeof(double) * 3 * (size_t)(s->nobj + 1));
+    double* hi = (double*)malloc(sizeof(double) * 3 * (size_t)(s->nobj + 1));
+    expanded_object_boxes(s, V, lo, hi);
+    for (int64_t q = 0; q < vol_probes(V); q++) {
+      double P[3];
+      probe_position(V, q, P);
+      int in = inside_any(s, lo, hi, P);
+      if (V->states[q] == ORC_SLEEPING && in) V->states[q] = ORC_NEWLY_AWAKE;
+      else if (V->states[q] == ORC_AWAKE && !in) V->states[q] = ORC_SLEEPING;
+    }
+    free(lo);
+    free(hi);
+  }
+}
+
+static int active_state(uint8_t s) {
+  return s == ORC_NEWLY_AWAKE || s == ORC_NEWLY_VIGILANT || s == ORC_AWAKE || s == ORC_VIGILANT;
+}
+
+/* One frame (Section "Probe Update" and the last two steps of the full
+   initialization): state step; every active probe traces its rotated
+   spherical-Fibonacci rays and shades them against the previous atlases of
+   all volumes; only then are all probes blended (hysteresis 0 for Newly
+   states) and Newly states promoted. */
+int64_t orc_update_frame(const orc_scene* s, const orc_lights* L, orc_volume* vols, int32_t nvol,
+                         const float R[9], orc_ray_record* records, int64_t capacity) {
+  orc_state_step(s, vols, nvol);
+  /* previous atlases and states, read by hit shading */
+  orc_volume* prev = (orc_volume*)malloc(sizeof(orc_volume) * (size_t)(nvol ? nvol : 1));
+  int64_t total_rays = 0;
+  for (int32_t v = 0; v < nvol; v++) {
+    prev[v] = vols[v];
+    int64_t P = vol_probes(&vols[v]);
+    prev[v].irr = (double*)malloc(sizeof(double) * (size_t)P * 192);
+    prev[v].dist = (double*)malloc(sizeof(double) * (size_t)P * 512);
+    prev[v].states = (uint8_t*)malloc((size_t)P);
+    memcpy(prev[v].irr, vols[v].irr, sizeof(double) * (size_t)P * 192);
+    memcpy(prev[v].dist, vols[v].dist, sizeof(double) * (size_t)P * 512);
+    memcpy(prev[v].states, vols[v].states, (size_t)P);
+    for (int64_t q = 0; q < P; q++)
+      if (active_state(vols[v].states[q])) total_rays += vols[v].rays;
+  }
+  orc_ray_record* rec = (orc_ray_record*)malloc(sizeof(orc_ray_record) * (size_t)(total_rays ? total_rays : 1));
+  int64_t off = 0;
+  for (int32_t v = 0; v < nvol; v++) {
+    orc_volume* V = &vols[v];
+    int64_t P = vol_probes(V);
+    int64_t* slot = (int64_t*)malloc(sizeof(int64_t) * (size_t)P);
+    int64_t na = 0;
+    for (int64_t q = 0; q < P; q++) slot[q] = active_state(V->states[q]) ? na++ : -1;
+    double dmax = V->dmax;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < P; q++) {
+      if (slot[q] < 0) continue;
+      double Pq[3];
+      probe_position(V, q, Pq);
+      for (int32_t r = 0; r < V->rays; r++) {
+        double w[3];
+        orc_sf_direction(r, V->rays, R, w);
+        orc_shade_ray(s, L, prev, nvol, Pq, w, dmax, &rec[off + slot[q] * V->rays + r]);
+      }
+    }
+    off += na * V->rays;
+    free(slot);
+  }
+  /* blend */
+  off = 0;
+  for (int32_t v = 0; v < nvol; v++) {
+    orc_volume* V = &vols[v];
+    int64_t P = vol_probes(V);
+    int32_t N = V->rays;
+    double* omega = (double*)malloc(sizeof(double) * 3 * (size_t)N);
+    for (int32_t r = 0; r < N; r++) orc_sf_direction(r, N, R, omega + 3 * r);
+    int64_t* slot = (int64_t*)malloc(sizeof(int64_t) * (size_t)P);
+    int64_t na = 0;
+    for (int64_t q = 0; q < P; q++) slot[q] = active_state(V->states[q]) ? na++ : -1;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < P; q++) {
+      if (slot[q] < 0) continue;
+      double* rgb = (double*)malloc(sizeof(double) * 3 * (size_t)N);
+      double* d = (double*)malloc(sizeof(double) * (size_t)N);
+      for (int32_t r = 0; r < N; r++) {
+        const orc_ray_record* rr = &rec[off + slot[q] * N + r];
+        for (int c = 0; c < 3; c++) rgb[3 * r + c] = rr->rgb[c];
+        d[r] = rr->d;
+      }
+      int fresh = V->states[q] == ORC_NEWLY_AWAKE || V->states[q] == ORC_NEWLY_VIGILANT;
+      orc_blend_probe(N, omega, rgb, d, (double)V->cos_power, fresh ? 0.0 : (double)V->alpha_irr,
+                      fresh ? 0.0 : (double)V->alpha_dist, V->irr + q * 192, V->dist + q * 512);
+      free(rgb);
+      free(d);
+    }
+    for (int64_t q = 0; q < P; q++) {
+      if (V->states[q] == ORC_NEWLY_AWAKE) V->states[q] = ORC_AWAKE;
+      else if (V->states[q] == ORC_NEWLY_VIGILANT) V->states[q] = ORC_VIGILANT;
+    }
+    off += na * N;
+    free(omega);
+    free(slot);
+  }
+  if (records) memcpy(records, rec, sizeof(orc_ray_record) * (size_t)(total_rays < capacity ? total_rays : capacity));
+  free(rec);
+  for (int32_t v = 0; v < nvol; v++) {
+    free(prev[v].irr);
+    free(prev[v].dist);
+    free(prev[v].states);
+  }
+  free(prev);
+  return total_rays;
+}

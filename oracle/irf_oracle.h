@@ -1,0 +1,141 @@
+/*
+ * FP64 CPU oracle of the probe update and probe query of the irradiance
+ * field with visibility (Majercik et al., "Scaling Probe-Based Real-Time
+ * Dynamic Global Illumination for Production").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code is the slow, plain reference that the
+ * GPU library is checked against.  It shares no code, header, table or
+ * helper with the GPU library, and nothing in the product may link or call
+ * it; only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load it.
+ *
+ * All arithmetic is IEEE double.  Inputs arrive as the same float32 arrays
+ * that the GPU library receives and are promoted on entry.
+ */
+#ifndef IRF_ORACLE_H
+#define IRF_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* probe states (Section "Probe States") */
+enum { ORC_OFF = 0, ORC_SLEEPING = 1, ORC_NEWLY_AWAKE = 2, ORC_NEWLY_VIGILANT = 3,
+       ORC_AWAKE = 4, ORC_VIGILANT = 5 };
+
+/* ray flags: where a float32 tracer may legitimately decide differently */
+enum {
+  ORC_F_GRAZE = 1,     /* closest hit lies within eps_b of a triangle edge      */
+  ORC_F_TIE = 2,       /* another hit within eps_t * t of the closest           */
+  ORC_F_NEARMISS = 4,  /* a triangle missed by less than eps_b before t(1+eps_t) */
+  ORC_F_EDGEON = 8,    /* ray nearly parallel to the hit plane (face side unsure) */
+  ORC_F_SHADOW = 16    /* at least one shadow ray of this hit is ambiguous       */
+};
+
+typedef struct orc_scene orc_scene;
+
+orc_scene* orc_scene_create(const float* vertices, int64_t n_vertices,
+                            const uint32_t* indices, int64_t n_tris,
+                            const uint32_t* tri_material, const uint32_t* tri_object,
+                            const float* albedo, const float* emission, int32_t n_materials);
+void orc_scene_free(orc_scene* s);
+int64_t orc_scene_bvh_nodes(const orc_scene* s);
+
+typedef struct {
+  int32_t n_dir;
+  const float* dir_to_light;    /* [n_dir][3] */
+  const float* dir_irradiance;  /* [n_dir][3] */
+  int32_t n_point;
+  const float* point_pos;       /* [n_point][3] */
+  const float* point_intensity; /* [n_point][3] */
+  float sky[3];
+} orc_lights;
+
+typedef struct {
+  float origin[3];
+  float spacing[3];
+  int32_t counts[3];
+  int32_t rays;
+  float alpha_irr, alpha_dist;
+  float cos_power;
+  float bias;         /* B of the self-shadow bias */
+  float dmax;         /* distance clamp */
+  int32_t cheb_power;
+  double* irr;        /* [P][8][8][3]   */
+  double* dist;       /* [P][16][16][2] */
+  uint8_t* states;    /* [P] */
+  const float* offsets; /* [P][3] or NULL */
+} orc_volume;
+
+typedef struct {
+  int32_t tri;       /* original triangle id, -1 on miss */
+  int32_t flags;
+  double t;          /* hit distance (INFINITY on miss) */
+  double bmin;       /* smallest barycentric of the hit */
+} orc_hit;
+
+#define ORC_CAGE 16
+typedef struct {
+  int32_t tri;
+  int32_t flags;
+  double t;
+  double rgb[3];
+  double d;
+  uint32_t vis;          /* bit l: shadow ray to light l unoccluded */
+  int32_t n_cage;        /* probes that carried weight in the hit's query */
+  int32_t cage[ORC_CAGE];/* global probe ids (volume base + q); -1 pads */
+  double kappa[3];       /* absolute float32 sensitivity of rgb (units of u) */
+} orc_ray_record;
+
+/* ---- octahedral map (Cigolle et al. 2014), square [-1,1]^2 ---- */
+void orc_oct_encode(const double v[3], double p[2]);
+void orc_oct_decode(const double p[2], double v[3]);
+/* direction of interior cell (x, y), 1 <= x, y <= m-2, of an m x m tile */
+void orc_texel_direction(int32_t m, int32_t x, int32_t y, double v[3]);
+/* source cell of border cell (x, y) of an m x m tile */
+void orc_border_source(int32_t m, int32_t x, int32_t y, int32_t* sx, int32_t* sy);
+/* bilinear sample of an m x m tile with nch channels in direction v */
+void orc_sample_tile(const double* tile, int32_t m, int32_t nch, const double v[3], double* out);
+
+/* ---- rays ---- */
+void orc_sf_direction(int32_t i, int32_t n, const float R[9], double out[3]);
+
+/* ---- nearest hit ---- */
+void orc_trace(const orc_scene* s, const double o[3], const double d[3], int32_t static_only,
+               orc_hit* hit);
+void orc_trace_brute(const orc_scene* s, const double o[3], const double d[3], int32_t static_only,
+                     orc_hit* hit);
+void orc_trace_batch(const orc_scene* s, int64_t n, const double* o, const double* d,
+                     int32_t static_only, int32_t brute, orc_hit* hits);
+
+/* ---- blend of one probe (Eq. U, cos and cos^p weights, hysteresis) ---- */
+void orc_blend_probe(int32_t n, const double* omega, const double* rgb, const double* d,
+                     double cos_power, double alpha_irr, double alpha_dist,
+                     double* irr_tile, double* dist_tile);
+
+/* ---- query E(X, n, w_o) over cascaded volumes ---- */
+void orc_query(const orc_volume* vols, int32_t nvol, const double X[3], const double n[3],
+               const double wo[3], double out[3], double kappa[3],
+               int32_t* cage, int32_t* n_cage);
+void orc_query_batch(const orc_volume* vols, int32_t nvol, int64_t nq, const float* pos,
+                     const float* nrm, const float* view, double* out, double* kappa);
+
+/* ---- probe states ---- */
+void orc_classify(const orc_scene* s, orc_volume* vols, int32_t nvol, const float* rotations,
+                  int32_t K, int32_t* n_back, int32_t* n_flagged, double* t_front);
+void orc_state_step(const orc_scene* s, orc_volume* vols, int32_t nvol);
+
+/* ---- one update frame for all volumes; records (optional) receive, per
+   volume in order, per active probe in index order, per ray, one record ---- */
+int64_t orc_update_frame(const orc_scene* s, const orc_lights* L, orc_volume* vols, int32_t nvol,
+                         const float R[9], orc_ray_record* records, int64_t capacity);
+
+/* ---- shading of a single ray from o along w (exposed for pins) ---- */
+void orc_shade_ray(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol,
+                   const double o[3], const double w[3], double dmax, orc_ray_record* rec);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
