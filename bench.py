@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Benchmark of the probe update + probe query on one MI355X.
+
+A step is one pass of the whole hot path over the 16x8x16-probe city (256
+rays per probe, ~100k triangles, 8 point lights, 32 emissive quads): the
+per-frame update (state step and compaction, ray directions, nearest-hit
+traversal, shadow rays, hit shading with the previous frame's probes, blend
+with hysteresis and border texels, state promotion) followed by the query of
+the full 1920x1080 G-buffer.  Inputs are synthetic and seeded; everything
+is resident on the GPU before timing starts.
+
+Prints one JSON line (see the design notes for the fields).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "probe update ms/frame, Grays/s, queries/s; MFMA vs FP32 blend at stated error"
+HBM_PEAK_GBS = 8000.0
+
+
+def query_bytes(w, states):
+    """Algorithmic bytes of the query pass: per point 36 B in + 12 B out,
+    the 8 cage states (1 B each) and, per sampled probe, 4 irradiance texels
+    (3 x 4 B) and 4 distance texels (2 x 4 B)."""
+    d = w.volumes[0]
+    q = w.queries
+    u = (q.pos.astype(np.float64) - np.array(d.origin)) / np.array(d.spacing)
+    cnt = np.array(d.counts)
+    g = np.clip(np.floor(u), 0, cnt - 2).astype(np.int64)
+    sampled = np.isin(states, [4, 5])
+    n = np.zeros(len(u), np.int64)
+    for c in range(8):
+        cb = np.array([c & 1, (c >> 1) & 1, (c >> 2) & 1])
+        gg = g + cb
+        idx = gg[:, 0] + cnt[0] * (gg[:, 1] + cnt[1] * gg[:, 2])
+        n += sampled[idx]
+    return int(len(u) * (36 + 12 + 8) + n.sum() * (4 * 12 + 4 * 8)), float(n.mean())
+
+
+def cpu_baseline(w, n_frames=3):
+    """The FP64 oracle on the host cores, same workload and step."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    sc = oracle.Scene(w.scene)
+    ov = [oracle.Volume(d) for d in w.volumes]
+    oracle.classify(sc, ov, w.classify_rotations)
+    oracle.update_frame(sc, w.lights, ov, w.frame_rotation(1), records=False)
+    times = []
+    q = w.queries
+    for f in range(2, 2 + n_frames):
+        t0 = time.perf_counter()
+        oracle.update_frame(sc, w.lights, ov, w.frame_rotation(f), records=False)
+        oracle.query(ov, q.pos, q.nrm, q.view)
+        times.append(time.perf_counter() - t0)
+    return {"value": round(1e3 * float(np.median(times)), 3), "unit": "ms/frame", "cores": threads, "kind": "oracle",
+            "sample": f"full step (update frame + {q.n} G-buffer queries), FP64, OpenMP, median of {n_frames} frames"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2009_10796_amd import irf, scenes as S
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    t_setup = time.perf_counter()
+    w = S.config1()
+    ctx = irf.build_workload(w, device=0)
+    ctx.classify(w.classify_rotations)
+    q = w.queries
+    pos = torch.from_numpy(q.pos).cuda()
+    nrm = torch.from_numpy(q.nrm).cuda()
+    view = torch.from_numpy(q.view).cuda()
+    out = torch.empty_like(pos)
+    R = S.rotations(w.config, 1 + args.warmup + args.steps, start_frame=1)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    print(f"[bench] setup {setup_s:.1f}s, {w.scene.n_triangles} triangles, {q.n} queries", file=sys.stderr, flush=True)
+
+    f = 0
+    for _ in range(max(1, args.warmup)):
+        ctx.update_probes(R[f])
+        ctx.query_irradiance(pos, nrm, view, out)
+        f += 1
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.update_probes(R[f])
+        ctx.query_irradiance(pos, nrm, view, out)
+        f += 1
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    stats = ctx.frame_stats()
+    ms_step = 1e3 * (t1 - t0) / args.steps
+    print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    kern = {k: {"launches": n, "avg_us": round(1e3 * ms / max(1, n), 2)} for k, (n, ms) in prof.items()}
+    upd = [k for k in kern if k != "query"]
+    update_ms = sum(kern[k]["avg_us"] for k in upd) / 1e3
+    query_ms = kern["query"]["avg_us"] / 1e3
+    prim, shad = stats["probe_rays"], stats["shadow_rays"]
+    states = ctx.volumes[0].states.cpu().numpy()
+    qbytes, mean_sampled = query_bytes(w, states)
+    dominant = max(kern, key=lambda k: kern[k]["avg_us"])
+    roof = None
+    q_gbs = qbytes / (query_ms * 1e-3) / 1e9
+    roof_query = {"kernel": "query", "bound": "hbm", "achieved": round(q_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(q_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                  "algorithmic_bytes_per_launch": qbytes}
+    if dominant == "query":
+        roof = roof_query
+    line = {
+        "metric": METRIC,
+        "value": round(ms_step, 4),
+        "unit": "ms/frame",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "probes": int(w.volumes[0].n_probes), "active_probes": int(stats["active_probes"]),
+                   "rays_per_probe": int(w.volumes[0].rays_per_probe), "triangles": int(w.scene.n_triangles),
+                   "point_lights": 8, "queries": int(q.n), "blend": "f32", "atlas": "f32"},
+        "update_ms": round(update_ms, 4),
+        "query_ms": round(query_ms, 4),
+        "rays": {"primary": int(prim), "shadow": int(shad), "total": int(prim + shad)},
+        "grays_per_s": {"primary": round(prim / (kern["trace"]["avg_us"] * 1e-6) / 1e9, 3),
+                        "shadow": round(shad / (kern.get("shadow", {"avg_us": float("inf")})["avg_us"] * 1e-6) / 1e9, 3),
+                        "total_update": round((prim + shad) / (update_ms * 1e-3) / 1e9, 3)},
+        "queries_per_s": round(q.n / (query_ms * 1e-3), 1),
+        "kernels_us": kern,
+        "dominant_kernel": dominant,
+        "query_roofline": roof_query,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] oracle CPU baseline ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,243 @@
+/*
+ * irf -- irradiance field with visibility on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the per-frame probe update and the probe query of the method of
+ * Majercik, Marrs, Spjut and McGuire, "Scaling Probe-Based Real-Time Dynamic
+ * Global Illumination for Production" (JCGT 2021, arXiv 2009.10796), which
+ * refines DDGI (Majercik et al. 2019).  Sections of the paper are cited by
+ * title.
+ *
+ * Conventions
+ *  - Every call returns irf_status; IRF_OK is 0.  Arguments are validated
+ *    before anything is launched.  A failed call leaves the context unchanged
+ *    and sets a thread-local message (irf_last_error).
+ *  - Host pointers are read during the call only (copied).  Device pointers
+ *    belong to the caller; the library never frees them and reads/writes
+ *    them asynchronously on the given stream, so they must stay alive until
+ *    that stream's work is done.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Vectors are float32 x,y,z triples; matrices are row-major float32.
+ *  - Triangles are counter-clockwise seen from their front side.
+ *  - Probe q of a volume with counts (nx, ny, nz) has grid index (i, j, k),
+ *    q = i + nx * (j + ny * k), and sits at origin + (i, j, k) * spacing plus
+ *    its offset.
+ *  - One context per thread; a context is tied to the HIP device it was
+ *    created on.
+ */
+#ifndef IRF_H
+#define IRF_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IRF_OK = 0,
+  IRF_E_INVALID = 1,     /* bad argument (NULL, out of range, non-finite, ...) */
+  IRF_E_NOMEM = 2,       /* device or host allocation failed */
+  IRF_E_HIP = 3,         /* a HIP runtime call failed (message has details) */
+  IRF_E_STATE = 4,       /* call not valid now (e.g. update before bind) */
+  IRF_E_UNSUPPORTED = 5  /* valid request this build does not implement */
+} irf_status;
+
+/* Probe states (Section "Probe States"). */
+enum {
+  IRF_OFF = 0, IRF_SLEEPING = 1, IRF_NEWLY_AWAKE = 2, IRF_NEWLY_VIGILANT = 3,
+  IRF_AWAKE = 4, IRF_VIGILANT = 5
+};
+
+/* Atlas storage types and blend arithmetic. */
+enum { IRF_ATLAS_F32 = 0, IRF_ATLAS_F16 = 1 };
+enum { IRF_BLEND_F32 = 0, IRF_BLEND_BF16 = 1, IRF_BLEND_F16 = 2 };
+
+#define IRF_MAX_VOLUMES 8
+#define IRF_MAX_LIGHTS 32
+#define IRF_MAX_ROTATIONS 8
+
+typedef struct irf_ctx irf_ctx;
+
+/* Error reporting.  The message is thread-local and valid until the next
+   failing call on this thread. */
+const char* irf_status_str(irf_status s);
+const char* irf_last_error(void);
+/* Library version, e.g. "irf 0.1 gfx950". */
+const char* irf_version(void);
+
+/* Context: owns the scene (BVH), light set, per-frame scratch and the
+   volume descriptions.  `hip_device` is a HIP device ordinal. */
+irf_status irf_create(int32_t hip_device, irf_ctx** out);
+/* Frees every library-owned device allocation.  NULL is accepted. */
+void irf_destroy(irf_ctx* ctx);
+
+/* Triangle scene.  Host arrays; copied.  The BVH is built on the host
+   (binned SAH, two-wide, depth-limited) and uploaded synchronously.  A later
+   call replaces the scene.
+     vertices      [n_vertices][3]
+     indices       [n_triangles][3], each < n_vertices
+     tri_material  [n_triangles], each < n_materials
+     tri_object    [n_triangles], 0 = static, k > 0 = dynamic object k; NULL
+                   means all static (classification rays see static triangles
+                   only; dynamic objects wake nearby probes, Section "Full
+                   Probe Initialization Algorithm")
+     albedo, emission [n_materials][3] (Lambertian albedo; emitted radiance) */
+typedef struct {
+  const float* vertices;
+  int64_t n_vertices;
+  const uint32_t* indices;
+  int64_t n_triangles;
+  const uint32_t* tri_material;
+  const uint32_t* tri_object;
+  const float* albedo;
+  const float* emission;
+  int32_t n_materials;
+} irf_scene_desc;
+irf_status irf_set_scene(irf_ctx* ctx, const irf_scene_desc* desc);
+
+/* Lights used by hit shading (Section "Probe Update": hits are shaded by the
+   deferred-shading model, here Lambertian with shadow rays).  Host arrays,
+   copied into the context; the next launched frame uses them, so a capture of
+   irf_update_probes records the lights current at capture time.
+     dir_to_light   [n_dir][3] unit vectors toward each directional light
+     dir_irradiance [n_dir][3] irradiance on a surface facing the light
+     point_pos      [n_point][3]
+     point_intensity[n_point][3] radiant intensity, W/sr
+     sky[3]         radiance returned by rays that hit nothing
+   n_dir + n_point <= IRF_MAX_LIGHTS. */
+typedef struct {
+  const float* dir_to_light;
+  const float* dir_irradiance;
+  int32_t n_dir;
+  const float* point_pos;
+  const float* point_intensity;
+  int32_t n_point;
+  float sky[3];
+} irf_lights_desc;
+irf_status irf_set_lights(irf_ctx* ctx, const irf_lights_desc* desc);
+
+/* Probe volume.  Volumes are blended from the first created (densest) to the
+   last (sparsest) (Section "Multiple Probe Volumes").
+     counts          >= 2 per axis
+     rays_per_probe  multiple of 32, 32..1024 (spherical Fibonacci rays under
+                     one random rotation per frame, Section "Probe Update")
+     hysteresis_*    in [0, 1]: weight of the old texel (Eq. U)
+     cos_power       exponent p of the distance weight max(0, n.w)^p, > 0
+     self_shadow_bias B of Eq. 1, >= 0
+     max_distance    distance clamp for misses and hits; <= 0 selects
+                     1.5 * |spacing|
+     cheb_power      exponent of the Chebyshev visibility weight, 1..4
+     atlas_dtype     IRF_ATLAS_F32 or IRF_ATLAS_F16
+     blend           IRF_BLEND_F32 (vector ALU), IRF_BLEND_BF16 or
+                     IRF_BLEND_F16 (matrix cores, float32 accumulation) */
+typedef struct {
+  float origin[3];
+  float spacing[3];
+  int32_t counts[3];
+  int32_t rays_per_probe;
+  float hysteresis_irr;
+  float hysteresis_dist;
+  float cos_power;
+  float self_shadow_bias;
+  float max_distance;
+  int32_t cheb_power;
+  int32_t atlas_dtype;
+  int32_t blend;
+} irf_volume_desc;
+irf_status irf_create_volume(irf_ctx* ctx, const irf_volume_desc* desc, int32_t* volume_id);
+
+/* Sizes in bytes of the caller-owned buffers of a volume, and its probe
+   count.  Layouts:
+     irradiance [P][8][8][4]  (RGB + unused 4th channel; float or half)
+     distance   [P][16][16][2] (mean distance, mean distance^2)
+     states     [P] uint8
+     offsets    [P][3] float  */
+typedef struct {
+  int64_t n_probes;
+  int64_t irradiance_bytes;
+  int64_t distance_bytes;
+  int64_t states_bytes;
+  int64_t offsets_bytes;
+} irf_buffer_sizes;
+irf_status irf_volume_sizes(const irf_ctx* ctx, int32_t volume, irf_buffer_sizes* out);
+
+/* Binds caller-owned device buffers (16-byte aligned) to a volume.  The
+   update reads and writes irradiance, distance and states in place; offsets
+   may be NULL (all zero).  Initial contents are the caller's (zeros and
+   IRF_NEWLY_VIGILANT, or the result of irf_classify). */
+irf_status irf_bind_volume(irf_ctx* ctx, int32_t volume, void* irradiance, void* distance,
+                           uint8_t* states, const float* offsets);
+
+/* Probe classification (Section "Full Probe Initialization Algorithm", steps
+   1-2): per probe, K x rays_per_probe distance-only rays against static
+   triangles under the K host rotations [K][9] (1 <= K <= IRF_MAX_ROTATIONS).
+   More than 25 % backfaces -> OFF; else a front face closer than the largest
+   spacing -> NEWLY_VIGILANT; else SLEEPING; then sleeping probes inside the
+   box of a dynamic object grown by one cell plus the self-shadow bias become
+   NEWLY_AWAKE.  Writes the bound states of every volume.  Async. */
+irf_status irf_classify(irf_ctx* ctx, const float* rotations, int32_t K, void* stream);
+
+/* One update frame for all bound volumes (Section "Probe Update"): state
+   step (dynamic-object wake/sleep), compaction of active probes (Newly
+   Awake, Newly Vigilant, Awake, Vigilant), spherical-Fibonacci rays under
+   `rotation` (host [9]), nearest-hit BVH traversal, hit shading (direct
+   light with shadow rays, emission, previous frame's irradiance queried from
+   all volumes, backface rule), blend of irradiance (cosine weights) and mean
+   distance / distance^2 (cosine^p weights) with hysteresis (0 for Newly
+   states), border texels, promotion of Newly states.  Async. */
+irf_status irf_update_probes(irf_ctx* ctx, const float* rotation, void* stream);
+
+/* Query E(X, n, w_o) (Section "Probe Query", Eq. 1, Section "Multiple Probe
+   Volumes") for n points.  pos, nrm, view, out_rgb: device [n][3] float;
+   view is the unit direction from the point toward the viewer.  The result
+   is in the units of the irradiance texels (cosine-weighted mean radiance).
+   n = 0 is a no-op.  Async. */
+irf_status irf_query_irradiance(irf_ctx* ctx, const float* pos, const float* nrm, const float* view,
+                                int64_t n, float* out_rgb, void* stream);
+
+/* Per-ray records of the last update for one volume, in active-probe order
+   (ascending probe index) then ray order.  Synchronizes `stream`.  Writes at
+   most `capacity` records to the device buffer `out` and the count to
+   *count (host). */
+typedef struct {
+  int32_t tri;    /* original triangle index, -1 for a miss */
+  float t;        /* hit distance (unclamped), +inf for a miss */
+  float rgb[3];   /* shaded radiance carried by the ray */
+  float d;        /* distance entered into the distance texels */
+  uint32_t vis;   /* bit l: shadow ray toward light l (directional first) unblocked */
+  int32_t probe;  /* probe index within the volume */
+} irf_ray_record;
+irf_status irf_ray_records(irf_ctx* ctx, int32_t volume, irf_ray_record* out, int64_t capacity,
+                           int64_t* count, void* stream);
+
+/* Frame statistics of the last update (synchronizes `stream`):
+   out[0] active probes, out[1] probe rays traced, out[2] shadow rays traced,
+   out[3] probe rays that hit a front face. */
+irf_status irf_frame_stats(irf_ctx* ctx, int64_t out[4], void* stream);
+
+/* Kernel timing.  While enabled, every kernel the library launches is
+   bracketed by HIP events recorded on the stream it is launched on;
+   irf_profile_read synchronizes those events and returns, per kernel name,
+   the number of launches and their summed duration (ms) since the last
+   reset.  Costs one event pair per launch; off by default. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+} irf_kernel_time;
+irf_status irf_profile_enable(irf_ctx* ctx, int32_t enable);
+irf_status irf_profile_read(irf_ctx* ctx, irf_kernel_time* out, int32_t capacity, int32_t* count, int32_t reset);
+
+/* Host-side helpers that need no device (used by tests of the host logic). */
+/* Validates a volume description exactly as irf_create_volume does. */
+irf_status irf_validate_volume_desc(const irf_volume_desc* desc);
+/* Builds the BVH of a scene on the host and reports its statistics:
+   out[0] nodes, out[1] leaves, out[2] max depth, out[3] SAH cost,
+   out[4] 1 if every triangle is referenced exactly once and every node box
+   contains its children, else 0. */
+irf_status irf_bvh_stats(const irf_scene_desc* desc, double out[5]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

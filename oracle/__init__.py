@@ -39,12 +39,12 @@ class Hit(C.Structure):
 class RayRecord(C.Structure):
     _fields_ = [("tri", C.c_int32), ("flags", C.c_int32), ("t", C.c_double), ("rgb", C.c_double * 3),
                 ("d", C.c_double), ("vis", C.c_uint32), ("n_cage", C.c_int32),
-                ("cage", C.c_int32 * CAGE), ("kappa", C.c_double * 3)]
+                ("cage", C.c_int32 * CAGE), ("kappa", C.c_double * 3), ("cosi", C.c_double)]
 
 
 RECORD_DTYPE = np.dtype([("tri", np.int32), ("flags", np.int32), ("t", np.float64), ("rgb", np.float64, 3),
                          ("d", np.float64), ("vis", np.uint32), ("n_cage", np.int32),
-                         ("cage", np.int32, CAGE), ("kappa", np.float64, 3)], align=True)
+                         ("cage", np.int32, CAGE), ("kappa", np.float64, 3), ("cosi", np.float64)], align=True)
 assert RECORD_DTYPE.itemsize == C.sizeof(RayRecord)
 HIT_DTYPE = np.dtype([("tri", np.int32), ("flags", np.int32), ("t", np.float64), ("bmin", np.float64)], align=True)
 

@@ -702,6 +702,7 @@ void orc_shade_ray(const orc_scene* s, const orc_lights* L, const orc_volume* vo
   sub3(tri_v(s, h.tri, 2), tri_v(s, h.tri, 0), e2);
   cross3(e1, e2, ng);
   normalize3(ng);
+  rec->cosi = fabs(dot3(w, ng)) / len3(w);
   if (dot3(w, ng) > 0.0) {
     rec->d = fmin(0.2 * h.t, dmax);
     return;

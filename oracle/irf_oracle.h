@@ -86,6 +86,7 @@ typedef struct {
   int32_t n_cage;        /* probes that carried weight in the hit's query */
   int32_t cage[ORC_CAGE];/* global probe ids (volume base + q); -1 pads */
   double kappa[3];       /* absolute float32 sensitivity of rgb (units of u) */
+  double cosi;           /* |cos| of the angle between ray and hit plane (0 on a miss) */
 } orc_ray_record;
 
 /* ---- octahedral map (Cigolle et al. 2014), square [-1,1]^2 ---- */

@@ -1,0 +1,640 @@
+// C ABI of the irf library: argument validation, ownership of the scene and
+// frame scratch, and the launch sequence of one update frame.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "irf_internal.h"
+
+using namespace irf;
+
+namespace {
+
+thread_local std::string g_err;
+
+irf_status fail(irf_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(IRF_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  irf_status reserve(size_t count) {
+    if (count <= n && p) return IRF_OK;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+    if (count == 0) return IRF_OK;
+    hipError_t e = hipMalloc((void**)&p, sizeof(T) * count);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return fail(IRF_E_NOMEM, "hipMalloc(%zu bytes) failed: %s", sizeof(T) * count, hipGetErrorString(e));
+    }
+    n = count;
+    return IRF_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+}  // namespace
+
+struct irf_ctx {
+  int device = 0;
+  // scene
+  bool has_scene = false;
+  DevBuf<float4> nodes, tris, albedo, emission;
+  DevBuf<float> obj_lo, obj_hi;
+  int32_t n_tris = 0, n_nodes = 0, n_materials = 0, n_obj = 0;
+  double bvh_stats[5] = {0, 0, 0, 0, 0};
+  // lights
+  LightSet lights;
+  // volumes
+  int32_t n_vol = 0;
+  irf_volume_desc desc[IRF_MAX_VOLUMES];
+  VolumeGPU vol[IRF_MAX_VOLUMES];
+  bool bound[IRF_MAX_VOLUMES];
+  // frame scratch
+  DevBuf<int32_t> active;
+  DevBuf<FrameCounters> counters;
+  DevBuf<float4> omega;
+  DevBuf<HitRec> hits;
+  DevBuf<uint8_t> vis;
+  DevBuf<float4> rays;
+  DevBuf<int32_t> class_back;
+  DevBuf<uint32_t> class_tf;
+  bool frame_done = false;
+  // kernel timing
+  bool prof = false;
+  struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  std::map<std::string, std::pair<int64_t, double>> prof_acc;
+};
+
+namespace {
+
+irf_status set_device(const irf_ctx* c) {
+  HIP_TRY(hipSetDevice(c->device));
+  return IRF_OK;
+}
+
+SceneGPU scene_view(const irf_ctx* c) {
+  SceneGPU s;
+  s.nodes = c->nodes.p;
+  s.tris = c->tris.p;
+  s.albedo = c->albedo.p;
+  s.emission = c->emission.p;
+  s.n_tris = c->n_tris;
+  s.n_nodes = c->n_nodes;
+  return s;
+}
+
+ObjectBoxes boxes_view(const irf_ctx* c) {
+  ObjectBoxes b;
+  b.lo = c->obj_lo.p;
+  b.hi = c->obj_hi.p;
+  b.n = c->n_obj;
+  return b;
+}
+
+VolumeSet volume_view(const irf_ctx* c) {
+  VolumeSet vs;
+  memset(&vs, 0, sizeof(vs));
+  vs.n = c->n_vol;
+  for (int v = 0; v < c->n_vol; v++) vs.v[v] = c->vol[v];
+  return vs;
+}
+
+int64_t total_probes(const irf_ctx* c) {
+  int64_t p = 0;
+  for (int v = 0; v < c->n_vol; v++) p += c->vol[v].n_probes;
+  return p;
+}
+
+int64_t total_rays(const irf_ctx* c) {
+  int64_t r = 0;
+  for (int v = 0; v < c->n_vol; v++) r += (int64_t)c->vol[v].n_probes * c->vol[v].rays;
+  return r;
+}
+
+irf_status ensure_scratch(irf_ctx* c) {
+  irf_status s;
+  int64_t P = total_probes(c), R = total_rays(c);
+  int nl = c->lights.n_dir + c->lights.n_point;
+  int64_t om = 0;
+  for (int v = 0; v < c->n_vol; v++) om += c->vol[v].rays;
+  if ((s = c->active.reserve((size_t)P)) != IRF_OK) return s;
+  if ((s = c->counters.reserve(1)) != IRF_OK) return s;
+  if ((s = c->omega.reserve((size_t)om)) != IRF_OK) return s;
+  if ((s = c->hits.reserve((size_t)R)) != IRF_OK) return s;
+  if ((s = c->vis.reserve((size_t)R * (size_t)(nl > 0 ? nl : 1))) != IRF_OK) return s;
+  if ((s = c->rays.reserve((size_t)R)) != IRF_OK) return s;
+  return IRF_OK;
+}
+
+FrameScratch scratch_view(const irf_ctx* c) {
+  FrameScratch f;
+  f.active = c->active.p;
+  f.counters = c->counters.p;
+  f.omega = c->omega.p;
+  f.hits = c->hits.p;
+  f.vis = c->vis.p;
+  f.rays = c->rays.p;
+  f.rays_lp = nullptr;
+  f.max_rays = total_rays(c);
+  f.max_slots = (int32_t)total_probes(c);
+  return f;
+}
+
+irf_status check_ready(const irf_ctx* c) {
+  if (!c->has_scene) return fail(IRF_E_STATE, "no scene: call irf_set_scene first");
+  if (c->n_vol == 0) return fail(IRF_E_STATE, "no volume: call irf_create_volume first");
+  for (int v = 0; v < c->n_vol; v++)
+    if (!c->bound[v]) return fail(IRF_E_STATE, "volume %d has no bound buffers (irf_bind_volume)", v);
+  return IRF_OK;
+}
+
+hipEvent_t prof_event(irf_ctx* c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events on its stream while timing is enabled.
+struct ProfScope {
+  irf_ctx* c;
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(irf_ctx* c_, const char* n, hipStream_t s_) : c(c_), name(n), s(s_) {
+    if (c->prof && (a = prof_event(c))) (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = prof_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    c->prof_pending.push_back({name, a, b});
+  }
+};
+
+irf_status launched() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(IRF_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return IRF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* irf_status_str(irf_status s) {
+  switch (s) {
+    case IRF_OK: return "IRF_OK";
+    case IRF_E_INVALID: return "IRF_E_INVALID";
+    case IRF_E_NOMEM: return "IRF_E_NOMEM";
+    case IRF_E_HIP: return "IRF_E_HIP";
+    case IRF_E_STATE: return "IRF_E_STATE";
+    case IRF_E_UNSUPPORTED: return "IRF_E_UNSUPPORTED";
+  }
+  return "IRF_E_UNKNOWN";
+}
+
+const char* irf_last_error(void) { return g_err.c_str(); }
+
+const char* irf_version(void) { return "irf 0.1 gfx950"; }
+
+irf_status irf_create(int32_t hip_device, irf_ctx** out) {
+  if (!out) return fail(IRF_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) return fail(IRF_E_HIP, "no HIP device available");
+  if (hip_device < 0 || hip_device >= n) return fail(IRF_E_INVALID, "device %d out of range [0, %d)", hip_device, n);
+  HIP_TRY(hipSetDevice(hip_device));
+  irf_ctx* c = new (std::nothrow) irf_ctx();
+  if (!c) return fail(IRF_E_NOMEM, "context allocation failed");
+  c->device = hip_device;
+  memset(&c->lights, 0, sizeof(c->lights));
+  for (int v = 0; v < IRF_MAX_VOLUMES; v++) c->bound[v] = false;
+  *out = c;
+  return IRF_OK;
+}
+
+void irf_destroy(irf_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  c->nodes.release();
+  c->tris.release();
+  c->albedo.release();
+  c->emission.release();
+  c->obj_lo.release();
+  c->obj_hi.release();
+  c->active.release();
+  c->counters.release();
+  c->omega.release();
+  c->hits.release();
+  c->vis.release();
+  c->rays.release();
+  c->class_back.release();
+  c->class_tf.release();
+  for (auto& r : c->prof_pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->prof_pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+static irf_status validate_scene(const irf_scene_desc* d) {
+  if (!d) return fail(IRF_E_INVALID, "scene desc is NULL");
+  if (d->n_triangles < 0 || d->n_vertices < 0) return fail(IRF_E_INVALID, "negative counts");
+  if (d->n_triangles >= (1ll << 27)) return fail(IRF_E_INVALID, "too many triangles (%lld)", (long long)d->n_triangles);
+  if (d->n_materials < 1) return fail(IRF_E_INVALID, "n_materials must be >= 1");
+  if (d->n_triangles > 0 && (!d->vertices || !d->indices || !d->tri_material))
+    return fail(IRF_E_INVALID, "NULL geometry array");
+  if (!d->albedo || !d->emission) return fail(IRF_E_INVALID, "NULL material array");
+  for (int64_t i = 0; i < d->n_vertices; i++)
+    if (!finite3(d->vertices + 3 * i)) return fail(IRF_E_INVALID, "vertex %lld is not finite", (long long)i);
+  for (int64_t t = 0; t < d->n_triangles; t++) {
+    for (int k = 0; k < 3; k++)
+      if ((int64_t)d->indices[3 * t + k] >= d->n_vertices)
+        return fail(IRF_E_INVALID, "triangle %lld references vertex %u >= %lld", (long long)t, d->indices[3 * t + k],
+                    (long long)d->n_vertices);
+    if ((int32_t)d->tri_material[t] >= d->n_materials || (int32_t)d->tri_material[t] < 0)
+      return fail(IRF_E_INVALID, "triangle %lld material out of range", (long long)t);
+  }
+  for (int32_t m = 0; m < d->n_materials; m++)
+    if (!finite3(d->albedo + 3 * m) || !finite3(d->emission + 3 * m))
+      return fail(IRF_E_INVALID, "material %d is not finite", m);
+  return IRF_OK;
+}
+
+irf_status irf_bvh_stats(const irf_scene_desc* d, double out[5]) {
+  irf_status s = validate_scene(d);
+  if (s != IRF_OK) return s;
+  if (!out) return fail(IRF_E_INVALID, "out is NULL");
+  std::vector<float4> nodes, tris;
+  build_bvh(d->vertices, d->n_vertices, d->indices, d->n_triangles, d->tri_material, d->tri_object, nodes, tris, out);
+  return IRF_OK;
+}
+
+irf_status irf_set_scene(irf_ctx* c, const irf_scene_desc* d) {
+  if (!c) return fail(IRF_E_INVALID, "ctx is NULL");
+  irf_status s = validate_scene(d);
+  if (s != IRF_OK) return s;
+  if ((s = set_device(c)) != IRF_OK) return s;
+  std::vector<float4> nodes, tris;
+  double st[5];
+  build_bvh(d->vertices, d->n_vertices, d->indices, d->n_triangles, d->tri_material, d->tri_object, nodes, tris, st);
+  if (st[4] != 1.0) return fail(IRF_E_INVALID, "BVH validation failed");
+  if (st[2] > kMaxDepth) return fail(IRF_E_UNSUPPORTED, "BVH depth %g exceeds %d", st[2], kMaxDepth);
+  // dynamic object boxes
+  int32_t nobj = 0;
+  if (d->tri_object)
+    for (int64_t t = 0; t < d->n_triangles; t++) nobj = std::max(nobj, (int32_t)d->tri_object[t]);
+  std::vector<float> lo((size_t)nobj * 3, INFINITY), hi((size_t)nobj * 3, -INFINITY);
+  for (int64_t t = 0; d->tri_object && t < d->n_triangles; t++) {
+    int32_t o = (int32_t)d->tri_object[t];
+    if (o <= 0) continue;
+    for (int k = 0; k < 3; k++)
+      for (int a = 0; a < 3; a++) {
+        float x = d->vertices[(size_t)d->indices[3 * t + k] * 3 + a];
+        lo[(size_t)(o - 1) * 3 + a] = std::min(lo[(size_t)(o - 1) * 3 + a], x);
+        hi[(size_t)(o - 1) * 3 + a] = std::max(hi[(size_t)(o - 1) * 3 + a], x);
+      }
+  }
+  // objects with no triangles are dropped (their boxes stay empty)
+  std::vector<float> blo, bhi;
+  for (int32_t o = 0; o < nobj; o++)
+    if (lo[(size_t)o * 3] <= hi[(size_t)o * 3])
+      for (int a = 0; a < 3; a++) {
+        blo.push_back(lo[(size_t)o * 3 + a]);
+        bhi.push_back(hi[(size_t)o * 3 + a]);
+      }
+  std::vector<float4> alb((size_t)d->n_materials), emi((size_t)d->n_materials);
+  for (int32_t m = 0; m < d->n_materials; m++) {
+    alb[(size_t)m] = make_float4(d->albedo[3 * m], d->albedo[3 * m + 1], d->albedo[3 * m + 2], 0.0f);
+    emi[(size_t)m] = make_float4(d->emission[3 * m], d->emission[3 * m + 1], d->emission[3 * m + 2], 0.0f);
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  if ((s = c->nodes.reserve(nodes.size())) != IRF_OK) return s;
+  if ((s = c->tris.reserve(tris.size())) != IRF_OK) return s;
+  if ((s = c->albedo.reserve(alb.size())) != IRF_OK) return s;
+  if ((s = c->emission.reserve(emi.size())) != IRF_OK) return s;
+  if ((s = c->obj_lo.reserve(blo.size())) != IRF_OK) return s;
+  if ((s = c->obj_hi.reserve(bhi.size())) != IRF_OK) return s;
+  if (!nodes.empty()) HIP_TRY(hipMemcpy(c->nodes.p, nodes.data(), nodes.size() * sizeof(float4), hipMemcpyHostToDevice));
+  if (!tris.empty()) HIP_TRY(hipMemcpy(c->tris.p, tris.data(), tris.size() * sizeof(float4), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->albedo.p, alb.data(), alb.size() * sizeof(float4), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->emission.p, emi.data(), emi.size() * sizeof(float4), hipMemcpyHostToDevice));
+  if (!blo.empty()) {
+    HIP_TRY(hipMemcpy(c->obj_lo.p, blo.data(), blo.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->obj_hi.p, bhi.data(), bhi.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
+  c->n_tris = (int32_t)d->n_triangles;
+  c->n_nodes = (int32_t)(nodes.size() / 4);
+  c->n_materials = d->n_materials;
+  c->n_obj = (int32_t)(blo.size() / 3);
+  for (int i = 0; i < 5; i++) c->bvh_stats[i] = st[i];
+  c->has_scene = true;
+  return IRF_OK;
+}
+
+irf_status irf_set_lights(irf_ctx* c, const irf_lights_desc* d) {
+  if (!c || !d) return fail(IRF_E_INVALID, "NULL argument");
+  if (d->n_dir < 0 || d->n_point < 0 || d->n_dir + d->n_point > IRF_MAX_LIGHTS)
+    return fail(IRF_E_INVALID, "light count must be in [0, %d]", IRF_MAX_LIGHTS);
+  if ((d->n_dir > 0 && (!d->dir_to_light || !d->dir_irradiance)) ||
+      (d->n_point > 0 && (!d->point_pos || !d->point_intensity)))
+    return fail(IRF_E_INVALID, "NULL light array");
+  if (!finite3(d->sky)) return fail(IRF_E_INVALID, "sky is not finite");
+  LightSet L;
+  memset(&L, 0, sizeof(L));
+  for (int l = 0; l < d->n_dir; l++) {
+    if (!finite3(d->dir_to_light + 3 * l) || !finite3(d->dir_irradiance + 3 * l))
+      return fail(IRF_E_INVALID, "directional light %d is not finite", l);
+    for (int a = 0; a < 3; a++) {
+      L.dir[l][a] = d->dir_to_light[3 * l + a];
+      L.irr[l][a] = d->dir_irradiance[3 * l + a];
+    }
+  }
+  for (int p = 0; p < d->n_point; p++) {
+    if (!finite3(d->point_pos + 3 * p) || !finite3(d->point_intensity + 3 * p))
+      return fail(IRF_E_INVALID, "point light %d is not finite", p);
+    for (int a = 0; a < 3; a++) {
+      L.pos[p][a] = d->point_pos[3 * p + a];
+      L.irr[d->n_dir + p][a] = d->point_intensity[3 * p + a];
+    }
+  }
+  L.n_dir = d->n_dir;
+  L.n_point = d->n_point;
+  for (int a = 0; a < 3; a++) L.sky[a] = d->sky[a];
+  c->lights = L;
+  return IRF_OK;
+}
+
+irf_status irf_validate_volume_desc(const irf_volume_desc* d) {
+  if (!d) return fail(IRF_E_INVALID, "volume desc is NULL");
+  int64_t P = 1;
+  for (int a = 0; a < 3; a++) {
+    if (d->counts[a] < 2) return fail(IRF_E_INVALID, "counts[%d] = %d must be >= 2", a, d->counts[a]);
+    if (!(std::isfinite(d->spacing[a]) && d->spacing[a] > 0.0f))
+      return fail(IRF_E_INVALID, "spacing[%d] must be finite and > 0", a);
+    if (!std::isfinite(d->origin[a])) return fail(IRF_E_INVALID, "origin[%d] is not finite", a);
+    P *= d->counts[a];
+  }
+  if (P > (1 << 22)) return fail(IRF_E_INVALID, "too many probes (%lld > %d)", (long long)P, 1 << 22);
+  if (d->rays_per_probe < 32 || d->rays_per_probe > 1024 || d->rays_per_probe % 32)
+    return fail(IRF_E_INVALID, "rays_per_probe = %d must be a multiple of 32 in [32, 1024]", d->rays_per_probe);
+  if (!(d->hysteresis_irr >= 0.0f && d->hysteresis_irr <= 1.0f) ||
+      !(d->hysteresis_dist >= 0.0f && d->hysteresis_dist <= 1.0f))
+    return fail(IRF_E_INVALID, "hysteresis must be in [0, 1]");
+  if (!(std::isfinite(d->cos_power) && d->cos_power > 0.0f)) return fail(IRF_E_INVALID, "cos_power must be > 0");
+  if (!(std::isfinite(d->self_shadow_bias) && d->self_shadow_bias >= 0.0f))
+    return fail(IRF_E_INVALID, "self_shadow_bias must be finite and >= 0");
+  if (!std::isfinite(d->max_distance)) return fail(IRF_E_INVALID, "max_distance is not finite");
+  if (d->cheb_power < 1 || d->cheb_power > 4) return fail(IRF_E_INVALID, "cheb_power must be in [1, 4]");
+  if (d->atlas_dtype != IRF_ATLAS_F32 && d->atlas_dtype != IRF_ATLAS_F16)
+    return fail(IRF_E_INVALID, "unknown atlas_dtype %d", d->atlas_dtype);
+  if (d->blend != IRF_BLEND_F32 && d->blend != IRF_BLEND_BF16 && d->blend != IRF_BLEND_F16)
+    return fail(IRF_E_INVALID, "unknown blend %d", d->blend);
+  return IRF_OK;
+}
+
+irf_status irf_create_volume(irf_ctx* c, const irf_volume_desc* d, int32_t* volume_id) {
+  if (!c || !volume_id) return fail(IRF_E_INVALID, "NULL argument");
+  irf_status s = irf_validate_volume_desc(d);
+  if (s != IRF_OK) return s;
+  if (c->n_vol >= IRF_MAX_VOLUMES) return fail(IRF_E_INVALID, "at most %d volumes", IRF_MAX_VOLUMES);
+  if (d->blend != IRF_BLEND_F32) return fail(IRF_E_UNSUPPORTED, "matrix-core blend not built in this library");
+  int64_t P = (int64_t)d->counts[0] * d->counts[1] * d->counts[2];
+  if (total_probes(c) + P > (1 << 24)) return fail(IRF_E_INVALID, "too many probes in total");
+  int v = c->n_vol;
+  c->desc[v] = *d;
+  VolumeGPU& V = c->vol[v];
+  memset(&V, 0, sizeof(V));
+  for (int a = 0; a < 3; a++) {
+    V.origin[a] = d->origin[a];
+    V.spacing[a] = d->spacing[a];
+    V.counts[a] = d->counts[a];
+  }
+  V.n_probes = (int32_t)P;
+  V.rays = d->rays_per_probe;
+  V.alpha_irr = d->hysteresis_irr;
+  V.alpha_dist = d->hysteresis_dist;
+  V.cos_power = d->cos_power;
+  float pi = std::floor(d->cos_power);
+  V.cos_power_int = (pi == d->cos_power && pi >= 1.0f && pi <= 64.0f) ? (int32_t)pi : 0;
+  V.bias = d->self_shadow_bias;
+  if (d->max_distance > 0.0f) {
+    V.dmax = d->max_distance;
+  } else {
+    double l = std::sqrt((double)d->spacing[0] * d->spacing[0] + (double)d->spacing[1] * d->spacing[1] +
+                         (double)d->spacing[2] * d->spacing[2]);
+    V.dmax = (float)(1.5 * l);
+  }
+  V.cheb_power = d->cheb_power;
+  V.atlas_f16 = d->atlas_dtype == IRF_ATLAS_F16;
+  V.blend = d->blend;
+  V.probe_base = (int32_t)total_probes(c);
+  int32_t ob = 0;
+  for (int u = 0; u < v; u++) ob += c->vol[u].rays;
+  V.omega_base = ob;
+  c->bound[v] = false;
+  c->n_vol = v + 1;
+  *volume_id = v;
+  return IRF_OK;
+}
+
+irf_status irf_volume_sizes(const irf_ctx* c, int32_t vol, irf_buffer_sizes* out) {
+  if (!c || !out) return fail(IRF_E_INVALID, "NULL argument");
+  if (vol < 0 || vol >= c->n_vol) return fail(IRF_E_INVALID, "volume %d does not exist", vol);
+  int64_t P = c->vol[vol].n_probes;
+  int64_t es = c->vol[vol].atlas_f16 ? 2 : 4;
+  out->n_probes = P;
+  out->irradiance_bytes = P * kIrrTexels * 4 * es;
+  out->distance_bytes = P * kDistTexels * 2 * es;
+  out->states_bytes = P;
+  out->offsets_bytes = P * 3 * 4;
+  return IRF_OK;
+}
+
+irf_status irf_bind_volume(irf_ctx* c, int32_t vol, void* irr, void* dist, uint8_t* states, const float* offsets) {
+  if (!c) return fail(IRF_E_INVALID, "ctx is NULL");
+  if (vol < 0 || vol >= c->n_vol) return fail(IRF_E_INVALID, "volume %d does not exist", vol);
+  if (!irr || !dist || !states) return fail(IRF_E_INVALID, "NULL buffer");
+  if (((uintptr_t)irr & 15) || ((uintptr_t)dist & 15) || ((uintptr_t)offsets & 3))
+    return fail(IRF_E_INVALID, "buffers must be 16-byte aligned (offsets 4-byte)");
+  c->vol[vol].irr = irr;
+  c->vol[vol].dist = dist;
+  c->vol[vol].states = states;
+  c->vol[vol].offsets = offsets;
+  c->bound[vol] = true;
+  return IRF_OK;
+}
+
+irf_status irf_classify(irf_ctx* c, const float* rotations, int32_t K, void* stream) {
+  if (!c || !rotations) return fail(IRF_E_INVALID, "NULL argument");
+  if (K < 1 || K > IRF_MAX_ROTATIONS) return fail(IRF_E_INVALID, "K = %d must be in [1, %d]", K, IRF_MAX_ROTATIONS);
+  for (int i = 0; i < 9 * K; i++)
+    if (!std::isfinite(rotations[i])) return fail(IRF_E_INVALID, "rotation %d is not finite", i / 9);
+  irf_status s = check_ready(c);
+  if (s != IRF_OK) return s;
+  if ((s = set_device(c)) != IRF_OK) return s;
+  int64_t P = total_probes(c);
+  if ((s = c->class_back.reserve((size_t)P)) != IRF_OK) return s;
+  if ((s = c->class_tf.reserve((size_t)P)) != IRF_OK) return s;
+  launch_classify(volume_view(c), scene_view(c), boxes_view(c), rotations, K, c->class_back.p, c->class_tf.p,
+                  (hipStream_t)stream);
+  return launched();
+}
+
+irf_status irf_update_probes(irf_ctx* c, const float* rotation, void* stream) {
+  if (!c || !rotation) return fail(IRF_E_INVALID, "NULL argument");
+  for (int i = 0; i < 9; i++)
+    if (!std::isfinite(rotation[i])) return fail(IRF_E_INVALID, "rotation is not finite");
+  irf_status s = check_ready(c);
+  if (s != IRF_OK) return s;
+  if ((s = set_device(c)) != IRF_OK) return s;
+  if ((s = ensure_scratch(c)) != IRF_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  VolumeSet vs = volume_view(c);
+  FrameScratch fs = scratch_view(c);
+  SceneGPU sc = scene_view(c);
+  { ProfScope p(c, "state_compact", st); launch_state_compact(vs, boxes_view(c), fs, st); }
+  { ProfScope p(c, "directions", st); launch_directions(vs, rotation, fs.omega, st); }
+  { ProfScope p(c, "trace", st); launch_trace(vs, sc, fs, st); }
+  if (c->lights.n_dir + c->lights.n_point > 0) {
+    ProfScope p(c, "shadow", st);
+    launch_shadow(vs, sc, c->lights, fs, st);
+  }
+  { ProfScope p(c, "shade", st); launch_shade(vs, sc, c->lights, fs, st); }
+  { ProfScope p(c, "blend_f32", st); launch_blend(vs, fs, st); }
+  c->frame_done = true;
+  return launched();
+}
+
+irf_status irf_query_irradiance(irf_ctx* c, const float* pos, const float* nrm, const float* view, int64_t n,
+                                float* out, void* stream) {
+  if (!c) return fail(IRF_E_INVALID, "ctx is NULL");
+  if (n < 0) return fail(IRF_E_INVALID, "n < 0");
+  if (n == 0) return IRF_OK;
+  if (!pos || !nrm || !view || !out) return fail(IRF_E_INVALID, "NULL array");
+  if (c->n_vol == 0) return fail(IRF_E_STATE, "no volume");
+  for (int v = 0; v < c->n_vol; v++)
+    if (!c->bound[v]) return fail(IRF_E_STATE, "volume %d has no bound buffers", v);
+  irf_status s = set_device(c);
+  if (s != IRF_OK) return s;
+  {
+    ProfScope p(c, "query", (hipStream_t)stream);
+    launch_query(volume_view(c), pos, nrm, view, n, out, (hipStream_t)stream);
+  }
+  return launched();
+}
+
+irf_status irf_ray_records(irf_ctx* c, int32_t vol, irf_ray_record* out, int64_t capacity, int64_t* count,
+                           void* stream) {
+  if (!c || !count) return fail(IRF_E_INVALID, "NULL argument");
+  if (vol < 0 || vol >= c->n_vol) return fail(IRF_E_INVALID, "volume %d does not exist", vol);
+  if (!c->frame_done) return fail(IRF_E_STATE, "no update frame has run");
+  irf_status s = set_device(c);
+  if (s != IRF_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  FrameCounters C;
+  HIP_TRY(hipMemcpyAsync(&C, c->counters.p, sizeof(C), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  int64_t n = C.ray_base[vol + 1] - C.ray_base[vol];
+  *count = n;
+  if (!out || capacity <= 0) return IRF_OK;
+  launch_records(volume_view(c), vol, scene_view(c), scratch_view(c), c->lights.n_dir + c->lights.n_point, out,
+                 n < capacity ? n : capacity, st);
+  return launched();
+}
+
+irf_status irf_frame_stats(irf_ctx* c, int64_t out[4], void* stream) {
+  if (!c || !out) return fail(IRF_E_INVALID, "NULL argument");
+  if (!c->frame_done) return fail(IRF_E_STATE, "no update frame has run");
+  irf_status s = set_device(c);
+  if (s != IRF_OK) return s;
+  FrameCounters C;
+  HIP_TRY(hipMemcpyAsync(&C, c->counters.p, sizeof(C), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  out[0] = C.slot_base[c->n_vol];
+  out[1] = C.ray_base[c->n_vol];
+  out[2] = (int64_t)C.shadow_rays;
+  out[3] = (int64_t)C.front_hits;
+  return IRF_OK;
+}
+
+irf_status irf_profile_enable(irf_ctx* c, int32_t enable) {
+  if (!c) return fail(IRF_E_INVALID, "ctx is NULL");
+  c->prof = enable != 0;
+  return IRF_OK;
+}
+
+irf_status irf_profile_read(irf_ctx* c, irf_kernel_time* out, int32_t capacity, int32_t* count, int32_t reset) {
+  if (!c || !count) return fail(IRF_E_INVALID, "NULL argument");
+  irf_status s = set_device(c);
+  if (s != IRF_OK) return s;
+  for (auto& r : c->prof_pending) {
+    HIP_TRY(hipEventSynchronize(r.b));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    auto& acc = c->prof_acc[r.name];
+    acc.first += 1;
+    acc.second += ms;
+    c->prof_pool.push_back(r.a);
+    c->prof_pool.push_back(r.b);
+  }
+  c->prof_pending.clear();
+  int32_t n = 0;
+  for (auto& kv : c->prof_acc) {
+    if (out && n < capacity) {
+      memset(out[n].name, 0, sizeof(out[n].name));
+      strncpy(out[n].name, kv.first.c_str(), sizeof(out[n].name) - 1);
+      out[n].launches = kv.second.first;
+      out[n].total_ms = kv.second.second;
+    }
+    n++;
+  }
+  *count = n;
+  if (reset) c->prof_acc.clear();
+  return IRF_OK;
+}
+
+}  // extern "C"

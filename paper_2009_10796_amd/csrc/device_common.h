@@ -1,0 +1,225 @@
+// Device helpers shared by the irf kernels: octahedral map, probe positions,
+// tile sampling and the probe query E(X, n, w_o).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "irf_internal.h"
+
+namespace irf {
+
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
+__device__ __forceinline__ float3 operator+(float3 a, float3 b) { return f3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ float3 operator-(float3 a, float3 b) { return f3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float3 operator*(float s, float3 a) { return f3(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ float dot(float3 a, float3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+__device__ __forceinline__ float3 cross(float3 a, float3 b) {
+  return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float length(float3 a) { return sqrtf(dot(a, a)); }
+__device__ __forceinline__ float3 normalize_or_zero(float3 a) {
+  float l = length(a);
+  return l > 0.0f ? (1.0f / l) * a : f3(0.0f, 0.0f, 0.0f);
+}
+__device__ __forceinline__ float signnz(float x) { return x >= 0.0f ? 1.0f : -1.0f; }
+__device__ __forceinline__ float clampf(float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi); }
+
+// Octahedral map of the unit sphere onto [-1,1]^2 (Cigolle et al. 2014).
+__device__ __forceinline__ float2 oct_encode(float3 v) {
+  float l1 = fabsf(v.x) + fabsf(v.y) + fabsf(v.z);
+  float x = v.x / l1, y = v.y / l1;
+  if (v.z < 0.0f) {
+    float nx = (1.0f - fabsf(y)) * signnz(x);
+    float ny = (1.0f - fabsf(x)) * signnz(y);
+    x = nx;
+    y = ny;
+  }
+  return make_float2(x, y);
+}
+
+__device__ __forceinline__ float3 oct_decode(float x, float y) {
+  float z = 1.0f - fabsf(x) - fabsf(y);
+  if (z < 0.0f) {
+    float nx = (1.0f - fabsf(y)) * signnz(x);
+    float ny = (1.0f - fabsf(x)) * signnz(y);
+    x = nx;
+    y = ny;
+  }
+  return normalize_or_zero(f3(x, y, z));
+}
+
+// Direction of interior cell (x, y), 1 <= x, y <= M-2, of an M x M tile.
+template <int M>
+__device__ __forceinline__ float3 texel_direction(int x, int y) {
+  constexpr float k = (float)(M - 2);
+  return oct_decode((2.0f * (float)(x - 1) + 1.0f) / k - 1.0f, (2.0f * (float)(y - 1) + 1.0f) / k - 1.0f);
+}
+
+// Source cell of border cell (x, y): the neighbour across the octahedral
+// seam (edges mirror, corners take the opposite interior corner).
+template <int M>
+__device__ __forceinline__ void border_source(int x, int y, int& sx, int& sy) {
+  constexpr int k = M - 2;
+  bool bx = (x == 0 || x == k + 1), by = (y == 0 || y == k + 1);
+  if (bx && by) {
+    sx = (x == 0) ? k : 1;
+    sy = (y == 0) ? k : 1;
+  } else if (by) {
+    sx = k + 1 - x;
+    sy = (y == 0) ? 1 : k;
+  } else if (bx) {
+    sx = (x == 0) ? 1 : k;
+    sy = k + 1 - y;
+  } else {
+    sx = x;
+    sy = y;
+  }
+}
+
+// Bilinear footprint of direction v in an M x M tile.
+template <int M>
+__device__ __forceinline__ void tile_footprint(float3 v, int& x0, int& y0, float& fx, float& fy) {
+  constexpr int k = M - 2;
+  float2 p = oct_encode(v);
+  float cx = fmaf(fmaf(0.5f, p.x, 0.5f), (float)k, 0.5f);
+  float cy = fmaf(fmaf(0.5f, p.y, 0.5f), (float)k, 0.5f);
+  x0 = min(max((int)floorf(cx), 0), k);
+  y0 = min(max((int)floorf(cy), 0), k);
+  fx = clampf(cx - (float)x0, 0.0f, 1.0f);
+  fy = clampf(cy - (float)y0, 0.0f, 1.0f);
+}
+
+__device__ __forceinline__ float3 probe_position(const VolumeGPU& V, int q) {
+  int i = q % V.counts[0];
+  int j = (q / V.counts[0]) % V.counts[1];
+  int k = q / (V.counts[0] * V.counts[1]);
+  float3 P = f3(fmaf((float)i, V.spacing[0], V.origin[0]), fmaf((float)j, V.spacing[1], V.origin[1]),
+                fmaf((float)k, V.spacing[2], V.origin[2]));
+  if (V.offsets) {
+    P.x += V.offsets[3 * q + 0];
+    P.y += V.offsets[3 * q + 1];
+    P.z += V.offsets[3 * q + 2];
+  }
+  return P;
+}
+
+__device__ __forceinline__ float3 load_irr(const VolumeGPU& V, int idx) {
+  if (V.atlas_f16) {
+    h4 h = ((const h4*)V.irr)[idx];
+    return f3((float)h.x, (float)h.y, (float)h.z);
+  }
+  float4 f = ((const float4*)V.irr)[idx];
+  return f3(f.x, f.y, f.z);
+}
+
+__device__ __forceinline__ float2 load_dist(const VolumeGPU& V, int idx) {
+  if (V.atlas_f16) {
+    h2 h = ((const h2*)V.dist)[idx];
+    return make_float2((float)h.x, (float)h.y);
+  }
+  return ((const float2*)V.dist)[idx];
+}
+
+__device__ __forceinline__ float3 sample_irradiance(const VolumeGPU& V, int q, float3 n) {
+  int x0, y0;
+  float fx, fy;
+  tile_footprint<kIrrTile>(n, x0, y0, fx, fy);
+  int b = q * kIrrTexels + y0 * kIrrTile + x0;
+  float3 a = load_irr(V, b), c = load_irr(V, b + 1);
+  float3 d = load_irr(V, b + kIrrTile), e = load_irr(V, b + kIrrTile + 1);
+  float3 top = (1.0f - fx) * a + fx * c;
+  float3 bot = (1.0f - fx) * d + fx * e;
+  return (1.0f - fy) * top + fy * bot;
+}
+
+__device__ __forceinline__ float2 sample_distance(const VolumeGPU& V, int q, float3 v) {
+  int x0, y0;
+  float fx, fy;
+  tile_footprint<kDistTile>(v, x0, y0, fx, fy);
+  int b = q * kDistTexels + y0 * kDistTile + x0;
+  float2 a = load_dist(V, b), c = load_dist(V, b + 1);
+  float2 d = load_dist(V, b + kDistTile), e = load_dist(V, b + kDistTile + 1);
+  float tx = (1.0f - fx) * a.x + fx * c.x, ty = (1.0f - fx) * a.y + fx * c.y;
+  float bx = (1.0f - fx) * d.x + fx * e.x, by = (1.0f - fx) * d.y + fx * e.y;
+  return make_float2((1.0f - fy) * tx + fy * bx, (1.0f - fy) * ty + fy * by);
+}
+
+__device__ __forceinline__ bool sampled_state(uint8_t s) { return s == IRF_AWAKE || s == IRF_VIGILANT; }
+
+// One volume's 8-probe cage (Section "Probe Query"): trilinear x backface x
+// Chebyshev visibility at the point moved by the self-shadow bias (Eq. 1);
+// normalised.  Returns false when no probe carries weight.
+__device__ inline float3 volume_query(const VolumeGPU& V, float3 X, float3 n, float3 wo) {
+  float u[3] = {(X.x - V.origin[0]) / V.spacing[0], (X.y - V.origin[1]) / V.spacing[1],
+                (X.z - V.origin[2]) / V.spacing[2]};
+  int g[3];
+  float f[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    float fl = floorf(u[a]);
+    g[a] = (int)clampf(fl, 0.0f, (float)(V.counts[a] - 2));
+    f[a] = clampf(u[a] - (float)g[a], 0.0f, 1.0f);
+  }
+  float D = fminf(V.spacing[0], fminf(V.spacing[1], V.spacing[2]));
+  float sb = 0.75f * D * V.bias;
+  float3 Xb = f3(fmaf(fmaf(0.2f, n.x, 0.8f * wo.x), sb, X.x), fmaf(fmaf(0.2f, n.y, 0.8f * wo.y), sb, X.y),
+                 fmaf(fmaf(0.2f, n.z, 0.8f * wo.z), sb, X.z));
+  float3 acc = f3(0.0f, 0.0f, 0.0f);
+  float W = 0.0f;
+  for (int c = 0; c < 8; c++) {
+    int cb0 = c & 1, cb1 = (c >> 1) & 1, cb2 = (c >> 2) & 1;
+    int q = (g[0] + cb0) + V.counts[0] * ((g[1] + cb1) + V.counts[1] * (g[2] + cb2));
+    if (!sampled_state(V.states[q])) continue;
+    float wt = (cb0 ? f[0] : 1.0f - f[0]) * (cb1 ? f[1] : 1.0f - f[1]) * (cb2 ? f[2] : 1.0f - f[2]);
+    float3 P = probe_position(V, q);
+    float3 toP = normalize_or_zero(P - X);
+    float h = (1.0f + dot(n, toP)) * 0.5f;
+    float w = wt * fmaf(h, h, 0.2f);
+    float3 z = Xb - P;
+    float r = length(z);
+    if (r > 0.0f) {
+      float2 m = sample_distance(V, q, (1.0f / r) * z);
+      if (r > m.x) {
+        float var = fmaxf(fmaf(-m.x, m.x, m.y), 0.0f);
+        float dl = r - m.x;
+        float ch = var / fmaf(dl, dl, var);
+        float p = ch;
+        for (int e = 1; e < V.cheb_power; e++) p *= ch;
+        w *= p;
+      }
+    }
+    float3 e = sample_irradiance(V, q, n);
+    acc = acc + w * e;
+    W += w;
+  }
+  return W > 0.0f ? (1.0f / W) * acc : f3(0.0f, 0.0f, 0.0f);
+}
+
+// Cascaded volumes (Section "Multiple Probe Volumes"): densest first, linear
+// fall-off over the last cell of each axis (product of axes), accumulate
+// until the weights reach one; the sparsest volume takes the remainder.
+__device__ inline float3 query_irradiance(const VolumeSet& vs, float3 X, float3 n, float3 wo) {
+  float3 E = f3(0.0f, 0.0f, 0.0f);
+  float Wt = 0.0f;
+  for (int v = 0; v < vs.n; v++) {
+    if (Wt >= 1.0f) break;
+    const VolumeGPU& V = vs.v[v];
+    float wv = 1.0f;
+    float Xa[3] = {X.x, X.y, X.z};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      float u = (Xa[a] - V.origin[a]) / V.spacing[a];
+      wv *= clampf(fminf(u, (float)(V.counts[a] - 1) - u), 0.0f, 1.0f);
+    }
+    float wuse = (v == vs.n - 1) ? 1.0f - Wt : fminf(wv, 1.0f - Wt);
+    if (wuse > 0.0f) {
+      E = E + wuse * volume_query(V, X, n, wo);
+      Wt += wuse;
+    }
+  }
+  return E;
+}
+
+}  // namespace irf

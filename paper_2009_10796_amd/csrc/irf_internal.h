@@ -1,0 +1,120 @@
+// Internal types of the irf library (device-visible structures and launch
+// entry points shared between translation units).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/irf.h"
+
+namespace irf {
+
+constexpr int kIrrTile = 8;      // 6x6 interior + one-texel border
+constexpr int kDistTile = 16;    // 14x14 interior + one-texel border
+constexpr int kIrrTexels = kIrrTile * kIrrTile;
+constexpr int kDistTexels = kDistTile * kDistTile;
+constexpr int kMaxDepth = 48;    // BVH depth limit = traversal stack size
+constexpr int kLeafMax = 8;
+
+// Device view of one probe volume.
+struct VolumeGPU {
+  float origin[3];
+  float spacing[3];
+  int32_t counts[3];
+  int32_t n_probes;
+  int32_t rays;
+  float alpha_irr, alpha_dist;
+  float cos_power;
+  int32_t cos_power_int;    // p if p is an integer in [1, 64], else 0
+  float bias;               // B of the self-shadow bias
+  float dmax;
+  int32_t cheb_power;
+  int32_t atlas_f16;
+  int32_t blend;
+  int32_t probe_base;       // first global probe id of this volume
+  int32_t omega_base;       // first entry of this volume in the direction table
+  void* irr;                // [P][8][8] float4 or half4
+  void* dist;               // [P][16][16] float2 or half2
+  uint8_t* states;          // [P]
+  const float* offsets;     // [P][3] or null
+};
+
+struct VolumeSet {
+  VolumeGPU v[IRF_MAX_VOLUMES];
+  int32_t n;
+};
+
+// Lights by value (kernel argument).
+struct LightSet {
+  float dir[IRF_MAX_LIGHTS][3];     // directional: unit vector toward the light
+  float irr[IRF_MAX_LIGHTS][3];     // directional: irradiance; point: intensity
+  float pos[IRF_MAX_LIGHTS][3];     // point: position
+  int32_t n_dir;
+  int32_t n_point;
+  float sky[3];
+};
+
+// Dynamic-object boxes (state step and classification wake rule).
+struct ObjectBoxes {
+  const float* lo;   // [n][3]
+  const float* hi;   // [n][3]
+  int32_t n;
+};
+
+// Per-frame counters written by the compaction kernel.
+struct FrameCounters {
+  int32_t slot_base[IRF_MAX_VOLUMES + 1];  // active probes of volume v: [slot_base[v], slot_base[v+1])
+  int64_t ray_base[IRF_MAX_VOLUMES + 1];   // rays of volume v: [ray_base[v], ray_base[v+1])
+  unsigned long long shadow_rays;          // shadow rays traced this frame
+  unsigned long long front_hits;           // probe rays that hit a front face
+};
+
+// Scene on the device.
+struct SceneGPU {
+  const float4* nodes;     // [n_nodes][4]  (two child boxes + child links)
+  const float4* tris;      // [n_tris][3]   (v0 | orig id, v1 | object, v2 | material)
+  const float4* albedo;    // [M]
+  const float4* emission;  // [M]
+  int32_t n_tris;
+  int32_t n_nodes;
+};
+
+struct HitRec {
+  int32_t tri;   // BVH-order triangle, -1 miss
+  float t;
+};
+
+// Frame scratch (library-owned device memory).
+struct FrameScratch {
+  int32_t* active;          // [max_slots] global probe id per active slot
+  FrameCounters* counters;  // device
+  float4* omega;            // [sum rays] direction table for this frame
+  HitRec* hits;             // [max_rays]
+  uint8_t* vis;             // [n_lights][max_rays]
+  float4* rays;             // [max_rays] rgb + distance (float32 path)
+  void* rays_lp;            // [max_rays] 4 x bf16/f16 (matrix-core path)
+  int64_t max_rays;
+  int32_t max_slots;
+};
+
+// ---- host-side BVH builder (bvh_build.cpp)
+int build_bvh(const float* vertices, int64_t nv, const uint32_t* indices, int64_t nt,
+              const uint32_t* tri_material, const uint32_t* tri_object,
+              std::vector<float4>& nodes, std::vector<float4>& tris, double stats[5]);
+
+// ---- launches (kernels_*.hip); all asynchronous on `s`
+void launch_directions(const VolumeSet& vs, const float R[9], float4* omega, hipStream_t s);
+void launch_state_compact(const VolumeSet& vs, ObjectBoxes boxes, FrameScratch fs, hipStream_t s);
+void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, hipStream_t s);
+void launch_shadow(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s);
+void launch_shade(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s);
+void launch_blend(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
+void launch_query(const VolumeSet& vs, const float* pos, const float* nrm, const float* view, int64_t n,
+                  float* out, hipStream_t s);
+void launch_classify(const VolumeSet& vs, SceneGPU sc, ObjectBoxes boxes, const float* rotations, int K,
+                     int32_t* back, uint32_t* tfront, hipStream_t s);
+void launch_records(const VolumeSet& vs, int vol, SceneGPU sc, FrameScratch fs, int n_lights,
+                    irf_ray_record* out, int64_t count, hipStream_t s);
+
+}  // namespace irf

@@ -1,0 +1,495 @@
+// Ray traversal and hit shading for the probe update (Section "Probe
+// Update": probes trace rotated spherical-Fibonacci rays and shade the hits
+// with the deferred-shading model plus the previous frame's probes).
+//
+// Wavefront layout: one launch traces every active probe ray of every volume
+// (their hits are packed across volumes, as the paper packs the ray data of
+// all volumes into one texture); one launch traces the shadow rays, ordered
+// light-major so that a wave carries 64 neighbouring rays of one probe toward
+// one light; one launch shades.  Traversal keeps its stack in LDS, one
+// column per lane ([depth][lane] so that lanes at the same depth hit distinct
+// banks); nodes are one 64-byte record holding both child boxes.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace irf {
+
+constexpr int kTraceBlock = 128;
+
+struct Ray {
+  float3 o, d, inv;
+  int kx, ky, kz;
+  float Sx, Sy, Sz;
+};
+
+__device__ __forceinline__ float sel(float3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+
+// Precomputation of the watertight ray/triangle test (Woop, Benthin and Wald
+// 2013): the axis of largest |d| becomes z, the other two are sheared.
+__device__ __forceinline__ Ray make_ray(float3 o, float3 d) {
+  Ray r;
+  r.o = o;
+  r.d = d;
+  const float tiny = 1e-30f;
+  r.inv = f3(1.0f / (fabsf(d.x) > tiny ? d.x : copysignf(tiny, d.x)),
+             1.0f / (fabsf(d.y) > tiny ? d.y : copysignf(tiny, d.y)),
+             1.0f / (fabsf(d.z) > tiny ? d.z : copysignf(tiny, d.z)));
+  float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+  int kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+  int kx = kz == 2 ? 0 : kz + 1;
+  int ky = kx == 2 ? 0 : kx + 1;
+  if (sel(d, kz) < 0.0f) {
+    int t = kx;
+    kx = ky;
+    ky = t;
+  }
+  r.kx = kx;
+  r.ky = ky;
+  r.kz = kz;
+  float dz = sel(d, kz);
+  r.Sx = sel(d, kx) / dz;
+  r.Sy = sel(d, ky) / dz;
+  r.Sz = 1.0f / dz;
+  return r;
+}
+
+// Entry distance of the ray into a box within [0, tmax]; the exit distance is
+// widened by 2 gamma_3 so that float rounding never culls a box the ray
+// touches (Ize 2013).
+__device__ __forceinline__ bool box_hit(const Ray& r, float lx, float ly, float lz, float hx, float hy, float hz,
+                                        float tmax, float& tnear) {
+  float t0x = (lx - r.o.x) * r.inv.x, t1x = (hx - r.o.x) * r.inv.x;
+  float t0y = (ly - r.o.y) * r.inv.y, t1y = (hy - r.o.y) * r.inv.y;
+  float t0z = (lz - r.o.z) * r.inv.z, t1z = (hz - r.o.z) * r.inv.z;
+  float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+  float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+  tnear = tn;
+  return tn <= tf * 1.0000004f;
+}
+
+// Watertight ray/triangle test; on a hit with 0 < t < tmax returns t.
+__device__ __forceinline__ bool tri_hit(const Ray& r, float4 a, float4 b, float4 c, float tmax, float& t) {
+  float3 A = f3(a.x - r.o.x, a.y - r.o.y, a.z - r.o.z);
+  float3 B = f3(b.x - r.o.x, b.y - r.o.y, b.z - r.o.z);
+  float3 C = f3(c.x - r.o.x, c.y - r.o.y, c.z - r.o.z);
+  float Akz = sel(A, r.kz), Bkz = sel(B, r.kz), Ckz = sel(C, r.kz);
+  float Ax = sel(A, r.kx) - r.Sx * Akz, Ay = sel(A, r.ky) - r.Sy * Akz;
+  float Bx = sel(B, r.kx) - r.Sx * Bkz, By = sel(B, r.ky) - r.Sy * Bkz;
+  float Cx = sel(C, r.kx) - r.Sx * Ckz, Cy = sel(C, r.ky) - r.Sy * Ckz;
+  float U = Cx * By - Cy * Bx;
+  float V = Ax * Cy - Ay * Cx;
+  float W = Bx * Ay - By * Ax;
+  if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+  float det = U + V + W;
+  if (det == 0.0f) return false;
+  float T = U * (r.Sz * Akz) + V * (r.Sz * Bkz) + W * (r.Sz * Ckz);
+  if (det > 0.0f) {
+    if (!(T > 0.0f) || !(T < tmax * det)) return false;
+  } else {
+    if (!(T < 0.0f) || !(T > tmax * det)) return false;
+  }
+  t = T / det;
+  return t > 0.0f && t < tmax;
+}
+
+__device__ __forceinline__ int bits_i(float f) { return __float_as_int(f); }
+
+// Two-wide BVH traversal.  ANY: stop at the first hit (shadow rays).
+// STATIC_ONLY: skip triangles of dynamic objects (classification rays).
+// `stack` points at this lane's column of the LDS stack; `stride` = block size.
+template <bool ANY, bool STATIC_ONLY>
+__device__ inline int traverse(const SceneGPU& sc, const Ray& ray, float tmax, float& t_out, int* stack,
+                               int stride) {
+  int best = -1;
+  float tbest = tmax;
+  if (sc.n_nodes == 0) {
+    t_out = tbest;
+    return -1;
+  }
+  int sp = 0;
+  int node = 0;
+  bool done = false;
+  while (!done) {
+    while (node >= 0) {
+      const float4* np = sc.nodes + (size_t)node * 4;
+      float4 n0 = np[0], n1 = np[1], n2 = np[2], n3 = np[3];
+      float t0, t1;
+      bool h0 = box_hit(ray, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tbest, t0);
+      bool h1 = box_hit(ray, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tbest, t1);
+      int l0 = bits_i(n3.x), l1 = bits_i(n3.y);
+      if (h0 && h1) {
+        int nearc = t0 <= t1 ? l0 : l1;
+        int farc = t0 <= t1 ? l1 : l0;
+        if (sp < kMaxDepth) {
+          stack[sp * stride] = farc;
+          sp++;
+        }
+        node = nearc;
+      } else if (h0) {
+        node = l0;
+      } else if (h1) {
+        node = l1;
+      } else {
+        if (sp == 0) {
+          done = true;
+          break;
+        }
+        sp--;
+        node = stack[sp * stride];
+      }
+    }
+    if (done) break;
+    int code = ~node;
+    int first = code >> 3, count = (code & 7) + 1;
+    for (int i = first; i < first + count; i++) {
+      const float4* tp = sc.tris + (size_t)i * 3;
+      float4 a = tp[0], b = tp[1], c = tp[2];
+      if (STATIC_ONLY && bits_i(b.w) != 0) continue;
+      float t;
+      if (tri_hit(ray, a, b, c, tbest, t)) {
+        tbest = t;
+        best = i;
+        if (ANY) {
+          t_out = t;
+          return i;
+        }
+      }
+    }
+    if (sp == 0) break;
+    sp--;
+    node = stack[sp * stride];
+  }
+  t_out = tbest;
+  return best;
+}
+
+// ---- per-ray bookkeeping shared by the update kernels
+
+struct RaySlot {
+  int v;       // volume
+  int q;       // probe within the volume
+  int r;       // ray index within the probe
+};
+
+__device__ __forceinline__ RaySlot locate_ray(const VolumeSet& vs, const FrameCounters& C, const int32_t* active,
+                                              int64_t id) {
+  int v = 0;
+  while (v + 1 < vs.n && id >= C.ray_base[v + 1]) v++;
+  const VolumeGPU& V = vs.v[v];
+  int64_t local = id - C.ray_base[v];
+  int slot = (int)(local / V.rays);
+  RaySlot s;
+  s.v = v;
+  s.r = (int)(local - (int64_t)slot * V.rays);
+  s.q = active[C.slot_base[v] + slot] - V.probe_base;
+  return s;
+}
+
+__device__ __forceinline__ float3 tri_normal(const SceneGPU& sc, int tri) {
+  const float4* tp = sc.tris + (size_t)tri * 3;
+  float4 a = tp[0], b = tp[1], c = tp[2];
+  float3 e1 = f3(b.x - a.x, b.y - a.y, b.z - a.z), e2 = f3(c.x - a.x, c.y - a.y, c.z - a.z);
+  return normalize_or_zero(cross(e1, e2));
+}
+
+// Shadow-ray origin: the hit lifted off the surface along its normal.
+__device__ __forceinline__ float3 shadow_origin(float3 X, float3 ng) {
+  float xm = fmaxf(fabsf(X.x), fmaxf(fabsf(X.y), fabsf(X.z)));
+  float eps = 1e-4f * fmaxf(1.0f, xm);
+  return X + eps * ng;
+}
+
+__global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeSet vs, SceneGPU sc, FrameScratch fs) {
+  __shared__ int stack[kMaxDepth * kTraceBlock];
+  const FrameCounters& C = *fs.counters;
+  int64_t id = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
+  if (id >= C.ray_base[vs.n]) return;
+  RaySlot s = locate_ray(vs, C, fs.active, id);
+  const VolumeGPU& V = vs.v[s.v];
+  float3 o = probe_position(V, s.q);
+  float4 w = fs.omega[V.omega_base + s.r];
+  Ray ray = make_ray(o, f3(w.x, w.y, w.z));
+  float t;
+  int tri = traverse<false, false>(sc, ray, INFINITY, t, stack + threadIdx.x, kTraceBlock);
+  HitRec h;
+  h.tri = tri;
+  h.t = tri >= 0 ? t : INFINITY;
+  fs.hits[id] = h;
+}
+
+// Hit point and geometric normal of a front-face hit, else false.
+__device__ __forceinline__ bool front_hit(const VolumeSet& vs, const SceneGPU& sc, const FrameScratch& fs,
+                                          const FrameCounters& C, int64_t id, float3& X, float3& ng, float3& w3,
+                                          HitRec& h) {
+  RaySlot s = locate_ray(vs, C, fs.active, id);
+  const VolumeGPU& V = vs.v[s.v];
+  float3 o = probe_position(V, s.q);
+  float4 w = fs.omega[V.omega_base + s.r];
+  w3 = f3(w.x, w.y, w.z);
+  h = fs.hits[id];
+  if (h.tri < 0) return false;
+  ng = tri_normal(sc, h.tri);
+  if (dot(w3, ng) > 0.0f) return false;
+  X = f3(fmaf(h.t, w3.x, o.x), fmaf(h.t, w3.y, o.y), fmaf(h.t, w3.z, o.z));
+  return true;
+}
+
+__global__ __launch_bounds__(kTraceBlock) void k_shadow(VolumeSet vs, SceneGPU sc, LightSet L, FrameScratch fs) {
+  __shared__ int stack[kMaxDepth * kTraceBlock];
+  const FrameCounters& C = *fs.counters;
+  int64_t gid = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
+  int l = (int)(gid / fs.max_rays);
+  int64_t id = gid - (int64_t)l * fs.max_rays;
+  if (l >= L.n_dir + L.n_point || id >= C.ray_base[vs.n]) return;
+  float3 X, ng, w;
+  HitRec h;
+  uint8_t vis = 0;
+  bool traced = false;
+  if (front_hit(vs, sc, fs, C, id, X, ng, w, h)) {
+    float3 Xs = shadow_origin(X, ng);
+    float3 dl;
+    float tmax;
+    if (l < L.n_dir) {
+      dl = f3(L.dir[l][0], L.dir[l][1], L.dir[l][2]);
+      tmax = INFINITY;
+    } else {
+      int p = l - L.n_dir;
+      float3 u = f3(L.pos[p][0], L.pos[p][1], L.pos[p][2]) - Xs;
+      float dist = length(u);
+      dl = (1.0f / dist) * u;
+      tmax = dist * (1.0f - 1e-6f);
+      if (!(dist > 0.0f)) tmax = -1.0f;
+    }
+    if (tmax > 0.0f && dot(ng, dl) > 0.0f) {
+      Ray ray = make_ray(Xs, dl);
+      float t;
+      int hit = traverse<true, false>(sc, ray, tmax, t, stack + threadIdx.x, kTraceBlock);
+      vis = hit < 0 ? 1 : 0;
+      traced = true;
+    }
+  }
+  fs.vis[(int64_t)l * fs.max_rays + id] = vis;
+  unsigned long long m = __ballot(traced);
+  if ((threadIdx.x & 63) == __ffsll((long long)__ballot(1)) - 1 && m)
+    atomicAdd(&fs.counters->shadow_rays, (unsigned long long)__popcll(m));
+}
+
+// Radiance and distance carried by each probe ray (backface rule of the
+// self-shadow-bias section: radiance 0, distance shortened by 80 %).
+__global__ __launch_bounds__(kTraceBlock) void k_shade(VolumeSet vs, SceneGPU sc, LightSet L, FrameScratch fs) {
+  const FrameCounters& C = *fs.counters;
+  int64_t id = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
+  if (id >= C.ray_base[vs.n]) return;
+  RaySlot s = locate_ray(vs, C, fs.active, id);
+  const VolumeGPU& V = vs.v[s.v];
+  float3 o = probe_position(V, s.q);
+  float4 w4 = fs.omega[V.omega_base + s.r];
+  float3 w = f3(w4.x, w4.y, w4.z);
+  HitRec h = fs.hits[id];
+  float4 out;
+  bool front = false;
+  if (h.tri < 0) {
+    out = make_float4(L.sky[0], L.sky[1], L.sky[2], V.dmax);
+  } else {
+    float3 ng = tri_normal(sc, h.tri);
+    if (dot(w, ng) > 0.0f) {
+      out = make_float4(0.0f, 0.0f, 0.0f, fminf(0.2f * h.t, V.dmax));
+    } else {
+      front = true;
+      float3 X = f3(fmaf(h.t, w.x, o.x), fmaf(h.t, w.y, o.y), fmaf(h.t, w.z, o.z));
+      float3 Xs = shadow_origin(X, ng);
+      float3 direct = f3(0.0f, 0.0f, 0.0f);
+      int nl = L.n_dir + L.n_point;
+      for (int l = 0; l < nl; l++) {
+        if (!fs.vis[(int64_t)l * fs.max_rays + id]) continue;
+        if (l < L.n_dir) {
+          float c = dot(ng, f3(L.dir[l][0], L.dir[l][1], L.dir[l][2]));
+          direct = direct + c * f3(L.irr[l][0], L.irr[l][1], L.irr[l][2]);
+        } else {
+          int p = l - L.n_dir;
+          float3 u = f3(L.pos[p][0], L.pos[p][1], L.pos[p][2]) - Xs;
+          float dist = length(u);
+          float c = dot(ng, (1.0f / dist) * u);
+          float k = c / (dist * dist);
+          direct = direct + k * f3(L.irr[l][0], L.irr[l][1], L.irr[l][2]);
+        }
+      }
+      float3 ind = query_irradiance(vs, X, ng, f3(-w.x, -w.y, -w.z));
+      int m = bits_i(sc.tris[(size_t)h.tri * 3 + 2].w);
+      float4 al = sc.albedo[m], em = sc.emission[m];
+      const float inv_pi = 0.318309886183790672f;
+      out = make_float4(fmaf(al.x, fmaf(direct.x, inv_pi, ind.x), em.x), fmaf(al.y, fmaf(direct.y, inv_pi, ind.y), em.y),
+                        fmaf(al.z, fmaf(direct.z, inv_pi, ind.z), em.z), fminf(h.t, V.dmax));
+    }
+  }
+  fs.rays[id] = out;
+  unsigned long long m = __ballot(front);
+  if ((threadIdx.x & 63) == __ffsll((long long)__ballot(1)) - 1 && m)
+    atomicAdd(&fs.counters->front_hits, (unsigned long long)__popcll(m));
+}
+
+// ---- classification (Section "Full Probe Initialization Algorithm")
+
+struct ClassifyArgs {
+  float R[IRF_MAX_ROTATIONS][9];
+  int K;
+  int64_t base[IRF_MAX_VOLUMES + 1];   // thread ranges per volume: P * K * N
+};
+
+__device__ __forceinline__ float3 sf_direction(int i, int n, const float* R) {
+  // frac(i * golden ratio) exactly, from the 0.64 fixed-point golden ratio
+  uint64_t fr = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+  float f = (float)(fr >> 40) * 0x1p-24f;
+  float t = (float)(2 * i + 1) / (float)n;
+  float z = 1.0f - t;
+  float rr = sqrtf(t * (2.0f - t));
+  float sn, cs;
+  sincospif(2.0f * f, &sn, &cs);
+  float3 p = f3(rr * cs, rr * sn, z);
+  return f3(fmaf(R[0], p.x, fmaf(R[1], p.y, R[2] * p.z)), fmaf(R[3], p.x, fmaf(R[4], p.y, R[5] * p.z)),
+            fmaf(R[6], p.x, fmaf(R[7], p.y, R[8] * p.z)));
+}
+
+__global__ __launch_bounds__(kTraceBlock) void k_classify(VolumeSet vs, SceneGPU sc, ClassifyArgs A, int32_t* back,
+                                                          uint32_t* tfront) {
+  __shared__ int stack[kMaxDepth * kTraceBlock];
+  int64_t gid = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
+  if (gid >= A.base[vs.n]) return;
+  int v = 0;
+  while (v + 1 < vs.n && gid >= A.base[v + 1]) v++;
+  const VolumeGPU& V = vs.v[v];
+  int64_t local = gid - A.base[v];
+  int per_probe = A.K * V.rays;
+  int q = (int)(local / per_probe);
+  int rem = (int)(local - (int64_t)q * per_probe);
+  int k = rem / V.rays, r = rem - k * V.rays;
+  float3 o = probe_position(V, q);
+  float3 w = sf_direction(r, V.rays, A.R[k]);
+  Ray ray = make_ray(o, w);
+  float t;
+  int tri = traverse<false, true>(sc, ray, INFINITY, t, stack + threadIdx.x, kTraceBlock);
+  if (tri < 0) return;
+  int gq = V.probe_base + q;
+  if (dot(w, tri_normal(sc, tri)) > 0.0f)
+    atomicAdd(&back[gq], 1);
+  else
+    atomicMin(&tfront[gq], __float_as_uint(t));
+}
+
+__device__ __forceinline__ bool inside_grown_box(const VolumeGPU& V, ObjectBoxes ob, float3 P) {
+  float D = fminf(V.spacing[0], fminf(V.spacing[1], V.spacing[2]));
+  float b = 0.75f * D * V.bias;
+  for (int o = 0; o < ob.n; o++) {
+    bool in = true;
+    float Pa[3] = {P.x, P.y, P.z};
+    for (int a = 0; a < 3; a++) {
+      float g = V.spacing[a] + b;
+      in = in && Pa[a] >= ob.lo[3 * o + a] - g && Pa[a] <= ob.hi[3 * o + a] + g;
+    }
+    if (in) return true;
+  }
+  return false;
+}
+
+__global__ void k_classify_finish(VolumeSet vs, ObjectBoxes ob, int K, const int32_t* back, const uint32_t* tfront) {
+  int v = blockIdx.y;
+  if (v >= vs.n) return;
+  const VolumeGPU& V = vs.v[v];
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= V.n_probes) return;
+  int gq = V.probe_base + q;
+  float smax = fmaxf(V.spacing[0], fmaxf(V.spacing[1], V.spacing[2]));
+  float tf = __uint_as_float(tfront[gq]);
+  uint8_t st;
+  if ((double)back[gq] / ((double)K * V.rays) > 0.25) st = IRF_OFF;
+  else if (tf < smax) st = IRF_NEWLY_VIGILANT;
+  else st = IRF_SLEEPING;
+  if (st == IRF_SLEEPING && inside_grown_box(V, ob, probe_position(V, q))) st = IRF_NEWLY_AWAKE;
+  V.states[q] = st;
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+// ---- debug records
+
+__global__ void k_records(VolumeSet vs, int vol, SceneGPU sc, FrameScratch fs, int n_lights, irf_ray_record* out,
+                          int64_t count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const FrameCounters& C = *fs.counters;
+  int64_t id = C.ray_base[vol] + i;
+  const VolumeGPU& V = vs.v[vol];
+  HitRec h = fs.hits[id];
+  float4 r = fs.rays[id];
+  irf_ray_record rec;
+  rec.tri = h.tri >= 0 ? bits_i(sc.tris[(size_t)h.tri * 3].w) : -1;
+  rec.t = h.t;
+  rec.rgb[0] = r.x;
+  rec.rgb[1] = r.y;
+  rec.rgb[2] = r.z;
+  rec.d = r.w;
+  uint32_t vis = 0;
+  for (int l = 0; l < n_lights; l++)
+    if (fs.vis[(int64_t)l * fs.max_rays + id]) vis |= 1u << l;
+  rec.vis = vis;
+  rec.probe = fs.active[C.slot_base[vol] + (int)(i / V.rays)] - V.probe_base;
+  out[i] = rec;
+}
+
+// ---- launches
+
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, hipStream_t s) {
+  if (fs.max_rays == 0) return;
+  hipLaunchKernelGGL(k_trace, dim3(blocks_for(fs.max_rays, kTraceBlock)), dim3(kTraceBlock), 0, s, vs, sc, fs);
+}
+
+void launch_shadow(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s) {
+  int nl = L.n_dir + L.n_point;
+  if (fs.max_rays == 0 || nl == 0) return;
+  hipLaunchKernelGGL(k_shadow, dim3(blocks_for(fs.max_rays * nl, kTraceBlock)), dim3(kTraceBlock), 0, s, vs, sc, L,
+                     fs);
+}
+
+void launch_shade(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s) {
+  if (fs.max_rays == 0) return;
+  hipLaunchKernelGGL(k_shade, dim3(blocks_for(fs.max_rays, kTraceBlock)), dim3(kTraceBlock), 0, s, vs, sc, L, fs);
+}
+
+void launch_classify(const VolumeSet& vs, SceneGPU sc, ObjectBoxes boxes, const float* rotations, int K,
+                     int32_t* back, uint32_t* tfront, hipStream_t s) {
+  ClassifyArgs A;
+  for (int k = 0; k < K; k++)
+    for (int i = 0; i < 9; i++) A.R[k][i] = rotations[9 * k + i];
+  A.K = K;
+  A.base[0] = 0;
+  int total_probes = 0;
+  for (int v = 0; v < vs.n; v++) {
+    A.base[v + 1] = A.base[v] + (int64_t)vs.v[v].n_probes * K * vs.v[v].rays;
+    total_probes += vs.v[v].n_probes;
+  }
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(total_probes, 256)), dim3(256), 0, s, (uint32_t*)back, 0u,
+                     (int64_t)total_probes);
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(total_probes, 256)), dim3(256), 0, s, tfront,
+                     (uint32_t)0x7f800000u, (int64_t)total_probes);
+  if (A.base[vs.n] > 0)
+    hipLaunchKernelGGL(k_classify, dim3(blocks_for(A.base[vs.n], kTraceBlock)), dim3(kTraceBlock), 0, s, vs, sc, A,
+                       back, tfront);
+  int maxp = 0;
+  for (int v = 0; v < vs.n; v++) maxp = vs.v[v].n_probes > maxp ? vs.v[v].n_probes : maxp;
+  hipLaunchKernelGGL(k_classify_finish, dim3(blocks_for(maxp, 256), vs.n), dim3(256), 0, s, vs, boxes, K, back,
+                     tfront);
+}
+
+void launch_records(const VolumeSet& vs, int vol, SceneGPU sc, FrameScratch fs, int n_lights, irf_ray_record* out,
+                    int64_t count, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_records, dim3(blocks_for(count, 256)), dim3(256), 0, s, vs, vol, sc, fs, n_lights, out, count);
+}
+
+}  // namespace irf

@@ -1,0 +1,291 @@
+"""Python binding of the irf C ABI (``include/irf.h``).
+
+Argument marshalling only: every step of the probe update and query runs in
+the HIP kernels of ``libirf.so``.  PyTorch provides device memory (the
+volume buffers, query inputs and outputs) and the current HIP stream.  If
+the library is missing or the GPU is unavailable, calls raise instead of
+falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libirf.so")
+
+OK, E_INVALID, E_NOMEM, E_HIP, E_STATE, E_UNSUPPORTED = range(6)
+OFF, SLEEPING, NEWLY_AWAKE, NEWLY_VIGILANT, AWAKE, VIGILANT = range(6)
+ATLAS_F32, ATLAS_F16 = 0, 1
+BLEND = {"f32": 0, "bf16": 1, "f16": 2}
+MAX_VOLUMES, MAX_LIGHTS, MAX_ROTATIONS = 8, 32, 8
+
+
+class IrfError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("vertices", C.c_void_p), ("n_vertices", C.c_int64), ("indices", C.c_void_p),
+                ("n_triangles", C.c_int64), ("tri_material", C.c_void_p), ("tri_object", C.c_void_p),
+                ("albedo", C.c_void_p), ("emission", C.c_void_p), ("n_materials", C.c_int32)]
+
+
+class LightsDesc(C.Structure):
+    _fields_ = [("dir_to_light", C.c_void_p), ("dir_irradiance", C.c_void_p), ("n_dir", C.c_int32),
+                ("point_pos", C.c_void_p), ("point_intensity", C.c_void_p), ("n_point", C.c_int32),
+                ("sky", C.c_float * 3)]
+
+
+class VolumeDescC(C.Structure):
+    _fields_ = [("origin", C.c_float * 3), ("spacing", C.c_float * 3), ("counts", C.c_int32 * 3),
+                ("rays_per_probe", C.c_int32), ("hysteresis_irr", C.c_float), ("hysteresis_dist", C.c_float),
+                ("cos_power", C.c_float), ("self_shadow_bias", C.c_float), ("max_distance", C.c_float),
+                ("cheb_power", C.c_int32), ("atlas_dtype", C.c_int32), ("blend", C.c_int32)]
+
+
+class BufferSizes(C.Structure):
+    _fields_ = [("n_probes", C.c_int64), ("irradiance_bytes", C.c_int64), ("distance_bytes", C.c_int64),
+                ("states_bytes", C.c_int64), ("offsets_bytes", C.c_int64)]
+
+
+class KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
+RECORD_DTYPE = np.dtype([("tri", np.int32), ("t", np.float32), ("rgb", np.float32, 3), ("d", np.float32),
+                         ("vis", np.uint32), ("probe", np.int32)])
+
+# every function the header declares, with (restype, argtypes)
+_vp, _i32, _i64 = C.c_void_p, C.c_int32, C.c_int64
+SIGNATURES = {
+    "irf_status_str": (C.c_char_p, [C.c_int]),
+    "irf_last_error": (C.c_char_p, []),
+    "irf_version": (C.c_char_p, []),
+    "irf_create": (C.c_int, [_i32, C.POINTER(_vp)]),
+    "irf_destroy": (None, [_vp]),
+    "irf_set_scene": (C.c_int, [_vp, C.POINTER(SceneDesc)]),
+    "irf_set_lights": (C.c_int, [_vp, C.POINTER(LightsDesc)]),
+    "irf_create_volume": (C.c_int, [_vp, C.POINTER(VolumeDescC), C.POINTER(_i32)]),
+    "irf_volume_sizes": (C.c_int, [_vp, _i32, C.POINTER(BufferSizes)]),
+    "irf_bind_volume": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "irf_classify": (C.c_int, [_vp, _vp, _i32, _vp]),
+    "irf_update_probes": (C.c_int, [_vp, _vp, _vp]),
+    "irf_query_irradiance": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp]),
+    "irf_ray_records": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(_i64), _vp]),
+    "irf_frame_stats": (C.c_int, [_vp, C.POINTER(_i64 * 4), _vp]),
+    "irf_profile_enable": (C.c_int, [_vp, _i32]),
+    "irf_profile_read": (C.c_int, [_vp, _vp, _i32, C.POINTER(_i32), _i32]),
+    "irf_validate_volume_desc": (C.c_int, [C.POINTER(VolumeDescC)]),
+    "irf_bvh_stats": (C.c_int, [C.POINTER(SceneDesc), C.POINTER(C.c_double * 5)]),
+}
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Loads libirf.so (building it first only if it is absent)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _build
+            _build.build()
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise IrfError(status, load().irf_last_error().decode())
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p) if a is not None and a.size else None
+
+
+def scene_desc(scene):
+    keep = [_np(scene.vertices, np.float32), _np(scene.indices, np.uint32), _np(scene.tri_material, np.uint32),
+            _np(scene.tri_object, np.uint32), _np(scene.albedo, np.float32), _np(scene.emission, np.float32)]
+    d = SceneDesc(_ptr(keep[0]), keep[0].shape[0], _ptr(keep[1]), keep[1].shape[0], _ptr(keep[2]),
+                  _ptr(keep[3]), keep[4].ctypes.data_as(C.c_void_p), keep[5].ctypes.data_as(C.c_void_p),
+                  keep[4].shape[0])
+    return d, keep
+
+
+def volume_desc(desc) -> VolumeDescC:
+    d = VolumeDescC()
+    for a in range(3):
+        d.origin[a] = desc.origin[a]
+        d.spacing[a] = desc.spacing[a]
+        d.counts[a] = desc.counts[a]
+    d.rays_per_probe = desc.rays_per_probe
+    d.hysteresis_irr = desc.hysteresis_irr
+    d.hysteresis_dist = desc.hysteresis_dist
+    d.cos_power = desc.cos_power
+    d.self_shadow_bias = desc.self_shadow_bias
+    d.max_distance = desc.max_distance
+    d.cheb_power = desc.cheb_power
+    d.atlas_dtype = ATLAS_F16 if desc.atlas_f16 else ATLAS_F32
+    d.blend = BLEND[desc.blend]
+    return d
+
+
+def validate_volume_desc(desc) -> None:
+    d = volume_desc(desc)
+    _check(load().irf_validate_volume_desc(C.byref(d)))
+
+
+def bvh_stats(scene) -> dict:
+    d, keep = scene_desc(scene)
+    out = (C.c_double * 5)()
+    _check(load().irf_bvh_stats(C.byref(d), C.byref(out)))
+    return {"nodes": int(out[0]), "leaves": int(out[1]), "depth": int(out[2]), "sah": out[3], "valid": out[4] == 1.0}
+
+
+def _stream(torch):
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Volume:
+    """Caller-owned (torch) device buffers of one probe volume."""
+
+    def __init__(self, ctx: "Context", vid: int, desc, torch, device):
+        self.ctx, self.id, self.desc = ctx, vid, desc
+        sz = BufferSizes()
+        _check(load().irf_volume_sizes(ctx.handle, vid, C.byref(sz)))
+        P = int(sz.n_probes)
+        dt = torch.float16 if desc.atlas_f16 else torch.float32
+        self.irradiance = torch.zeros((P, 8, 8, 4), dtype=dt, device=device)
+        self.distance = torch.zeros((P, 16, 16, 2), dtype=dt, device=device)
+        self.states = torch.full((P,), NEWLY_VIGILANT, dtype=torch.uint8, device=device)
+        self.offsets = torch.zeros((P, 3), dtype=torch.float32, device=device)
+        assert self.irradiance.numel() * self.irradiance.element_size() == sz.irradiance_bytes
+        assert self.distance.numel() * self.distance.element_size() == sz.distance_bytes
+        self.rebind()
+
+    def rebind(self):
+        _check(load().irf_bind_volume(self.ctx.handle, self.id, C.c_void_p(self.irradiance.data_ptr()),
+                                      C.c_void_p(self.distance.data_ptr()), C.c_void_p(self.states.data_ptr()),
+                                      C.c_void_p(self.offsets.data_ptr())))
+
+    @property
+    def n_probes(self) -> int:
+        return int(self.states.shape[0])
+
+
+class Context:
+    """One irf context on one GPU."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        if not torch.cuda.is_available():
+            raise IrfError(E_HIP, "no GPU available for the irf library")
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        _check(load().irf_create(device, C.byref(h)))
+        self.handle = h
+        self.volumes: List[Volume] = []
+        self.n_lights = 0
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().irf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_scene(self, scene) -> None:
+        d, keep = scene_desc(scene)
+        _check(load().irf_set_scene(self.handle, C.byref(d)))
+
+    def set_lights(self, lights) -> None:
+        keep = [_np(lights.dir_to_light, np.float32).reshape(-1, 3), _np(lights.dir_irradiance, np.float32).reshape(-1, 3),
+                _np(lights.point_pos, np.float32).reshape(-1, 3), _np(lights.point_intensity, np.float32).reshape(-1, 3)]
+        d = LightsDesc(_ptr(keep[0]), _ptr(keep[1]), keep[0].shape[0], _ptr(keep[2]), _ptr(keep[3]), keep[2].shape[0])
+        for a in range(3):
+            d.sky[a] = float(lights.sky[a])
+        _check(load().irf_set_lights(self.handle, C.byref(d)))
+        self.n_lights = keep[0].shape[0] + keep[2].shape[0]
+
+    def create_volume(self, desc) -> Volume:
+        d = volume_desc(desc)
+        vid = C.c_int32()
+        _check(load().irf_create_volume(self.handle, C.byref(d), C.byref(vid)))
+        v = Volume(self, vid.value, desc, self.torch, self.device)
+        self.volumes.append(v)
+        return v
+
+    def classify(self, rotations) -> None:
+        R = _np(rotations, np.float32).reshape(-1, 9)
+        _check(load().irf_classify(self.handle, _ptr(R), R.shape[0], _stream(self.torch)))
+
+    def update_probes(self, rotation) -> None:
+        R = _np(rotation, np.float32).reshape(9)
+        _check(load().irf_update_probes(self.handle, _ptr(R), _stream(self.torch)))
+
+    def query_irradiance(self, pos, nrm, view, out=None):
+        torch = self.torch
+        n = int(pos.shape[0])
+        for t in (pos, nrm, view):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (n, 3):
+                raise IrfError(E_INVALID, "query inputs must be contiguous float32 CUDA tensors of shape [n, 3]")
+        if out is None:
+            out = torch.empty((n, 3), dtype=torch.float32, device=pos.device)
+        _check(load().irf_query_irradiance(self.handle, C.c_void_p(pos.data_ptr()), C.c_void_p(nrm.data_ptr()),
+                                           C.c_void_p(view.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                           _stream(self.torch)))
+        return out
+
+    def frame_stats(self) -> dict:
+        out = (C.c_int64 * 4)()
+        _check(load().irf_frame_stats(self.handle, C.byref(out), _stream(self.torch)))
+        return {"active_probes": out[0], "probe_rays": out[1], "shadow_rays": out[2], "front_hits": out[3]}
+
+    def profile(self, enable: bool = True) -> None:
+        _check(load().irf_profile_enable(self.handle, int(enable)))
+
+    def profile_read(self, reset: bool = True) -> dict:
+        n = C.c_int32()
+        _check(load().irf_profile_read(self.handle, None, 0, C.byref(n), 0))
+        arr = (KernelTime * max(1, n.value))()
+        _check(load().irf_profile_read(self.handle, arr, n.value, C.byref(n), int(reset)))
+        return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n.value)}
+
+    def ray_records(self, vol: int) -> np.ndarray:
+        torch = self.torch
+        cnt = C.c_int64()
+        _check(load().irf_ray_records(self.handle, vol, None, 0, C.byref(cnt), _stream(torch)))
+        n = int(cnt.value)
+        buf = torch.empty((max(1, n) * RECORD_DTYPE.itemsize,), dtype=torch.uint8, device=self.device)
+        _check(load().irf_ray_records(self.handle, vol, C.c_void_p(buf.data_ptr()), n, C.byref(cnt), _stream(torch)))
+        torch.cuda.current_stream().synchronize()
+        return buf[: n * RECORD_DTYPE.itemsize].cpu().numpy().view(RECORD_DTYPE)
+
+
+def build_workload(w, device: int = 0):
+    """Context with the workload's scene, lights and volumes (in order)."""
+    ctx = Context(device)
+    ctx.set_scene(w.scene)
+    ctx.set_lights(w.lights)
+    for d in w.volumes:
+        ctx.create_volume(d)
+    return ctx

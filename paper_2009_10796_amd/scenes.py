@@ -438,23 +438,49 @@ def camera_gbuffer(eye, target, vfov_deg, width, height, boxes, quads, ground):
     best = np.where(ok, t, best)
     nrm[ok] = (0.0, 1.0, 0.0)
     inv = 1.0 / np.where(d == 0, 1e-30, d)
+    pix_x = np.tile(np.arange(width), height)
+    pix_y = np.repeat(np.arange(height), width)
+
+    def candidates(lo, hi):
+        # pixels inside the screen rectangle spanned by the box's corners
+        cs = np.array([[x, y, z] for x in (lo[0], hi[0]) for y in (lo[1], hi[1]) for z in (lo[2], hi[2])]) - eye
+        zc = cs @ fwd
+        if np.any(zc <= 1e-6):
+            return np.arange(n_pix)
+        sx = (cs @ right) / (zc * tw)
+        sy = (cs @ up) / (zc * th)
+        x0 = int(np.floor((sx.min() + 1) / 2 * width)) - 1
+        x1 = int(np.ceil((sx.max() + 1) / 2 * width)) + 1
+        y0 = int(np.floor((1 - sy.max()) / 2 * height)) - 1
+        y1 = int(np.ceil((1 - sy.min()) / 2 * height)) + 1
+        x0, y0 = max(x0, 0), max(y0, 0)
+        x1, y1 = min(x1, width), min(y1, height)
+        if x0 >= x1 or y0 >= y1:
+            return np.zeros(0, dtype=np.int64)
+        yy, xx = np.meshgrid(np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
+        return (yy * width + xx).ravel()
+
     for lo, hi in boxes:
         lo = np.asarray(lo)
         hi = np.asarray(hi)
-        t0 = (lo - eye) * inv
-        t1 = (hi - eye) * inv
+        idx = candidates(lo, hi)
+        if idx.size == 0:
+            continue
+        t0 = (lo - eye) * inv[idx]
+        t1 = (hi - eye) * inv[idx]
         tmin = np.minimum(t0, t1)
         tmax = np.maximum(t0, t1)
         tn = tmin.max(axis=1)
         tf = tmax.min(axis=1)
-        hit = (tn <= tf) & (tn > 0) & (tn < best)
+        hit = (tn <= tf) & (tn > 0) & (tn < best[idx])
         if not np.any(hit):
             continue
-        axis = tmin.argmax(axis=1)
-        n = np.zeros((n_pix, 3))
-        n[np.arange(n_pix), axis] = -np.sign(d[np.arange(n_pix), axis])
-        best = np.where(hit, tn, best)
-        nrm[hit] = n[hit]
+        hi_idx = idx[hit]
+        axis = tmin[hit].argmax(axis=1)
+        n = np.zeros((hi_idx.size, 3))
+        n[np.arange(hi_idx.size), axis] = -np.sign(d[hi_idx, axis])
+        best[hi_idx] = tn[hit]
+        nrm[hi_idx] = n
     for (ax, c0, (a0, a1), (b0, b1), s) in quads:
         k = 0 if ax == "x" else 2
         other = 2 if ax == "x" else 0

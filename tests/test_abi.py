@@ -1,0 +1,92 @@
+"""The C ABI library: it loads, exports every function its header declares,
+and its host-side logic (validation, BVH build) behaves without a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2009_10796_amd import irf, scenes as S
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "irf.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(irf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = irf.load()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(irf.SIGNATURES), set(names) ^ set(irf.SIGNATURES)
+
+
+def test_status_strings_and_version():
+    lib = irf.load()
+    assert lib.irf_status_str(0) == b"IRF_OK"
+    assert lib.irf_status_str(4) == b"IRF_E_STATE"
+    assert lib.irf_version().startswith(b"irf")
+
+
+def _good():
+    return S.VolumeDesc(origin=(0, 0, 0), spacing=(1, 1, 1), counts=(4, 4, 4), rays_per_probe=64)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("counts", (1, 4, 4)), ("spacing", (1, 0, 1)), ("spacing", (1, float("nan"), 1)),
+    ("rays_per_probe", 48), ("rays_per_probe", 0), ("rays_per_probe", 2048),
+    ("hysteresis_irr", 1.5), ("hysteresis_dist", -0.1), ("cos_power", 0.0),
+    ("self_shadow_bias", -1.0), ("cheb_power", 0), ("cheb_power", 5), ("max_distance", float("inf")),
+    ("origin", (0, float("inf"), 0)),
+])
+def test_volume_validation_rejects(field, value):
+    d = _good()
+    setattr(d, field, value)
+    with pytest.raises(irf.IrfError) as e:
+        irf.validate_volume_desc(d)
+    assert e.value.status == irf.E_INVALID
+
+
+def test_volume_validation_accepts():
+    irf.validate_volume_desc(_good())
+    d = _good()
+    d.rays_per_probe, d.atlas_f16, d.blend = 1024, True, "bf16"
+    irf.validate_volume_desc(d)
+
+
+@pytest.mark.parametrize("make", [lambda: S.config0().scene, lambda: S.random_triangle_soup(3000),
+                                  lambda: S.sphere_scene(3.0, 2), lambda: S.config1(gbuffer=False).scene])
+def test_host_bvh_is_valid_and_shallow(make):
+    st = irf.bvh_stats(make())
+    assert st["valid"]
+    assert 1 <= st["depth"] <= 48
+    assert st["leaves"] >= 1
+
+
+def test_host_bvh_single_triangle_and_empty():
+    verts = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32)
+    sc = S.Scene(verts, np.array([[0, 1, 2]], np.uint32), np.zeros(1, np.uint32), np.zeros(1, np.uint32),
+                 np.full((1, 3), 0.5, np.float32), np.zeros((1, 3), np.float32))
+    assert irf.bvh_stats(sc)["valid"]
+    assert irf.bvh_stats(S.empty_scene())["valid"]
+
+
+def test_scene_validation_rejects_bad_indices_and_materials():
+    sc = S.config0().scene
+    bad = S.Scene(sc.vertices, sc.indices.copy(), sc.tri_material, sc.tri_object, sc.albedo, sc.emission)
+    bad.indices[3, 1] = 10_000
+    with pytest.raises(irf.IrfError):
+        irf.bvh_stats(bad)
+    bad = S.Scene(sc.vertices, sc.indices, sc.tri_material.copy(), sc.tri_object, sc.albedo, sc.emission)
+    bad.tri_material[0] = 99
+    with pytest.raises(irf.IrfError):
+        irf.bvh_stats(bad)
+    bad = S.Scene(sc.vertices.copy(), sc.indices, sc.tri_material, sc.tri_object, sc.albedo, sc.emission)
+    bad.vertices[0, 0] = np.nan
+    with pytest.raises(irf.IrfError):
+        irf.bvh_stats(bad)
