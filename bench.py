@@ -25,6 +25,8 @@ if ROOT not in sys.path:
 
 METRIC = "probe update ms/frame, Grays/s, queries/s; MFMA vs FP32 blend at stated error"
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+NODE_BYTES, TRI_BYTES, RAY_IO_BYTES = 64, 48, 32
 
 
 def query_bytes(w, states):
@@ -122,16 +124,31 @@ def main():
     update_ms = sum(kern[k]["avg_us"] for k in upd) / 1e3
     query_ms = kern["query"]["avg_us"] / 1e3
     prim, shad = stats["probe_rays"], stats["shadow_rays"]
+    trav = ctx.traversal_stats()
     states = ctx.volumes[0].states.cpu().numpy()
     qbytes, mean_sampled = query_bytes(w, states)
+
+    def hbm(kernel, nbytes):
+        gbs = nbytes / (kern[kernel]["avg_us"] * 1e-6) / 1e9
+        return {"kernel": kernel, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "algorithmic_bytes_per_launch": int(nbytes)}
+
+    rooflines = {
+        "trace": hbm("trace", trav["probe_nodes"] * NODE_BYTES + trav["probe_tris"] * TRI_BYTES + prim * RAY_IO_BYTES),
+        "query": hbm("query", qbytes),
+    }
+    if "shadow" in kern:
+        rooflines["shadow"] = hbm("shadow", trav["shadow_nodes"] * NODE_BYTES + trav["shadow_tris"] * TRI_BYTES
+                                  + shad * RAY_IO_BYTES)
+    n_rays = w.volumes[0].rays_per_probe
+    blend_flops = 2.0 * n_rays * (36 * 3 + 196 * 2) * stats["active_probes"]
+    bk = [k for k in kern if k.startswith("blend")][0]
+    tf = blend_flops / (kern[bk]["avg_us"] * 1e-6) / 1e12
+    rooflines["blend"] = {"kernel": bk, "bound": "alu", "achieved": round(tf, 3), "peak": FP32_PEAK_TFLOPS,
+                          "unit": "TFLOP/s", "frac": round(tf / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                          "algorithmic_flops_per_launch": blend_flops}
     dominant = max(kern, key=lambda k: kern[k]["avg_us"])
-    roof = None
-    q_gbs = qbytes / (query_ms * 1e-3) / 1e9
-    roof_query = {"kernel": "query", "bound": "hbm", "achieved": round(q_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(q_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                  "algorithmic_bytes_per_launch": qbytes}
-    if dominant == "query":
-        roof = roof_query
+    roof = rooflines.get(dominant if not dominant.startswith("blend") else "blend")
     line = {
         "metric": METRIC,
         "value": round(ms_step, 4),
@@ -157,7 +174,8 @@ def main():
         "queries_per_s": round(q.n / (query_ms * 1e-3), 1),
         "kernels_us": kern,
         "dominant_kernel": dominant,
-        "query_roofline": roof_query,
+        "traversal": {k: int(v) for k, v in trav.items()},
+        "kernel_rooflines": rooflines,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -215,6 +215,12 @@ irf_status irf_ray_records(irf_ctx* ctx, int32_t volume, irf_ray_record* out, in
    out[3] probe rays that hit a front face. */
 irf_status irf_frame_stats(irf_ctx* ctx, int64_t out[4], void* stream);
 
+/* Traversal work of the last update, re-traced in a counting mode that is
+   never part of a frame (synchronizes `stream`): out[0] BVH nodes fetched
+   and out[1] triangles tested by the probe rays, out[2] nodes and out[3]
+   triangles by the shadow rays.  A node is 64 bytes, a triangle 48. */
+irf_status irf_traversal_stats(irf_ctx* ctx, int64_t out[4], void* stream);
+
 /* Kernel timing.  While enabled, every kernel the library launches is
    bracketed by HIP events recorded on the stream it is launched on;
    irf_profile_read synchronizes those events and returns, per kernel name,

@@ -533,6 +533,26 @@ void orc_blend_probe(int32_t n, const double* omega, const double* rgb, const do
 }
 
 /* ------------------------------------------------------------------- query */
+/* smallest and largest value of the four bilinear taps (diagnostics for the
+   float32 sensitivity estimate only) */
+static void footprint_range(const double* tile, int32_t m, int32_t nch, const double v[3], double* lo, double* hi) {
+  int32_t k = m - 2;
+  double p[2];
+  orc_oct_encode(v, p);
+  double cx = 1.0 + (0.5 * p[0] + 0.5) * k - 0.5;
+  double cy = 1.0 + (0.5 * p[1] + 0.5) * k - 0.5;
+  int32_t x0 = (int32_t)floor(cx), y0 = (int32_t)floor(cy);
+  if (x0 < 0) x0 = 0;
+  if (x0 > k) x0 = k;
+  if (y0 < 0) y0 = 0;
+  if (y0 > k) y0 = k;
+  for (int c = 0; c < nch; c++) {
+    double a = tile[(y0 * m + x0) * nch + c], b = tile[(y0 * m + x0 + 1) * nch + c];
+    double cc = tile[((y0 + 1) * m + x0) * nch + c], dd = tile[((y0 + 1) * m + x0 + 1) * nch + c];
+    lo[c] = fmin(fmin(a, b), fmin(cc, dd));
+    hi[c] = fmax(fmax(a, b), fmax(cc, dd));
+  }
+}
 static int64_t vol_probes(const orc_volume* V) { return (int64_t)V->counts[0] * V->counts[1] * V->counts[2]; }
 
 static void probe_position(const orc_volume* V, int64_t q, double P[3]) {
@@ -586,19 +606,23 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
     double r = len3(z);
     double wv = 1.0, s = 8.0;
     if (r > 0.0) {
-      double zd[3] = {z[0] / r, z[1] / r, z[2] / r}, mm[2];
+      double zd[3] = {z[0] / r, z[1] / r, z[2] / r}, mm[2], lo[2], hi[2];
       orc_sample_tile(V->dist + q * 16 * 16 * 2, 16, 2, zd, mm);
       if (r > mm[0]) {
+        footprint_range(V->dist + q * 16 * 16 * 2, 16, 2, zd, lo, hi);
         double var = fmax(mm[1] - mm[0] * mm[0], 0.0);
         double dl = r - mm[0];
         double ch = var / (var + dl * dl);
         wv = pow(ch, (double)V->cheb_power);
         /* relative float32 sensitivity of the Chebyshev weight (units of u):
-           cancellation in mu2 - mu^2 and in r - mu, incl. bilinear position */
-        double sp = 32.0 * (fabs(mm[0]) + r);
-        double sv = 32.0 * (fabs(mm[1]) + 2.0 * mm[0] * mm[0] + sp * fabs(mm[0]));
+           the bilinear position (k * few u of a texel) and the rounding of
+           mu, mu2 and r enter through the cancellations mu2 - mu^2, r - mu */
+        double dmu = 4.0 * fabs(mm[0]) + 32.0 * (hi[0] - lo[0]);
+        double dmu2 = 4.0 * fabs(mm[1]) + 32.0 * (hi[1] - lo[1]);
+        double dvar = dmu2 + 2.0 * fabs(mm[0]) * dmu + 4.0 * (fabs(mm[1]) + mm[0] * mm[0]);
+        double ddl = 4.0 * r + dmu;
         if (var > 0.0)
-          s += V->cheb_power * ((1.0 - ch) * sv / var + 2.0 * (1.0 - ch) * sp / dl);
+          s += V->cheb_power * (1.0 - ch) * (dvar / var + 2.0 * ddl / dl);
         else
           s = INFINITY; /* zero variance: float32 rounding decides the weight */
       }
@@ -678,6 +702,36 @@ void orc_query_batch(const orc_volume* vols, int32_t nvol, int64_t nq, const flo
 }
 
 /* ----------------------------------------------------------------- shading */
+/* Lambertian radiance leaving front-face hit X (geometric normal ng) toward
+   -w, given which shadow rays are unblocked (bit l of vis): emission plus
+   albedo x (direct irradiance / pi + previous-frame probe irradiance). */
+static void front_radiance(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol, int32_t m,
+                           const double X[3], const double ng[3], const double w[3], uint32_t vis, double rgb[3],
+                           double kq[3], int32_t* cage, int32_t* n_cage) {
+  double direct[3] = {0, 0, 0};
+  double xmax = fmax(fabs(X[0]), fmax(fabs(X[1]), fabs(X[2])));
+  double eps = 1e-4 * fmax(1.0, xmax);
+  double Xs[3] = {X[0] + eps * ng[0], X[1] + eps * ng[1], X[2] + eps * ng[2]};
+  int32_t li = 0;
+  for (int32_t l = 0; l < L->n_dir; l++, li++) {
+    if (!(vis >> li & 1u)) continue;
+    double dl[3] = {L->dir_to_light[3 * l], L->dir_to_light[3 * l + 1], L->dir_to_light[3 * l + 2]};
+    double c = dot3(ng, dl);
+    for (int k = 0; k < 3; k++) direct[k] += (double)L->dir_irradiance[3 * l + k] * c;
+  }
+  for (int32_t l = 0; l < L->n_point; l++, li++) {
+    if (!(vis >> li & 1u)) continue;
+    double u[3] = {L->point_pos[3 * l] - Xs[0], L->point_pos[3 * l + 1] - Xs[1], L->point_pos[3 * l + 2] - Xs[2]};
+    double dist = len3(u);
+    double c = dot3(ng, u) / dist;
+    for (int k = 0; k < 3; k++) direct[k] += (double)L->point_intensity[3 * l + k] * c / (dist * dist);
+  }
+  double wo[3] = {-w[0], -w[1], -w[2]}, ind[3] = {0, 0, 0};
+  for (int k = 0; k < 3; k++) kq[k] = 0.0;
+  if (nvol > 0) orc_query(vols, nvol, X, ng, wo, ind, kq, cage, n_cage);
+  for (int k = 0; k < 3; k++) rgb[k] = s->emission[m * 3 + k] + s->albedo[m * 3 + k] * (direct[k] / M_PI + ind[k]);
+}
+
 /* Section "Probe Update" (hit shading) and the backface rule of the
    self-shadow-bias section: a miss sees the sky at the distance clamp; a
    backface records radiance 0 and 20 % of its distance; a front face is
@@ -708,23 +762,19 @@ void orc_shade_ray(const orc_scene* s, const orc_lights* L, const orc_volume* vo
     return;
   }
   rec->d = fmin(h.t, dmax);
-  double X[3], wo[3] = {-w[0], -w[1], -w[2]};
+  double X[3];
   for (int a = 0; a < 3; a++) X[a] = o[a] + h.t * w[a];
   int32_t m = s->material[h.tri];
-  double direct[3] = {0, 0, 0};
+  /* shadow rays from the lifted hit point; any triangle, either side, occludes */
   double xmax = fmax(fabs(X[0]), fmax(fabs(X[1]), fabs(X[2])));
   double eps = 1e-4 * fmax(1.0, xmax);
   double Xs[3] = {X[0] + eps * ng[0], X[1] + eps * ng[1], X[2] + eps * ng[2]};
   int32_t li = 0;
   for (int32_t l = 0; l < L->n_dir; l++, li++) {
     double dl[3] = {L->dir_to_light[3 * l], L->dir_to_light[3 * l + 1], L->dir_to_light[3 * l + 2]};
-    double c = dot3(ng, dl);
-    if (c <= 0.0) continue;
+    if (dot3(ng, dl) <= 0.0) continue;
     int amb = 0;
-    if (!occluded(s, Xs, dl, INFINITY, &amb)) {
-      rec->vis |= 1u << li;
-      for (int k = 0; k < 3; k++) direct[k] += (double)L->dir_irradiance[3 * l + k] * c;
-    }
+    if (!occluded(s, Xs, dl, INFINITY, &amb)) rec->vis |= 1u << li;
     if (amb) rec->flags |= ORC_F_SHADOW;
   }
   for (int32_t l = 0; l < L->n_point; l++, li++) {
@@ -732,22 +782,22 @@ void orc_shade_ray(const orc_scene* s, const orc_lights* L, const orc_volume* vo
     double dist = len3(u);
     if (!(dist > 0.0)) continue;
     double uh[3] = {u[0] / dist, u[1] / dist, u[2] / dist};
-    double c = dot3(ng, uh);
-    if (c <= 0.0) continue;
+    if (dot3(ng, uh) <= 0.0) continue;
     int amb = 0;
-    if (!occluded(s, Xs, uh, dist * (1.0 - 1e-6), &amb)) {
-      rec->vis |= 1u << li;
-      for (int k = 0; k < 3; k++) direct[k] += (double)L->point_intensity[3 * l + k] * c / (dist * dist);
-    }
+    if (!occluded(s, Xs, uh, dist * (1.0 - 1e-6), &amb)) rec->vis |= 1u << li;
     if (amb) rec->flags |= ORC_F_SHADOW;
   }
-  double ind[3] = {0, 0, 0}, kq[3] = {0, 0, 0};
-  if (nvol > 0) orc_query(vols, nvol, X, ng, wo, ind, kq, rec->cage, &rec->n_cage);
-  for (int k = 0; k < 3; k++) {
-    double alb = s->albedo[m * 3 + k];
-    rec->rgb[k] = s->emission[m * 3 + k] + alb * (direct[k] / M_PI + ind[k]);
-    rec->kappa[k] = alb * (kq[k] + 16.0 * direct[k] / M_PI) + 8.0 * fabs(rec->rgb[k]);
-  }
+  double kq[3];
+  front_radiance(s, L, vols, nvol, m, X, ng, w, rec->vis, rec->rgb, kq, rec->cage, &rec->n_cage);
+  /* float32 sensitivity: the query's own, rounding of the sum, and the
+     hit point's float32 error along the ray (about t u / |cos|), measured
+     by a finite difference of the shading at that scale */
+  double ep = fmin(1e-2, U32 * (8.0 / fmax(rec->cosi, 1e-6) + 16.0));
+  double X2[3], rgb2[3], kq2[3];
+  for (int a = 0; a < 3; a++) X2[a] = o[a] + h.t * (1.0 + ep) * w[a];
+  front_radiance(s, L, vols, nvol, m, X2, ng, w, rec->vis, rgb2, kq2, NULL, NULL);
+  for (int k = 0; k < 3; k++)
+    rec->kappa[k] = s->albedo[m * 3 + k] * kq[k] + 8.0 * fabs(rec->rgb[k]) + fabs(rgb2[k] - rec->rgb[k]) / U32;
 }
 
 /* ----------------------------------------------------------------- states */

@@ -85,6 +85,10 @@ struct irf_ctx {
   DevBuf<HitRec> hits;
   DevBuf<uint8_t> vis;
   DevBuf<float4> rays;
+  DevBuf<uint32_t> shadow_tasks;
+  DevBuf<int32_t> wave_tasks;
+  DevBuf<int64_t> wave_offset;
+  DevBuf<unsigned long long> stats;
   DevBuf<int32_t> class_back;
   DevBuf<uint32_t> class_tf;
   bool frame_done = false;
@@ -114,6 +118,7 @@ SceneGPU scene_view(const irf_ctx* c) {
   s.emission = c->emission.p;
   s.n_tris = c->n_tris;
   s.n_nodes = c->n_nodes;
+  s.stack_depth = (int32_t)c->bvh_stats[2];
   return s;
 }
 
@@ -149,6 +154,7 @@ irf_status ensure_scratch(irf_ctx* c) {
   irf_status s;
   int64_t P = total_probes(c), R = total_rays(c);
   int nl = c->lights.n_dir + c->lights.n_point;
+  if (R >= (1ll << 27)) return fail(IRF_E_UNSUPPORTED, "too many rays per frame (%lld >= 2^27)", (long long)R);
   int64_t om = 0;
   for (int v = 0; v < c->n_vol; v++) om += c->vol[v].rays;
   if ((s = c->active.reserve((size_t)P)) != IRF_OK) return s;
@@ -157,6 +163,10 @@ irf_status ensure_scratch(irf_ctx* c) {
   if ((s = c->hits.reserve((size_t)R)) != IRF_OK) return s;
   if ((s = c->vis.reserve((size_t)R * (size_t)(nl > 0 ? nl : 1))) != IRF_OK) return s;
   if ((s = c->rays.reserve((size_t)R)) != IRF_OK) return s;
+  if ((s = c->shadow_tasks.reserve((size_t)((R + 63) / 64 * 64) * (size_t)(nl > 0 ? nl : 1))) != IRF_OK) return s;
+  if ((s = c->wave_tasks.reserve((size_t)((R + 63) / 64))) != IRF_OK) return s;
+  if ((s = c->wave_offset.reserve((size_t)((R + 63) / 64))) != IRF_OK) return s;
+  if ((s = c->stats.reserve(8)) != IRF_OK) return s;
   return IRF_OK;
 }
 
@@ -168,6 +178,9 @@ FrameScratch scratch_view(const irf_ctx* c) {
   f.hits = c->hits.p;
   f.vis = c->vis.p;
   f.rays = c->rays.p;
+  f.shadow_tasks = c->shadow_tasks.p;
+  f.wave_tasks = c->wave_tasks.p;
+  f.wave_offset = c->wave_offset.p;
   f.rays_lp = nullptr;
   f.max_rays = total_rays(c);
   f.max_slots = (int32_t)total_probes(c);
@@ -270,6 +283,10 @@ void irf_destroy(irf_ctx* c) {
   c->hits.release();
   c->vis.release();
   c->rays.release();
+  c->shadow_tasks.release();
+  c->wave_tasks.release();
+  c->wave_offset.release();
+  c->stats.release();
   c->class_back.release();
   c->class_tf.release();
   for (auto& r : c->prof_pending) {
@@ -538,7 +555,7 @@ irf_status irf_update_probes(irf_ctx* c, const float* rotation, void* stream) {
   SceneGPU sc = scene_view(c);
   { ProfScope p(c, "state_compact", st); launch_state_compact(vs, boxes_view(c), fs, st); }
   { ProfScope p(c, "directions", st); launch_directions(vs, rotation, fs.omega, st); }
-  { ProfScope p(c, "trace", st); launch_trace(vs, sc, fs, st); }
+  { ProfScope p(c, "trace", st); launch_trace(vs, sc, c->lights, fs, st); }
   if (c->lights.n_dir + c->lights.n_point > 0) {
     ProfScope p(c, "shadow", st);
     launch_shadow(vs, sc, c->lights, fs, st);
@@ -591,13 +608,33 @@ irf_status irf_frame_stats(irf_ctx* c, int64_t out[4], void* stream) {
   if (!c->frame_done) return fail(IRF_E_STATE, "no update frame has run");
   irf_status s = set_device(c);
   if (s != IRF_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  launch_frame_stats(volume_view(c), scene_view(c), scratch_view(c), c->stats.p, st);
+  if ((s = launched()) != IRF_OK) return s;
   FrameCounters C;
-  HIP_TRY(hipMemcpyAsync(&C, c->counters.p, sizeof(C), hipMemcpyDeviceToHost, (hipStream_t)stream));
-  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  unsigned long long k[4];
+  HIP_TRY(hipMemcpyAsync(&C, c->counters.p, sizeof(C), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(k, c->stats.p, sizeof(k), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
   out[0] = C.slot_base[c->n_vol];
   out[1] = C.ray_base[c->n_vol];
-  out[2] = (int64_t)C.shadow_rays;
-  out[3] = (int64_t)C.front_hits;
+  out[2] = c->lights.n_dir + c->lights.n_point > 0 ? (int64_t)k[0] : 0;
+  out[3] = (int64_t)k[1];
+  return IRF_OK;
+}
+
+irf_status irf_traversal_stats(irf_ctx* c, int64_t out[4], void* stream) {
+  if (!c || !out) return fail(IRF_E_INVALID, "NULL argument");
+  if (!c->frame_done) return fail(IRF_E_STATE, "no update frame has run");
+  irf_status s = set_device(c);
+  if (s != IRF_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  launch_traversal_stats(volume_view(c), scene_view(c), c->lights, scratch_view(c), c->stats.p, st);
+  if ((s = launched()) != IRF_OK) return s;
+  unsigned long long k[4];
+  HIP_TRY(hipMemcpyAsync(k, c->stats.p, sizeof(k), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int i = 0; i < 4; i++) out[i] = (int64_t)k[i];
   return IRF_OK;
 }
 

@@ -66,8 +66,7 @@ struct ObjectBoxes {
 struct FrameCounters {
   int32_t slot_base[IRF_MAX_VOLUMES + 1];  // active probes of volume v: [slot_base[v], slot_base[v+1])
   int64_t ray_base[IRF_MAX_VOLUMES + 1];   // rays of volume v: [ray_base[v], ray_base[v+1])
-  unsigned long long shadow_rays;          // shadow rays traced this frame
-  unsigned long long front_hits;           // probe rays that hit a front face
+  int64_t shadow_total;                    // shadow rays queued this frame
 };
 
 // Scene on the device.
@@ -78,6 +77,7 @@ struct SceneGPU {
   const float4* emission;  // [M]
   int32_t n_tris;
   int32_t n_nodes;
+  int32_t stack_depth;     // traversal stack entries needed (BVH depth)
 };
 
 struct HitRec {
@@ -93,6 +93,10 @@ struct FrameScratch {
   HitRec* hits;             // [max_rays]
   uint8_t* vis;             // [n_lights][max_rays]
   float4* rays;             // [max_rays] rgb + distance (float32 path)
+  uint32_t* shadow_tasks;   // [max_rays * n_lights]: per source wave of 64 rays, a slice of
+                            // 64 * n_lights tasks (ray id << 5 | light), light-major
+  int32_t* wave_tasks;      // [max_rays / 64] number of tasks in each slice
+  int64_t* wave_offset;     // [max_rays / 64] exclusive prefix sum of wave_tasks
   void* rays_lp;            // [max_rays] 4 x bf16/f16 (matrix-core path)
   int64_t max_rays;
   int32_t max_slots;
@@ -106,7 +110,7 @@ int build_bvh(const float* vertices, int64_t nv, const uint32_t* indices, int64_
 // ---- launches (kernels_*.hip); all asynchronous on `s`
 void launch_directions(const VolumeSet& vs, const float R[9], float4* omega, hipStream_t s);
 void launch_state_compact(const VolumeSet& vs, ObjectBoxes boxes, FrameScratch fs, hipStream_t s);
-void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, hipStream_t s);
+void launch_trace(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s);
 void launch_shadow(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s);
 void launch_shade(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s);
 void launch_blend(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
@@ -114,6 +118,9 @@ void launch_query(const VolumeSet& vs, const float* pos, const float* nrm, const
                   float* out, hipStream_t s);
 void launch_classify(const VolumeSet& vs, SceneGPU sc, ObjectBoxes boxes, const float* rotations, int K,
                      int32_t* back, uint32_t* tfront, hipStream_t s);
+void launch_traversal_stats(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, unsigned long long* out,
+                            hipStream_t s);
+void launch_frame_stats(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, unsigned long long* out, hipStream_t s);
 void launch_records(const VolumeSet& vs, int vol, SceneGPU sc, FrameScratch fs, int n_lights,
                     irf_ray_record* out, int64_t count, hipStream_t s);
 

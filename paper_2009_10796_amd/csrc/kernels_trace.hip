@@ -98,9 +98,19 @@ __device__ __forceinline__ int bits_i(float f) { return __float_as_int(f); }
 // Two-wide BVH traversal.  ANY: stop at the first hit (shadow rays).
 // STATIC_ONLY: skip triangles of dynamic objects (classification rays).
 // `stack` points at this lane's column of the LDS stack; `stride` = block size.
-template <bool ANY, bool STATIC_ONLY>
+struct NoCount {
+  __device__ __forceinline__ void node() {}
+  __device__ __forceinline__ void tri() {}
+};
+struct Count {
+  unsigned long long nodes = 0, tris = 0;
+  __device__ __forceinline__ void node() { nodes++; }
+  __device__ __forceinline__ void tri() { tris++; }
+};
+
+template <bool ANY, bool STATIC_ONLY, typename CNT = NoCount>
 __device__ inline int traverse(const SceneGPU& sc, const Ray& ray, float tmax, float& t_out, int* stack,
-                               int stride) {
+                               int stride, CNT* cnt = nullptr) {
   int best = -1;
   float tbest = tmax;
   if (sc.n_nodes == 0) {
@@ -114,6 +124,7 @@ __device__ inline int traverse(const SceneGPU& sc, const Ray& ray, float tmax, f
     while (node >= 0) {
       const float4* np = sc.nodes + (size_t)node * 4;
       float4 n0 = np[0], n1 = np[1], n2 = np[2], n3 = np[3];
+      if (cnt) cnt->node();
       float t0, t1;
       bool h0 = box_hit(ray, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tbest, t0);
       bool h1 = box_hit(ray, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tbest, t1);
@@ -121,7 +132,7 @@ __device__ inline int traverse(const SceneGPU& sc, const Ray& ray, float tmax, f
       if (h0 && h1) {
         int nearc = t0 <= t1 ? l0 : l1;
         int farc = t0 <= t1 ? l1 : l0;
-        if (sp < kMaxDepth) {
+        if (sp < sc.stack_depth) {
           stack[sp * stride] = farc;
           sp++;
         }
@@ -145,6 +156,7 @@ __device__ inline int traverse(const SceneGPU& sc, const Ray& ray, float tmax, f
     for (int i = first; i < first + count; i++) {
       const float4* tp = sc.tris + (size_t)i * 3;
       float4 a = tp[0], b = tp[1], c = tp[2];
+      if (cnt) cnt->tri();
       if (STATIC_ONLY && bits_i(b.w) != 0) continue;
       float t;
       if (tri_hit(ray, a, b, c, tbest, t)) {
@@ -200,8 +212,42 @@ __device__ __forceinline__ float3 shadow_origin(float3 X, float3 ng) {
   return X + eps * ng;
 }
 
-__global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeSet vs, SceneGPU sc, FrameScratch fs) {
-  __shared__ int stack[kMaxDepth * kTraceBlock];
+extern __shared__ int dyn_stack[];
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+static inline size_t stack_bytes(const SceneGPU& sc) {
+  return sizeof(int) * (size_t)(sc.stack_depth > 0 ? sc.stack_depth : 1) * kTraceBlock;
+}
+
+// Whether a shadow ray from front-face hit X toward light l is needed (the
+// light is in front of the surface), with its direction and range.
+__device__ __forceinline__ bool shadow_ray(const LightSet& L, int l, float3 X, float3 ng, float3& Xs, float3& dl,
+                                           float& tmax) {
+  Xs = shadow_origin(X, ng);
+  if (l < L.n_dir) {
+    dl = f3(L.dir[l][0], L.dir[l][1], L.dir[l][2]);
+    tmax = INFINITY;
+  } else {
+    int p = l - L.n_dir;
+    float3 u = f3(L.pos[p][0], L.pos[p][1], L.pos[p][2]) - Xs;
+    float dist = length(u);
+    if (!(dist > 0.0f)) return false;
+    dl = (1.0f / dist) * u;
+    tmax = dist * (1.0f - 1e-6f);
+  }
+  return dot(ng, dl) > 0.0f;
+}
+
+// Nearest hit of every active probe ray.  Front-face hits also queue their
+// shadow rays in the slice of their wave (light-major, so the tasks of one
+// light from one probe stay contiguous) and clear their visibility bytes.
+// No atomics: each wave owns its slice and writes its own count.
+__global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeSet vs, SceneGPU sc, LightSet L, FrameScratch fs) {
   const FrameCounters& C = *fs.counters;
   int64_t id = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
   if (id >= C.ray_base[vs.n]) return;
@@ -209,70 +255,98 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeSet vs, SceneGPU sc
   const VolumeGPU& V = vs.v[s.v];
   float3 o = probe_position(V, s.q);
   float4 w = fs.omega[V.omega_base + s.r];
-  Ray ray = make_ray(o, f3(w.x, w.y, w.z));
+  float3 w3 = f3(w.x, w.y, w.z);
+  Ray ray = make_ray(o, w3);
   float t;
-  int tri = traverse<false, false>(sc, ray, INFINITY, t, stack + threadIdx.x, kTraceBlock);
+  int tri = traverse<false, false>(sc, ray, INFINITY, t, dyn_stack + threadIdx.x, kTraceBlock);
   HitRec h;
   h.tri = tri;
   h.t = tri >= 0 ? t : INFINITY;
   fs.hits[id] = h;
+  int nl = L.n_dir + L.n_point;
+  if (nl == 0) return;
+  bool front = false;
+  float3 X, ng;
+  if (tri >= 0) {
+    ng = tri_normal(sc, tri);
+    front = dot(w3, ng) <= 0.0f;
+    X = f3(fmaf(h.t, w3.x, o.x), fmaf(h.t, w3.y, o.y), fmaf(h.t, w3.z, o.z));
+  }
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = id >> 6;
+  uint32_t* slice = fs.shadow_tasks + wave * 64 * nl;
+  int n = 0;
+  for (int l = 0; l < nl; l++) {
+    fs.vis[(int64_t)l * fs.max_rays + id] = 0;
+    bool need = false;
+    if (front) {
+      float3 Xs, dl;
+      float tmax;
+      need = shadow_ray(L, l, X, ng, Xs, dl, tmax);
+    }
+    unsigned long long m = __ballot(need);
+    if (need) slice[n + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)(id << 5) | (uint32_t)l;
+    n += __popcll(m);
+  }
+  if (lane == __ffsll((long long)__ballot(1)) - 1) fs.wave_tasks[wave] = n;
 }
 
-// Hit point and geometric normal of a front-face hit, else false.
-__device__ __forceinline__ bool front_hit(const VolumeSet& vs, const SceneGPU& sc, const FrameScratch& fs,
-                                          const FrameCounters& C, int64_t id, float3& X, float3& ng, float3& w3,
-                                          HitRec& h) {
+// Exclusive prefix sum of the per-wave task counts (one workgroup).
+constexpr int kScanBlock = 1024;
+__global__ __launch_bounds__(kScanBlock) void k_scan_tasks(VolumeSet vs, FrameScratch fs) {
+  __shared__ int64_t part[kScanBlock];
+  FrameCounters* C = fs.counters;
+  const int64_t waves = (C->ray_base[vs.n] + 63) / 64;
+  const int64_t per = (waves + kScanBlock - 1) / kScanBlock;
+  const int64_t b = threadIdx.x * per, e = min(b + per, waves);
+  int64_t sum = 0;
+  for (int64_t i = b; i < e; i++) sum += fs.wave_tasks[i];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    int64_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t run = part[threadIdx.x] - sum;
+  for (int64_t i = b; i < e; i++) {
+    fs.wave_offset[i] = run;
+    run += fs.wave_tasks[i];
+  }
+  if (threadIdx.x == kScanBlock - 1) C->shadow_total = part[kScanBlock - 1];
+}
+
+// Any-hit shadow rays over the dense task index space: task k lives in the
+// slice of the last wave whose offset is <= k.
+__global__ __launch_bounds__(kTraceBlock) void k_shadow(VolumeSet vs, SceneGPU sc, LightSet L, FrameScratch fs) {
+  const FrameCounters& C = *fs.counters;
+  int64_t k = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
+  if (k >= C.shadow_total) return;
+  const int nl = L.n_dir + L.n_point;
+  int64_t lo = 0, hi = (C.ray_base[vs.n] + 63) / 64 - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) >> 1;
+    if (fs.wave_offset[mid] <= k) lo = mid;
+    else hi = mid - 1;
+  }
+  uint32_t task = fs.shadow_tasks[lo * 64 * nl + (k - fs.wave_offset[lo])];
+  int64_t id = task >> 5;
+  int l = task & 31;
   RaySlot s = locate_ray(vs, C, fs.active, id);
   const VolumeGPU& V = vs.v[s.v];
   float3 o = probe_position(V, s.q);
   float4 w = fs.omega[V.omega_base + s.r];
-  w3 = f3(w.x, w.y, w.z);
-  h = fs.hits[id];
-  if (h.tri < 0) return false;
-  ng = tri_normal(sc, h.tri);
-  if (dot(w3, ng) > 0.0f) return false;
-  X = f3(fmaf(h.t, w3.x, o.x), fmaf(h.t, w3.y, o.y), fmaf(h.t, w3.z, o.z));
-  return true;
-}
-
-__global__ __launch_bounds__(kTraceBlock) void k_shadow(VolumeSet vs, SceneGPU sc, LightSet L, FrameScratch fs) {
-  __shared__ int stack[kMaxDepth * kTraceBlock];
-  const FrameCounters& C = *fs.counters;
-  int64_t gid = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
-  int l = (int)(gid / fs.max_rays);
-  int64_t id = gid - (int64_t)l * fs.max_rays;
-  if (l >= L.n_dir + L.n_point || id >= C.ray_base[vs.n]) return;
-  float3 X, ng, w;
-  HitRec h;
-  uint8_t vis = 0;
-  bool traced = false;
-  if (front_hit(vs, sc, fs, C, id, X, ng, w, h)) {
-    float3 Xs = shadow_origin(X, ng);
-    float3 dl;
-    float tmax;
-    if (l < L.n_dir) {
-      dl = f3(L.dir[l][0], L.dir[l][1], L.dir[l][2]);
-      tmax = INFINITY;
-    } else {
-      int p = l - L.n_dir;
-      float3 u = f3(L.pos[p][0], L.pos[p][1], L.pos[p][2]) - Xs;
-      float dist = length(u);
-      dl = (1.0f / dist) * u;
-      tmax = dist * (1.0f - 1e-6f);
-      if (!(dist > 0.0f)) tmax = -1.0f;
-    }
-    if (tmax > 0.0f && dot(ng, dl) > 0.0f) {
-      Ray ray = make_ray(Xs, dl);
-      float t;
-      int hit = traverse<true, false>(sc, ray, tmax, t, stack + threadIdx.x, kTraceBlock);
-      vis = hit < 0 ? 1 : 0;
-      traced = true;
-    }
-  }
-  fs.vis[(int64_t)l * fs.max_rays + id] = vis;
-  unsigned long long m = __ballot(traced);
-  if ((threadIdx.x & 63) == __ffsll((long long)__ballot(1)) - 1 && m)
-    atomicAdd(&fs.counters->shadow_rays, (unsigned long long)__popcll(m));
+  HitRec h = fs.hits[id];
+  float3 ng = tri_normal(sc, h.tri);
+  float3 X = f3(fmaf(h.t, w.x, o.x), fmaf(h.t, w.y, o.y), fmaf(h.t, w.z, o.z));
+  float3 Xs, dl;
+  float tmax;
+  shadow_ray(L, l, X, ng, Xs, dl, tmax);
+  Ray ray = make_ray(Xs, dl);
+  float t;
+  int hit = traverse<true, false>(sc, ray, tmax, t, dyn_stack + threadIdx.x, kTraceBlock);
+  if (hit < 0) fs.vis[(int64_t)l * fs.max_rays + id] = 1;
 }
 
 // Radiance and distance carried by each probe ray (backface rule of the
@@ -288,7 +362,6 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(VolumeSet vs, SceneGPU sc
   float3 w = f3(w4.x, w4.y, w4.z);
   HitRec h = fs.hits[id];
   float4 out;
-  bool front = false;
   if (h.tri < 0) {
     out = make_float4(L.sky[0], L.sky[1], L.sky[2], V.dmax);
   } else {
@@ -296,7 +369,6 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(VolumeSet vs, SceneGPU sc
     if (dot(w, ng) > 0.0f) {
       out = make_float4(0.0f, 0.0f, 0.0f, fminf(0.2f * h.t, V.dmax));
     } else {
-      front = true;
       float3 X = f3(fmaf(h.t, w.x, o.x), fmaf(h.t, w.y, o.y), fmaf(h.t, w.z, o.z));
       float3 Xs = shadow_origin(X, ng);
       float3 direct = f3(0.0f, 0.0f, 0.0f);
@@ -324,9 +396,6 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(VolumeSet vs, SceneGPU sc
     }
   }
   fs.rays[id] = out;
-  unsigned long long m = __ballot(front);
-  if ((threadIdx.x & 63) == __ffsll((long long)__ballot(1)) - 1 && m)
-    atomicAdd(&fs.counters->front_hits, (unsigned long long)__popcll(m));
 }
 
 // ---- classification (Section "Full Probe Initialization Algorithm")
@@ -353,7 +422,6 @@ __device__ __forceinline__ float3 sf_direction(int i, int n, const float* R) {
 
 __global__ __launch_bounds__(kTraceBlock) void k_classify(VolumeSet vs, SceneGPU sc, ClassifyArgs A, int32_t* back,
                                                           uint32_t* tfront) {
-  __shared__ int stack[kMaxDepth * kTraceBlock];
   int64_t gid = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
   if (gid >= A.base[vs.n]) return;
   int v = 0;
@@ -368,7 +436,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_classify(VolumeSet vs, SceneGPU
   float3 w = sf_direction(r, V.rays, A.R[k]);
   Ray ray = make_ray(o, w);
   float t;
-  int tri = traverse<false, true>(sc, ray, INFINITY, t, stack + threadIdx.x, kTraceBlock);
+  int tri = traverse<false, true>(sc, ray, INFINITY, t, dyn_stack + threadIdx.x, kTraceBlock);
   if (tri < 0) return;
   int gq = V.probe_base + q;
   if (dot(w, tri_normal(sc, tri)) > 0.0f)
@@ -409,9 +477,100 @@ __global__ void k_classify_finish(VolumeSet vs, ObjectBoxes ob, int K, const int
   V.states[q] = st;
 }
 
-__global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = value;
+// ---- traversal statistics (on demand): node and triangle fetches of the
+// last frame's probe rays (out[0..1]) and shadow rays (out[2..3])
+
+__device__ __forceinline__ void add_block(unsigned long long* out, unsigned long long v) {
+  // one atomic per wave
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
+}
+
+__global__ __launch_bounds__(kTraceBlock) void k_trace_count(VolumeSet vs, SceneGPU sc, FrameScratch fs,
+                                                             unsigned long long* out) {
+  const FrameCounters& C = *fs.counters;
+  int64_t id = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
+  Count cnt;
+  if (id < C.ray_base[vs.n]) {
+    RaySlot s = locate_ray(vs, C, fs.active, id);
+    const VolumeGPU& V = vs.v[s.v];
+    float4 w = fs.omega[V.omega_base + s.r];
+    Ray ray = make_ray(probe_position(V, s.q), f3(w.x, w.y, w.z));
+    float t;
+    traverse<false, false, Count>(sc, ray, INFINITY, t, dyn_stack + threadIdx.x, kTraceBlock, &cnt);
+  }
+  add_block(&out[0], cnt.nodes);
+  add_block(&out[1], cnt.tris);
+}
+
+__global__ __launch_bounds__(kTraceBlock) void k_shadow_count(VolumeSet vs, SceneGPU sc, LightSet L, FrameScratch fs,
+                                                              unsigned long long* out) {
+  const FrameCounters& C = *fs.counters;
+  int64_t k = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
+  Count cnt;
+  if (k < C.shadow_total) {
+    const int nl = L.n_dir + L.n_point;
+    int64_t lo = 0, hi = (C.ray_base[vs.n] + 63) / 64 - 1;
+    while (lo < hi) {
+      int64_t mid = (lo + hi + 1) >> 1;
+      if (fs.wave_offset[mid] <= k) lo = mid;
+      else hi = mid - 1;
+    }
+    uint32_t task = fs.shadow_tasks[lo * 64 * nl + (k - fs.wave_offset[lo])];
+    int64_t id = task >> 5;
+    int l = task & 31;
+    RaySlot s = locate_ray(vs, C, fs.active, id);
+    const VolumeGPU& V = vs.v[s.v];
+    float3 o = probe_position(V, s.q);
+    float4 w = fs.omega[V.omega_base + s.r];
+    HitRec h = fs.hits[id];
+    float3 ng = tri_normal(sc, h.tri);
+    float3 X = f3(fmaf(h.t, w.x, o.x), fmaf(h.t, w.y, o.y), fmaf(h.t, w.z, o.z));
+    float3 Xs, dl;
+    float tmax;
+    shadow_ray(L, l, X, ng, Xs, dl, tmax);
+    float t;
+    traverse<true, false, Count>(sc, make_ray(Xs, dl), tmax, t, dyn_stack + threadIdx.x, kTraceBlock, &cnt);
+  }
+  add_block(&out[2], cnt.nodes);
+  add_block(&out[3], cnt.tris);
+}
+
+void launch_traversal_stats(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, unsigned long long* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)out, 0u, (int64_t)8);
+  if (fs.max_rays == 0) return;
+  hipLaunchKernelGGL(k_trace_count, dim3(blocks_for(fs.max_rays, kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s,
+                     vs, sc, fs, out);
+  int nl = L.n_dir + L.n_point;
+  if (nl == 0) return;
+  int64_t cap = (fs.max_rays + 63) / 64 * 64 * nl;
+  hipLaunchKernelGGL(k_shadow_count, dim3(blocks_for(cap, kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc,
+                     L, fs, out);
+}
+
+// ---- frame statistics (on demand, outside the frame)
+
+__global__ void k_frame_stats(VolumeSet vs, SceneGPU sc, FrameScratch fs, unsigned long long* out) {
+  const FrameCounters& C = *fs.counters;
+  int64_t total = C.ray_base[vs.n];
+  unsigned long long tasks = 0, front = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    HitRec h = fs.hits[i];
+    if (h.tri >= 0) {
+      RaySlot s = locate_ray(vs, C, fs.active, i);
+      float4 w = fs.omega[vs.v[s.v].omega_base + s.r];
+      if (dot(f3(w.x, w.y, w.z), tri_normal(sc, h.tri)) <= 0.0f) front++;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) tasks = (unsigned long long)C.shadow_total;
+  atomicAdd(&out[0], tasks);
+  atomicAdd(&out[1], front);
+}
+
+void launch_frame_stats(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, unsigned long long* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)out, 0u, (int64_t)4);
+  hipLaunchKernelGGL(k_frame_stats, dim3(256), dim3(256), 0, s, vs, sc, fs, out);
 }
 
 // ---- debug records
@@ -442,17 +601,18 @@ __global__ void k_records(VolumeSet vs, int vol, SceneGPU sc, FrameScratch fs, i
 
 // ---- launches
 
-static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
-
-void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, hipStream_t s) {
+void launch_trace(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s) {
   if (fs.max_rays == 0) return;
-  hipLaunchKernelGGL(k_trace, dim3(blocks_for(fs.max_rays, kTraceBlock)), dim3(kTraceBlock), 0, s, vs, sc, fs);
+  hipLaunchKernelGGL(k_trace, dim3(blocks_for(fs.max_rays, kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc,
+                     L, fs);
 }
 
 void launch_shadow(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s) {
   int nl = L.n_dir + L.n_point;
   if (fs.max_rays == 0 || nl == 0) return;
-  hipLaunchKernelGGL(k_shadow, dim3(blocks_for(fs.max_rays * nl, kTraceBlock)), dim3(kTraceBlock), 0, s, vs, sc, L,
+  hipLaunchKernelGGL(k_scan_tasks, dim3(1), dim3(kScanBlock), 0, s, vs, fs);
+  int64_t cap = (fs.max_rays + 63) / 64 * 64 * nl;
+  hipLaunchKernelGGL(k_shadow, dim3(blocks_for(cap, kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, L,
                      fs);
 }
 
@@ -478,8 +638,8 @@ void launch_classify(const VolumeSet& vs, SceneGPU sc, ObjectBoxes boxes, const 
   hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(total_probes, 256)), dim3(256), 0, s, tfront,
                      (uint32_t)0x7f800000u, (int64_t)total_probes);
   if (A.base[vs.n] > 0)
-    hipLaunchKernelGGL(k_classify, dim3(blocks_for(A.base[vs.n], kTraceBlock)), dim3(kTraceBlock), 0, s, vs, sc, A,
-                       back, tfront);
+    hipLaunchKernelGGL(k_classify, dim3(blocks_for(A.base[vs.n], kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s,
+                       vs, sc, A, back, tfront);
   int maxp = 0;
   for (int v = 0; v < vs.n; v++) maxp = vs.v[v].n_probes > maxp ? vs.v[v].n_probes : maxp;
   hipLaunchKernelGGL(k_classify_finish, dim3(blocks_for(maxp, 256), vs.n), dim3(256), 0, s, vs, boxes, K, back,

@@ -118,8 +118,6 @@ __global__ __launch_bounds__(kCompactBlock) void k_state_compact(VolumeSet vs, O
   if (threadIdx.x == 0) {
     C.slot_base[vs.n] = slot;
     C.ray_base[vs.n] = rays;
-    C.shadow_rays = 0;
-    C.front_hits = 0;
     *fs.counters = C;
   }
 }

@@ -79,6 +79,7 @@ SIGNATURES = {
     "irf_query_irradiance": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp]),
     "irf_ray_records": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(_i64), _vp]),
     "irf_frame_stats": (C.c_int, [_vp, C.POINTER(_i64 * 4), _vp]),
+    "irf_traversal_stats": (C.c_int, [_vp, C.POINTER(_i64 * 4), _vp]),
     "irf_profile_enable": (C.c_int, [_vp, _i32]),
     "irf_profile_read": (C.c_int, [_vp, _vp, _i32, C.POINTER(_i32), _i32]),
     "irf_validate_volume_desc": (C.c_int, [C.POINTER(VolumeDescC)]),
@@ -259,6 +260,11 @@ class Context:
         out = (C.c_int64 * 4)()
         _check(load().irf_frame_stats(self.handle, C.byref(out), _stream(self.torch)))
         return {"active_probes": out[0], "probe_rays": out[1], "shadow_rays": out[2], "front_hits": out[3]}
+
+    def traversal_stats(self) -> dict:
+        out = (C.c_int64 * 4)()
+        _check(load().irf_traversal_stats(self.handle, C.byref(out), _stream(self.torch)))
+        return {"probe_nodes": out[0], "probe_tris": out[1], "shadow_nodes": out[2], "shadow_tris": out[3]}
 
     def profile(self, enable: bool = True) -> None:
         _check(load().irf_profile_enable(self.handle, int(enable)))

@@ -133,8 +133,9 @@ def test_update_and_query_parity(torch, name):
     print(f"[parity] {name} query stage: n={len(es)} fail={int((~ok).any(1).sum())} "
           f"ill-conditioned={int(loose.sum())}", flush=True)
     assert ok.all(), np.argwhere(~ok)[:5]
-    # end to end (each side's own atlas): texel differences propagate
-    ok, _ = within(eg, eo, kappa=ko * 64 + 64 * np.abs(eo) / U32 * 1e-6)
+    # end to end (each side's own atlas): the atlases agree to ~32 u relative
+    # (checked above), which the query amplifies by the same sensitivity
+    ok, _ = within(eg, eo, kappa=32 * ko)
     print(f"[parity] {name} query end-to-end: fail={int((~ok).any(1).sum())}", flush=True)
     assert (~ok).any(1).mean() <= 1e-3
     ctx.close()
