@@ -67,12 +67,49 @@ def cpu_baseline(w, n_frames=3):
             "sample": f"full step (update frame + {q.n} G-buffer queries), FP64, OpenMP, median of {n_frames} frames"}
 
 
+def blend_variants(w, R, frames, irf, torch):
+    """Blend kernel time of every blend mode on the same workload and frames,
+    and each mode's irradiance difference from the float32 matrix-core path
+    (relative, floor 1e-3 of the channel maximum)."""
+    import copy
+    res, ref = {}, None
+    for mode, f16 in (("f32", False), ("f32_valu", False), ("bf16", False), ("f16", False), ("bf16", True),
+                      ("f16", True)):
+        ww = copy.deepcopy(w)
+        for d in ww.volumes:
+            d.blend, d.atlas_f16 = mode, f16
+        ctx = irf.build_workload(ww, device=0)
+        ctx.classify(ww.classify_rotations)
+        for f in range(frames):
+            if f == frames - 3:
+                torch.cuda.synchronize()
+                ctx.profile(True)
+                ctx.profile_read(reset=True)
+            ctx.update_probes(R[f])
+        torch.cuda.synchronize()
+        prof = ctx.profile_read(reset=True)
+        irr = ctx.volumes[0].irradiance[..., :3].float().cpu().numpy().astype(np.float64)
+        bk = [k for k in prof if k.startswith("blend")][0]
+        t_us = 1e3 * prof[bk][1] / prof[bk][0] + (1e3 * prof["weights"][1] / prof["weights"][0]
+                                                    if "weights" in prof else 0.0)
+        key = mode + ("+f16atlas" if f16 else "")
+        if ref is None:
+            ref = irr
+        t = 1e-3 * np.abs(ref).reshape(-1, 3).max(0)
+        rel = np.abs(irr - ref) / np.maximum(np.abs(ref), t)
+        res[key] = {"blend_us": round(t_us, 2), "irr_vs_f32_max": float(rel.max()),
+                    "irr_vs_f32_p99": float(np.quantile(rel, 0.99))}
+        ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-blend-variants", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -144,9 +181,9 @@ def main():
     blend_flops = 2.0 * n_rays * (36 * 3 + 196 * 2) * stats["active_probes"]
     bk = [k for k in kern if k.startswith("blend")][0]
     tf = blend_flops / (kern[bk]["avg_us"] * 1e-6) / 1e12
-    rooflines["blend"] = {"kernel": bk, "bound": "alu", "achieved": round(tf, 3), "peak": FP32_PEAK_TFLOPS,
-                          "unit": "TFLOP/s", "frac": round(tf / FP32_PEAK_TFLOPS, 4), "traffic": None,
-                          "algorithmic_flops_per_launch": blend_flops}
+    rooflines["blend"] = {"kernel": bk, "bound": "mfma" if bk == "blend_mma" else "alu", "achieved": round(tf, 3),
+                          "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / FP32_PEAK_TFLOPS, 4),
+                          "traffic": None, "algorithmic_flops_per_launch": blend_flops}
     dominant = max(kern, key=lambda k: kern[k]["avg_us"])
     roof = rooflines.get(dominant if not dominant.startswith("blend") else "blend")
     line = {
@@ -178,6 +215,9 @@ def main():
         "kernel_rooflines": rooflines,
         "roofline": roof,
     }
+    if not args.no_blend_variants:
+        print("[bench] blend variants ...", file=sys.stderr, flush=True)
+        line["blend_variants"] = blend_variants(w, R, 8, irf, torch)
     if not args.no_cpu_baseline:
         print("[bench] oracle CPU baseline ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)

@@ -50,7 +50,7 @@ enum {
 
 /* Atlas storage types and blend arithmetic. */
 enum { IRF_ATLAS_F32 = 0, IRF_ATLAS_F16 = 1 };
-enum { IRF_BLEND_F32 = 0, IRF_BLEND_BF16 = 1, IRF_BLEND_F16 = 2 };
+enum { IRF_BLEND_F32 = 0, IRF_BLEND_BF16 = 1, IRF_BLEND_F16 = 2, IRF_BLEND_F32_VALU = 3 };
 
 #define IRF_MAX_VOLUMES 8
 #define IRF_MAX_LIGHTS 32
@@ -128,8 +128,13 @@ irf_status irf_set_lights(irf_ctx* ctx, const irf_lights_desc* desc);
                      1.5 * |spacing|
      cheb_power      exponent of the Chebyshev visibility weight, 1..4
      atlas_dtype     IRF_ATLAS_F32 or IRF_ATLAS_F16
-     blend           IRF_BLEND_F32 (vector ALU), IRF_BLEND_BF16 or
-                     IRF_BLEND_F16 (matrix cores, float32 accumulation) */
+     blend           how the texels are blended (Eq. U): IRF_BLEND_F32,
+                     IRF_BLEND_BF16, IRF_BLEND_F16 = one shared (texel x ray)
+                     weight matrix times the rays of the probes on the matrix
+                     cores, inputs in that precision, float32 accumulation and
+                     float32 normalisation by the sum of the stored weights;
+                     IRF_BLEND_F32_VALU = vector ALU, one workgroup per probe
+                     with its rays in LDS (the paper's compute-shader shape) */
 typedef struct {
   float origin[3];
   float spacing[3];

@@ -89,6 +89,8 @@ struct irf_ctx {
   DevBuf<int32_t> wave_tasks;
   DevBuf<int64_t> wave_offset;
   DevBuf<unsigned long long> stats;
+  DevBuf<char> weights;
+  DevBuf<float> inv_row_sum;
   DevBuf<int32_t> class_back;
   DevBuf<uint32_t> class_tf;
   bool frame_done = false;
@@ -167,6 +169,10 @@ irf_status ensure_scratch(irf_ctx* c) {
   if ((s = c->wave_tasks.reserve((size_t)((R + 63) / 64))) != IRF_OK) return s;
   if ((s = c->wave_offset.reserve((size_t)((R + 63) / 64))) != IRF_OK) return s;
   if ((s = c->stats.reserve(8)) != IRF_OK) return s;
+  int64_t wbytes = 0;
+  for (int v = 0; v < c->n_vol; v++) wbytes += 256ll * c->vol[v].rays * 4;
+  if ((s = c->weights.reserve((size_t)(wbytes > 0 ? wbytes : 16))) != IRF_OK) return s;
+  if ((s = c->inv_row_sum.reserve((size_t)256 * (c->n_vol > 0 ? c->n_vol : 1))) != IRF_OK) return s;
   return IRF_OK;
 }
 
@@ -181,6 +187,8 @@ FrameScratch scratch_view(const irf_ctx* c) {
   f.shadow_tasks = c->shadow_tasks.p;
   f.wave_tasks = c->wave_tasks.p;
   f.wave_offset = c->wave_offset.p;
+  f.weights = c->weights.p;
+  f.inv_row_sum = c->inv_row_sum.p;
   f.rays_lp = nullptr;
   f.max_rays = total_rays(c);
   f.max_slots = (int32_t)total_probes(c);
@@ -287,6 +295,8 @@ void irf_destroy(irf_ctx* c) {
   c->wave_tasks.release();
   c->wave_offset.release();
   c->stats.release();
+  c->weights.release();
+  c->inv_row_sum.release();
   c->class_back.release();
   c->class_tf.release();
   for (auto& r : c->prof_pending) {
@@ -448,7 +458,8 @@ irf_status irf_validate_volume_desc(const irf_volume_desc* d) {
   if (d->cheb_power < 1 || d->cheb_power > 4) return fail(IRF_E_INVALID, "cheb_power must be in [1, 4]");
   if (d->atlas_dtype != IRF_ATLAS_F32 && d->atlas_dtype != IRF_ATLAS_F16)
     return fail(IRF_E_INVALID, "unknown atlas_dtype %d", d->atlas_dtype);
-  if (d->blend != IRF_BLEND_F32 && d->blend != IRF_BLEND_BF16 && d->blend != IRF_BLEND_F16)
+  if (d->blend != IRF_BLEND_F32 && d->blend != IRF_BLEND_BF16 && d->blend != IRF_BLEND_F16 &&
+      d->blend != IRF_BLEND_F32_VALU)
     return fail(IRF_E_INVALID, "unknown blend %d", d->blend);
   return IRF_OK;
 }
@@ -458,7 +469,6 @@ irf_status irf_create_volume(irf_ctx* c, const irf_volume_desc* d, int32_t* volu
   irf_status s = irf_validate_volume_desc(d);
   if (s != IRF_OK) return s;
   if (c->n_vol >= IRF_MAX_VOLUMES) return fail(IRF_E_INVALID, "at most %d volumes", IRF_MAX_VOLUMES);
-  if (d->blend != IRF_BLEND_F32) return fail(IRF_E_UNSUPPORTED, "matrix-core blend not built in this library");
   int64_t P = (int64_t)d->counts[0] * d->counts[1] * d->counts[2];
   if (total_probes(c) + P > (1 << 24)) return fail(IRF_E_INVALID, "too many probes in total");
   int v = c->n_vol;
@@ -492,6 +502,9 @@ irf_status irf_create_volume(irf_ctx* c, const irf_volume_desc* d, int32_t* volu
   int32_t ob = 0;
   for (int u = 0; u < v; u++) ob += c->vol[u].rays;
   V.omega_base = ob;
+  int64_t wb = 0;
+  for (int u = 0; u < v; u++) wb += 256ll * c->vol[u].rays * 4;
+  V.weight_base = wb;
   c->bound[v] = false;
   c->n_vol = v + 1;
   *volume_id = v;
@@ -555,13 +568,26 @@ irf_status irf_update_probes(irf_ctx* c, const float* rotation, void* stream) {
   SceneGPU sc = scene_view(c);
   { ProfScope p(c, "state_compact", st); launch_state_compact(vs, boxes_view(c), fs, st); }
   { ProfScope p(c, "directions", st); launch_directions(vs, rotation, fs.omega, st); }
+  bool any_mma = false, any_valu = false;
+  for (int v = 0; v < c->n_vol; v++) (c->vol[v].blend == IRF_BLEND_F32_VALU ? any_valu : any_mma) = true;
+  if (any_mma) {
+    ProfScope p(c, "weights", st);
+    launch_weights(vs, fs, st);
+  }
   { ProfScope p(c, "trace", st); launch_trace(vs, sc, c->lights, fs, st); }
   if (c->lights.n_dir + c->lights.n_point > 0) {
     ProfScope p(c, "shadow", st);
     launch_shadow(vs, sc, c->lights, fs, st);
   }
   { ProfScope p(c, "shade", st); launch_shade(vs, sc, c->lights, fs, st); }
-  { ProfScope p(c, "blend_f32", st); launch_blend(vs, fs, st); }
+  if (any_valu) {
+    ProfScope p(c, "blend_valu", st);
+    launch_blend(vs, fs, st);
+  }
+  if (any_mma) {
+    ProfScope p(c, "blend_mma", st);
+    launch_blend_mma(vs, fs, st);
+  }
   c->frame_done = true;
   return launched();
 }

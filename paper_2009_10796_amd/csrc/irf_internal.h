@@ -34,6 +34,7 @@ struct VolumeGPU {
   int32_t blend;
   int32_t probe_base;       // first global probe id of this volume
   int32_t omega_base;       // first entry of this volume in the direction table
+  int64_t weight_base;      // byte offset of this volume's blend weights
   void* irr;                // [P][8][8] float4 or half4
   void* dist;               // [P][16][16] float2 or half2
   uint8_t* states;          // [P]
@@ -97,6 +98,8 @@ struct FrameScratch {
                             // 64 * n_lights tasks (ray id << 5 | light), light-major
   int32_t* wave_tasks;      // [max_rays / 64] number of tasks in each slice
   int64_t* wave_offset;     // [max_rays / 64] exclusive prefix sum of wave_tasks
+  void* weights;            // per volume: 256 weight rows x rays (float32 [k][row] or 16-bit [row][k])
+  float* inv_row_sum;       // [n_volumes][256] 1 / sum of the stored weights of each row (0 = none)
   void* rays_lp;            // [max_rays] 4 x bf16/f16 (matrix-core path)
   int64_t max_rays;
   int32_t max_slots;
@@ -114,6 +117,8 @@ void launch_trace(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs,
 void launch_shadow(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s);
 void launch_shade(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s);
 void launch_blend(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
+void launch_weights(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
+void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
 void launch_query(const VolumeSet& vs, const float* pos, const float* nrm, const float* view, int64_t n,
                   float* out, hipStream_t s);
 void launch_classify(const VolumeSet& vs, SceneGPU sc, ObjectBoxes boxes, const float* rotations, int K,

@@ -1,0 +1,364 @@
+// The blend of the probe update as a GEMM on the matrix cores.
+//
+// Eq. U, read as a normalised weighted average (Section "Probe Update"), is
+// for every probe the same contraction over rays:
+//   new_E[texel][c]  = sum_r W_E[texel][r] L[r][c]      / sum_r W_E[texel][r]
+//   new_D[texel][j]  = sum_r W_D[texel][r] d[r]^(j+1)   / sum_r W_D[texel][r]
+// with W_E = max(0, n.w) and W_D = max(0, n.w)^p shared by all probes of a
+// volume (one rotation per frame).  k_weights builds W once per frame (rows:
+// 36 irradiance interior texels padded to 48, then 196 distance interior
+// texels padded to 208) and the reciprocal row sums of the *stored* weights,
+// so a constant radiance is reproduced exactly whatever the input precision.
+// k_blend_mma multiplies W by the rays of 8 probes at a time:
+//   columns  0..23  R,G,B of probes 0..7 (24..31 zero),
+//   columns 32..39  d, 40..47 d^2 of probes 0..7,
+// with v_mfma_f32_16x16x4_f32 (float32 inputs) or v_mfma_f32_16x16x32_{bf16,f16}
+// (16-bit inputs), float32 accumulation.  The epilogue normalises, applies the
+// per-probe hysteresis (0 for Newly states) and writes each texel and the
+// border cells that repeat it; k_promote then promotes Newly states.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace irf {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+constexpr int kRows = 256;        // 48 irradiance + 208 distance rows
+constexpr int kIrrRows = 48;
+constexpr int kPB = 8;            // probes per workgroup
+constexpr int kRSplit = 2;        // workgroups per probe block (row tiles split)
+constexpr int kKC = 256;          // rays per LDS chunk
+constexpr int kBlendMmaBlock = 256;
+constexpr int kBfStride = 49;     // float32 B tile: [k][48 + 1]
+constexpr int kBtStride = kKC + 8;// 16-bit B tile: [col][KC + 8]
+
+__device__ __forceinline__ float pow_w(float c, const VolumeGPU& V) {
+  if (V.cos_power_int > 0) {
+    float r = 1.0f, b = c;
+    int e = V.cos_power_int;
+    while (e) {
+      if (e & 1) r *= b;
+      b *= b;
+      e >>= 1;
+    }
+    return r;
+  }
+  return powf(c, V.cos_power);
+}
+
+// Direction of weight row `row` (irradiance rows first), false for padding.
+__device__ __forceinline__ bool row_direction(int row, float3& n) {
+  if (row < kIrrRows) {
+    if (row >= 36) return false;
+    n = texel_direction<kIrrTile>(row % 6 + 1, row / 6 + 1);
+    return true;
+  }
+  int r = row - kIrrRows;
+  if (r >= 196) return false;
+  n = texel_direction<kDistTile>(r % 14 + 1, r / 14 + 1);
+  return true;
+}
+
+__device__ __forceinline__ float round_to(float w, int mode) {
+  if (mode == IRF_BLEND_BF16) return (float)(__bf16)w;
+  if (mode == IRF_BLEND_F16) return (float)(_Float16)w;
+  return w;
+}
+
+// One workgroup per (weight row, volume): the row's weights over all rays in
+// the volume's storage format, and 1 / (float32 sum of the stored weights).
+__global__ __launch_bounds__(256) void k_weights(VolumeSet vs, FrameScratch fs) {
+  __shared__ float part[256];
+  const int row = blockIdx.x, v = blockIdx.y;
+  if (v >= vs.n) return;
+  const VolumeGPU& V = vs.v[v];
+  if (V.blend == IRF_BLEND_F32_VALU) return;
+  const int N = V.rays;
+  float3 n = f3(0.0f, 0.0f, 0.0f);
+  bool real = row_direction(row, n);
+  float sum = 0.0f;
+  for (int k = threadIdx.x; k < N; k += 256) {
+    float w = 0.0f;
+    if (real) {
+      float4 o = fs.omega[V.omega_base + k];
+      float c = fmaf(n.x, o.x, fmaf(n.y, o.y, n.z * o.z));
+      w = c > 0.0f ? (row < kIrrRows ? c : pow_w(c, V)) : 0.0f;
+    }
+    w = round_to(w, V.blend);
+    sum += w;
+    char* base = (char*)fs.weights + V.weight_base;
+    if (V.blend == IRF_BLEND_F32) {
+      ((float*)base)[(size_t)k * kRows + row] = w;               // [k][row]
+    } else if (V.blend == IRF_BLEND_BF16) {
+      ((__bf16*)base)[(size_t)row * N + k] = (__bf16)w;          // [row][k]
+    } else {
+      ((_Float16*)base)[(size_t)row * N + k] = (_Float16)w;
+    }
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) fs.inv_row_sum[v * kRows + row] = part[0] > 0.0f ? 1.0f / part[0] : 0.0f;
+}
+
+struct BlendArgs {
+  int32_t block_base[IRF_MAX_VOLUMES + 1];   // workgroups of volume v: [block_base[v], block_base[v+1])
+};
+
+template <int MODE>
+struct Mma;
+
+// float32 inputs: v_mfma_f32_16x16x4_f32.  A fragment: lane l holds
+// W[row0 + l%16][k0 + l/16]; B fragment: B[k0 + l/16][col0 + l%16].
+template <>
+struct Mma<IRF_BLEND_F32> {
+  static constexpr int KSTEP = 4;
+  static constexpr int KB = 16;    // k-steps whose A fragments are loaded together
+  typedef float A;
+  __device__ static A load_a(const char* wbase, int row_tile, int k, int N, int lane) {
+    return ((const float*)wbase)[(size_t)(k + lane / 16) * kRows + row_tile * 16 + lane % 16];
+  }
+  __device__ static A load_b(const char* lds, int col_base, int k, int lane) {
+    return ((const float*)lds)[(k + lane / 16) * kBfStride + col_base + lane % 16];
+  }
+  __device__ static v4f mma(A a, A b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+
+// 16-bit inputs: v_mfma_f32_16x16x32_{bf16,f16}.  A fragment: lane l holds
+// W[row0 + l%16][k0 + 8(l/16) .. +7]; B fragment: B[k0 + 8(l/16) .. +7][col0 + l%16].
+template <>
+struct Mma<IRF_BLEND_BF16> {
+  static constexpr int KSTEP = 32;
+  static constexpr int KB = 8;
+  typedef v8bf A;
+  __device__ static A load_a(const char* wbase, int row_tile, int k, int N, int lane) {
+    return *(const v8bf*)((const __bf16*)wbase + (size_t)(row_tile * 16 + lane % 16) * N + k + 8 * (lane / 16));
+  }
+  __device__ static A load_b(const char* lds, int col_base, int k, int lane) {
+    return *(const v8bf*)((const __bf16*)lds + (col_base + lane % 16) * kBtStride + k + 8 * (lane / 16));
+  }
+  __device__ static v4f mma(A a, A b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+
+template <>
+struct Mma<IRF_BLEND_F16> {
+  static constexpr int KSTEP = 32;
+  static constexpr int KB = 8;
+  typedef v8h A;
+  __device__ static A load_a(const char* wbase, int row_tile, int k, int N, int lane) {
+    return *(const v8h*)((const _Float16*)wbase + (size_t)(row_tile * 16 + lane % 16) * N + k + 8 * (lane / 16));
+  }
+  __device__ static A load_b(const char* lds, int col_base, int k, int lane) {
+    return *(const v8h*)((const _Float16*)lds + (col_base + lane % 16) * kBtStride + k + 8 * (lane / 16));
+  }
+  __device__ static v4f mma(A a, A b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+};
+
+template <int MODE>
+__device__ __forceinline__ void store_b(void* lds, int k, int col, float x) {
+  if constexpr (MODE == IRF_BLEND_F32) {
+    ((float*)lds)[k * kBfStride + col] = x;
+  } else if constexpr (MODE == IRF_BLEND_BF16) {
+    ((__bf16*)lds)[col * kBtStride + k] = (__bf16)x;
+  } else {
+    ((_Float16*)lds)[col * kBtStride + k] = (_Float16)x;
+  }
+}
+
+__device__ __forceinline__ void store_irr(const VolumeGPU& V, int q, int x, int y, int c, float val) {
+  int j = q * kIrrTexels + y * kIrrTile + x;
+  if (V.atlas_f16) ((_Float16*)V.irr)[4 * j + c] = (_Float16)val;
+  else ((float*)V.irr)[4 * j + c] = val;
+}
+
+__device__ __forceinline__ void store_dist(const VolumeGPU& V, int q, int x, int y, int c, float val) {
+  int j = q * kDistTexels + y * kDistTile + x;
+  if (V.atlas_f16) ((_Float16*)V.dist)[2 * j + c] = (_Float16)val;
+  else ((float*)V.dist)[2 * j + c] = val;
+}
+
+__device__ __forceinline__ float load_ch(const VolumeGPU& V, bool irr, int q, int x, int y, int c) {
+  if (irr) {
+    int j = q * kIrrTexels + y * kIrrTile + x;
+    return V.atlas_f16 ? (float)((const _Float16*)V.irr)[4 * j + c] : ((const float*)V.irr)[4 * j + c];
+  }
+  int j = q * kDistTexels + y * kDistTile + x;
+  return V.atlas_f16 ? (float)((const _Float16*)V.dist)[2 * j + c] : ((const float*)V.dist)[2 * j + c];
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlendMmaBlock) void k_blend_mma(VolumeSet vs, FrameScratch fs, BlendArgs A) {
+  constexpr int LDS_BYTES =
+      MODE == IRF_BLEND_F32 ? kKC * kBfStride * 4 : 48 * kBtStride * 2;
+  __shared__ __attribute__((aligned(16))) char lds[LDS_BYTES];
+  __shared__ int s_q[kPB];
+  __shared__ uint8_t s_state[kPB];
+  const FrameCounters& C = *fs.counters;
+  const int wg = blockIdx.x / kRSplit, split = blockIdx.x % kRSplit;
+  int v = 0;
+  while (v + 1 < vs.n && wg >= A.block_base[v + 1]) v++;
+  const VolumeGPU& V = vs.v[v];
+  if (V.blend != MODE) return;
+  const int count = C.slot_base[v + 1] - C.slot_base[v];
+  const int slot0 = (wg - A.block_base[v]) * kPB;
+  if (slot0 >= count) return;
+  const int np = min(kPB, count - slot0);
+  const int N = V.rays;
+  if (threadIdx.x < kPB) {
+    int q = threadIdx.x < np ? fs.active[C.slot_base[v] + slot0 + threadIdx.x] - V.probe_base : -1;
+    s_q[threadIdx.x] = q;
+    s_state[threadIdx.x] = q >= 0 ? V.states[q] : (uint8_t)IRF_OFF;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // this wave's row tiles: the workgroup owns tiles rt = split, split + kRSplit, ...
+  // (8 of 16) and wave w takes the w-th and (w+4)-th of those
+  int rt_list[2] = {split + kRSplit * wave, split + kRSplit * (wave + 4)};
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  const float4* rays = fs.rays + C.ray_base[v] + (int64_t)slot0 * N;
+  for (int kc = 0; kc < N; kc += kKC) {
+    const int kn = min(kKC, N - kc);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kPB * kn; e += kBlendMmaBlock) {
+      int p = e / kn, k = e - p * kn;
+      float4 r = p < np ? rays[(int64_t)p * N + kc + k] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      store_b<MODE>(lds, k, 3 * p + 0, r.x);
+      store_b<MODE>(lds, k, 3 * p + 1, r.y);
+      store_b<MODE>(lds, k, 3 * p + 2, r.z);
+      store_b<MODE>(lds, k, 24 + p, 0.0f);
+      store_b<MODE>(lds, k, 32 + p, r.w);
+      store_b<MODE>(lds, k, 40 + p, r.w * r.w);
+    }
+    __syncthreads();
+    typedef Mma<MODE> M;
+    const char* wbase = (const char*)fs.weights + V.weight_base;
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+      const int rt = rt_list[i];
+      for (int k0 = 0; k0 < kn; k0 += M::KB * M::KSTEP) {
+        typename M::A a[M::KB];
+#pragma unroll
+        for (int j = 0; j < M::KB; j++)
+          if (k0 + j * M::KSTEP < kn) a[j] = M::load_a(wbase, rt, kc + k0 + j * M::KSTEP, N, lane);
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+          if (c == 1 && rt >= 3) continue;   // distance rows have one column tile
+          const int col_base = rt < 3 ? 16 * c : 32;
+#pragma unroll
+          for (int j = 0; j < M::KB; j++)
+            if (k0 + j * M::KSTEP < kn)
+              acc[i][c] = M::mma(a[j], M::load_b(lds, col_base, k0 + j * M::KSTEP, lane), acc[i][c]);
+        }
+      }
+    }
+  }
+  // epilogue: lane holds rows rt*16 + 4*(lane/16) + r, column col_base + lane%16
+  const float* inv = fs.inv_row_sum + v * kRows;
+#pragma unroll
+  for (int i = 0; i < 2; i++) {
+    const int rt = rt_list[i];
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      if (j == 1 && rt >= 3) continue;
+      const int col = (rt < 3 ? 16 * j : 32) + lane % 16;
+      int p, c;
+      if (rt < 3) {
+        p = col / 3;
+        c = col % 3;
+        if (col >= 24) continue;
+      } else {
+        p = col - 32 < 8 ? col - 32 : col - 40;
+        c = col - 32 < 8 ? 0 : 1;
+      }
+      if (p >= np) continue;
+      const int q = s_q[p];
+      const uint8_t st = s_state[p];
+      const bool fresh = st == IRF_NEWLY_AWAKE || st == IRF_NEWLY_VIGILANT;
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int row = rt * 16 + 4 * (lane / 16) + r;
+        const float s = inv[row];
+        if (s == 0.0f) continue;   // padding row, or no ray with positive weight: keep the texel
+        const float nv = acc[i][j][r] * s;
+        if (rt < 3) {
+          const int x = row % 6 + 1, y = row / 6 + 1;
+          const float a = fresh ? 0.0f : V.alpha_irr;
+          const float val = a * load_ch(V, true, q, x, y, c) + (1.0f - a) * nv;
+          store_irr(V, q, x, y, c, val);
+          if (y == 1) store_irr(V, q, 7 - x, 0, c, val);
+          if (y == 6) store_irr(V, q, 7 - x, 7, c, val);
+          if (x == 1) store_irr(V, q, 0, 7 - y, c, val);
+          if (x == 6) store_irr(V, q, 7, 7 - y, c, val);
+          if (x == 6 && y == 6) store_irr(V, q, 0, 0, c, val);
+          if (x == 1 && y == 6) store_irr(V, q, 7, 0, c, val);
+          if (x == 6 && y == 1) store_irr(V, q, 0, 7, c, val);
+          if (x == 1 && y == 1) store_irr(V, q, 7, 7, c, val);
+        } else {
+          const int rr = row - kIrrRows;
+          const int x = rr % 14 + 1, y = rr / 14 + 1;
+          const float a = fresh ? 0.0f : V.alpha_dist;
+          const float val = a * load_ch(V, false, q, x, y, c) + (1.0f - a) * nv;
+          store_dist(V, q, x, y, c, val);
+          if (y == 1) store_dist(V, q, 15 - x, 0, c, val);
+          if (y == 14) store_dist(V, q, 15 - x, 15, c, val);
+          if (x == 1) store_dist(V, q, 0, 15 - y, c, val);
+          if (x == 14) store_dist(V, q, 15, 15 - y, c, val);
+          if (x == 14 && y == 14) store_dist(V, q, 0, 0, c, val);
+          if (x == 1 && y == 14) store_dist(V, q, 15, 0, c, val);
+          if (x == 14 && y == 1) store_dist(V, q, 0, 15, c, val);
+          if (x == 1 && y == 1) store_dist(V, q, 15, 15, c, val);
+        }
+      }
+    }
+  }
+  // Newly states are promoted by k_promote once every workgroup has read them.
+}
+
+__global__ void k_promote(VolumeSet vs, FrameScratch fs) {
+  const FrameCounters& C = *fs.counters;
+  int gslot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gslot >= C.slot_base[vs.n]) return;
+  int v = 0;
+  while (v + 1 < vs.n && gslot >= C.slot_base[v + 1]) v++;
+  const VolumeGPU& V = vs.v[v];
+  if (V.blend == IRF_BLEND_F32_VALU) return;   // that kernel promotes its own probes
+  int q = fs.active[gslot] - V.probe_base;
+  uint8_t st = V.states[q];
+  if (st == IRF_NEWLY_AWAKE) V.states[q] = IRF_AWAKE;
+  else if (st == IRF_NEWLY_VIGILANT) V.states[q] = IRF_VIGILANT;
+}
+
+void launch_weights(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
+  hipLaunchKernelGGL(k_weights, dim3(kRows, vs.n), dim3(256), 0, s, vs, fs);
+}
+
+void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
+  BlendArgs A;
+  A.block_base[0] = 0;
+  bool mode_present[3] = {false, false, false};
+  for (int v = 0; v < vs.n; v++) {
+    A.block_base[v + 1] = A.block_base[v] + (vs.v[v].n_probes + kPB - 1) / kPB;
+    if (vs.v[v].blend <= IRF_BLEND_F16) mode_present[vs.v[v].blend] = true;
+  }
+  const unsigned grid = (unsigned)A.block_base[vs.n] * kRSplit;
+  if (grid == 0) return;
+  if (mode_present[IRF_BLEND_F32])
+    hipLaunchKernelGGL(k_blend_mma<IRF_BLEND_F32>, dim3(grid), dim3(kBlendMmaBlock), 0, s, vs, fs, A);
+  if (mode_present[IRF_BLEND_BF16])
+    hipLaunchKernelGGL(k_blend_mma<IRF_BLEND_BF16>, dim3(grid), dim3(kBlendMmaBlock), 0, s, vs, fs, A);
+  if (mode_present[IRF_BLEND_F16])
+    hipLaunchKernelGGL(k_blend_mma<IRF_BLEND_F16>, dim3(grid), dim3(kBlendMmaBlock), 0, s, vs, fs, A);
+  if (fs.max_slots > 0)
+    hipLaunchKernelGGL(k_promote, dim3((fs.max_slots + 255) / 256), dim3(256), 0, s, vs, fs);
+}
+
+}  // namespace irf

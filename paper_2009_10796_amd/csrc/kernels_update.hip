@@ -167,6 +167,7 @@ __global__ __launch_bounds__(kBlendBlock) void k_blend_f32(VolumeSet vs, FrameSc
   int v = 0;
   while (v + 1 < vs.n && gslot >= C.slot_base[v + 1]) v++;
   const VolumeGPU& V = vs.v[v];
+  if (V.blend != IRF_BLEND_F32_VALU) return;
   int slot = gslot - C.slot_base[v];
   int q = fs.active[gslot] - V.probe_base;
   const int N = V.rays;

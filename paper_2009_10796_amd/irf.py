@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libirf.so")
 OK, E_INVALID, E_NOMEM, E_HIP, E_STATE, E_UNSUPPORTED = range(6)
 OFF, SLEEPING, NEWLY_AWAKE, NEWLY_VIGILANT, AWAKE, VIGILANT = range(6)
 ATLAS_F32, ATLAS_F16 = 0, 1
-BLEND = {"f32": 0, "bf16": 1, "f16": 2}
+BLEND = {"f32": 0, "bf16": 1, "f16": 2, "f32_valu": 3}
 MAX_VOLUMES, MAX_LIGHTS, MAX_ROTATIONS = 8, 32, 8
 
 

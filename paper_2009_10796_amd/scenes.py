@@ -140,7 +140,7 @@ class VolumeDesc:
     max_distance: float = 0.0    # 0 -> 1.5 * |spacing|
     cheb_power: int = 1
     atlas_f16: bool = False
-    blend: str = "f32"           # "f32" | "bf16" | "f16"
+    blend: str = "f32"           # "f32" | "bf16" | "f16" (matrix cores) | "f32_valu"
 
     @property
     def n_probes(self) -> int:

@@ -61,3 +61,33 @@ def compare_records(g, o, taint_probes_prev=None, probe_base=0):
     report = {"rays": len(g), "flagged": int(flagged.sum()), "flips": int((flip_tri | flip_vis).sum()),
               "unflagged_flips": int(bad_flip.sum()), "tainted": int(tainted.sum())}
     return tainted, bad_flip, report
+
+
+def texel_check(gv, ov, probes, rec_o, slot_of, rel=1e-5):
+    """Compare the atlases of `probes` (oracle float64 vs GPU): per texel
+    |g - o| <= rel * max(|o|, tau) + 8 u kappa, kappa = the largest kappa of
+    the probe's rays (their radiance enters the texel as a convex combination)."""
+    gi = gv.irradiance[..., :3].float().cpu().numpy().astype(np.float64)
+    gd = gv.distance.float().cpu().numpy().astype(np.float64)
+    oi, od = ov.irr, ov.dist
+    ti = tau(oi.reshape(-1, 3))
+    td = tau(od.reshape(-1, 2))
+    worst = 0.0
+    bad = []
+    for q in probes:
+        k = rec_o["kappa"][slot_of[q]].max() if q in slot_of else 0.0
+        tol_i = rel * np.maximum(np.abs(oi[q]), ti.reshape(1, 1, 3)) + 8 * U32 * k
+        tol_d = rel * np.maximum(np.abs(od[q]), td.reshape(1, 1, 2))
+        ei = np.abs(gi[q] - oi[q]) / tol_i
+        ed = np.abs(gd[q] - od[q]) / tol_d
+        m = max(ei.max(), ed.max())
+        worst = max(worst, m)
+        if m > 1:
+            bad.append((q, float(ei.max()), float(ed.max())))
+    return worst, bad
+
+
+def slots_of(rec_g, n_rays):
+    probes = rec_g["probe"]
+    probe_list = probes[::n_rays]
+    return {int(q): np.arange(i * n_rays, (i + 1) * n_rays) for i, q in enumerate(probe_list)}

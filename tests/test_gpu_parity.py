@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from paper_2009_10796_amd import scenes as S
-from tests.gpu_helpers import U32, compare_records, tau, within
+from tests.gpu_helpers import U32, compare_records, tau, texel_check, within
 
 pytestmark = pytest.mark.gpu
 
@@ -28,28 +28,6 @@ def _workload(name):
     if name == "room":
         return S.config0()
     return S.config1()
-
-
-def _texel_check(gv, ov, probes, rec_o, slot_of, rel=1e-5):
-    """Compare atlases of the probes in `probes` (oracle float64 vs GPU)."""
-    gi = gv.irradiance[..., :3].float().cpu().numpy().astype(np.float64)
-    gd = gv.distance.float().cpu().numpy().astype(np.float64)
-    oi, od = ov.irr, ov.dist
-    ti = tau(oi.reshape(-1, 3))
-    td = tau(od.reshape(-1, 2))
-    worst = 0.0
-    bad = []
-    for q in probes:
-        k = rec_o["kappa"][slot_of[q]].max() if q in slot_of else 0.0
-        tol_i = rel * np.maximum(np.abs(oi[q]), ti.reshape(1, 1, 3)) + 8 * U32 * k
-        tol_d = rel * np.maximum(np.abs(od[q]), td.reshape(1, 1, 2))
-        ei = np.abs(gi[q] - oi[q]) / tol_i
-        ed = np.abs(gd[q] - od[q]) / tol_d
-        m = max(ei.max(), ed.max())
-        worst = max(worst, m)
-        if m > 1:
-            bad.append((q, float(ei.max()), float(ed.max())))
-    return worst, bad
 
 
 @pytest.mark.parametrize("name", ["room", "city"])
@@ -107,7 +85,7 @@ def test_update_and_query_parity(torch, name):
         slot_of = {int(q): np.arange(i * n_rays, (i + 1) * n_rays) for i, q in enumerate(probe_list)}
         taint_probes = np.unique(probes[tainted])
         clean_probes = [int(q) for q in range(gv.n_probes) if q not in set(taint_probes.tolist())]
-        worst, bad = _texel_check(gv, ov[0], clean_probes, rec_o, slot_of)
+        worst, bad = texel_check(gv, ov[0], clean_probes, rec_o, slot_of)
         print(f"[parity] {name} frame {f}: texel worst err/tol = {worst:.3f}, tainted probes {len(taint_probes)}",
               flush=True)
         assert not bad, bad[:5]
