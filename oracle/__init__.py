@@ -59,7 +59,8 @@ class VolumeStruct(C.Structure):
     _fields_ = [("origin", C.c_float * 3), ("spacing", C.c_float * 3), ("counts", C.c_int32 * 3),
                 ("rays", C.c_int32), ("alpha_irr", C.c_float), ("alpha_dist", C.c_float),
                 ("cos_power", C.c_float), ("bias", C.c_float), ("dmax", C.c_float), ("cheb_power", C.c_int32),
-                ("irr", C.c_void_p), ("dist", C.c_void_p), ("states", C.c_void_p), ("offsets", C.c_void_p)]
+                ("irr", C.c_void_p), ("dist", C.c_void_p), ("states", C.c_void_p), ("offsets", C.c_void_p),
+                ("irr_kappa", C.c_void_p), ("dist_kappa", C.c_void_p)]
 
 
 def _p(a):
@@ -200,6 +201,9 @@ class Volume:
         if states is not None:
             self.states[:] = states
         self.offsets = np.zeros((P, 3), dtype=np.float32)
+        # float32 sensitivity of every texel (units of 2^-24), carried by the blend
+        self.irr_kappa = np.zeros((P, 8, 8, 3))
+        self.dist_kappa = np.zeros((P, 16, 16, 2))
 
     def struct(self) -> VolumeStruct:
         d = self.desc
@@ -216,6 +220,7 @@ class Volume:
         for arr in (self.irr, self.dist, self.states, self.offsets):
             assert arr.flags.c_contiguous
         s.irr, s.dist, s.states, s.offsets = _p(self.irr), _p(self.dist), _p(self.states), _p(self.offsets)
+        s.irr_kappa, s.dist_kappa = _p(self.irr_kappa), _p(self.dist_kappa)
         return s
 
 

@@ -485,6 +485,12 @@ void orc_sf_direction(int32_t i, int32_t n, const float R[9], double out[3]) {
 void orc_blend_probe(int32_t n, const double* omega, const double* rgb, const double* d,
                      double cos_power, double alpha_irr, double alpha_dist,
                      double* irr, double* dist) {
+  orc_blend_probe_k(n, omega, rgb, NULL, d, cos_power, alpha_irr, alpha_dist, irr, dist, NULL, NULL);
+}
+
+void orc_blend_probe_k(int32_t n, const double* omega, const double* rgb, const double* rgb_kappa, const double* d,
+                       double cos_power, double alpha_irr, double alpha_dist, double* irr, double* dist,
+                       double* irr_k, double* dist_k) {
   for (int32_t y = 1; y <= 6; y++)
     for (int32_t x = 1; x <= 6; x++) {
       double nt[3], W = 0, acc[3] = {0, 0, 0};
@@ -497,7 +503,20 @@ void orc_blend_probe(int32_t n, const double* omega, const double* rgb, const do
       if (W > 0.0)
         for (int c = 0; c < 3; c++) {
           double* t = &irr[(y * 8 + x) * 3 + c];
-          *t = alpha_irr * (*t) + (1.0 - alpha_irr) * (acc[c] / W);
+          double nv = acc[c] / W;
+          if (irr_k) {
+            double kw = 0.0, kr = 0.0;
+            for (int32_t r = 0; r < n; r++) {
+              double cw = dot3(nt, omega + 3 * r);
+              double w = fmax(0.0, cw);
+              if (cw > -8.0 * U32) kw += fabs(rgb[3 * r + c] - nv) * 8.0;
+              if (rgb_kappa) kr += w * rgb_kappa[3 * r + c];
+            }
+            double kn = kw / W + kr / W + 8.0 * fabs(nv);
+            double* kt = &irr_k[(y * 8 + x) * 3 + c];
+            *kt = alpha_irr * (*kt) + (1.0 - alpha_irr) * kn + 4.0 * fabs(*t);
+          }
+          *t = alpha_irr * (*t) + (1.0 - alpha_irr) * nv;
         }
     }
   for (int32_t y = 1; y <= 14; y++)
@@ -512,8 +531,23 @@ void orc_blend_probe(int32_t n, const double* omega, const double* rgb, const do
       }
       if (W > 0.0) {
         double* t = &dist[(y * 16 + x) * 2];
-        t[0] = alpha_dist * t[0] + (1.0 - alpha_dist) * (m1 / W);
-        t[1] = alpha_dist * t[1] + (1.0 - alpha_dist) * (m2 / W);
+        double n1 = m1 / W, n2 = m2 / W;
+        if (dist_k) {
+          double k1 = 0.0, k2 = 0.0;
+          for (int32_t r = 0; r < n; r++) {
+            double cw = dot3(nt, omega + 3 * r);
+            if (cw <= -8.0 * U32) continue;
+            /* |dw/dc| * 8u with w = c^p */
+            double dw = cos_power * pow(fmax(cw, 8.0 * U32), cos_power - 1.0) * 8.0;
+            k1 += fabs(d[r] - n1) * dw;
+            k2 += fabs(d[r] * d[r] - n2) * dw;
+          }
+          double* kt = &dist_k[(y * 16 + x) * 2];
+          kt[0] = alpha_dist * kt[0] + (1.0 - alpha_dist) * (k1 / W + 8.0 * fabs(n1)) + 4.0 * fabs(t[0]);
+          kt[1] = alpha_dist * kt[1] + (1.0 - alpha_dist) * (k2 / W + 8.0 * fabs(n2)) + 4.0 * fabs(t[1]);
+        }
+        t[0] = alpha_dist * t[0] + (1.0 - alpha_dist) * n1;
+        t[1] = alpha_dist * t[1] + (1.0 - alpha_dist) * n2;
       }
     }
   for (int32_t y = 0; y < 8; y++)
@@ -521,14 +555,20 @@ void orc_blend_probe(int32_t n, const double* omega, const double* rgb, const do
       int32_t sx, sy;
       orc_border_source(8, x, y, &sx, &sy);
       if (sx != x || sy != y)
-        for (int c = 0; c < 3; c++) irr[(y * 8 + x) * 3 + c] = irr[(sy * 8 + sx) * 3 + c];
+        for (int c = 0; c < 3; c++) {
+          irr[(y * 8 + x) * 3 + c] = irr[(sy * 8 + sx) * 3 + c];
+          if (irr_k) irr_k[(y * 8 + x) * 3 + c] = irr_k[(sy * 8 + sx) * 3 + c];
+        }
     }
   for (int32_t y = 0; y < 16; y++)
     for (int32_t x = 0; x < 16; x++) {
       int32_t sx, sy;
       orc_border_source(16, x, y, &sx, &sy);
       if (sx != x || sy != y)
-        for (int c = 0; c < 2; c++) dist[(y * 16 + x) * 2 + c] = dist[(sy * 16 + sx) * 2 + c];
+        for (int c = 0; c < 2; c++) {
+          dist[(y * 16 + x) * 2 + c] = dist[(sy * 16 + sx) * 2 + c];
+          if (dist_k) dist_k[(y * 16 + x) * 2 + c] = dist_k[(sy * 16 + sx) * 2 + c];
+        }
     }
 }
 
@@ -585,7 +625,7 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
     f[a] = clampd(u[a] - (double)g[a], 0.0, 1.0);
     Xb[a] = X[a] + (0.2 * n[a] + 0.8 * wo[a]) * (0.75 * D) * (double)V->bias;
   }
-  double w[8], e[8][3], sens[8];
+  double w[8], e[8][3], ek[8][3], sens[8];
   int32_t ids[8];
   double W = 0;
   int used = 0;
@@ -619,6 +659,13 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
            mu, mu2 and r enter through the cancellations mu2 - mu^2, r - mu */
         double dmu = 4.0 * fabs(mm[0]) + 32.0 * (hi[0] - lo[0]);
         double dmu2 = 4.0 * fabs(mm[1]) + 32.0 * (hi[1] - lo[1]);
+        if (V->dist_kappa) {
+          /* the float32 atlas itself differs by its texels' sensitivity */
+          double kk[2];
+          orc_sample_tile(V->dist_kappa + q * 16 * 16 * 2, 16, 2, zd, kk);
+          dmu += kk[0];
+          dmu2 += kk[1];
+        }
         double dvar = dmu2 + 2.0 * fabs(mm[0]) * dmu + 4.0 * (fabs(mm[1]) + mm[0] * mm[0]);
         double ddl = 4.0 * r + dmu;
         if (var > 0.0)
@@ -631,6 +678,8 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
     w[used] = wt * wb * wv;
     sens[used] = s;
     orc_sample_tile(V->irr + q * 8 * 8 * 3, 8, 3, n, e[used]);
+    if (V->irr_kappa) orc_sample_tile(V->irr_kappa + q * 8 * 8 * 3, 8, 3, n, ek[used]);
+    else ek[used][0] = ek[used][1] = ek[used][2] = 0.0;
     W += w[used];
     used++;
   }
@@ -649,7 +698,7 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
     for (int c = 0; c < 3; c++) {
       double dv = fabs(e[i][c] - out[c]);
       double term = isinf(sens[i]) ? (dv > 0 ? dv / U32 : 0.0) : (w[i] / W) * dv * sens[i];
-      kap[c] += term + (w[i] / W) * 16.0 * fabs(e[i][c]);
+      kap[c] += term + (w[i] / W) * (16.0 * fabs(e[i][c]) + ek[i][c]);
     }
     if (w[i] > 0.0 && cage && ncage && *ncage < 8) cage[(*ncage)++] = ids[i];
   }
@@ -959,16 +1008,22 @@ int64_t orc_update_frame(const orc_scene* s, const orc_lights* L, orc_volume* vo
     for (int64_t q = 0; q < P; q++) {
       if (slot[q] < 0) continue;
       double* rgb = (double*)malloc(sizeof(double) * 3 * (size_t)N);
+      double* rk = (double*)malloc(sizeof(double) * 3 * (size_t)N);
       double* d = (double*)malloc(sizeof(double) * (size_t)N);
       for (int32_t r = 0; r < N; r++) {
         const orc_ray_record* rr = &rec[off + slot[q] * N + r];
-        for (int c = 0; c < 3; c++) rgb[3 * r + c] = rr->rgb[c];
+        for (int c = 0; c < 3; c++) {
+          rgb[3 * r + c] = rr->rgb[c];
+          rk[3 * r + c] = rr->kappa[c];
+        }
         d[r] = rr->d;
       }
       int fresh = V->states[q] == ORC_NEWLY_AWAKE || V->states[q] == ORC_NEWLY_VIGILANT;
-      orc_blend_probe(N, omega, rgb, d, (double)V->cos_power, fresh ? 0.0 : (double)V->alpha_irr,
-                      fresh ? 0.0 : (double)V->alpha_dist, V->irr + q * 192, V->dist + q * 512);
+      orc_blend_probe_k(N, omega, rgb, rk, d, (double)V->cos_power, fresh ? 0.0 : (double)V->alpha_irr,
+                        fresh ? 0.0 : (double)V->alpha_dist, V->irr + q * 192, V->dist + q * 512,
+                        V->irr_kappa ? V->irr_kappa + q * 192 : NULL, V->dist_kappa ? V->dist_kappa + q * 512 : NULL);
       free(rgb);
+      free(rk);
       free(d);
     }
     for (int64_t q = 0; q < P; q++) {

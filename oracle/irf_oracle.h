@@ -66,6 +66,8 @@ typedef struct {
   double* dist;       /* [P][16][16][2] */
   uint8_t* states;    /* [P] */
   const float* offsets; /* [P][3] or NULL */
+  double* irr_kappa;  /* [P][8][8][3] or NULL: float32 sensitivity of each texel (units of u) */
+  double* dist_kappa; /* [P][16][16][2] or NULL */
 } orc_volume;
 
 typedef struct {
@@ -114,6 +116,13 @@ void orc_trace_batch(const orc_scene* s, int64_t n, const double* o, const doubl
 void orc_blend_probe(int32_t n, const double* omega, const double* rgb, const double* d,
                      double cos_power, double alpha_irr, double alpha_dist,
                      double* irr_tile, double* dist_tile);
+/* the same blend, also carrying the float32 sensitivity of every texel
+   (units of u): the rays' own (rgb_kappa, [n][3], may be NULL), the weights'
+   (a float32 cosine is off by about 8 u absolute) and rounding; kappa tiles
+   blend with the same hysteresis as the texels */
+void orc_blend_probe_k(int32_t n, const double* omega, const double* rgb, const double* rgb_kappa, const double* d,
+                       double cos_power, double alpha_irr, double alpha_dist, double* irr_tile, double* dist_tile,
+                       double* irr_kappa, double* dist_kappa);
 
 /* ---- query E(X, n, w_o) over cascaded volumes ---- */
 void orc_query(const orc_volume* vols, int32_t nvol, const double X[3], const double n[3],

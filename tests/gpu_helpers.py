@@ -63,10 +63,11 @@ def compare_records(g, o, taint_probes_prev=None, probe_base=0):
     return tainted, bad_flip, report
 
 
-def texel_check(gv, ov, probes, rec_o, slot_of, rel=1e-5):
+def texel_check(gv, ov, probes, rec_o=None, slot_of=None, rel=1e-5):
     """Compare the atlases of `probes` (oracle float64 vs GPU): per texel
-    |g - o| <= rel * max(|o|, tau) + 8 u kappa, kappa = the largest kappa of
-    the probe's rays (their radiance enters the texel as a convex combination)."""
+    |g - o| <= rel * max(|o|, tau) + 8 u kappa, kappa = the oracle's float32
+    sensitivity of that texel (its rays' radiance, its blend weights and
+    rounding, carried through the hysteresis)."""
     gi = gv.irradiance[..., :3].float().cpu().numpy().astype(np.float64)
     gd = gv.distance.float().cpu().numpy().astype(np.float64)
     oi, od = ov.irr, ov.dist
@@ -75,9 +76,8 @@ def texel_check(gv, ov, probes, rec_o, slot_of, rel=1e-5):
     worst = 0.0
     bad = []
     for q in probes:
-        k = rec_o["kappa"][slot_of[q]].max() if q in slot_of else 0.0
-        tol_i = rel * np.maximum(np.abs(oi[q]), ti.reshape(1, 1, 3)) + 8 * U32 * k
-        tol_d = rel * np.maximum(np.abs(od[q]), td.reshape(1, 1, 2))
+        tol_i = rel * np.maximum(np.abs(oi[q]), ti.reshape(1, 1, 3)) + 8 * U32 * ov.irr_kappa[q]
+        tol_d = rel * np.maximum(np.abs(od[q]), td.reshape(1, 1, 2)) + 8 * U32 * ov.dist_kappa[q]
         ei = np.abs(gi[q] - oi[q]) / tol_i
         ed = np.abs(gd[q] - od[q]) / tol_d
         m = max(ei.max(), ed.max())
