@@ -200,6 +200,32 @@ irf_status irf_update_probes(irf_ctx* ctx, const float* rotation, void* stream);
 irf_status irf_query_irradiance(irf_ctx* ctx, const float* pos, const float* nrm, const float* view,
                                 int64_t n, float* out_rgb, void* stream);
 
+/* Launch shapes of the frame's main kernels: the number of workgroups of
+   the persistent probe-ray traversal, shadow-ray traversal, hit shading and
+   matrix-core blend; each strides over the work of all volumes.  0 selects
+   one workgroup per work unit of the largest possible frame.  Values are
+   normally chosen by the autotuner (paper_2009_10796_amd/autotune.py). */
+typedef struct {
+  int32_t trace_blocks;
+  int32_t shadow_blocks;
+  int32_t shade_blocks;
+  int32_t blend_blocks;
+} irf_tuning;
+irf_status irf_set_tuning(irf_ctx* ctx, const irf_tuning* tuning);
+irf_status irf_get_tuning(const irf_ctx* ctx, irf_tuning* tuning);
+
+/* A whole update frame captured as a HIP graph.  irf_graph_capture records
+   the frame's launches on `stream` (not the null stream) without running
+   them; irf_graph_launch replays it with a new rotation and the context's
+   current lights (the frame's parameters are arguments of its first node,
+   updated before each launch).  A graph stays valid while the scene,
+   volumes, bound buffers, light count and tuning are unchanged; otherwise
+   irf_graph_launch returns IRF_E_STATE and the frame must be captured again. */
+typedef struct irf_graph irf_graph;
+irf_status irf_graph_capture(irf_ctx* ctx, void* stream, irf_graph** out);
+irf_status irf_graph_launch(irf_ctx* ctx, irf_graph* graph, const float* rotation, void* stream);
+void irf_graph_destroy(irf_graph* graph);
+
 /* Per-ray records of the last update for one volume, in active-probe order
    (ascending probe index) then ray order.  Synchronizes `stream`.  Writes at
    most `capacity` records to the device buffer `out` and the count to

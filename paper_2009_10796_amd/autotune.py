@@ -1,0 +1,74 @@
+"""Autotuner of the frame's launch shapes.
+
+For each persistent kernel of the update (probe-ray traversal, shadow-ray
+traversal, hit shading, matrix-core blend) it times a set of grid sizes
+(multiples of the compute-unit count, plus 0 = one workgroup per work unit)
+on the live workload, with the library's own kernel timing, and keeps the
+fastest.  The choice is returned as a dict, can be saved as JSON and applied
+to another context with ``apply``.  Tuning runs real frames: call it during
+warm-up.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, Iterable, Optional
+
+KNOBS = (("trace_blocks", "trace"), ("shadow_blocks", "shadow"), ("shade_blocks", "shade"),
+         ("blend_blocks", "blend_mma"))
+
+
+def candidates(cu: int) -> list:
+    return [0] + [cu * k for k in (1, 2, 4, 8, 16)]
+
+
+def autotune(ctx, rotations: Iterable, frames_per_candidate: int = 3, cu: Optional[int] = None,
+             step=None) -> Dict[str, int]:
+    """Tunes ctx in place.  `rotations` supplies one rotation per frame run;
+    `step(R)` runs one frame (default: ctx.update_probes)."""
+    torch = ctx.torch
+    if cu is None:
+        cu = torch.cuda.get_device_properties(ctx.device).multi_processor_count
+    step = step or ctx.update_probes
+    rot = iter(rotations)
+    chosen = {}
+    report = {}
+    for knob, kernel in KNOBS:
+        times = {}
+        for c in candidates(cu):
+            ctx.set_tuning(**{knob: c})
+            step(next(rot))                       # settle
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            ctx.profile_read(reset=True)
+            for _ in range(frames_per_candidate):
+                step(next(rot))
+            torch.cuda.synchronize()
+            prof = ctx.profile_read(reset=True)
+            ctx.profile(False)
+            if kernel not in prof:
+                break
+            n, ms = prof[kernel]
+            times[c] = ms / n
+        if times:
+            best = min(times, key=times.get)
+            ctx.set_tuning(**{knob: best})
+            chosen[knob] = best
+            report[knob] = {str(k): round(1e3 * v, 2) for k, v in times.items()}
+    ctx.tuning_report = report
+    return chosen
+
+
+def save(tuning: Dict[str, int], path: str, workload: str, report: Optional[dict] = None) -> None:
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump({"workload": workload, "tuning": tuning, "candidate_us": report or {}}, f, indent=1)
+
+
+def load(path: str) -> Dict[str, int]:
+    with open(path) as f:
+        return {k: int(v) for k, v in json.load(f)["tuning"].items()}
+
+
+def apply(ctx, tuning: Dict[str, int]) -> None:
+    ctx.set_tuning(**tuning)

@@ -79,6 +79,7 @@ struct irf_ctx {
   VolumeGPU vol[IRF_MAX_VOLUMES];
   bool bound[IRF_MAX_VOLUMES];
   // frame scratch
+  DevBuf<FrameParams> params;
   DevBuf<int32_t> active;
   DevBuf<FrameCounters> counters;
   DevBuf<float4> omega;
@@ -94,6 +95,7 @@ struct irf_ctx {
   DevBuf<int32_t> class_back;
   DevBuf<uint32_t> class_tf;
   bool frame_done = false;
+  Tuning tune = {0, 0, 0, 0};
   // kernel timing
   bool prof = false;
   struct ProfRec {
@@ -114,6 +116,7 @@ irf_status set_device(const irf_ctx* c) {
 
 SceneGPU scene_view(const irf_ctx* c) {
   SceneGPU s;
+  memset(&s, 0, sizeof(s));   // padding too: frame_signature hashes the bytes
   s.nodes = c->nodes.p;
   s.tris = c->tris.p;
   s.albedo = c->albedo.p;
@@ -126,6 +129,7 @@ SceneGPU scene_view(const irf_ctx* c) {
 
 ObjectBoxes boxes_view(const irf_ctx* c) {
   ObjectBoxes b;
+  memset(&b, 0, sizeof(b));
   b.lo = c->obj_lo.p;
   b.hi = c->obj_hi.p;
   b.n = c->n_obj;
@@ -159,6 +163,7 @@ irf_status ensure_scratch(irf_ctx* c) {
   if (R >= (1ll << 27)) return fail(IRF_E_UNSUPPORTED, "too many rays per frame (%lld >= 2^27)", (long long)R);
   int64_t om = 0;
   for (int v = 0; v < c->n_vol; v++) om += c->vol[v].rays;
+  if ((s = c->params.reserve(1)) != IRF_OK) return s;
   if ((s = c->active.reserve((size_t)P)) != IRF_OK) return s;
   if ((s = c->counters.reserve(1)) != IRF_OK) return s;
   if ((s = c->omega.reserve((size_t)om)) != IRF_OK) return s;
@@ -178,6 +183,8 @@ irf_status ensure_scratch(irf_ctx* c) {
 
 FrameScratch scratch_view(const irf_ctx* c) {
   FrameScratch f;
+  memset(&f, 0, sizeof(f));   // padding too: frame_signature hashes the bytes
+  f.params = c->params.p;
   f.active = c->active.p;
   f.counters = c->counters.p;
   f.omega = c->omega.p;
@@ -238,7 +245,69 @@ irf_status launched() {
   return IRF_OK;
 }
 
+// One update frame, asynchronously on `st` (also what a graph captures).
+void enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st) {
+  VolumeSet vs = volume_view(c);
+  FrameScratch fs = scratch_view(c);
+  SceneGPU sc = scene_view(c);
+  const int nl = c->lights.n_dir + c->lights.n_point;
+  FrameParams fp;
+  for (int i = 0; i < 9; i++) fp.R[i] = rotation[i];
+  fp.L = c->lights;
+  launch_set_params(fp, fs, st);
+  { ProfScope p(c, "state_compact", st); launch_state_compact(vs, boxes_view(c), fs, st); }
+  { ProfScope p(c, "directions", st); launch_directions(vs, fs, st); }
+  bool any_mma = false, any_valu = false;
+  for (int v = 0; v < c->n_vol; v++) (c->vol[v].blend == IRF_BLEND_F32_VALU ? any_valu : any_mma) = true;
+  if (any_mma) {
+    ProfScope p(c, "weights", st);
+    launch_weights(vs, fs, st);
+  }
+  { ProfScope p(c, "trace", st); launch_trace(vs, sc, fs, c->tune.trace_blocks, st); }
+  if (nl > 0) {
+    ProfScope p(c, "shadow", st);
+    launch_shadow(vs, sc, nl, fs, c->tune.shadow_blocks, st);
+  }
+  { ProfScope p(c, "shade", st); launch_shade(vs, sc, fs, c->tune.shade_blocks, st); }
+  if (any_valu) {
+    ProfScope p(c, "blend_valu", st);
+    launch_blend(vs, fs, st);
+  }
+  if (any_mma) {
+    ProfScope p(c, "blend_mma", st);
+    launch_blend_mma(vs, fs, c->tune.blend_blocks, st);
+  }
+}
+
+// Hash of everything a captured frame bakes into its nodes.
+uint64_t frame_signature(const irf_ctx* c) {
+  VolumeSet vs = volume_view(c);
+  FrameScratch fs = scratch_view(c);
+  SceneGPU sc = scene_view(c);
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; i++) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  mix(&vs, sizeof(vs));
+  mix(&fs, sizeof(fs));
+  mix(&sc, sizeof(sc));
+  mix(&c->tune, sizeof(c->tune));
+  int nl = c->lights.n_dir + c->lights.n_point;
+  mix(&nl, sizeof(nl));
+  return h;
+}
+
 }  // namespace
+
+struct irf_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t params_node = nullptr;
+  hipKernelNodeParams kp;
+  uint64_t signature = 0;
+  irf_ctx* ctx = nullptr;
+};
 
 extern "C" {
 
@@ -285,6 +354,7 @@ void irf_destroy(irf_ctx* c) {
   c->emission.release();
   c->obj_lo.release();
   c->obj_hi.release();
+  c->params.release();
   c->active.release();
   c->counters.release();
   c->omega.release();
@@ -562,32 +632,7 @@ irf_status irf_update_probes(irf_ctx* c, const float* rotation, void* stream) {
   if (s != IRF_OK) return s;
   if ((s = set_device(c)) != IRF_OK) return s;
   if ((s = ensure_scratch(c)) != IRF_OK) return s;
-  hipStream_t st = (hipStream_t)stream;
-  VolumeSet vs = volume_view(c);
-  FrameScratch fs = scratch_view(c);
-  SceneGPU sc = scene_view(c);
-  { ProfScope p(c, "state_compact", st); launch_state_compact(vs, boxes_view(c), fs, st); }
-  { ProfScope p(c, "directions", st); launch_directions(vs, rotation, fs.omega, st); }
-  bool any_mma = false, any_valu = false;
-  for (int v = 0; v < c->n_vol; v++) (c->vol[v].blend == IRF_BLEND_F32_VALU ? any_valu : any_mma) = true;
-  if (any_mma) {
-    ProfScope p(c, "weights", st);
-    launch_weights(vs, fs, st);
-  }
-  { ProfScope p(c, "trace", st); launch_trace(vs, sc, c->lights, fs, st); }
-  if (c->lights.n_dir + c->lights.n_point > 0) {
-    ProfScope p(c, "shadow", st);
-    launch_shadow(vs, sc, c->lights, fs, st);
-  }
-  { ProfScope p(c, "shade", st); launch_shade(vs, sc, c->lights, fs, st); }
-  if (any_valu) {
-    ProfScope p(c, "blend_valu", st);
-    launch_blend(vs, fs, st);
-  }
-  if (any_mma) {
-    ProfScope p(c, "blend_mma", st);
-    launch_blend_mma(vs, fs, st);
-  }
+  enqueue_frame(c, rotation, (hipStream_t)stream);
   c->frame_done = true;
   return launched();
 }
@@ -655,13 +700,119 @@ irf_status irf_traversal_stats(irf_ctx* c, int64_t out[4], void* stream) {
   irf_status s = set_device(c);
   if (s != IRF_OK) return s;
   hipStream_t st = (hipStream_t)stream;
-  launch_traversal_stats(volume_view(c), scene_view(c), c->lights, scratch_view(c), c->stats.p, st);
+  launch_traversal_stats(volume_view(c), scene_view(c), c->lights.n_dir + c->lights.n_point, scratch_view(c),
+                         c->stats.p, st);
   if ((s = launched()) != IRF_OK) return s;
   unsigned long long k[4];
   HIP_TRY(hipMemcpyAsync(k, c->stats.p, sizeof(k), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   for (int i = 0; i < 4; i++) out[i] = (int64_t)k[i];
   return IRF_OK;
+}
+
+irf_status irf_set_tuning(irf_ctx* c, const irf_tuning* t) {
+  if (!c || !t) return fail(IRF_E_INVALID, "NULL argument");
+  if (t->trace_blocks < 0 || t->shadow_blocks < 0 || t->shade_blocks < 0 || t->blend_blocks < 0)
+    return fail(IRF_E_INVALID, "tuning values must be >= 0");
+  c->tune.trace_blocks = t->trace_blocks;
+  c->tune.shadow_blocks = t->shadow_blocks;
+  c->tune.shade_blocks = t->shade_blocks;
+  c->tune.blend_blocks = t->blend_blocks;
+  return IRF_OK;
+}
+
+irf_status irf_get_tuning(const irf_ctx* c, irf_tuning* t) {
+  if (!c || !t) return fail(IRF_E_INVALID, "NULL argument");
+  t->trace_blocks = c->tune.trace_blocks;
+  t->shadow_blocks = c->tune.shadow_blocks;
+  t->shade_blocks = c->tune.shade_blocks;
+  t->blend_blocks = c->tune.blend_blocks;
+  return IRF_OK;
+}
+
+irf_status irf_graph_capture(irf_ctx* c, void* stream, irf_graph** out) {
+  if (!c || !out) return fail(IRF_E_INVALID, "NULL argument");
+  *out = nullptr;
+  if (!stream) return fail(IRF_E_INVALID, "capture needs a stream other than the null stream");
+  irf_status s = check_ready(c);
+  if (s != IRF_OK) return s;
+  if ((s = set_device(c)) != IRF_OK) return s;
+  if ((s = ensure_scratch(c)) != IRF_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const float identity[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  const bool prof = c->prof;
+  c->prof = false;
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    c->prof = prof;
+    return fail(IRF_E_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  enqueue_frame(c, identity, st);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(st, &graph);
+  c->prof = prof;
+  if (e != hipSuccess) return fail(IRF_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  irf_graph* g = new irf_graph();
+  g->graph = graph;
+  g->ctx = c;
+  size_t n = 0;
+  HIP_TRY(hipGraphGetRootNodes(graph, nullptr, &n));
+  std::vector<hipGraphNode_t> roots(n);
+  if (n) HIP_TRY(hipGraphGetRootNodes(graph, roots.data(), &n));
+  for (auto node : roots) {
+    hipGraphNodeType type;
+    if (hipGraphNodeGetType(node, &type) != hipSuccess || type != hipGraphNodeTypeKernel) continue;
+    hipKernelNodeParams kp;
+    if (hipGraphKernelNodeGetParams(node, &kp) != hipSuccess) continue;
+    if (kp.func == set_params_kernel()) {
+      g->params_node = node;
+      g->kp = kp;
+    }
+  }
+  if (!g->params_node) {
+    (void)hipGraphDestroy(graph);
+    delete g;
+    return fail(IRF_E_HIP, "captured frame has no parameter node");
+  }
+  e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    delete g;
+    return fail(IRF_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  g->signature = frame_signature(c);
+  *out = g;
+  return IRF_OK;
+}
+
+irf_status irf_graph_launch(irf_ctx* c, irf_graph* g, const float* rotation, void* stream) {
+  if (!c || !g || !rotation) return fail(IRF_E_INVALID, "NULL argument");
+  if (g->ctx != c) return fail(IRF_E_INVALID, "graph belongs to another context");
+  for (int i = 0; i < 9; i++)
+    if (!std::isfinite(rotation[i])) return fail(IRF_E_INVALID, "rotation is not finite");
+  if (frame_signature(c) != g->signature)
+    return fail(IRF_E_STATE, "scene, volumes, buffers, light count or tuning changed since capture: capture again");
+  irf_status s = set_device(c);
+  if (s != IRF_OK) return s;
+  FrameParams fp;
+  for (int i = 0; i < 9; i++) fp.R[i] = rotation[i];
+  fp.L = c->lights;
+  FrameParams* dst = c->params.p;
+  void* args[2] = {&fp, &dst};
+  hipKernelNodeParams kp = g->kp;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  HIP_TRY(hipGraphExecKernelNodeSetParams(g->exec, g->params_node, &kp));
+  HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  c->frame_done = true;
+  return IRF_OK;
+}
+
+void irf_graph_destroy(irf_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 irf_status irf_profile_enable(irf_ctx* c, int32_t enable) {

@@ -56,6 +56,20 @@ struct LightSet {
   float sky[3];
 };
 
+// Per-frame parameters read by the frame's kernels from device memory.
+struct FrameParams {
+  float R[9];      // rotation of the spherical-Fibonacci pattern
+  LightSet L;
+};
+
+// Launch shapes chosen by the autotuner (0 = default).
+struct Tuning {
+  int32_t trace_blocks;
+  int32_t shadow_blocks;
+  int32_t shade_blocks;
+  int32_t blend_blocks;
+};
+
 // Dynamic-object boxes (state step and classification wake rule).
 struct ObjectBoxes {
   const float* lo;   // [n][3]
@@ -88,6 +102,7 @@ struct HitRec {
 
 // Frame scratch (library-owned device memory).
 struct FrameScratch {
+  FrameParams* params;      // rotation and lights of the frame
   int32_t* active;          // [max_slots] global probe id per active slot
   FrameCounters* counters;  // device
   float4* omega;            // [sum rays] direction table for this frame
@@ -111,19 +126,21 @@ int build_bvh(const float* vertices, int64_t nv, const uint32_t* indices, int64_
               std::vector<float4>& nodes, std::vector<float4>& tris, double stats[5]);
 
 // ---- launches (kernels_*.hip); all asynchronous on `s`
-void launch_directions(const VolumeSet& vs, const float R[9], float4* omega, hipStream_t s);
+void launch_set_params(const FrameParams& p, FrameScratch fs, hipStream_t s);
+const void* set_params_kernel();
+void launch_directions(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
 void launch_state_compact(const VolumeSet& vs, ObjectBoxes boxes, FrameScratch fs, hipStream_t s);
-void launch_trace(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s);
-void launch_shadow(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s);
-void launch_shade(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s);
+void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s);
+void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, hipStream_t s);
+void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s);
 void launch_blend(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
 void launch_weights(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
-void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
+void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, int grid, hipStream_t s);
 void launch_query(const VolumeSet& vs, const float* pos, const float* nrm, const float* view, int64_t n,
                   float* out, hipStream_t s);
 void launch_classify(const VolumeSet& vs, SceneGPU sc, ObjectBoxes boxes, const float* rotations, int K,
                      int32_t* back, uint32_t* tfront, hipStream_t s);
-void launch_traversal_stats(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, unsigned long long* out,
+void launch_traversal_stats(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, unsigned long long* out,
                             hipStream_t s);
 void launch_frame_stats(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, unsigned long long* out, hipStream_t s);
 void launch_records(const VolumeSet& vs, int vol, SceneGPU sc, FrameScratch fs, int n_lights,

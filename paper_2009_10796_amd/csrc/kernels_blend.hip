@@ -107,10 +107,6 @@ __global__ __launch_bounds__(256) void k_weights(VolumeSet vs, FrameScratch fs) 
   if (threadIdx.x == 0) fs.inv_row_sum[v * kRows + row] = part[0] > 0.0f ? 1.0f / part[0] : 0.0f;
 }
 
-struct BlendArgs {
-  int32_t block_base[IRF_MAX_VOLUMES + 1];   // workgroups of volume v: [block_base[v], block_base[v+1])
-};
-
 template <int MODE>
 struct Mma;
 
@@ -193,21 +189,11 @@ __device__ __forceinline__ float load_ch(const VolumeGPU& V, bool irr, int q, in
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kBlendMmaBlock) void k_blend_mma(VolumeSet vs, FrameScratch fs, BlendArgs A) {
-  constexpr int LDS_BYTES =
-      MODE == IRF_BLEND_F32 ? kKC * kBfStride * 4 : 48 * kBtStride * 2;
-  __shared__ __attribute__((aligned(16))) char lds[LDS_BYTES];
-  __shared__ int s_q[kPB];
-  __shared__ uint8_t s_state[kPB];
-  const FrameCounters& C = *fs.counters;
-  const int wg = blockIdx.x / kRSplit, split = blockIdx.x % kRSplit;
-  int v = 0;
-  while (v + 1 < vs.n && wg >= A.block_base[v + 1]) v++;
+__device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScratch& fs, const FrameCounters& C, int v,
+                                           int pblock, int split, char* lds, int* s_q, uint8_t* s_state) {
   const VolumeGPU& V = vs.v[v];
-  if (V.blend != MODE) return;
   const int count = C.slot_base[v + 1] - C.slot_base[v];
-  const int slot0 = (wg - A.block_base[v]) * kPB;
-  if (slot0 >= count) return;
+  const int slot0 = pblock * kPB;
   const int np = min(kPB, count - slot0);
   const int N = V.rays;
   if (threadIdx.x < kPB) {
@@ -323,6 +309,30 @@ __global__ __launch_bounds__(kBlendMmaBlock) void k_blend_mma(VolumeSet vs, Fram
   // Newly states are promoted by k_promote once every workgroup has read them.
 }
 
+// Persistent over work items (probe block x row split) of every volume whose
+// blend mode is MODE.
+template <int MODE>
+__global__ __launch_bounds__(kBlendMmaBlock) void k_blend_mma(VolumeSet vs, FrameScratch fs) {
+  constexpr int LDS_BYTES = MODE == IRF_BLEND_F32 ? kKC * kBfStride * 4 : 48 * kBtStride * 2;
+  __shared__ __attribute__((aligned(16))) char lds[LDS_BYTES];
+  __shared__ int s_q[kPB];
+  __shared__ uint8_t s_state[kPB];
+  const FrameCounters& C = *fs.counters;
+  int item_base[IRF_MAX_VOLUMES + 1];
+  item_base[0] = 0;
+  for (int v = 0; v < vs.n; v++) {
+    int count = vs.v[v].blend == MODE ? C.slot_base[v + 1] - C.slot_base[v] : 0;
+    item_base[v + 1] = item_base[v] + (count + kPB - 1) / kPB * kRSplit;
+  }
+  for (int wi = blockIdx.x; wi < item_base[vs.n]; wi += gridDim.x) {
+    int v = 0;
+    while (v + 1 < vs.n && wi >= item_base[v + 1]) v++;
+    const int local = wi - item_base[v];
+    __syncthreads();   // the previous item's epilogue has finished with s_q / s_state
+    blend_item<MODE>(vs, fs, C, v, local / kRSplit, local % kRSplit, lds, s_q, s_state);
+  }
+}
+
 __global__ void k_promote(VolumeSet vs, FrameScratch fs) {
   const FrameCounters& C = *fs.counters;
   int gslot = blockIdx.x * blockDim.x + threadIdx.x;
@@ -341,22 +351,21 @@ void launch_weights(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
   hipLaunchKernelGGL(k_weights, dim3(kRows, vs.n), dim3(256), 0, s, vs, fs);
 }
 
-void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
-  BlendArgs A;
-  A.block_base[0] = 0;
+void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, int grid, hipStream_t s) {
   bool mode_present[3] = {false, false, false};
+  int full = 0;
   for (int v = 0; v < vs.n; v++) {
-    A.block_base[v + 1] = A.block_base[v] + (vs.v[v].n_probes + kPB - 1) / kPB;
+    full += (vs.v[v].n_probes + kPB - 1) / kPB * kRSplit;
     if (vs.v[v].blend <= IRF_BLEND_F16) mode_present[vs.v[v].blend] = true;
   }
-  const unsigned grid = (unsigned)A.block_base[vs.n] * kRSplit;
-  if (grid == 0) return;
+  if (full == 0) return;
+  const unsigned g = (unsigned)(grid > 0 && grid < full ? grid : full);
   if (mode_present[IRF_BLEND_F32])
-    hipLaunchKernelGGL(k_blend_mma<IRF_BLEND_F32>, dim3(grid), dim3(kBlendMmaBlock), 0, s, vs, fs, A);
+    hipLaunchKernelGGL(k_blend_mma<IRF_BLEND_F32>, dim3(g), dim3(kBlendMmaBlock), 0, s, vs, fs);
   if (mode_present[IRF_BLEND_BF16])
-    hipLaunchKernelGGL(k_blend_mma<IRF_BLEND_BF16>, dim3(grid), dim3(kBlendMmaBlock), 0, s, vs, fs, A);
+    hipLaunchKernelGGL(k_blend_mma<IRF_BLEND_BF16>, dim3(g), dim3(kBlendMmaBlock), 0, s, vs, fs);
   if (mode_present[IRF_BLEND_F16])
-    hipLaunchKernelGGL(k_blend_mma<IRF_BLEND_F16>, dim3(grid), dim3(kBlendMmaBlock), 0, s, vs, fs, A);
+    hipLaunchKernelGGL(k_blend_mma<IRF_BLEND_F16>, dim3(g), dim3(kBlendMmaBlock), 0, s, vs, fs);
   if (fs.max_slots > 0)
     hipLaunchKernelGGL(k_promote, dim3((fs.max_slots + 255) / 256), dim3(256), 0, s, vs, fs);
 }

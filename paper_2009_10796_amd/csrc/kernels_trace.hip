@@ -246,11 +246,12 @@ __device__ __forceinline__ bool shadow_ray(const LightSet& L, int l, float3 X, f
 // Nearest hit of every active probe ray.  Front-face hits also queue their
 // shadow rays in the slice of their wave (light-major, so the tasks of one
 // light from one probe stay contiguous) and clear their visibility bytes.
-// No atomics: each wave owns its slice and writes its own count.
-__global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeSet vs, SceneGPU sc, LightSet L, FrameScratch fs) {
-  const FrameCounters& C = *fs.counters;
-  int64_t id = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
-  if (id >= C.ray_base[vs.n]) return;
+// No atomics: each wave owns its slice and writes its own count.  The grid
+// strides over the rays of all volumes (persistent when the grid is smaller
+// than the ray count); the stride is a multiple of 64, so a wave always holds
+// 64 consecutive rays.
+__device__ __forceinline__ void trace_one(const VolumeSet& vs, const SceneGPU& sc, const LightSet& L,
+                                          const FrameScratch& fs, const FrameCounters& C, int64_t id) {
   RaySlot s = locate_ray(vs, C, fs.active, id);
   const VolumeGPU& V = vs.v[s.v];
   float3 o = probe_position(V, s.q);
@@ -291,6 +292,15 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeSet vs, SceneGPU sc
   if (lane == __ffsll((long long)__ballot(1)) - 1) fs.wave_tasks[wave] = n;
 }
 
+__global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeSet vs, SceneGPU sc, FrameScratch fs) {
+  const FrameCounters& C = *fs.counters;
+  const LightSet& L = fs.params->L;
+  const int64_t total = C.ray_base[vs.n];
+  for (int64_t id = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x; id < total;
+       id += (int64_t)gridDim.x * kTraceBlock)
+    trace_one(vs, sc, L, fs, C, id);
+}
+
 // Exclusive prefix sum of the per-wave task counts (one workgroup).
 constexpr int kScanBlock = 1024;
 __global__ __launch_bounds__(kScanBlock) void k_scan_tasks(VolumeSet vs, FrameScratch fs) {
@@ -318,19 +328,23 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tasks(VolumeSet vs, FrameSc
 }
 
 // Any-hit shadow rays over the dense task index space: task k lives in the
-// slice of the last wave whose offset is <= k.
-__global__ __launch_bounds__(kTraceBlock) void k_shadow(VolumeSet vs, SceneGPU sc, LightSet L, FrameScratch fs) {
-  const FrameCounters& C = *fs.counters;
-  int64_t k = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
-  if (k >= C.shadow_total) return;
-  const int nl = L.n_dir + L.n_point;
-  int64_t lo = 0, hi = (C.ray_base[vs.n] + 63) / 64 - 1;
+// slice of the last wave whose offset is <= k.  Grid-stride over all tasks.
+__device__ __forceinline__ int64_t task_wave(const FrameScratch& fs, const FrameCounters& C, int nvol, int64_t k) {
+  int64_t lo = 0, hi = (C.ray_base[nvol] + 63) / 64 - 1;
   while (lo < hi) {
     int64_t mid = (lo + hi + 1) >> 1;
     if (fs.wave_offset[mid] <= k) lo = mid;
     else hi = mid - 1;
   }
-  uint32_t task = fs.shadow_tasks[lo * 64 * nl + (k - fs.wave_offset[lo])];
+  return lo;
+}
+
+template <typename CNT>
+__device__ __forceinline__ void shadow_one(const VolumeSet& vs, const SceneGPU& sc, const LightSet& L,
+                                           const FrameScratch& fs, const FrameCounters& C, int64_t k, CNT* cnt) {
+  const int nl = L.n_dir + L.n_point;
+  int64_t src = task_wave(fs, C, vs.n, k);
+  uint32_t task = fs.shadow_tasks[src * 64 * nl + (k - fs.wave_offset[src])];
   int64_t id = task >> 5;
   int l = task & 31;
   RaySlot s = locate_ray(vs, C, fs.active, id);
@@ -345,16 +359,22 @@ __global__ __launch_bounds__(kTraceBlock) void k_shadow(VolumeSet vs, SceneGPU s
   shadow_ray(L, l, X, ng, Xs, dl, tmax);
   Ray ray = make_ray(Xs, dl);
   float t;
-  int hit = traverse<true, false>(sc, ray, tmax, t, dyn_stack + threadIdx.x, kTraceBlock);
-  if (hit < 0) fs.vis[(int64_t)l * fs.max_rays + id] = 1;
+  int hit = traverse<true, false, CNT>(sc, ray, tmax, t, dyn_stack + threadIdx.x, kTraceBlock, cnt);
+  if (!cnt && hit < 0) fs.vis[(int64_t)l * fs.max_rays + id] = 1;
+}
+
+__global__ __launch_bounds__(kTraceBlock) void k_shadow(VolumeSet vs, SceneGPU sc, FrameScratch fs) {
+  const FrameCounters& C = *fs.counters;
+  const LightSet& L = fs.params->L;
+  const int64_t total = C.shadow_total;
+  for (int64_t k = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x; k < total; k += (int64_t)gridDim.x * kTraceBlock)
+    shadow_one<NoCount>(vs, sc, L, fs, C, k, nullptr);
 }
 
 // Radiance and distance carried by each probe ray (backface rule of the
 // self-shadow-bias section: radiance 0, distance shortened by 80 %).
-__global__ __launch_bounds__(kTraceBlock) void k_shade(VolumeSet vs, SceneGPU sc, LightSet L, FrameScratch fs) {
-  const FrameCounters& C = *fs.counters;
-  int64_t id = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
-  if (id >= C.ray_base[vs.n]) return;
+__device__ __forceinline__ void shade_one(const VolumeSet& vs, const SceneGPU& sc, const LightSet& L,
+                                          const FrameScratch& fs, const FrameCounters& C, int64_t id) {
   RaySlot s = locate_ray(vs, C, fs.active, id);
   const VolumeGPU& V = vs.v[s.v];
   float3 o = probe_position(V, s.q);
@@ -396,6 +416,15 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(VolumeSet vs, SceneGPU sc
     }
   }
   fs.rays[id] = out;
+}
+
+__global__ __launch_bounds__(kTraceBlock) void k_shade(VolumeSet vs, SceneGPU sc, FrameScratch fs) {
+  const FrameCounters& C = *fs.counters;
+  const LightSet& L = fs.params->L;
+  const int64_t total = C.ray_base[vs.n];
+  for (int64_t id = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x; id < total;
+       id += (int64_t)gridDim.x * kTraceBlock)
+    shade_one(vs, sc, L, fs, C, id);
 }
 
 // ---- classification (Section "Full Probe Initialization Algorithm")
@@ -503,50 +532,26 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_count(VolumeSet vs, Scene
   add_block(&out[1], cnt.tris);
 }
 
-__global__ __launch_bounds__(kTraceBlock) void k_shadow_count(VolumeSet vs, SceneGPU sc, LightSet L, FrameScratch fs,
+__global__ __launch_bounds__(kTraceBlock) void k_shadow_count(VolumeSet vs, SceneGPU sc, FrameScratch fs,
                                                               unsigned long long* out) {
   const FrameCounters& C = *fs.counters;
   int64_t k = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
   Count cnt;
-  if (k < C.shadow_total) {
-    const int nl = L.n_dir + L.n_point;
-    int64_t lo = 0, hi = (C.ray_base[vs.n] + 63) / 64 - 1;
-    while (lo < hi) {
-      int64_t mid = (lo + hi + 1) >> 1;
-      if (fs.wave_offset[mid] <= k) lo = mid;
-      else hi = mid - 1;
-    }
-    uint32_t task = fs.shadow_tasks[lo * 64 * nl + (k - fs.wave_offset[lo])];
-    int64_t id = task >> 5;
-    int l = task & 31;
-    RaySlot s = locate_ray(vs, C, fs.active, id);
-    const VolumeGPU& V = vs.v[s.v];
-    float3 o = probe_position(V, s.q);
-    float4 w = fs.omega[V.omega_base + s.r];
-    HitRec h = fs.hits[id];
-    float3 ng = tri_normal(sc, h.tri);
-    float3 X = f3(fmaf(h.t, w.x, o.x), fmaf(h.t, w.y, o.y), fmaf(h.t, w.z, o.z));
-    float3 Xs, dl;
-    float tmax;
-    shadow_ray(L, l, X, ng, Xs, dl, tmax);
-    float t;
-    traverse<true, false, Count>(sc, make_ray(Xs, dl), tmax, t, dyn_stack + threadIdx.x, kTraceBlock, &cnt);
-  }
+  if (k < C.shadow_total) shadow_one<Count>(vs, sc, fs.params->L, fs, C, k, &cnt);
   add_block(&out[2], cnt.nodes);
   add_block(&out[3], cnt.tris);
 }
 
-void launch_traversal_stats(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, unsigned long long* out,
+void launch_traversal_stats(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, unsigned long long* out,
                             hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)out, 0u, (int64_t)8);
   if (fs.max_rays == 0) return;
   hipLaunchKernelGGL(k_trace_count, dim3(blocks_for(fs.max_rays, kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s,
                      vs, sc, fs, out);
-  int nl = L.n_dir + L.n_point;
-  if (nl == 0) return;
-  int64_t cap = (fs.max_rays + 63) / 64 * 64 * nl;
+  if (n_lights == 0) return;
+  int64_t cap = (fs.max_rays + 63) / 64 * 64 * n_lights;
   hipLaunchKernelGGL(k_shadow_count, dim3(blocks_for(cap, kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc,
-                     L, fs, out);
+                     fs, out);
 }
 
 // ---- frame statistics (on demand, outside the frame)
@@ -601,24 +606,29 @@ __global__ void k_records(VolumeSet vs, int vol, SceneGPU sc, FrameScratch fs, i
 
 // ---- launches
 
-void launch_trace(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s) {
-  if (fs.max_rays == 0) return;
-  hipLaunchKernelGGL(k_trace, dim3(blocks_for(fs.max_rays, kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc,
-                     L, fs);
+// grid: 0 = one block per 128 items of the largest possible frame;
+// otherwise a persistent grid of that many blocks striding over the items
+static inline unsigned grid_for(int64_t items, int grid) {
+  unsigned full = blocks_for(items, kTraceBlock);
+  if (grid <= 0 || (unsigned)grid > full) return full > 0 ? full : 1;
+  return (unsigned)grid;
 }
 
-void launch_shadow(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s) {
-  int nl = L.n_dir + L.n_point;
-  if (fs.max_rays == 0 || nl == 0) return;
+void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s) {
+  if (fs.max_rays == 0) return;
+  hipLaunchKernelGGL(k_trace, dim3(grid_for(fs.max_rays, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs);
+}
+
+void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, hipStream_t s) {
+  if (fs.max_rays == 0 || n_lights == 0) return;
   hipLaunchKernelGGL(k_scan_tasks, dim3(1), dim3(kScanBlock), 0, s, vs, fs);
-  int64_t cap = (fs.max_rays + 63) / 64 * 64 * nl;
-  hipLaunchKernelGGL(k_shadow, dim3(blocks_for(cap, kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, L,
-                     fs);
+  int64_t cap = (fs.max_rays + 63) / 64 * 64 * n_lights;
+  hipLaunchKernelGGL(k_shadow, dim3(grid_for(cap, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs);
 }
 
-void launch_shade(const VolumeSet& vs, SceneGPU sc, LightSet L, FrameScratch fs, hipStream_t s) {
+void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s) {
   if (fs.max_rays == 0) return;
-  hipLaunchKernelGGL(k_shade, dim3(blocks_for(fs.max_rays, kTraceBlock)), dim3(kTraceBlock), 0, s, vs, sc, L, fs);
+  hipLaunchKernelGGL(k_shade, dim3(grid_for(fs.max_rays, grid)), dim3(kTraceBlock), 0, s, vs, sc, fs);
 }
 
 void launch_classify(const VolumeSet& vs, SceneGPU sc, ObjectBoxes boxes, const float* rotations, int K,

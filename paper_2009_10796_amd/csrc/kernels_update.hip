@@ -30,18 +30,20 @@ __device__ __forceinline__ float3 sf_dir(int i, int n, const float* R) {
             fmaf(R[6], p.x, fmaf(R[7], p.y, R[8] * p.z)));
 }
 
-struct Rot {
-  float m[9];
-};
+// The frame's parameters (rotation, lights) are kernel arguments of this one
+// node, so a captured frame is re-launched with new ones by updating it.
+__global__ void k_set_params(FrameParams p, FrameParams* dst) {
+  if (threadIdx.x == 0) *dst = p;
+}
 
-__global__ void k_directions(VolumeSet vs, Rot R, float4* omega) {
+__global__ void k_directions(VolumeSet vs, FrameScratch fs) {
   int v = blockIdx.y;
   if (v >= vs.n) return;
   const VolumeGPU& V = vs.v[v];
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= V.rays) return;
-  float3 w = sf_dir(r, V.rays, R.m);
-  omega[V.omega_base + r] = make_float4(w.x, w.y, w.z, 0.0f);
+  float3 w = sf_dir(r, V.rays, fs.params->R);
+  fs.omega[V.omega_base + r] = make_float4(w.x, w.y, w.z, 0.0f);
 }
 
 __device__ __forceinline__ bool active_state(uint8_t s) {
@@ -276,12 +278,16 @@ __global__ __launch_bounds__(kQueryBlock) void k_query(VolumeSet vs, const float
 
 static inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-void launch_directions(const VolumeSet& vs, const float R[9], float4* omega, hipStream_t s) {
-  Rot r;
-  for (int i = 0; i < 9; i++) r.m[i] = R[i];
+void launch_set_params(const FrameParams& p, FrameScratch fs, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_params, dim3(1), dim3(64), 0, s, p, fs.params);
+}
+
+const void* set_params_kernel() { return (const void*)k_set_params; }
+
+void launch_directions(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
   int maxr = 0;
   for (int v = 0; v < vs.n; v++) maxr = vs.v[v].rays > maxr ? vs.v[v].rays : maxr;
-  hipLaunchKernelGGL(k_directions, dim3(nblocks(maxr, 256), vs.n), dim3(256), 0, s, vs, r, omega);
+  hipLaunchKernelGGL(k_directions, dim3(nblocks(maxr, 256), vs.n), dim3(256), 0, s, vs, fs);
 }
 
 void launch_state_compact(const VolumeSet& vs, ObjectBoxes boxes, FrameScratch fs, hipStream_t s) {

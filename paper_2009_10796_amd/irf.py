@@ -54,6 +54,11 @@ class BufferSizes(C.Structure):
                 ("states_bytes", C.c_int64), ("offsets_bytes", C.c_int64)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("trace_blocks", C.c_int32), ("shadow_blocks", C.c_int32), ("shade_blocks", C.c_int32),
+                ("blend_blocks", C.c_int32)]
+
+
 class KernelTime(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double)]
 
@@ -80,6 +85,11 @@ SIGNATURES = {
     "irf_ray_records": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(_i64), _vp]),
     "irf_frame_stats": (C.c_int, [_vp, C.POINTER(_i64 * 4), _vp]),
     "irf_traversal_stats": (C.c_int, [_vp, C.POINTER(_i64 * 4), _vp]),
+    "irf_set_tuning": (C.c_int, [_vp, C.POINTER(Tuning)]),
+    "irf_get_tuning": (C.c_int, [_vp, C.POINTER(Tuning)]),
+    "irf_graph_capture": (C.c_int, [_vp, _vp, C.POINTER(_vp)]),
+    "irf_graph_launch": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "irf_graph_destroy": (None, [_vp]),
     "irf_profile_enable": (C.c_int, [_vp, _i32]),
     "irf_profile_read": (C.c_int, [_vp, _vp, _i32, C.POINTER(_i32), _i32]),
     "irf_validate_volume_desc": (C.c_int, [C.POINTER(VolumeDescC)]),
@@ -266,6 +276,26 @@ class Context:
         _check(load().irf_traversal_stats(self.handle, C.byref(out), _stream(self.torch)))
         return {"probe_nodes": out[0], "probe_tris": out[1], "shadow_nodes": out[2], "shadow_tris": out[3]}
 
+    def set_tuning(self, **kw) -> None:
+        t = Tuning()
+        _check(load().irf_get_tuning(self.handle, C.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        _check(load().irf_set_tuning(self.handle, C.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(load().irf_get_tuning(self.handle, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+    def capture_frame(self, stream=None) -> "FrameGraph":
+        """Captures one update frame as a HIP graph on `stream` (a torch
+        stream other than the default one)."""
+        st = stream or self.torch.cuda.current_stream()
+        g = C.c_void_p()
+        _check(load().irf_graph_capture(self.handle, C.c_void_p(st.cuda_stream), C.byref(g)))
+        return FrameGraph(self, g, st)
+
     def profile(self, enable: bool = True) -> None:
         _check(load().irf_profile_enable(self.handle, int(enable)))
 
@@ -285,6 +315,29 @@ class Context:
         _check(load().irf_ray_records(self.handle, vol, C.c_void_p(buf.data_ptr()), n, C.byref(cnt), _stream(torch)))
         torch.cuda.current_stream().synchronize()
         return buf[: n * RECORD_DTYPE.itemsize].cpu().numpy().view(RECORD_DTYPE)
+
+
+class FrameGraph:
+    """A captured update frame; launch(rotation) replays it with the
+    context's current lights."""
+
+    def __init__(self, ctx: Context, handle, stream):
+        self.ctx, self.handle, self.stream = ctx, handle, stream
+
+    def launch(self, rotation) -> None:
+        R = _np(rotation, np.float32).reshape(9)
+        _check(load().irf_graph_launch(self.ctx.handle, self.handle, _ptr(R), C.c_void_p(self.stream.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().irf_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def build_workload(w, device: int = 0):

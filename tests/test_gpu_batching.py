@@ -1,0 +1,116 @@
+"""Batched frame: persistent launches over all cascades, the frame captured as
+a HIP graph, and the autotuner.  Every variant must give the same atlases,
+bit for bit, as the plain eager frame (the frame's kernels are
+deterministic: no atomics, fixed reduction orders)."""
+import numpy as np
+import pytest
+
+from paper_2009_10796_amd import scenes as S
+from tests.test_gpu_cascades import small_terrain
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _snapshot(ctx):
+    return [(v.irradiance.cpu().numpy().copy(), v.distance.cpu().numpy().copy(), v.states.cpu().numpy().copy())
+            for v in ctx.volumes]
+
+
+def _same(a, b):
+    return all(np.array_equal(x, y) for va, vb in zip(a, b) for x, y in zip(va, vb))
+
+
+def test_persistent_grids_match_default(torch):
+    from paper_2009_10796_amd import irf
+    w = small_terrain()
+    A = irf.build_workload(w)
+    B = irf.build_workload(w)
+    # tiny persistent grids: every workgroup loops over many work items
+    B.set_tuning(trace_blocks=7, shadow_blocks=5, shade_blocks=3, blend_blocks=2)
+    for c in (A, B):
+        c.classify(w.classify_rotations)
+    for f in (1, 2, 3):
+        L = S.sun_for_frame(f)
+        R = w.frame_rotation(f)
+        for c in (A, B):
+            c.set_lights(L)
+            c.update_probes(R)
+        torch.cuda.synchronize()
+        assert _same(_snapshot(A), _snapshot(B)), f
+    A.close()
+    B.close()
+
+
+def test_graph_replays_match_eager(torch):
+    from paper_2009_10796_amd import irf
+    w = small_terrain()
+    A = irf.build_workload(w)
+    B = irf.build_workload(w)
+    for c in (A, B):
+        c.classify(w.classify_rotations)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        g = B.capture_frame(s)
+    q = S.surface_points(w.scene, 4096, 3)
+    pos, nrm = torch.from_numpy(q.pos).cuda(), torch.from_numpy(q.nrm).cuda()
+    for f in range(1, 7):
+        L = S.sun_for_frame(f)
+        R = w.frame_rotation(f)
+        A.set_lights(L)
+        B.set_lights(L)
+        A.update_probes(R)
+        with torch.cuda.stream(s):
+            g.launch(R)
+        s.synchronize()
+        torch.cuda.synchronize()
+        assert _same(_snapshot(A), _snapshot(B)), f
+        # eager work between replays, on the same context
+        ea = A.query_irradiance(pos, nrm, nrm).cpu().numpy()
+        eb = B.query_irradiance(pos, nrm, nrm).cpu().numpy()
+        assert np.array_equal(ea, eb)
+    # a change the graph baked in is refused
+    B.set_tuning(trace_blocks=11)
+    with pytest.raises(irf.IrfError) as e:
+        with torch.cuda.stream(s):
+            g.launch(w.frame_rotation(9))
+    assert e.value.status == irf.E_STATE
+    g.close()
+    A.close()
+    B.close()
+
+
+def test_autotuner_keeps_results(torch):
+    from paper_2009_10796_amd import autotune, irf
+    w = small_terrain()
+    A = irf.build_workload(w)
+    B = irf.build_workload(w)
+    for c in (A, B):
+        c.classify(w.classify_rotations)
+        c.set_lights(S.sun_for_frame(0))
+    chosen = autotune.autotune(B, S.rotations(3, 200, start_frame=100), frames_per_candidate=1)
+    assert set(chosen) == {"trace_blocks", "shadow_blocks", "shade_blocks", "blend_blocks"}
+    # after tuning, the same frames from the same state agree with the default launch shapes
+    for c in (A, B):
+        for v in c.volumes:
+            v.irradiance.zero_()
+            v.distance.zero_()
+    B_states = [v.states.clone() for v in B.volumes]
+    for va, s_ in zip(A.volumes, B_states):
+        va.states.copy_(s_)
+    for f in (1, 2):
+        R = w.frame_rotation(f)
+        A.update_probes(R)
+        B.update_probes(R)
+    torch.cuda.synchronize()
+    assert _same(_snapshot(A), _snapshot(B))
+    A.close()
+    B.close()
