@@ -103,6 +103,67 @@ def blend_variants(w, R, frames, irf, torch):
     return res
 
 
+def terrain_batched(irf, torch, frames=60):
+    """The batching workload: four cascades of 32x16x32 probes (1, 2, 4, 8 m)
+    over ~1.1M triangles of terrain and buildings, 192 rays, a sun moving
+    1 degree per frame; launch shapes autotuned, the frame captured as a HIP
+    graph and replayed for `frames` frames."""
+    from paper_2009_10796_amd import autotune, scenes as S
+    w = S.config3()
+    ctx = irf.build_workload(w, device=0)
+    ctx.classify(w.classify_rotations)
+    R = S.rotations(w.config, 400, start_frame=1)
+    states0 = [v.states.clone() for v in ctx.volumes]
+    # frames 1-2 converge the probes, then tune on later frames
+    ctx.set_lights(S.sun_for_frame(0))
+    for f in range(2):
+        ctx.update_probes(R[f])
+    tuning = autotune.autotune(ctx, R[200:], frames_per_candidate=2)
+    for v, st in zip(ctx.volumes, states0):
+        v.states.copy_(st)
+        v.irradiance.zero_()
+        v.distance.zero_()
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        g = ctx.capture_frame(s)
+    times = []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    active = []
+    for f in range(frames):
+        ctx.set_lights(S.sun_for_frame(f))
+        with torch.cuda.stream(s):
+            ev0.record(s)
+            g.launch(R[f])
+            ev1.record(s)
+        ev1.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+        if f == 1:
+            active = [int(np.isin(v.states.cpu().numpy(), [4, 5]).sum()) for v in ctx.volumes]
+    stats = ctx.frame_stats()
+    eager = []
+    for f in range(frames, frames + 10):
+        ctx.set_lights(S.sun_for_frame(f))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.update_probes(R[f])
+        torch.cuda.synchronize()
+        eager.append(1e3 * (time.perf_counter() - t0))
+    g.close()
+    ctx.close()
+    steady = np.array(times[2:])
+    prim, shad = stats["probe_rays"], stats["shadow_rays"]
+    p50 = float(np.median(steady))
+    return {"workload": w.name, "triangles": int(w.scene.n_triangles), "frames": frames,
+            "probes_per_cascade": int(w.volumes[0].n_probes), "active_per_cascade": active,
+            "rays_per_frame": {"primary": int(prim), "shadow": int(shad)},
+            "graph_ms_per_frame": {"p50": round(p50, 4), "p95": round(float(np.quantile(steady, 0.95)), 4),
+                                   "first": round(times[0], 4)},
+            "eager_ms_per_frame_p50": round(float(np.median(eager)), 4),
+            "grays_per_s": round((prim + shad) / (p50 * 1e-3) / 1e9, 3),
+            "tuning": tuning}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +171,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-blend-variants", action="store_true")
+    ap.add_argument("--no-terrain", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -218,6 +280,9 @@ def main():
     if not args.no_blend_variants:
         print("[bench] blend variants ...", file=sys.stderr, flush=True)
         line["blend_variants"] = blend_variants(w, R, 8, irf, torch)
+    if not args.no_terrain:
+        print("[bench] terrain (batched cascades) ...", file=sys.stderr, flush=True)
+        line["batched"] = terrain_batched(irf, torch)
     if not args.no_cpu_baseline:
         print("[bench] oracle CPU baseline ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)

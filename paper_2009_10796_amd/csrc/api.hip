@@ -80,6 +80,7 @@ struct irf_ctx {
   bool bound[IRF_MAX_VOLUMES];
   // frame scratch
   DevBuf<FrameParams> params;
+  DevBuf<int32_t> block_active;
   DevBuf<int32_t> active;
   DevBuf<FrameCounters> counters;
   DevBuf<float4> omega;
@@ -165,6 +166,9 @@ irf_status ensure_scratch(irf_ctx* c) {
   for (int v = 0; v < c->n_vol; v++) om += c->vol[v].rays;
   if ((s = c->params.reserve(1)) != IRF_OK) return s;
   if ((s = c->active.reserve((size_t)P)) != IRF_OK) return s;
+  int64_t nb = 0;
+  for (int v = 0; v < c->n_vol; v++) nb += (c->vol[v].n_probes + 1023) / 1024;
+  if ((s = c->block_active.reserve((size_t)(nb > 0 ? nb : 1))) != IRF_OK) return s;
   if ((s = c->counters.reserve(1)) != IRF_OK) return s;
   if ((s = c->omega.reserve((size_t)om)) != IRF_OK) return s;
   if ((s = c->hits.reserve((size_t)R)) != IRF_OK) return s;
@@ -185,6 +189,7 @@ FrameScratch scratch_view(const irf_ctx* c) {
   FrameScratch f;
   memset(&f, 0, sizeof(f));   // padding too: frame_signature hashes the bytes
   f.params = c->params.p;
+  f.block_active = c->block_active.p;
   f.active = c->active.p;
   f.counters = c->counters.p;
   f.omega = c->omega.p;
@@ -356,6 +361,7 @@ void irf_destroy(irf_ctx* c) {
   c->obj_hi.release();
   c->params.release();
   c->active.release();
+  c->block_active.release();
   c->counters.release();
   c->omega.release();
   c->hits.release();

@@ -103,6 +103,7 @@ struct HitRec {
 // Frame scratch (library-owned device memory).
 struct FrameScratch {
   FrameParams* params;      // rotation and lights of the frame
+  int32_t* block_active;    // [compaction workgroups] active probes per workgroup
   int32_t* active;          // [max_slots] global probe id per active slot
   FrameCounters* counters;  // device
   float4* omega;            // [sum rays] direction table for this frame

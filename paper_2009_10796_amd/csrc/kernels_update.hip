@@ -67,59 +67,96 @@ __device__ __forceinline__ bool near_dynamic(const VolumeGPU& V, ObjectBoxes ob,
 
 constexpr int kCompactBlock = 1024;
 
-// Single workgroup: state step, then an ordered compaction (ascending probe
-// index within each volume, volumes in order) with wave ballots.
-__global__ __launch_bounds__(kCompactBlock) void k_state_compact(VolumeSet vs, ObjectBoxes ob, FrameScratch fs) {
+// Workgroups of volume v: [A.block_base[v], A.block_base[v+1]), each covering
+// kCompactBlock consecutive probes of that volume only.
+struct CompactArgs {
+  int32_t block_base[IRF_MAX_VOLUMES + 1];
+};
+
+__device__ __forceinline__ int compact_volume(const CompactArgs& A, int nvol, int b) {
+  int v = 0;
+  while (v + 1 < nvol && b >= A.block_base[v + 1]) v++;
+  return v;
+}
+
+// Pass 1: state step (dynamic-object wake/sleep) and the number of active
+// probes of every workgroup.
+__global__ __launch_bounds__(kCompactBlock) void k_state_count(VolumeSet vs, ObjectBoxes ob, CompactArgs A,
+                                                                FrameScratch fs) {
   __shared__ int wave_tot[kCompactBlock / 64];
-  __shared__ int wave_off[kCompactBlock / 64];
-  __shared__ FrameCounters C;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int slot = 0;
-  int64_t rays = 0;
-  for (int v = 0; v < vs.n; v++) {
-    const VolumeGPU& V = vs.v[v];
-    if (threadIdx.x == 0) {
-      C.slot_base[v] = slot;
-      C.ray_base[v] = rays;
+  const int b = blockIdx.x;
+  const int v = compact_volume(A, vs.n, b);
+  const VolumeGPU& V = vs.v[v];
+  const int q = (b - A.block_base[v]) * kCompactBlock + threadIdx.x;
+  bool act = false;
+  if (q < V.n_probes) {
+    uint8_t st = V.states[q];
+    if (ob.n > 0 && (st == IRF_SLEEPING || st == IRF_AWAKE)) {
+      bool near = near_dynamic(V, ob, probe_position(V, q));
+      uint8_t ns = st;
+      if (st == IRF_SLEEPING && near) ns = IRF_NEWLY_AWAKE;
+      if (st == IRF_AWAKE && !near) ns = IRF_SLEEPING;
+      if (ns != st) V.states[q] = ns;
+      st = ns;
     }
-    int start = slot;
-    for (int base = 0; base < V.n_probes; base += kCompactBlock) {
-      int q = base + threadIdx.x;
-      bool act = false;
-      if (q < V.n_probes) {
-        uint8_t st = V.states[q];
-        if (ob.n > 0 && (st == IRF_SLEEPING || st == IRF_AWAKE)) {
-          bool near = near_dynamic(V, ob, probe_position(V, q));
-          uint8_t ns = st;
-          if (st == IRF_SLEEPING && near) ns = IRF_NEWLY_AWAKE;
-          if (st == IRF_AWAKE && !near) ns = IRF_SLEEPING;
-          if (ns != st) V.states[q] = ns;
-          st = ns;
-        }
-        act = active_state(st);
-      }
-      unsigned long long m = __ballot(act);
-      int before = __popcll(m & ((1ull << lane) - 1ull));
-      if (lane == 0) wave_tot[wave] = __popcll(m);
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int w = 0; w < kCompactBlock / 64; w++) {
-          wave_off[w] = acc;
-          acc += wave_tot[w];
-        }
-        wave_tot[0] = acc;   // block total (read after the next barrier)
-      }
-      __syncthreads();
-      if (act) fs.active[slot + wave_off[wave] + before] = V.probe_base + q;
-      slot += wave_tot[0];
-      __syncthreads();
-    }
-    rays += (int64_t)(slot - start) * V.rays;
+    act = active_state(st);
   }
+  unsigned long long m = __ballot(act);
+  if ((threadIdx.x & 63) == 0) wave_tot[threadIdx.x >> 6] = __popcll(m);
+  __syncthreads();
   if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < kCompactBlock / 64; w++) t += wave_tot[w];
+    fs.block_active[b] = t;
+  }
+}
+
+// Pass 2: ordered scatter of the active list (ascending probe index within a
+// volume, volumes in order) and the per-volume slot and ray bases.
+__global__ __launch_bounds__(kCompactBlock) void k_state_scatter(VolumeSet vs, CompactArgs A, FrameScratch fs) {
+  __shared__ int wave_off[kCompactBlock / 64];
+  __shared__ int s_base;
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int v = compact_volume(A, vs.n, b);
+  const VolumeGPU& V = vs.v[v];
+  // offset of this workgroup: active probes of all earlier workgroups
+  if (wave == 0) {
+    int part = 0;
+    for (int i = lane; i < b; i += 64) part += fs.block_active[i];
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off);
+    if (lane == 0) s_base = part;
+  }
+  const int q = (b - A.block_base[v]) * kCompactBlock + threadIdx.x;
+  const bool act = q < V.n_probes && active_state(V.states[q]);
+  unsigned long long m = __ballot(act);
+  if (lane == 0) wave_off[wave] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int w = 0; w < kCompactBlock / 64; w++) {
+      int t = wave_off[w];
+      wave_off[w] = acc;
+      acc += t;
+    }
+  }
+  __syncthreads();
+  if (act) fs.active[s_base + wave_off[wave] + __popcll(m & ((1ull << lane) - 1ull))] = V.probe_base + q;
+  if (b == 0 && threadIdx.x == 0) {
+    FrameCounters C;
+    int slot = 0;
+    int64_t rays = 0;
+    for (int u = 0; u < vs.n; u++) {
+      C.slot_base[u] = slot;
+      C.ray_base[u] = rays;
+      int cnt = 0;
+      for (int i = A.block_base[u]; i < A.block_base[u + 1]; i++) cnt += fs.block_active[i];
+      slot += cnt;
+      rays += (int64_t)cnt * vs.v[u].rays;
+    }
     C.slot_base[vs.n] = slot;
     C.ray_base[vs.n] = rays;
+    C.shadow_total = 0;
     *fs.counters = C;
   }
 }
@@ -291,7 +328,12 @@ void launch_directions(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
 }
 
 void launch_state_compact(const VolumeSet& vs, ObjectBoxes boxes, FrameScratch fs, hipStream_t s) {
-  hipLaunchKernelGGL(k_state_compact, dim3(1), dim3(kCompactBlock), 0, s, vs, boxes, fs);
+  CompactArgs A;
+  A.block_base[0] = 0;
+  for (int v = 0; v < vs.n; v++) A.block_base[v + 1] = A.block_base[v] + (vs.v[v].n_probes + kCompactBlock - 1) / kCompactBlock;
+  if (A.block_base[vs.n] == 0) return;
+  hipLaunchKernelGGL(k_state_count, dim3(A.block_base[vs.n]), dim3(kCompactBlock), 0, s, vs, boxes, A, fs);
+  hipLaunchKernelGGL(k_state_scatter, dim3(A.block_base[vs.n]), dim3(kCompactBlock), 0, s, vs, A, fs);
 }
 
 void launch_blend(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
