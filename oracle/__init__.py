@@ -72,6 +72,7 @@ def _declare(L):
     L.orc_scene_create.restype = vp
     L.orc_scene_create.argtypes = [vp, i64, vp, i64, vp, vp, vp, vp, i32]
     L.orc_scene_free.argtypes = [vp]
+    L.orc_scene_set_emission.argtypes = [vp, dp]
     L.orc_scene_bvh_nodes.restype = i64
     L.orc_scene_bvh_nodes.argtypes = [vp]
     for name in ("orc_oct_encode", "orc_oct_decode"):
@@ -88,6 +89,8 @@ def _declare(L):
     L.orc_update_frame.restype = i64
     L.orc_update_frame.argtypes = [vp, vp, vp, i32, vp, vp, i64]
     L.orc_shade_ray.argtypes = [vp, vp, vp, i32, dp, dp, C.c_double, vp]
+    L.orc_query_backward.argtypes = [vp, i32, dp, dp, dp, dp, vp, vp]
+    L.orc_update_backward.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, dp]
 
 
 # ---------------------------------------------------------------- wrappers
@@ -165,6 +168,10 @@ class Scene:
         if getattr(self, "handle", None) and _lib is not None:
             _lib.orc_scene_free(self.handle)
             self.handle = None
+
+    def set_emission(self, emission) -> None:
+        e = np.ascontiguousarray(emission, dtype=np.float64).reshape(-1, 3)
+        lib().orc_scene_set_emission(self.handle, _p(e))
 
     def trace(self, origins, dirs, static_only=False, brute=False) -> np.ndarray:
         o = _d(origins).reshape(-1, 3)
@@ -275,3 +282,51 @@ def shade_ray(scene: Scene, lights, vols: List[Volume], o, w, dmax) -> np.ndarra
     lib().orc_shade_ray(scene.handle, C.byref(L), _vol_array(vols), len(vols), _p(_d(o, 3)), _p(_d(w, 3)),
                         float(dmax), _p(rec))
     return rec[0]
+
+
+# ------------------------------------------------------------------ adjoint
+
+
+def _ptr_array(arrs):
+    a = (C.c_void_p * len(arrs))()
+    for i, x in enumerate(arrs):
+        assert x.dtype == np.float64 and x.flags.c_contiguous
+        a[i] = x.ctypes.data
+    return a
+
+
+def query_backward(vols: List[Volume], pos, nrm, view, gout, g_irr, g_dist):
+    """Accumulates dLoss/d(texels) of the query (float64 gradient arrays shaped
+    like each volume's irr / dist atlases)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    nrm = np.ascontiguousarray(nrm, dtype=np.float64).reshape(-1, 3)
+    view = np.ascontiguousarray(view, dtype=np.float64).reshape(-1, 3)
+    gout = np.ascontiguousarray(gout, dtype=np.float64).reshape(-1, 3)
+    arr = _vol_array(vols)
+    gi, gd = _ptr_array(g_irr), _ptr_array(g_dist)
+    for i in range(pos.shape[0]):
+        lib().orc_query_backward(arr, len(vols), _p(pos[i]), _p(nrm[i]), _p(view[i]), _p(gout[i]), gi, gd)
+
+
+def update_backward(scene: Scene, prev: List[Volume], R, records, g_new_irr, g_new_dist, g_prev_irr, g_prev_dist,
+                    g_emission):
+    R = np.ascontiguousarray(R, dtype=np.float32).reshape(9)
+    rec = np.ascontiguousarray(records)
+    assert rec.dtype == RECORD_DTYPE
+    assert g_emission.dtype == np.float64 and g_emission.flags.c_contiguous
+    lib().orc_update_backward(scene.handle, _vol_array(prev), len(prev), _p(R), _p(rec), _ptr_array(g_new_irr),
+                              _ptr_array(g_new_dist), _ptr_array(g_prev_irr), _ptr_array(g_prev_dist),
+                              _p(g_emission))
+
+
+def copy_volumes(vols: List[Volume]) -> List[Volume]:
+    out = []
+    for v in vols:
+        c = Volume(v.desc, states=v.states)
+        c.irr[:] = v.irr
+        c.dist[:] = v.dist
+        c.offsets[:] = v.offsets
+        c.irr_kappa[:] = v.irr_kappa
+        c.dist_kappa[:] = v.dist_kappa
+        out.append(c)
+    return out

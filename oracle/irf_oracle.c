@@ -207,6 +207,10 @@ void orc_scene_free(orc_scene* s) {
 
 int64_t orc_scene_bvh_nodes(const orc_scene* s) { return s->nnodes; }
 
+void orc_scene_set_emission(orc_scene* s, const double* emission) {
+  for (int32_t m = 0; m < 3 * s->nm; m++) s->emission[m] = emission[m];
+}
+
 /* ---------------------------------------------------------- intersection */
 /* Plane intersection of ray o + t d with triangle t (Moller-Trumbore):
    returns 0 if the ray is parallel to the plane, else t and the three
@@ -1043,4 +1047,226 @@ int64_t orc_update_frame(const orc_scene* s, const orc_lights* L, orc_volume* vo
   }
   free(prev);
   return total_rays;
+}
+
+/* ================================================================ adjoint */
+/* Reverse pass of the query and of one update frame with the ray hits and
+   shadow decisions of the forward frame held fixed (the quantities are then
+   smooth functions of emission and texels, except at the Chebyshev branch
+   point r = mu where the weight is C1). */
+
+static void footprint(int32_t m, const double v[3], int32_t* x0, int32_t* y0, double* fx, double* fy) {
+  int32_t k = m - 2;
+  double p[2];
+  orc_oct_encode(v, p);
+  double cx = 1.0 + (0.5 * p[0] + 0.5) * k - 0.5;
+  double cy = 1.0 + (0.5 * p[1] + 0.5) * k - 0.5;
+  *x0 = (int32_t)floor(cx);
+  *y0 = (int32_t)floor(cy);
+  if (*x0 < 0) *x0 = 0;
+  if (*x0 > k) *x0 = k;
+  if (*y0 < 0) *y0 = 0;
+  if (*y0 > k) *y0 = k;
+  *fx = clampd(cx - *x0, 0.0, 1.0);
+  *fy = clampd(cy - *y0, 0.0, 1.0);
+}
+
+/* adds g (nch channels) to the four bilinear taps of direction v */
+static void scatter_tile(double* gtile, int32_t m, int32_t nch, const double v[3], const double* g) {
+  int32_t x0, y0;
+  double fx, fy;
+  footprint(m, v, &x0, &y0, &fx, &fy);
+  const double bw[4] = {(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy};
+  const int32_t idx[4] = {y0 * m + x0, y0 * m + x0 + 1, (y0 + 1) * m + x0, (y0 + 1) * m + x0 + 1};
+  for (int t = 0; t < 4; t++)
+    for (int c = 0; c < nch; c++) gtile[idx[t] * nch + c] += bw[t] * g[c];
+}
+
+static void volume_query_backward(const orc_volume* V, const double X[3], const double n[3], const double wo[3],
+                                  const double g[3], double* g_irr, double* g_dist) {
+  double u[3], f[3], Xb[3];
+  int64_t gi[3];
+  double D = fmin((double)V->spacing[0], fmin((double)V->spacing[1], (double)V->spacing[2]));
+  for (int a = 0; a < 3; a++) {
+    u[a] = (X[a] - (double)V->origin[a]) / (double)V->spacing[a];
+    gi[a] = (int64_t)clampd(floor(u[a]), 0.0, (double)(V->counts[a] - 2));
+    f[a] = clampd(u[a] - (double)gi[a], 0.0, 1.0);
+    Xb[a] = X[a] + (0.2 * n[a] + 0.8 * wo[a]) * (0.75 * D) * (double)V->bias;
+  }
+  double w[8], e[8][3], wtb[8], zd[8][3], mmv[8][2], rr[8];
+  int64_t qs[8];
+  int cheb[8];
+  int used = 0;
+  double W = 0.0;
+  for (int c = 0; c < 8; c++) {
+    int cb[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+    int64_t q = (gi[0] + cb[0]) + (int64_t)V->counts[0] * ((gi[1] + cb[1]) + (int64_t)V->counts[1] * (gi[2] + cb[2]));
+    if (!sampled_state(V->states[q])) continue;
+    double wt = 1.0;
+    for (int a = 0; a < 3; a++) wt *= cb[a] ? f[a] : 1.0 - f[a];
+    double P[3], toP[3];
+    probe_position(V, q, P);
+    sub3(P, X, toP);
+    normalize3(toP);
+    double h = (1.0 + dot3(n, toP)) * 0.5;
+    double wb = h * h + 0.2;
+    double z[3];
+    sub3(Xb, P, z);
+    double r = len3(z);
+    double wv = 1.0;
+    cheb[used] = 0;
+    if (r > 0.0) {
+      for (int a = 0; a < 3; a++) zd[used][a] = z[a] / r;
+      orc_sample_tile(V->dist + q * 512, 16, 2, zd[used], mmv[used]);
+      if (r > mmv[used][0]) {
+        double var = fmax(mmv[used][1] - mmv[used][0] * mmv[used][0], 0.0);
+        double dl = r - mmv[used][0];
+        wv = pow(var / (var + dl * dl), (double)V->cheb_power);
+        cheb[used] = 1;
+      }
+    }
+    rr[used] = r;
+    qs[used] = q;
+    wtb[used] = wt * wb;
+    w[used] = wt * wb * wv;
+    orc_sample_tile(V->irr + q * 192, 8, 3, n, e[used]);
+    W += w[used];
+    used++;
+  }
+  if (!(W > 0.0)) return;
+  double E[3] = {0, 0, 0};
+  for (int i = 0; i < used; i++)
+    for (int c = 0; c < 3; c++) E[c] += w[i] * e[i][c] / W;
+  for (int i = 0; i < used; i++) {
+    double ge[3] = {g[0] * w[i] / W, g[1] * w[i] / W, g[2] * w[i] / W};
+    scatter_tile(g_irr + qs[i] * 192, 8, 3, n, ge);
+    if (!cheb[i]) continue;
+    double gw = 0.0;
+    for (int c = 0; c < 3; c++) gw += g[c] * (e[i][c] - E[c]) / W;
+    double mu = mmv[i][0], mu2 = mmv[i][1];
+    double raw = mu2 - mu * mu;
+    double var = fmax(raw, 0.0);
+    double dl = rr[i] - mu;
+    double den = var + dl * dl;
+    double ch = var / den;
+    double dch_dvar = dl * dl / (den * den);
+    double dch_ddl = -2.0 * dl * var / (den * den);
+    double dvar_dmu = raw > 0.0 ? -2.0 * mu : 0.0, dvar_dmu2 = raw > 0.0 ? 1.0 : 0.0;
+    double k = (double)V->cheb_power;
+    double dwv_dch = k * pow(ch, k - 1.0);
+    double gwv = gw * wtb[i] * dwv_dch;
+    double gd[2] = {gwv * (dch_dvar * dvar_dmu - dch_ddl), gwv * dch_dvar * dvar_dmu2};
+    scatter_tile(g_dist + qs[i] * 512, 16, 2, zd[i], gd);
+  }
+}
+
+void orc_query_backward(const orc_volume* vols, int32_t nvol, const double X[3], const double n[3],
+                        const double wo[3], const double gout[3], double** g_irr, double** g_dist) {
+  double Wt = 0.0;
+  for (int32_t v = 0; v < nvol; v++) {
+    const orc_volume* V = &vols[v];
+    if (Wt >= 1.0) break;
+    double wv = 1.0;
+    for (int a = 0; a < 3; a++) {
+      double u = (X[a] - (double)V->origin[a]) / (double)V->spacing[a];
+      wv *= clampd(fmin(u, (double)(V->counts[a] - 1) - u), 0.0, 1.0);
+    }
+    double wuse = (v == nvol - 1) ? 1.0 - Wt : fmin(wv, 1.0 - Wt);
+    if (wuse > 0.0) {
+      double g[3] = {wuse * gout[0], wuse * gout[1], wuse * gout[2]};
+      volume_query_backward(V, X, n, wo, g, g_irr[v], g_dist[v]);
+      Wt += wuse;
+    }
+  }
+}
+
+void orc_update_backward(const orc_scene* s, const orc_volume* prev, int32_t nvol, const float R[9],
+                         const orc_ray_record* records, double** g_new_irr, double** g_new_dist,
+                         double** g_prev_irr, double** g_prev_dist, double* g_emission) {
+  int64_t off = 0;
+  for (int32_t v = 0; v < nvol; v++) {
+    const orc_volume* V = &prev[v];
+    int64_t P = vol_probes(V);
+    int32_t N = V->rays;
+    double* omega = (double*)malloc(sizeof(double) * 3 * (size_t)N);
+    double* gL = (double*)malloc(sizeof(double) * 3 * (size_t)N);
+    for (int32_t r = 0; r < N; r++) orc_sf_direction(r, N, R, omega + 3 * r);
+    for (int64_t q = 0; q < P; q++) {
+      const double* gi = g_new_irr[v] + q * 192;
+      const double* gd = g_new_dist[v] + q * 512;
+      double* pi = g_prev_irr[v] + q * 192;
+      double* pd = g_prev_dist[v] + q * 512;
+      if (!active_state(V->states[q])) {
+        /* not updated this frame: output texels are the input texels */
+        for (int i = 0; i < 192; i++) pi[i] += gi[i];
+        for (int i = 0; i < 512; i++) pd[i] += gd[i];
+        continue;
+      }
+      int fresh = V->states[q] == ORC_NEWLY_AWAKE || V->states[q] == ORC_NEWLY_VIGILANT;
+      double ai = fresh ? 0.0 : (double)V->alpha_irr, ad = fresh ? 0.0 : (double)V->alpha_dist;
+      /* border texels repeat interior texels: fold their gradients */
+      double fi[192], fd[512];
+      memset(fi, 0, sizeof(fi));
+      memset(fd, 0, sizeof(fd));
+      for (int32_t y = 0; y < 8; y++)
+        for (int32_t x = 0; x < 8; x++) {
+          int32_t sx, sy;
+          orc_border_source(8, x, y, &sx, &sy);
+          for (int c = 0; c < 3; c++) fi[(sy * 8 + sx) * 3 + c] += gi[(y * 8 + x) * 3 + c];
+        }
+      for (int32_t y = 0; y < 16; y++)
+        for (int32_t x = 0; x < 16; x++) {
+          int32_t sx, sy;
+          orc_border_source(16, x, y, &sx, &sy);
+          for (int c = 0; c < 2; c++) fd[(sy * 16 + sx) * 2 + c] += gd[(y * 16 + x) * 2 + c];
+        }
+      for (int32_t r = 0; r < N; r++) gL[3 * r] = gL[3 * r + 1] = gL[3 * r + 2] = 0.0;
+      for (int32_t y = 1; y <= 6; y++)
+        for (int32_t x = 1; x <= 6; x++) {
+          double nt[3], W = 0.0;
+          orc_texel_direction(8, x, y, nt);
+          for (int32_t r = 0; r < N; r++) W += fmax(0.0, dot3(nt, omega + 3 * r));
+          const double* g = &fi[(y * 8 + x) * 3];
+          if (!(W > 0.0)) {
+            for (int c = 0; c < 3; c++) pi[(y * 8 + x) * 3 + c] += g[c];
+            continue;
+          }
+          for (int c = 0; c < 3; c++) pi[(y * 8 + x) * 3 + c] += ai * g[c];
+          for (int32_t r = 0; r < N; r++) {
+            double wr = fmax(0.0, dot3(nt, omega + 3 * r)) / W;
+            for (int c = 0; c < 3; c++) gL[3 * r + c] += (1.0 - ai) * wr * g[c];
+          }
+        }
+      for (int32_t y = 1; y <= 14; y++)
+        for (int32_t x = 1; x <= 14; x++) {
+          double nt[3], W = 0.0;
+          orc_texel_direction(16, x, y, nt);
+          for (int32_t r = 0; r < N; r++) W += pow(fmax(0.0, dot3(nt, omega + 3 * r)), (double)V->cos_power);
+          for (int c = 0; c < 2; c++) pd[(y * 16 + x) * 2 + c] += (W > 0.0 ? ad : 1.0) * fd[(y * 16 + x) * 2 + c];
+        }
+      /* ray radiance -> emission and previous-frame irradiance at the hit */
+      double Pq[3];
+      probe_position(V, q, Pq);
+      for (int32_t r = 0; r < N; r++, off++) {
+        const orc_ray_record* rec = &records[off];
+        if (rec->tri < 0) continue;
+        double e1[3], e2[3], ng[3];
+        sub3(tri_v(s, rec->tri, 1), tri_v(s, rec->tri, 0), e1);
+        sub3(tri_v(s, rec->tri, 2), tri_v(s, rec->tri, 0), e2);
+        cross3(e1, e2, ng);
+        normalize3(ng);
+        const double* w = omega + 3 * r;
+        if (dot3(w, ng) > 0.0) continue;
+        int32_t m = s->material[rec->tri];
+        for (int c = 0; c < 3; c++) g_emission[m * 3 + c] += gL[3 * r + c];
+        double X[3], wo[3] = {-w[0], -w[1], -w[2]};
+        for (int a = 0; a < 3; a++) X[a] = Pq[a] + rec->t * w[a];
+        double gq[3];
+        for (int c = 0; c < 3; c++) gq[c] = s->albedo[m * 3 + c] * gL[3 * r + c];
+        orc_query_backward(prev, nvol, X, ng, wo, gq, g_prev_irr, g_prev_dist);
+      }
+    }
+    free(omega);
+    free(gL);
+  }
 }

@@ -40,6 +40,7 @@ orc_scene* orc_scene_create(const float* vertices, int64_t n_vertices,
                             const uint32_t* tri_material, const uint32_t* tri_object,
                             const float* albedo, const float* emission, int32_t n_materials);
 void orc_scene_free(orc_scene* s);
+void orc_scene_set_emission(orc_scene* s, const double* emission); /* [M][3] */
 int64_t orc_scene_bvh_nodes(const orc_scene* s);
 
 typedef struct {
@@ -140,6 +141,20 @@ void orc_state_step(const orc_scene* s, orc_volume* vols, int32_t nvol);
    volume in order, per active probe in index order, per ray, one record ---- */
 int64_t orc_update_frame(const orc_scene* s, const orc_lights* L, orc_volume* vols, int32_t nvol,
                          const float R[9], orc_ray_record* records, int64_t capacity);
+
+/* ---- adjoint, ray hits and shadow decisions held fixed ----
+   g_irr[v] / g_dist[v]: per volume, [P][8][8][3] / [P][16][16][2] float64,
+   gradients accumulate (+=). */
+void orc_query_backward(const orc_volume* vols, int32_t nvol, const double X[3], const double n[3],
+                        const double wo[3], const double gout[3], double** g_irr, double** g_dist);
+/* Backward of one update frame.  prev: the frame's input atlases and the
+   states after the frame's state step (before promotion); records: the
+   frame's ray records (per volume in order, per active probe, per ray);
+   g_new_*: dLoss/d(output atlases); accumulates dLoss/d(input atlases) into
+   g_prev_* and dLoss/d(emission) into g_emission [M][3]. */
+void orc_update_backward(const orc_scene* s, const orc_volume* prev, int32_t nvol, const float R[9],
+                         const orc_ray_record* records, double** g_new_irr, double** g_new_dist,
+                         double** g_prev_irr, double** g_prev_dist, double* g_emission);
 
 /* ---- shading of a single ray from o along w (exposed for pins) ---- */
 void orc_shade_ray(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol,

@@ -1,0 +1,68 @@
+"""The differentiable-frame workload shared by the adjoint tests: the city
+with 64 emissive quads, a volume of probes, frame 1 converged, then one
+differentiable frame A0 -> A1 with ray hits fixed, queried at surface points;
+loss = mean squared difference from a target made with emitter radiances
+perturbed by a seeded +/-30 %."""
+import numpy as np
+
+from paper_2009_10796_amd import scenes as S
+
+
+def workload(full=False):
+    w = S.config4(n_points=65536 if full else 3000)
+    if not full:
+        # a 6x4x6-probe volume at 1 m inside the city, 64 rays: the oracle runs
+        # a frame in milliseconds, so finite differences over every emitter fit
+        w.volumes[0] = S.VolumeDesc(origin=(5.5, 0.5, 5.5), spacing=(1.0, 1.0, 1.0), counts=(6, 4, 6),
+                                    rays_per_probe=64)
+        pts = w.queries
+        inside = np.all((pts.pos >= [5.5, 0.0, 5.5]) & (pts.pos <= [10.5, 3.5, 10.5]), axis=1)
+        w.queries = S.Queries(pts.pos[inside][:1500], pts.nrm[inside][:1500], pts.view[inside][:1500])
+    return w
+
+
+class OracleFrame:
+    """Oracle forward of the differentiable frame and its adjoint."""
+
+    def __init__(self, w):
+        import oracle
+        self.o = oracle
+        self.w = w
+        self.sc = oracle.Scene(w.scene)
+        vols = [oracle.Volume(d) for d in w.volumes]
+        oracle.classify(self.sc, vols, w.classify_rotations)
+        oracle.update_frame(self.sc, w.lights, vols, w.frame_rotation(1), records=False)
+        self.A0 = vols
+        self.R = w.frame_rotation(2)
+        self.emission = w.scene.emission.astype(np.float64)
+        self.target = self.forward(S.target_emission(w).astype(np.float64), self.A0)[0]
+
+    def forward(self, emission, A0):
+        o = self.o
+        self.sc.set_emission(emission)
+        vols = o.copy_volumes(A0)
+        rec = o.update_frame(self.sc, self.w.lights, vols, self.R)
+        q = self.w.queries
+        E, _ = o.query(vols, q.pos, q.nrm, q.view)
+        return E, vols, rec
+
+    def loss(self, emission, A0):
+        E = self.forward(emission, A0)[0]
+        return float(np.mean((E - self.target) ** 2))
+
+    def gradients(self, emission, A0):
+        o = self.o
+        E, A1, rec = self.forward(emission, A0)
+        q = self.w.queries
+        gE = 2.0 * (E - self.target) / E.size
+        g1i = [np.zeros_like(v.irr) for v in A1]
+        g1d = [np.zeros_like(v.dist) for v in A1]
+        o.query_backward(A1, q.pos, q.nrm, q.view, gE, g1i, g1d)
+        prev = o.copy_volumes(A0)
+        o.state_step(self.sc, prev)        # the frame's states before promotion
+        g0i = [np.zeros_like(v.irr) for v in A0]
+        g0d = [np.zeros_like(v.dist) for v in A0]
+        ge = np.zeros_like(emission)
+        self.sc.set_emission(emission)
+        o.update_backward(self.sc, prev, self.R, rec, g1i, g1d, g0i, g0d, ge)
+        return ge, g0i, g0d
