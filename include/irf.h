@@ -226,6 +226,30 @@ irf_status irf_graph_capture(irf_ctx* ctx, void* stream, irf_graph** out);
 irf_status irf_graph_launch(irf_ctx* ctx, irf_graph* graph, const float* rotation, void* stream);
 void irf_graph_destroy(irf_graph* graph);
 
+/* ---- adjoint (differentiation of query -> blend -> hit shading with the
+   ray hits and shadow decisions of the forward frame held fixed) ----
+   Gradients are float32 device buffers with the atlas layouts
+   (irradiance [P][8][8][4], distance [P][16][16][2]) and accumulate (+=);
+   per-volume buffers are passed as a host array of n_volumes device
+   pointers.  Volumes must have float32 atlases. */
+
+/* While enabled, each irf_update_probes also saves the frame's input atlases
+   and its states after the state step (library memory), for
+   irf_update_backward. */
+irf_status irf_set_differentiable(irf_ctx* ctx, int32_t enable);
+/* Replaces the materials' emitted radiance from a device array [n_materials][3]. */
+irf_status irf_set_emission(irf_ctx* ctx, const float* emission, void* stream);
+/* dLoss/d(atlases) of irf_query_irradiance at the same points given
+   grad_out = dLoss/dE [n][3] (device); reads the current atlases. */
+irf_status irf_query_backward(irf_ctx* ctx, const float* pos, const float* nrm, const float* view, int64_t n,
+                              const float* grad_out, float* const* grad_irr, float* const* grad_dist, void* stream);
+/* Backward of the last update frame: from dLoss/d(output atlases) to
+   dLoss/d(input atlases) and dLoss/d(emission) [n_materials][3].  The blend
+   is differentiated with float32 weights whatever the forward blend mode. */
+irf_status irf_update_backward(irf_ctx* ctx, float* const* grad_new_irr, float* const* grad_new_dist,
+                               float* const* grad_prev_irr, float* const* grad_prev_dist, float* grad_emission,
+                               void* stream);
+
 /* Per-ray records of the last update for one volume, in active-probe order
    (ascending probe index) then ray order.  Synchronizes `stream`.  Writes at
    most `capacity` records to the device buffer `out` and the count to

@@ -89,8 +89,8 @@ def _declare(L):
     L.orc_update_frame.restype = i64
     L.orc_update_frame.argtypes = [vp, vp, vp, i32, vp, vp, i64]
     L.orc_shade_ray.argtypes = [vp, vp, vp, i32, dp, dp, C.c_double, vp]
-    L.orc_query_backward.argtypes = [vp, i32, dp, dp, dp, dp, vp, vp]
-    L.orc_update_backward.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, dp]
+    L.orc_query_backward.argtypes = [vp, i32, dp, dp, dp, dp, vp]
+    L.orc_update_backward.argtypes = [vp, vp, i32, vp, vp, vp, vp, dp]
 
 
 # ---------------------------------------------------------------- wrappers
@@ -295,27 +295,54 @@ def _ptr_array(arrs):
     return a
 
 
-def query_backward(vols: List[Volume], pos, nrm, view, gout, g_irr, g_dist):
-    """Accumulates dLoss/d(texels) of the query (float64 gradient arrays shaped
-    like each volume's irr / dist atlases)."""
+class _Grads(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("g_irr", "g_dist", "a_irr", "a_dist", "s_irr", "s_dist")]
+
+
+def _grads(g_irr, g_dist, a_irr=None, a_dist=None, s_irr=None, s_dist=None):
+    """orc_grads over per-volume float64 arrays (None: not wanted); the
+    pointer arrays are kept alive on the returned structure."""
+    G = _Grads()
+    keep = []
+    for name, arrs in (("g_irr", g_irr), ("g_dist", g_dist), ("a_irr", a_irr), ("a_dist", a_dist),
+                       ("s_irr", s_irr), ("s_dist", s_dist)):
+        if arrs is None:
+            continue
+        pa = _ptr_array(arrs)
+        keep.append(pa)
+        setattr(G, name, C.cast(pa, C.c_void_p))
+    G._keep = keep
+    return G
+
+
+def query_backward(vols: List[Volume], pos, nrm, view, gout, g_irr, g_dist, a_irr=None, a_dist=None, s_irr=None,
+                   s_dist=None):
+    """Accumulates dLoss/d(texels) of the query into float64 arrays shaped
+    like each volume's irr / dist atlases; optionally the per-texel sum of
+    term magnitudes (a_*) and float32 sensitivity (s_*)."""
     pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
     nrm = np.ascontiguousarray(nrm, dtype=np.float64).reshape(-1, 3)
     view = np.ascontiguousarray(view, dtype=np.float64).reshape(-1, 3)
     gout = np.ascontiguousarray(gout, dtype=np.float64).reshape(-1, 3)
     arr = _vol_array(vols)
-    gi, gd = _ptr_array(g_irr), _ptr_array(g_dist)
+    G = _grads(g_irr, g_dist, a_irr, a_dist, s_irr, s_dist)
     for i in range(pos.shape[0]):
-        lib().orc_query_backward(arr, len(vols), _p(pos[i]), _p(nrm[i]), _p(view[i]), _p(gout[i]), gi, gd)
+        lib().orc_query_backward(arr, len(vols), _p(pos[i]), _p(nrm[i]), _p(view[i]), _p(gout[i]), C.byref(G))
 
 
 def update_backward(scene: Scene, prev: List[Volume], R, records, g_new_irr, g_new_dist, g_prev_irr, g_prev_dist,
-                    g_emission):
+                    g_emission, a_new_irr=None, a_new_dist=None, a_prev_irr=None, a_prev_dist=None, s_prev_irr=None,
+                    s_prev_dist=None):
+    """Backward of one update frame (see orc_update_backward): accumulates
+    dLoss/d(input atlases) and dLoss/d(emission); a_new_* are magnitude
+    bounds of the upstream gradient (default |g_new|)."""
     R = np.ascontiguousarray(R, dtype=np.float32).reshape(9)
     rec = np.ascontiguousarray(records)
     assert rec.dtype == RECORD_DTYPE
     assert g_emission.dtype == np.float64 and g_emission.flags.c_contiguous
-    lib().orc_update_backward(scene.handle, _vol_array(prev), len(prev), _p(R), _p(rec), _ptr_array(g_new_irr),
-                              _ptr_array(g_new_dist), _ptr_array(g_prev_irr), _ptr_array(g_prev_dist),
+    Gn = _grads(g_new_irr, g_new_dist, a_new_irr, a_new_dist)
+    Gp = _grads(g_prev_irr, g_prev_dist, a_prev_irr, a_prev_dist, s_prev_irr, s_prev_dist)
+    lib().orc_update_backward(scene.handle, _vol_array(prev), len(prev), _p(R), _p(rec), C.byref(Gn), C.byref(Gp),
                               _p(g_emission))
 
 

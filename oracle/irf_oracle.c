@@ -1082,8 +1082,69 @@ static void scatter_tile(double* gtile, int32_t m, int32_t nch, const double v[3
     for (int c = 0; c < nch; c++) gtile[idx[t] * nch + c] += bw[t] * g[c];
 }
 
-static void volume_query_backward(const orc_volume* V, const double X[3], const double n[3], const double wo[3],
-                                  const double g[3], double* g_irr, double* g_dist) {
+/* The terms of a query's gradient, one per (texel, tap), before they are
+   added into the gradient atlases.  Keeping them apart lets the reverse pass
+   also report, per texel, the sum of the magnitudes of its terms and how far
+   float32 evaluation of the same terms may move them (a finite difference
+   over the float32 error of each input of the Chebyshev factor, of the
+   irradiance values and of the hit point).  Those two are test
+   infrastructure for judging a float32 implementation; the gradient does not
+   depend on them. */
+typedef struct {
+  int32_t vol, dist;   /* volume; 0: irradiance texel (3 channels), 1: distance texel (2) */
+  int64_t elem;        /* offset of the texel's first channel in its atlas */
+  double g[3], a[3];   /* gradient terms; magnitude bounds of the same terms */
+} term;
+
+typedef struct {
+  int32_t n, cap;
+  term* t;
+} term_list;
+
+static term* term_push(term_list* L) {
+  if (L->n == L->cap) {
+    L->cap = L->cap ? 2 * L->cap : 256;
+    L->t = (term*)realloc(L->t, sizeof(term) * (size_t)L->cap);
+  }
+  term* t = &L->t[L->n++];
+  memset(t, 0, sizeof(*t));
+  return t;
+}
+
+/* the four bilinear taps of direction v in a tile with nch channels */
+static void push_taps(term_list* L, int32_t vol, int32_t dist, int64_t tile_elem, int32_t m, int32_t nch,
+                      const double v[3], const double* g, const double* a) {
+  int32_t x0, y0;
+  double fx, fy;
+  footprint(m, v, &x0, &y0, &fx, &fy);
+  const double bw[4] = {(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy};
+  const int32_t idx[4] = {y0 * m + x0, y0 * m + x0 + 1, (y0 + 1) * m + x0, (y0 + 1) * m + x0 + 1};
+  for (int k = 0; k < 4; k++) {
+    term* t = term_push(L);
+    t->vol = vol;
+    t->dist = dist;
+    t->elem = tile_elem + (int64_t)idx[k] * nch;
+    for (int c = 0; c < nch; c++) {
+      t->g[c] = bw[k] * g[c];
+      t->a[c] = bw[k] * a[c];
+    }
+  }
+}
+
+/* Perturbations of the float32 inputs, in multiples of their error bound:
+   [0] mu, [1] mu2 (with the rounding of mu2 - mu^2), [2] r, [3] the sampled
+   irradiance (alternating in sign over the cage, which moves e_i - E). */
+typedef struct {
+  double mu, mu2, r, e;
+} perturb;
+
+/* Reverse pass of one volume's cage query (forward: volume_query): the
+   normalised weighted average of Eq. with the backface factor, the
+   Chebyshev factor of the visibility section and the self-shadow bias of
+   Eq. 1; g is dLoss/dE for this volume's share, ga its magnitude bound. */
+static void volume_query_terms(const orc_volume* V, int32_t vol, const double X[3], const double n[3],
+                               const double wo[3], const double g[3], const double ga[3], const perturb* pt,
+                               term_list* L) {
   double u[3], f[3], Xb[3];
   int64_t gi[3];
   double D = fmin((double)V->spacing[0], fmin((double)V->spacing[1], (double)V->spacing[2]));
@@ -1118,6 +1179,19 @@ static void volume_query_backward(const orc_volume* V, const double X[3], const 
     if (r > 0.0) {
       for (int a = 0; a < 3; a++) zd[used][a] = z[a] / r;
       orc_sample_tile(V->dist + q * 512, 16, 2, zd[used], mmv[used]);
+      if (pt) {
+        /* float32 error bounds of the sampled moments and of r, as in the
+           forward query's sensitivity */
+        double lo[2], hi[2], kk[2] = {0.0, 0.0};
+        footprint_range(V->dist + q * 512, 16, 2, zd[used], lo, hi);
+        if (V->dist_kappa) orc_sample_tile(V->dist_kappa + q * 512, 16, 2, zd[used], kk);
+        double m0 = mmv[used][0], m1 = mmv[used][1];
+        double dmu = (4.0 * fabs(m0) + 32.0 * (hi[0] - lo[0]) + kk[0]) * U32;
+        double dmu2 = (4.0 * fabs(m1) + 32.0 * (hi[1] - lo[1]) + kk[1] + 4.0 * (fabs(m1) + m0 * m0)) * U32;
+        mmv[used][0] = m0 + pt->mu * dmu;
+        mmv[used][1] = m1 + pt->mu2 * dmu2;
+        r += pt->r * 4.0 * r * U32;
+      }
       if (r > mmv[used][0]) {
         double var = fmax(mmv[used][1] - mmv[used][0] * mmv[used][0], 0.0);
         double dl = r - mmv[used][0];
@@ -1130,6 +1204,12 @@ static void volume_query_backward(const orc_volume* V, const double X[3], const 
     wtb[used] = wt * wb;
     w[used] = wt * wb * wv;
     orc_sample_tile(V->irr + q * 192, 8, 3, n, e[used]);
+    if (pt && pt->e != 0.0) {
+      double ek[3] = {0.0, 0.0, 0.0};
+      if (V->irr_kappa) orc_sample_tile(V->irr_kappa + q * 192, 8, 3, n, ek);
+      double sg = (used & 1) ? -pt->e : pt->e;
+      for (int c = 0; c < 3; c++) e[used][c] += sg * (16.0 * fabs(e[used][c]) + ek[c]) * U32;
+    }
     W += w[used];
     used++;
   }
@@ -1138,11 +1218,21 @@ static void volume_query_backward(const orc_volume* V, const double X[3], const 
   for (int i = 0; i < used; i++)
     for (int c = 0; c < 3; c++) E[c] += w[i] * e[i][c] / W;
   for (int i = 0; i < used; i++) {
-    double ge[3] = {g[0] * w[i] / W, g[1] * w[i] / W, g[2] * w[i] / W};
-    scatter_tile(g_irr + qs[i] * 192, 8, 3, n, ge);
+    /* dE/de_i = w_i / W, through the bilinear taps of the irradiance tile */
+    double ge[3], gea[3];
+    for (int c = 0; c < 3; c++) {
+      ge[c] = g[c] * w[i] / W;
+      gea[c] = ga[c] * w[i] / W;
+    }
+    push_taps(L, vol, 0, qs[i] * 192, 8, 3, n, ge, gea);
     if (!cheb[i]) continue;
-    double gw = 0.0;
-    for (int c = 0; c < 3; c++) gw += g[c] * (e[i][c] - E[c]) / W;
+    /* dE/dw_i = (e_i - E) / W; w_i = wt wb ch^k with ch = var / (var + dl^2),
+       var = max(mu2 - mu^2, 0), dl = r - mu */
+    double gw = 0.0, gwa = 0.0;
+    for (int c = 0; c < 3; c++) {
+      gw += g[c] * (e[i][c] - E[c]) / W;
+      gwa += ga[c] * (fabs(e[i][c]) + fabs(E[c])) / W;
+    }
     double mu = mmv[i][0], mu2 = mmv[i][1];
     double raw = mu2 - mu * mu;
     double var = fmax(raw, 0.0);
@@ -1154,14 +1244,18 @@ static void volume_query_backward(const orc_volume* V, const double X[3], const 
     double dvar_dmu = raw > 0.0 ? -2.0 * mu : 0.0, dvar_dmu2 = raw > 0.0 ? 1.0 : 0.0;
     double k = (double)V->cheb_power;
     double dwv_dch = k * pow(ch, k - 1.0);
-    double gwv = gw * wtb[i] * dwv_dch;
-    double gd[2] = {gwv * (dch_dvar * dvar_dmu - dch_ddl), gwv * dch_dvar * dvar_dmu2};
-    scatter_tile(g_dist + qs[i] * 512, 16, 2, zd[i], gd);
+    double cmu = wtb[i] * dwv_dch * (dch_dvar * dvar_dmu - dch_ddl);
+    double cmu2 = wtb[i] * dwv_dch * dch_dvar * dvar_dmu2;
+    double gd[2] = {gw * cmu, gw * cmu2}, gda[2] = {gwa * fabs(cmu), gwa * fabs(cmu2)};
+    push_taps(L, vol, 1, qs[i] * 512, 16, 2, zd[i], gd, gda);
   }
 }
 
-void orc_query_backward(const orc_volume* vols, int32_t nvol, const double X[3], const double n[3],
-                        const double wo[3], const double gout[3], double** g_irr, double** g_dist) {
+/* Section "Multiple Probe Volumes": the same share of dE as the forward
+   blend of volumes gives each volume */
+static void query_terms(const orc_volume* vols, int32_t nvol, const double X[3], const double n[3],
+                        const double wo[3], const double gout[3], const double gabs[3], const perturb* pt,
+                        term_list* L) {
   double Wt = 0.0;
   for (int32_t v = 0; v < nvol; v++) {
     const orc_volume* V = &vols[v];
@@ -1174,67 +1268,186 @@ void orc_query_backward(const orc_volume* vols, int32_t nvol, const double X[3],
     double wuse = (v == nvol - 1) ? 1.0 - Wt : fmin(wv, 1.0 - Wt);
     if (wuse > 0.0) {
       double g[3] = {wuse * gout[0], wuse * gout[1], wuse * gout[2]};
-      volume_query_backward(V, X, n, wo, g, g_irr[v], g_dist[v]);
+      double ga[3] = {wuse * gabs[0], wuse * gabs[1], wuse * gabs[2]};
+      volume_query_terms(V, v, X, n, wo, g, ga, pt, L);
       Wt += wuse;
     }
   }
 }
 
+static double* texel_ptr(double** arrays, const term* t) { return arrays[t->vol] + t->elem; }
+
+static void add_terms(const term_list* L, double** gi, double** gd, double** ai, double** ad) {
+  for (int32_t j = 0; j < L->n; j++) {
+    const term* t = &L->t[j];
+    int nch = t->dist ? 2 : 3;
+    double* g = texel_ptr(t->dist ? gd : gi, t);
+    for (int c = 0; c < nch; c++) g[c] += t->g[c];
+    if (ai && ad) {
+      double* a = texel_ptr(t->dist ? ad : ai, t);
+      for (int c = 0; c < nch; c++) a[c] += t->a[c];
+    }
+  }
+}
+
+static int term_cmp(const void* pa, const void* pb) {
+  const term* a = (const term*)pa;
+  const term* b = (const term*)pb;
+  if (a->vol != b->vol) return a->vol < b->vol ? -1 : 1;
+  if (a->dist != b->dist) return a->dist < b->dist ? -1 : 1;
+  if (a->elem != b->elem) return a->elem < b->elem ? -1 : 1;
+  return 0;
+}
+
+/* per texel: sums the terms of L (sorted, duplicates merged in place) */
+static void merge_terms(term_list* L) {
+  if (L->n == 0) return;
+  qsort(L->t, (size_t)L->n, sizeof(term), term_cmp);
+  int32_t o = 0;
+  for (int32_t j = 1; j < L->n; j++) {
+    if (term_cmp(&L->t[o], &L->t[j]) == 0) {
+      for (int c = 0; c < 3; c++) {
+        L->t[o].g[c] += L->t[j].g[c];
+        L->t[o].a[c] += L->t[j].a[c];
+      }
+    } else {
+      L->t[++o] = L->t[j];
+    }
+  }
+  L->n = o + 1;
+}
+
+/* adds |per-texel terms of A - per-texel terms of B| (both merged) */
+static void add_abs_diff(const term_list* A, const term_list* B, double** si, double** sd) {
+  int32_t i = 0, j = 0;
+  while (i < A->n || j < B->n) {
+    int cmp = i == A->n ? 1 : j == B->n ? -1 : term_cmp(&A->t[i], &B->t[j]);
+    const term* t = cmp <= 0 ? &A->t[i] : &B->t[j];
+    double* s = texel_ptr(t->dist ? sd : si, t);
+    for (int c = 0; c < (t->dist ? 2 : 3); c++) {
+      double va = cmp <= 0 ? A->t[i].g[c] : 0.0, vb = cmp >= 0 ? B->t[j].g[c] : 0.0;
+      s[c] += fabs(va - vb);
+    }
+    if (cmp <= 0) i++;
+    if (cmp >= 0) j++;
+  }
+}
+
+/* gradient, magnitudes and float32 sensitivities of one query at X; a hit
+   point X2 (or NULL) is X moved by its own float32 error */
+static void query_backward_full(const orc_volume* vols, int32_t nvol, const double X[3], const double X2[3],
+                                const double n[3], const double wo[3], const double g[3], const double ga[3],
+                                const orc_grads* G) {
+  term_list L0 = {0, 0, NULL};
+  query_terms(vols, nvol, X, n, wo, g, ga, NULL, &L0);
+  add_terms(&L0, G->g_irr, G->g_dist, G->a_irr, G->a_dist);
+  if (G->s_irr && G->s_dist) {
+    merge_terms(&L0);
+    static const perturb P[8] = {{1, 0, 0, 0}, {-1, 0, 0, 0}, {0, 1, 0, 0}, {0, -1, 0, 0},
+                                 {0, 0, 1, 0}, {0, 0, -1, 0}, {0, 0, 0, 1}, {0, 0, 0, -1}};
+    term_list Lp = {0, 0, NULL};
+    for (int k = 0; k < 8; k++) {
+      Lp.n = 0;
+      query_terms(vols, nvol, X, n, wo, g, ga, &P[k], &Lp);
+      merge_terms(&Lp);
+      add_abs_diff(&L0, &Lp, G->s_irr, G->s_dist);
+    }
+    if (X2) {
+      Lp.n = 0;
+      query_terms(vols, nvol, X2, n, wo, g, ga, NULL, &Lp);
+      merge_terms(&Lp);
+      add_abs_diff(&L0, &Lp, G->s_irr, G->s_dist);
+    }
+    free(Lp.t);
+  }
+  free(L0.t);
+}
+
+void orc_query_backward(const orc_volume* vols, int32_t nvol, const double X[3], const double n[3],
+                        const double wo[3], const double gout[3], const orc_grads* G) {
+  double ga[3] = {fabs(gout[0]), fabs(gout[1]), fabs(gout[2])};
+  query_backward_full(vols, nvol, X, NULL, n, wo, gout, ga, G);
+}
+
 void orc_update_backward(const orc_scene* s, const orc_volume* prev, int32_t nvol, const float R[9],
-                         const orc_ray_record* records, double** g_new_irr, double** g_new_dist,
-                         double** g_prev_irr, double** g_prev_dist, double* g_emission) {
+                         const orc_ray_record* records, const orc_grads* Gnew, const orc_grads* Gprev,
+                         double* g_emission) {
   int64_t off = 0;
+  const int mag = Gprev->a_irr && Gprev->a_dist;
   for (int32_t v = 0; v < nvol; v++) {
     const orc_volume* V = &prev[v];
     int64_t P = vol_probes(V);
     int32_t N = V->rays;
     double* omega = (double*)malloc(sizeof(double) * 3 * (size_t)N);
     double* gL = (double*)malloc(sizeof(double) * 3 * (size_t)N);
+    double* gLa = (double*)malloc(sizeof(double) * 3 * (size_t)N);
     for (int32_t r = 0; r < N; r++) orc_sf_direction(r, N, R, omega + 3 * r);
     for (int64_t q = 0; q < P; q++) {
-      const double* gi = g_new_irr[v] + q * 192;
-      const double* gd = g_new_dist[v] + q * 512;
-      double* pi = g_prev_irr[v] + q * 192;
-      double* pd = g_prev_dist[v] + q * 512;
+      const double* gi = Gnew->g_irr[v] + q * 192;
+      const double* gd = Gnew->g_dist[v] + q * 512;
+      /* magnitude bounds of the upstream gradient: given, else |g| */
+      double ain[192], adn[512];
+      for (int i = 0; i < 192; i++) ain[i] = Gnew->a_irr ? Gnew->a_irr[v][q * 192 + i] : fabs(gi[i]);
+      for (int i = 0; i < 512; i++) adn[i] = Gnew->a_dist ? Gnew->a_dist[v][q * 512 + i] : fabs(gd[i]);
+      double* pi = Gprev->g_irr[v] + q * 192;
+      double* pd = Gprev->g_dist[v] + q * 512;
+      double* pia = mag ? Gprev->a_irr[v] + q * 192 : NULL;
+      double* pda = mag ? Gprev->a_dist[v] + q * 512 : NULL;
       if (!active_state(V->states[q])) {
         /* not updated this frame: output texels are the input texels */
         for (int i = 0; i < 192; i++) pi[i] += gi[i];
         for (int i = 0; i < 512; i++) pd[i] += gd[i];
+        if (mag) {
+          for (int i = 0; i < 192; i++) pia[i] += ain[i];
+          for (int i = 0; i < 512; i++) pda[i] += adn[i];
+        }
         continue;
       }
       int fresh = V->states[q] == ORC_NEWLY_AWAKE || V->states[q] == ORC_NEWLY_VIGILANT;
       double ai = fresh ? 0.0 : (double)V->alpha_irr, ad = fresh ? 0.0 : (double)V->alpha_dist;
       /* border texels repeat interior texels: fold their gradients */
-      double fi[192], fd[512];
+      double fi[192], fd[512], fia[192], fda[512];
       memset(fi, 0, sizeof(fi));
       memset(fd, 0, sizeof(fd));
+      memset(fia, 0, sizeof(fia));
+      memset(fda, 0, sizeof(fda));
       for (int32_t y = 0; y < 8; y++)
         for (int32_t x = 0; x < 8; x++) {
           int32_t sx, sy;
           orc_border_source(8, x, y, &sx, &sy);
-          for (int c = 0; c < 3; c++) fi[(sy * 8 + sx) * 3 + c] += gi[(y * 8 + x) * 3 + c];
+          for (int c = 0; c < 3; c++) {
+            fi[(sy * 8 + sx) * 3 + c] += gi[(y * 8 + x) * 3 + c];
+            fia[(sy * 8 + sx) * 3 + c] += ain[(y * 8 + x) * 3 + c];
+          }
         }
       for (int32_t y = 0; y < 16; y++)
         for (int32_t x = 0; x < 16; x++) {
           int32_t sx, sy;
           orc_border_source(16, x, y, &sx, &sy);
-          for (int c = 0; c < 2; c++) fd[(sy * 16 + sx) * 2 + c] += gd[(y * 16 + x) * 2 + c];
+          for (int c = 0; c < 2; c++) {
+            fd[(sy * 16 + sx) * 2 + c] += gd[(y * 16 + x) * 2 + c];
+            fda[(sy * 16 + sx) * 2 + c] += adn[(y * 16 + x) * 2 + c];
+          }
         }
-      for (int32_t r = 0; r < N; r++) gL[3 * r] = gL[3 * r + 1] = gL[3 * r + 2] = 0.0;
+      for (int32_t r = 0; r < 3 * N; r++) gL[r] = gLa[r] = 0.0;
       for (int32_t y = 1; y <= 6; y++)
         for (int32_t x = 1; x <= 6; x++) {
           double nt[3], W = 0.0;
           orc_texel_direction(8, x, y, nt);
           for (int32_t r = 0; r < N; r++) W += fmax(0.0, dot3(nt, omega + 3 * r));
-          const double* g = &fi[(y * 8 + x) * 3];
-          if (!(W > 0.0)) {
-            for (int c = 0; c < 3; c++) pi[(y * 8 + x) * 3 + c] += g[c];
-            continue;
+          const int e0 = (y * 8 + x) * 3;
+          double keep = W > 0.0 ? ai : 1.0;
+          for (int c = 0; c < 3; c++) {
+            pi[e0 + c] += keep * fi[e0 + c];
+            if (mag) pia[e0 + c] += keep * fia[e0 + c];
           }
-          for (int c = 0; c < 3; c++) pi[(y * 8 + x) * 3 + c] += ai * g[c];
+          if (!(W > 0.0)) continue;
           for (int32_t r = 0; r < N; r++) {
             double wr = fmax(0.0, dot3(nt, omega + 3 * r)) / W;
-            for (int c = 0; c < 3; c++) gL[3 * r + c] += (1.0 - ai) * wr * g[c];
+            for (int c = 0; c < 3; c++) {
+              gL[3 * r + c] += (1.0 - ai) * wr * fi[e0 + c];
+              gLa[3 * r + c] += (1.0 - ai) * wr * fia[e0 + c];
+            }
           }
         }
       for (int32_t y = 1; y <= 14; y++)
@@ -1242,7 +1455,12 @@ void orc_update_backward(const orc_scene* s, const orc_volume* prev, int32_t nvo
           double nt[3], W = 0.0;
           orc_texel_direction(16, x, y, nt);
           for (int32_t r = 0; r < N; r++) W += pow(fmax(0.0, dot3(nt, omega + 3 * r)), (double)V->cos_power);
-          for (int c = 0; c < 2; c++) pd[(y * 16 + x) * 2 + c] += (W > 0.0 ? ad : 1.0) * fd[(y * 16 + x) * 2 + c];
+          const int e0 = (y * 16 + x) * 2;
+          double keep = W > 0.0 ? ad : 1.0;
+          for (int c = 0; c < 2; c++) {
+            pd[e0 + c] += keep * fd[e0 + c];
+            if (mag) pda[e0 + c] += keep * fda[e0 + c];
+          }
         }
       /* ray radiance -> emission and previous-frame irradiance at the hit */
       double Pq[3];
@@ -1259,14 +1477,24 @@ void orc_update_backward(const orc_scene* s, const orc_volume* prev, int32_t nvo
         if (dot3(w, ng) > 0.0) continue;
         int32_t m = s->material[rec->tri];
         for (int c = 0; c < 3; c++) g_emission[m * 3 + c] += gL[3 * r + c];
-        double X[3], wo[3] = {-w[0], -w[1], -w[2]};
-        for (int a = 0; a < 3; a++) X[a] = Pq[a] + rec->t * w[a];
-        double gq[3];
-        for (int c = 0; c < 3; c++) gq[c] = s->albedo[m * 3 + c] * gL[3 * r + c];
-        orc_query_backward(prev, nvol, X, ng, wo, gq, g_prev_irr, g_prev_dist);
+        double X[3], X2[3], wo[3] = {-w[0], -w[1], -w[2]};
+        /* the hit point moved by its float32 error along the ray, as for
+           the forward shading's sensitivity */
+        double ep = fmin(1e-2, U32 * (8.0 / fmax(rec->cosi, 1e-6) + 16.0));
+        for (int a = 0; a < 3; a++) {
+          X[a] = Pq[a] + rec->t * w[a];
+          X2[a] = Pq[a] + rec->t * (1.0 + ep) * w[a];
+        }
+        double gq[3], gqa[3];
+        for (int c = 0; c < 3; c++) {
+          gq[c] = s->albedo[m * 3 + c] * gL[3 * r + c];
+          gqa[c] = s->albedo[m * 3 + c] * gLa[3 * r + c];
+        }
+        query_backward_full(prev, nvol, X, X2, ng, wo, gq, gqa, Gprev);
       }
     }
     free(omega);
     free(gL);
+    free(gLa);
   }
 }

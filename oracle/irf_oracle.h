@@ -143,18 +143,34 @@ int64_t orc_update_frame(const orc_scene* s, const orc_lights* L, orc_volume* vo
                          const float R[9], orc_ray_record* records, int64_t capacity);
 
 /* ---- adjoint, ray hits and shadow decisions held fixed ----
-   g_irr[v] / g_dist[v]: per volume, [P][8][8][3] / [P][16][16][2] float64,
-   gradients accumulate (+=). */
+   Per volume v: g_irr[v] / g_dist[v] are [P][8][8][3] / [P][16][16][2]
+   float64 arrays; everything accumulates (+=).  Optional (NULL to skip):
+   a_*: per texel, the sum of the magnitudes of the terms that make up its
+   gradient (with the upstream gradient replaced by its magnitude bound);
+   s_*: per texel, how far the terms move when the float32 inputs of the
+   query (sampled moments, r, irradiance, hit point) move by their float32
+   error bounds.  a_ and s_ are test infrastructure for judging a float32
+   implementation; they do not change the gradient. */
+typedef struct {
+  double** g_irr;
+  double** g_dist;
+  double** a_irr;
+  double** a_dist;
+  double** s_irr;
+  double** s_dist;
+} orc_grads;
+
 void orc_query_backward(const orc_volume* vols, int32_t nvol, const double X[3], const double n[3],
-                        const double wo[3], const double gout[3], double** g_irr, double** g_dist);
+                        const double wo[3], const double gout[3], const orc_grads* G);
 /* Backward of one update frame.  prev: the frame's input atlases and the
    states after the frame's state step (before promotion); records: the
    frame's ray records (per volume in order, per active probe, per ray);
-   g_new_*: dLoss/d(output atlases); accumulates dLoss/d(input atlases) into
-   g_prev_* and dLoss/d(emission) into g_emission [M][3]. */
+   Gnew: dLoss/d(output atlases) in g_*, with magnitude bounds in a_* (NULL:
+   |g|); accumulates dLoss/d(input atlases) into Gprev (a_*, s_* optional)
+   and dLoss/d(emission) into g_emission [M][3]. */
 void orc_update_backward(const orc_scene* s, const orc_volume* prev, int32_t nvol, const float R[9],
-                         const orc_ray_record* records, double** g_new_irr, double** g_new_dist,
-                         double** g_prev_irr, double** g_prev_dist, double* g_emission);
+                         const orc_ray_record* records, const orc_grads* Gnew, const orc_grads* Gprev,
+                         double* g_emission);
 
 /* ---- shading of a single ray from o along w (exposed for pins) ---- */
 void orc_shade_ray(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol,

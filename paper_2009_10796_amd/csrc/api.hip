@@ -96,7 +96,13 @@ struct irf_ctx {
   DevBuf<int32_t> class_back;
   DevBuf<uint32_t> class_tf;
   bool frame_done = false;
+  bool diff_frame = false;   // the last frame saved its inputs for the adjoint
   Tuning tune = {0, 0, 0, 0};
+  // adjoint: the frame's input atlases and states, saved by each update
+  bool diff = false;
+  DevBuf<char> saved;
+  int64_t saved_irr[IRF_MAX_VOLUMES], saved_dist[IRF_MAX_VOLUMES], saved_states[IRF_MAX_VOLUMES];
+  DevBuf<float4> grad_rays;
   // kernel timing
   bool prof = false;
   struct ProfRec {
@@ -178,6 +184,20 @@ irf_status ensure_scratch(irf_ctx* c) {
   if ((s = c->wave_tasks.reserve((size_t)((R + 63) / 64))) != IRF_OK) return s;
   if ((s = c->wave_offset.reserve((size_t)((R + 63) / 64))) != IRF_OK) return s;
   if ((s = c->stats.reserve(8)) != IRF_OK) return s;
+  if (c->diff) {
+    int64_t off = 0;
+    for (int v = 0; v < c->n_vol; v++) {
+      int64_t P = c->vol[v].n_probes, es = c->vol[v].atlas_f16 ? 2 : 4;
+      c->saved_irr[v] = off;
+      off += (P * kIrrTexels * 4 * es + 255) / 256 * 256;
+      c->saved_dist[v] = off;
+      off += (P * kDistTexels * 2 * es + 255) / 256 * 256;
+      c->saved_states[v] = off;
+      off += (P + 255) / 256 * 256;
+    }
+    if ((s = c->saved.reserve((size_t)off)) != IRF_OK) return s;
+    if ((s = c->grad_rays.reserve((size_t)(R > 0 ? R : 1))) != IRF_OK) return s;
+  }
   int64_t wbytes = 0;
   for (int v = 0; v < c->n_vol; v++) wbytes += 256ll * c->vol[v].rays * 4;
   if ((s = c->weights.reserve((size_t)(wbytes > 0 ? wbytes : 16))) != IRF_OK) return s;
@@ -199,6 +219,7 @@ FrameScratch scratch_view(const irf_ctx* c) {
   f.shadow_tasks = c->shadow_tasks.p;
   f.wave_tasks = c->wave_tasks.p;
   f.wave_offset = c->wave_offset.p;
+  f.grad_rays = c->grad_rays.p;
   f.weights = c->weights.p;
   f.inv_row_sum = c->inv_row_sum.p;
   f.rays_lp = nullptr;
@@ -261,6 +282,15 @@ void enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st) {
   fp.L = c->lights;
   launch_set_params(fp, fs, st);
   { ProfScope p(c, "state_compact", st); launch_state_compact(vs, boxes_view(c), fs, st); }
+  if (c->diff) {
+    // the frame's inputs for the adjoint: atlases and the stepped states
+    for (int v = 0; v < c->n_vol; v++) {
+      int64_t P = c->vol[v].n_probes, es = c->vol[v].atlas_f16 ? 2 : 4;
+      launch_copy(c->saved.p + c->saved_irr[v], c->vol[v].irr, P * kIrrTexels * 4 * es, st);
+      launch_copy(c->saved.p + c->saved_dist[v], c->vol[v].dist, P * kDistTexels * 2 * es, st);
+      launch_copy(c->saved.p + c->saved_states[v], c->vol[v].states, P, st);
+    }
+  }
   { ProfScope p(c, "directions", st); launch_directions(vs, fs, st); }
   bool any_mma = false, any_valu = false;
   for (int v = 0; v < c->n_vol; v++) (c->vol[v].blend == IRF_BLEND_F32_VALU ? any_valu : any_mma) = true;
@@ -298,6 +328,9 @@ uint64_t frame_signature(const irf_ctx* c) {
   mix(&fs, sizeof(fs));
   mix(&sc, sizeof(sc));
   mix(&c->tune, sizeof(c->tune));
+  // a differentiable frame also writes the saved inputs
+  const void* sv = c->diff ? (const void*)c->saved.p : nullptr;
+  mix(&sv, sizeof(sv));
   int nl = c->lights.n_dir + c->lights.n_point;
   mix(&nl, sizeof(nl));
   return h;
@@ -371,6 +404,8 @@ void irf_destroy(irf_ctx* c) {
   c->wave_tasks.release();
   c->wave_offset.release();
   c->stats.release();
+  c->saved.release();
+  c->grad_rays.release();
   c->weights.release();
   c->inv_row_sum.release();
   c->class_back.release();
@@ -426,6 +461,7 @@ irf_status irf_set_scene(irf_ctx* c, const irf_scene_desc* d) {
   build_bvh(d->vertices, d->n_vertices, d->indices, d->n_triangles, d->tri_material, d->tri_object, nodes, tris, st);
   if (st[4] != 1.0) return fail(IRF_E_INVALID, "BVH validation failed");
   if (st[2] > kMaxDepth) return fail(IRF_E_UNSUPPORTED, "BVH depth %g exceeds %d", st[2], kMaxDepth);
+  c->frame_done = c->diff_frame = false;   // the last frame's records refer to the old scene
   // dynamic object boxes
   int32_t nobj = 0;
   if (d->tri_object)
@@ -548,6 +584,7 @@ irf_status irf_create_volume(irf_ctx* c, const irf_volume_desc* d, int32_t* volu
   int64_t P = (int64_t)d->counts[0] * d->counts[1] * d->counts[2];
   if (total_probes(c) + P > (1 << 24)) return fail(IRF_E_INVALID, "too many probes in total");
   int v = c->n_vol;
+  c->frame_done = c->diff_frame = false;   // the last frame did not cover this volume
   c->desc[v] = *d;
   VolumeGPU& V = c->vol[v];
   memset(&V, 0, sizeof(V));
@@ -640,6 +677,7 @@ irf_status irf_update_probes(irf_ctx* c, const float* rotation, void* stream) {
   if ((s = ensure_scratch(c)) != IRF_OK) return s;
   enqueue_frame(c, rotation, (hipStream_t)stream);
   c->frame_done = true;
+  c->diff_frame = c->diff;
   return launched();
 }
 
@@ -811,6 +849,7 @@ irf_status irf_graph_launch(irf_ctx* c, irf_graph* g, const float* rotation, voi
   HIP_TRY(hipGraphExecKernelNodeSetParams(g->exec, g->params_node, &kp));
   HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
   c->frame_done = true;
+  c->diff_frame = c->diff;   // the signature pins the mode to the capture's
   return IRF_OK;
 }
 
@@ -819,6 +858,68 @@ void irf_graph_destroy(irf_graph* g) {
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
+}
+
+irf_status irf_set_differentiable(irf_ctx* c, int32_t enable) {
+  if (!c) return fail(IRF_E_INVALID, "ctx is NULL");
+  c->diff = enable != 0;
+  c->diff_frame = false;   // a backward needs a frame run in this mode
+  return IRF_OK;
+}
+
+irf_status irf_set_emission(irf_ctx* c, const float* emission, void* stream) {
+  if (!c || !emission) return fail(IRF_E_INVALID, "NULL argument");
+  if (!c->has_scene) return fail(IRF_E_STATE, "no scene");
+  irf_status s = set_device(c);
+  if (s != IRF_OK) return s;
+  launch_set_emission(emission, c->emission.p, c->n_materials, (hipStream_t)stream);
+  return launched();
+}
+
+static irf_status grad_set(const irf_ctx* c, float* const* irr, float* const* dist, GradSet& G) {
+  memset(&G, 0, sizeof(G));
+  if (!irr || !dist) return fail(IRF_E_INVALID, "NULL gradient array");
+  for (int v = 0; v < c->n_vol; v++) {
+    if (c->vol[v].atlas_f16) return fail(IRF_E_UNSUPPORTED, "gradients need float32 atlases");
+    if (!irr[v] || !dist[v]) return fail(IRF_E_INVALID, "NULL gradient buffer for volume %d", v);
+    G.irr[v] = irr[v];
+    G.dist[v] = dist[v];
+  }
+  return IRF_OK;
+}
+
+irf_status irf_query_backward(irf_ctx* c, const float* pos, const float* nrm, const float* view, int64_t n,
+                              const float* grad_out, float* const* grad_irr, float* const* grad_dist, void* stream) {
+  if (!c) return fail(IRF_E_INVALID, "ctx is NULL");
+  if (n < 0) return fail(IRF_E_INVALID, "n < 0");
+  if (n == 0) return IRF_OK;
+  if (!pos || !nrm || !view || !grad_out) return fail(IRF_E_INVALID, "NULL array");
+  irf_status s = check_ready(c);
+  if (s != IRF_OK) return s;
+  GradSet G;
+  if ((s = grad_set(c, grad_irr, grad_dist, G)) != IRF_OK) return s;
+  if ((s = set_device(c)) != IRF_OK) return s;
+  launch_query_backward(volume_view(c), pos, nrm, view, n, grad_out, G, (hipStream_t)stream);
+  return launched();
+}
+
+irf_status irf_update_backward(irf_ctx* c, float* const* g_new_irr, float* const* g_new_dist, float* const* g_prev_irr,
+                               float* const* g_prev_dist, float* g_emission, void* stream) {
+  if (!c || !g_emission) return fail(IRF_E_INVALID, "NULL argument");
+  if (!c->diff_frame) return fail(IRF_E_STATE, "no frame was run with irf_set_differentiable(ctx, 1)");
+  irf_status s;
+  GradSet Gn, Gp;
+  if ((s = grad_set(c, g_new_irr, g_new_dist, Gn)) != IRF_OK) return s;
+  if ((s = grad_set(c, g_prev_irr, g_prev_dist, Gp)) != IRF_OK) return s;
+  if ((s = set_device(c)) != IRF_OK) return s;
+  VolumeSet prev = volume_view(c);
+  for (int v = 0; v < c->n_vol; v++) {
+    prev.v[v].irr = c->saved.p + c->saved_irr[v];
+    prev.v[v].dist = c->saved.p + c->saved_dist[v];
+    prev.v[v].states = (uint8_t*)(c->saved.p + c->saved_states[v]);
+  }
+  launch_update_backward(prev, scene_view(c), scratch_view(c), Gn, Gp, g_emission, (hipStream_t)stream);
+  return launched();
 }
 
 irf_status irf_profile_enable(irf_ctx* c, int32_t enable) {

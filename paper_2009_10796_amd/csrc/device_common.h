@@ -91,6 +91,22 @@ __device__ __forceinline__ void tile_footprint(float3 v, int& x0, int& y0, float
   fy = clampf(cy - (float)y0, 0.0f, 1.0f);
 }
 
+// Distance-blend weight cos^p of a positive cosine (square-and-multiply for
+// an integer exponent, so every kernel gets the same float32 value).
+__device__ __forceinline__ float pow_weight(float c, const VolumeGPU& V) {
+  if (V.cos_power_int > 0) {
+    float r = 1.0f, b = c;
+    int e = V.cos_power_int;
+    while (e) {
+      if (e & 1) r *= b;
+      b *= b;
+      e >>= 1;
+    }
+    return r;
+  }
+  return powf(c, V.cos_power);
+}
+
 __device__ __forceinline__ float3 probe_position(const VolumeGPU& V, int q) {
   int i = q % V.counts[0];
   int j = (q / V.counts[0]) % V.counts[1];

@@ -95,6 +95,11 @@ struct SceneGPU {
   int32_t stack_depth;     // traversal stack entries needed (BVH depth)
 };
 
+struct GradSet {
+  float* irr[IRF_MAX_VOLUMES];
+  float* dist[IRF_MAX_VOLUMES];
+};
+
 struct HitRec {
   int32_t tri;   // BVH-order triangle, -1 miss
   float t;
@@ -114,6 +119,7 @@ struct FrameScratch {
                             // 64 * n_lights tasks (ray id << 5 | light), light-major
   int32_t* wave_tasks;      // [max_rays / 64] number of tasks in each slice
   int64_t* wave_offset;     // [max_rays / 64] exclusive prefix sum of wave_tasks
+  float4* grad_rays;        // [max_rays] adjoint: dLoss/d(ray radiance)
   void* weights;            // per volume: 256 weight rows x rays (float32 [k][row] or 16-bit [row][k])
   float* inv_row_sum;       // [n_volumes][256] 1 / sum of the stored weights of each row (0 = none)
   void* rays_lp;            // [max_rays] 4 x bf16/f16 (matrix-core path)
@@ -143,6 +149,13 @@ void launch_classify(const VolumeSet& vs, SceneGPU sc, ObjectBoxes boxes, const 
                      int32_t* back, uint32_t* tfront, hipStream_t s);
 void launch_traversal_stats(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, unsigned long long* out,
                             hipStream_t s);
+struct GradSet;
+void launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t s);
+void launch_set_emission(const float* src, float4* dst, int m, hipStream_t s);
+void launch_query_backward(const VolumeSet& vs, const float* pos, const float* nrm, const float* view, int64_t n,
+                           const float* gout, const GradSet& G, hipStream_t s);
+void launch_update_backward(const VolumeSet& prev, SceneGPU sc, FrameScratch fs, const GradSet& Gnew,
+                            const GradSet& Gprev, float* g_emission, hipStream_t s);
 void launch_frame_stats(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, unsigned long long* out, hipStream_t s);
 void launch_records(const VolumeSet& vs, int vol, SceneGPU sc, FrameScratch fs, int n_lights,
                     irf_ray_record* out, int64_t count, hipStream_t s);

@@ -35,20 +35,6 @@ constexpr int kBlendMmaBlock = 256;
 constexpr int kBfStride = 49;     // float32 B tile: [k][48 + 1]
 constexpr int kBtStride = kKC + 8;// 16-bit B tile: [col][KC + 8]
 
-__device__ __forceinline__ float pow_w(float c, const VolumeGPU& V) {
-  if (V.cos_power_int > 0) {
-    float r = 1.0f, b = c;
-    int e = V.cos_power_int;
-    while (e) {
-      if (e & 1) r *= b;
-      b *= b;
-      e >>= 1;
-    }
-    return r;
-  }
-  return powf(c, V.cos_power);
-}
-
 // Direction of weight row `row` (irradiance rows first), false for padding.
 __device__ __forceinline__ bool row_direction(int row, float3& n) {
   if (row < kIrrRows) {
@@ -85,7 +71,7 @@ __global__ __launch_bounds__(256) void k_weights(VolumeSet vs, FrameScratch fs) 
     if (real) {
       float4 o = fs.omega[V.omega_base + k];
       float c = fmaf(n.x, o.x, fmaf(n.y, o.y, n.z * o.z));
-      w = c > 0.0f ? (row < kIrrRows ? c : pow_w(c, V)) : 0.0f;
+      w = c > 0.0f ? (row < kIrrRows ? c : pow_weight(c, V)) : 0.0f;
     }
     w = round_to(w, V.blend);
     sum += w;

@@ -167,20 +167,6 @@ constexpr int kBlendBlock = 256;
 constexpr int kDistInterior = (kDistTile - 2) * (kDistTile - 2);   // 196
 constexpr int kIrrInterior = (kIrrTile - 2) * (kIrrTile - 2);      // 36
 
-__device__ __forceinline__ float pow_weight(float c, const VolumeGPU& V) {
-  if (V.cos_power_int > 0) {
-    float r = 1.0f, b = c;
-    int e = V.cos_power_int;
-    while (e) {
-      if (e & 1) r *= b;
-      b *= b;
-      e >>= 1;
-    }
-    return r;
-  }
-  return powf(c, V.cos_power);
-}
-
 // Writes value to interior cell (x, y) of an M-tile and to every border cell
 // that repeats it.
 template <int M, typename F>

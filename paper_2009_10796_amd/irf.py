@@ -90,6 +90,10 @@ SIGNATURES = {
     "irf_graph_capture": (C.c_int, [_vp, _vp, C.POINTER(_vp)]),
     "irf_graph_launch": (C.c_int, [_vp, _vp, _vp, _vp]),
     "irf_graph_destroy": (None, [_vp]),
+    "irf_set_differentiable": (C.c_int, [_vp, _i32]),
+    "irf_set_emission": (C.c_int, [_vp, _vp, _vp]),
+    "irf_query_backward": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
+    "irf_update_backward": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "irf_profile_enable": (C.c_int, [_vp, _i32]),
     "irf_profile_read": (C.c_int, [_vp, _vp, _i32, C.POINTER(_i32), _i32]),
     "irf_validate_volume_desc": (C.c_int, [C.POINTER(VolumeDescC)]),
@@ -212,6 +216,7 @@ class Context:
         self.handle = h
         self.volumes: List[Volume] = []
         self.n_lights = 0
+        self.frames = 0          # update frames run (eager or replayed)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -252,6 +257,7 @@ class Context:
     def update_probes(self, rotation) -> None:
         R = _np(rotation, np.float32).reshape(9)
         _check(load().irf_update_probes(self.handle, _ptr(R), _stream(self.torch)))
+        self.frames += 1
 
     def query_irradiance(self, pos, nrm, view, out=None):
         torch = self.torch
@@ -265,6 +271,36 @@ class Context:
                                            C.c_void_p(view.data_ptr()), n, C.c_void_p(out.data_ptr()),
                                            _stream(self.torch)))
         return out
+
+    # ---- adjoint
+
+    def set_differentiable(self, enable: bool = True) -> None:
+        _check(load().irf_set_differentiable(self.handle, int(enable)))
+
+    def set_emission(self, emission) -> None:
+        e = emission.detach().to(self.device, self.torch.float32).contiguous()
+        _check(load().irf_set_emission(self.handle, C.c_void_p(e.data_ptr()), _stream(self.torch)))
+        self._emission_keep = e
+
+    @staticmethod
+    def _ptrs(tensors):
+        a = (C.c_void_p * len(tensors))()
+        for i, t in enumerate(tensors):
+            assert t.is_contiguous() and t.dtype.is_floating_point
+            a[i] = t.data_ptr()
+        return a
+
+    def query_backward(self, pos, nrm, view, grad_out, grad_irr, grad_dist) -> None:
+        n = int(pos.shape[0])
+        g = grad_out.contiguous()
+        _check(load().irf_query_backward(self.handle, C.c_void_p(pos.data_ptr()), C.c_void_p(nrm.data_ptr()),
+                                         C.c_void_p(view.data_ptr()), n, C.c_void_p(g.data_ptr()),
+                                         self._ptrs(grad_irr), self._ptrs(grad_dist), _stream(self.torch)))
+
+    def update_backward(self, g_new_irr, g_new_dist, g_prev_irr, g_prev_dist, g_emission) -> None:
+        _check(load().irf_update_backward(self.handle, self._ptrs(g_new_irr), self._ptrs(g_new_dist),
+                                          self._ptrs(g_prev_irr), self._ptrs(g_prev_dist),
+                                          C.c_void_p(g_emission.data_ptr()), _stream(self.torch)))
 
     def frame_stats(self) -> dict:
         out = (C.c_int64 * 4)()
@@ -327,6 +363,7 @@ class FrameGraph:
     def launch(self, rotation) -> None:
         R = _np(rotation, np.float32).reshape(9)
         _check(load().irf_graph_launch(self.ctx.handle, self.handle, _ptr(R), C.c_void_p(self.stream.cuda_stream)))
+        self.ctx.frames += 1
 
     def close(self):
         if getattr(self, "handle", None):

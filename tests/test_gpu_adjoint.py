@@ -1,0 +1,232 @@
+"""GPU adjoint (reverse of query -> blend -> hit shading, ray hits held fixed)
+against the oracle's adjoint, which is pinned by central differences in FP64.
+
+Workload: the reduced differentiable frame of tests/adjoint_case (city with
+64 emissive quads, a 6x4x6 volume of 64-ray probes, frame 1 converged, then
+one frame from A0 to A1 queried at surface points).  The GPU starts from the
+oracle's A0 and probe states, rounded to float32 (oracle -> GPU input only).
+
+Tolerance.  Each gradient element is a sum of terms (an upstream gradient
+times float32 coefficients: normalised blend and query weights and their
+Chebyshev derivatives), accumulated by atomics in arbitrary order.  The
+oracle reports per element the sum of the terms' magnitudes (a) and how far
+the terms move when the float32 inputs of each query (sampled moments, r,
+irradiance, hit point) move by their float32 error bounds (s).  Elements are
+compared as |g - o| <= 1e-5 a + s (+ 1e-7 of the array's largest |o|).  s is
+large exactly where the Chebyshev factor is ill-conditioned (variance near
+zero with r close to mu), as for the forward parity.
+"""
+import numpy as np
+import pytest
+
+from paper_2009_10796_amd import scenes as S
+from tests.adjoint_case import OracleFrame, workload
+from tests.gpu_helpers import compare_records
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def frame():
+    fr = OracleFrame(workload())
+    for v in fr.A0:
+        v.irr[:] = v.irr.astype(np.float32)
+        v.dist[:] = v.dist.astype(np.float32)
+    fr.target = fr.forward(S.target_emission(fr.w).astype(np.float64), fr.A0)[0]
+    return fr
+
+
+def _gpu_context(torch, fr):
+    from paper_2009_10796_amd import irf
+    ctx = irf.build_workload(fr.w)
+    for gv, o in zip(ctx.volumes, fr.A0):
+        gv.states.copy_(torch.from_numpy(o.states.copy()))
+    return ctx
+
+
+def _load_a0(torch, ctx, fr):
+    for gv, o in zip(ctx.volumes, fr.A0):
+        gv.irradiance.zero_()
+        gv.irradiance[..., :3].copy_(torch.from_numpy(o.irr.astype(np.float32)))
+        gv.distance.copy_(torch.from_numpy(o.dist.astype(np.float32)))
+        gv.states.copy_(torch.from_numpy(o.states.copy()))
+
+
+def _close(g, o, a=None, sens=None, name=""):
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    scale = max(np.abs(o).max(), 1e-30)
+    tol = 1e-7 * scale + (1e-5 * a if a is not None else 1e-4 * scale) + (sens if sens is not None else 0.0)
+    err = np.abs(g - o)
+    ratio = err / tol
+    agg = float(np.linalg.norm(g - o) / max(np.linalg.norm(o), 1e-30))
+    print(f"[adjoint] {name}: max|o|={scale:.3e} worst err/tol={ratio.max():.3f} rel L2={agg:.2e} "
+          f"elements with s > 1e-3 max|o|: {int((sens > 1e-3 * scale).sum()) if sens is not None else 0}", flush=True)
+    return bool(np.all(err <= tol))
+
+
+def _zeros(vols):
+    return [np.zeros_like(v.irr) for v in vols], [np.zeros_like(v.dist) for v in vols]
+
+
+def _gpu_zeros(torch, ctx):
+    dev = ctx.device
+    return ([torch.zeros(v.irradiance.shape, dtype=torch.float32, device=dev) for v in ctx.volumes],
+            [torch.zeros(v.distance.shape, dtype=torch.float32, device=dev) for v in ctx.volumes])
+
+
+def test_query_backward_matches_oracle(torch, frame):
+    import oracle
+    fr = frame
+    ctx = _gpu_context(torch, fr)
+    # atlases: the oracle's A1, float32 (query stage alone)
+    E, A1, _ = fr.forward(fr.emission, fr.A0)
+    for o in A1:
+        o.irr[:] = o.irr.astype(np.float32)
+        o.dist[:] = o.dist.astype(np.float32)
+        o.irr_kappa[:] = 0.0
+        o.dist_kappa[:] = 0.0
+    for gv, o in zip(ctx.volumes, A1):
+        gv.irradiance.zero_()
+        gv.irradiance[..., :3].copy_(torch.from_numpy(o.irr.astype(np.float32)))
+        gv.distance.copy_(torch.from_numpy(o.dist.astype(np.float32)))
+        gv.states.copy_(torch.from_numpy(o.states.copy()))
+    q = fr.w.queries
+    gout = S.Stream(951, 2).uniform(3 * len(q.pos), -1.0, 1.0).reshape(-1, 3).astype(np.float32)
+    gi, gd = _zeros(A1)
+    ai, ad = _zeros(A1)
+    si, sd = _zeros(A1)
+    oracle.query_backward(A1, q.pos, q.nrm, q.view, gout, gi, gd, ai, ad, si, sd)
+    dev = ctx.device
+    Gi, Gd = _gpu_zeros(torch, ctx)
+    pos, nrm, view = (torch.from_numpy(a).to(dev) for a in (q.pos, q.nrm, q.view))
+    ctx.query_backward(pos, nrm, view, torch.from_numpy(gout).to(dev), Gi, Gd)
+    torch.cuda.synchronize()
+    gi_g = Gi[0].cpu().numpy()
+    assert np.all(gi_g[..., 3] == 0)
+    assert np.abs(gi[0]).max() > 0 and np.abs(gd[0]).max() > 0
+    assert _close(gi_g[..., :3], gi[0], ai[0], si[0], name="query dE/dirr")
+    assert _close(Gd[0].cpu().numpy(), gd[0], ad[0], sd[0], name="query dE/ddist")
+    # linear in the upstream gradient
+    Gi2, Gd2 = _gpu_zeros(torch, ctx)
+    ctx.query_backward(pos, nrm, view, torch.from_numpy(2 * gout).to(dev), Gi2, Gd2)
+    torch.cuda.synchronize()
+    assert _close(Gi2[0].cpu().numpy(), 2 * gi_g, name="linearity")
+    ctx.close()
+
+
+def test_frame_backward_matches_oracle(torch, frame):
+    import oracle
+    fr = frame
+    ctx = _gpu_context(torch, fr)
+    _load_a0(torch, ctx, fr)
+    dev = ctx.device
+    e0 = fr.emission
+    ctx.set_emission(torch.from_numpy(e0.astype(np.float32)).to(dev))
+    ctx.set_differentiable(True)
+    ctx.update_probes(fr.R)
+    torch.cuda.synchronize()
+    # the oracle's frame from the same A0
+    E_o, A1_o, rec_o = fr.forward(e0, fr.A0)
+    rec_g = ctx.ray_records(0)
+    tainted, _, rep = compare_records(rec_g, rec_o)
+    print(f"[adjoint] frame records: {rep}", flush=True)
+    assert rep["unflagged_flips"] == 0
+    # upstream: the oracle's dLoss/d(A1), rounded to float32, fed to both
+    q = fr.w.queries
+    gE = 2.0 * (E_o - fr.target) / E_o.size
+    g1i, g1d = _zeros(A1_o)
+    oracle.query_backward(A1_o, q.pos, q.nrm, q.view, gE, g1i, g1d)
+    g1i = [g.astype(np.float32).astype(np.float64) for g in g1i]
+    g1d = [g.astype(np.float32).astype(np.float64) for g in g1d]
+    prev = oracle.copy_volumes(fr.A0)
+    oracle.state_step(fr.sc, prev)
+    for v in prev:
+        v.irr_kappa[:] = 0.0      # the GPU reads the same float32 A0
+        v.dist_kappa[:] = 0.0
+    g0i, g0d = _zeros(prev)
+    a0i, a0d = _zeros(prev)
+    s0i, s0d = _zeros(prev)
+    ge_o = np.zeros_like(e0)
+    fr.sc.set_emission(e0)
+    oracle.update_backward(fr.sc, prev, fr.R, rec_o, g1i, g1d, g0i, g0d, ge_o, a_prev_irr=a0i, a_prev_dist=a0d,
+                           s_prev_irr=s0i, s_prev_dist=s0d)
+    Gi, Gd = [], []
+    for gv, a, b in zip(ctx.volumes, g1i, g1d):
+        t = torch.zeros(gv.irradiance.shape, dtype=torch.float32)
+        t[..., :3] = torch.from_numpy(a.astype(np.float32))
+        Gi.append(t.to(dev))
+        Gd.append(torch.from_numpy(b.astype(np.float32)).to(dev))
+    P0i, P0d = _gpu_zeros(torch, ctx)
+    ge = torch.zeros((e0.shape[0], 3), dtype=torch.float32, device=dev)
+    ctx.update_backward(Gi, Gd, P0i, P0d, ge)
+    torch.cuda.synchronize()
+    # rays whose hit differs (oracle-flagged) and the probes they feed are
+    # compared by validity only: none in this workload
+    assert rep["flips"] == 0, rep
+    assert _close(ge.cpu().numpy(), ge_o, name="dL/demission")
+    assert _close(P0i[0].cpu().numpy()[..., :3], g0i[0], a0i[0], s0i[0], name="dL/dirr0")
+    assert _close(P0d[0].cpu().numpy(), g0d[0], a0d[0], s0d[0], name="dL/ddist0")
+    # backward needs a differentiable frame
+    ctx.set_differentiable(False)
+    from paper_2009_10796_amd import irf
+    with pytest.raises(irf.IrfError):
+        ctx.update_backward(Gi, Gd, P0i, P0d, ge)
+    ctx.close()
+
+
+def test_autograd_matches_directional_difference(torch, frame):
+    """The autograd wrapper against the GPU's own forward: with hits fixed the
+    loss is quadratic in the emitter radiance, so a central difference along
+    a direction equals the directional derivative up to float32 rounding of
+    the loss."""
+    from paper_2009_10796_amd import diff
+    fr = frame
+    ctx = _gpu_context(torch, fr)
+    dev = ctx.device
+    q = fr.w.queries
+    pos, nrm, view = (torch.from_numpy(a).to(dev) for a in (q.pos, q.nrm, q.view))
+    A0 = []
+    for o in fr.A0:
+        irr = torch.zeros((o.irr.shape[0], 8, 8, 4), dtype=torch.float32)
+        irr[..., :3] = torch.from_numpy(o.irr.astype(np.float32))
+        A0 += [irr.to(dev), torch.from_numpy(o.dist.astype(np.float32)).to(dev)]
+    states0 = [torch.from_numpy(o.states.copy()).to(dev) for o in fr.A0]
+    target = torch.from_numpy(fr.target.astype(np.float32)).to(dev)
+
+    def loss(e, grad=False):
+        for gv, s0 in zip(ctx.volumes, states0):
+            gv.states.copy_(s0)
+        a = [t.clone().requires_grad_(grad) for t in A0]
+        E = diff.frame_and_query(ctx, fr.R, pos, nrm, view, e, a)
+        L = ((E.double() - target.double()) ** 2).mean()
+        return L, a
+
+    e = torch.from_numpy(fr.emission.astype(np.float32)).to(dev).requires_grad_(True)
+    L, a = loss(e, grad=True)
+    L.backward()
+    ge = e.grad.double().cpu().numpy()
+    assert np.abs(ge).max() > 0
+    d = S.Stream(952, 3).uniform(ge.size, -1.0, 1.0).reshape(ge.shape)
+    d *= (fr.emission != 0) | (np.arange(len(d)) == 0)[:, None]
+    h = 0.05
+    with torch.no_grad():
+        dt = torch.from_numpy(d.astype(np.float32)).to(dev)
+        Lp = float(loss(e.detach() + h * dt)[0])
+        Lm = float(loss(e.detach() - h * dt)[0])
+    fd = (Lp - Lm) / (2 * h)
+    dd = float((ge * d).sum())
+    print(f"[adjoint] directional: fd={fd:.6e} grad.d={dd:.6e}", flush=True)
+    assert abs(fd - dd) <= 1e-3 * abs(dd) + 1e-6 * float(L.detach())
+    # the texel gradients come back through autograd too
+    assert a[0].grad is not None and a[1].grad is not None
+    assert float(a[0].grad.abs().max()) > 0
+    ctx.close()
