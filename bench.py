@@ -164,6 +164,72 @@ def terrain_batched(irf, torch, frames=60):
             "tuning": tuning}
 
 
+def adjoint_timing(irf, torch, reps=10):
+    """The differentiable frame at full size (city volume, 64 emissive quads,
+    65,536 surface points): forward frame with its inputs saved, query,
+    query backward, update backward; median times over `reps`."""
+    from paper_2009_10796_amd import scenes as S
+    w = S.config4()
+    ctx = irf.build_workload(w, device=0)
+    ctx.classify(w.classify_rotations)
+    for f in (1, 2):
+        ctx.update_probes(w.frame_rotation(f))
+    q = w.queries
+    pos, nrm, view = (torch.from_numpy(a).cuda() for a in (q.pos, q.nrm, q.view))
+    target = torch.zeros((q.n, 3), device="cuda")
+    st0 = [v.states.clone() for v in ctx.volumes]
+    a0 = [(v.irradiance.clone(), v.distance.clone()) for v in ctx.volumes]
+    V = ctx.volumes
+    Gi = [torch.zeros(v.irradiance.shape, device="cuda") for v in V]
+    Gd = [torch.zeros(v.distance.shape, device="cuda") for v in V]
+    Pi = [torch.zeros_like(t) for t in Gi]
+    Pd = [torch.zeros_like(t) for t in Gd]
+    ge = torch.zeros((w.scene.emission.shape[0], 3), device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    rows = {"frame_saving_inputs": [], "query": [], "query_backward": [], "update_backward": [], "frame_plain": []}
+    for mode in (True, False):
+        ctx.set_differentiable(mode)
+        for i in range(reps + 2):
+            for v, s0, (a, b) in zip(V, st0, a0):
+                v.states.copy_(s0)
+                v.irradiance.copy_(a)
+                v.distance.copy_(b)
+            R = w.frame_rotation(3)
+            ev[0].record()
+            ctx.update_probes(R)
+            ev[1].record()
+            if not mode:
+                ev[1].synchronize()
+                if i >= 2:
+                    rows["frame_plain"].append(ev[0].elapsed_time(ev[1]))
+                continue
+            E = ctx.query_irradiance(pos, nrm, view)
+            ev[2].record()
+            gE = (2.0 / E.numel()) * (E - target)
+            for t in Gi + Gd + Pi + Pd + [ge]:
+                t.zero_()
+            ev[3].record()
+            ctx.query_backward(pos, nrm, view, gE, Gi, Gd)
+            ev[4].record()
+            ctx.update_backward(Gi, Gd, Pi, Pd, ge)
+            e5 = torch.cuda.Event(enable_timing=True)
+            e5.record()
+            e5.synchronize()
+            if i >= 2:
+                rows["frame_saving_inputs"].append(ev[0].elapsed_time(ev[1]))
+                rows["query"].append(ev[1].elapsed_time(ev[2]))
+                rows["query_backward"].append(ev[3].elapsed_time(ev[4]))
+                rows["update_backward"].append(ev[4].elapsed_time(e5))
+    ctx.set_differentiable(False)
+    stats = ctx.frame_stats()
+    ctx.close()
+    med = {k: round(float(np.median(v)), 4) for k, v in rows.items()}
+    return {"workload": w.name, "points": int(q.n), "emitter_parameters": 64 * 3,
+            "texel_gradients": int(V[0].n_probes * (64 * 3 + 256 * 2)), "active_probes": int(stats["active_probes"]),
+            "ms": med,
+            "backward_ms": round(med["query_backward"] + med["update_backward"], 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +238,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-blend-variants", action="store_true")
     ap.add_argument("--no-terrain", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -283,6 +350,9 @@ def main():
     if not args.no_terrain:
         print("[bench] terrain (batched cascades) ...", file=sys.stderr, flush=True)
         line["batched"] = terrain_batched(irf, torch)
+    if not args.no_adjoint:
+        print("[bench] adjoint (differentiable frame) ...", file=sys.stderr, flush=True)
+        line["adjoint"] = adjoint_timing(irf, torch)
     if not args.no_cpu_baseline:
         print("[bench] oracle CPU baseline ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)

@@ -66,3 +66,41 @@ class OracleFrame:
         self.sc.set_emission(emission)
         o.update_backward(self.sc, prev, self.R, rec, g1i, g1d, g0i, g0d, ge)
         return ge, g0i, g0d
+
+
+class FullFrame:
+    """The differentiable frame at full size (city volume 16x8x16, 256 rays,
+    65,536 surface points): classify, frames 1-2 give A0 (rounded to
+    float32), frame 3 is the differentiable frame."""
+
+    def __init__(self):
+        import oracle
+        self.o = oracle
+        w = workload(full=True)
+        self.w = w
+        self.sc = oracle.Scene(w.scene)
+        vols = [oracle.Volume(d) for d in w.volumes]
+        oracle.classify(self.sc, vols, w.classify_rotations)
+        for f in (1, 2):
+            oracle.update_frame(self.sc, w.lights, vols, w.frame_rotation(f), records=False)
+        for v in vols:
+            v.irr[:] = v.irr.astype(np.float32)
+            v.dist[:] = v.dist.astype(np.float32)
+            v.irr_kappa[:] = 0.0
+            v.dist_kappa[:] = 0.0
+        self.A0 = vols
+        self.R = w.frame_rotation(3)
+        self.emission = w.scene.emission.astype(np.float64)
+        self.target = self.forward(S.target_emission(w).astype(np.float64))[0]
+
+    def forward(self, emission):
+        o = self.o
+        self.sc.set_emission(emission)
+        vols = o.copy_volumes(self.A0)
+        rec = o.update_frame(self.sc, self.w.lights, vols, self.R)
+        q = self.w.queries
+        E, _ = o.query(vols, q.pos, q.nrm, q.view)
+        return E, vols, rec
+
+    def loss(self, emission):
+        return float(np.mean((self.forward(emission)[0] - self.target) ** 2))

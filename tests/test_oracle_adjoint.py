@@ -105,3 +105,34 @@ def test_gradient_is_linear_in_the_residual(frame):
     frame.target = t0
     assert np.allclose(ge2, 2 * ge1, rtol=1e-9, atol=1e-18)
     assert np.allclose(gi2[0], 2 * gi1[0], rtol=1e-9, atol=1e-18)
+
+
+def test_full_size_emitter_gradient_directional_differences():
+    """Full-size differentiable frame: the loss is quadratic in the emitter
+    radiances (hits fixed), so a central difference along any direction
+    equals the directional derivative up to FP64 rounding."""
+    from tests.adjoint_case import FullFrame
+    fr = FullFrame()
+    o = fr.o
+    E, A1, rec = fr.forward(fr.emission)
+    q = fr.w.queries
+    gE = 2.0 * (E - fr.target) / E.size
+    g1i = [np.zeros_like(v.irr) for v in A1]
+    g1d = [np.zeros_like(v.dist) for v in A1]
+    o.query_backward(A1, q.pos, q.nrm, q.view, gE, g1i, g1d)
+    prev = o.copy_volumes(fr.A0)
+    o.state_step(fr.sc, prev)
+    g0i = [np.zeros_like(v.irr) for v in prev]
+    g0d = [np.zeros_like(v.dist) for v in prev]
+    ge = np.zeros_like(fr.emission)
+    fr.sc.set_emission(fr.emission)
+    o.update_backward(fr.sc, prev, fr.R, rec, g1i, g1d, g0i, g0d, ge)
+    assert np.count_nonzero(ge[-64:]) >= 150     # the 64 emissive quads (the last materials)
+    st = S.Stream(953, 1)
+    for k in range(3):
+        d = st.uniform(ge.size, -1.0, 1.0).reshape(ge.shape)
+        h = 0.1
+        fd = (fr.loss(fr.emission + h * d) - fr.loss(fr.emission - h * d)) / (2 * h)
+        dd = float((ge * d).sum())
+        print(f"direction {k}: fd={fd:.12e} grad.d={dd:.12e}")
+        assert abs(fd - dd) <= 1e-8 * abs(dd) + 1e-14
