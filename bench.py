@@ -27,6 +27,40 @@ METRIC = "probe update ms/frame, Grays/s, queries/s; MFMA vs FP32 blend at state
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 NODE_BYTES, TRI_BYTES, RAY_IO_BYTES = 64, 48, 32
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "city-16x8x16-256rays_hbm_traffic.md")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the library's kernel sources (a change voids measured
+    hardware byte counts)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2009_10796_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic() -> dict:
+    """Per-launch DRAM bytes per kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a known-size copy), when it was
+    taken on the current kernel sources; else {}."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            text = f.read()
+    except OSError:
+        return {}
+    block = text.split("```json")[-1].split("```")[0] if "```json" in text else ""
+    try:
+        data = json.loads(block)
+    except ValueError:
+        return {}
+    if data.get("kernel_source_sha256") != kernel_source_hash():
+        return {}
+    return {k: int(v) for k, v in data.get("bytes_per_launch", {}).items()}
 
 
 def query_bytes(w, states):
@@ -239,6 +273,11 @@ def main():
     ap.add_argument("--no-blend-variants", action="store_true")
     ap.add_argument("--no-terrain", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--only", choices=["terrain", "adjoint"],
+                    help="run one secondary section alone and print its JSON (for per-section profiles)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="copy 256 MiB device-to-device three times before timing (a known-size kernel for "
+                         "scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -249,6 +288,10 @@ def main():
     from paper_2009_10796_amd import irf, scenes as S
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.only:
+        fn = terrain_batched if args.only == "terrain" else adjoint_timing
+        print(json.dumps({"section": args.only, **fn(irf, torch)}), flush=True)
+        return
     t_setup = time.perf_counter()
     w = S.config1()
     ctx = irf.build_workload(w, device=0)
@@ -263,6 +306,13 @@ def main():
     setup_s = time.perf_counter() - t_setup
     print(f"[bench] setup {setup_s:.1f}s, {w.scene.n_triangles} triangles, {q.n} queries", file=sys.stderr, flush=True)
 
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     f = 0
     for _ in range(max(1, args.warmup)):
         ctx.update_probes(R[f])
@@ -294,10 +344,13 @@ def main():
     states = ctx.volumes[0].states.cpu().numpy()
     qbytes, mean_sampled = query_bytes(w, states)
 
+    traffic = measured_traffic()
+
     def hbm(kernel, nbytes):
         gbs = nbytes / (kern[kernel]["avg_us"] * 1e-6) / 1e9
         return {"kernel": kernel, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "algorithmic_bytes_per_launch": int(nbytes)}
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic.get(kernel),
+                "algorithmic_bytes_per_launch": int(nbytes)}
 
     rooflines = {
         "trace": hbm("trace", trav["probe_nodes"] * NODE_BYTES + trav["probe_tris"] * TRI_BYTES + prim * RAY_IO_BYTES),
@@ -312,7 +365,7 @@ def main():
     tf = blend_flops / (kern[bk]["avg_us"] * 1e-6) / 1e12
     rooflines["blend"] = {"kernel": bk, "bound": "mfma" if bk == "blend_mma" else "alu", "achieved": round(tf, 3),
                           "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / FP32_PEAK_TFLOPS, 4),
-                          "traffic": None, "algorithmic_flops_per_launch": blend_flops}
+                          "traffic": traffic.get(bk), "algorithmic_flops_per_launch": blend_flops}
     dominant = max(kern, key=lambda k: kern[k]["avg_us"])
     roof = rooflines.get(dominant if not dominant.startswith("blend") else "blend")
     line = {

@@ -12,6 +12,10 @@
 
 #include "irf_internal.h"
 
+namespace irf {
+thread_local KernelTiming* g_kernel_timing = nullptr;
+}
+
 using namespace irf;
 
 namespace {
@@ -247,21 +251,36 @@ hipEvent_t prof_event(irf_ctx* c) {
   return e;
 }
 
-// Brackets one launch with events on its stream while timing is enabled.
+// While timing is enabled, times the kernels launched in its scope with
+// events stamped on their dispatches.
 struct ProfScope {
   irf_ctx* c;
   const char* name;
-  hipStream_t s;
-  hipEvent_t a = nullptr;
-  ProfScope(irf_ctx* c_, const char* n, hipStream_t s_) : c(c_), name(n), s(s_) {
-    if (c->prof && (a = prof_event(c))) (void)hipEventRecord(a, s);
+  KernelTiming t;
+  KernelTiming* outer;
+  bool on = false;
+  ProfScope(irf_ctx* c_, const char* n, hipStream_t) : c(c_), name(n), outer(g_kernel_timing) {
+    if (!c->prof) return;
+    t.start = prof_event(c);
+    t.stop = prof_event(c);
+    t.first = true;
+    if (t.start && t.stop) {
+      on = true;
+      g_kernel_timing = &t;
+    } else {
+      if (t.start) c->prof_pool.push_back(t.start);
+      if (t.stop) c->prof_pool.push_back(t.stop);
+    }
   }
   ~ProfScope() {
-    if (!a) return;
-    hipEvent_t b = prof_event(c);
-    if (!b) return;
-    (void)hipEventRecord(b, s);
-    c->prof_pending.push_back({name, a, b});
+    if (!on) return;
+    g_kernel_timing = outer;
+    if (!t.first) {
+      c->prof_pending.push_back({name, t.start, t.stop});
+    } else {   // nothing was launched
+      c->prof_pool.push_back(t.start);
+      c->prof_pool.push_back(t.stop);
+    }
   }
 };
 
@@ -300,8 +319,8 @@ void enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st) {
   }
   { ProfScope p(c, "trace", st); launch_trace(vs, sc, fs, c->tune.trace_blocks, st); }
   if (nl > 0) {
-    ProfScope p(c, "shadow", st);
-    launch_shadow(vs, sc, nl, fs, c->tune.shadow_blocks, st);
+    { ProfScope p(c, "scan_tasks", st); launch_scan_tasks(vs, fs, st); }
+    { ProfScope p(c, "shadow", st); launch_shadow(vs, sc, nl, fs, c->tune.shadow_blocks, st); }
   }
   { ProfScope p(c, "shade", st); launch_shade(vs, sc, fs, c->tune.shade_blocks, st); }
   if (any_valu) {
@@ -309,8 +328,8 @@ void enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st) {
     launch_blend(vs, fs, st);
   }
   if (any_mma) {
-    ProfScope p(c, "blend_mma", st);
-    launch_blend_mma(vs, fs, c->tune.blend_blocks, st);
+    { ProfScope p(c, "blend_mma", st); launch_blend_mma(vs, fs, c->tune.blend_blocks, st); }
+    { ProfScope p(c, "promote", st); launch_promote(fs, vs, st); }
   }
 }
 

@@ -2,6 +2,7 @@
 // entry points shared between translation units).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include <vector>
@@ -9,6 +10,28 @@
 #include "../../include/irf.h"
 
 namespace irf {
+
+// Kernel timing: while the API times a stage it points g_kernel_timing at a
+// start/stop event pair; irf_launch then stamps the first kernel's start and
+// every kernel's end on the dispatch itself (hipExtLaunchKernel), so the
+// measured time is kernel execution only.
+struct KernelTiming {
+  hipEvent_t start, stop;
+  bool first;
+};
+extern thread_local KernelTiming* g_kernel_timing;
+
+template <typename F, typename... Args>
+inline void irf_launch(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, Args... args) {
+  KernelTiming* t = g_kernel_timing;
+  if (!t) {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+    return;
+  }
+  hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, t->first ? t->start : nullptr, t->stop, 0u, args...);
+  t->first = false;
+}
+
 
 constexpr int kIrrTile = 8;      // 6x6 interior + one-texel border
 constexpr int kDistTile = 16;    // 14x14 interior + one-texel border
@@ -138,10 +161,12 @@ const void* set_params_kernel();
 void launch_directions(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
 void launch_state_compact(const VolumeSet& vs, ObjectBoxes boxes, FrameScratch fs, hipStream_t s);
 void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s);
+void launch_scan_tasks(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
 void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, hipStream_t s);
 void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s);
 void launch_blend(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
 void launch_weights(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
+void launch_promote(FrameScratch fs, const VolumeSet& vs, hipStream_t s);
 void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, int grid, hipStream_t s);
 void launch_query(const VolumeSet& vs, const float* pos, const float* nrm, const float* view, int64_t n,
                   float* out, hipStream_t s);

@@ -300,20 +300,20 @@ __global__ void k_copy_bytes(uint8_t* dst, const uint8_t* src, int64_t n) {
 void launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t s) {
   if (bytes <= 0) return;
   if (bytes % 4 == 0 && ((uintptr_t)dst & 3) == 0 && ((uintptr_t)src & 3) == 0)
-    hipLaunchKernelGGL(k_copy_words, dim3(1024), dim3(256), 0, s, (uint32_t*)dst, (const uint32_t*)src, bytes / 4);
+    irf_launch(k_copy_words, dim3(1024), dim3(256), 0, s, (uint32_t*)dst, (const uint32_t*)src, bytes / 4);
   else
-    hipLaunchKernelGGL(k_copy_bytes, dim3(1024), dim3(256), 0, s, (uint8_t*)dst, (const uint8_t*)src, bytes);
+    irf_launch(k_copy_bytes, dim3(1024), dim3(256), 0, s, (uint8_t*)dst, (const uint8_t*)src, bytes);
 }
 
 void launch_set_emission(const float* src, float4* dst, int m, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_emission, dim3((m + 255) / 256), dim3(256), 0, s, src, dst, m);
+  irf_launch(k_set_emission, dim3((m + 255) / 256), dim3(256), 0, s, src, dst, m);
 }
 
 void launch_query_backward(const VolumeSet& vs, const float* pos, const float* nrm, const float* view, int64_t n,
                            const float* gout, const GradSet& G, hipStream_t s) {
   if (n == 0) return;
   int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_query_backward, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, vs, pos, nrm,
+  irf_launch(k_query_backward, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, vs, pos, nrm,
                      view, n, gout, G);
 }
 
@@ -322,10 +322,10 @@ void launch_update_backward(const VolumeSet& prev, SceneGPU sc, FrameScratch fs,
   int P = 0;
   for (int v = 0; v < prev.n; v++) P += prev.v[v].n_probes;
   if (P == 0) return;
-  hipLaunchKernelGGL(k_blend_backward, dim3(P), dim3(kBwdBlock), 0, s, prev, fs, Gnew, Gprev);
+  irf_launch(k_blend_backward, dim3(P), dim3(kBwdBlock), 0, s, prev, fs, Gnew, Gprev);
   if (fs.max_rays > 0) {
     int64_t blocks = (fs.max_rays + 255) / 256;
-    hipLaunchKernelGGL(k_shade_backward, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, prev, sc,
+    irf_launch(k_shade_backward, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, prev, sc,
                        fs, Gprev, g_emission);
   }
 }

@@ -334,7 +334,7 @@ __global__ void k_promote(VolumeSet vs, FrameScratch fs) {
 }
 
 void launch_weights(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
-  hipLaunchKernelGGL(k_weights, dim3(kRows, vs.n), dim3(256), 0, s, vs, fs);
+  irf_launch(k_weights, dim3(kRows, vs.n), dim3(256), 0, s, vs, fs);
 }
 
 void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, int grid, hipStream_t s) {
@@ -347,13 +347,15 @@ void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, int grid, hipStream_
   if (full == 0) return;
   const unsigned g = (unsigned)(grid > 0 && grid < full ? grid : full);
   if (mode_present[IRF_BLEND_F32])
-    hipLaunchKernelGGL(k_blend_mma<IRF_BLEND_F32>, dim3(g), dim3(kBlendMmaBlock), 0, s, vs, fs);
+    irf_launch(k_blend_mma<IRF_BLEND_F32>, dim3(g), dim3(kBlendMmaBlock), 0, s, vs, fs);
   if (mode_present[IRF_BLEND_BF16])
-    hipLaunchKernelGGL(k_blend_mma<IRF_BLEND_BF16>, dim3(g), dim3(kBlendMmaBlock), 0, s, vs, fs);
+    irf_launch(k_blend_mma<IRF_BLEND_BF16>, dim3(g), dim3(kBlendMmaBlock), 0, s, vs, fs);
   if (mode_present[IRF_BLEND_F16])
-    hipLaunchKernelGGL(k_blend_mma<IRF_BLEND_F16>, dim3(g), dim3(kBlendMmaBlock), 0, s, vs, fs);
-  if (fs.max_slots > 0)
-    hipLaunchKernelGGL(k_promote, dim3((fs.max_slots + 255) / 256), dim3(256), 0, s, vs, fs);
+    irf_launch(k_blend_mma<IRF_BLEND_F16>, dim3(g), dim3(kBlendMmaBlock), 0, s, vs, fs);
+}
+
+void launch_promote(FrameScratch fs, const VolumeSet& vs, hipStream_t s) {
+  if (fs.max_slots > 0) irf_launch(k_promote, dim3((fs.max_slots + 255) / 256), dim3(256), 0, s, vs, fs);
 }
 
 }  // namespace irf

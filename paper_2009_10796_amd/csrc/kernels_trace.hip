@@ -544,13 +544,13 @@ __global__ __launch_bounds__(kTraceBlock) void k_shadow_count(VolumeSet vs, Scen
 
 void launch_traversal_stats(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, unsigned long long* out,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)out, 0u, (int64_t)8);
+  irf_launch(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)out, 0u, (int64_t)8);
   if (fs.max_rays == 0) return;
-  hipLaunchKernelGGL(k_trace_count, dim3(blocks_for(fs.max_rays, kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s,
+  irf_launch(k_trace_count, dim3(blocks_for(fs.max_rays, kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s,
                      vs, sc, fs, out);
   if (n_lights == 0) return;
   int64_t cap = (fs.max_rays + 63) / 64 * 64 * n_lights;
-  hipLaunchKernelGGL(k_shadow_count, dim3(blocks_for(cap, kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc,
+  irf_launch(k_shadow_count, dim3(blocks_for(cap, kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc,
                      fs, out);
 }
 
@@ -574,8 +574,8 @@ __global__ void k_frame_stats(VolumeSet vs, SceneGPU sc, FrameScratch fs, unsign
 }
 
 void launch_frame_stats(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, unsigned long long* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)out, 0u, (int64_t)4);
-  hipLaunchKernelGGL(k_frame_stats, dim3(256), dim3(256), 0, s, vs, sc, fs, out);
+  irf_launch(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)out, 0u, (int64_t)4);
+  irf_launch(k_frame_stats, dim3(256), dim3(256), 0, s, vs, sc, fs, out);
 }
 
 // ---- debug records
@@ -616,19 +616,23 @@ static inline unsigned grid_for(int64_t items, int grid) {
 
 void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s) {
   if (fs.max_rays == 0) return;
-  hipLaunchKernelGGL(k_trace, dim3(grid_for(fs.max_rays, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs);
+  irf_launch(k_trace, dim3(grid_for(fs.max_rays, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs);
+}
+
+void launch_scan_tasks(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
+  if (fs.max_rays == 0) return;
+  irf_launch(k_scan_tasks, dim3(1), dim3(kScanBlock), 0, s, vs, fs);
 }
 
 void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, hipStream_t s) {
   if (fs.max_rays == 0 || n_lights == 0) return;
-  hipLaunchKernelGGL(k_scan_tasks, dim3(1), dim3(kScanBlock), 0, s, vs, fs);
   int64_t cap = (fs.max_rays + 63) / 64 * 64 * n_lights;
-  hipLaunchKernelGGL(k_shadow, dim3(grid_for(cap, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs);
+  irf_launch(k_shadow, dim3(grid_for(cap, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs);
 }
 
 void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s) {
   if (fs.max_rays == 0) return;
-  hipLaunchKernelGGL(k_shade, dim3(grid_for(fs.max_rays, grid)), dim3(kTraceBlock), 0, s, vs, sc, fs);
+  irf_launch(k_shade, dim3(grid_for(fs.max_rays, grid)), dim3(kTraceBlock), 0, s, vs, sc, fs);
 }
 
 void launch_classify(const VolumeSet& vs, SceneGPU sc, ObjectBoxes boxes, const float* rotations, int K,
@@ -643,23 +647,23 @@ void launch_classify(const VolumeSet& vs, SceneGPU sc, ObjectBoxes boxes, const 
     A.base[v + 1] = A.base[v] + (int64_t)vs.v[v].n_probes * K * vs.v[v].rays;
     total_probes += vs.v[v].n_probes;
   }
-  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(total_probes, 256)), dim3(256), 0, s, (uint32_t*)back, 0u,
+  irf_launch(k_fill_u32, dim3(blocks_for(total_probes, 256)), dim3(256), 0, s, (uint32_t*)back, 0u,
                      (int64_t)total_probes);
-  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(total_probes, 256)), dim3(256), 0, s, tfront,
+  irf_launch(k_fill_u32, dim3(blocks_for(total_probes, 256)), dim3(256), 0, s, tfront,
                      (uint32_t)0x7f800000u, (int64_t)total_probes);
   if (A.base[vs.n] > 0)
-    hipLaunchKernelGGL(k_classify, dim3(blocks_for(A.base[vs.n], kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s,
+    irf_launch(k_classify, dim3(blocks_for(A.base[vs.n], kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s,
                        vs, sc, A, back, tfront);
   int maxp = 0;
   for (int v = 0; v < vs.n; v++) maxp = vs.v[v].n_probes > maxp ? vs.v[v].n_probes : maxp;
-  hipLaunchKernelGGL(k_classify_finish, dim3(blocks_for(maxp, 256), vs.n), dim3(256), 0, s, vs, boxes, K, back,
+  irf_launch(k_classify_finish, dim3(blocks_for(maxp, 256), vs.n), dim3(256), 0, s, vs, boxes, K, back,
                      tfront);
 }
 
 void launch_records(const VolumeSet& vs, int vol, SceneGPU sc, FrameScratch fs, int n_lights, irf_ray_record* out,
                     int64_t count, hipStream_t s) {
   if (count == 0) return;
-  hipLaunchKernelGGL(k_records, dim3(blocks_for(count, 256)), dim3(256), 0, s, vs, vol, sc, fs, n_lights, out, count);
+  irf_launch(k_records, dim3(blocks_for(count, 256)), dim3(256), 0, s, vs, vol, sc, fs, n_lights, out, count);
 }
 
 }  // namespace irf

@@ -302,7 +302,7 @@ __global__ __launch_bounds__(kQueryBlock) void k_query(VolumeSet vs, const float
 static inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 void launch_set_params(const FrameParams& p, FrameScratch fs, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_params, dim3(1), dim3(64), 0, s, p, fs.params);
+  irf_launch(k_set_params, dim3(1), dim3(64), 0, s, p, fs.params);
 }
 
 const void* set_params_kernel() { return (const void*)k_set_params; }
@@ -310,7 +310,7 @@ const void* set_params_kernel() { return (const void*)k_set_params; }
 void launch_directions(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
   int maxr = 0;
   for (int v = 0; v < vs.n; v++) maxr = vs.v[v].rays > maxr ? vs.v[v].rays : maxr;
-  hipLaunchKernelGGL(k_directions, dim3(nblocks(maxr, 256), vs.n), dim3(256), 0, s, vs, fs);
+  irf_launch(k_directions, dim3(nblocks(maxr, 256), vs.n), dim3(256), 0, s, vs, fs);
 }
 
 void launch_state_compact(const VolumeSet& vs, ObjectBoxes boxes, FrameScratch fs, hipStream_t s) {
@@ -318,19 +318,19 @@ void launch_state_compact(const VolumeSet& vs, ObjectBoxes boxes, FrameScratch f
   A.block_base[0] = 0;
   for (int v = 0; v < vs.n; v++) A.block_base[v + 1] = A.block_base[v] + (vs.v[v].n_probes + kCompactBlock - 1) / kCompactBlock;
   if (A.block_base[vs.n] == 0) return;
-  hipLaunchKernelGGL(k_state_count, dim3(A.block_base[vs.n]), dim3(kCompactBlock), 0, s, vs, boxes, A, fs);
-  hipLaunchKernelGGL(k_state_scatter, dim3(A.block_base[vs.n]), dim3(kCompactBlock), 0, s, vs, A, fs);
+  irf_launch(k_state_count, dim3(A.block_base[vs.n]), dim3(kCompactBlock), 0, s, vs, boxes, A, fs);
+  irf_launch(k_state_scatter, dim3(A.block_base[vs.n]), dim3(kCompactBlock), 0, s, vs, A, fs);
 }
 
 void launch_blend(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
   if (fs.max_slots == 0) return;
-  hipLaunchKernelGGL(k_blend_f32, dim3(fs.max_slots), dim3(kBlendBlock), 0, s, vs, fs);
+  irf_launch(k_blend_f32, dim3(fs.max_slots), dim3(kBlendBlock), 0, s, vs, fs);
 }
 
 void launch_query(const VolumeSet& vs, const float* pos, const float* nrm, const float* view, int64_t n, float* out,
                   hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_query, dim3(nblocks(n, kQueryBlock)), dim3(kQueryBlock), 0, s, vs, pos, nrm, view, n, out);
+  irf_launch(k_query, dim3(nblocks(n, kQueryBlock)), dim3(kQueryBlock), 0, s, vs, pos, nrm, view, n, out);
 }
 
 }  // namespace irf
