@@ -60,7 +60,8 @@ class VolumeStruct(C.Structure):
                 ("rays", C.c_int32), ("alpha_irr", C.c_float), ("alpha_dist", C.c_float),
                 ("cos_power", C.c_float), ("bias", C.c_float), ("dmax", C.c_float), ("cheb_power", C.c_int32),
                 ("irr", C.c_void_p), ("dist", C.c_void_p), ("states", C.c_void_p), ("offsets", C.c_void_p),
-                ("irr_kappa", C.c_void_p), ("dist_kappa", C.c_void_p)]
+                ("irr_kappa", C.c_void_p), ("dist_kappa", C.c_void_p), ("gamma", C.c_float),
+                ("texel_thresholds", C.c_int32)]
 
 
 def _p(a):
@@ -83,6 +84,7 @@ def _declare(L):
     L.orc_sf_direction.argtypes = [i32, i32, vp, dp]
     L.orc_trace_batch.argtypes = [vp, i64, dp, dp, i32, i32, vp]
     L.orc_blend_probe.argtypes = [i32, dp, dp, dp, C.c_double, C.c_double, C.c_double, dp, dp]
+    L.orc_blend_probe_ex.argtypes = [i32, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double, i32, dp, dp]
     L.orc_query_batch.argtypes = [vp, i32, i64, vp, vp, vp, dp, dp]
     L.orc_classify.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
     L.orc_state_step.argtypes = [vp, vp, i32]
@@ -150,6 +152,16 @@ def blend_probe(omega, rgb, d, cos_power, alpha_irr, alpha_dist, irr_tile, dist_
     assert dist_tile.dtype == np.float64 and dist_tile.flags.c_contiguous
     lib().orc_blend_probe(len(d), _p(omega), _p(rgb), _p(d), cos_power, alpha_irr, alpha_dist,
                           _p(irr_tile), _p(dist_tile))
+
+
+def blend_probe_ex(omega, rgb, d, cos_power, alpha_irr, alpha_dist, gamma, thresholds, irr_tile, dist_tile):
+    """blend_probe with the perception encoding exponent (1 = linear) and
+    the per-texel irradiance hysteresis thresholds."""
+    omega, rgb, d = _d(omega), _d(rgb), _d(d)
+    assert irr_tile.dtype == np.float64 and irr_tile.flags.c_contiguous
+    assert dist_tile.dtype == np.float64 and dist_tile.flags.c_contiguous
+    lib().orc_blend_probe_ex(len(d), _p(omega), _p(rgb), _p(d), cos_power, alpha_irr, alpha_dist, float(gamma),
+                             int(bool(thresholds)), _p(irr_tile), _p(dist_tile))
 
 
 class Scene:
@@ -224,6 +236,8 @@ class Volume:
         s.cos_power, s.bias = d.cos_power, d.self_shadow_bias
         s.dmax = d.resolved_max_distance()
         s.cheb_power = d.cheb_power
+        s.gamma = float(getattr(d, "irradiance_gamma", 1.0))
+        s.texel_thresholds = int(bool(getattr(d, "texel_thresholds", False)))
         for arr in (self.irr, self.dist, self.states, self.offsets):
             assert arr.flags.c_contiguous
         s.irr, s.dist, s.states, s.offsets = _p(self.irr), _p(self.dist), _p(self.states), _p(self.offsets)
@@ -295,6 +309,12 @@ def _ptr_array(arrs):
     return a
 
 
+def _linear_only(vols):
+    for v in vols:
+        if getattr(v.desc, "irradiance_gamma", 1.0) != 1.0 or getattr(v.desc, "texel_thresholds", False):
+            raise ValueError("the adjoint covers linear irradiance texels without per-texel thresholds")
+
+
 class _Grads(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("g_irr", "g_dist", "a_irr", "a_dist", "s_irr", "s_dist")]
 
@@ -320,6 +340,7 @@ def query_backward(vols: List[Volume], pos, nrm, view, gout, g_irr, g_dist, a_ir
     """Accumulates dLoss/d(texels) of the query into float64 arrays shaped
     like each volume's irr / dist atlases; optionally the per-texel sum of
     term magnitudes (a_*) and float32 sensitivity (s_*)."""
+    _linear_only(vols)
     pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
     nrm = np.ascontiguousarray(nrm, dtype=np.float64).reshape(-1, 3)
     view = np.ascontiguousarray(view, dtype=np.float64).reshape(-1, 3)
@@ -336,6 +357,7 @@ def update_backward(scene: Scene, prev: List[Volume], R, records, g_new_irr, g_n
     """Backward of one update frame (see orc_update_backward): accumulates
     dLoss/d(input atlases) and dLoss/d(emission); a_new_* are magnitude
     bounds of the upstream gradient (default |g_new|)."""
+    _linear_only(prev)
     R = np.ascontiguousarray(R, dtype=np.float32).reshape(9)
     rec = np.ascontiguousarray(records)
     assert rec.dtype == RECORD_DTYPE

@@ -489,12 +489,30 @@ void orc_sf_direction(int32_t i, int32_t n, const float R[9], double out[3]) {
 void orc_blend_probe(int32_t n, const double* omega, const double* rgb, const double* d,
                      double cos_power, double alpha_irr, double alpha_dist,
                      double* irr, double* dist) {
-  orc_blend_probe_k(n, omega, rgb, NULL, d, cos_power, alpha_irr, alpha_dist, irr, dist, NULL, NULL);
+  orc_blend_probe_k(n, omega, rgb, NULL, d, cos_power, alpha_irr, alpha_dist, 1.0, 0, irr, dist, NULL, NULL);
+}
+
+void orc_blend_probe_ex(int32_t n, const double* omega, const double* rgb, const double* d, double cos_power,
+                        double alpha_irr, double alpha_dist, double gamma, int32_t thresholds, double* irr,
+                        double* dist) {
+  orc_blend_probe_k(n, omega, rgb, NULL, d, cos_power, alpha_irr, alpha_dist, gamma, thresholds, irr, dist, NULL,
+                    NULL);
+}
+
+/* Section "Fast Convergence Heuristics": the irradiance hysteresis of one
+   texel given the largest per-channel change between the new (encoded) value
+   and the stored one: lowered by 0.15 (not below 0) above a change of 0.25,
+   and 0 above 0.8 (the probe is taken to see a new distribution). */
+static double texel_hysteresis(double alpha, double change) {
+  double a = alpha;
+  if (change > 0.25) a = fmax(0.0, a - 0.15);
+  if (change > 0.8) a = 0.0;
+  return a;
 }
 
 void orc_blend_probe_k(int32_t n, const double* omega, const double* rgb, const double* rgb_kappa, const double* d,
-                       double cos_power, double alpha_irr, double alpha_dist, double* irr, double* dist,
-                       double* irr_k, double* dist_k) {
+                       double cos_power, double alpha_irr, double alpha_dist, double gamma, int32_t thresholds,
+                       double* irr, double* dist, double* irr_k, double* dist_k) {
   for (int32_t y = 1; y <= 6; y++)
     for (int32_t x = 1; x <= 6; x++) {
       double nt[3], W = 0, acc[3] = {0, 0, 0};
@@ -504,24 +522,56 @@ void orc_blend_probe_k(int32_t n, const double* omega, const double* rgb, const 
         W += w;
         for (int c = 0; c < 3; c++) acc[c] += w * rgb[3 * r + c];
       }
-      if (W > 0.0)
-        for (int c = 0; c < 3; c++) {
-          double* t = &irr[(y * 8 + x) * 3 + c];
-          double nv = acc[c] / W;
-          if (irr_k) {
-            double kw = 0.0, kr = 0.0;
-            for (int32_t r = 0; r < n; r++) {
-              double cw = dot3(nt, omega + 3 * r);
-              double w = fmax(0.0, cw);
-              if (cw > -8.0 * U32) kw += fabs(rgb[3 * r + c] - nv) * 8.0;
-              if (rgb_kappa) kr += w * rgb_kappa[3 * r + c];
-            }
-            double kn = kw / W + kr / W + 8.0 * fabs(nv);
-            double* kt = &irr_k[(y * 8 + x) * 3 + c];
-            *kt = alpha_irr * (*kt) + (1.0 - alpha_irr) * kn + 4.0 * fabs(*t);
+      if (!(W > 0.0)) continue;
+      double* t = &irr[(y * 8 + x) * 3];
+      double nv[3], enc[3], kn[3], kenc[3];
+      for (int c = 0; c < 3; c++) {
+        nv[c] = acc[c] / W;
+        /* Section "Perception-based exponential encoding": the stored value
+           is the new mean raised to 1/gamma; the hysteresis then blends in
+           the encoded domain */
+        enc[c] = gamma != 1.0 ? pow(fmax(nv[c], 0.0), 1.0 / gamma) : nv[c];
+        if (irr_k) {
+          double kw = 0.0, kr = 0.0;
+          for (int32_t r = 0; r < n; r++) {
+            double cw = dot3(nt, omega + 3 * r);
+            double w = fmax(0.0, cw);
+            if (cw > -8.0 * U32) kw += fabs(rgb[3 * r + c] - nv[c]) * 8.0;
+            if (rgb_kappa) kr += w * rgb_kappa[3 * r + c];
           }
-          *t = alpha_irr * (*t) + (1.0 - alpha_irr) * nv;
+          kn[c] = kw / W + kr / W + 8.0 * fabs(nv[c]);
+          if (gamma != 1.0) {
+            /* the encoded value's range over the linear value's error bound */
+            double e = 8.0 * U32 * kn[c];
+            double hi = pow(fmax(nv[c], 0.0) + e, 1.0 / gamma), lo = pow(fmax(nv[c] - e, 0.0), 1.0 / gamma);
+            kenc[c] = fmax(hi - enc[c], enc[c] - lo) / (8.0 * U32) + 8.0 * enc[c];
+          } else {
+            kenc[c] = kn[c];
+          }
         }
+      }
+      double a = alpha_irr, flip = 0.0;
+      if (thresholds) {
+        double change = 0.0;
+        for (int c = 0; c < 3; c++) change = fmax(change, fabs(enc[c] - t[c]));
+        a = texel_hysteresis(alpha_irr, change);
+        if (irr_k) {
+          /* a float32 evaluation may see the change on the other side of a
+             threshold: the jump between the two outcomes enters the
+             sensitivity */
+          double dc = 0.0;
+          for (int c = 0; c < 3; c++) dc = fmax(dc, 8.0 * U32 * (kenc[c] + irr_k[(y * 8 + x) * 3 + c]) + 4.0 * U32);
+          double a_lo = texel_hysteresis(alpha_irr, change + dc), a_hi = texel_hysteresis(alpha_irr, change - dc);
+          flip = a_hi - a_lo;
+        }
+      }
+      for (int c = 0; c < 3; c++) {
+        if (irr_k) {
+          double* kt = &irr_k[(y * 8 + x) * 3 + c];
+          *kt = a * (*kt) + (1.0 - a) * kenc[c] + 4.0 * fabs(t[c]) + flip * fabs(t[c] - enc[c]) / (8.0 * U32);
+        }
+        t[c] = a * t[c] + (1.0 - a) * enc[c];
+      }
     }
   for (int32_t y = 1; y <= 14; y++)
     for (int32_t x = 1; x <= 14; x++) {
@@ -684,15 +734,30 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
     orc_sample_tile(V->irr + q * 8 * 8 * 3, 8, 3, n, e[used]);
     if (V->irr_kappa) orc_sample_tile(V->irr_kappa + q * 8 * 8 * 3, 8, 3, n, ek[used]);
     else ek[used][0] = ek[used][1] = ek[used][2] = 0.0;
+    if (V->gamma != 1.0f) {
+      /* Section "Perception-based exponential encoding": each probe's sample
+         is decoded to the power gamma/2, so the cage blend runs on a
+         gamma-2 curve; the normalised result is squared back below */
+      double h = 0.5 * (double)V->gamma;
+      for (int k = 0; k < 3; k++) {
+        double ev = fmax(e[used][k], 0.0);
+        double dec = pow(ev, h);
+        double ee = (16.0 * fabs(e[used][k]) + ek[used][k]) * U32;
+        double hi = pow(ev + ee, h), lo = pow(fmax(ev - ee, 0.0), h);
+        ek[used][k] = fmax(hi - dec, dec - lo) / U32;
+        e[used][k] = dec;
+      }
+    }
     W += w[used];
     used++;
   }
   for (int c = 0; c < 3; c++) { out[c] = 0.0; kap[c] = 0.0; }
   if (ncage) *ncage = 0;
+  const int sq = V->gamma != 1.0f;
   if (!(W > 0.0)) {
     /* no visible probe: float32 may find tiny positive weights */
     for (int i = 0; i < used; i++)
-      for (int c = 0; c < 3; c++) kap[c] = fmax(kap[c], fabs(e[i][c]) / U32);
+      for (int c = 0; c < 3; c++) kap[c] = fmax(kap[c], (sq ? e[i][c] * e[i][c] : fabs(e[i][c])) / U32);
     return;
   }
   for (int i = 0; i < used; i++)
@@ -706,6 +771,11 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
     }
     if (w[i] > 0.0 && cage && ncage && *ncage < 8) cage[(*ncage)++] = ids[i];
   }
+  if (sq)
+    for (int c = 0; c < 3; c++) {
+      kap[c] = 2.0 * fabs(out[c]) * kap[c] + 8.0 * out[c] * out[c];
+      out[c] = out[c] * out[c];
+    }
 }
 
 /* Section "Multiple Probe Volumes": volumes are visited from most to least
@@ -1024,7 +1094,8 @@ int64_t orc_update_frame(const orc_scene* s, const orc_lights* L, orc_volume* vo
       }
       int fresh = V->states[q] == ORC_NEWLY_AWAKE || V->states[q] == ORC_NEWLY_VIGILANT;
       orc_blend_probe_k(N, omega, rgb, rk, d, (double)V->cos_power, fresh ? 0.0 : (double)V->alpha_irr,
-                        fresh ? 0.0 : (double)V->alpha_dist, V->irr + q * 192, V->dist + q * 512,
+                        fresh ? 0.0 : (double)V->alpha_dist, (double)V->gamma, V->texel_thresholds,
+                        V->irr + q * 192, V->dist + q * 512,
                         V->irr_kappa ? V->irr_kappa + q * 192 : NULL, V->dist_kappa ? V->dist_kappa + q * 512 : NULL);
       free(rgb);
       free(rk);

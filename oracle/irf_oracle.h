@@ -69,6 +69,8 @@ typedef struct {
   const float* offsets; /* [P][3] or NULL */
   double* irr_kappa;  /* [P][8][8][3] or NULL: float32 sensitivity of each texel (units of u) */
   double* dist_kappa; /* [P][16][16][2] or NULL */
+  float gamma;        /* perception encoding exponent of irradiance texels; 1 = linear */
+  int32_t texel_thresholds; /* per-texel hysteresis thresholds on irradiance: 0 / 1 */
 } orc_volume;
 
 typedef struct {
@@ -122,8 +124,16 @@ void orc_blend_probe(int32_t n, const double* omega, const double* rgb, const do
    (a float32 cosine is off by about 8 u absolute) and rounding; kappa tiles
    blend with the same hysteresis as the texels */
 void orc_blend_probe_k(int32_t n, const double* omega, const double* rgb, const double* rgb_kappa, const double* d,
-                       double cos_power, double alpha_irr, double alpha_dist, double* irr_tile, double* dist_tile,
-                       double* irr_kappa, double* dist_kappa);
+                       double cos_power, double alpha_irr, double alpha_dist, double gamma, int32_t thresholds,
+                       double* irr_tile, double* dist_tile, double* irr_kappa, double* dist_kappa);
+/* the blend with the convergence refinements of the sections on perception
+   encoding and fast convergence: irradiance texels store the new mean raised
+   to 1/gamma (gamma = 1: linear), and with thresholds != 0 the irradiance
+   hysteresis of a texel drops by 0.15 when its largest per-channel change (in
+   stored units) exceeds 0.25 and to 0 when it exceeds 0.8 */
+void orc_blend_probe_ex(int32_t n, const double* omega, const double* rgb, const double* d, double cos_power,
+                        double alpha_irr, double alpha_dist, double gamma, int32_t thresholds, double* irr_tile,
+                        double* dist_tile);
 
 /* ---- query E(X, n, w_o) over cascaded volumes ---- */
 void orc_query(const orc_volume* vols, int32_t nvol, const double X[3], const double n[3],

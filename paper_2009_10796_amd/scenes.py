@@ -141,6 +141,8 @@ class VolumeDesc:
     cheb_power: int = 1
     atlas_f16: bool = False
     blend: str = "f32"           # "f32" | "bf16" | "f16" (matrix cores) | "f32_valu"
+    irradiance_gamma: float = 1.0   # perception encoding exponent (1 = linear texels)
+    texel_thresholds: bool = False  # per-texel irradiance hysteresis thresholds
 
     @property
     def n_probes(self) -> int:
