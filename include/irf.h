@@ -134,7 +134,18 @@ irf_status irf_set_lights(irf_ctx* ctx, const irf_lights_desc* desc);
                      cores, inputs in that precision, float32 accumulation and
                      float32 normalisation by the sum of the stored weights;
                      IRF_BLEND_F32_VALU = vector ALU, one workgroup per probe
-                     with its rays in LDS (the paper's compute-shader shape) */
+                     with its rays in LDS (the paper's compute-shader shape)
+     irradiance_gamma perception encoding of irradiance texels (Section
+                     "Perception-based exponential encoding"): texels store
+                     the new mean to the power 1/gamma and blend in that
+                     encoding; the query raises each probe's sample to
+                     gamma/2, blends, and squares.  0 or 1 = linear texels;
+                     else in [1, 16] (the paper uses 5)
+     texel_thresholds 1 = per-texel irradiance hysteresis (Section "Fast
+                     Convergence Heuristics"): a texel whose largest
+                     per-channel change in stored units exceeds 0.25 blends
+                     with hysteresis lowered by 0.15 (not below 0), above 0.8
+                     with hysteresis 0; distance texels are not affected */
 typedef struct {
   float origin[3];
   float spacing[3];
@@ -148,6 +159,8 @@ typedef struct {
   int32_t cheb_power;
   int32_t atlas_dtype;
   int32_t blend;
+  float irradiance_gamma;
+  int32_t texel_thresholds;
 } irf_volume_desc;
 irf_status irf_create_volume(irf_ctx* ctx, const irf_volume_desc* desc, int32_t* volume_id);
 
@@ -231,7 +244,9 @@ void irf_graph_destroy(irf_graph* graph);
    Gradients are float32 device buffers with the atlas layouts
    (irradiance [P][8][8][4], distance [P][16][16][2]) and accumulate (+=);
    per-volume buffers are passed as a host array of n_volumes device
-   pointers.  Volumes must have float32 atlases. */
+   pointers.  Volumes must have float32 atlases, linear irradiance texels
+   (irradiance_gamma 0 or 1) and no per-texel thresholds
+   (IRF_E_UNSUPPORTED otherwise). */
 
 /* While enabled, each irf_update_probes also saves the frame's input atlases
    and its states after the state step (library memory), for

@@ -592,6 +592,9 @@ irf_status irf_validate_volume_desc(const irf_volume_desc* d) {
   if (d->blend != IRF_BLEND_F32 && d->blend != IRF_BLEND_BF16 && d->blend != IRF_BLEND_F16 &&
       d->blend != IRF_BLEND_F32_VALU)
     return fail(IRF_E_INVALID, "unknown blend %d", d->blend);
+  if (!(d->irradiance_gamma == 0.0f || (d->irradiance_gamma >= 1.0f && d->irradiance_gamma <= 16.0f)))
+    return fail(IRF_E_INVALID, "irradiance_gamma must be 0 (linear) or in [1, 16]");
+  if (d->texel_thresholds != 0 && d->texel_thresholds != 1) return fail(IRF_E_INVALID, "texel_thresholds must be 0 or 1");
   return IRF_OK;
 }
 
@@ -617,6 +620,10 @@ irf_status irf_create_volume(irf_ctx* c, const irf_volume_desc* d, int32_t* volu
   V.alpha_irr = d->hysteresis_irr;
   V.alpha_dist = d->hysteresis_dist;
   V.cos_power = d->cos_power;
+  V.gamma = d->irradiance_gamma == 0.0f ? 1.0f : d->irradiance_gamma;
+  V.inv_gamma = 1.0f / V.gamma;
+  V.half_gamma = 0.5f * V.gamma;
+  V.thresholds = d->texel_thresholds;
   float pi = std::floor(d->cos_power);
   V.cos_power_int = (pi == d->cos_power && pi >= 1.0f && pi <= 64.0f) ? (int32_t)pi : 0;
   V.bias = d->self_shadow_bias;
@@ -900,6 +907,8 @@ static irf_status grad_set(const irf_ctx* c, float* const* irr, float* const* di
   if (!irr || !dist) return fail(IRF_E_INVALID, "NULL gradient array");
   for (int v = 0; v < c->n_vol; v++) {
     if (c->vol[v].atlas_f16) return fail(IRF_E_UNSUPPORTED, "gradients need float32 atlases");
+    if (c->vol[v].gamma != 1.0f || c->vol[v].thresholds)
+      return fail(IRF_E_UNSUPPORTED, "gradients need linear irradiance texels without per-texel thresholds");
     if (!irr[v] || !dist[v]) return fail(IRF_E_INVALID, "NULL gradient buffer for volume %d", v);
     G.irr[v] = irr[v];
     G.dist[v] = dist[v];

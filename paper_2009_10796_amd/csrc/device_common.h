@@ -164,6 +164,39 @@ __device__ __forceinline__ float2 sample_distance(const VolumeGPU& V, int q, flo
 
 __device__ __forceinline__ bool sampled_state(uint8_t s) { return s == IRF_AWAKE || s == IRF_VIGILANT; }
 
+// Section "Perception-based exponential encoding": irradiance texels store the
+// new mean to the power 1/gamma (and blend in that encoding); the query
+// raises each probe's sample to gamma/2, blends on that curve and squares.
+__device__ __forceinline__ float encode_irr(const VolumeGPU& V, float x) {
+  return V.gamma == 1.0f ? x : powf(fmaxf(x, 0.0f), V.inv_gamma);
+}
+
+__device__ __forceinline__ float3 decode_irr_half(const VolumeGPU& V, float3 e) {
+  return f3(powf(fmaxf(e.x, 0.0f), V.half_gamma), powf(fmaxf(e.y, 0.0f), V.half_gamma),
+            powf(fmaxf(e.z, 0.0f), V.half_gamma));
+}
+
+// Section "Fast Convergence Heuristics": the irradiance hysteresis of one
+// texel from the largest per-channel change in stored units between the new
+// (encoded) value and the stored one -- lowered by 0.15 (not below 0) above
+// 0.25, and 0 above 0.8.
+__device__ __forceinline__ float texel_alpha(const VolumeGPU& V, float alpha, float3 enc, float3 old) {
+  if (!V.thresholds) return alpha;
+  float change = fmaxf(fabsf(enc.x - old.x), fmaxf(fabsf(enc.y - old.y), fabsf(enc.z - old.z)));
+  float a = alpha;
+  if (change > 0.25f) a = fmaxf(0.0f, a - 0.15f);
+  if (change > 0.8f) a = 0.0f;
+  return a;
+}
+
+// The new stored irradiance texel (Eq. U in the stored encoding) from the
+// stored one and the new normalised mean.
+__device__ __forceinline__ float3 irr_texel_update(const VolumeGPU& V, float alpha, float3 old, float3 mean) {
+  float3 e = f3(encode_irr(V, mean.x), encode_irr(V, mean.y), encode_irr(V, mean.z));
+  float a = texel_alpha(V, alpha, e, old);
+  return f3(a * old.x + (1.0f - a) * e.x, a * old.y + (1.0f - a) * e.y, a * old.z + (1.0f - a) * e.z);
+}
+
 // One volume's 8-probe cage (Section "Probe Query"): trilinear x backface x
 // Chebyshev visibility at the point moved by the self-shadow bias (Eq. 1);
 // normalised.  Returns false when no probe carries weight.
@@ -207,10 +240,13 @@ __device__ inline float3 volume_query(const VolumeGPU& V, float3 X, float3 n, fl
       }
     }
     float3 e = sample_irradiance(V, q, n);
+    if (V.gamma != 1.0f) e = decode_irr_half(V, e);
     acc = acc + w * e;
     W += w;
   }
-  return W > 0.0f ? (1.0f / W) * acc : f3(0.0f, 0.0f, 0.0f);
+  if (!(W > 0.0f)) return f3(0.0f, 0.0f, 0.0f);
+  float3 r = (1.0f / W) * acc;
+  return V.gamma != 1.0f ? f3(r.x * r.x, r.y * r.y, r.z * r.z) : r;
 }
 
 // Cascaded volumes (Section "Multiple Probe Volumes"): densest first, linear

@@ -55,6 +55,8 @@ struct VolumeGPU {
   int32_t cheb_power;
   int32_t atlas_f16;
   int32_t blend;
+  float gamma, inv_gamma, half_gamma;   // perception encoding of irradiance texels (1 = linear)
+  int32_t thresholds;       // per-texel irradiance hysteresis thresholds (0 / 1)
   int32_t probe_base;       // first global probe id of this volume
   int32_t omega_base;       // first entry of this volume in the direction table
   int64_t weight_base;      // byte offset of this volume's blend weights

@@ -10,12 +10,13 @@
 // texels padded to 208) and the reciprocal row sums of the *stored* weights,
 // so a constant radiance is reproduced exactly whatever the input precision.
 // k_blend_mma multiplies W by the rays of 8 probes at a time:
-//   columns  0..23  R,G,B of probes 0..7 (24..31 zero),
+//   columns  0..7 R, 8..15 G, 16..23 B of probes 0..7 (24..31 zero),
 //   columns 32..39  d, 40..47 d^2 of probes 0..7,
 // with v_mfma_f32_16x16x4_f32 (float32 inputs) or v_mfma_f32_16x16x32_{bf16,f16}
 // (16-bit inputs), float32 accumulation.  The epilogue normalises, applies the
-// per-probe hysteresis (0 for Newly states) and writes each texel and the
-// border cells that repeat it; k_promote then promotes Newly states.
+// hysteresis (0 for Newly states; for irradiance the stored encoding and the
+// per-texel thresholds of the convergence sections) and writes each texel and
+// the border cells that repeat it; k_promote then promotes Newly states.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -153,10 +154,19 @@ __device__ __forceinline__ void store_b(void* lds, int k, int col, float x) {
   }
 }
 
-__device__ __forceinline__ void store_irr(const VolumeGPU& V, int q, int x, int y, int c, float val) {
+// One irradiance texel (RGB, 4th channel 0), float4 or half4.
+__device__ __forceinline__ void store_irr4(const VolumeGPU& V, int q, int x, int y, float3 val) {
   int j = q * kIrrTexels + y * kIrrTile + x;
-  if (V.atlas_f16) ((_Float16*)V.irr)[4 * j + c] = (_Float16)val;
-  else ((float*)V.irr)[4 * j + c] = val;
+  if (V.atlas_f16) {
+    h4 h;
+    h.x = (_Float16)val.x;
+    h.y = (_Float16)val.y;
+    h.z = (_Float16)val.z;
+    h.w = (_Float16)0.0f;
+    ((h4*)V.irr)[j] = h;
+  } else {
+    ((float4*)V.irr)[j] = make_float4(val.x, val.y, val.z, 0.0f);
+  }
 }
 
 __device__ __forceinline__ void store_dist(const VolumeGPU& V, int q, int x, int y, int c, float val) {
@@ -203,9 +213,11 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
     for (int e = threadIdx.x; e < kPB * kn; e += kBlendMmaBlock) {
       int p = e / kn, k = e - p * kn;
       float4 r = p < np ? rays[(int64_t)p * N + kc + k] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      store_b<MODE>(lds, k, 3 * p + 0, r.x);
-      store_b<MODE>(lds, k, 3 * p + 1, r.y);
-      store_b<MODE>(lds, k, 3 * p + 2, r.z);
+      // columns: R of probe p at p, G at 8 + p, B at 16 + p (zeros at 24 + p),
+      // so one lane of the epilogue holds R and B of a texel and G is 8 lanes up
+      store_b<MODE>(lds, k, p, r.x);
+      store_b<MODE>(lds, k, 8 + p, r.y);
+      store_b<MODE>(lds, k, 16 + p, r.z);
       store_b<MODE>(lds, k, 24 + p, 0.0f);
       store_b<MODE>(lds, k, 32 + p, r.w);
       store_b<MODE>(lds, k, 40 + p, r.w * r.w);
@@ -238,58 +250,66 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
 #pragma unroll
   for (int i = 0; i < 2; i++) {
     const int rt = rt_list[i];
+    if (rt < 3) {
+      // irradiance rows: lane%16 = p < 8 holds R (tile 0) and B (tile 1) of
+      // probe p; G comes from 8 lanes up.  The whole texel is updated at once
+      // (encoding, per-texel hysteresis) by that lane.
+      const int p = lane % 16;
+      float gch[4];
 #pragma unroll
-    for (int j = 0; j < 2; j++) {
-      if (j == 1 && rt >= 3) continue;
-      const int col = (rt < 3 ? 16 * j : 32) + lane % 16;
-      int p, c;
-      if (rt < 3) {
-        p = col / 3;
-        c = col % 3;
-        if (col >= 24) continue;
-      } else {
-        p = col - 32 < 8 ? col - 32 : col - 40;
-        c = col - 32 < 8 ? 0 : 1;
-      }
-      if (p >= np) continue;
+      for (int r = 0; r < 4; r++) gch[r] = __shfl_down(acc[i][0][r], 8, 16);
+      if (p >= 8 || p >= np) continue;
       const int q = s_q[p];
       const uint8_t st = s_state[p];
       const bool fresh = st == IRF_NEWLY_AWAKE || st == IRF_NEWLY_VIGILANT;
+      const float a = fresh ? 0.0f : V.alpha_irr;
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int row = rt * 16 + 4 * (lane / 16) + r;
-        const float s = inv[row];
-        if (s == 0.0f) continue;   // padding row, or no ray with positive weight: keep the texel
-        const float nv = acc[i][j][r] * s;
-        if (rt < 3) {
-          const int x = row % 6 + 1, y = row / 6 + 1;
-          const float a = fresh ? 0.0f : V.alpha_irr;
-          const float val = a * load_ch(V, true, q, x, y, c) + (1.0f - a) * nv;
-          store_irr(V, q, x, y, c, val);
-          if (y == 1) store_irr(V, q, 7 - x, 0, c, val);
-          if (y == 6) store_irr(V, q, 7 - x, 7, c, val);
-          if (x == 1) store_irr(V, q, 0, 7 - y, c, val);
-          if (x == 6) store_irr(V, q, 7, 7 - y, c, val);
-          if (x == 6 && y == 6) store_irr(V, q, 0, 0, c, val);
-          if (x == 1 && y == 6) store_irr(V, q, 7, 0, c, val);
-          if (x == 6 && y == 1) store_irr(V, q, 0, 7, c, val);
-          if (x == 1 && y == 1) store_irr(V, q, 7, 7, c, val);
-        } else {
-          const int rr = row - kIrrRows;
-          const int x = rr % 14 + 1, y = rr / 14 + 1;
-          const float a = fresh ? 0.0f : V.alpha_dist;
-          const float val = a * load_ch(V, false, q, x, y, c) + (1.0f - a) * nv;
-          store_dist(V, q, x, y, c, val);
-          if (y == 1) store_dist(V, q, 15 - x, 0, c, val);
-          if (y == 14) store_dist(V, q, 15 - x, 15, c, val);
-          if (x == 1) store_dist(V, q, 0, 15 - y, c, val);
-          if (x == 14) store_dist(V, q, 15, 15 - y, c, val);
-          if (x == 14 && y == 14) store_dist(V, q, 0, 0, c, val);
-          if (x == 1 && y == 14) store_dist(V, q, 15, 0, c, val);
-          if (x == 14 && y == 1) store_dist(V, q, 0, 15, c, val);
-          if (x == 1 && y == 1) store_dist(V, q, 15, 15, c, val);
-        }
+        const float sc = inv[row];
+        if (sc == 0.0f) continue;   // padding row, or no ray with positive weight: keep the texel
+        const int x = row % 6 + 1, y = row / 6 + 1;
+        const float3 old = load_irr(V, q * kIrrTexels + y * kIrrTile + x);
+        const float3 val = irr_texel_update(V, a, old, f3(acc[i][0][r] * sc, gch[r] * sc, acc[i][1][r] * sc));
+        store_irr4(V, q, x, y, val);
+        if (y == 1) store_irr4(V, q, 7 - x, 0, val);
+        if (y == 6) store_irr4(V, q, 7 - x, 7, val);
+        if (x == 1) store_irr4(V, q, 0, 7 - y, val);
+        if (x == 6) store_irr4(V, q, 7, 7 - y, val);
+        if (x == 6 && y == 6) store_irr4(V, q, 0, 0, val);
+        if (x == 1 && y == 6) store_irr4(V, q, 7, 0, val);
+        if (x == 6 && y == 1) store_irr4(V, q, 0, 7, val);
+        if (x == 1 && y == 1) store_irr4(V, q, 7, 7, val);
       }
+      continue;
+    }
+    // distance rows: one column tile, d of probe p at 32 + p, d^2 at 40 + p
+    const int col = 32 + lane % 16;
+    const int p = col - 32 < 8 ? col - 32 : col - 40;
+    const int c = col - 32 < 8 ? 0 : 1;
+    if (p >= np) continue;
+    const int q = s_q[p];
+    const uint8_t st = s_state[p];
+    const bool fresh = st == IRF_NEWLY_AWAKE || st == IRF_NEWLY_VIGILANT;
+    const float a = fresh ? 0.0f : V.alpha_dist;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int row = rt * 16 + 4 * (lane / 16) + r;
+      const float sc = inv[row];
+      if (sc == 0.0f) continue;
+      const float nv = acc[i][0][r] * sc;
+      const int rr = row - kIrrRows;
+      const int x = rr % 14 + 1, y = rr / 14 + 1;
+      const float val = a * load_ch(V, false, q, x, y, c) + (1.0f - a) * nv;
+      store_dist(V, q, x, y, c, val);
+      if (y == 1) store_dist(V, q, 15 - x, 0, c, val);
+      if (y == 14) store_dist(V, q, 15 - x, 15, c, val);
+      if (x == 1) store_dist(V, q, 0, 15 - y, c, val);
+      if (x == 14) store_dist(V, q, 15, 15 - y, c, val);
+      if (x == 14 && y == 14) store_dist(V, q, 0, 0, c, val);
+      if (x == 1 && y == 14) store_dist(V, q, 15, 0, c, val);
+      if (x == 14 && y == 1) store_dist(V, q, 0, 15, c, val);
+      if (x == 1 && y == 1) store_dist(V, q, 15, 15, c, val);
     }
   }
   // Newly states are promoted by k_promote once every workgroup has read them.

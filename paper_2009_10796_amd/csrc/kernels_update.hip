@@ -258,8 +258,7 @@ __global__ __launch_bounds__(kBlendBlock) void k_blend_f32(VolumeSet vs, FrameSc
       int idx = q * kIrrTexels + y * kIrrTile + x;
       float3 old = load_irr(V, idx);
       float iw = 1.0f / W;
-      float3 val = f3(a * old.x + (1.0f - a) * (acc.x * iw), a * old.y + (1.0f - a) * (acc.y * iw),
-                      a * old.z + (1.0f - a) * (acc.z * iw));
+      float3 val = irr_texel_update(V, a, old, f3(acc.x * iw, acc.y * iw, acc.z * iw));
       store_with_border<kIrrTile>(x, y, [&](int xx, int yy) {
         int j = q * kIrrTexels + yy * kIrrTile + xx;
         if (V.atlas_f16) {

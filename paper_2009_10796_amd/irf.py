@@ -46,7 +46,8 @@ class VolumeDescC(C.Structure):
     _fields_ = [("origin", C.c_float * 3), ("spacing", C.c_float * 3), ("counts", C.c_int32 * 3),
                 ("rays_per_probe", C.c_int32), ("hysteresis_irr", C.c_float), ("hysteresis_dist", C.c_float),
                 ("cos_power", C.c_float), ("self_shadow_bias", C.c_float), ("max_distance", C.c_float),
-                ("cheb_power", C.c_int32), ("atlas_dtype", C.c_int32), ("blend", C.c_int32)]
+                ("cheb_power", C.c_int32), ("atlas_dtype", C.c_int32), ("blend", C.c_int32),
+                ("irradiance_gamma", C.c_float), ("texel_thresholds", C.c_int32)]
 
 
 class BufferSizes(C.Structure):
@@ -156,6 +157,8 @@ def volume_desc(desc) -> VolumeDescC:
     d.cheb_power = desc.cheb_power
     d.atlas_dtype = ATLAS_F16 if desc.atlas_f16 else ATLAS_F32
     d.blend = BLEND[desc.blend]
+    d.irradiance_gamma = float(getattr(desc, "irradiance_gamma", 1.0))
+    d.texel_thresholds = int(bool(getattr(desc, "texel_thresholds", False)))
     return d
 
 

@@ -42,7 +42,8 @@ def _good():
     ("rays_per_probe", 48), ("rays_per_probe", 0), ("rays_per_probe", 2048),
     ("hysteresis_irr", 1.5), ("hysteresis_dist", -0.1), ("cos_power", 0.0),
     ("self_shadow_bias", -1.0), ("cheb_power", 0), ("cheb_power", 5), ("max_distance", float("inf")),
-    ("origin", (0, float("inf"), 0)),
+    ("origin", (0, float("inf"), 0)), ("irradiance_gamma", 0.5), ("irradiance_gamma", 17.0),
+    ("irradiance_gamma", float("nan")),
 ])
 def test_volume_validation_rejects(field, value):
     d = _good()
@@ -56,6 +57,8 @@ def test_volume_validation_accepts():
     irf.validate_volume_desc(_good())
     d = _good()
     d.rays_per_probe, d.atlas_f16, d.blend = 1024, True, "bf16"
+    irf.validate_volume_desc(d)
+    d.irradiance_gamma, d.texel_thresholds = 5.0, True
     irf.validate_volume_desc(d)
 
 
