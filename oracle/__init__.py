@@ -88,6 +88,7 @@ def _declare(L):
     L.orc_query_batch.argtypes = [vp, i32, i64, vp, vp, vp, dp, dp]
     L.orc_classify.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
     L.orc_state_step.argtypes = [vp, vp, i32]
+    L.orc_optimize_offsets.argtypes = [vp, vp, vp, i32, C.c_double, vp]
     L.orc_update_frame.restype = i64
     L.orc_update_frame.argtypes = [vp, vp, vp, i32, vp, vp, i64]
     L.orc_shade_ray.argtypes = [vp, vp, vp, i32, dp, dp, C.c_double, vp]
@@ -261,6 +262,17 @@ def classify(scene: Scene, vols: List[Volume], rotations: np.ndarray):
     arr = _vol_array(vols)
     lib().orc_classify(scene.handle, arr, len(vols), _p(R), R.shape[0], _p(n_back), _p(n_flag), _p(t_front))
     return n_back, n_flag, t_front
+
+
+def optimize_offsets(scene: Scene, vol: Volume, rotations, offset_limit: float = 0.45) -> np.ndarray:
+    """Probe relocation (Section "Probe Position Adjustment"): one iteration
+    per rotation; updates vol.offsets in place; returns the per-probe
+    ambiguity bits (bit i: iteration i)."""
+    R = np.ascontiguousarray(rotations, dtype=np.float32).reshape(-1, 9)
+    amb = np.zeros(vol.desc.n_probes, dtype=np.int32)
+    arr = _vol_array([vol])
+    lib().orc_optimize_offsets(scene.handle, C.byref(arr[0]), _p(R), len(R), float(offset_limit), _p(amb))
+    return amb
 
 
 def state_step(scene: Scene, vols: List[Volume]):

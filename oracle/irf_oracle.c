@@ -997,6 +997,127 @@ void orc_classify(const orc_scene* s, orc_volume* vols, int32_t nvol, const floa
   }
 }
 
+/* ------------------------------------------------------- probe relocation */
+/* Section "Probe Position Adjustment": iterations of the offset optimizer,
+   each tracing the probe's rays against static geometry under one rotation.
+   A probe that sees more than 25 % backfaces moves along the vector to its
+   closest backface, scaled as far as the per-axis offset limit allows (less
+   1e-3 of the scale); it moves only if that scale exceeds 1, i.e. only if it
+   gets through the backface.  Otherwise, unless the farthest and closest
+   front faces lie within 60 degrees of each other (one surface seen), it
+   moves min(0.2, distance) toward the farthest front face.  Readings of the
+   listing: the direction used in the 60-degree test is the farthest front
+   face's ray direction; a probe for which neither branch applies keeps its
+   offset; a front-face move that would leave the offset limit is not taken;
+   an axis along which the backface vector has no component does not limit
+   the scale.  Offsets are kept in float32 between iterations.  ambiguous[q]
+   (may be NULL) gets bit i set when iteration i's decision for probe q
+   depends on something a float32 tracer may see otherwise (a flagged ray
+   near an extreme, a tie, a count or a dot product at its threshold). */
+static double axis_scale(double cur, double lim, double v) {
+  if (v == 0.0) return INFINITY;
+  return fmax((lim - cur) / v, (-lim - cur) / v);
+}
+
+void orc_optimize_offsets(const orc_scene* s, orc_volume* V, const float* rotations, int32_t iterations,
+                          double offset_limit, int32_t* ambiguous) {
+  int64_t P = vol_probes(V);
+  float* offsets = (float*)V->offsets;
+  const int32_t N = V->rays;
+  double lim[3];
+  for (int a = 0; a < 3; a++) lim[a] = offset_limit * (double)V->spacing[a];
+  if (ambiguous)
+    for (int64_t q = 0; q < P; q++) ambiguous[q] = 0;
+  for (int32_t it = 0; it < iterations; it++) {
+    const float* R = rotations + 9 * it;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < P; q++) {
+      double Pq[3];
+      probe_position(V, q, Pq);
+      int32_t back = 0, n_flag = 0, flag_miss = 0;
+      double tcb = INFINITY, tcf = INFINITY, tff = -1.0;
+      int32_t rcb = -1, rcf = -1, rff = -1;
+      double* ts = (double*)malloc(sizeof(double) * (size_t)N);
+      int8_t* kind = (int8_t*)malloc((size_t)N); /* 0 miss, 1 front, 2 back */
+      int32_t* fl = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+      for (int32_t r = 0; r < N; r++) {
+        double w[3];
+        orc_sf_direction(r, N, R, w);
+        orc_hit h;
+        orc_trace(s, Pq, w, 1, &h);
+        fl[r] = h.flags;
+        if (h.flags) {
+          n_flag++;
+          if (h.tri < 0) flag_miss = 1;
+        }
+        kind[r] = 0;
+        ts[r] = h.t;
+        if (h.tri < 0) continue;
+        double e1[3], e2[3], ng[3];
+        sub3(tri_v(s, h.tri, 1), tri_v(s, h.tri, 0), e1);
+        sub3(tri_v(s, h.tri, 2), tri_v(s, h.tri, 0), e2);
+        cross3(e1, e2, ng);
+        if (dot3(w, ng) > 0.0) {
+          kind[r] = 2;
+          back++;
+          if (h.t < tcb) { tcb = h.t; rcb = r; }
+        } else {
+          kind[r] = 1;
+          if (h.t < tcf) { tcf = h.t; rcf = r; }
+          if (h.t > tff) { tff = h.t; rff = r; }
+        }
+      }
+      double cur[3] = {offsets[3 * q], offsets[3 * q + 1], offsets[3 * q + 2]};
+      double nw[3] = {cur[0], cur[1], cur[2]};
+      int amb = flag_miss;
+      /* the count decides the branch: ambiguous if flagged rays could move it across */
+      if (abs(4 * back - N) <= 4 * n_flag) amb = 1;
+      if (4 * back > N) {
+        /* near-ties or flagged rays at the closest backface */
+        for (int32_t r = 0; r < N; r++)
+          if (kind[r] == 2 && r != rcb && ts[r] <= tcb * (1.0 + 1e-6)) amb = 1;
+          else if (fl[r] && ts[r] <= tcb * (1.0 + 1e-4)) amb = 1;
+        double w[3];
+        orc_sf_direction(rcb, N, R, w);
+        double v[3] = {w[0] * tcb, w[1] * tcb, w[2] * tcb};
+        double sc = INFINITY;
+        for (int a = 0; a < 3; a++) sc = fmin(sc, axis_scale(cur[a], lim[a], v[a]));
+        sc -= 1e-3;
+        if (fabs(sc - 1.0) < 1e-5 * fmax(1.0, fabs(sc))) amb = 1;
+        if (sc > 1.0)
+          for (int a = 0; a < 3; a++) nw[a] = cur[a] + v[a] * sc;
+      } else if (rff >= 0) {
+        for (int32_t r = 0; r < N; r++) {
+          if (kind[r] == 1 && r != rcf && ts[r] <= tcf * (1.0 + 1e-6)) amb = 1;
+          if (kind[r] == 1 && r != rff && ts[r] >= tff * (1.0 - 1e-6)) amb = 1;
+          if (fl[r] && (ts[r] <= tcf * (1.0 + 1e-4) || ts[r] >= tff * (1.0 - 1e-4))) amb = 1;
+        }
+        double wf[3], wc[3];
+        orc_sf_direction(rff, N, R, wf);
+        orc_sf_direction(rcf, N, R, wc);
+        double c = dot3(wf, wc);
+        if (fabs(c - 0.5) < 1e-5) amb = 1;
+        if (!(c > 0.5)) {
+          double step = fmin(0.2, tff), cand[3];
+          int inside = 1;
+          for (int a = 0; a < 3; a++) {
+            cand[a] = cur[a] + step * wf[a];
+            if (fabs(cand[a]) > lim[a]) inside = 0;
+            if (fabs(fabs(cand[a]) - lim[a]) < 1e-6 * lim[a]) amb = 1;
+          }
+          if (inside)
+            for (int a = 0; a < 3; a++) nw[a] = cand[a];
+        }
+      }
+      for (int a = 0; a < 3; a++) offsets[3 * q + a] = (float)nw[a];
+      if (ambiguous && amb) ambiguous[q] |= 1 << it;
+      free(ts);
+      free(kind);
+      free(fl);
+    }
+  }
+}
+
 /* Per-frame state step: sleeping probes near a dynamic object wake (Newly
    Awake); awake probes no longer near any dynamic object go back to sleep. */
 void orc_state_step(const orc_scene* s, orc_volume* vols, int32_t nvol) {

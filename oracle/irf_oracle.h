@@ -152,6 +152,14 @@ void orc_state_step(const orc_scene* s, orc_volume* vols, int32_t nvol);
 int64_t orc_update_frame(const orc_scene* s, const orc_lights* L, orc_volume* vols, int32_t nvol,
                          const float R[9], orc_ray_record* records, int64_t capacity);
 
+/* ---- probe relocation (Section "Probe Position Adjustment") ----
+   iterations rotations [iterations][9]; offsets of V (float32 [P][3]) are
+   updated in place; offset_limit is a fraction of the spacing per axis;
+   ambiguous [P] (or NULL): bit i set when iteration i's decision for the
+   probe depends on something float32 may decide otherwise. */
+void orc_optimize_offsets(const orc_scene* s, orc_volume* V, const float* rotations, int32_t iterations,
+                          double offset_limit, int32_t* ambiguous);
+
 /* ---- adjoint, ray hits and shadow decisions held fixed ----
    Per volume v: g_irr[v] / g_dist[v] are [P][8][8][3] / [P][16][16][2]
    float64 arrays; everything accumulates (+=).  Optional (NULL to skip):
