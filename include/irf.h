@@ -181,7 +181,8 @@ irf_status irf_volume_sizes(const irf_ctx* ctx, int32_t volume, irf_buffer_sizes
 
 /* Binds caller-owned device buffers (16-byte aligned) to a volume.  The
    update reads and writes irradiance, distance and states in place; offsets
-   may be NULL (all zero).  Initial contents are the caller's (zeros and
+   may be NULL (all zero; irf_optimize_probes then refuses), and are written
+   only by irf_optimize_probes.  Initial contents are the caller's (zeros and
    IRF_NEWLY_VIGILANT, or the result of irf_classify). */
 irf_status irf_bind_volume(irf_ctx* ctx, int32_t volume, void* irradiance, void* distance,
                            uint8_t* states, const float* offsets);
@@ -194,6 +195,21 @@ irf_status irf_bind_volume(irf_ctx* ctx, int32_t volume, void* irradiance, void*
    box of a dynamic object grown by one cell plus the self-shadow bias become
    NEWLY_AWAKE.  Writes the bound states of every volume.  Async. */
 irf_status irf_classify(irf_ctx* ctx, const float* rotations, int32_t K, void* stream);
+
+/* Probe relocation (Section "Probe Position Adjustment"), run before
+   irf_classify: `iterations` passes (the paper uses 5), pass i tracing every
+   probe's rays against static triangles from its current position under
+   host rotation rotations[i][9].  A probe seeing more than 25 % backfaces
+   moves along the vector to its closest backface, scaled as far as the
+   offset limit allows less 1e-3 of the scale, if that scale exceeds 1 (it
+   gets through); otherwise, unless its farthest and closest front faces lie
+   within 60 degrees, it steps min(0.2, distance) toward the farthest front
+   face, if that stays within the limit; else it keeps its offset.
+   offset_limit in (0, 0.5] is a fraction of the spacing per axis.  Reads and
+   writes the bound offsets of every volume (IRF_E_STATE if a volume has
+   none).  Async. */
+irf_status irf_optimize_probes(irf_ctx* ctx, const float* rotations, int32_t iterations, float offset_limit,
+                               void* stream);
 
 /* One update frame for all bound volumes (Section "Probe Update"): state
    step (dynamic-object wake/sleep), compaction of active probes (Newly

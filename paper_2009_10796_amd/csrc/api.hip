@@ -99,6 +99,7 @@ struct irf_ctx {
   DevBuf<float> inv_row_sum;
   DevBuf<int32_t> class_back;
   DevBuf<uint32_t> class_tf;
+  DevBuf<unsigned long long> reloc_keys;
   bool frame_done = false;
   bool diff_frame = false;   // the last frame saved its inputs for the adjoint
   Tuning tune = {0, 0, 0, 0};
@@ -429,6 +430,7 @@ void irf_destroy(irf_ctx* c) {
   c->inv_row_sum.release();
   c->class_back.release();
   c->class_tf.release();
+  c->reloc_keys.release();
   for (auto& r : c->prof_pending) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -690,6 +692,27 @@ irf_status irf_classify(irf_ctx* c, const float* rotations, int32_t K, void* str
   if ((s = c->class_tf.reserve((size_t)P)) != IRF_OK) return s;
   launch_classify(volume_view(c), scene_view(c), boxes_view(c), rotations, K, c->class_back.p, c->class_tf.p,
                   (hipStream_t)stream);
+  return launched();
+}
+
+irf_status irf_optimize_probes(irf_ctx* c, const float* rotations, int32_t iterations, float offset_limit,
+                               void* stream) {
+  if (!c || !rotations) return fail(IRF_E_INVALID, "NULL argument");
+  if (iterations < 1 || iterations > 64) return fail(IRF_E_INVALID, "iterations = %d must be in [1, 64]", iterations);
+  if (!(offset_limit > 0.0f && offset_limit <= 0.5f)) return fail(IRF_E_INVALID, "offset_limit must be in (0, 0.5]");
+  for (int i = 0; i < 9 * iterations; i++)
+    if (!std::isfinite(rotations[i])) return fail(IRF_E_INVALID, "rotation %d is not finite", i / 9);
+  irf_status s = check_ready(c);
+  if (s != IRF_OK) return s;
+  for (int v = 0; v < c->n_vol; v++)
+    if (!c->vol[v].offsets) return fail(IRF_E_STATE, "volume %d has no offsets buffer bound", v);
+  if ((s = set_device(c)) != IRF_OK) return s;
+  int64_t P = total_probes(c);
+  if ((s = c->class_back.reserve((size_t)P)) != IRF_OK) return s;
+  if ((s = c->reloc_keys.reserve((size_t)(3 * P))) != IRF_OK) return s;
+  for (int it = 0; it < iterations; it++)
+    launch_relocate(volume_view(c), scene_view(c), rotations + 9 * it, offset_limit, c->class_back.p,
+                    c->reloc_keys.p, (hipStream_t)stream);
   return launched();
 }
 

@@ -172,6 +172,8 @@ void launch_promote(FrameScratch fs, const VolumeSet& vs, hipStream_t s);
 void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, int grid, hipStream_t s);
 void launch_query(const VolumeSet& vs, const float* pos, const float* nrm, const float* view, int64_t n,
                   float* out, hipStream_t s);
+void launch_relocate(const VolumeSet& vs, SceneGPU sc, const float* rotation, float limit, int32_t* back,
+                     unsigned long long* keys, hipStream_t s);
 void launch_classify(const VolumeSet& vs, SceneGPU sc, ObjectBoxes boxes, const float* rotations, int K,
                      int32_t* back, uint32_t* tfront, hipStream_t s);
 void launch_traversal_stats(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, unsigned long long* out,

@@ -506,6 +506,129 @@ __global__ void k_classify_finish(VolumeSet vs, ObjectBoxes ob, int K, const int
   V.states[q] = st;
 }
 
+// ---- probe relocation (Section "Probe Position Adjustment")
+//
+// One iteration: every probe traces its rays (static geometry, one shared
+// rotation) from its current position; per probe the backface count and
+// three packed keys (t bits << 32 | ray) are reduced with atomics -- the
+// closest backface and the closest front face (minimum), the farthest front
+// face (maximum, ray stored complemented so ties keep the lowest ray) -- and
+// k_reloc_finish moves the probe.
+
+struct RelocArgs {
+  float R[9];
+  float limit;                          // offset limit, fraction of the spacing per axis
+  int64_t base[IRF_MAX_VOLUMES + 1];    // ray ranges per volume: P * N
+};
+
+__global__ void k_reloc_init(int32_t* back, unsigned long long* keys, int64_t P) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P; q += (int64_t)gridDim.x * blockDim.x) {
+    back[q] = 0;
+    keys[3 * q + 0] = ~0ull;
+    keys[3 * q + 1] = ~0ull;
+    keys[3 * q + 2] = 0ull;
+  }
+}
+
+__global__ __launch_bounds__(kTraceBlock) void k_reloc_rays(VolumeSet vs, SceneGPU sc, RelocArgs A, int32_t* back,
+                                                            unsigned long long* keys) {
+  int64_t gid = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
+  if (gid >= A.base[vs.n]) return;
+  int v = 0;
+  while (v + 1 < vs.n && gid >= A.base[v + 1]) v++;
+  const VolumeGPU& V = vs.v[v];
+  int64_t local = gid - A.base[v];
+  int q = (int)(local / V.rays), r = (int)(local - (int64_t)q * V.rays);
+  float3 w = sf_direction(r, V.rays, A.R);
+  Ray ray = make_ray(probe_position(V, q), w);
+  float t;
+  int tri = traverse<false, true>(sc, ray, INFINITY, t, dyn_stack + threadIdx.x, kTraceBlock);
+  if (tri < 0) return;
+  const int64_t gq = V.probe_base + q;
+  const unsigned long long tk = (unsigned long long)__float_as_uint(t) << 32;
+  if (dot(w, tri_normal(sc, tri)) > 0.0f) {
+    atomicAdd(&back[gq], 1);
+    atomicMin(&keys[3 * gq + 0], tk | (unsigned)r);
+  } else {
+    atomicMin(&keys[3 * gq + 1], tk | (unsigned)r);
+    atomicMax(&keys[3 * gq + 2], tk | (0xffffffffu - (unsigned)r));
+  }
+}
+
+// Largest scale along v before an axis leaves [-lim, lim]; an axis with no
+// component along v does not limit it.
+__device__ __forceinline__ float axis_scale(float cur, float lim, float v) {
+  if (v == 0.0f) return INFINITY;
+  return fmaxf((lim - cur) / v, (-lim - cur) / v);
+}
+
+__global__ void k_reloc_finish(VolumeSet vs, RelocArgs A, const int32_t* back, const unsigned long long* keys) {
+  int v = blockIdx.y;
+  if (v >= vs.n) return;
+  const VolumeGPU& V = vs.v[v];
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= V.n_probes) return;
+  const int64_t gq = V.probe_base + q;
+  float* off = const_cast<float*>(V.offsets) + 3 * q;
+  const float cur[3] = {off[0], off[1], off[2]};
+  float lim[3];
+  for (int a = 0; a < 3; a++) lim[a] = A.limit * V.spacing[a];
+  const int N = V.rays;
+  float nw[3] = {cur[0], cur[1], cur[2]};
+  if (4 * back[gq] > N) {
+    // more than 25 % backfaces: through the closest backface, as far as the
+    // offset limit allows (less 1e-3 of the scale), only if that gets through
+    const unsigned long long k = keys[3 * gq + 0];
+    const float t = __uint_as_float((unsigned)(k >> 32));
+    const float3 w = sf_direction((int)(k & 0xffffffffu), N, A.R);
+    const float vv[3] = {t * w.x, t * w.y, t * w.z};
+    float sc = INFINITY;
+    for (int a = 0; a < 3; a++) sc = fminf(sc, axis_scale(cur[a], lim[a], vv[a]));
+    sc -= 1e-3f;
+    if (sc > 1.0f)
+      for (int a = 0; a < 3; a++) nw[a] = cur[a] + vv[a] * sc;
+  } else if (keys[3 * gq + 2] != 0ull) {
+    // a bounded step toward the farthest front face, unless it lies within
+    // 60 degrees of the closest one (the probe sees one surface)
+    const unsigned long long kf = keys[3 * gq + 2], kc = keys[3 * gq + 1];
+    const float tf = __uint_as_float((unsigned)(kf >> 32));
+    const float3 wf = sf_direction((int)(0xffffffffu - (unsigned)(kf & 0xffffffffu)), N, A.R);
+    const float3 wc = sf_direction((int)(kc & 0xffffffffu), N, A.R);
+    if (!(dot(wf, wc) > 0.5f)) {
+      const float step = fminf(0.2f, tf);
+      const float cand[3] = {cur[0] + step * wf.x, cur[1] + step * wf.y, cur[2] + step * wf.z};
+      bool inside = true;
+      for (int a = 0; a < 3; a++) inside = inside && fabsf(cand[a]) <= lim[a];
+      if (inside)
+        for (int a = 0; a < 3; a++) nw[a] = cand[a];
+    }
+  }
+  off[0] = nw[0];
+  off[1] = nw[1];
+  off[2] = nw[2];
+}
+
+void launch_relocate(const VolumeSet& vs, SceneGPU sc, const float* rotation, float limit, int32_t* back,
+                     unsigned long long* keys, hipStream_t s) {
+  RelocArgs A;
+  for (int i = 0; i < 9; i++) A.R[i] = rotation[i];
+  A.limit = limit;
+  A.base[0] = 0;
+  int64_t P = 0;
+  int maxp = 0;
+  for (int v = 0; v < vs.n; v++) {
+    A.base[v + 1] = A.base[v] + (int64_t)vs.v[v].n_probes * vs.v[v].rays;
+    P += vs.v[v].n_probes;
+    maxp = vs.v[v].n_probes > maxp ? vs.v[v].n_probes : maxp;
+  }
+  if (P == 0) return;
+  irf_launch(k_reloc_init, dim3(blocks_for(P, 256)), dim3(256), 0, s, back, keys, P);
+  irf_launch(k_reloc_rays, dim3(blocks_for(A.base[vs.n], kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s, vs,
+             sc, A, back, keys);
+  irf_launch(k_reloc_finish, dim3(blocks_for(maxp, 256), vs.n), dim3(256), 0, s, vs, A, (const int32_t*)back,
+             (const unsigned long long*)keys);
+}
+
 // ---- traversal statistics (on demand): node and triangle fetches of the
 // last frame's probe rays (out[0..1]) and shadow rays (out[2..3])
 

@@ -91,6 +91,7 @@ SIGNATURES = {
     "irf_graph_capture": (C.c_int, [_vp, _vp, C.POINTER(_vp)]),
     "irf_graph_launch": (C.c_int, [_vp, _vp, _vp, _vp]),
     "irf_graph_destroy": (None, [_vp]),
+    "irf_optimize_probes": (C.c_int, [_vp, _vp, _i32, C.c_float, _vp]),
     "irf_set_differentiable": (C.c_int, [_vp, _i32]),
     "irf_set_emission": (C.c_int, [_vp, _vp, _vp]),
     "irf_query_backward": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
@@ -256,6 +257,11 @@ class Context:
     def classify(self, rotations) -> None:
         R = _np(rotations, np.float32).reshape(-1, 9)
         _check(load().irf_classify(self.handle, _ptr(R), R.shape[0], _stream(self.torch)))
+
+    def optimize_probes(self, rotations, offset_limit: float = 0.45) -> None:
+        """Probe relocation: one pass per rotation (run before classify)."""
+        R = _np(rotations, np.float32).reshape(-1, 9)
+        _check(load().irf_optimize_probes(self.handle, _ptr(R), len(R), float(offset_limit), _stream(self.torch)))
 
     def update_probes(self, rotation) -> None:
         R = _np(rotation, np.float32).reshape(9)
