@@ -61,7 +61,8 @@ class VolumeStruct(C.Structure):
                 ("cos_power", C.c_float), ("bias", C.c_float), ("dmax", C.c_float), ("cheb_power", C.c_int32),
                 ("irr", C.c_void_p), ("dist", C.c_void_p), ("states", C.c_void_p), ("offsets", C.c_void_p),
                 ("irr_kappa", C.c_void_p), ("dist_kappa", C.c_void_p), ("gamma", C.c_float),
-                ("texel_thresholds", C.c_int32)]
+                ("texel_thresholds", C.c_int32), ("phase", C.c_int32 * 3), ("tracking", C.c_int32),
+                ("camera", C.c_float * 3)]
 
 
 def _p(a):
@@ -89,6 +90,7 @@ def _declare(L):
     L.orc_classify.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
     L.orc_state_step.argtypes = [vp, vp, i32]
     L.orc_optimize_offsets.argtypes = [vp, vp, vp, i32, C.c_double, vp]
+    L.orc_track_volume.argtypes = [vp, vp, vp, vp, i32, vp]
     L.orc_update_frame.restype = i64
     L.orc_update_frame.argtypes = [vp, vp, vp, i32, vp, vp, i64]
     L.orc_shade_ray.argtypes = [vp, vp, vp, i32, dp, dp, C.c_double, vp]
@@ -224,14 +226,23 @@ class Volume:
         # float32 sensitivity of every texel (units of 2^-24), carried by the blend
         self.irr_kappa = np.zeros((P, 8, 8, 3))
         self.dist_kappa = np.zeros((P, 16, 16, 2))
+        # tracking window (Section "Tracking Windows"): current origin, circular
+        # buffer phase, camera for the blend weight (initially the window centre)
+        self.origin = np.asarray(desc.origin, dtype=np.float32).copy()
+        self.phase = np.zeros(3, dtype=np.int32)
+        self.tracking = bool(getattr(desc, "tracking", False))
+        self.camera = (self.origin + 0.5 * (np.asarray(desc.counts) - 1) * np.asarray(desc.spacing)).astype(np.float32)
 
     def struct(self) -> VolumeStruct:
         d = self.desc
         s = VolumeStruct()
         for a in range(3):
-            s.origin[a] = d.origin[a]
+            s.origin[a] = self.origin[a]
             s.spacing[a] = d.spacing[a]
             s.counts[a] = d.counts[a]
+            s.phase[a] = self.phase[a]
+            s.camera[a] = self.camera[a]
+        s.tracking = int(self.tracking)
         s.rays = d.rays_per_probe
         s.alpha_irr, s.alpha_dist = d.hysteresis_irr, d.hysteresis_dist
         s.cos_power, s.bias = d.cos_power, d.self_shadow_bias
@@ -273,6 +284,22 @@ def optimize_offsets(scene: Scene, vol: Volume, rotations, offset_limit: float =
     arr = _vol_array([vol])
     lib().orc_optimize_offsets(scene.handle, C.byref(arr[0]), _p(R), len(R), float(offset_limit), _p(amb))
     return amb
+
+
+def track_volume(scene: Scene, vol: Volume, camera, rotations) -> np.ndarray:
+    """Tracking window (Section "Tracking Windows"): moves the window toward
+    the camera, reinitialises the planes that enter (classification with the
+    given rotations), stores the camera; returns the shift in cells."""
+    cam = np.ascontiguousarray(camera, dtype=np.float32).reshape(3)
+    R = np.ascontiguousarray(rotations, dtype=np.float32).reshape(-1, 9)
+    arr = _vol_array([vol])
+    shift = np.zeros(3, dtype=np.int32)
+    lib().orc_track_volume(scene.handle, C.byref(arr[0]), _p(cam), _p(R), len(R), _p(shift))
+    for a in range(3):
+        vol.origin[a] = arr[0].origin[a]
+        vol.phase[a] = arr[0].phase[a]
+        vol.camera[a] = arr[0].camera[a]
+    return shift
 
 
 def state_step(scene: Scene, vols: List[Volume]):
@@ -384,6 +411,9 @@ def copy_volumes(vols: List[Volume]) -> List[Volume]:
     out = []
     for v in vols:
         c = Volume(v.desc, states=v.states)
+        c.origin[:] = v.origin
+        c.phase[:] = v.phase
+        c.camera[:] = v.camera
         c.irr[:] = v.irr
         c.dist[:] = v.dist
         c.offsets[:] = v.offsets

@@ -649,13 +649,48 @@ static void footprint_range(const double* tile, int32_t m, int32_t nch, const do
 }
 static int64_t vol_probes(const orc_volume* V) { return (int64_t)V->counts[0] * V->counts[1] * V->counts[2]; }
 
+static int64_t wrap(int64_t i, int64_t n) { return ((i % n) + n) % n; }
+
+/* Logical grid index of storage slot q (Section "Tracking Windows": a
+   tracking volume is a circular buffer; the slot of logical probe i along an
+   axis is (i + phase) mod n). */
+static void logical_index(const orc_volume* V, int64_t q, int64_t g[3]) {
+  int64_t s[3] = {q % V->counts[0], (q / V->counts[0]) % V->counts[1], q / ((int64_t)V->counts[0] * V->counts[1])};
+  for (int a = 0; a < 3; a++) g[a] = wrap(s[a] - V->phase[a], V->counts[a]);
+}
+
+/* Storage slot of logical probe (i, j, k). */
+static int64_t storage_index(const orc_volume* V, int64_t i, int64_t j, int64_t k) {
+  return wrap(i + V->phase[0], V->counts[0]) +
+         (int64_t)V->counts[0] * (wrap(j + V->phase[1], V->counts[1]) + (int64_t)V->counts[1] * wrap(k + V->phase[2], V->counts[2]));
+}
+
 static void probe_position(const orc_volume* V, int64_t q, double P[3]) {
-  int64_t i = q % V->counts[0], j = (q / V->counts[0]) % V->counts[1], k = q / ((int64_t)V->counts[0] * V->counts[1]);
-  int64_t g[3] = {i, j, k};
+  int64_t g[3];
+  logical_index(V, q, g);
   for (int a = 0; a < 3; a++) {
     P[a] = (double)V->origin[a] + (double)g[a] * (double)V->spacing[a];
     if (V->offsets) P[a] += (double)V->offsets[q * 3 + a];
   }
+}
+
+/* Section "Multiple Probe Volumes": a volume's weight falls linearly from 1
+   to 0 over its last grid cell along each axis (product over axes).  For a
+   volume that tracks the camera the transition region is tightened by one
+   cell and centred on the camera. */
+static double volume_weight(const orc_volume* V, const double X[3]) {
+  double wv = 1.0;
+  for (int a = 0; a < 3; a++) {
+    double sp = (double)V->spacing[a];
+    if (V->tracking) {
+      double h = 0.5 * (double)(V->counts[a] - 1) - 1.0;
+      wv *= clampd(h - fabs(X[a] - (double)V->camera[a]) / sp, 0.0, 1.0);
+    } else {
+      double u = (X[a] - (double)V->origin[a]) / sp;
+      wv *= clampd(fmin(u, (double)(V->counts[a] - 1) - u), 0.0, 1.0);
+    }
+  }
+  return wv;
 }
 
 static int sampled_state(uint8_t s) { return s == ORC_AWAKE || s == ORC_VIGILANT; }
@@ -685,7 +720,7 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
   int used = 0;
   for (int c = 0; c < 8; c++) {
     int cb[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
-    int64_t q = (g[0] + cb[0]) + (int64_t)V->counts[0] * ((g[1] + cb[1]) + (int64_t)V->counts[1] * (g[2] + cb[2]));
+    int64_t q = storage_index(V, g[0] + cb[0], g[1] + cb[1], g[2] + cb[2]);
     if (!sampled_state(V->states[q])) continue;
     double wt = 1.0;
     for (int a = 0; a < 3; a++) wt *= cb[a] ? f[a] : 1.0 - f[a];
@@ -791,11 +826,7 @@ void orc_query(const orc_volume* vols, int32_t nvol, const double X[3], const do
   for (int32_t v = 0; v < nvol; v++) {
     const orc_volume* V = &vols[v];
     if (Wt >= 1.0) break;
-    double wv = 1.0;
-    for (int a = 0; a < 3; a++) {
-      double u = (X[a] - (double)V->origin[a]) / (double)V->spacing[a];
-      wv *= clampd(fmin(u, (double)(V->counts[a] - 1) - u), 0.0, 1.0);
-    }
+    double wv = volume_weight(V, X);
     double wuse = (v == nvol - 1) ? 1.0 - Wt : fmin(wv, 1.0 - Wt);
     if (wuse > 0.0) {
       double ev[3], kv[3];
@@ -950,6 +981,42 @@ static int inside_any(const orc_scene* s, const double* lo, const double* hi, co
    it Newly Vigilant, otherwise it sleeps; sleeping probes inside the box of
    a dynamic object (grown by one cell and the self-shadow bias) become Newly
    Awake. */
+/* One probe's classification (steps 1-2): K x N distance-only rays against
+   static triangles from its position. */
+static uint8_t classify_probe(const orc_scene* s, const orc_volume* V, int64_t q, const float* rotations, int32_t K,
+                              const double* lo, const double* hi, int32_t* n_back, int32_t* n_flagged,
+                              double* t_front) {
+  double smax = fmax((double)V->spacing[0], fmax((double)V->spacing[1], (double)V->spacing[2]));
+  double Pq[3];
+  probe_position(V, q, Pq);
+  int32_t back = 0, flagged = 0;
+  double tf = INFINITY;
+  for (int32_t k = 0; k < K; k++)
+    for (int32_t r = 0; r < V->rays; r++) {
+      double w[3];
+      orc_sf_direction(r, V->rays, rotations + 9 * k, w);
+      orc_hit h;
+      orc_trace(s, Pq, w, 1, &h);
+      if (h.flags) flagged++;
+      if (h.tri < 0) continue;
+      double e1[3], e2[3], ng[3];
+      sub3(tri_v(s, h.tri, 1), tri_v(s, h.tri, 0), e1);
+      sub3(tri_v(s, h.tri, 2), tri_v(s, h.tri, 0), e2);
+      cross3(e1, e2, ng);
+      if (dot3(w, ng) > 0.0) back++;
+      else if (h.t < tf) tf = h.t;
+    }
+  uint8_t st;
+  if ((double)back / ((double)K * V->rays) > 0.25) st = ORC_OFF;
+  else if (tf < smax) st = ORC_NEWLY_VIGILANT;
+  else st = ORC_SLEEPING;
+  if (st == ORC_SLEEPING && inside_any(s, lo, hi, Pq)) st = ORC_NEWLY_AWAKE;
+  if (n_back) *n_back = back;
+  if (n_flagged) *n_flagged = flagged;
+  if (t_front) *t_front = tf;
+  return st;
+}
+
 void orc_classify(const orc_scene* s, orc_volume* vols, int32_t nvol, const float* rotations,
                   int32_t K, int32_t* n_back, int32_t* n_flagged, double* t_front) {
   int64_t base = 0;
@@ -959,42 +1026,71 @@ void orc_classify(const orc_scene* s, orc_volume* vols, int32_t nvol, const floa
     double* lo = (double*)malloc(sizeof(double) * 3 * (size_t)(s->nobj + 1));
     double* hi = (double*)malloc(sizeof(double) * 3 * (size_t)(s->nobj + 1));
     expanded_object_boxes(s, V, lo, hi);
-    double smax = fmax((double)V->spacing[0], fmax((double)V->spacing[1], (double)V->spacing[2]));
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t q = 0; q < P; q++) {
-      double Pq[3];
-      probe_position(V, q, Pq);
-      int32_t back = 0, flagged = 0;
-      double tf = INFINITY;
-      for (int32_t k = 0; k < K; k++)
-        for (int32_t r = 0; r < V->rays; r++) {
-          double w[3];
-          orc_sf_direction(r, V->rays, rotations + 9 * k, w);
-          orc_hit h;
-          orc_trace(s, Pq, w, 1, &h);
-          if (h.flags) flagged++;
-          if (h.tri < 0) continue;
-          double e1[3], e2[3], ng[3];
-          sub3(tri_v(s, h.tri, 1), tri_v(s, h.tri, 0), e1);
-          sub3(tri_v(s, h.tri, 2), tri_v(s, h.tri, 0), e2);
-          cross3(e1, e2, ng);
-          if (dot3(w, ng) > 0.0) back++;
-          else if (h.t < tf) tf = h.t;
-        }
-      uint8_t st;
-      if ((double)back / ((double)K * V->rays) > 0.25) st = ORC_OFF;
-      else if (tf < smax) st = ORC_NEWLY_VIGILANT;
-      else st = ORC_SLEEPING;
-      if (st == ORC_SLEEPING && inside_any(s, lo, hi, Pq)) st = ORC_NEWLY_AWAKE;
-      V->states[q] = st;
-      if (n_back) n_back[base + q] = back;
-      if (n_flagged) n_flagged[base + q] = flagged;
-      if (t_front) t_front[base + q] = tf;
-    }
+    for (int64_t q = 0; q < P; q++)
+      V->states[q] = classify_probe(s, V, q, rotations, K, lo, hi, n_back ? n_back + base + q : NULL,
+                                    n_flagged ? n_flagged + base + q : NULL, t_front ? t_front + base + q : NULL);
     free(lo);
     free(hi);
     base += P;
   }
+}
+
+/* Section "Tracking Windows": the window follows the camera in whole cells;
+   a plane leaving behind the camera is reused for the plane entering in
+   front (circular buffer), and its probes start over through the state
+   machine (reset texels and offsets, classification). */
+void orc_track_volume(const orc_scene* s, orc_volume* V, const float camera[3], const float* rotations, int32_t K,
+                      int32_t* shift_out) {
+  int64_t lo_new[3], hi_new[3];
+  int32_t shift[3];
+  for (int a = 0; a < 3; a++) {
+    double sp = (double)V->spacing[a];
+    double center = (double)V->origin[a] + 0.5 * (double)(V->counts[a] - 1) * sp;
+    double d = (double)camera[a] - center;
+    int32_t k = 0;
+    while (d > sp) {
+      k++;
+      d -= sp;
+    }
+    while (d < -sp) {
+      k--;
+      d += sp;
+    }
+    shift[a] = k;
+    V->origin[a] = (float)((double)V->origin[a] + (double)k * sp);
+    V->phase[a] = (int32_t)wrap((int64_t)V->phase[a] + k, V->counts[a]);
+    int64_t n = V->counts[a], m = k > 0 ? (k < n ? k : n) : (-k < n ? -k : n);
+    if (k > 0) { lo_new[a] = n - m; hi_new[a] = n - 1; }
+    else if (k < 0) { lo_new[a] = 0; hi_new[a] = m - 1; }
+    else { lo_new[a] = 1; hi_new[a] = 0; }   /* empty */
+    V->camera[a] = camera[a];
+  }
+  if (shift_out)
+    for (int a = 0; a < 3; a++) shift_out[a] = shift[a];
+  double* blo = (double*)malloc(sizeof(double) * 3 * (size_t)(s->nobj + 1));
+  double* bhi = (double*)malloc(sizeof(double) * 3 * (size_t)(s->nobj + 1));
+  expanded_object_boxes(s, V, blo, bhi);
+  int64_t P = vol_probes(V);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t q = 0; q < P; q++) {
+    int64_t g[3];
+    logical_index(V, q, g);
+    int fresh = 0;
+    for (int a = 0; a < 3; a++) fresh |= g[a] >= lo_new[a] && g[a] <= hi_new[a];
+    if (!fresh) continue;
+    for (int i = 0; i < 192; i++) V->irr[q * 192 + i] = 0.0;
+    for (int i = 0; i < 512; i++) V->dist[q * 512 + i] = 0.0;
+    if (V->irr_kappa)
+      for (int i = 0; i < 192; i++) V->irr_kappa[q * 192 + i] = 0.0;
+    if (V->dist_kappa)
+      for (int i = 0; i < 512; i++) V->dist_kappa[q * 512 + i] = 0.0;
+    if (V->offsets)
+      for (int a = 0; a < 3; a++) ((float*)V->offsets)[q * 3 + a] = 0.0f;
+    V->states[q] = classify_probe(s, V, q, rotations, K, blo, bhi, NULL, NULL, NULL);
+  }
+  free(blo);
+  free(bhi);
 }
 
 /* ------------------------------------------------------- probe relocation */
@@ -1353,7 +1449,7 @@ static void volume_query_terms(const orc_volume* V, int32_t vol, const double X[
   double W = 0.0;
   for (int c = 0; c < 8; c++) {
     int cb[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
-    int64_t q = (gi[0] + cb[0]) + (int64_t)V->counts[0] * ((gi[1] + cb[1]) + (int64_t)V->counts[1] * (gi[2] + cb[2]));
+    int64_t q = storage_index(V, gi[0] + cb[0], gi[1] + cb[1], gi[2] + cb[2]);
     if (!sampled_state(V->states[q])) continue;
     double wt = 1.0;
     for (int a = 0; a < 3; a++) wt *= cb[a] ? f[a] : 1.0 - f[a];
@@ -1452,11 +1548,7 @@ static void query_terms(const orc_volume* vols, int32_t nvol, const double X[3],
   for (int32_t v = 0; v < nvol; v++) {
     const orc_volume* V = &vols[v];
     if (Wt >= 1.0) break;
-    double wv = 1.0;
-    for (int a = 0; a < 3; a++) {
-      double u = (X[a] - (double)V->origin[a]) / (double)V->spacing[a];
-      wv *= clampd(fmin(u, (double)(V->counts[a] - 1) - u), 0.0, 1.0);
-    }
+    double wv = volume_weight(V, X);
     double wuse = (v == nvol - 1) ? 1.0 - Wt : fmin(wv, 1.0 - Wt);
     if (wuse > 0.0) {
       double g[3] = {wuse * gout[0], wuse * gout[1], wuse * gout[2]};

@@ -71,6 +71,9 @@ typedef struct {
   double* dist_kappa; /* [P][16][16][2] or NULL */
   float gamma;        /* perception encoding exponent of irradiance texels; 1 = linear */
   int32_t texel_thresholds; /* per-texel hysteresis thresholds on irradiance: 0 / 1 */
+  int32_t phase[3];   /* tracking window: storage slot of logical probe i is (i + phase) mod n */
+  int32_t tracking;   /* 1: the volume tracks the camera (window + camera-centred blend weight) */
+  float camera[3];    /* camera position for the blend weight of a tracking volume */
 } orc_volume;
 
 typedef struct {
@@ -151,6 +154,16 @@ void orc_state_step(const orc_scene* s, orc_volume* vols, int32_t nvol);
    volume in order, per active probe in index order, per ray, one record ---- */
 int64_t orc_update_frame(const orc_scene* s, const orc_lights* L, orc_volume* vols, int32_t nvol,
                          const float R[9], orc_ray_record* records, int64_t capacity);
+
+/* ---- tracking window (Section "Tracking Windows") ----
+   Moves V's window toward the camera: along each axis, while the camera is
+   more than one spacing from the window centre, the window shifts one cell
+   toward it; the plane left behind is reused (circular buffer) for the new
+   plane in front, whose probes are reset (zero texels and offsets) and
+   classified with the K rotations as in orc_classify.  Stores the camera for
+   the blend weight.  shift (int32[3], may be NULL) receives the cells moved. */
+void orc_track_volume(const orc_scene* s, orc_volume* V, const float camera[3], const float* rotations, int32_t K,
+                      int32_t* shift);
 
 /* ---- probe relocation (Section "Probe Position Adjustment") ----
    iterations rotations [iterations][9]; offsets of V (float32 [P][3]) are

@@ -143,6 +143,7 @@ class VolumeDesc:
     blend: str = "f32"           # "f32" | "bf16" | "f16" (matrix cores) | "f32_valu"
     irradiance_gamma: float = 1.0   # perception encoding exponent (1 = linear texels)
     texel_thresholds: bool = False  # per-texel irradiance hysteresis thresholds
+    tracking: bool = False       # window that follows the camera, camera-centred blend weight
 
     @property
     def n_probes(self) -> int:
