@@ -145,7 +145,13 @@ irf_status irf_set_lights(irf_ctx* ctx, const irf_lights_desc* desc);
                      Convergence Heuristics"): a texel whose largest
                      per-channel change in stored units exceeds 0.25 blends
                      with hysteresis lowered by 0.15 (not below 0), above 0.8
-                     with hysteresis 0; distance texels are not affected */
+                     with hysteresis 0; distance texels are not affected
+     tracking        1 = a window that follows the camera (Section "Tracking
+                     Windows"; counts >= 5 per axis): moved with
+                     irf_track_volume, stored as a circular buffer, and
+                     blended with a camera-centred weight (the per-axis ramp
+                     tightened by one cell, Section "Multiple Probe Volumes");
+                     the camera starts at the window centre */
 typedef struct {
   float origin[3];
   float spacing[3];
@@ -161,6 +167,7 @@ typedef struct {
   int32_t blend;
   float irradiance_gamma;
   int32_t texel_thresholds;
+  int32_t tracking;
 } irf_volume_desc;
 irf_status irf_create_volume(irf_ctx* ctx, const irf_volume_desc* desc, int32_t* volume_id);
 
@@ -195,6 +202,23 @@ irf_status irf_bind_volume(irf_ctx* ctx, int32_t volume, void* irradiance, void*
    box of a dynamic object grown by one cell plus the self-shadow bias become
    NEWLY_AWAKE.  Writes the bound states of every volume.  Async. */
 irf_status irf_classify(irf_ctx* ctx, const float* rotations, int32_t K, void* stream);
+
+/* Tracking window (Section "Tracking Windows") of a volume created with
+   tracking = 1.  Along each axis, while the camera (host float[3]) is more
+   than one spacing from the window centre, the window moves one cell toward
+   it: the plane left behind is reused, in place, for the plane entering in
+   front (circular buffer; the storage slot of logical probe i is
+   (i + phase) mod n, see irf_volume_window).  Entering probes start over:
+   their texels and offsets are zeroed and they are classified as in
+   irf_classify with the K host rotations [K][9].  The camera is kept for the
+   blend weight of queries.  shift (host int32[3], may be NULL) receives the
+   cells moved.  Moving the window changes the volume's origin and phase, so
+   a captured frame graph must be captured again.  Async. */
+irf_status irf_track_volume(irf_ctx* ctx, int32_t volume, const float* camera, const float* rotations, int32_t K,
+                            int32_t* shift, void* stream);
+/* Current window of a volume: origin of logical probe (0,0,0), storage
+   phase per axis, camera position of the blend weight. */
+irf_status irf_volume_window(const irf_ctx* ctx, int32_t volume, float origin[3], int32_t phase[3], float camera[3]);
 
 /* Probe relocation (Section "Probe Position Adjustment"), run before
    irf_classify: `iterations` passes (the paper uses 5), pass i tracing every

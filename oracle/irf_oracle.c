@@ -489,14 +489,14 @@ void orc_sf_direction(int32_t i, int32_t n, const float R[9], double out[3]) {
 void orc_blend_probe(int32_t n, const double* omega, const double* rgb, const double* d,
                      double cos_power, double alpha_irr, double alpha_dist,
                      double* irr, double* dist) {
-  orc_blend_probe_k(n, omega, rgb, NULL, d, cos_power, alpha_irr, alpha_dist, 1.0, 0, irr, dist, NULL, NULL);
+  orc_blend_probe_k(n, omega, rgb, NULL, d, NULL, cos_power, alpha_irr, alpha_dist, 1.0, 0, irr, dist, NULL, NULL);
 }
 
 void orc_blend_probe_ex(int32_t n, const double* omega, const double* rgb, const double* d, double cos_power,
                         double alpha_irr, double alpha_dist, double gamma, int32_t thresholds, double* irr,
                         double* dist) {
-  orc_blend_probe_k(n, omega, rgb, NULL, d, cos_power, alpha_irr, alpha_dist, gamma, thresholds, irr, dist, NULL,
-                    NULL);
+  orc_blend_probe_k(n, omega, rgb, NULL, d, NULL, cos_power, alpha_irr, alpha_dist, gamma, thresholds, irr, dist,
+                    NULL, NULL);
 }
 
 /* Section "Fast Convergence Heuristics": the irradiance hysteresis of one
@@ -511,8 +511,8 @@ static double texel_hysteresis(double alpha, double change) {
 }
 
 void orc_blend_probe_k(int32_t n, const double* omega, const double* rgb, const double* rgb_kappa, const double* d,
-                       double cos_power, double alpha_irr, double alpha_dist, double gamma, int32_t thresholds,
-                       double* irr, double* dist, double* irr_k, double* dist_k) {
+                       const double* d_kappa, double cos_power, double alpha_irr, double alpha_dist, double gamma,
+                       int32_t thresholds, double* irr, double* dist, double* irr_k, double* dist_k) {
   for (int32_t y = 1; y <= 6; y++)
     for (int32_t x = 1; x <= 6; x++) {
       double nt[3], W = 0, acc[3] = {0, 0, 0};
@@ -595,6 +595,12 @@ void orc_blend_probe_k(int32_t n, const double* omega, const double* rgb, const 
             double dw = cos_power * pow(fmax(cw, 8.0 * U32), cos_power - 1.0) * 8.0;
             k1 += fabs(d[r] - n1) * dw;
             k2 += fabs(d[r] * d[r] - n2) * dw;
+            if (d_kappa && cw > 0.0) {
+              /* the ray's own distance error */
+              double w = pow(cw, cos_power);
+              k1 += w * d_kappa[r];
+              k2 += w * 2.0 * fabs(d[r]) * d_kappa[r];
+            }
           }
           double* kt = &dist_k[(y * 16 + x) * 2];
           kt[0] = alpha_dist * kt[0] + (1.0 - alpha_dist) * (k1 / W + 8.0 * fabs(n1)) + 4.0 * fabs(t[0]);
@@ -1238,6 +1244,16 @@ static int active_state(uint8_t s) {
   return s == ORC_NEWLY_AWAKE || s == ORC_NEWLY_VIGILANT || s == ORC_AWAKE || s == ORC_VIGILANT;
 }
 
+/* float32 sensitivity (units of u) of a ray's recorded distance: the hit
+   distance's error along the ray, t (8 / |cos| + 16) (0.2 t for a
+   backface), unless the distance sits at the clamp beyond that error */
+static double ray_distance_kappa(const orc_ray_record* rr, double dmax) {
+  if (rr->tri < 0) return 0.0;
+  double tt = rr->d < dmax ? rr->d : (rr->d == fmin(0.2 * rr->t, dmax) && 0.2 * rr->t < rr->t ? 0.2 * rr->t : rr->t);
+  double err = tt * (8.0 / fmax(rr->cosi, 1e-6) + 16.0);
+  return tt <= dmax * (1.0 + 4.0 * U32) + err * U32 ? err : 0.0;
+}
+
 /* One frame (Section "Probe Update" and the last two steps of the full
    initialization): state step; every active probe traces its rotated
    spherical-Fibonacci rays and shades them against the previous atlases of
@@ -1301,6 +1317,7 @@ int64_t orc_update_frame(const orc_scene* s, const orc_lights* L, orc_volume* vo
       double* rgb = (double*)malloc(sizeof(double) * 3 * (size_t)N);
       double* rk = (double*)malloc(sizeof(double) * 3 * (size_t)N);
       double* d = (double*)malloc(sizeof(double) * (size_t)N);
+      double* dk = (double*)malloc(sizeof(double) * (size_t)N);
       for (int32_t r = 0; r < N; r++) {
         const orc_ray_record* rr = &rec[off + slot[q] * N + r];
         for (int c = 0; c < 3; c++) {
@@ -1308,15 +1325,17 @@ int64_t orc_update_frame(const orc_scene* s, const orc_lights* L, orc_volume* vo
           rk[3 * r + c] = rr->kappa[c];
         }
         d[r] = rr->d;
+        dk[r] = ray_distance_kappa(rr, (double)V->dmax);
       }
       int fresh = V->states[q] == ORC_NEWLY_AWAKE || V->states[q] == ORC_NEWLY_VIGILANT;
-      orc_blend_probe_k(N, omega, rgb, rk, d, (double)V->cos_power, fresh ? 0.0 : (double)V->alpha_irr,
+      orc_blend_probe_k(N, omega, rgb, rk, d, dk, (double)V->cos_power, fresh ? 0.0 : (double)V->alpha_irr,
                         fresh ? 0.0 : (double)V->alpha_dist, (double)V->gamma, V->texel_thresholds,
                         V->irr + q * 192, V->dist + q * 512,
                         V->irr_kappa ? V->irr_kappa + q * 192 : NULL, V->dist_kappa ? V->dist_kappa + q * 512 : NULL);
       free(rgb);
       free(rk);
       free(d);
+      free(dk);
     }
     for (int64_t q = 0; q < P; q++) {
       if (V->states[q] == ORC_NEWLY_AWAKE) V->states[q] = ORC_AWAKE;

@@ -123,12 +123,12 @@ void orc_blend_probe(int32_t n, const double* omega, const double* rgb, const do
                      double cos_power, double alpha_irr, double alpha_dist,
                      double* irr_tile, double* dist_tile);
 /* the same blend, also carrying the float32 sensitivity of every texel
-   (units of u): the rays' own (rgb_kappa, [n][3], may be NULL), the weights'
+   (units of u): the rays' own (rgb_kappa [n][3] and d_kappa [n], may be NULL), the weights'
    (a float32 cosine is off by about 8 u absolute) and rounding; kappa tiles
    blend with the same hysteresis as the texels */
 void orc_blend_probe_k(int32_t n, const double* omega, const double* rgb, const double* rgb_kappa, const double* d,
-                       double cos_power, double alpha_irr, double alpha_dist, double gamma, int32_t thresholds,
-                       double* irr_tile, double* dist_tile, double* irr_kappa, double* dist_kappa);
+                       const double* d_kappa, double cos_power, double alpha_irr, double alpha_dist, double gamma,
+                       int32_t thresholds, double* irr_tile, double* dist_tile, double* irr_kappa, double* dist_kappa);
 /* the blend with the convergence refinements of the sections on perception
    encoding and fast convergence: irradiance texels store the new mean raised
    to 1/gamma (gamma = 1: linear), and with thresholds != 0 the irradiance

@@ -108,6 +108,7 @@ struct irf_ctx {
   DevBuf<char> saved;
   int64_t saved_irr[IRF_MAX_VOLUMES], saved_dist[IRF_MAX_VOLUMES], saved_states[IRF_MAX_VOLUMES];
   DevBuf<float4> grad_rays;
+  DevBuf<float4> probe_pos;
   // kernel timing
   bool prof = false;
   struct ProfRec {
@@ -177,6 +178,7 @@ irf_status ensure_scratch(irf_ctx* c) {
   for (int v = 0; v < c->n_vol; v++) om += c->vol[v].rays;
   if ((s = c->params.reserve(1)) != IRF_OK) return s;
   if ((s = c->active.reserve((size_t)P)) != IRF_OK) return s;
+  if ((s = c->probe_pos.reserve((size_t)(P > 0 ? P : 1))) != IRF_OK) return s;
   int64_t nb = 0;
   for (int v = 0; v < c->n_vol; v++) nb += (c->vol[v].n_probes + 1023) / 1024;
   if ((s = c->block_active.reserve((size_t)(nb > 0 ? nb : 1))) != IRF_OK) return s;
@@ -225,6 +227,7 @@ FrameScratch scratch_view(const irf_ctx* c) {
   f.wave_tasks = c->wave_tasks.p;
   f.wave_offset = c->wave_offset.p;
   f.grad_rays = c->grad_rays.p;
+  f.probe_pos = c->probe_pos.p;
   f.weights = c->weights.p;
   f.inv_row_sum = c->inv_row_sum.p;
   f.rays_lp = nullptr;
@@ -426,6 +429,7 @@ void irf_destroy(irf_ctx* c) {
   c->stats.release();
   c->saved.release();
   c->grad_rays.release();
+  c->probe_pos.release();
   c->weights.release();
   c->inv_row_sum.release();
   c->class_back.release();
@@ -597,6 +601,10 @@ irf_status irf_validate_volume_desc(const irf_volume_desc* d) {
   if (!(d->irradiance_gamma == 0.0f || (d->irradiance_gamma >= 1.0f && d->irradiance_gamma <= 16.0f)))
     return fail(IRF_E_INVALID, "irradiance_gamma must be 0 (linear) or in [1, 16]");
   if (d->texel_thresholds != 0 && d->texel_thresholds != 1) return fail(IRF_E_INVALID, "texel_thresholds must be 0 or 1");
+  if (d->tracking != 0 && d->tracking != 1) return fail(IRF_E_INVALID, "tracking must be 0 or 1");
+  if (d->tracking)
+    for (int a = 0; a < 3; a++)
+      if (d->counts[a] < 5) return fail(IRF_E_INVALID, "a tracking volume needs counts >= 5 per axis");
   return IRF_OK;
 }
 
@@ -626,6 +634,11 @@ irf_status irf_create_volume(irf_ctx* c, const irf_volume_desc* d, int32_t* volu
   V.inv_gamma = 1.0f / V.gamma;
   V.half_gamma = 0.5f * V.gamma;
   V.thresholds = d->texel_thresholds;
+  V.tracking = d->tracking;
+  for (int a = 0; a < 3; a++) {
+    V.phase[a] = 0;
+    V.camera[a] = d->origin[a] + 0.5f * (float)(d->counts[a] - 1) * d->spacing[a];   // the window centre
+  }
   float pi = std::floor(d->cos_power);
   V.cos_power_int = (pi == d->cos_power && pi >= 1.0f && pi <= 64.0f) ? (int32_t)pi : 0;
   V.bias = d->self_shadow_bias;
@@ -690,7 +703,10 @@ irf_status irf_classify(irf_ctx* c, const float* rotations, int32_t K, void* str
   int64_t P = total_probes(c);
   if ((s = c->class_back.reserve((size_t)P)) != IRF_OK) return s;
   if ((s = c->class_tf.reserve((size_t)P)) != IRF_OK) return s;
-  launch_classify(volume_view(c), scene_view(c), boxes_view(c), rotations, K, c->class_back.p, c->class_tf.p,
+  PlaneMask all;
+  memset(&all, 0, sizeof(all));
+  all.vol = -1;
+  launch_classify(volume_view(c), scene_view(c), boxes_view(c), rotations, K, c->class_back.p, c->class_tf.p, all,
                   (hipStream_t)stream);
   return launched();
 }
@@ -714,6 +730,86 @@ irf_status irf_optimize_probes(irf_ctx* c, const float* rotations, int32_t itera
     launch_relocate(volume_view(c), scene_view(c), rotations + 9 * it, offset_limit, c->class_back.p,
                     c->reloc_keys.p, (hipStream_t)stream);
   return launched();
+}
+
+irf_status irf_track_volume(irf_ctx* c, int32_t vol, const float* camera, const float* rotations, int32_t K,
+                            int32_t* shift, void* stream) {
+  if (!c || !camera || !rotations) return fail(IRF_E_INVALID, "NULL argument");
+  if (vol < 0 || vol >= c->n_vol) return fail(IRF_E_INVALID, "no volume %d", vol);
+  if (!c->vol[vol].tracking) return fail(IRF_E_STATE, "volume %d was not created with tracking", vol);
+  if (K < 1 || K > IRF_MAX_ROTATIONS) return fail(IRF_E_INVALID, "K = %d must be in [1, %d]", K, IRF_MAX_ROTATIONS);
+  for (int i = 0; i < 9 * K; i++)
+    if (!std::isfinite(rotations[i])) return fail(IRF_E_INVALID, "rotation %d is not finite", i / 9);
+  VolumeGPU& V = c->vol[vol];
+  for (int a = 0; a < 3; a++) {
+    if (!std::isfinite(camera[a])) return fail(IRF_E_INVALID, "camera is not finite");
+    double center = (double)V.origin[a] + 0.5 * (double)(V.counts[a] - 1) * (double)V.spacing[a];
+    if (std::fabs((double)camera[a] - center) > 1e6 * (double)V.spacing[a])
+      return fail(IRF_E_INVALID, "camera more than 1e6 cells from the window");
+  }
+  irf_status s = check_ready(c);
+  if (s != IRF_OK) return s;
+  if ((s = set_device(c)) != IRF_OK) return s;
+  // whole-cell shifts toward the camera while it is more than one spacing from
+  // the window centre (host, double precision)
+  PlaneMask m;
+  memset(&m, 0, sizeof(m));
+  m.vol = vol;
+  int32_t k3[3];
+  bool moved = false;
+  for (int a = 0; a < 3; a++) {
+    const double sp = (double)V.spacing[a];
+    double d = (double)camera[a] - ((double)V.origin[a] + 0.5 * (double)(V.counts[a] - 1) * sp);
+    int32_t k = 0;
+    while (d > sp) {
+      k++;
+      d -= sp;
+    }
+    while (d < -sp) {
+      k--;
+      d += sp;
+    }
+    k3[a] = k;
+    const int n = V.counts[a];
+    V.origin[a] = (float)((double)V.origin[a] + (double)k * sp);
+    V.phase[a] = (int32_t)((((int64_t)V.phase[a] + k) % n + n) % n);
+    const int mm = k > 0 ? (k < n ? k : n) : (-k < n ? -k : n);
+    if (k > 0) {
+      m.lo[a] = n - mm;
+      m.hi[a] = n - 1;
+    } else if (k < 0) {
+      m.lo[a] = 0;
+      m.hi[a] = mm - 1;
+    } else {
+      m.lo[a] = 1;
+      m.hi[a] = 0;
+    }
+    moved = moved || k != 0;
+    V.camera[a] = camera[a];
+  }
+  if (shift)
+    for (int a = 0; a < 3; a++) shift[a] = k3[a];
+  if (moved) {
+    // the entering planes start over: zero texels and offsets, classification
+    if ((s = c->class_back.reserve((size_t)total_probes(c))) != IRF_OK) return s;
+    if ((s = c->class_tf.reserve((size_t)total_probes(c))) != IRF_OK) return s;
+    VolumeSet vs = volume_view(c);
+    launch_track_reset(vs, m, (hipStream_t)stream);
+    launch_classify(vs, scene_view(c), boxes_view(c), rotations, K, c->class_back.p, c->class_tf.p, m,
+                    (hipStream_t)stream);
+  }
+  return launched();
+}
+
+irf_status irf_volume_window(const irf_ctx* c, int32_t vol, float origin[3], int32_t phase[3], float camera[3]) {
+  if (!c || !origin || !phase || !camera) return fail(IRF_E_INVALID, "NULL argument");
+  if (vol < 0 || vol >= c->n_vol) return fail(IRF_E_INVALID, "no volume %d", vol);
+  for (int a = 0; a < 3; a++) {
+    origin[a] = c->vol[vol].origin[a];
+    phase[a] = c->vol[vol].phase[a];
+    camera[a] = c->vol[vol].camera[a];
+  }
+  return IRF_OK;
 }
 
 irf_status irf_update_probes(irf_ctx* c, const float* rotation, void* stream) {

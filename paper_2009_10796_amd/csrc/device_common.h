@@ -25,6 +25,10 @@ __device__ __forceinline__ float3 normalize_or_zero(float3 a) {
 }
 __device__ __forceinline__ float signnz(float x) { return x >= 0.0f ? 1.0f : -1.0f; }
 __device__ __forceinline__ float clampf(float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi); }
+// Hardware reciprocal and reciprocal square root (1 ulp), for the query's
+// inner loop.
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsq_fast(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // Octahedral map of the unit sphere onto [-1,1]^2 (Cigolle et al. 2014).
 __device__ __forceinline__ float2 oct_encode(float3 v) {
@@ -91,6 +95,27 @@ __device__ __forceinline__ void tile_footprint(float3 v, int& x0, int& y0, float
   fy = clampf(cy - (float)y0, 0.0f, 1.0f);
 }
 
+// The same footprint with the octahedral projection's division done by the
+// hardware reciprocal (query path).
+template <int M>
+__device__ __forceinline__ void tile_footprint_fast(float3 v, int& x0, int& y0, float& fx, float& fy) {
+  constexpr int k = M - 2;
+  const float il1 = rcp_fast(fabsf(v.x) + fabsf(v.y) + fabsf(v.z));
+  float x = v.x * il1, y = v.y * il1;
+  if (v.z < 0.0f) {
+    const float nx = (1.0f - fabsf(y)) * signnz(x);
+    const float ny = (1.0f - fabsf(x)) * signnz(y);
+    x = nx;
+    y = ny;
+  }
+  const float cx = fmaf(fmaf(0.5f, x, 0.5f), (float)k, 0.5f);
+  const float cy = fmaf(fmaf(0.5f, y, 0.5f), (float)k, 0.5f);
+  x0 = min(max((int)floorf(cx), 0), k);
+  y0 = min(max((int)floorf(cy), 0), k);
+  fx = clampf(cx - (float)x0, 0.0f, 1.0f);
+  fy = clampf(cy - (float)y0, 0.0f, 1.0f);
+}
+
 // Distance-blend weight cos^p of a positive cosine (square-and-multiply for
 // an integer exponent, so every kernel gets the same float32 value).
 __device__ __forceinline__ float pow_weight(float c, const VolumeGPU& V) {
@@ -107,10 +132,33 @@ __device__ __forceinline__ float pow_weight(float c, const VolumeGPU& V) {
   return powf(c, V.cos_power);
 }
 
+// Section "Tracking Windows": a tracking volume is a circular buffer, the
+// storage slot of logical grid index i along an axis being (i + phase) mod n
+// (phase 0 for other volumes).  Both arguments below are within one period.
+__device__ __forceinline__ int slot_of(int i, int phase, int n) {
+  int x = i + phase;
+  return x >= n ? x - n : x;
+}
+__device__ __forceinline__ int logical_of(int s, int phase, int n) {
+  int x = s - phase;
+  return x < 0 ? x + n : x;
+}
+
+__device__ __forceinline__ int storage_index(const VolumeGPU& V, int i, int j, int k) {
+  return slot_of(i, V.phase[0], V.counts[0]) +
+         V.counts[0] * (slot_of(j, V.phase[1], V.counts[1]) + V.counts[1] * slot_of(k, V.phase[2], V.counts[2]));
+}
+
+__device__ __forceinline__ void logical_index(const VolumeGPU& V, int q, int g[3]) {
+  g[0] = logical_of(q % V.counts[0], V.phase[0], V.counts[0]);
+  g[1] = logical_of((q / V.counts[0]) % V.counts[1], V.phase[1], V.counts[1]);
+  g[2] = logical_of(q / (V.counts[0] * V.counts[1]), V.phase[2], V.counts[2]);
+}
+
 __device__ __forceinline__ float3 probe_position(const VolumeGPU& V, int q) {
-  int i = q % V.counts[0];
-  int j = (q / V.counts[0]) % V.counts[1];
-  int k = q / (V.counts[0] * V.counts[1]);
+  int g[3];
+  logical_index(V, q, g);
+  int i = g[0], j = g[1], k = g[2];
   float3 P = f3(fmaf((float)i, V.spacing[0], V.origin[0]), fmaf((float)j, V.spacing[1], V.origin[1]),
                 fmaf((float)k, V.spacing[2], V.origin[2]));
   if (V.offsets) {
@@ -215,38 +263,85 @@ __device__ inline float3 volume_query(const VolumeGPU& V, float3 X, float3 n, fl
   float sb = 0.75f * D * V.bias;
   float3 Xb = f3(fmaf(fmaf(0.2f, n.x, 0.8f * wo.x), sb, X.x), fmaf(fmaf(0.2f, n.y, 0.8f * wo.y), sb, X.y),
                  fmaf(fmaf(0.2f, n.z, 0.8f * wo.z), sb, X.z));
+  // the irradiance lookup direction is the normal for every probe of the cage
+  int ix, iy;
+  float ifx, ify;
+  tile_footprint_fast<kIrrTile>(n, ix, iy, ifx, ify);
+  const int irr_off = iy * kIrrTile + ix;
   float3 acc = f3(0.0f, 0.0f, 0.0f);
   float W = 0.0f;
   for (int c = 0; c < 8; c++) {
-    int cb0 = c & 1, cb1 = (c >> 1) & 1, cb2 = (c >> 2) & 1;
-    int q = (g[0] + cb0) + V.counts[0] * ((g[1] + cb1) + V.counts[1] * (g[2] + cb2));
+    const int cb0 = c & 1, cb1 = (c >> 1) & 1, cb2 = (c >> 2) & 1;
+    const int li = g[0] + cb0, lj = g[1] + cb1, lk = g[2] + cb2;
+    const int q = storage_index(V, li, lj, lk);
     if (!sampled_state(V.states[q])) continue;
     float wt = (cb0 ? f[0] : 1.0f - f[0]) * (cb1 ? f[1] : 1.0f - f[1]) * (cb2 ? f[2] : 1.0f - f[2]);
-    float3 P = probe_position(V, q);
-    float3 toP = normalize_or_zero(P - X);
-    float h = (1.0f + dot(n, toP)) * 0.5f;
+    // probe position from its logical index (as probe_position computes it)
+    float3 P = f3(fmaf((float)li, V.spacing[0], V.origin[0]), fmaf((float)lj, V.spacing[1], V.origin[1]),
+                  fmaf((float)lk, V.spacing[2], V.origin[2]));
+    if (V.offsets) {
+      P.x += V.offsets[3 * q + 0];
+      P.y += V.offsets[3 * q + 1];
+      P.z += V.offsets[3 * q + 2];
+    }
+    const float3 toP = P - X;
+    const float d2 = dot(toP, toP);
+    const float h = fmaf(d2 > 0.0f ? dot(n, toP) * rsq_fast(d2) : 0.0f, 0.5f, 0.5f);
     float w = wt * fmaf(h, h, 0.2f);
-    float3 z = Xb - P;
-    float r = length(z);
-    if (r > 0.0f) {
-      float2 m = sample_distance(V, q, (1.0f / r) * z);
-      if (r > m.x) {
-        float var = fmaxf(fmaf(-m.x, m.x, m.y), 0.0f);
-        float dl = r - m.x;
-        float ch = var / fmaf(dl, dl, var);
+    const float3 z = Xb - P;
+    const float r2 = dot(z, z);
+    if (r2 > 0.0f) {
+      const float rinv = rsq_fast(r2);
+      const float r = r2 * rinv;
+      int x0, y0;
+      float fx, fy;
+      tile_footprint_fast<kDistTile>(rinv * z, x0, y0, fx, fy);
+      const int b = q * kDistTexels + y0 * kDistTile + x0;
+      const float2 da = load_dist(V, b), dc = load_dist(V, b + 1);
+      const float2 dd = load_dist(V, b + kDistTile), de = load_dist(V, b + kDistTile + 1);
+      const float mx = (1.0f - fy) * ((1.0f - fx) * da.x + fx * dc.x) + fy * ((1.0f - fx) * dd.x + fx * de.x);
+      if (r > mx) {
+        const float my = (1.0f - fy) * ((1.0f - fx) * da.y + fx * dc.y) + fy * ((1.0f - fx) * dd.y + fx * de.y);
+        const float var = fmaxf(fmaf(-mx, mx, my), 0.0f);
+        const float dl = r - mx;
+        const float den = fmaf(dl, dl, var);
+        const float ch = den > 0.0f ? var * rcp_fast(den) : 0.0f;
         float p = ch;
         for (int e = 1; e < V.cheb_power; e++) p *= ch;
         w *= p;
       }
     }
-    float3 e = sample_irradiance(V, q, n);
+    const int bi = q * kIrrTexels + irr_off;
+    const float3 ea = load_irr(V, bi), ec = load_irr(V, bi + 1);
+    const float3 ed = load_irr(V, bi + kIrrTile), ee = load_irr(V, bi + kIrrTile + 1);
+    float3 e = (1.0f - ify) * ((1.0f - ifx) * ea + ifx * ec) + ify * ((1.0f - ifx) * ed + ifx * ee);
     if (V.gamma != 1.0f) e = decode_irr_half(V, e);
     acc = acc + w * e;
     W += w;
   }
   if (!(W > 0.0f)) return f3(0.0f, 0.0f, 0.0f);
-  float3 r = (1.0f / W) * acc;
+  float3 r = rcp_fast(W) * acc;
   return V.gamma != 1.0f ? f3(r.x * r.x, r.y * r.y, r.z * r.z) : r;
+}
+
+// Section "Multiple Probe Volumes": a volume's weight falls linearly from 1 to
+// 0 over its last grid cell along each axis (product over axes); for a volume
+// that tracks the camera the transition region is tightened by one cell and
+// centred on the camera.
+__device__ __forceinline__ float volume_weight(const VolumeGPU& V, float3 X) {
+  float wv = 1.0f;
+  const float Xa[3] = {X.x, X.y, X.z};
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    if (V.tracking) {
+      float h = 0.5f * (float)(V.counts[a] - 1) - 1.0f;
+      wv *= clampf(h - fabsf(Xa[a] - V.camera[a]) / V.spacing[a], 0.0f, 1.0f);
+    } else {
+      float u = (Xa[a] - V.origin[a]) / V.spacing[a];
+      wv *= clampf(fminf(u, (float)(V.counts[a] - 1) - u), 0.0f, 1.0f);
+    }
+  }
+  return wv;
 }
 
 // Cascaded volumes (Section "Multiple Probe Volumes"): densest first, linear
@@ -258,13 +353,7 @@ __device__ inline float3 query_irradiance(const VolumeSet& vs, float3 X, float3 
   for (int v = 0; v < vs.n; v++) {
     if (Wt >= 1.0f) break;
     const VolumeGPU& V = vs.v[v];
-    float wv = 1.0f;
-    float Xa[3] = {X.x, X.y, X.z};
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-      float u = (Xa[a] - V.origin[a]) / V.spacing[a];
-      wv *= clampf(fminf(u, (float)(V.counts[a] - 1) - u), 0.0f, 1.0f);
-    }
+    float wv = volume_weight(V, X);
     float wuse = (v == vs.n - 1) ? 1.0f - Wt : fminf(wv, 1.0f - Wt);
     if (wuse > 0.0f) {
       E = E + wuse * volume_query(V, X, n, wo);

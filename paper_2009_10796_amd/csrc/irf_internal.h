@@ -57,6 +57,9 @@ struct VolumeGPU {
   int32_t blend;
   float gamma, inv_gamma, half_gamma;   // perception encoding of irradiance texels (1 = linear)
   int32_t thresholds;       // per-texel irradiance hysteresis thresholds (0 / 1)
+  int32_t phase[3];         // tracking window: slot of logical probe i is (i + phase) mod n
+  int32_t tracking;         // 1: camera-centred blend weight
+  float camera[3];          // camera position for that weight
   int32_t probe_base;       // first global probe id of this volume
   int32_t omega_base;       // first entry of this volume in the direction table
   int64_t weight_base;      // byte offset of this volume's blend weights
@@ -145,6 +148,7 @@ struct FrameScratch {
   int32_t* wave_tasks;      // [max_rays / 64] number of tasks in each slice
   int64_t* wave_offset;     // [max_rays / 64] exclusive prefix sum of wave_tasks
   float4* grad_rays;        // [max_rays] adjoint: dLoss/d(ray radiance)
+  float4* probe_pos;        // [max_slots] position of each active probe this frame (by slot)
   void* weights;            // per volume: 256 weight rows x rays (float32 [k][row] or 16-bit [row][k])
   float* inv_row_sum;       // [n_volumes][256] 1 / sum of the stored weights of each row (0 = none)
   void* rays_lp;            // [max_rays] 4 x bf16/f16 (matrix-core path)
@@ -174,8 +178,15 @@ void launch_query(const VolumeSet& vs, const float* pos, const float* nrm, const
                   float* out, hipStream_t s);
 void launch_relocate(const VolumeSet& vs, SceneGPU sc, const float* rotation, float limit, int32_t* back,
                      unsigned long long* keys, hipStream_t s);
+// Probes of entering planes of a tracking window: volume `vol` (-1: every
+// probe of every volume), logical index in [lo, hi] along some axis.
+struct PlaneMask {
+  int32_t vol;
+  int32_t lo[3], hi[3];
+};
+void launch_track_reset(const VolumeSet& vs, PlaneMask m, hipStream_t s);
 void launch_classify(const VolumeSet& vs, SceneGPU sc, ObjectBoxes boxes, const float* rotations, int K,
-                     int32_t* back, uint32_t* tfront, hipStream_t s);
+                     int32_t* back, uint32_t* tfront, PlaneMask mask, hipStream_t s);
 void launch_traversal_stats(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, unsigned long long* out,
                             hipStream_t s);
 struct GradSet;

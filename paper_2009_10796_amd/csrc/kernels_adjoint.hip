@@ -56,7 +56,7 @@ __device__ inline void volume_query_backward(const VolumeGPU& V, float3 X, float
   float3 E = f3(0.0f, 0.0f, 0.0f);
   for (int c = 0; c < 8; c++) {
     int cb0 = c & 1, cb1 = (c >> 1) & 1, cb2 = (c >> 2) & 1;
-    int q = (gi[0] + cb0) + V.counts[0] * ((gi[1] + cb1) + V.counts[1] * (gi[2] + cb2));
+    int q = storage_index(V, gi[0] + cb0, gi[1] + cb1, gi[2] + cb2);
     if (!sampled_state(V.states[q])) continue;
     float wt = (cb0 ? f[0] : 1.0f - f[0]) * (cb1 ? f[1] : 1.0f - f[1]) * (cb2 ? f[2] : 1.0f - f[2]);
     float3 P = probe_position(V, q);
@@ -118,12 +118,7 @@ __device__ inline void query_backward(const VolumeSet& vs, const GradSet& G, flo
   for (int v = 0; v < vs.n; v++) {
     if (Wt >= 1.0f) break;
     const VolumeGPU& V = vs.v[v];
-    float wv = 1.0f;
-    float Xa[3] = {X.x, X.y, X.z};
-    for (int a = 0; a < 3; a++) {
-      float u = (Xa[a] - V.origin[a]) / V.spacing[a];
-      wv *= clampf(fminf(u, (float)(V.counts[a] - 1) - u), 0.0f, 1.0f);
-    }
+    float wv = volume_weight(V, X);
     float wuse = (v == vs.n - 1) ? 1.0f - Wt : fminf(wv, 1.0f - Wt);
     if (wuse > 0.0f) {
       volume_query_backward(V, X, n, wo, wuse * g, G.irr[v], G.dist[v]);

@@ -182,20 +182,30 @@ struct RaySlot {
   int v;       // volume
   int q;       // probe within the volume
   int r;       // ray index within the probe
+  int gs;      // slot of the probe in the frame's active list
 };
 
+// Ray id -> (volume, probe, ray).  Ray ids of one frame are below 2^27
+// (checked by the API), so the division runs in 32 bits.
 __device__ __forceinline__ RaySlot locate_ray(const VolumeSet& vs, const FrameCounters& C, const int32_t* active,
                                               int64_t id) {
   int v = 0;
   while (v + 1 < vs.n && id >= C.ray_base[v + 1]) v++;
   const VolumeGPU& V = vs.v[v];
-  int64_t local = id - C.ray_base[v];
-  int slot = (int)(local / V.rays);
+  const uint32_t local = (uint32_t)(id - C.ray_base[v]);
+  const uint32_t slot = local / (uint32_t)V.rays;
   RaySlot s;
   s.v = v;
-  s.r = (int)(local - (int64_t)slot * V.rays);
-  s.q = active[C.slot_base[v] + slot] - V.probe_base;
+  s.r = (int)(local - slot * (uint32_t)V.rays);
+  s.gs = C.slot_base[v] + (int)slot;
+  s.q = active[s.gs] - V.probe_base;
   return s;
+}
+
+// Position of the ray's probe (computed once per frame at compaction).
+__device__ __forceinline__ float3 slot_position(const FrameScratch& fs, const RaySlot& s) {
+  const float4 p = fs.probe_pos[s.gs];
+  return f3(p.x, p.y, p.z);
 }
 
 __device__ __forceinline__ float3 tri_normal(const SceneGPU& sc, int tri) {
@@ -254,7 +264,7 @@ __device__ __forceinline__ void trace_one(const VolumeSet& vs, const SceneGPU& s
                                           const FrameScratch& fs, const FrameCounters& C, int64_t id) {
   RaySlot s = locate_ray(vs, C, fs.active, id);
   const VolumeGPU& V = vs.v[s.v];
-  float3 o = probe_position(V, s.q);
+  float3 o = slot_position(fs, s);
   float4 w = fs.omega[V.omega_base + s.r];
   float3 w3 = f3(w.x, w.y, w.z);
   Ray ray = make_ray(o, w3);
@@ -349,7 +359,7 @@ __device__ __forceinline__ void shadow_one(const VolumeSet& vs, const SceneGPU& 
   int l = task & 31;
   RaySlot s = locate_ray(vs, C, fs.active, id);
   const VolumeGPU& V = vs.v[s.v];
-  float3 o = probe_position(V, s.q);
+  float3 o = slot_position(fs, s);
   float4 w = fs.omega[V.omega_base + s.r];
   HitRec h = fs.hits[id];
   float3 ng = tri_normal(sc, h.tri);
@@ -377,7 +387,7 @@ __device__ __forceinline__ void shade_one(const VolumeSet& vs, const SceneGPU& s
                                           const FrameScratch& fs, const FrameCounters& C, int64_t id) {
   RaySlot s = locate_ray(vs, C, fs.active, id);
   const VolumeGPU& V = vs.v[s.v];
-  float3 o = probe_position(V, s.q);
+  float3 o = slot_position(fs, s);
   float4 w4 = fs.omega[V.omega_base + s.r];
   float3 w = f3(w4.x, w4.y, w4.z);
   HitRec h = fs.hits[id];
@@ -449,8 +459,20 @@ __device__ __forceinline__ float3 sf_direction(int i, int n, const float* R) {
             fmaf(R[6], p.x, fmaf(R[7], p.y, R[8] * p.z)));
 }
 
+// Whether probe q of volume v is selected by the mask (every probe when
+// m.vol < 0; else the probes of volume m.vol on an entering plane).
+__device__ __forceinline__ bool in_mask(const VolumeGPU& V, int v, int q, const PlaneMask& m) {
+  if (m.vol < 0) return true;
+  if (v != m.vol) return false;
+  int g[3];
+  logical_index(V, q, g);
+  bool in = false;
+  for (int a = 0; a < 3; a++) in = in || (g[a] >= m.lo[a] && g[a] <= m.hi[a]);
+  return in;
+}
+
 __global__ __launch_bounds__(kTraceBlock) void k_classify(VolumeSet vs, SceneGPU sc, ClassifyArgs A, int32_t* back,
-                                                          uint32_t* tfront) {
+                                                          uint32_t* tfront, PlaneMask mask) {
   int64_t gid = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
   if (gid >= A.base[vs.n]) return;
   int v = 0;
@@ -459,6 +481,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_classify(VolumeSet vs, SceneGPU
   int64_t local = gid - A.base[v];
   int per_probe = A.K * V.rays;
   int q = (int)(local / per_probe);
+  if (!in_mask(V, v, q, mask)) return;
   int rem = (int)(local - (int64_t)q * per_probe);
   int k = rem / V.rays, r = rem - k * V.rays;
   float3 o = probe_position(V, q);
@@ -489,12 +512,14 @@ __device__ __forceinline__ bool inside_grown_box(const VolumeGPU& V, ObjectBoxes
   return false;
 }
 
-__global__ void k_classify_finish(VolumeSet vs, ObjectBoxes ob, int K, const int32_t* back, const uint32_t* tfront) {
+__global__ void k_classify_finish(VolumeSet vs, ObjectBoxes ob, int K, const int32_t* back, const uint32_t* tfront,
+                                  PlaneMask mask) {
   int v = blockIdx.y;
   if (v >= vs.n) return;
   const VolumeGPU& V = vs.v[v];
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= V.n_probes) return;
+  if (!in_mask(V, v, q, mask)) return;
   int gq = V.probe_base + q;
   float smax = fmaxf(V.spacing[0], fmaxf(V.spacing[1], V.spacing[2]));
   float tf = __uint_as_float(tfront[gq]);
@@ -504,6 +529,26 @@ __global__ void k_classify_finish(VolumeSet vs, ObjectBoxes ob, int K, const int
   else st = IRF_SLEEPING;
   if (st == IRF_SLEEPING && inside_grown_box(V, ob, probe_position(V, q))) st = IRF_NEWLY_AWAKE;
   V.states[q] = st;
+}
+
+// ---- tracking window: probes of entering planes start over (zero texels
+// and offsets; the caller then classifies them)
+
+__global__ void k_track_reset(VolumeSet vs, PlaneMask m) {
+  const VolumeGPU& V = vs.v[m.vol];
+  int q = blockIdx.x;
+  if (q >= V.n_probes || !in_mask(V, m.vol, q, m)) return;
+  const int es = V.atlas_f16 ? 2 : 4;
+  uint32_t* irr = (uint32_t*)((char*)V.irr + (size_t)q * kIrrTexels * 4 * es);
+  uint32_t* dist = (uint32_t*)((char*)V.dist + (size_t)q * kDistTexels * 2 * es);
+  for (int i = threadIdx.x; i < kIrrTexels * es; i += blockDim.x) irr[i] = 0u;
+  for (int i = threadIdx.x; i < kDistTexels * es / 2; i += blockDim.x) dist[i] = 0u;
+  if (threadIdx.x < 3 && V.offsets) const_cast<float*>(V.offsets)[3 * q + threadIdx.x] = 0.0f;
+}
+
+void launch_track_reset(const VolumeSet& vs, PlaneMask m, hipStream_t s) {
+  const int P = vs.v[m.vol].n_probes;
+  if (P > 0) irf_launch(k_track_reset, dim3(P), dim3(256), 0, s, vs, m);
 }
 
 // ---- probe relocation (Section "Probe Position Adjustment")
@@ -647,7 +692,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_count(VolumeSet vs, Scene
     RaySlot s = locate_ray(vs, C, fs.active, id);
     const VolumeGPU& V = vs.v[s.v];
     float4 w = fs.omega[V.omega_base + s.r];
-    Ray ray = make_ray(probe_position(V, s.q), f3(w.x, w.y, w.z));
+    Ray ray = make_ray(slot_position(fs, s), f3(w.x, w.y, w.z));
     float t;
     traverse<false, false, Count>(sc, ray, INFINITY, t, dyn_stack + threadIdx.x, kTraceBlock, &cnt);
   }
@@ -759,7 +804,7 @@ void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, h
 }
 
 void launch_classify(const VolumeSet& vs, SceneGPU sc, ObjectBoxes boxes, const float* rotations, int K,
-                     int32_t* back, uint32_t* tfront, hipStream_t s) {
+                     int32_t* back, uint32_t* tfront, PlaneMask mask, hipStream_t s) {
   ClassifyArgs A;
   for (int k = 0; k < K; k++)
     for (int i = 0; i < 9; i++) A.R[k][i] = rotations[9 * k + i];
@@ -776,11 +821,11 @@ void launch_classify(const VolumeSet& vs, SceneGPU sc, ObjectBoxes boxes, const 
                      (uint32_t)0x7f800000u, (int64_t)total_probes);
   if (A.base[vs.n] > 0)
     irf_launch(k_classify, dim3(blocks_for(A.base[vs.n], kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s,
-                       vs, sc, A, back, tfront);
+                       vs, sc, A, back, tfront, mask);
   int maxp = 0;
   for (int v = 0; v < vs.n; v++) maxp = vs.v[v].n_probes > maxp ? vs.v[v].n_probes : maxp;
   irf_launch(k_classify_finish, dim3(blocks_for(maxp, 256), vs.n), dim3(256), 0, s, vs, boxes, K, back,
-                     tfront);
+                     tfront, mask);
 }
 
 void launch_records(const VolumeSet& vs, int vol, SceneGPU sc, FrameScratch fs, int n_lights, irf_ray_record* out,

@@ -141,7 +141,12 @@ __global__ __launch_bounds__(kCompactBlock) void k_state_scatter(VolumeSet vs, C
     }
   }
   __syncthreads();
-  if (act) fs.active[s_base + wave_off[wave] + __popcll(m & ((1ull << lane) - 1ull))] = V.probe_base + q;
+  if (act) {
+    const int slot = s_base + wave_off[wave] + __popcll(m & ((1ull << lane) - 1ull));
+    fs.active[slot] = V.probe_base + q;
+    const float3 P = probe_position(V, q);
+    fs.probe_pos[slot] = make_float4(P.x, P.y, P.z, 0.0f);
+  }
   if (b == 0 && threadIdx.x == 0) {
     FrameCounters C;
     int slot = 0;

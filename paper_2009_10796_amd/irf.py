@@ -47,7 +47,7 @@ class VolumeDescC(C.Structure):
                 ("rays_per_probe", C.c_int32), ("hysteresis_irr", C.c_float), ("hysteresis_dist", C.c_float),
                 ("cos_power", C.c_float), ("self_shadow_bias", C.c_float), ("max_distance", C.c_float),
                 ("cheb_power", C.c_int32), ("atlas_dtype", C.c_int32), ("blend", C.c_int32),
-                ("irradiance_gamma", C.c_float), ("texel_thresholds", C.c_int32)]
+                ("irradiance_gamma", C.c_float), ("texel_thresholds", C.c_int32), ("tracking", C.c_int32)]
 
 
 class BufferSizes(C.Structure):
@@ -92,6 +92,8 @@ SIGNATURES = {
     "irf_graph_launch": (C.c_int, [_vp, _vp, _vp, _vp]),
     "irf_graph_destroy": (None, [_vp]),
     "irf_optimize_probes": (C.c_int, [_vp, _vp, _i32, C.c_float, _vp]),
+    "irf_track_volume": (C.c_int, [_vp, _i32, _vp, _vp, _i32, _vp, _vp]),
+    "irf_volume_window": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
     "irf_set_differentiable": (C.c_int, [_vp, _i32]),
     "irf_set_emission": (C.c_int, [_vp, _vp, _vp]),
     "irf_query_backward": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
@@ -160,6 +162,7 @@ def volume_desc(desc) -> VolumeDescC:
     d.blend = BLEND[desc.blend]
     d.irradiance_gamma = float(getattr(desc, "irradiance_gamma", 1.0))
     d.texel_thresholds = int(bool(getattr(desc, "texel_thresholds", False)))
+    d.tracking = int(bool(getattr(desc, "tracking", False)))
     return d
 
 
@@ -262,6 +265,24 @@ class Context:
         """Probe relocation: one pass per rotation (run before classify)."""
         R = _np(rotations, np.float32).reshape(-1, 9)
         _check(load().irf_optimize_probes(self.handle, _ptr(R), len(R), float(offset_limit), _stream(self.torch)))
+
+    def track_volume(self, vol: int, camera, rotations) -> np.ndarray:
+        """Moves a tracking volume's window toward the camera (entering planes
+        reset and classified with `rotations`); returns the shift in cells."""
+        cam = _np(camera, np.float32).reshape(3)
+        R = _np(rotations, np.float32).reshape(-1, 9)
+        shift = np.zeros(3, dtype=np.int32)
+        _check(load().irf_track_volume(self.handle, vol, _ptr(cam), _ptr(R), len(R), _ptr(shift),
+                                       _stream(self.torch)))
+        return shift
+
+    def volume_window(self, vol: int):
+        """(origin, phase, camera) of a volume's window."""
+        o = np.zeros(3, np.float32)
+        ph = np.zeros(3, np.int32)
+        cam = np.zeros(3, np.float32)
+        _check(load().irf_volume_window(self.handle, vol, _ptr(o), _ptr(ph), _ptr(cam)))
+        return o, ph, cam
 
     def update_probes(self, rotation) -> None:
         R = _np(rotation, np.float32).reshape(9)

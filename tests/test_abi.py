@@ -93,3 +93,13 @@ def test_scene_validation_rejects_bad_indices_and_materials():
     bad.vertices[0, 0] = np.nan
     with pytest.raises(irf.IrfError):
         irf.bvh_stats(bad)
+
+
+def test_tracking_volume_needs_five_probes_per_axis():
+    d = _good()
+    d.tracking = True
+    with pytest.raises(irf.IrfError) as e:
+        irf.validate_volume_desc(d)
+    assert e.value.status == irf.E_INVALID
+    d.counts = (5, 5, 6)
+    irf.validate_volume_desc(d)
