@@ -126,21 +126,20 @@ __device__ inline int traverse(const SceneGPU& sc, const Ray& ray, float tmax, f
       float4 n0 = np[0], n1 = np[1], n2 = np[2], n3 = np[3];
       if (cnt) cnt->node();
       float t0, t1;
-      bool h0 = box_hit(ray, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tbest, t0);
-      bool h1 = box_hit(ray, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tbest, t1);
-      int l0 = bits_i(n3.x), l1 = bits_i(n3.y);
-      if (h0 && h1) {
-        int nearc = t0 <= t1 ? l0 : l1;
-        int farc = t0 <= t1 ? l1 : l0;
-        if (sp < sc.stack_depth) {
-          stack[sp * stride] = farc;
-          sp++;
-        }
+      const bool h0 = box_hit(ray, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tbest, t0);
+      const bool h1 = box_hit(ray, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tbest, t1);
+      const int l0 = bits_i(n3.x), l1 = bits_i(n3.y);
+      // branch-free step: descend into the nearer child that was hit and
+      // push the other one if both were; with neither, pop.  The slot above
+      // the top is always written (the stack has one spare entry).
+      const bool first0 = h0 && (!h1 || t0 <= t1);
+      const int nearc = first0 ? l0 : l1;
+      const int farc = first0 ? l1 : l0;
+      const int top = sp < sc.stack_depth ? sp : sc.stack_depth;
+      stack[top * stride] = farc;
+      sp = top + ((h0 && h1) ? 1 : 0);
+      if (h0 || h1) {
         node = nearc;
-      } else if (h0) {
-        node = l0;
-      } else if (h1) {
-        node = l1;
       } else {
         if (sp == 0) {
           done = true;
@@ -231,7 +230,7 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t n) {
 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 static inline size_t stack_bytes(const SceneGPU& sc) {
-  return sizeof(int) * (size_t)(sc.stack_depth > 0 ? sc.stack_depth : 1) * kTraceBlock;
+  return sizeof(int) * (size_t)((sc.stack_depth > 0 ? sc.stack_depth : 1) + 1) * kTraceBlock;   // + spare
 }
 
 // Whether a shadow ray from front-face hit X toward light l is needed (the
