@@ -75,6 +75,7 @@ def _declare(L):
     L.orc_scene_create.argtypes = [vp, i64, vp, i64, vp, vp, vp, vp, i32]
     L.orc_scene_free.argtypes = [vp]
     L.orc_scene_set_emission.argtypes = [vp, dp]
+    L.orc_scene_set_specular.argtypes = [vp, dp]
     L.orc_scene_bvh_nodes.restype = i64
     L.orc_scene_bvh_nodes.argtypes = [vp]
     for name in ("orc_oct_encode", "orc_oct_decode"):
@@ -87,6 +88,8 @@ def _declare(L):
     L.orc_blend_probe.argtypes = [i32, dp, dp, dp, C.c_double, C.c_double, C.c_double, dp, dp]
     L.orc_blend_probe_ex.argtypes = [i32, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double, i32, dp, dp]
     L.orc_query_batch.argtypes = [vp, i32, i64, vp, vp, vp, dp, dp]
+    L.orc_query_look.argtypes = [vp, i32, dp, dp, dp, dp, dp, dp, vp, vp]
+    L.orc_glossy_batch.argtypes = [vp, vp, vp, i32, i64, vp, vp, vp, vp]
     L.orc_classify.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
     L.orc_state_step.argtypes = [vp, vp, i32]
     L.orc_optimize_offsets.argtypes = [vp, vp, vp, i32, C.c_double, vp]
@@ -178,11 +181,18 @@ class Scene:
         self.n_triangles = int(i.shape[0])
         self.handle = lib().orc_scene_create(_p(v), v.shape[0], _p(i), i.shape[0], _p(m), _p(o),
                                              _p(a), _p(e), a.shape[0])
+        spec = getattr(scene, "specular", None)
+        if spec is not None:
+            self.set_specular(spec)
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.orc_scene_free(self.handle)
             self.handle = None
+
+    def set_specular(self, specular) -> None:
+        sp = np.ascontiguousarray(specular, dtype=np.float64).reshape(-1, 3)
+        lib().orc_scene_set_specular(self.handle, _p(sp))
 
     def set_emission(self, emission) -> None:
         e = np.ascontiguousarray(emission, dtype=np.float64).reshape(-1, 3)
@@ -327,6 +337,29 @@ def query(vols: List[Volume], pos, nrm, view):
     kap = np.zeros((pos.shape[0], 3))
     lib().orc_query_batch(_vol_array(vols), len(vols), pos.shape[0], _p(pos), _p(nrm), _p(view), _p(out), _p(kap))
     return out, kap
+
+
+def query_look(vols: List[Volume], X, n, wo, look):
+    """One query with the texels sampled in direction `look` (the probes'
+    filtered radiance); returns (value[3], kappa[3])."""
+    out, kap = np.zeros(3), np.zeros(3)
+    lib().orc_query_look(_vol_array(vols), len(vols), _p(_d(X, 3)), _p(_d(n, 3)), _p(_d(wo, 3)), _p(_d(look, 3)),
+                         _p(out), _p(kap), None, None)
+    return out, kap
+
+
+def glossy(scene: Scene, lights, vols: List[Volume], pos, nrm, view) -> np.ndarray:
+    """Second-order glossy (Section "Second Order Glossy"): per surface point
+    the record of its mirror ray (hit, shadow visibility, radiance toward the
+    point, float32 sensitivity)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
+    nrm = np.ascontiguousarray(nrm, dtype=np.float32).reshape(-1, 3)
+    view = np.ascontiguousarray(view, dtype=np.float32).reshape(-1, 3)
+    rec = np.zeros(pos.shape[0], dtype=RECORD_DTYPE)
+    L = make_lights(lights)
+    lib().orc_glossy_batch(scene.handle, C.byref(L), _vol_array(vols), len(vols), pos.shape[0], _p(pos), _p(nrm),
+                           _p(view), _p(rec))
+    return rec
 
 
 def shade_ray(scene: Scene, lights, vols: List[Volume], o, w, dmax) -> np.ndarray:

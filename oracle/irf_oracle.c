@@ -61,6 +61,7 @@ struct orc_scene {
   int32_t nm;
   double* albedo;     /* [M][3] */
   double* emission;   /* [M][3] */
+  double* specular;   /* [M][3] mirror reflectance (second-order glossy), zeros unless set */
   int32_t* order;     /* triangle ids in leaf order */
   onode* nodes;
   int64_t nnodes, cap;
@@ -169,6 +170,7 @@ orc_scene* orc_scene_create(const float* vertices, int64_t n_vertices, const uin
   s->nm = n_materials;
   s->albedo = (double*)malloc(sizeof(double) * 3 * (size_t)(n_materials ? n_materials : 1));
   s->emission = (double*)malloc(sizeof(double) * 3 * (size_t)(n_materials ? n_materials : 1));
+  s->specular = (double*)calloc(3 * (size_t)(n_materials ? n_materials : 1), sizeof(double));
   for (int32_t m = 0; m < 3 * n_materials; m++) {
     s->albedo[m] = albedo[m];
     s->emission[m] = emission[m];
@@ -201,11 +203,15 @@ orc_scene* orc_scene_create(const float* vertices, int64_t n_vertices, const uin
 void orc_scene_free(orc_scene* s) {
   if (!s) return;
   free(s->v); free(s->material); free(s->object); free(s->order); free(s->nodes);
-  free(s->albedo); free(s->emission); free(s->obj_lo); free(s->obj_hi);
+  free(s->albedo); free(s->emission); free(s->specular); free(s->obj_lo); free(s->obj_hi);
   free(s);
 }
 
 int64_t orc_scene_bvh_nodes(const orc_scene* s) { return s->nnodes; }
+
+void orc_scene_set_specular(orc_scene* s, const double* specular) {
+  for (int32_t m = 0; m < 3 * s->nm; m++) s->specular[m] = specular[m];
+}
 
 void orc_scene_set_emission(orc_scene* s, const double* emission) {
   for (int32_t m = 0; m < 3 * s->nm; m++) s->emission[m] = emission[m];
@@ -708,7 +714,8 @@ static int sampled_state(uint8_t s) { return s == ORC_AWAKE || s == ORC_VIGILANT
    irradiance texels sampled in direction n.  kap receives the absolute
    sensitivity of the result to float32 rounding (units of 2^-24). */
 static void volume_query(const orc_volume* V, int64_t base, const double X[3], const double n[3],
-                         const double wo[3], double out[3], double kap[3], int32_t* cage, int32_t* ncage) {
+                         const double wo[3], const double look[3], double out[3], double kap[3], int32_t* cage,
+                         int32_t* ncage) {
   double u[3], f[3];
   int64_t g[3];
   double D = fmin((double)V->spacing[0], fmin((double)V->spacing[1], (double)V->spacing[2]));
@@ -772,8 +779,8 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
     ids[used] = (int32_t)(base + q);
     w[used] = wt * wb * wv;
     sens[used] = s;
-    orc_sample_tile(V->irr + q * 8 * 8 * 3, 8, 3, n, e[used]);
-    if (V->irr_kappa) orc_sample_tile(V->irr_kappa + q * 8 * 8 * 3, 8, 3, n, ek[used]);
+    orc_sample_tile(V->irr + q * 8 * 8 * 3, 8, 3, look, e[used]);
+    if (V->irr_kappa) orc_sample_tile(V->irr_kappa + q * 8 * 8 * 3, 8, 3, look, ek[used]);
     else ek[used][0] = ek[used][1] = ek[used][2] = 0.0;
     if (V->gamma != 1.0f) {
       /* Section "Perception-based exponential encoding": each probe's sample
@@ -825,6 +832,15 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
    reach 1; the sparsest volume takes whatever weight remains. */
 void orc_query(const orc_volume* vols, int32_t nvol, const double X[3], const double n[3],
                const double wo[3], double out[3], double kappa[3], int32_t* cage, int32_t* n_cage) {
+  orc_query_look(vols, nvol, X, n, wo, n, out, kappa, cage, n_cage);
+}
+
+/* The query with the probes' texels sampled in direction `look` instead of
+   the normal (the cage weights still use X, n and w_o): the probes' filtered
+   radiance around `look`. */
+void orc_query_look(const orc_volume* vols, int32_t nvol, const double X[3], const double n[3],
+                    const double wo[3], const double look[3], double out[3], double kappa[3], int32_t* cage,
+                    int32_t* n_cage) {
   double Wt = 0.0;
   int64_t base = 0;
   for (int c = 0; c < 3; c++) { out[c] = 0.0; kappa[c] = 0.0; }
@@ -837,7 +853,7 @@ void orc_query(const orc_volume* vols, int32_t nvol, const double X[3], const do
     if (wuse > 0.0) {
       double ev[3], kv[3];
       int32_t cg[8], nc = 0;
-      volume_query(V, base, X, n, wo, ev, kv, cg, &nc);
+      volume_query(V, base, X, n, wo, look, ev, kv, cg, &nc);
       for (int c = 0; c < 3; c++) {
         out[c] += wuse * ev[c];
         kappa[c] += wuse * kv[c] + 4.0 * fabs(wuse * ev[c]);
@@ -892,6 +908,35 @@ static void front_radiance(const orc_scene* s, const orc_lights* L, const orc_vo
   for (int k = 0; k < 3; k++) rgb[k] = s->emission[m * 3 + k] + s->albedo[m * 3 + k] * (direct[k] / M_PI + ind[k]);
 }
 
+/* Shadow rays of a front-face hit X (geometric normal ng) toward every
+   light on its front side, from the hit lifted off the surface; any
+   triangle, either side, occludes.  Sets bit l of vis for an unblocked light
+   and ORC_F_SHADOW in flags for an ambiguous shadow ray. */
+static void hit_visibility(const orc_scene* s, const orc_lights* L, const double X[3], const double ng[3],
+                           uint32_t* vis, int32_t* flags) {
+  double xmax = fmax(fabs(X[0]), fmax(fabs(X[1]), fabs(X[2])));
+  double eps = 1e-4 * fmax(1.0, xmax);
+  double Xs[3] = {X[0] + eps * ng[0], X[1] + eps * ng[1], X[2] + eps * ng[2]};
+  int32_t li = 0;
+  for (int32_t l = 0; l < L->n_dir; l++, li++) {
+    double dl[3] = {L->dir_to_light[3 * l], L->dir_to_light[3 * l + 1], L->dir_to_light[3 * l + 2]};
+    if (dot3(ng, dl) <= 0.0) continue;
+    int amb = 0;
+    if (!occluded(s, Xs, dl, INFINITY, &amb)) *vis |= 1u << li;
+    if (amb) *flags |= ORC_F_SHADOW;
+  }
+  for (int32_t l = 0; l < L->n_point; l++, li++) {
+    double u[3] = {L->point_pos[3 * l] - Xs[0], L->point_pos[3 * l + 1] - Xs[1], L->point_pos[3 * l + 2] - Xs[2]};
+    double dist = len3(u);
+    if (!(dist > 0.0)) continue;
+    double uh[3] = {u[0] / dist, u[1] / dist, u[2] / dist};
+    if (dot3(ng, uh) <= 0.0) continue;
+    int amb = 0;
+    if (!occluded(s, Xs, uh, dist * (1.0 - 1e-6), &amb)) *vis |= 1u << li;
+    if (amb) *flags |= ORC_F_SHADOW;
+  }
+}
+
 /* Section "Probe Update" (hit shading) and the backface rule of the
    self-shadow-bias section: a miss sees the sky at the distance clamp; a
    backface records radiance 0 and 20 % of its distance; a front face is
@@ -925,28 +970,7 @@ void orc_shade_ray(const orc_scene* s, const orc_lights* L, const orc_volume* vo
   double X[3];
   for (int a = 0; a < 3; a++) X[a] = o[a] + h.t * w[a];
   int32_t m = s->material[h.tri];
-  /* shadow rays from the lifted hit point; any triangle, either side, occludes */
-  double xmax = fmax(fabs(X[0]), fmax(fabs(X[1]), fabs(X[2])));
-  double eps = 1e-4 * fmax(1.0, xmax);
-  double Xs[3] = {X[0] + eps * ng[0], X[1] + eps * ng[1], X[2] + eps * ng[2]};
-  int32_t li = 0;
-  for (int32_t l = 0; l < L->n_dir; l++, li++) {
-    double dl[3] = {L->dir_to_light[3 * l], L->dir_to_light[3 * l + 1], L->dir_to_light[3 * l + 2]};
-    if (dot3(ng, dl) <= 0.0) continue;
-    int amb = 0;
-    if (!occluded(s, Xs, dl, INFINITY, &amb)) rec->vis |= 1u << li;
-    if (amb) rec->flags |= ORC_F_SHADOW;
-  }
-  for (int32_t l = 0; l < L->n_point; l++, li++) {
-    double u[3] = {L->point_pos[3 * l] - Xs[0], L->point_pos[3 * l + 1] - Xs[1], L->point_pos[3 * l + 2] - Xs[2]};
-    double dist = len3(u);
-    if (!(dist > 0.0)) continue;
-    double uh[3] = {u[0] / dist, u[1] / dist, u[2] / dist};
-    if (dot3(ng, uh) <= 0.0) continue;
-    int amb = 0;
-    if (!occluded(s, Xs, uh, dist * (1.0 - 1e-6), &amb)) rec->vis |= 1u << li;
-    if (amb) rec->flags |= ORC_F_SHADOW;
-  }
+  hit_visibility(s, L, X, ng, &rec->vis, &rec->flags);
   double kq[3];
   front_radiance(s, L, vols, nvol, m, X, ng, w, rec->vis, rec->rgb, kq, rec->cage, &rec->n_cage);
   /* float32 sensitivity: the query's own, rounding of the sum, and the
@@ -958,6 +982,81 @@ void orc_shade_ray(const orc_scene* s, const orc_lights* L, const orc_volume* vo
   front_radiance(s, L, vols, nvol, m, X2, ng, w, rec->vis, rgb2, kq2, NULL, NULL);
   for (int k = 0; k < 3; k++)
     rec->kappa[k] = s->albedo[m * 3 + k] * kq[k] + 8.0 * fabs(rec->rgb[k]) + fabs(rgb2[k] - rec->rgb[k]) / U32;
+}
+
+/* Section "Second Order Glossy": the mirror reflection ray of a surface
+   point X (normal n, direction toward the viewer v) from X lifted off the
+   surface; its hit is shaded as a probe-ray hit (emission, albedo times
+   direct light over pi plus the probes' irradiance) plus the hit material's
+   mirror reflectance times the probes' filtered radiance in the hit's own
+   mirror direction -- the second and later glossy bounces come from the
+   probes instead of further rays.  A miss sees the sky; a backface is
+   black.  kappa: float32 sensitivity as for a probe ray. */
+static void glossy_front(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol, int32_t m,
+                         const double Y[3], const double ng[3], const double r[3], uint32_t vis, double rgb[3],
+                         double kap[3], int32_t* cage, int32_t* n_cage) {
+  double kq[3];
+  front_radiance(s, L, vols, nvol, m, Y, ng, r, vis, rgb, kq, cage, n_cage);
+  double c = dot3(ng, r);
+  double r2[3] = {r[0] - 2.0 * c * ng[0], r[1] - 2.0 * c * ng[1], r[2] - 2.0 * c * ng[2]};
+  double wo[3] = {-r[0], -r[1], -r[2]}, g[3], kg[3];
+  orc_query_look(vols, nvol, Y, ng, wo, r2, g, kg, NULL, NULL);
+  for (int k = 0; k < 3; k++) {
+    rgb[k] += s->specular[m * 3 + k] * g[k];
+    kap[k] = s->albedo[m * 3 + k] * kq[k] + s->specular[m * 3 + k] * kg[k];
+  }
+}
+
+void orc_glossy(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol, const double X[3],
+                const double n[3], const double v[3], orc_ray_record* rec) {
+  double c = dot3(n, v);
+  double r[3] = {2.0 * c * n[0] - v[0], 2.0 * c * n[1] - v[1], 2.0 * c * n[2] - v[2]};
+  normalize3(r);
+  double xmax = fmax(fabs(X[0]), fmax(fabs(X[1]), fabs(X[2])));
+  double eps = 1e-4 * fmax(1.0, xmax);
+  double o[3] = {X[0] + eps * n[0], X[1] + eps * n[1], X[2] + eps * n[2]};
+  orc_hit h;
+  orc_trace(s, o, r, 0, &h);
+  memset(rec, 0, sizeof(*rec));
+  for (int i = 0; i < ORC_CAGE; i++) rec->cage[i] = -1;
+  rec->tri = h.tri;
+  rec->t = h.t;
+  rec->flags = h.flags;
+  if (h.tri < 0) {
+    for (int k = 0; k < 3; k++) rec->rgb[k] = L->sky[k];
+    return;
+  }
+  double e1[3], e2[3], ng[3];
+  sub3(tri_v(s, h.tri, 1), tri_v(s, h.tri, 0), e1);
+  sub3(tri_v(s, h.tri, 2), tri_v(s, h.tri, 0), e2);
+  cross3(e1, e2, ng);
+  normalize3(ng);
+  rec->cosi = fabs(dot3(r, ng));
+  if (dot3(r, ng) > 0.0) return;   /* backface: black */
+  double Y[3];
+  for (int a = 0; a < 3; a++) Y[a] = o[a] + h.t * r[a];
+  int32_t m = s->material[h.tri];
+  hit_visibility(s, L, Y, ng, &rec->vis, &rec->flags);
+  double kap[3];
+  glossy_front(s, L, vols, nvol, m, Y, ng, r, rec->vis, rec->rgb, kap, rec->cage, &rec->n_cage);
+  /* the hit point's float32 error along the ray, and the reflection
+     direction's (about u per component over the distance t) */
+  double ep = fmin(1e-2, U32 * (8.0 / fmax(rec->cosi, 1e-6) + 16.0 + 8.0 / fmax(h.t, 1e-6)));
+  double Y2[3], rgb2[3], kap2[3];
+  for (int a = 0; a < 3; a++) Y2[a] = o[a] + h.t * (1.0 + ep) * r[a];
+  glossy_front(s, L, vols, nvol, m, Y2, ng, r, rec->vis, rgb2, kap2, NULL, NULL);
+  for (int k = 0; k < 3; k++) rec->kappa[k] = kap[k] + 8.0 * fabs(rec->rgb[k]) + fabs(rgb2[k] - rec->rgb[k]) / U32;
+}
+
+void orc_glossy_batch(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol, int64_t n,
+                      const float* pos, const float* nrm, const float* view, orc_ray_record* recs) {
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; i++) {
+    double X[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+    double nn[3] = {nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]};
+    double v[3] = {view[3 * i], view[3 * i + 1], view[3 * i + 2]};
+    orc_glossy(s, L, vols, nvol, X, nn, v, &recs[i]);
+  }
 }
 
 /* ----------------------------------------------------------------- states */

@@ -41,6 +41,7 @@ orc_scene* orc_scene_create(const float* vertices, int64_t n_vertices,
                             const float* albedo, const float* emission, int32_t n_materials);
 void orc_scene_free(orc_scene* s);
 void orc_scene_set_emission(orc_scene* s, const double* emission); /* [M][3] */
+void orc_scene_set_specular(orc_scene* s, const double* specular); /* [M][3], mirror reflectance */
 int64_t orc_scene_bvh_nodes(const orc_scene* s);
 
 typedef struct {
@@ -202,6 +203,20 @@ void orc_query_backward(const orc_volume* vols, int32_t nvol, const double X[3],
 void orc_update_backward(const orc_scene* s, const orc_volume* prev, int32_t nvol, const float R[9],
                          const orc_ray_record* records, const orc_grads* Gnew, const orc_grads* Gprev,
                          double* g_emission);
+
+/* ---- query with the texels sampled in direction `look` (filtered radiance) ---- */
+void orc_query_look(const orc_volume* vols, int32_t nvol, const double X[3], const double n[3],
+                    const double wo[3], const double look[3], double out[3], double kappa[3], int32_t* cage,
+                    int32_t* n_cage);
+
+/* ---- second-order glossy (Section "Second Order Glossy"): the mirror ray of
+   surface point X (normal n, toward-viewer v) and its shaded hit, whose own
+   mirror bounce is the probes' filtered radiance; record fields as for a
+   probe ray (d unused) ---- */
+void orc_glossy(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol, const double X[3],
+                const double n[3], const double v[3], orc_ray_record* rec);
+void orc_glossy_batch(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol, int64_t n,
+                      const float* pos, const float* nrm, const float* view, orc_ray_record* recs);
 
 /* ---- shading of a single ray from o along w (exposed for pins) ---- */
 void orc_shade_ray(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol,

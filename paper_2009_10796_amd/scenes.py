@@ -112,6 +112,12 @@ class Scene:
     tri_object: np.ndarray     # uint32 [T]
     albedo: np.ndarray         # float32 [M, 3]
     emission: np.ndarray       # float32 [M, 3]
+    specular: np.ndarray = None  # float32 [M, 3] mirror reflectance (second-order glossy); None = 0
+
+    def specular_or_zero(self) -> np.ndarray:
+        if self.specular is None:
+            return np.zeros_like(self.albedo)
+        return np.asarray(self.specular, dtype=np.float32).reshape(-1, 3)
 
     @property
     def n_triangles(self) -> int:
