@@ -198,6 +198,43 @@ def terrain_batched(irf, torch, frames=60):
             "tuning": tuning}
 
 
+def glossy_timing(irf, torch, reps=20):
+    """Second-order glossy over the city's G-buffer at quarter resolution
+    (every 4th pixel; mirror-reflective ground 0.3, buildings 0.1): mirror
+    ray, its shadow rays and two probe lookups per point, after two update
+    frames; median time over `reps`."""
+    from paper_2009_10796_amd import scenes as S
+    w = S.config1()
+    spec = np.full((w.scene.albedo.shape[0], 3), 0.1, np.float32)
+    spec[0] = 0.3
+    w.scene.specular = spec
+    ctx = irf.build_workload(w, device=0)
+    ctx.classify(w.classify_rotations)
+    for f in (1, 2):
+        ctx.update_probes(w.frame_rotation(f))
+    q = w.queries
+    sel = np.arange(0, q.n, 4)
+    pos, nrm, view = (torch.from_numpy(np.ascontiguousarray(a[sel])).cuda() for a in (q.pos, q.nrm, q.view))
+    for _ in range(3):
+        ctx.glossy(pos, nrm, view)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(reps):
+        ev0.record()
+        ctx.glossy(pos, nrm, view)
+        ev1.record()
+        ev1.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+    _, rec = ctx.glossy(pos, nrm, view, records=True)
+    ctx.close()
+    ms = float(np.median(times))
+    n = int(len(sel))
+    shadow = int(sum(bin(int(x)).count("1") for x in rec["vis"]))
+    return {"workload": w.name + "-glossy-quarter-res", "points": n, "ms": round(ms, 4),
+            "points_per_s": round(n / (ms * 1e-3), 1), "hits": int((rec["tri"] >= 0).sum()),
+            "unblocked_shadow_rays": shadow}
+
+
 def adjoint_timing(irf, torch, reps=10):
     """The differentiable frame at full size (city volume, 64 emissive quads,
     65,536 surface points): forward frame with its inputs saved, query,
@@ -273,7 +310,8 @@ def main():
     ap.add_argument("--no-blend-variants", action="store_true")
     ap.add_argument("--no-terrain", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--only", choices=["terrain", "adjoint"],
+    ap.add_argument("--no-glossy", action="store_true")
+    ap.add_argument("--only", choices=["terrain", "adjoint", "glossy"],
                     help="run one secondary section alone and print its JSON (for per-section profiles)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 256 MiB device-to-device three times before timing (a known-size kernel for "
@@ -289,7 +327,7 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     if args.only:
-        fn = terrain_batched if args.only == "terrain" else adjoint_timing
+        fn = {"terrain": terrain_batched, "adjoint": adjoint_timing, "glossy": glossy_timing}[args.only]
         print(json.dumps({"section": args.only, **fn(irf, torch)}), flush=True)
         return
     t_setup = time.perf_counter()
@@ -425,6 +463,9 @@ def main():
     if not args.no_terrain:
         print("[bench] terrain (batched cascades) ...", file=sys.stderr, flush=True)
         line["batched"] = terrain_batched(irf, torch)
+    if not args.no_glossy:
+        print("[bench] second-order glossy ...", file=sys.stderr, flush=True)
+        line["glossy"] = glossy_timing(irf, torch)
     if not args.no_adjoint:
         print("[bench] adjoint (differentiable frame) ...", file=sys.stderr, flush=True)
         line["adjoint"] = adjoint_timing(irf, torch)

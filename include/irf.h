@@ -81,7 +81,9 @@ void irf_destroy(irf_ctx* ctx);
                    means all static (classification rays see static triangles
                    only; dynamic objects wake nearby probes, Section "Full
                    Probe Initialization Algorithm")
-     albedo, emission [n_materials][3] (Lambertian albedo; emitted radiance) */
+     albedo, emission [n_materials][3] (Lambertian albedo; emitted radiance)
+     specular         [n_materials][3] mirror reflectance for the
+                   second-order glossy pass, or NULL (zero) */
 typedef struct {
   const float* vertices;
   int64_t n_vertices;
@@ -92,6 +94,7 @@ typedef struct {
   const float* albedo;
   const float* emission;
   int32_t n_materials;
+  const float* specular;
 } irf_scene_desc;
 irf_status irf_set_scene(irf_ctx* ctx, const irf_scene_desc* desc);
 
@@ -319,6 +322,23 @@ typedef struct {
 } irf_ray_record;
 irf_status irf_ray_records(irf_ctx* ctx, int32_t volume, irf_ray_record* out, int64_t capacity,
                            int64_t* count, void* stream);
+
+/* Second-order glossy (Section "Second Order Glossy"): for n surface points
+   (device float[n][3] positions, unit normals, unit directions toward the
+   viewer) the radiance arriving along each point's mirror direction,
+   out_rgb (device float[n][3]).  The mirror ray starts from the point lifted
+   off its surface by 1e-4 max(1, |X|inf); a miss sees the sky, a backface
+   is black; a front hit Y (material m, geometric normal ng) is shaded as a
+   probe-ray hit -- emission + albedo * (direct light / pi + the probes'
+   irradiance at Y) -- plus specular[m] times the probes' filtered radiance
+   in Y's own mirror direction (the query at Y with the texels sampled in
+   that direction), so second and later glossy bounces come from the
+   probes.  records (device, n entries, or NULL) receives per point the hit
+   triangle, distance, radiance and shadow visibility (d = 0, probe = -1).
+   n = 0 is valid.  Async. */
+irf_status irf_trace_glossy(irf_ctx* ctx, const float* pos, const float* nrm, const float* view, int64_t n,
+                            float* out_rgb, irf_ray_record* records, void* stream);
+
 
 /* Frame statistics of the last update (synchronizes `stream`):
    out[0] active probes, out[1] probe rays traced, out[2] shadow rays traced,

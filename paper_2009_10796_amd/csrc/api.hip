@@ -71,7 +71,7 @@ struct irf_ctx {
   int device = 0;
   // scene
   bool has_scene = false;
-  DevBuf<float4> nodes, tris, albedo, emission;
+  DevBuf<float4> nodes, tris, albedo, emission, specular;
   DevBuf<float> obj_lo, obj_hi;
   int32_t n_tris = 0, n_nodes = 0, n_materials = 0, n_obj = 0;
   double bvh_stats[5] = {0, 0, 0, 0, 0};
@@ -134,6 +134,7 @@ SceneGPU scene_view(const irf_ctx* c) {
   s.tris = c->tris.p;
   s.albedo = c->albedo.p;
   s.emission = c->emission.p;
+  s.specular = c->specular.p;
   s.n_tris = c->n_tris;
   s.n_nodes = c->n_nodes;
   s.stack_depth = (int32_t)c->bvh_stats[2];
@@ -427,6 +428,7 @@ void irf_destroy(irf_ctx* c) {
   c->wave_tasks.release();
   c->wave_offset.release();
   c->stats.release();
+  c->specular.release();
   c->saved.release();
   c->grad_rays.release();
   c->probe_pos.release();
@@ -510,22 +512,27 @@ irf_status irf_set_scene(irf_ctx* c, const irf_scene_desc* d) {
         blo.push_back(lo[(size_t)o * 3 + a]);
         bhi.push_back(hi[(size_t)o * 3 + a]);
       }
-  std::vector<float4> alb((size_t)d->n_materials), emi((size_t)d->n_materials);
+  std::vector<float4> alb((size_t)d->n_materials), emi((size_t)d->n_materials), spe((size_t)d->n_materials);
   for (int32_t m = 0; m < d->n_materials; m++) {
     alb[(size_t)m] = make_float4(d->albedo[3 * m], d->albedo[3 * m + 1], d->albedo[3 * m + 2], 0.0f);
     emi[(size_t)m] = make_float4(d->emission[3 * m], d->emission[3 * m + 1], d->emission[3 * m + 2], 0.0f);
+    spe[(size_t)m] = d->specular
+                         ? make_float4(d->specular[3 * m], d->specular[3 * m + 1], d->specular[3 * m + 2], 0.0f)
+                         : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
   HIP_TRY(hipDeviceSynchronize());
   if ((s = c->nodes.reserve(nodes.size())) != IRF_OK) return s;
   if ((s = c->tris.reserve(tris.size())) != IRF_OK) return s;
   if ((s = c->albedo.reserve(alb.size())) != IRF_OK) return s;
   if ((s = c->emission.reserve(emi.size())) != IRF_OK) return s;
+  if ((s = c->specular.reserve(spe.size())) != IRF_OK) return s;
   if ((s = c->obj_lo.reserve(blo.size())) != IRF_OK) return s;
   if ((s = c->obj_hi.reserve(bhi.size())) != IRF_OK) return s;
   if (!nodes.empty()) HIP_TRY(hipMemcpy(c->nodes.p, nodes.data(), nodes.size() * sizeof(float4), hipMemcpyHostToDevice));
   if (!tris.empty()) HIP_TRY(hipMemcpy(c->tris.p, tris.data(), tris.size() * sizeof(float4), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->albedo.p, alb.data(), alb.size() * sizeof(float4), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->emission.p, emi.data(), emi.size() * sizeof(float4), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->specular.p, spe.data(), spe.size() * sizeof(float4), hipMemcpyHostToDevice));
   if (!blo.empty()) {
     HIP_TRY(hipMemcpy(c->obj_lo.p, blo.data(), blo.size() * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->obj_hi.p, bhi.data(), bhi.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -1003,6 +1010,19 @@ void irf_graph_destroy(irf_graph* g) {
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
+}
+
+irf_status irf_trace_glossy(irf_ctx* c, const float* pos, const float* nrm, const float* view, int64_t n,
+                            float* out_rgb, irf_ray_record* records, void* stream) {
+  if (!c) return fail(IRF_E_INVALID, "ctx is NULL");
+  if (n < 0) return fail(IRF_E_INVALID, "n < 0");
+  if (n == 0) return IRF_OK;
+  if (!pos || !nrm || !view || !out_rgb) return fail(IRF_E_INVALID, "NULL array");
+  irf_status s = check_ready(c);
+  if (s != IRF_OK) return s;
+  if ((s = set_device(c)) != IRF_OK) return s;
+  launch_glossy(volume_view(c), scene_view(c), c->lights, pos, nrm, view, n, out_rgb, records, (hipStream_t)stream);
+  return launched();
 }
 
 irf_status irf_set_differentiable(irf_ctx* c, int32_t enable) {

@@ -248,7 +248,10 @@ __device__ __forceinline__ float3 irr_texel_update(const VolumeGPU& V, float alp
 // One volume's 8-probe cage (Section "Probe Query"): trilinear x backface x
 // Chebyshev visibility at the point moved by the self-shadow bias (Eq. 1);
 // normalised.  Returns false when no probe carries weight.
-__device__ inline float3 volume_query(const VolumeGPU& V, float3 X, float3 n, float3 wo) {
+// `look`: the direction the irradiance texels are sampled in (the normal for
+// the irradiance query; the second-order glossy pass samples the probes'
+// filtered radiance in a mirror direction).
+__device__ inline float3 volume_query(const VolumeGPU& V, float3 X, float3 n, float3 wo, float3 look) {
   float u[3] = {(X.x - V.origin[0]) / V.spacing[0], (X.y - V.origin[1]) / V.spacing[1],
                 (X.z - V.origin[2]) / V.spacing[2]};
   int g[3];
@@ -263,10 +266,10 @@ __device__ inline float3 volume_query(const VolumeGPU& V, float3 X, float3 n, fl
   float sb = 0.75f * D * V.bias;
   float3 Xb = f3(fmaf(fmaf(0.2f, n.x, 0.8f * wo.x), sb, X.x), fmaf(fmaf(0.2f, n.y, 0.8f * wo.y), sb, X.y),
                  fmaf(fmaf(0.2f, n.z, 0.8f * wo.z), sb, X.z));
-  // the irradiance lookup direction is the normal for every probe of the cage
+  // the irradiance lookup direction is the same for every probe of the cage
   int ix, iy;
   float ifx, ify;
-  tile_footprint_fast<kIrrTile>(n, ix, iy, ifx, ify);
+  tile_footprint_fast<kIrrTile>(look, ix, iy, ifx, ify);
   const int irr_off = iy * kIrrTile + ix;
   float3 acc = f3(0.0f, 0.0f, 0.0f);
   float W = 0.0f;
@@ -347,7 +350,7 @@ __device__ __forceinline__ float volume_weight(const VolumeGPU& V, float3 X) {
 // Cascaded volumes (Section "Multiple Probe Volumes"): densest first, linear
 // fall-off over the last cell of each axis (product of axes), accumulate
 // until the weights reach one; the sparsest volume takes the remainder.
-__device__ inline float3 query_irradiance(const VolumeSet& vs, float3 X, float3 n, float3 wo) {
+__device__ inline float3 query_look(const VolumeSet& vs, float3 X, float3 n, float3 wo, float3 look) {
   float3 E = f3(0.0f, 0.0f, 0.0f);
   float Wt = 0.0f;
   for (int v = 0; v < vs.n; v++) {
@@ -356,11 +359,15 @@ __device__ inline float3 query_irradiance(const VolumeSet& vs, float3 X, float3 
     float wv = volume_weight(V, X);
     float wuse = (v == vs.n - 1) ? 1.0f - Wt : fminf(wv, 1.0f - Wt);
     if (wuse > 0.0f) {
-      E = E + wuse * volume_query(V, X, n, wo);
+      E = E + wuse * volume_query(V, X, n, wo, look);
       Wt += wuse;
     }
   }
   return E;
+}
+
+__device__ inline float3 query_irradiance(const VolumeSet& vs, float3 X, float3 n, float3 wo) {
+  return query_look(vs, X, n, wo, n);
 }
 
 }  // namespace irf

@@ -118,6 +118,7 @@ struct SceneGPU {
   const float4* tris;      // [n_tris][3]   (v0 | orig id, v1 | object, v2 | material)
   const float4* albedo;    // [M]
   const float4* emission;  // [M]
+  const float4* specular;  // [M] mirror reflectance (second-order glossy)
   int32_t n_tris;
   int32_t n_nodes;
   int32_t stack_depth;     // traversal stack entries needed (BVH depth)
@@ -196,6 +197,8 @@ void launch_query_backward(const VolumeSet& vs, const float* pos, const float* n
                            const float* gout, const GradSet& G, hipStream_t s);
 void launch_update_backward(const VolumeSet& prev, SceneGPU sc, FrameScratch fs, const GradSet& Gnew,
                             const GradSet& Gprev, float* g_emission, hipStream_t s);
+void launch_glossy(const VolumeSet& vs, SceneGPU sc, const LightSet& L, const float* pos, const float* nrm,
+                   const float* view, int64_t n, float* out, irf_ray_record* rec, hipStream_t s);
 void launch_frame_stats(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, unsigned long long* out, hipStream_t s);
 void launch_records(const VolumeSet& vs, int vol, SceneGPU sc, FrameScratch fs, int n_lights,
                     irf_ray_record* out, int64_t count, hipStream_t s);

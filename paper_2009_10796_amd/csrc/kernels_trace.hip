@@ -530,6 +530,94 @@ __global__ void k_classify_finish(VolumeSet vs, ObjectBoxes ob, int K, const int
   V.states[q] = st;
 }
 
+// ---- second-order glossy (Section "Second Order Glossy")
+//
+// One thread per surface point: the mirror ray, its nearest hit, the hit's
+// shadow rays, and the shading of the hit with the probes (irradiance at the
+// hit; filtered radiance in the hit's own mirror direction for the further
+// glossy bounces).
+
+__global__ __launch_bounds__(kTraceBlock) void k_glossy(VolumeSet vs, SceneGPU sc, LightSet L,
+                                                        const float* __restrict__ pos, const float* __restrict__ nrm,
+                                                        const float* __restrict__ view, int64_t n,
+                                                        float* __restrict__ out, irf_ray_record* rec) {
+  const int64_t i = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
+  if (i >= n) return;
+  const float3 X = f3(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]);
+  const float3 N = f3(nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]);
+  const float3 Vw = f3(view[3 * i], view[3 * i + 1], view[3 * i + 2]);
+  const float c = dot(N, Vw);
+  const float3 r = normalize_or_zero(f3(fmaf(2.0f * c, N.x, -Vw.x), fmaf(2.0f * c, N.y, -Vw.y),
+                                        fmaf(2.0f * c, N.z, -Vw.z)));
+  const float3 o = shadow_origin(X, N);
+  float t;
+  const int tri = traverse<false, false>(sc, make_ray(o, r), INFINITY, t, dyn_stack + threadIdx.x, kTraceBlock);
+  float3 rgb = f3(0.0f, 0.0f, 0.0f);
+  uint32_t vis = 0;
+  if (tri < 0) {
+    rgb = f3(L.sky[0], L.sky[1], L.sky[2]);
+  } else {
+    const float3 ng = tri_normal(sc, tri);
+    if (dot(r, ng) <= 0.0f) {   // a backface is black
+      const float3 Y = f3(fmaf(t, r.x, o.x), fmaf(t, r.y, o.y), fmaf(t, r.z, o.z));
+      const float3 Ys = shadow_origin(Y, ng);
+      float3 direct = f3(0.0f, 0.0f, 0.0f);
+      const int nl = L.n_dir + L.n_point;
+      for (int l = 0; l < nl; l++) {
+        float3 Xs, dl;
+        float tmax;
+        if (!shadow_ray(L, l, Y, ng, Xs, dl, tmax)) continue;
+        float ts;
+        if (traverse<true, false>(sc, make_ray(Xs, dl), tmax, ts, dyn_stack + threadIdx.x, kTraceBlock) >= 0) continue;
+        vis |= 1u << l;
+        if (l < L.n_dir) {
+          const float cl = dot(ng, f3(L.dir[l][0], L.dir[l][1], L.dir[l][2]));
+          direct = direct + cl * f3(L.irr[l][0], L.irr[l][1], L.irr[l][2]);
+        } else {
+          const int p = l - L.n_dir;
+          const float3 u = f3(L.pos[p][0], L.pos[p][1], L.pos[p][2]) - Ys;
+          const float dist = length(u);
+          const float cl = dot(ng, (1.0f / dist) * u);
+          direct = direct + (cl / (dist * dist)) * f3(L.irr[l][0], L.irr[l][1], L.irr[l][2]);
+        }
+      }
+      const float3 wo = f3(-r.x, -r.y, -r.z);
+      const float3 E = query_irradiance(vs, Y, ng, wo);
+      const float cr = dot(ng, r);
+      const float3 r2 = f3(fmaf(-2.0f * cr, ng.x, r.x), fmaf(-2.0f * cr, ng.y, r.y), fmaf(-2.0f * cr, ng.z, r.z));
+      const float3 G = query_look(vs, Y, ng, wo, r2);
+      const int m = bits_i(sc.tris[(size_t)tri * 3 + 2].w);
+      const float4 al = sc.albedo[m], em = sc.emission[m], sp = sc.specular[m];
+      const float inv_pi = 0.318309886183790672f;
+      rgb = f3(fmaf(sp.x, G.x, fmaf(al.x, fmaf(direct.x, inv_pi, E.x), em.x)),
+               fmaf(sp.y, G.y, fmaf(al.y, fmaf(direct.y, inv_pi, E.y), em.y)),
+               fmaf(sp.z, G.z, fmaf(al.z, fmaf(direct.z, inv_pi, E.z), em.z)));
+    }
+  }
+  out[3 * i] = rgb.x;
+  out[3 * i + 1] = rgb.y;
+  out[3 * i + 2] = rgb.z;
+  if (rec) {
+    irf_ray_record q;
+    q.tri = tri >= 0 ? bits_i(sc.tris[(size_t)tri * 3].w) : -1;
+    q.t = tri >= 0 ? t : INFINITY;
+    q.rgb[0] = rgb.x;
+    q.rgb[1] = rgb.y;
+    q.rgb[2] = rgb.z;
+    q.d = 0.0f;
+    q.vis = vis;
+    q.probe = -1;
+    rec[i] = q;
+  }
+}
+
+void launch_glossy(const VolumeSet& vs, SceneGPU sc, const LightSet& L, const float* pos, const float* nrm,
+                   const float* view, int64_t n, float* out, irf_ray_record* rec, hipStream_t s) {
+  if (n == 0) return;
+  irf_launch(k_glossy, dim3(blocks_for(n, kTraceBlock)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, L, pos, nrm,
+             view, n, out, rec);
+}
+
 // ---- tracking window: probes of entering planes start over (zero texels
 // and offsets; the caller then classifies them)
 

@@ -33,7 +33,8 @@ class IrfError(RuntimeError):
 class SceneDesc(C.Structure):
     _fields_ = [("vertices", C.c_void_p), ("n_vertices", C.c_int64), ("indices", C.c_void_p),
                 ("n_triangles", C.c_int64), ("tri_material", C.c_void_p), ("tri_object", C.c_void_p),
-                ("albedo", C.c_void_p), ("emission", C.c_void_p), ("n_materials", C.c_int32)]
+                ("albedo", C.c_void_p), ("emission", C.c_void_p), ("n_materials", C.c_int32),
+                ("specular", C.c_void_p)]
 
 
 class LightsDesc(C.Structure):
@@ -94,6 +95,7 @@ SIGNATURES = {
     "irf_optimize_probes": (C.c_int, [_vp, _vp, _i32, C.c_float, _vp]),
     "irf_track_volume": (C.c_int, [_vp, _i32, _vp, _vp, _i32, _vp, _vp]),
     "irf_volume_window": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
+    "irf_trace_glossy": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "irf_set_differentiable": (C.c_int, [_vp, _i32]),
     "irf_set_emission": (C.c_int, [_vp, _vp, _vp]),
     "irf_query_backward": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
@@ -137,11 +139,13 @@ def _ptr(a: np.ndarray):
 
 
 def scene_desc(scene):
+    spec = scene.specular_or_zero() if hasattr(scene, "specular_or_zero") else np.zeros_like(scene.albedo)
     keep = [_np(scene.vertices, np.float32), _np(scene.indices, np.uint32), _np(scene.tri_material, np.uint32),
-            _np(scene.tri_object, np.uint32), _np(scene.albedo, np.float32), _np(scene.emission, np.float32)]
+            _np(scene.tri_object, np.uint32), _np(scene.albedo, np.float32), _np(scene.emission, np.float32),
+            _np(spec, np.float32)]
     d = SceneDesc(_ptr(keep[0]), keep[0].shape[0], _ptr(keep[1]), keep[1].shape[0], _ptr(keep[2]),
                   _ptr(keep[3]), keep[4].ctypes.data_as(C.c_void_p), keep[5].ctypes.data_as(C.c_void_p),
-                  keep[4].shape[0])
+                  keep[4].shape[0], keep[6].ctypes.data_as(C.c_void_p))
     return d, keep
 
 
@@ -301,6 +305,21 @@ class Context:
                                            C.c_void_p(view.data_ptr()), n, C.c_void_p(out.data_ptr()),
                                            _stream(self.torch)))
         return out
+
+    def glossy(self, pos, nrm, view, records: bool = False):
+        """Second-order glossy: radiance along each point's mirror direction
+        [n, 3] (and the per-point records when asked)."""
+        torch = self.torch
+        n = int(pos.shape[0])
+        out = torch.empty((n, 3), dtype=torch.float32, device=self.device)
+        rec = torch.empty((max(1, n) * RECORD_DTYPE.itemsize,), dtype=torch.uint8, device=self.device) if records else None
+        _check(load().irf_trace_glossy(self.handle, C.c_void_p(pos.data_ptr()), C.c_void_p(nrm.data_ptr()),
+                                       C.c_void_p(view.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                       C.c_void_p(rec.data_ptr()) if rec is not None else None, _stream(torch)))
+        if not records:
+            return out
+        torch.cuda.current_stream().synchronize()
+        return out, rec[: n * RECORD_DTYPE.itemsize].cpu().numpy().view(RECORD_DTYPE)
 
     # ---- adjoint
 
