@@ -344,6 +344,13 @@ def main():
     setup_s = time.perf_counter() - t_setup
     print(f"[bench] setup {setup_s:.1f}s, {w.scene.n_triangles} triangles, {q.n} queries", file=sys.stderr, flush=True)
 
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     f = 0
     for _ in range(max(1, args.warmup)):
         ctx.update_probes(R[f])
