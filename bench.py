@@ -124,8 +124,7 @@ def blend_variants(w, R, frames, irf, torch):
         prof = ctx.profile_read(reset=True)
         irr = ctx.volumes[0].irradiance[..., :3].float().cpu().numpy().astype(np.float64)
         bk = [k for k in prof if k.startswith("blend")][0]
-        t_us = 1e3 * prof[bk][1] / prof[bk][0] + (1e3 * prof["weights"][1] / prof["weights"][0]
-                                                    if "weights" in prof else 0.0)
+        t_us = 1e3 * prof[bk][1] / prof[bk][0]
         key = mode + ("+f16atlas" if f16 else "")
         if ref is None:
             ref = irr

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libirf.so")
-SOURCES = ["api.hip", "bvh_build.cpp", "kernels_trace.hip", "kernels_update.hip", "kernels_blend.hip", "kernels_adjoint.hip"]
+SOURCES = ["api.hip", "bvh_build.cpp", "kernels_frame.hip", "kernels_trace.hip", "kernels_update.hip", "kernels_blend.hip", "kernels_adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

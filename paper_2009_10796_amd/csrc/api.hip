@@ -94,6 +94,7 @@ struct irf_ctx {
   DevBuf<uint32_t> shadow_tasks;
   DevBuf<int32_t> wave_tasks;
   DevBuf<int64_t> wave_offset;
+  DevBuf<int32_t> batch_wave;
   DevBuf<unsigned long long> stats;
   DevBuf<char> weights;
   DevBuf<float> inv_row_sum;
@@ -190,7 +191,8 @@ irf_status ensure_scratch(irf_ctx* c) {
   if ((s = c->rays.reserve((size_t)R)) != IRF_OK) return s;
   if ((s = c->shadow_tasks.reserve((size_t)((R + 63) / 64 * 64) * (size_t)(nl > 0 ? nl : 1))) != IRF_OK) return s;
   if ((s = c->wave_tasks.reserve((size_t)((R + 63) / 64))) != IRF_OK) return s;
-  if ((s = c->wave_offset.reserve((size_t)((R + 63) / 64))) != IRF_OK) return s;
+  if ((s = c->wave_offset.reserve((size_t)((R + 63) / 64 + 1))) != IRF_OK) return s;
+  if ((s = c->batch_wave.reserve((size_t)((R + 63) / 64) * (size_t)(nl > 0 ? nl : 1))) != IRF_OK) return s;
   if ((s = c->stats.reserve(8)) != IRF_OK) return s;
   if (c->diff) {
     int64_t off = 0;
@@ -227,6 +229,7 @@ FrameScratch scratch_view(const irf_ctx* c) {
   f.shadow_tasks = c->shadow_tasks.p;
   f.wave_tasks = c->wave_tasks.p;
   f.wave_offset = c->wave_offset.p;
+  f.batch_wave = c->batch_wave.p;
   f.grad_rays = c->grad_rays.p;
   f.probe_pos = c->probe_pos.p;
   f.weights = c->weights.p;
@@ -304,8 +307,12 @@ void enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st) {
   FrameParams fp;
   for (int i = 0; i < 9; i++) fp.R[i] = rotation[i];
   fp.L = c->lights;
-  launch_set_params(fp, fs, st);
-  { ProfScope p(c, "state_compact", st); launch_state_compact(vs, boxes_view(c), fs, st); }
+  bool any_mma = false, any_valu = false;
+  for (int v = 0; v < c->n_vol; v++) (c->vol[v].blend == IRF_BLEND_F32_VALU ? any_valu : any_mma) = true;
+  {
+    ProfScope p(c, "frame_begin", st);
+    launch_frame_begin(make_frame_begin(fp, vs, boxes_view(c), fs, any_mma), st);
+  }
   if (c->diff) {
     // the frame's inputs for the adjoint: atlases and the stepped states
     for (int v = 0; v < c->n_vol; v++) {
@@ -314,13 +321,6 @@ void enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st) {
       launch_copy(c->saved.p + c->saved_dist[v], c->vol[v].dist, P * kDistTexels * 2 * es, st);
       launch_copy(c->saved.p + c->saved_states[v], c->vol[v].states, P, st);
     }
-  }
-  { ProfScope p(c, "directions", st); launch_directions(vs, fs, st); }
-  bool any_mma = false, any_valu = false;
-  for (int v = 0; v < c->n_vol; v++) (c->vol[v].blend == IRF_BLEND_F32_VALU ? any_valu : any_mma) = true;
-  if (any_mma) {
-    ProfScope p(c, "weights", st);
-    launch_weights(vs, fs, st);
   }
   { ProfScope p(c, "trace", st); launch_trace(vs, sc, fs, c->tune.trace_blocks, st); }
   if (nl > 0) {
@@ -333,8 +333,8 @@ void enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st) {
     launch_blend(vs, fs, st);
   }
   if (any_mma) {
-    { ProfScope p(c, "blend_mma", st); launch_blend_mma(vs, fs, c->tune.blend_blocks, st); }
-    { ProfScope p(c, "promote", st); launch_promote(fs, vs, st); }
+    ProfScope p(c, "blend_mma", st);
+    launch_blend_mma(vs, fs, c->tune.blend_blocks, st);
   }
 }
 
@@ -427,6 +427,7 @@ void irf_destroy(irf_ctx* c) {
   c->shadow_tasks.release();
   c->wave_tasks.release();
   c->wave_offset.release();
+  c->batch_wave.release();
   c->stats.release();
   c->specular.release();
   c->saved.release();
@@ -952,15 +953,15 @@ irf_status irf_graph_capture(irf_ctx* c, void* stream, irf_graph** out) {
   g->graph = graph;
   g->ctx = c;
   size_t n = 0;
-  HIP_TRY(hipGraphGetRootNodes(graph, nullptr, &n));
-  std::vector<hipGraphNode_t> roots(n);
-  if (n) HIP_TRY(hipGraphGetRootNodes(graph, roots.data(), &n));
-  for (auto node : roots) {
+  HIP_TRY(hipGraphGetNodes(graph, nullptr, &n));
+  std::vector<hipGraphNode_t> nodes(n);
+  if (n) HIP_TRY(hipGraphGetNodes(graph, nodes.data(), &n));
+  for (auto node : nodes) {
     hipGraphNodeType type;
     if (hipGraphNodeGetType(node, &type) != hipSuccess || type != hipGraphNodeTypeKernel) continue;
     hipKernelNodeParams kp;
     if (hipGraphKernelNodeGetParams(node, &kp) != hipSuccess) continue;
-    if (kp.func == set_params_kernel()) {
+    if (kp.func == frame_begin_kernel()) {
       g->params_node = node;
       g->kp = kp;
     }
@@ -993,8 +994,10 @@ irf_status irf_graph_launch(irf_ctx* c, irf_graph* g, const float* rotation, voi
   FrameParams fp;
   for (int i = 0; i < 9; i++) fp.R[i] = rotation[i];
   fp.L = c->lights;
-  FrameParams* dst = c->params.p;
-  void* args[2] = {&fp, &dst};
+  bool any_mma = false;
+  for (int v = 0; v < c->n_vol; v++) any_mma = any_mma || c->vol[v].blend != IRF_BLEND_F32_VALU;
+  FrameBegin fb = make_frame_begin(fp, volume_view(c), boxes_view(c), scratch_view(c), any_mma);
+  void* args[1] = {&fb};
   hipKernelNodeParams kp = g->kp;
   kp.kernelParams = args;
   kp.extra = nullptr;

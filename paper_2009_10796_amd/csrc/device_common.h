@@ -116,6 +116,28 @@ __device__ __forceinline__ void tile_footprint_fast(float3 v, int& x0, int& y0, 
   fy = clampf(cy - (float)y0, 0.0f, 1.0f);
 }
 
+// Rows of the matrix-core blend's weight matrix: the 36 irradiance interior
+// texels padded to 48, then the 196 distance interior texels padded to 208.
+constexpr int kRows = 256;
+constexpr int kIrrRows = 48;
+
+// Direction i of an n-ray spherical-Fibonacci pattern (Section "Probe
+// Update": the same rotated pattern for every probe of the frame), rotated by
+// the row-major matrix R.
+__device__ __forceinline__ float3 sf_direction(int i, int n, const float* R) {
+  // frac(i * golden ratio) exactly, from the 0.64 fixed-point golden ratio
+  uint64_t fr = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+  float f = (float)(fr >> 40) * 0x1p-24f;
+  float t = (float)(2 * i + 1) / (float)n;
+  float z = 1.0f - t;
+  float rr = sqrtf(t * (2.0f - t));
+  float sn, cs;
+  sincospif(2.0f * f, &sn, &cs);
+  float3 p = f3(rr * cs, rr * sn, z);
+  return f3(fmaf(R[0], p.x, fmaf(R[1], p.y, R[2] * p.z)), fmaf(R[3], p.x, fmaf(R[4], p.y, R[5] * p.z)),
+            fmaf(R[6], p.x, fmaf(R[7], p.y, R[8] * p.z)));
+}
+
 // Distance-blend weight cos^p of a positive cosine (square-and-multiply for
 // an integer exponent, so every kernel gets the same float32 value).
 __device__ __forceinline__ float pow_weight(float c, const VolumeGPU& V) {

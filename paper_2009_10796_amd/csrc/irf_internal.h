@@ -147,9 +147,12 @@ struct FrameScratch {
   uint32_t* shadow_tasks;   // [max_rays * n_lights]: per source wave of 64 rays, a slice of
                             // 64 * n_lights tasks (ray id << 5 | light), light-major
   int32_t* wave_tasks;      // [max_rays / 64] number of tasks in each slice
-  int64_t* wave_offset;     // [max_rays / 64] exclusive prefix sum of wave_tasks
+  int64_t* wave_offset;     // [max_rays / 64 + 1] exclusive prefix sum of wave_tasks, then the total
+  int32_t* batch_wave;      // [max_rays * n_lights / 64] slice holding the first task of each
+                            // batch of 64 consecutive tasks
   float4* grad_rays;        // [max_rays] adjoint: dLoss/d(ray radiance)
-  float4* probe_pos;        // [max_slots] position of each active probe this frame (by slot)
+  float4* probe_pos;        // [max_slots] position of each active probe this frame (by slot),
+                            // w = 1 for a Newly state (blended with no hysteresis), else 0
   void* weights;            // per volume: 256 weight rows x rays (float32 [k][row] or 16-bit [row][k])
   float* inv_row_sum;       // [n_volumes][256] 1 / sum of the stored weights of each row (0 = none)
   void* rays_lp;            // [max_rays] 4 x bf16/f16 (matrix-core path)
@@ -163,17 +166,29 @@ int build_bvh(const float* vertices, int64_t nv, const uint32_t* indices, int64_
               std::vector<float4>& nodes, std::vector<float4>& tris, double stats[5]);
 
 // ---- launches (kernels_*.hip); all asynchronous on `s`
-void launch_set_params(const FrameParams& p, FrameScratch fs, hipStream_t s);
-const void* set_params_kernel();
-void launch_directions(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
-void launch_state_compact(const VolumeSet& vs, ObjectBoxes boxes, FrameScratch fs, hipStream_t s);
+// Start of an update frame (kernels_frame.hip): the frame's parameters, ray
+// directions, matrix-core blend weights and the state step with the active
+// list, all in one kernel whose only argument is this struct (a captured
+// frame is re-launched with a new rotation by updating that one node).
+struct FrameBegin {
+  FrameParams p;
+  VolumeSet vs;
+  ObjectBoxes ob;
+  FrameScratch fs;
+  int32_t dir_blocks;    // workgroups of ray directions per volume
+  int32_t weight_rows;   // blend weight rows per volume (0: no matrix-core volume)
+  int32_t compact;       // 1: the last workgroup steps the states and packs the active list
+  int32_t total_probes;  // probes of every volume
+};
+FrameBegin make_frame_begin(const FrameParams& p, const VolumeSet& vs, ObjectBoxes ob, FrameScratch fs,
+                            bool weights);
+void launch_frame_begin(const FrameBegin& a, hipStream_t s);
+const void* frame_begin_kernel();
 void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s);
 void launch_scan_tasks(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
 void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, hipStream_t s);
 void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s);
 void launch_blend(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
-void launch_weights(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
-void launch_promote(FrameScratch fs, const VolumeSet& vs, hipStream_t s);
 void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, int grid, hipStream_t s);
 void launch_query(const VolumeSet& vs, const float* pos, const float* nrm, const float* view, int64_t n,
                   float* out, hipStream_t s);

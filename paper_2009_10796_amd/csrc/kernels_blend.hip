@@ -5,7 +5,7 @@
 //   new_E[texel][c]  = sum_r W_E[texel][r] L[r][c]      / sum_r W_E[texel][r]
 //   new_D[texel][j]  = sum_r W_D[texel][r] d[r]^(j+1)   / sum_r W_D[texel][r]
 // with W_E = max(0, n.w) and W_D = max(0, n.w)^p shared by all probes of a
-// volume (one rotation per frame).  k_weights builds W once per frame (rows:
+// volume (one rotation per frame).  k_frame_begin builds W once per frame (rows:
 // 36 irradiance interior texels padded to 48, then 196 distance interior
 // texels padded to 208) and the reciprocal row sums of the *stored* weights,
 // so a constant radiance is reproduced exactly whatever the input precision.
@@ -16,7 +16,8 @@
 // (16-bit inputs), float32 accumulation.  The epilogue normalises, applies the
 // hysteresis (0 for Newly states; for irradiance the stored encoding and the
 // per-texel thresholds of the convergence sections) and writes each texel and
-// the border cells that repeat it; k_promote then promotes Newly states.
+// the border cells that repeat it; the first row slice of each probe block
+// then promotes its Newly probes.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -27,72 +28,13 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
-constexpr int kRows = 256;        // 48 irradiance + 208 distance rows
-constexpr int kIrrRows = 48;
 constexpr int kPB = 8;            // probes per workgroup
-constexpr int kRSplit = 2;        // workgroups per probe block (row tiles split)
+constexpr int kRSplit = 4;        // workgroups per probe block (row tiles split)
+constexpr int kTilesPerWave = 16 / (4 * kRSplit);   // 16 row tiles over kRSplit workgroups of 4 waves
 constexpr int kKC = 256;          // rays per LDS chunk
 constexpr int kBlendMmaBlock = 256;
 constexpr int kBfStride = 49;     // float32 B tile: [k][48 + 1]
 constexpr int kBtStride = kKC + 8;// 16-bit B tile: [col][KC + 8]
-
-// Direction of weight row `row` (irradiance rows first), false for padding.
-__device__ __forceinline__ bool row_direction(int row, float3& n) {
-  if (row < kIrrRows) {
-    if (row >= 36) return false;
-    n = texel_direction<kIrrTile>(row % 6 + 1, row / 6 + 1);
-    return true;
-  }
-  int r = row - kIrrRows;
-  if (r >= 196) return false;
-  n = texel_direction<kDistTile>(r % 14 + 1, r / 14 + 1);
-  return true;
-}
-
-__device__ __forceinline__ float round_to(float w, int mode) {
-  if (mode == IRF_BLEND_BF16) return (float)(__bf16)w;
-  if (mode == IRF_BLEND_F16) return (float)(_Float16)w;
-  return w;
-}
-
-// One workgroup per (weight row, volume): the row's weights over all rays in
-// the volume's storage format, and 1 / (float32 sum of the stored weights).
-__global__ __launch_bounds__(256) void k_weights(VolumeSet vs, FrameScratch fs) {
-  __shared__ float part[256];
-  const int row = blockIdx.x, v = blockIdx.y;
-  if (v >= vs.n) return;
-  const VolumeGPU& V = vs.v[v];
-  if (V.blend == IRF_BLEND_F32_VALU) return;
-  const int N = V.rays;
-  float3 n = f3(0.0f, 0.0f, 0.0f);
-  bool real = row_direction(row, n);
-  float sum = 0.0f;
-  for (int k = threadIdx.x; k < N; k += 256) {
-    float w = 0.0f;
-    if (real) {
-      float4 o = fs.omega[V.omega_base + k];
-      float c = fmaf(n.x, o.x, fmaf(n.y, o.y, n.z * o.z));
-      w = c > 0.0f ? (row < kIrrRows ? c : pow_weight(c, V)) : 0.0f;
-    }
-    w = round_to(w, V.blend);
-    sum += w;
-    char* base = (char*)fs.weights + V.weight_base;
-    if (V.blend == IRF_BLEND_F32) {
-      ((float*)base)[(size_t)k * kRows + row] = w;               // [k][row]
-    } else if (V.blend == IRF_BLEND_BF16) {
-      ((__bf16*)base)[(size_t)row * N + k] = (__bf16)w;          // [row][k]
-    } else {
-      ((_Float16*)base)[(size_t)row * N + k] = (_Float16)w;
-    }
-  }
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) fs.inv_row_sum[v * kRows + row] = part[0] > 0.0f ? 1.0f / part[0] : 0.0f;
-}
 
 template <int MODE>
 struct Mma;
@@ -186,24 +128,27 @@ __device__ __forceinline__ float load_ch(const VolumeGPU& V, bool irr, int q, in
 
 template <int MODE>
 __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScratch& fs, const FrameCounters& C, int v,
-                                           int pblock, int split, char* lds, int* s_q, uint8_t* s_state) {
+                                           int pblock, int split, char* lds, int* s_q, bool* s_fresh) {
   const VolumeGPU& V = vs.v[v];
   const int count = C.slot_base[v + 1] - C.slot_base[v];
   const int slot0 = pblock * kPB;
   const int np = min(kPB, count - slot0);
   const int N = V.rays;
   if (threadIdx.x < kPB) {
-    int q = threadIdx.x < np ? fs.active[C.slot_base[v] + slot0 + threadIdx.x] - V.probe_base : -1;
-    s_q[threadIdx.x] = q;
-    s_state[threadIdx.x] = q >= 0 ? V.states[q] : (uint8_t)IRF_OFF;
+    const int gslot = C.slot_base[v] + slot0 + threadIdx.x;
+    const bool real = threadIdx.x < np;
+    s_q[threadIdx.x] = real ? fs.active[gslot] - V.probe_base : -1;
+    s_fresh[threadIdx.x] = real && fs.probe_pos[gslot].w != 0.0f;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // this wave's row tiles: the workgroup owns tiles rt = split, split + kRSplit, ...
-  // (8 of 16) and wave w takes the w-th and (w+4)-th of those
-  int rt_list[2] = {split + kRSplit * wave, split + kRSplit * (wave + 4)};
-  v4f acc[2][2];
+  // (16 / kRSplit of 16) and wave w takes the w-th, (w+4)-th, ... of those
+  int rt_list[kTilesPerWave];
 #pragma unroll
-  for (int i = 0; i < 2; i++)
+  for (int i = 0; i < kTilesPerWave; i++) rt_list[i] = split + kRSplit * (wave + 4 * i);
+  v4f acc[kTilesPerWave][2];
+#pragma unroll
+  for (int i = 0; i < kTilesPerWave; i++)
 #pragma unroll
     for (int j = 0; j < 2; j++) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
   const float4* rays = fs.rays + C.ray_base[v] + (int64_t)slot0 * N;
@@ -226,7 +171,7 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
     typedef Mma<MODE> M;
     const char* wbase = (const char*)fs.weights + V.weight_base;
 #pragma unroll
-    for (int i = 0; i < 2; i++) {
+    for (int i = 0; i < kTilesPerWave; i++) {
       const int rt = rt_list[i];
       for (int k0 = 0; k0 < kn; k0 += M::KB * M::KSTEP) {
         typename M::A a[M::KB];
@@ -248,7 +193,7 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
   // epilogue: lane holds rows rt*16 + 4*(lane/16) + r, column col_base + lane%16
   const float* inv = fs.inv_row_sum + v * kRows;
 #pragma unroll
-  for (int i = 0; i < 2; i++) {
+  for (int i = 0; i < kTilesPerWave; i++) {
     const int rt = rt_list[i];
     if (rt < 3) {
       // irradiance rows: lane%16 = p < 8 holds R (tile 0) and B (tile 1) of
@@ -260,9 +205,7 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
       for (int r = 0; r < 4; r++) gch[r] = __shfl_down(acc[i][0][r], 8, 16);
       if (p >= 8 || p >= np) continue;
       const int q = s_q[p];
-      const uint8_t st = s_state[p];
-      const bool fresh = st == IRF_NEWLY_AWAKE || st == IRF_NEWLY_VIGILANT;
-      const float a = fresh ? 0.0f : V.alpha_irr;
+      const float a = s_fresh[p] ? 0.0f : V.alpha_irr;
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int row = rt * 16 + 4 * (lane / 16) + r;
@@ -289,9 +232,7 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
     const int c = col - 32 < 8 ? 0 : 1;
     if (p >= np) continue;
     const int q = s_q[p];
-    const uint8_t st = s_state[p];
-    const bool fresh = st == IRF_NEWLY_AWAKE || st == IRF_NEWLY_VIGILANT;
-    const float a = fresh ? 0.0f : V.alpha_dist;
+    const float a = s_fresh[p] ? 0.0f : V.alpha_dist;
 #pragma unroll
     for (int r = 0; r < 4; r++) {
       const int row = rt * 16 + 4 * (lane / 16) + r;
@@ -312,7 +253,12 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
       if (x == 1 && y == 1) store_dist(V, q, 15, 15, c, val);
     }
   }
-  // Newly states are promoted by k_promote once every workgroup has read them.
+  // Newly states are promoted once blended (the Newly flag of this frame is
+  // the slot's, so no workgroup reads the state itself)
+  if (split == 0 && threadIdx.x < np && s_fresh[threadIdx.x]) {
+    const int q = s_q[threadIdx.x];
+    V.states[q] = V.states[q] == IRF_NEWLY_AWAKE ? IRF_AWAKE : IRF_VIGILANT;
+  }
 }
 
 // Persistent over work items (probe block x row split) of every volume whose
@@ -322,7 +268,7 @@ __global__ __launch_bounds__(kBlendMmaBlock) void k_blend_mma(VolumeSet vs, Fram
   constexpr int LDS_BYTES = MODE == IRF_BLEND_F32 ? kKC * kBfStride * 4 : 48 * kBtStride * 2;
   __shared__ __attribute__((aligned(16))) char lds[LDS_BYTES];
   __shared__ int s_q[kPB];
-  __shared__ uint8_t s_state[kPB];
+  __shared__ bool s_fresh[kPB];
   const FrameCounters& C = *fs.counters;
   int item_base[IRF_MAX_VOLUMES + 1];
   item_base[0] = 0;
@@ -334,27 +280,9 @@ __global__ __launch_bounds__(kBlendMmaBlock) void k_blend_mma(VolumeSet vs, Fram
     int v = 0;
     while (v + 1 < vs.n && wi >= item_base[v + 1]) v++;
     const int local = wi - item_base[v];
-    __syncthreads();   // the previous item's epilogue has finished with s_q / s_state
-    blend_item<MODE>(vs, fs, C, v, local / kRSplit, local % kRSplit, lds, s_q, s_state);
+    __syncthreads();   // the previous item's epilogue has finished with s_q / s_fresh
+    blend_item<MODE>(vs, fs, C, v, local / kRSplit, local % kRSplit, lds, s_q, s_fresh);
   }
-}
-
-__global__ void k_promote(VolumeSet vs, FrameScratch fs) {
-  const FrameCounters& C = *fs.counters;
-  int gslot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gslot >= C.slot_base[vs.n]) return;
-  int v = 0;
-  while (v + 1 < vs.n && gslot >= C.slot_base[v + 1]) v++;
-  const VolumeGPU& V = vs.v[v];
-  if (V.blend == IRF_BLEND_F32_VALU) return;   // that kernel promotes its own probes
-  int q = fs.active[gslot] - V.probe_base;
-  uint8_t st = V.states[q];
-  if (st == IRF_NEWLY_AWAKE) V.states[q] = IRF_AWAKE;
-  else if (st == IRF_NEWLY_VIGILANT) V.states[q] = IRF_VIGILANT;
-}
-
-void launch_weights(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
-  irf_launch(k_weights, dim3(kRows, vs.n), dim3(256), 0, s, vs, fs);
 }
 
 void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, int grid, hipStream_t s) {
@@ -372,10 +300,6 @@ void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, int grid, hipStream_
     irf_launch(k_blend_mma<IRF_BLEND_BF16>, dim3(g), dim3(kBlendMmaBlock), 0, s, vs, fs);
   if (mode_present[IRF_BLEND_F16])
     irf_launch(k_blend_mma<IRF_BLEND_F16>, dim3(g), dim3(kBlendMmaBlock), 0, s, vs, fs);
-}
-
-void launch_promote(FrameScratch fs, const VolumeSet& vs, hipStream_t s) {
-  if (fs.max_slots > 0) irf_launch(k_promote, dim3((fs.max_slots + 255) / 256), dim3(256), 0, s, vs, fs);
 }
 
 }  // namespace irf

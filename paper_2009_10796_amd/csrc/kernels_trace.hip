@@ -310,7 +310,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeSet vs, SceneGPU sc
     trace_one(vs, sc, L, fs, C, id);
 }
 
-// Exclusive prefix sum of the per-wave task counts (one workgroup).
+// Exclusive prefix sum of the per-wave task counts (one workgroup), with the
+// total as a sentinel after the last wave, and for every batch of 64
+// consecutive tasks the slice that holds its first task.
 constexpr int kScanBlock = 1024;
 __global__ __launch_bounds__(kScanBlock) void k_scan_tasks(VolumeSet vs, FrameScratch fs) {
   __shared__ int64_t part[kScanBlock];
@@ -330,29 +332,26 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tasks(VolumeSet vs, FrameSc
   }
   int64_t run = part[threadIdx.x] - sum;
   for (int64_t i = b; i < e; i++) {
+    const int64_t c = fs.wave_tasks[i];
     fs.wave_offset[i] = run;
-    run += fs.wave_tasks[i];
+    for (int64_t t = (run + 63) & ~63ll; t < run + c; t += 64) fs.batch_wave[t >> 6] = (int32_t)i;
+    run += c;
   }
-  if (threadIdx.x == kScanBlock - 1) C->shadow_total = part[kScanBlock - 1];
+  if (threadIdx.x == kScanBlock - 1) {
+    C->shadow_total = part[kScanBlock - 1];
+    fs.wave_offset[waves] = part[kScanBlock - 1];
+  }
 }
 
 // Any-hit shadow rays over the dense task index space: task k lives in the
-// slice of the last wave whose offset is <= k.  Grid-stride over all tasks.
-__device__ __forceinline__ int64_t task_wave(const FrameScratch& fs, const FrameCounters& C, int nvol, int64_t k) {
-  int64_t lo = 0, hi = (C.ray_base[nvol] + 63) / 64 - 1;
-  while (lo < hi) {
-    int64_t mid = (lo + hi + 1) >> 1;
-    if (fs.wave_offset[mid] <= k) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
+// slice of the last wave whose offset is <= k, found from the slice of the
+// first task of k's batch of 64.  Grid-stride over all tasks.
 template <typename CNT>
 __device__ __forceinline__ void shadow_one(const VolumeSet& vs, const SceneGPU& sc, const LightSet& L,
                                            const FrameScratch& fs, const FrameCounters& C, int64_t k, CNT* cnt) {
   const int nl = L.n_dir + L.n_point;
-  int64_t src = task_wave(fs, C, vs.n, k);
+  int64_t src = fs.batch_wave[k >> 6];
+  while (fs.wave_offset[src + 1] <= k) src++;
   uint32_t task = fs.shadow_tasks[src * 64 * nl + (k - fs.wave_offset[src])];
   int64_t id = task >> 5;
   int l = task & 31;
@@ -443,20 +442,6 @@ struct ClassifyArgs {
   int K;
   int64_t base[IRF_MAX_VOLUMES + 1];   // thread ranges per volume: P * K * N
 };
-
-__device__ __forceinline__ float3 sf_direction(int i, int n, const float* R) {
-  // frac(i * golden ratio) exactly, from the 0.64 fixed-point golden ratio
-  uint64_t fr = (uint64_t)i * 0x9E3779B97F4A7C15ull;
-  float f = (float)(fr >> 40) * 0x1p-24f;
-  float t = (float)(2 * i + 1) / (float)n;
-  float z = 1.0f - t;
-  float rr = sqrtf(t * (2.0f - t));
-  float sn, cs;
-  sincospif(2.0f * f, &sn, &cs);
-  float3 p = f3(rr * cs, rr * sn, z);
-  return f3(fmaf(R[0], p.x, fmaf(R[1], p.y, R[2] * p.z)), fmaf(R[3], p.x, fmaf(R[4], p.y, R[5] * p.z)),
-            fmaf(R[6], p.x, fmaf(R[7], p.y, R[8] * p.z)));
-}
 
 // Whether probe q of volume v is selected by the mask (every probe when
 // m.vol < 0; else the probes of volume m.vol on an entering plane).
@@ -875,7 +860,6 @@ void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, h
 }
 
 void launch_scan_tasks(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
-  if (fs.max_rays == 0) return;
   irf_launch(k_scan_tasks, dim3(1), dim3(kScanBlock), 0, s, vs, fs);
 }
 

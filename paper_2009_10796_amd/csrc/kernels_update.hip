@@ -1,10 +1,5 @@
-// Per-frame bookkeeping and the vector-ALU blend of the probe update, plus
-// the query kernel.
+// The vector-ALU blend of the probe update, and the query kernel.
 //
-//  k_directions     rotated spherical-Fibonacci ray directions of the frame
-//                   (one rotation shared by every probe of every volume)
-//  k_state_compact  per-frame state step (dynamic-object wake/sleep) and the
-//                   list of active probes, packed across volumes
 //  k_blend_f32      Eq. U per texel as a normalised weighted average with
 //                   hysteresis; one workgroup per active probe with the
 //                   probe's rays in LDS (the paper's coherent compute-shader
@@ -15,156 +10,6 @@
 #include "device_common.h"
 
 namespace irf {
-
-__device__ __forceinline__ float3 sf_dir(int i, int n, const float* R) {
-  // frac(i * golden ratio) exactly, from the 0.64 fixed-point golden ratio
-  uint64_t fr = (uint64_t)i * 0x9E3779B97F4A7C15ull;
-  float f = (float)(fr >> 40) * 0x1p-24f;
-  float t = (float)(2 * i + 1) / (float)n;
-  float z = 1.0f - t;
-  float rr = sqrtf(t * (2.0f - t));
-  float sn, cs;
-  sincospif(2.0f * f, &sn, &cs);
-  float3 p = f3(rr * cs, rr * sn, z);
-  return f3(fmaf(R[0], p.x, fmaf(R[1], p.y, R[2] * p.z)), fmaf(R[3], p.x, fmaf(R[4], p.y, R[5] * p.z)),
-            fmaf(R[6], p.x, fmaf(R[7], p.y, R[8] * p.z)));
-}
-
-// The frame's parameters (rotation, lights) are kernel arguments of this one
-// node, so a captured frame is re-launched with new ones by updating it.
-__global__ void k_set_params(FrameParams p, FrameParams* dst) {
-  if (threadIdx.x == 0) *dst = p;
-}
-
-__global__ void k_directions(VolumeSet vs, FrameScratch fs) {
-  int v = blockIdx.y;
-  if (v >= vs.n) return;
-  const VolumeGPU& V = vs.v[v];
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= V.rays) return;
-  float3 w = sf_dir(r, V.rays, fs.params->R);
-  fs.omega[V.omega_base + r] = make_float4(w.x, w.y, w.z, 0.0f);
-}
-
-__device__ __forceinline__ bool active_state(uint8_t s) {
-  return s == IRF_NEWLY_AWAKE || s == IRF_NEWLY_VIGILANT || s == IRF_AWAKE || s == IRF_VIGILANT;
-}
-
-__device__ __forceinline__ bool near_dynamic(const VolumeGPU& V, ObjectBoxes ob, float3 P) {
-  float D = fminf(V.spacing[0], fminf(V.spacing[1], V.spacing[2]));
-  float b = 0.75f * D * V.bias;
-  for (int o = 0; o < ob.n; o++) {
-    bool in = true;
-    float Pa[3] = {P.x, P.y, P.z};
-    for (int a = 0; a < 3; a++) {
-      float g = V.spacing[a] + b;
-      in = in && Pa[a] >= ob.lo[3 * o + a] - g && Pa[a] <= ob.hi[3 * o + a] + g;
-    }
-    if (in) return true;
-  }
-  return false;
-}
-
-constexpr int kCompactBlock = 1024;
-
-// Workgroups of volume v: [A.block_base[v], A.block_base[v+1]), each covering
-// kCompactBlock consecutive probes of that volume only.
-struct CompactArgs {
-  int32_t block_base[IRF_MAX_VOLUMES + 1];
-};
-
-__device__ __forceinline__ int compact_volume(const CompactArgs& A, int nvol, int b) {
-  int v = 0;
-  while (v + 1 < nvol && b >= A.block_base[v + 1]) v++;
-  return v;
-}
-
-// Pass 1: state step (dynamic-object wake/sleep) and the number of active
-// probes of every workgroup.
-__global__ __launch_bounds__(kCompactBlock) void k_state_count(VolumeSet vs, ObjectBoxes ob, CompactArgs A,
-                                                                FrameScratch fs) {
-  __shared__ int wave_tot[kCompactBlock / 64];
-  const int b = blockIdx.x;
-  const int v = compact_volume(A, vs.n, b);
-  const VolumeGPU& V = vs.v[v];
-  const int q = (b - A.block_base[v]) * kCompactBlock + threadIdx.x;
-  bool act = false;
-  if (q < V.n_probes) {
-    uint8_t st = V.states[q];
-    if (ob.n > 0 && (st == IRF_SLEEPING || st == IRF_AWAKE)) {
-      bool near = near_dynamic(V, ob, probe_position(V, q));
-      uint8_t ns = st;
-      if (st == IRF_SLEEPING && near) ns = IRF_NEWLY_AWAKE;
-      if (st == IRF_AWAKE && !near) ns = IRF_SLEEPING;
-      if (ns != st) V.states[q] = ns;
-      st = ns;
-    }
-    act = active_state(st);
-  }
-  unsigned long long m = __ballot(act);
-  if ((threadIdx.x & 63) == 0) wave_tot[threadIdx.x >> 6] = __popcll(m);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int t = 0;
-    for (int w = 0; w < kCompactBlock / 64; w++) t += wave_tot[w];
-    fs.block_active[b] = t;
-  }
-}
-
-// Pass 2: ordered scatter of the active list (ascending probe index within a
-// volume, volumes in order) and the per-volume slot and ray bases.
-__global__ __launch_bounds__(kCompactBlock) void k_state_scatter(VolumeSet vs, CompactArgs A, FrameScratch fs) {
-  __shared__ int wave_off[kCompactBlock / 64];
-  __shared__ int s_base;
-  const int b = blockIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int v = compact_volume(A, vs.n, b);
-  const VolumeGPU& V = vs.v[v];
-  // offset of this workgroup: active probes of all earlier workgroups
-  if (wave == 0) {
-    int part = 0;
-    for (int i = lane; i < b; i += 64) part += fs.block_active[i];
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off);
-    if (lane == 0) s_base = part;
-  }
-  const int q = (b - A.block_base[v]) * kCompactBlock + threadIdx.x;
-  const bool act = q < V.n_probes && active_state(V.states[q]);
-  unsigned long long m = __ballot(act);
-  if (lane == 0) wave_off[wave] = __popcll(m);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int w = 0; w < kCompactBlock / 64; w++) {
-      int t = wave_off[w];
-      wave_off[w] = acc;
-      acc += t;
-    }
-  }
-  __syncthreads();
-  if (act) {
-    const int slot = s_base + wave_off[wave] + __popcll(m & ((1ull << lane) - 1ull));
-    fs.active[slot] = V.probe_base + q;
-    const float3 P = probe_position(V, q);
-    fs.probe_pos[slot] = make_float4(P.x, P.y, P.z, 0.0f);
-  }
-  if (b == 0 && threadIdx.x == 0) {
-    FrameCounters C;
-    int slot = 0;
-    int64_t rays = 0;
-    for (int u = 0; u < vs.n; u++) {
-      C.slot_base[u] = slot;
-      C.ray_base[u] = rays;
-      int cnt = 0;
-      for (int i = A.block_base[u]; i < A.block_base[u + 1]; i++) cnt += fs.block_active[i];
-      slot += cnt;
-      rays += (int64_t)cnt * vs.v[u].rays;
-    }
-    C.slot_base[vs.n] = slot;
-    C.ray_base[vs.n] = rays;
-    C.shadow_total = 0;
-    *fs.counters = C;
-  }
-}
 
 // ---- blend (vector ALU, float32)
 
@@ -304,27 +149,6 @@ __global__ __launch_bounds__(kQueryBlock) void k_query(VolumeSet vs, const float
 // ---- launches
 
 static inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
-
-void launch_set_params(const FrameParams& p, FrameScratch fs, hipStream_t s) {
-  irf_launch(k_set_params, dim3(1), dim3(64), 0, s, p, fs.params);
-}
-
-const void* set_params_kernel() { return (const void*)k_set_params; }
-
-void launch_directions(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
-  int maxr = 0;
-  for (int v = 0; v < vs.n; v++) maxr = vs.v[v].rays > maxr ? vs.v[v].rays : maxr;
-  irf_launch(k_directions, dim3(nblocks(maxr, 256), vs.n), dim3(256), 0, s, vs, fs);
-}
-
-void launch_state_compact(const VolumeSet& vs, ObjectBoxes boxes, FrameScratch fs, hipStream_t s) {
-  CompactArgs A;
-  A.block_base[0] = 0;
-  for (int v = 0; v < vs.n; v++) A.block_base[v + 1] = A.block_base[v] + (vs.v[v].n_probes + kCompactBlock - 1) / kCompactBlock;
-  if (A.block_base[vs.n] == 0) return;
-  irf_launch(k_state_count, dim3(A.block_base[vs.n]), dim3(kCompactBlock), 0, s, vs, boxes, A, fs);
-  irf_launch(k_state_scatter, dim3(A.block_base[vs.n]), dim3(kCompactBlock), 0, s, vs, A, fs);
-}
 
 void launch_blend(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
   if (fs.max_slots == 0) return;
