@@ -19,6 +19,7 @@ constexpr int kTraceBlock = 128;
 
 struct Ray {
   float3 o, d, inv;
+  float3 off_l, off_h;   // slab offsets of the low and high box bounds (see make_ray)
   int kx, ky, kz;
   float Sx, Sy, Sz;
 };
@@ -35,6 +36,18 @@ __device__ __forceinline__ Ray make_ray(float3 o, float3 d) {
   r.inv = f3(1.0f / (fabsf(d.x) > tiny ? d.x : copysignf(tiny, d.x)),
              1.0f / (fabsf(d.y) > tiny ? d.y : copysignf(tiny, d.y)),
              1.0f / (fabsf(d.z) > tiny ? d.z : copysignf(tiny, d.z)));
+  // Slab distances as one FMA, t = b * inv + off: off = -o * inv, moved by
+  // e = 3u |o * inv| toward the outside of the slab (entry bound earlier,
+  // exit bound later), which covers the rounding of -o * inv and of the
+  // offset itself; the FMA's own relative rounding is left to the widening
+  // of the exit distance in box_hit.
+  const float3 oi = f3(r.o.x * r.inv.x, r.o.y * r.inv.y, r.o.z * r.inv.z);
+  const float3 e = f3(0x3p-24f * fabsf(oi.x), 0x3p-24f * fabsf(oi.y), 0x3p-24f * fabsf(oi.z));
+  // inv > 0: the low bound is the entry; inv < 0: the high bound is
+  r.off_l = f3(r.inv.x > 0.0f ? -oi.x - e.x : -oi.x + e.x, r.inv.y > 0.0f ? -oi.y - e.y : -oi.y + e.y,
+               r.inv.z > 0.0f ? -oi.z - e.z : -oi.z + e.z);
+  r.off_h = f3(r.inv.x > 0.0f ? -oi.x + e.x : -oi.x - e.x, r.inv.y > 0.0f ? -oi.y + e.y : -oi.y - e.y,
+               r.inv.z > 0.0f ? -oi.z + e.z : -oi.z - e.z);
   float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
   int kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
   int kx = kz == 2 ? 0 : kz + 1;
@@ -54,14 +67,16 @@ __device__ __forceinline__ Ray make_ray(float3 o, float3 d) {
   return r;
 }
 
-// Entry distance of the ray into a box within [0, tmax]; the exit distance is
-// widened by 2 gamma_3 so that float rounding never culls a box the ray
-// touches (Ize 2013).
+// Entry distance of the ray into a box within [0, tmax].  Conservative: the
+// slab offsets carry the absolute rounding of the origin term, and the exit
+// distance is widened by 2 gamma_3 for the relative rounding of the inverse
+// direction and the FMA (after Ize 2013), so float rounding never culls a box
+// the ray touches.
 __device__ __forceinline__ bool box_hit(const Ray& r, float lx, float ly, float lz, float hx, float hy, float hz,
                                         float tmax, float& tnear) {
-  float t0x = (lx - r.o.x) * r.inv.x, t1x = (hx - r.o.x) * r.inv.x;
-  float t0y = (ly - r.o.y) * r.inv.y, t1y = (hy - r.o.y) * r.inv.y;
-  float t0z = (lz - r.o.z) * r.inv.z, t1z = (hz - r.o.z) * r.inv.z;
+  float t0x = fmaf(lx, r.inv.x, r.off_l.x), t1x = fmaf(hx, r.inv.x, r.off_h.x);
+  float t0y = fmaf(ly, r.inv.y, r.off_l.y), t1y = fmaf(hy, r.inv.y, r.off_h.y);
+  float t0z = fmaf(lz, r.inv.z, r.off_l.z), t1z = fmaf(hz, r.inv.z, r.off_h.z);
   float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
   float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
   tnear = tn;
@@ -95,6 +110,10 @@ __device__ __forceinline__ bool tri_hit(const Ray& r, float4 a, float4 b, float4
 
 __device__ __forceinline__ int bits_i(float f) { return __float_as_int(f); }
 
+// Node value that ends a traversal: negative like a leaf link, and not one
+// (a leaf link is ~(first << 3 | count - 1) with first < 2^27).
+constexpr int kTraversalDone = INT_MIN;
+
 // Two-wide BVH traversal.  ANY: stop at the first hit (shadow rays).
 // STATIC_ONLY: skip triangles of dynamic objects (classification rays).
 // `stack` points at this lane's column of the LDS stack; `stride` = block size.
@@ -119,8 +138,7 @@ __device__ inline int traverse(const SceneGPU& sc, const Ray& ray, float tmax, f
   }
   int sp = 0;
   int node = 0;
-  bool done = false;
-  while (!done) {
+  while (true) {
     while (node >= 0) {
       const float4* np = sc.nodes + (size_t)node * 4;
       float4 n0 = np[0], n1 = np[1], n2 = np[2], n3 = np[3];
@@ -132,24 +150,21 @@ __device__ inline int traverse(const SceneGPU& sc, const Ray& ray, float tmax, f
       // branch-free step: descend into the nearer child that was hit and
       // push the other one if both were; with neither, pop.  The slot above
       // the top is always written (the stack has one spare entry).
-      const bool first0 = h0 && (!h1 || t0 <= t1);
+      const bool first0 = h0 & (!h1 | (t0 <= t1));
       const int nearc = first0 ? l0 : l1;
       const int farc = first0 ? l1 : l0;
       const int top = sp < sc.stack_depth ? sp : sc.stack_depth;
       stack[top * stride] = farc;
       sp = top + ((h0 && h1) ? 1 : 0);
-      if (h0 || h1) {
-        node = nearc;
-      } else {
-        if (sp == 0) {
-          done = true;
-          break;
-        }
-        sp--;
-        node = stack[sp * stride];
-      }
+      // the pop is read whether or not it is taken (no branch); an empty
+      // stack with no child hit ends the traversal
+      const int below = sp > 0 ? sp - 1 : 0;
+      const int popped = stack[below * stride];
+      const bool any = h0 || h1;
+      node = any ? nearc : (sp == 0 ? kTraversalDone : popped);
+      sp = any ? sp : below;
     }
-    if (done) break;
+    if (node == kTraversalDone) break;
     int code = ~node;
     int first = code >> 3, count = (code & 7) + 1;
     for (int i = first; i < first + count; i++) {
