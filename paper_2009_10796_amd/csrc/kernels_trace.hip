@@ -380,7 +380,20 @@ __device__ __forceinline__ void shadow_one(const VolumeSet& vs, const SceneGPU& 
   float3 Xs, dl;
   float tmax;
   shadow_ray(L, l, X, ng, Xs, dl, tmax);
-  Ray ray = make_ray(Xs, dl);
+  Ray ray;
+  if (l < L.n_dir) {
+    ray = make_ray(Xs, dl);
+  } else {
+    // A point light's segment is traced from the light toward the surface:
+    // the same segment (to the shadow origin, whose float32 end lands within
+    // a few ulps of it), and the rays of a wave -- one light, hit points of
+    // neighbouring rays of one probe -- then share their origin and stay a
+    // coherent bundle through the tree.
+    const int p = l - L.n_dir;
+    const float3 P = f3(L.pos[p][0], L.pos[p][1], L.pos[p][2]);
+    tmax = length(P - Xs);
+    ray = make_ray(P, f3(-dl.x, -dl.y, -dl.z));
+  }
   float t;
   int hit = traverse<true, false, CNT>(sc, ray, tmax, t, dyn_stack + threadIdx.x, kTraceBlock, cnt);
   if (!cnt && hit < 0) fs.vis[(int64_t)l * fs.max_rays + id] = 1;
