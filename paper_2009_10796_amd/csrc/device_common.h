@@ -267,48 +267,84 @@ __device__ __forceinline__ float3 irr_texel_update(const VolumeGPU& V, float alp
   return f3(a * old.x + (1.0f - a) * e.x, a * old.y + (1.0f - a) * e.y, a * old.z + (1.0f - a) * e.z);
 }
 
+template <bool F16>
+__device__ __forceinline__ float3 load_irr_t(const VolumeGPU& V, int idx) {
+  if constexpr (F16) {
+    const h4 h = ((const h4*)V.irr)[idx];
+    return f3((float)h.x, (float)h.y, (float)h.z);
+  } else {
+    const float4 f = ((const float4*)V.irr)[idx];
+    return f3(f.x, f.y, f.z);
+  }
+}
+
+template <bool F16>
+__device__ __forceinline__ float2 load_dist_t(const VolumeGPU& V, int idx) {
+  if constexpr (F16) {
+    const h2 h = ((const h2*)V.dist)[idx];
+    return make_float2((float)h.x, (float)h.y);
+  } else {
+    return ((const float2*)V.dist)[idx];
+  }
+}
+
 // One volume's 8-probe cage (Section "Probe Query"): trilinear x backface x
 // Chebyshev visibility at the point moved by the self-shadow bias (Eq. 1);
-// normalised.  Returns false when no probe carries weight.
+// normalised.  Returns zero when no probe carries weight.
 // `look`: the direction the irradiance texels are sampled in (the normal for
 // the irradiance query; the second-order glossy pass samples the probes'
 // filtered radiance in a mirror direction).
-__device__ inline float3 volume_query(const VolumeGPU& V, float3 X, float3 n, float3 wo, float3 look) {
-  float u[3] = {(X.x - V.origin[0]) / V.spacing[0], (X.y - V.origin[1]) / V.spacing[1],
-                (X.z - V.origin[2]) / V.spacing[2]};
+// The cage is unrolled: the eight state bytes are fetched together, and each
+// probe's texel fetches carry no format branch between them (F16: half
+// atlases), so they are in flight together.
+template <bool F16>
+__device__ __forceinline__ float3 volume_query_t(const VolumeGPU& V, float3 X, float3 n, float3 wo, float3 look) {
+  const float Xa[3] = {X.x, X.y, X.z};
   int g[3];
-  float f[3];
+  float f[3], Pa[3][2];
 #pragma unroll
   for (int a = 0; a < 3; a++) {
-    float fl = floorf(u[a]);
+    const float u = (Xa[a] - V.origin[a]) / V.spacing[a];
+    const float fl = floorf(u);
     g[a] = (int)clampf(fl, 0.0f, (float)(V.counts[a] - 2));
-    f[a] = clampf(u[a] - (float)g[a], 0.0f, 1.0f);
+    f[a] = clampf(u - (float)g[a], 0.0f, 1.0f);
+    // probe coordinates of the cage's two planes along the axis, from the
+    // logical index (as probe_position computes them)
+    Pa[a][0] = fmaf((float)g[a], V.spacing[a], V.origin[a]);
+    Pa[a][1] = fmaf((float)(g[a] + 1), V.spacing[a], V.origin[a]);
   }
-  float D = fminf(V.spacing[0], fminf(V.spacing[1], V.spacing[2]));
-  float sb = 0.75f * D * V.bias;
-  float3 Xb = f3(fmaf(fmaf(0.2f, n.x, 0.8f * wo.x), sb, X.x), fmaf(fmaf(0.2f, n.y, 0.8f * wo.y), sb, X.y),
-                 fmaf(fmaf(0.2f, n.z, 0.8f * wo.z), sb, X.z));
+  const float D = fminf(V.spacing[0], fminf(V.spacing[1], V.spacing[2]));
+  const float sb = 0.75f * D * V.bias;
+  const float3 Xb = f3(fmaf(fmaf(0.2f, n.x, 0.8f * wo.x), sb, X.x), fmaf(fmaf(0.2f, n.y, 0.8f * wo.y), sb, X.y),
+                       fmaf(fmaf(0.2f, n.z, 0.8f * wo.z), sb, X.z));
   // the irradiance lookup direction is the same for every probe of the cage
   int ix, iy;
   float ifx, ify;
   tile_footprint_fast<kIrrTile>(look, ix, iy, ifx, ify);
   const int irr_off = iy * kIrrTile + ix;
+  int q[8];
+  bool use[8];
+#pragma unroll
+  for (int c = 0; c < 8; c++) q[c] = storage_index(V, g[0] + (c & 1), g[1] + ((c >> 1) & 1), g[2] + ((c >> 2) & 1));
+#pragma unroll
+  for (int c = 0; c < 8; c++) use[c] = sampled_state(V.states[q[c]]);
   float3 acc = f3(0.0f, 0.0f, 0.0f);
   float W = 0.0f;
+#pragma unroll
   for (int c = 0; c < 8; c++) {
+    if (!use[c]) continue;
     const int cb0 = c & 1, cb1 = (c >> 1) & 1, cb2 = (c >> 2) & 1;
-    const int li = g[0] + cb0, lj = g[1] + cb1, lk = g[2] + cb2;
-    const int q = storage_index(V, li, lj, lk);
-    if (!sampled_state(V.states[q])) continue;
-    float wt = (cb0 ? f[0] : 1.0f - f[0]) * (cb1 ? f[1] : 1.0f - f[1]) * (cb2 ? f[2] : 1.0f - f[2]);
-    // probe position from its logical index (as probe_position computes it)
-    float3 P = f3(fmaf((float)li, V.spacing[0], V.origin[0]), fmaf((float)lj, V.spacing[1], V.origin[1]),
-                  fmaf((float)lk, V.spacing[2], V.origin[2]));
+    const float wt = (cb0 ? f[0] : 1.0f - f[0]) * (cb1 ? f[1] : 1.0f - f[1]) * (cb2 ? f[2] : 1.0f - f[2]);
+    float3 P = f3(Pa[0][cb0], Pa[1][cb1], Pa[2][cb2]);
     if (V.offsets) {
-      P.x += V.offsets[3 * q + 0];
-      P.y += V.offsets[3 * q + 1];
-      P.z += V.offsets[3 * q + 2];
+      P.x += V.offsets[3 * q[c] + 0];
+      P.y += V.offsets[3 * q[c] + 1];
+      P.z += V.offsets[3 * q[c] + 2];
     }
+    // the probe's irradiance texels do not depend on its weight: fetch first
+    const int bi = q[c] * kIrrTexels + irr_off;
+    const float3 ea = load_irr_t<F16>(V, bi), ec = load_irr_t<F16>(V, bi + 1);
+    const float3 ed = load_irr_t<F16>(V, bi + kIrrTile), ee = load_irr_t<F16>(V, bi + kIrrTile + 1);
     const float3 toP = P - X;
     const float d2 = dot(toP, toP);
     const float h = fmaf(d2 > 0.0f ? dot(n, toP) * rsq_fast(d2) : 0.0f, 0.5f, 0.5f);
@@ -316,14 +352,13 @@ __device__ inline float3 volume_query(const VolumeGPU& V, float3 X, float3 n, fl
     const float3 z = Xb - P;
     const float r2 = dot(z, z);
     if (r2 > 0.0f) {
-      const float rinv = rsq_fast(r2);
-      const float r = r2 * rinv;
+      const float r = r2 * rsq_fast(r2);
       int x0, y0;
       float fx, fy;
-      tile_footprint_fast<kDistTile>(rinv * z, x0, y0, fx, fy);
-      const int b = q * kDistTexels + y0 * kDistTile + x0;
-      const float2 da = load_dist(V, b), dc = load_dist(V, b + 1);
-      const float2 dd = load_dist(V, b + kDistTile), de = load_dist(V, b + kDistTile + 1);
+      tile_footprint_fast<kDistTile>(z, x0, y0, fx, fy);   // the octahedral map is scale-free
+      const int b = q[c] * kDistTexels + y0 * kDistTile + x0;
+      const float2 da = load_dist_t<F16>(V, b), dc = load_dist_t<F16>(V, b + 1);
+      const float2 dd = load_dist_t<F16>(V, b + kDistTile), de = load_dist_t<F16>(V, b + kDistTile + 1);
       const float mx = (1.0f - fy) * ((1.0f - fx) * da.x + fx * dc.x) + fy * ((1.0f - fx) * dd.x + fx * de.x);
       if (r > mx) {
         const float my = (1.0f - fy) * ((1.0f - fx) * da.y + fx * dc.y) + fy * ((1.0f - fx) * dd.y + fx * de.y);
@@ -336,17 +371,18 @@ __device__ inline float3 volume_query(const VolumeGPU& V, float3 X, float3 n, fl
         w *= p;
       }
     }
-    const int bi = q * kIrrTexels + irr_off;
-    const float3 ea = load_irr(V, bi), ec = load_irr(V, bi + 1);
-    const float3 ed = load_irr(V, bi + kIrrTile), ee = load_irr(V, bi + kIrrTile + 1);
     float3 e = (1.0f - ify) * ((1.0f - ifx) * ea + ifx * ec) + ify * ((1.0f - ifx) * ed + ifx * ee);
     if (V.gamma != 1.0f) e = decode_irr_half(V, e);
     acc = acc + w * e;
     W += w;
   }
   if (!(W > 0.0f)) return f3(0.0f, 0.0f, 0.0f);
-  float3 r = rcp_fast(W) * acc;
+  const float3 r = rcp_fast(W) * acc;
   return V.gamma != 1.0f ? f3(r.x * r.x, r.y * r.y, r.z * r.z) : r;
+}
+
+__device__ __forceinline__ float3 volume_query(const VolumeGPU& V, float3 X, float3 n, float3 wo, float3 look) {
+  return V.atlas_f16 ? volume_query_t<true>(V, X, n, wo, look) : volume_query_t<false>(V, X, n, wo, look);
 }
 
 // Section "Multiple Probe Volumes": a volume's weight falls linearly from 1 to
@@ -372,7 +408,7 @@ __device__ __forceinline__ float volume_weight(const VolumeGPU& V, float3 X) {
 // Cascaded volumes (Section "Multiple Probe Volumes"): densest first, linear
 // fall-off over the last cell of each axis (product of axes), accumulate
 // until the weights reach one; the sparsest volume takes the remainder.
-__device__ inline float3 query_look(const VolumeSet& vs, float3 X, float3 n, float3 wo, float3 look) {
+__device__ __forceinline__ float3 query_look(const VolumeSet& vs, float3 X, float3 n, float3 wo, float3 look) {
   float3 E = f3(0.0f, 0.0f, 0.0f);
   float Wt = 0.0f;
   for (int v = 0; v < vs.n; v++) {
@@ -388,7 +424,7 @@ __device__ inline float3 query_look(const VolumeSet& vs, float3 X, float3 n, flo
   return E;
 }
 
-__device__ inline float3 query_irradiance(const VolumeSet& vs, float3 X, float3 n, float3 wo) {
+__device__ __forceinline__ float3 query_irradiance(const VolumeSet& vs, float3 X, float3 n, float3 wo) {
   return query_look(vs, X, n, wo, n);
 }
 
