@@ -91,7 +91,7 @@ struct irf_ctx {
   DevBuf<HitRec> hits;
   DevBuf<uint8_t> vis;
   DevBuf<float4> rays;
-  DevBuf<uint32_t> shadow_tasks;
+  DevBuf<float4> shadow_tasks;
   DevBuf<int32_t> wave_tasks;
   DevBuf<int64_t> wave_offset;
   DevBuf<int32_t> batch_wave;

@@ -144,8 +144,9 @@ struct FrameScratch {
   HitRec* hits;             // [max_rays]
   uint8_t* vis;             // [n_lights][max_rays]
   float4* rays;             // [max_rays] rgb + distance (float32 path)
-  uint32_t* shadow_tasks;   // [max_rays * n_lights]: per source wave of 64 rays, a slice of
-                            // 64 * n_lights tasks (ray id << 5 | light), light-major
+  float4* shadow_tasks;     // [max_rays * n_lights]: per source wave of 64 rays, a slice of
+                            // 64 * n_lights tasks, light-major: the shadow origin and, in w,
+                            // the bits of (ray id << 5 | light)
   int32_t* wave_tasks;      // [max_rays / 64] number of tasks in each slice
   int64_t* wave_offset;     // [max_rays / 64 + 1] exclusive prefix sum of wave_tasks, then the total
   int32_t* batch_wave;      // [max_rays * n_lights / 64] slice holding the first task of each

@@ -299,18 +299,20 @@ __device__ __forceinline__ void trace_one(const VolumeSet& vs, const SceneGPU& s
   }
   const int lane = threadIdx.x & 63;
   const int64_t wave = id >> 6;
-  uint32_t* slice = fs.shadow_tasks + wave * 64 * nl;
+  float4* slice = fs.shadow_tasks + wave * 64 * nl;
   int n = 0;
   for (int l = 0; l < nl; l++) {
     fs.vis[(int64_t)l * fs.max_rays + id] = 0;
     bool need = false;
+    float3 Xs, dl;
     if (front) {
-      float3 Xs, dl;
       float tmax;
       need = shadow_ray(L, l, X, ng, Xs, dl, tmax);
     }
     unsigned long long m = __ballot(need);
-    if (need) slice[n + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)(id << 5) | (uint32_t)l;
+    if (need)
+      slice[n + __popcll(m & ((1ull << lane) - 1ull))] =
+          make_float4(Xs.x, Xs.y, Xs.z, __uint_as_float((uint32_t)(id << 5) | (uint32_t)l));
     n += __popcll(m);
   }
   if (lane == __ffsll((long long)__ballot(1)) - 1) fs.wave_tasks[wave] = n;
@@ -330,22 +332,30 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeSet vs, SceneGPU sc
 // consecutive tasks the slice that holds its first task.
 constexpr int kScanBlock = 1024;
 __global__ __launch_bounds__(kScanBlock) void k_scan_tasks(VolumeSet vs, FrameScratch fs) {
-  __shared__ int64_t part[kScanBlock];
+  __shared__ int64_t wave_sum[kScanBlock / 64];
   FrameCounters* C = fs.counters;
   const int64_t waves = (C->ray_base[vs.n] + 63) / 64;
   const int64_t per = (waves + kScanBlock - 1) / kScanBlock;
   const int64_t b = threadIdx.x * per, e = min(b + per, waves);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int64_t sum = 0;
   for (int64_t i = b; i < e; i++) sum += fs.wave_tasks[i];
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (int off = 1; off < kScanBlock; off <<= 1) {
-    int64_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+  // inclusive scan within the wave, then across the waves' totals
+  int64_t incl = sum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
   }
-  int64_t run = part[threadIdx.x] - sum;
+  if (lane == 63) wave_sum[wave] = incl;
+  __syncthreads();
+  int64_t before = 0, total = 0;
+  for (int w = 0; w < kScanBlock / 64; w++) {
+    const int64_t t = wave_sum[w];
+    before += w < wave ? t : 0;
+    total += t;
+  }
+  int64_t run = before + incl - sum;
   for (int64_t i = b; i < e; i++) {
     const int64_t c = fs.wave_tasks[i];
     fs.wave_offset[i] = run;
@@ -353,8 +363,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tasks(VolumeSet vs, FrameSc
     run += c;
   }
   if (threadIdx.x == kScanBlock - 1) {
-    C->shadow_total = part[kScanBlock - 1];
-    fs.wave_offset[waves] = part[kScanBlock - 1];
+    C->shadow_total = total;
+    fs.wave_offset[waves] = total;
   }
 }
 
@@ -366,23 +376,24 @@ __device__ __forceinline__ void shadow_one(const VolumeSet& vs, const SceneGPU& 
                                            const FrameScratch& fs, const FrameCounters& C, int64_t k, CNT* cnt) {
   const int nl = L.n_dir + L.n_point;
   int64_t src = fs.batch_wave[k >> 6];
-  while (fs.wave_offset[src + 1] <= k) src++;
-  uint32_t task = fs.shadow_tasks[src * 64 * nl + (k - fs.wave_offset[src])];
-  int64_t id = task >> 5;
-  int l = task & 31;
-  RaySlot s = locate_ray(vs, C, fs.active, id);
-  const VolumeGPU& V = vs.v[s.v];
-  float3 o = slot_position(fs, s);
-  float4 w = fs.omega[V.omega_base + s.r];
-  HitRec h = fs.hits[id];
-  float3 ng = tri_normal(sc, h.tri);
-  float3 X = f3(fmaf(h.t, w.x, o.x), fmaf(h.t, w.y, o.y), fmaf(h.t, w.z, o.z));
-  float3 Xs, dl;
-  float tmax;
-  shadow_ray(L, l, X, ng, Xs, dl, tmax);
+  int64_t off = fs.wave_offset[src], next = fs.wave_offset[src + 1];
+  while (next <= k) {
+    src++;
+    off = next;
+    next = fs.wave_offset[src + 1];
+  }
+  // the task carries the shadow origin computed at the hit, so the ray needs
+  // no other load
+  const float4 task = fs.shadow_tasks[src * 64 * nl + (k - off)];
+  const uint32_t word = __float_as_uint(task.w);
+  const int64_t id = word >> 5;
+  const int l = word & 31;
+  const float3 Xs = f3(task.x, task.y, task.z);
   Ray ray;
+  float tmax;
   if (l < L.n_dir) {
-    ray = make_ray(Xs, dl);
+    ray = make_ray(Xs, f3(L.dir[l][0], L.dir[l][1], L.dir[l][2]));
+    tmax = INFINITY;
   } else {
     // A point light's segment is traced from the light toward the surface:
     // the same segment (to the shadow origin, whose float32 end lands within
@@ -391,7 +402,10 @@ __device__ __forceinline__ void shadow_one(const VolumeSet& vs, const SceneGPU& 
     // coherent bundle through the tree.
     const int p = l - L.n_dir;
     const float3 P = f3(L.pos[p][0], L.pos[p][1], L.pos[p][2]);
-    tmax = length(P - Xs);
+    const float3 u = P - Xs;
+    const float dist = length(u);
+    const float3 dl = (1.0f / dist) * u;
+    tmax = dist;
     ray = make_ray(P, f3(-dl.x, -dl.y, -dl.z));
   }
   float t;
