@@ -248,6 +248,17 @@ irf_status irf_optimize_probes(irf_ctx* ctx, const float* rotations, int32_t ite
    states), border texels, promotion of Newly states.  Async. */
 irf_status irf_update_probes(irf_ctx* ctx, const float* rotation, void* stream);
 
+/* The same frame, with its atlas writes (the blend) ordered after
+   `atlas_event` (a hipEvent_t the caller recorded, typically after the
+   previous frame's queries on another stream; NULL: none).  Everything
+   before the blend -- state step, rays, traversal, shadow rays, hit shading,
+   which only read the atlases -- may then run beside those queries: an
+   engine's probe trace for the next frame overlapping its shading of the
+   current one.  The caller orders its next queries after this frame (an
+   event recorded on `stream` after this call).  IRF_E_HIP if waiting on the
+   event fails.  Async. */
+irf_status irf_update_probes_after(irf_ctx* ctx, const float* rotation, void* stream, void* atlas_event);
+
 /* Query E(X, n, w_o) (Section "Probe Query", Eq. 1, Section "Multiple Probe
    Volumes") for n points.  pos, nrm, view, out_rgb: device [n][3] float;
    view is the unit direction from the point toward the viewer.  The result

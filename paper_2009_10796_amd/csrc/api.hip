@@ -298,8 +298,9 @@ irf_status launched() {
   return IRF_OK;
 }
 
-// One update frame, asynchronously on `st` (also what a graph captures).
-void enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st) {
+// One update frame, asynchronously on `st` (also what a graph captures); the
+// blend waits for `atlas_wait` when given.
+hipError_t enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st, hipEvent_t atlas_wait = nullptr) {
   VolumeSet vs = volume_view(c);
   FrameScratch fs = scratch_view(c);
   SceneGPU sc = scene_view(c);
@@ -328,6 +329,10 @@ void enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st) {
     { ProfScope p(c, "shadow", st); launch_shadow(vs, sc, nl, fs, c->tune.shadow_blocks, st); }
   }
   { ProfScope p(c, "shade", st); launch_shade(vs, sc, fs, c->tune.shade_blocks, st); }
+  if (atlas_wait) {
+    hipError_t e = hipStreamWaitEvent(st, atlas_wait, 0);
+    if (e != hipSuccess) return e;
+  }
   if (any_valu) {
     ProfScope p(c, "blend_valu", st);
     launch_blend(vs, fs, st);
@@ -336,6 +341,7 @@ void enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st) {
     ProfScope p(c, "blend_mma", st);
     launch_blend_mma(vs, fs, c->tune.blend_blocks, st);
   }
+  return hipSuccess;
 }
 
 // Hash of everything a captured frame bakes into its nodes.
@@ -820,7 +826,7 @@ irf_status irf_volume_window(const irf_ctx* c, int32_t vol, float origin[3], int
   return IRF_OK;
 }
 
-irf_status irf_update_probes(irf_ctx* c, const float* rotation, void* stream) {
+irf_status irf_update_probes_after(irf_ctx* c, const float* rotation, void* stream, void* atlas_event) {
   if (!c || !rotation) return fail(IRF_E_INVALID, "NULL argument");
   for (int i = 0; i < 9; i++)
     if (!std::isfinite(rotation[i])) return fail(IRF_E_INVALID, "rotation is not finite");
@@ -828,10 +834,21 @@ irf_status irf_update_probes(irf_ctx* c, const float* rotation, void* stream) {
   if (s != IRF_OK) return s;
   if ((s = set_device(c)) != IRF_OK) return s;
   if ((s = ensure_scratch(c)) != IRF_OK) return s;
-  enqueue_frame(c, rotation, (hipStream_t)stream);
+  if (atlas_event) {
+    // reject a bad event before any of the frame is enqueued
+    hipError_t q = hipEventQuery((hipEvent_t)atlas_event);
+    if (q != hipSuccess && q != hipErrorNotReady)
+      return fail(IRF_E_INVALID, "atlas_event is not a usable event: %s", hipGetErrorString(q));
+  }
+  hipError_t e = enqueue_frame(c, rotation, (hipStream_t)stream, (hipEvent_t)atlas_event);
+  if (e != hipSuccess) return fail(IRF_E_HIP, "waiting on the atlas event: %s", hipGetErrorString(e));
   c->frame_done = true;
   c->diff_frame = c->diff;
   return launched();
+}
+
+irf_status irf_update_probes(irf_ctx* c, const float* rotation, void* stream) {
+  return irf_update_probes_after(c, rotation, stream, nullptr);
 }
 
 irf_status irf_query_irradiance(irf_ctx* c, const float* pos, const float* nrm, const float* view, int64_t n,

@@ -83,6 +83,7 @@ SIGNATURES = {
     "irf_bind_volume": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "irf_classify": (C.c_int, [_vp, _vp, _i32, _vp]),
     "irf_update_probes": (C.c_int, [_vp, _vp, _vp]),
+    "irf_update_probes_after": (C.c_int, [_vp, _vp, _vp, _vp]),
     "irf_query_irradiance": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp]),
     "irf_ray_records": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(_i64), _vp]),
     "irf_frame_stats": (C.c_int, [_vp, C.POINTER(_i64 * 4), _vp]),
@@ -288,9 +289,16 @@ class Context:
         _check(load().irf_volume_window(self.handle, vol, _ptr(o), _ptr(ph), _ptr(cam)))
         return o, ph, cam
 
-    def update_probes(self, rotation) -> None:
+    def update_probes(self, rotation, after=None) -> None:
+        """One update frame on the current stream.  `after`: a recorded
+        torch.cuda.Event (e.g. after the previous frame's queries on another
+        stream) that the frame's atlas writes wait for."""
         R = _np(rotation, np.float32).reshape(9)
-        _check(load().irf_update_probes(self.handle, _ptr(R), _stream(self.torch)))
+        if after is None:
+            _check(load().irf_update_probes(self.handle, _ptr(R), _stream(self.torch)))
+        else:
+            _check(load().irf_update_probes_after(self.handle, _ptr(R), _stream(self.torch),
+                                                  C.c_void_p(after.cuda_event)))
         self.frames += 1
 
     def query_irradiance(self, pos, nrm, view, out=None):

@@ -114,3 +114,43 @@ def test_autotuner_keeps_results(torch):
     assert _same(_snapshot(A), _snapshot(B))
     A.close()
     B.close()
+
+
+def test_pipelined_frames_match_serial(torch):
+    """The query of frame f on a second stream beside frame f+1's tracing,
+    the atlas writes of f+1 ordered after that query by an event: every
+    query and the final atlases equal the one-stream run bit for bit."""
+    from paper_2009_10796_amd import irf
+    w = small_terrain()
+    A = irf.build_workload(w)
+    B = irf.build_workload(w)
+    for c in (A, B):
+        c.classify(w.classify_rotations)
+    q = S.surface_points(w.scene, 8192, 5)
+    pos, nrm = torch.from_numpy(q.pos).cuda(), torch.from_numpy(q.nrm).cuda()
+    frames = range(1, 9)
+    serial = []
+    for f in frames:
+        A.set_lights(S.sun_for_frame(f))
+        A.update_probes(w.frame_rotation(f))
+        serial.append(A.query_irradiance(pos, nrm, nrm))
+    torch.cuda.synchronize()
+    Q = torch.cuda.Stream()
+    piped, prev = [], None
+    for f in frames:
+        B.set_lights(S.sun_for_frame(f))
+        B.update_probes(w.frame_rotation(f), after=prev)
+        done = torch.cuda.Event()
+        done.record()
+        Q.wait_event(done)
+        with torch.cuda.stream(Q):
+            piped.append(B.query_irradiance(pos, nrm, nrm))
+            prev = torch.cuda.Event()
+            prev.record(Q)
+    torch.cuda.current_stream().wait_event(prev)
+    torch.cuda.synchronize()
+    for f, (a, b) in enumerate(zip(serial, piped)):
+        assert torch.equal(a, b), f
+    assert _same(_snapshot(A), _snapshot(B))
+    A.close()
+    B.close()
