@@ -27,8 +27,8 @@
 
 namespace irf {
 
-constexpr int kBeginBlock = 256;
-constexpr int kPerThread = 16;                             // probes per thread, one-workgroup compaction
+constexpr int kBeginBlock = 1024;                          // >= the largest ray count: one pass per row
+constexpr int kPerThread = 4;                              // probes per thread, one-workgroup compaction
 constexpr int kSmallProbes = kBeginBlock * kPerThread;     // 4096
 
 __device__ __forceinline__ bool active_state(uint8_t s) {

@@ -331,6 +331,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeSet vs, SceneGPU sc
 // total as a sentinel after the last wave, and for every batch of 64
 // consecutive tasks the slice that holds its first task.
 constexpr int kScanBlock = 1024;
+constexpr int kScanRegs = 8;     // per-thread counts held in registers (more are re-read)
 __global__ __launch_bounds__(kScanBlock) void k_scan_tasks(VolumeSet vs, FrameScratch fs) {
   __shared__ int64_t wave_sum[kScanBlock / 64];
   FrameCounters* C = fs.counters;
@@ -338,8 +339,14 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tasks(VolumeSet vs, FrameSc
   const int64_t per = (waves + kScanBlock - 1) / kScanBlock;
   const int64_t b = threadIdx.x * per, e = min(b + per, waves);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the first kScanRegs counts of this thread, fetched together and kept
+  int32_t cnt[kScanRegs];
+#pragma unroll
+  for (int j = 0; j < kScanRegs; j++) cnt[j] = b + j < e ? fs.wave_tasks[b + j] : 0;
   int64_t sum = 0;
-  for (int64_t i = b; i < e; i++) sum += fs.wave_tasks[i];
+#pragma unroll
+  for (int j = 0; j < kScanRegs; j++) sum += cnt[j];
+  for (int64_t i = b + kScanRegs; i < e; i++) sum += fs.wave_tasks[i];
   // inclusive scan within the wave, then across the waves' totals
   int64_t incl = sum;
 #pragma unroll
@@ -356,12 +363,15 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tasks(VolumeSet vs, FrameSc
     total += t;
   }
   int64_t run = before + incl - sum;
-  for (int64_t i = b; i < e; i++) {
-    const int64_t c = fs.wave_tasks[i];
+  auto place = [&](int64_t i, int64_t c) {
     fs.wave_offset[i] = run;
     for (int64_t t = (run + 63) & ~63ll; t < run + c; t += 64) fs.batch_wave[t >> 6] = (int32_t)i;
     run += c;
-  }
+  };
+#pragma unroll
+  for (int j = 0; j < kScanRegs; j++)
+    if (b + j < e) place(b + j, cnt[j]);
+  for (int64_t i = b + kScanRegs; i < e; i++) place(i, fs.wave_tasks[i]);
   if (threadIdx.x == kScanBlock - 1) {
     C->shadow_total = total;
     fs.wave_offset[waves] = total;
