@@ -329,52 +329,60 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeSet vs, SceneGPU sc
 
 // Exclusive prefix sum of the per-wave task counts (one workgroup), with the
 // total as a sentinel after the last wave, and for every batch of 64
-// consecutive tasks the slice that holds its first task.
+// consecutive tasks the slice that holds its first task.  Tiles of
+// 4 x kScanBlock counts: each thread reads four consecutive counts with one
+// 16-byte load (coalesced across the wave), the workgroup scans the thread
+// sums, and a running carry joins the tiles.
 constexpr int kScanBlock = 1024;
-constexpr int kScanRegs = 8;     // per-thread counts held in registers (more are re-read)
 __global__ __launch_bounds__(kScanBlock) void k_scan_tasks(VolumeSet vs, FrameScratch fs) {
   __shared__ int64_t wave_sum[kScanBlock / 64];
   FrameCounters* C = fs.counters;
   const int64_t waves = (C->ray_base[vs.n] + 63) / 64;
-  const int64_t per = (waves + kScanBlock - 1) / kScanBlock;
-  const int64_t b = threadIdx.x * per, e = min(b + per, waves);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // the first kScanRegs counts of this thread, fetched together and kept
-  int32_t cnt[kScanRegs];
+  int64_t carry = 0;
+  for (int64_t tile = 0; tile < waves; tile += 4 * kScanBlock) {
+    const int64_t i0 = tile + 4 * (int64_t)threadIdx.x;
+    int32_t c[4];
+    if (i0 + 3 < waves) {
+      const int4 v = *(const int4*)(fs.wave_tasks + i0);
+      c[0] = v.x;
+      c[1] = v.y;
+      c[2] = v.z;
+      c[3] = v.w;
+    } else {
 #pragma unroll
-  for (int j = 0; j < kScanRegs; j++) cnt[j] = b + j < e ? fs.wave_tasks[b + j] : 0;
-  int64_t sum = 0;
+      for (int j = 0; j < 4; j++) c[j] = i0 + j < waves ? fs.wave_tasks[i0 + j] : 0;
+    }
+    const int64_t sum = (int64_t)c[0] + c[1] + c[2] + c[3];
+    // inclusive scan within the wave, then across the waves' totals
+    int64_t incl = sum;
 #pragma unroll
-  for (int j = 0; j < kScanRegs; j++) sum += cnt[j];
-  for (int64_t i = b + kScanRegs; i < e; i++) sum += fs.wave_tasks[i];
-  // inclusive scan within the wave, then across the waves' totals
-  int64_t incl = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t y = __shfl_up(incl, off);
+      if (lane >= off) incl += y;
+    }
+    if (lane == 63) wave_sum[wave] = incl;
+    __syncthreads();
+    int64_t before = 0, total = 0;
+    for (int w = 0; w < kScanBlock / 64; w++) {
+      const int64_t t = wave_sum[w];
+      before += w < wave ? t : 0;
+      total += t;
+    }
+    __syncthreads();   // wave_sum is rewritten by the next tile
+    int64_t run = carry + before + incl - sum;
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int64_t y = __shfl_up(incl, off);
-    if (lane >= off) incl += y;
+    for (int j = 0; j < 4; j++) {
+      if (i0 + j >= waves) break;
+      fs.wave_offset[i0 + j] = run;
+      for (int64_t t = (run + 63) & ~63ll; t < run + c[j]; t += 64) fs.batch_wave[t >> 6] = (int32_t)(i0 + j);
+      run += c[j];
+    }
+    carry += total;
   }
-  if (lane == 63) wave_sum[wave] = incl;
-  __syncthreads();
-  int64_t before = 0, total = 0;
-  for (int w = 0; w < kScanBlock / 64; w++) {
-    const int64_t t = wave_sum[w];
-    before += w < wave ? t : 0;
-    total += t;
-  }
-  int64_t run = before + incl - sum;
-  auto place = [&](int64_t i, int64_t c) {
-    fs.wave_offset[i] = run;
-    for (int64_t t = (run + 63) & ~63ll; t < run + c; t += 64) fs.batch_wave[t >> 6] = (int32_t)i;
-    run += c;
-  };
-#pragma unroll
-  for (int j = 0; j < kScanRegs; j++)
-    if (b + j < e) place(b + j, cnt[j]);
-  for (int64_t i = b + kScanRegs; i < e; i++) place(i, fs.wave_tasks[i]);
-  if (threadIdx.x == kScanBlock - 1) {
-    C->shadow_total = total;
-    fs.wave_offset[waves] = total;
+  if (threadIdx.x == 0) {
+    C->shadow_total = carry;
+    fs.wave_offset[waves] = carry;
   }
 }
 
