@@ -2,6 +2,7 @@
 // frame scratch, and the launch sequence of one update frame.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -88,6 +89,8 @@ struct irf_ctx {
   DevBuf<int32_t> active;
   DevBuf<FrameCounters> counters;
   DevBuf<float4> omega;
+  DevBuf<int16_t> order;           // per volume at omega_base: coherent trace order of its rays
+  std::vector<int32_t> order_rays;  // ray counts the order was built for
   DevBuf<HitRec> hits;
   DevBuf<uint8_t> vis;
   DevBuf<float4> rays;
@@ -155,8 +158,57 @@ VolumeSet volume_view(const irf_ctx* c) {
   VolumeSet vs;
   memset(&vs, 0, sizeof(vs));
   vs.n = c->n_vol;
-  for (int v = 0; v < c->n_vol; v++) vs.v[v] = c->vol[v];
+  const bool ordered = (int)c->order_rays.size() == c->n_vol && c->order.p;
+  for (int v = 0; v < c->n_vol; v++) {
+    vs.v[v] = c->vol[v];
+    vs.v[v].order = ordered ? c->order.p + c->vol[v].omega_base : nullptr;
+  }
   return vs;
+}
+
+// Order in which the probe-ray traversal takes the N rays of a probe: the
+// unrotated spherical-Fibonacci directions grouped into N / 64 compact cones
+// (greedy balanced assignment, nearest first, to the directions of an
+// (N / 64)-point pattern), so that a wave traces one cone rather than a band
+// of the sphere; the frame's rotation keeps the cones compact.  Only the lane
+// a ray runs on changes: every ray keeps its index and result.
+void coherent_order(int N, int16_t* out) {
+  const int G = N / 64;
+  if (G <= 1) {
+    for (int i = 0; i < N; i++) out[i] = (int16_t)i;
+    return;
+  }
+  auto dir = [](int i, int n, double w[3]) {
+    const double z = 1.0 - (2.0 * i + 1.0) / n, r = std::sqrt(std::max(0.0, 1.0 - z * z));
+    const double f = std::fmod(i * 0.61803398874989484820, 1.0), phi = 6.28318530717958647692 * f;
+    w[0] = r * std::cos(phi);
+    w[1] = r * std::sin(phi);
+    w[2] = z;
+  };
+  std::vector<double> d(3 * (size_t)N), cen(3 * (size_t)G);
+  for (int i = 0; i < N; i++) dir(i, N, &d[3 * i]);
+  for (int g = 0; g < G; g++) dir(g, G, &cen[3 * g]);
+  struct Pair {
+    double c;
+    int i, g;
+  };
+  std::vector<Pair> pairs;
+  pairs.reserve((size_t)N * G);
+  for (int i = 0; i < N; i++)
+    for (int g = 0; g < G; g++)
+      pairs.push_back({d[3 * i] * cen[3 * g] + d[3 * i + 1] * cen[3 * g + 1] + d[3 * i + 2] * cen[3 * g + 2], i, g});
+  std::stable_sort(pairs.begin(), pairs.end(), [](const Pair& a, const Pair& b) { return a.c > b.c; });
+  const int cap = (N + G - 1) / G;
+  std::vector<int> group(N, -1), count(G, 0);
+  for (const Pair& p : pairs)
+    if (group[p.i] < 0 && count[p.g] < cap) {
+      group[p.i] = p.g;
+      count[p.g]++;
+    }
+  int k = 0;
+  for (int g = 0; g < G; g++)
+    for (int i = 0; i < N; i++)
+      if (group[i] == g) out[k++] = (int16_t)i;
 }
 
 int64_t total_probes(const irf_ctx* c) {
@@ -186,6 +238,16 @@ irf_status ensure_scratch(irf_ctx* c) {
   if ((s = c->block_active.reserve((size_t)(nb > 0 ? nb : 1))) != IRF_OK) return s;
   if ((s = c->counters.reserve(1)) != IRF_OK) return s;
   if ((s = c->omega.reserve((size_t)om)) != IRF_OK) return s;
+  std::vector<int32_t> rays_now(c->n_vol);
+  for (int v = 0; v < c->n_vol; v++) rays_now[v] = c->vol[v].rays;
+  if (rays_now != c->order_rays) {
+    std::vector<int16_t> h((size_t)(om > 0 ? om : 1));
+    for (int v = 0; v < c->n_vol; v++) coherent_order(c->vol[v].rays, &h[c->vol[v].omega_base]);
+    c->order_rays.clear();
+    if ((s = c->order.reserve(h.size())) != IRF_OK) return s;
+    HIP_TRY(hipMemcpy(c->order.p, h.data(), h.size() * sizeof(int16_t), hipMemcpyHostToDevice));
+    c->order_rays = rays_now;
+  }
   if ((s = c->hits.reserve((size_t)R)) != IRF_OK) return s;
   if ((s = c->vis.reserve((size_t)R * (size_t)(nl > 0 ? nl : 1))) != IRF_OK) return s;
   if ((s = c->rays.reserve((size_t)R)) != IRF_OK) return s;
@@ -427,6 +489,8 @@ void irf_destroy(irf_ctx* c) {
   c->block_active.release();
   c->counters.release();
   c->omega.release();
+  c->order.release();
+  c->order_rays.clear();
   c->hits.release();
   c->vis.release();
   c->rays.release();

@@ -67,6 +67,7 @@ struct VolumeGPU {
   void* dist;               // [P][16][16] float2 or half2
   uint8_t* states;          // [P]
   const float* offsets;     // [P][3] or null
+  const int16_t* order;     // [rays] order in which the probe-ray traversal takes a probe's rays
 };
 
 struct VolumeSet {

@@ -274,10 +274,15 @@ __device__ __forceinline__ bool shadow_ray(const LightSet& L, int l, float3 X, f
 // strides over the rays of all volumes (persistent when the grid is smaller
 // than the ray count); the stride is a multiple of 64, so a wave always holds
 // 64 consecutive rays.
+// The work index walks each probe's rays in the volume's coherent order
+// (compact cones of the pattern, one per wave); results are stored by ray id.
 __device__ __forceinline__ void trace_one(const VolumeSet& vs, const SceneGPU& sc, const LightSet& L,
-                                          const FrameScratch& fs, const FrameCounters& C, int64_t id) {
-  RaySlot s = locate_ray(vs, C, fs.active, id);
+                                          const FrameScratch& fs, const FrameCounters& C, int64_t work) {
+  RaySlot s = locate_ray(vs, C, fs.active, work);
   const VolumeGPU& V = vs.v[s.v];
+  const int r = V.order ? V.order[s.r] : s.r;
+  const int64_t id = work - s.r + r;
+  s.r = r;
   float3 o = slot_position(fs, s);
   float4 w = fs.omega[V.omega_base + s.r];
   float3 w3 = f3(w.x, w.y, w.z);
@@ -298,7 +303,7 @@ __device__ __forceinline__ void trace_one(const VolumeSet& vs, const SceneGPU& s
     X = f3(fmaf(h.t, w3.x, o.x), fmaf(h.t, w3.y, o.y), fmaf(h.t, w3.z, o.z));
   }
   const int lane = threadIdx.x & 63;
-  const int64_t wave = id >> 6;
+  const int64_t wave = work >> 6;
   float4* slice = fs.shadow_tasks + wave * 64 * nl;
   int n = 0;
   for (int l = 0; l < nl; l++) {
@@ -322,9 +327,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeSet vs, SceneGPU sc
   const FrameCounters& C = *fs.counters;
   const LightSet& L = fs.params->L;
   const int64_t total = C.ray_base[vs.n];
-  for (int64_t id = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x; id < total;
-       id += (int64_t)gridDim.x * kTraceBlock)
-    trace_one(vs, sc, L, fs, C, id);
+  for (int64_t work = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x; work < total;
+       work += (int64_t)gridDim.x * kTraceBlock)
+    trace_one(vs, sc, L, fs, C, work);
 }
 
 // Exclusive prefix sum of the per-wave task counts (one workgroup), with the
