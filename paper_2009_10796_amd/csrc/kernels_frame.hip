@@ -219,6 +219,8 @@ __device__ void weight_row(const FrameBegin& a, int v, int row) {
   }
 }
 
+static_assert(sizeof(FrameBegin) <= 4096, "the frame-start argument block must fit the 4 KiB kernel-argument limit");
+
 __global__ __launch_bounds__(kBeginBlock) void k_frame_begin(FrameBegin a) {
   const int v = blockIdx.y;
   if (v >= a.vs.n) return;
