@@ -284,8 +284,8 @@ irf_status irf_get_tuning(const irf_ctx* ctx, irf_tuning* tuning);
 /* A whole update frame captured as a HIP graph.  irf_graph_capture records
    the frame's launches on `stream` (not the null stream) without running
    them; irf_graph_launch replays it with a new rotation and the context's
-   current lights (the frame's parameters are arguments of its first node,
-   updated before each launch).  A graph stays valid while the scene,
+   current lights (the frame's parameters are the argument block of its
+   frame-start node, updated before each launch).  A graph stays valid while the scene,
    volumes, bound buffers, light count and tuning are unchanged; otherwise
    irf_graph_launch returns IRF_E_STATE and the frame must be captured again. */
 typedef struct irf_graph irf_graph;
