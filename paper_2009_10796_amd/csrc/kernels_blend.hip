@@ -47,7 +47,8 @@ struct Mma<IRF_BLEND_F32> {
   static constexpr int KB = 16;    // k-steps whose A fragments are loaded together
   typedef float A;
   __device__ static A load_a(const char* wbase, int row_tile, int k, int N, int lane) {
-    return ((const float*)wbase)[(size_t)(k + lane / 16) * kRows + row_tile * 16 + lane % 16];
+    const int kk = min(k + lane / 16, N - 1);   // rays past N: any finite weight (their B is zero)
+    return ((const float*)wbase)[(size_t)kk * kRows + row_tile * 16 + lane % 16];
   }
   __device__ static A load_b(const char* lds, int col_base, int k, int lane) {
     return ((const float*)lds)[(k + lane / 16) * kBfStride + col_base + lane % 16];
@@ -63,7 +64,8 @@ struct Mma<IRF_BLEND_BF16> {
   static constexpr int KB = 8;
   typedef v8bf A;
   __device__ static A load_a(const char* wbase, int row_tile, int k, int N, int lane) {
-    return *(const v8bf*)((const __bf16*)wbase + (size_t)(row_tile * 16 + lane % 16) * N + k + 8 * (lane / 16));
+    const int kk = min(k + 8 * (lane / 16), N - 8);   // rays past N: any finite weights (their B is zero)
+    return *(const v8bf*)((const __bf16*)wbase + (size_t)(row_tile * 16 + lane % 16) * N + kk);
   }
   __device__ static A load_b(const char* lds, int col_base, int k, int lane) {
     return *(const v8bf*)((const __bf16*)lds + (col_base + lane % 16) * kBtStride + k + 8 * (lane / 16));
@@ -77,7 +79,8 @@ struct Mma<IRF_BLEND_F16> {
   static constexpr int KB = 8;
   typedef v8h A;
   __device__ static A load_a(const char* wbase, int row_tile, int k, int N, int lane) {
-    return *(const v8h*)((const _Float16*)wbase + (size_t)(row_tile * 16 + lane % 16) * N + k + 8 * (lane / 16));
+    const int kk = min(k + 8 * (lane / 16), N - 8);   // rays past N: any finite weights (their B is zero)
+    return *(const v8h*)((const _Float16*)wbase + (size_t)(row_tile * 16 + lane % 16) * N + kk);
   }
   __device__ static A load_b(const char* lds, int col_base, int k, int lane) {
     return *(const v8h*)((const _Float16*)lds + (col_base + lane % 16) * kBtStride + k + 8 * (lane / 16));
@@ -152,9 +155,23 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
 #pragma unroll
     for (int j = 0; j < 2; j++) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
   const float4* rays = fs.rays + C.ray_base[v] + (int64_t)slot0 * N;
+  typedef Mma<MODE> M;
+  constexpr int kRound = M::KB * M::KSTEP;   // rays per round of A fragments
+  static_assert(kKC % kRound == 0, "whole rounds per chunk");
+  const char* wbase = (const char*)fs.weights + V.weight_base;
   for (int kc = 0; kc < N; kc += kKC) {
     const int kn = min(kKC, N - kc);
+    // the products run over whole rounds with no per-step guard (a guarded
+    // step splits the accumulator chain into basic blocks); rays from kn to
+    // the round's end are zero in B
+    const int rounds = (kn + kRound - 1) / kRound;
+    const int kpad = rounds * kRound;
     __syncthreads();
+    for (int e = threadIdx.x; e < kPB * (kpad - kn); e += kBlendMmaBlock) {
+      const int p = e / (kpad - kn), k = kn + e % (kpad - kn);
+#pragma unroll
+      for (int c = 0; c < 6; c++) store_b<MODE>(lds, k, 8 * c + p, 0.0f);
+    }
     for (int e = threadIdx.x; e < kPB * kn; e += kBlendMmaBlock) {
       int p = e / kn, k = e - p * kn;
       float4 r = p < np ? rays[(int64_t)p * N + kc + k] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -168,24 +185,32 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
       store_b<MODE>(lds, k, 40 + p, r.w * r.w);
     }
     __syncthreads();
-    typedef Mma<MODE> M;
-    const char* wbase = (const char*)fs.weights + V.weight_base;
 #pragma unroll
     for (int i = 0; i < kTilesPerWave; i++) {
       const int rt = rt_list[i];
-      for (int k0 = 0; k0 < kn; k0 += M::KB * M::KSTEP) {
-        typename M::A a[M::KB];
+      if (rt < 3) {
+        // irradiance rows: two column tiles (R, G | B, 0), chains interleaved
+        for (int r0 = 0; r0 < rounds; r0++) {
+          const int k0 = r0 * kRound;
+          typename M::A a[M::KB];
 #pragma unroll
-        for (int j = 0; j < M::KB; j++)
-          if (k0 + j * M::KSTEP < kn) a[j] = M::load_a(wbase, rt, kc + k0 + j * M::KSTEP, N, lane);
+          for (int j = 0; j < M::KB; j++) a[j] = M::load_a(wbase, rt, kc + k0 + j * M::KSTEP, N, lane);
 #pragma unroll
-        for (int c = 0; c < 2; c++) {
-          if (c == 1 && rt >= 3) continue;   // distance rows have one column tile
-          const int col_base = rt < 3 ? 16 * c : 32;
+          for (int j = 0; j < M::KB; j++) {
+            acc[i][0] = M::mma(a[j], M::load_b(lds, 0, k0 + j * M::KSTEP, lane), acc[i][0]);
+            acc[i][1] = M::mma(a[j], M::load_b(lds, 16, k0 + j * M::KSTEP, lane), acc[i][1]);
+          }
+        }
+      } else {
+        // distance rows: one column tile (d, d^2)
+        for (int r0 = 0; r0 < rounds; r0++) {
+          const int k0 = r0 * kRound;
+          typename M::A a[M::KB];
+#pragma unroll
+          for (int j = 0; j < M::KB; j++) a[j] = M::load_a(wbase, rt, kc + k0 + j * M::KSTEP, N, lane);
 #pragma unroll
           for (int j = 0; j < M::KB; j++)
-            if (k0 + j * M::KSTEP < kn)
-              acc[i][c] = M::mma(a[j], M::load_b(lds, col_base, k0 + j * M::KSTEP, lane), acc[i][c]);
+            acc[i][0] = M::mma(a[j], M::load_b(lds, 32, k0 + j * M::KSTEP, lane), acc[i][0]);
         }
       }
     }
