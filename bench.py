@@ -97,8 +97,63 @@ def cpu_baseline(w, n_frames=3):
         oracle.update_frame(sc, w.lights, ov, w.frame_rotation(f), records=False)
         oracle.query(ov, q.pos, q.nrm, q.view)
         times.append(time.perf_counter() - t0)
-    return {"value": round(1e3 * float(np.median(times)), 3), "unit": "ms/frame", "cores": threads, "kind": "oracle",
-            "sample": f"full step (update frame + {q.n} G-buffer queries), FP64, OpenMP, median of {n_frames} frames"}
+    out = {"value": round(1e3 * float(np.median(times)), 3), "unit": "ms/frame", "cores": threads, "kind": "oracle",
+           "sample": f"full step (update frame + {q.n} G-buffer queries), FP64, OpenMP, median of {n_frames} frames"}
+    out.update(host_cpu())
+    out["one_thread"] = cpu_one_thread()
+    return out
+
+
+def host_cpu() -> dict:
+    """The host's CPU model, its logical CPU count and the CPUs this process
+    may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
+# The oracle's full step at one thread, in a child process (OpenMP fixes its
+# thread count at start-up): warm-up frame, then one timed update frame and
+# the G-buffer query.
+_ONE_THREAD_STEP = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle
+from paper_2009_10796_amd import scenes as S
+w = S.config1()
+sc = oracle.Scene(w.scene)
+ov = [oracle.Volume(d) for d in w.volumes]
+oracle.classify(sc, ov, w.classify_rotations)
+oracle.update_frame(sc, w.lights, ov, w.frame_rotation(1), records=False)
+q = w.queries
+t0 = time.perf_counter()
+oracle.update_frame(sc, w.lights, ov, w.frame_rotation(2), records=False)
+t1 = time.perf_counter()
+oracle.query(ov, q.pos, q.nrm, q.view)
+t2 = time.perf_counter()
+print(json.dumps({"update_ms": 1e3 * (t1 - t0), "query_ms": 1e3 * (t2 - t1)}))
+"""
+
+
+def cpu_one_thread() -> dict:
+    """The same step of the oracle on one host core (one frame)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", _ONE_THREAD_STEP, ROOT], env=env, capture_output=True, text=True,
+                           timeout=900)
+        d = json.loads(r.stdout.strip().splitlines()[-1])
+    except Exception as e:   # reported, never fatal to the GPU figures
+        return {"error": f"{type(e).__name__}: {e}"}
+    return {"value": round(d["update_ms"] + d["query_ms"], 1), "unit": "ms/frame", "cores": 1,
+            "update_ms": round(d["update_ms"], 1), "query_ms": round(d["query_ms"], 1)}
 
 
 def blend_variants(w, R, frames, irf, torch):

@@ -288,6 +288,41 @@ __device__ __forceinline__ float2 load_dist_t(const VolumeGPU& V, int idx) {
   }
 }
 
+// Two horizontally adjacent texels of one tile row (x, x + 1; contiguous in
+// the atlas, the second never past the row) with one wide load: 16 bytes for
+// a float2 distance pair or a half4 irradiance pair, 8 for a half2 distance
+// pair.  Atlas rows start at the texel size's alignment, so the wide load is
+// aligned to the texel, not to its own width (dword alignment is what global
+// loads need).
+typedef float f4_a8 __attribute__((ext_vector_type(4), aligned(8)));
+typedef _Float16 h8_a8 __attribute__((ext_vector_type(8), aligned(8)));
+typedef _Float16 h4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+
+template <bool F16>
+__device__ __forceinline__ void load_irr_pair_t(const VolumeGPU& V, int idx, float3& a, float3& b) {
+  if constexpr (F16) {
+    const h8_a8 h = *(const h8_a8*)((const h4*)V.irr + idx);
+    a = f3((float)h[0], (float)h[1], (float)h[2]);
+    b = f3((float)h[4], (float)h[5], (float)h[6]);
+  } else {
+    a = load_irr_t<false>(V, idx);
+    b = load_irr_t<false>(V, idx + 1);
+  }
+}
+
+template <bool F16>
+__device__ __forceinline__ void load_dist_pair_t(const VolumeGPU& V, int idx, float2& a, float2& b) {
+  if constexpr (F16) {
+    const h4_a4 h = *(const h4_a4*)((const h2*)V.dist + idx);
+    a = make_float2((float)h[0], (float)h[1]);
+    b = make_float2((float)h[2], (float)h[3]);
+  } else {
+    const f4_a8 f = *(const f4_a8*)((const float2*)V.dist + idx);
+    a = make_float2(f[0], f[1]);
+    b = make_float2(f[2], f[3]);
+  }
+}
+
 // One volume's 8-probe cage (Section "Probe Query"): trilinear x backface x
 // Chebyshev visibility at the point moved by the self-shadow bias (Eq. 1);
 // normalised.  Returns zero when no probe carries weight.
@@ -343,8 +378,9 @@ __device__ __forceinline__ float3 volume_query_t(const VolumeGPU& V, float3 X, f
     }
     // the probe's irradiance texels do not depend on its weight: fetch first
     const int bi = q[c] * kIrrTexels + irr_off;
-    const float3 ea = load_irr_t<F16>(V, bi), ec = load_irr_t<F16>(V, bi + 1);
-    const float3 ed = load_irr_t<F16>(V, bi + kIrrTile), ee = load_irr_t<F16>(V, bi + kIrrTile + 1);
+    float3 ea, ec, ed, ee;
+    load_irr_pair_t<F16>(V, bi, ea, ec);
+    load_irr_pair_t<F16>(V, bi + kIrrTile, ed, ee);
     const float3 toP = P - X;
     const float d2 = dot(toP, toP);
     const float h = fmaf(d2 > 0.0f ? dot(n, toP) * rsq_fast(d2) : 0.0f, 0.5f, 0.5f);
@@ -357,8 +393,9 @@ __device__ __forceinline__ float3 volume_query_t(const VolumeGPU& V, float3 X, f
       float fx, fy;
       tile_footprint_fast<kDistTile>(z, x0, y0, fx, fy);   // the octahedral map is scale-free
       const int b = q[c] * kDistTexels + y0 * kDistTile + x0;
-      const float2 da = load_dist_t<F16>(V, b), dc = load_dist_t<F16>(V, b + 1);
-      const float2 dd = load_dist_t<F16>(V, b + kDistTile), de = load_dist_t<F16>(V, b + kDistTile + 1);
+      float2 da, dc, dd, de;
+      load_dist_pair_t<F16>(V, b, da, dc);
+      load_dist_pair_t<F16>(V, b + kDistTile, dd, de);
       const float mx = (1.0f - fy) * ((1.0f - fx) * da.x + fx * dc.x) + fy * ((1.0f - fx) * dd.x + fx * de.x);
       if (r > mx) {
         const float my = (1.0f - fy) * ((1.0f - fx) * da.y + fx * dc.y) + fy * ((1.0f - fx) * dd.y + fx * de.y);

@@ -448,12 +448,25 @@ __global__ __launch_bounds__(kTraceBlock) void k_shadow(VolumeSet vs, SceneGPU s
 // self-shadow-bias section: radiance 0, distance shortened by 80 %).
 __device__ __forceinline__ void shade_one(const VolumeSet& vs, const SceneGPU& sc, const LightSet& L,
                                           const FrameScratch& fs, const FrameCounters& C, int64_t id) {
+  HitRec h = fs.hits[id];
   RaySlot s = locate_ray(vs, C, fs.active, id);
   const VolumeGPU& V = vs.v[s.v];
   float3 o = slot_position(fs, s);
   float4 w4 = fs.omega[V.omega_base + s.r];
   float3 w = f3(w4.x, w4.y, w4.z);
-  HitRec h = fs.hits[id];
+  // the visibility byte of every light, fetched up front and together (they
+  // depend on the ray id alone): groups of eight unconditional loads (a light
+  // index past the last reads the last light's byte again and is masked
+  // off), one wait per group instead of one per light
+  const int nl = L.n_dir + L.n_point;
+  uint32_t vis = 0;
+  for (int l0 = 0; l0 < nl; l0 += 8) {
+    uint8_t b[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) b[j] = fs.vis[(int64_t)min(l0 + j, nl - 1) * fs.max_rays + id];
+#pragma unroll
+    for (int j = 0; j < 8; j++) vis |= (b[j] != 0 && l0 + j < nl ? 1u : 0u) << (l0 + j);
+  }
   float4 out;
   if (h.tri < 0) {
     out = make_float4(L.sky[0], L.sky[1], L.sky[2], V.dmax);
@@ -465,9 +478,8 @@ __device__ __forceinline__ void shade_one(const VolumeSet& vs, const SceneGPU& s
       float3 X = f3(fmaf(h.t, w.x, o.x), fmaf(h.t, w.y, o.y), fmaf(h.t, w.z, o.z));
       float3 Xs = shadow_origin(X, ng);
       float3 direct = f3(0.0f, 0.0f, 0.0f);
-      int nl = L.n_dir + L.n_point;
       for (int l = 0; l < nl; l++) {
-        if (!fs.vis[(int64_t)l * fs.max_rays + id]) continue;
+        if (!((vis >> l) & 1u)) continue;
         if (l < L.n_dir) {
           float c = dot(ng, f3(L.dir[l][0], L.dir[l][1], L.dir[l][2]));
           direct = direct + c * f3(L.irr[l][0], L.irr[l][1], L.irr[l][2]);
