@@ -130,10 +130,17 @@ struct GradSet {
   float* dist[IRF_MAX_VOLUMES];
 };
 
+// Nearest hit of one probe ray.  The hit triangle's geometric normal and
+// material ride along, so the hit shading starts without fetching the
+// triangle again.
 struct HitRec {
   int32_t tri;   // BVH-order triangle, -1 miss
   float t;
+  int32_t mat;   // material of the triangle (hits only)
+  int32_t pad;
+  float n[4];    // unit geometric normal of the triangle in n[0..2] (hits only)
 };
+static_assert(sizeof(HitRec) == 32, "two 16-byte halves");
 
 // Frame scratch (library-owned device memory).
 struct FrameScratch {

@@ -229,6 +229,15 @@ __device__ __forceinline__ float3 tri_normal(const SceneGPU& sc, int tri) {
   return normalize_or_zero(cross(e1, e2));
 }
 
+// The normal and the material of a triangle from one fetch of its record.
+__device__ __forceinline__ float3 tri_normal_material(const SceneGPU& sc, int tri, int& mat) {
+  const float4* tp = sc.tris + (size_t)tri * 3;
+  float4 a = tp[0], b = tp[1], c = tp[2];
+  mat = bits_i(c.w);
+  float3 e1 = f3(b.x - a.x, b.y - a.y, b.z - a.z), e2 = f3(c.x - a.x, c.y - a.y, c.z - a.z);
+  return normalize_or_zero(cross(e1, e2));
+}
+
 // Shadow-ray origin: the hit lifted off the surface along its normal.
 __device__ __forceinline__ float3 shadow_origin(float3 X, float3 ng) {
   float xm = fmaxf(fabsf(X.x), fmaxf(fabsf(X.y), fabsf(X.z)));
@@ -267,7 +276,8 @@ __device__ __forceinline__ bool shadow_ray(const LightSet& L, int l, float3 X, f
   return dot(ng, dl) > 0.0f;
 }
 
-// Nearest hit of every active probe ray.  Front-face hits also queue their
+// Nearest hit of every active probe ray, stored with the hit triangle's
+// normal and material for the hit shading.  Front-face hits also queue their
 // shadow rays in the slice of their wave (light-major, so the tasks of one
 // light from one probe stay contiguous) and clear their visibility bytes.
 // No atomics: each wave owns its slice and writes its own count.  The grid
@@ -292,13 +302,20 @@ __device__ __forceinline__ void trace_one(const VolumeSet& vs, const SceneGPU& s
   HitRec h;
   h.tri = tri;
   h.t = tri >= 0 ? t : INFINITY;
+  h.mat = 0;
+  h.pad = 0;
+  float3 ng = f3(0.0f, 0.0f, 0.0f);
+  if (tri >= 0) ng = tri_normal_material(sc, tri, h.mat);
+  h.n[0] = ng.x;
+  h.n[1] = ng.y;
+  h.n[2] = ng.z;
+  h.n[3] = 0.0f;
   fs.hits[id] = h;
   int nl = L.n_dir + L.n_point;
   if (nl == 0) return;
   bool front = false;
-  float3 X, ng;
+  float3 X;
   if (tri >= 0) {
-    ng = tri_normal(sc, tri);
     front = dot(w3, ng) <= 0.0f;
     X = f3(fmaf(h.t, w3.x, o.x), fmaf(h.t, w3.y, o.y), fmaf(h.t, w3.z, o.z));
   }
@@ -471,7 +488,7 @@ __device__ __forceinline__ void shade_one(const VolumeSet& vs, const SceneGPU& s
   if (h.tri < 0) {
     out = make_float4(L.sky[0], L.sky[1], L.sky[2], V.dmax);
   } else {
-    float3 ng = tri_normal(sc, h.tri);
+    const float3 ng = f3(h.n[0], h.n[1], h.n[2]);
     if (dot(w, ng) > 0.0f) {
       out = make_float4(0.0f, 0.0f, 0.0f, fminf(0.2f * h.t, V.dmax));
     } else {
@@ -493,8 +510,7 @@ __device__ __forceinline__ void shade_one(const VolumeSet& vs, const SceneGPU& s
         }
       }
       float3 ind = query_irradiance(vs, X, ng, f3(-w.x, -w.y, -w.z));
-      int m = bits_i(sc.tris[(size_t)h.tri * 3 + 2].w);
-      float4 al = sc.albedo[m], em = sc.emission[m];
+      float4 al = sc.albedo[h.mat], em = sc.emission[h.mat];
       const float inv_pi = 0.318309886183790672f;
       out = make_float4(fmaf(al.x, fmaf(direct.x, inv_pi, ind.x), em.x), fmaf(al.y, fmaf(direct.y, inv_pi, ind.y), em.y),
                         fmaf(al.z, fmaf(direct.z, inv_pi, ind.z), em.z), fminf(h.t, V.dmax));
