@@ -701,6 +701,7 @@ irf_status irf_create_volume(irf_ctx* c, const irf_volume_desc* d, int32_t* volu
   for (int a = 0; a < 3; a++) {
     V.origin[a] = d->origin[a];
     V.spacing[a] = d->spacing[a];
+    V.inv_spacing[a] = 1.0f / d->spacing[a];
     V.counts[a] = d->counts[a];
   }
   V.n_probes = (int32_t)P;

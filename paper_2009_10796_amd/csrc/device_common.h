@@ -339,7 +339,7 @@ __device__ __forceinline__ float3 volume_query_t(const VolumeGPU& V, float3 X, f
   float f[3], Pa[3][2];
 #pragma unroll
   for (int a = 0; a < 3; a++) {
-    const float u = (Xa[a] - V.origin[a]) / V.spacing[a];
+    const float u = (Xa[a] - V.origin[a]) * V.inv_spacing[a];
     const float fl = floorf(u);
     g[a] = (int)clampf(fl, 0.0f, (float)(V.counts[a] - 2));
     f[a] = clampf(u - (float)g[a], 0.0f, 1.0f);
@@ -433,9 +433,9 @@ __device__ __forceinline__ float volume_weight(const VolumeGPU& V, float3 X) {
   for (int a = 0; a < 3; a++) {
     if (V.tracking) {
       float h = 0.5f * (float)(V.counts[a] - 1) - 1.0f;
-      wv *= clampf(h - fabsf(Xa[a] - V.camera[a]) / V.spacing[a], 0.0f, 1.0f);
+      wv *= clampf(h - fabsf(Xa[a] - V.camera[a]) * V.inv_spacing[a], 0.0f, 1.0f);
     } else {
-      float u = (Xa[a] - V.origin[a]) / V.spacing[a];
+      float u = (Xa[a] - V.origin[a]) * V.inv_spacing[a];
       wv *= clampf(fminf(u, (float)(V.counts[a] - 1) - u), 0.0f, 1.0f);
     }
   }

@@ -44,6 +44,7 @@ constexpr int kLeafMax = 8;
 struct VolumeGPU {
   float origin[3];
   float spacing[3];
+  float inv_spacing[3];     // 1 / spacing, correctly rounded float32 (grid coordinates by a product)
   int32_t counts[3];
   int32_t n_probes;
   int32_t rays;

@@ -33,8 +33,8 @@ __device__ __forceinline__ void scatter_bilinear(float* tile, int nch, int strid
 // Reverse pass of one volume's cage query (forward: volume_query).
 __device__ inline void volume_query_backward(const VolumeGPU& V, float3 X, float3 n, float3 wo, float3 g, float* gI,
                                              float* gD) {
-  float u[3] = {(X.x - V.origin[0]) / V.spacing[0], (X.y - V.origin[1]) / V.spacing[1],
-                (X.z - V.origin[2]) / V.spacing[2]};
+  float u[3] = {(X.x - V.origin[0]) * V.inv_spacing[0], (X.y - V.origin[1]) * V.inv_spacing[1],
+                (X.z - V.origin[2]) * V.inv_spacing[2]};
   int gi[3];
   float f[3];
   for (int a = 0; a < 3; a++) {
