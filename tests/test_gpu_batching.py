@@ -1,7 +1,8 @@
 """Batched frame: persistent launches over all cascades, the frame captured as
 a HIP graph, and the autotuner.  Every variant must give the same atlases,
 bit for bit, as the plain eager frame (the frame's kernels are
-deterministic: no atomics, fixed reduction orders)."""
+deterministic: no atomics, fixed reduction orders).  Graph replays are also
+checked on 8,192 probes, where the frame start compacts in two passes."""
 import numpy as np
 import pytest
 
@@ -49,9 +50,11 @@ def test_persistent_grids_match_default(torch):
     B.close()
 
 
-def test_graph_replays_match_eager(torch):
+@pytest.mark.parametrize("size", ["1024 probes", "8192 probes"])
+def test_graph_replays_match_eager(torch, size):
     from paper_2009_10796_amd import irf
-    w = small_terrain()
+    # above 4,096 probes the captured frame holds the two-pass compaction
+    w = small_terrain() if size == "1024 probes" else small_terrain(cascade_counts=(16, 8, 16), rays=32)
     A = irf.build_workload(w)
     B = irf.build_workload(w)
     for c in (A, B):
