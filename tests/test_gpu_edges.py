@@ -6,7 +6,12 @@
 * The largest ray count (1024 rays per probe): the blend walks its rays in
   four chunks, the trace order has sixteen cones, a weight row fills the
   frame start's workgroup.  Records and texels against the FP64 oracle, for
-  the float32 and the float16 matrix-core blends."""
+  the float32 and the float16 matrix-core blends.
+* The largest light count (32: the sun and 31 point lights): light index 31
+  in the five light bits of a shadow task, every wave slice 64 x 32 tasks
+  wide, the hit shading's visibility bytes gathered in four groups of
+  eight.  Records (visibility bits of all 32 lights), radiance and texels
+  against the oracle."""
 import numpy as np
 import pytest
 
@@ -112,4 +117,60 @@ def test_largest_ray_count(torch, blend):
                   f"p99 {np.quantile(err, 0.99):.2e}", flush=True)
             assert np.quantile(err, 0.99) <= 4 * 2.0 ** -11 and err.max() <= 8 * 2.0 ** -11
         taint = tp.astype(np.int64)
+    ctx.close()
+
+
+def _many_lights(L, n_point):
+    """The room's sun plus n_point point lights on a fixed lattice inside the
+    room (odd coordinates, so none lies on a surface), intensities from a
+    fixed pattern."""
+    i = np.arange(n_point)
+    pos = np.stack([0.9 + 2.0 * (i % 4) + 0.13 * (i % 3), 0.8 + 1.7 * ((i // 4) % 4) + 0.11 * (i % 5),
+                    1.1 + 3.1 * (i // 16) + 0.17 * (i % 7)], 1).astype(np.float32)
+    inten = np.stack([1.0 + 0.5 * (i % 5), 2.0 + 0.25 * (i % 3), 1.5 + 0.5 * (i % 4)], 1).astype(np.float32)
+    return S.Lights(L.dir_to_light, L.dir_irradiance, pos, inten, L.sky)
+
+
+def test_largest_light_count(torch):
+    import oracle
+    from paper_2009_10796_amd import irf
+    w = S.config0()
+    w.lights = _many_lights(w.lights, 32 - len(w.lights.dir_to_light))
+    n_lights = len(w.lights.dir_to_light) + len(w.lights.point_pos)
+    assert n_lights == 32
+    ctx = irf.build_workload(w)
+    osc = oracle.Scene(w.scene)
+    ov = [oracle.Volume(d) for d in w.volumes]
+    ctx.classify(w.classify_rotations)
+    oracle.classify(osc, ov, w.classify_rotations)
+    gv, o = ctx.volumes[0], ov[0]
+    gs = gv.states.cpu().numpy()
+    diff = np.nonzero(gs != o.states)[0]
+    assert len(diff) <= 1
+    if len(diff):
+        gs[diff] = o.states[diff]
+        gv.states.copy_(torch.from_numpy(gs))
+    taint = np.zeros(0, np.int64)
+    last_light_seen = 0
+    for f in (1, 2):
+        R = w.frame_rotation(f)
+        ctx.update_probes(R)
+        rec_o = oracle.update_frame(osc, w.lights, ov, R)
+        torch.cuda.synchronize()
+        rec_g = ctx.ray_records(0)
+        assert np.array_equal(gv.states.cpu().numpy(), o.states)
+        tainted, _, rep = compare_records(rec_g, rec_o, taint)
+        stats = ctx.frame_stats()
+        last_light_seen += int(((rec_g["vis"] >> 31) & 1).sum())
+        print(f"[edges] 32 lights, frame {f}: {rep}, shadow rays {stats['shadow_rays']}", flush=True)
+        assert rep["unflagged_flips"] == 0
+        ok, _ = within(rec_g["rgb"][~tainted], rec_o["rgb"][~tainted], kappa=rec_o["kappa"][~tainted])
+        assert ok.all(), np.argwhere(~ok)[:5]
+        tp = np.unique(rec_g["probe"][tainted])
+        clean = [q for q in range(gv.n_probes) if q not in set(tp.tolist())]
+        worst, bad = texel_check(gv, o, clean, rec_o, slots_of(rec_g, w.volumes[0].rays_per_probe))
+        print(f"[edges] 32 lights, frame {f}: texel worst err/tol {worst:.3f}", flush=True)
+        assert not bad, bad[:5]
+        taint = tp.astype(np.int64)
+    assert last_light_seen > 0          # the 32nd light reached some hits
     ctx.close()
