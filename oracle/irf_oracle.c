@@ -811,6 +811,14 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
   for (int i = 0; i < used; i++)
     for (int c = 0; c < 3; c++) out[c] += w[i] * e[i][c];
   for (int c = 0; c < 3; c++) out[c] /= W;
+  /* a weight whose relative float32 sensitivity reaches 1 (its Chebyshev
+     variance below the float32 resolution of mu2 - mu^2) may be zero in
+     float32; if that holds for every probe that carries weight, float32 may
+     find no probe with weight, and the query is then zero (the mirror of
+     the W = 0 case above) */
+  int all_fragile = 1;
+  for (int i = 0; i < used; i++)
+    if (w[i] > 0.0 && !(sens[i] * U32 >= 1.0)) all_fragile = 0;
   for (int i = 0; i < used; i++) {
     for (int c = 0; c < 3; c++) {
       double dv = fabs(e[i][c] - out[c]);
@@ -819,6 +827,8 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
     }
     if (w[i] > 0.0 && cage && ncage && *ncage < 8) cage[(*ncage)++] = ids[i];
   }
+  if (all_fragile)
+    for (int c = 0; c < 3; c++) kap[c] += fabs(out[c]) / U32;
   if (sq)
     for (int c = 0; c < 3; c++) {
       kap[c] = 2.0 * fabs(out[c]) * kap[c] + 8.0 * out[c] * out[c];

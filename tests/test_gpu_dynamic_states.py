@@ -1,0 +1,105 @@
+"""The probe state machine's dynamic-object transitions on the GPU against
+the oracle (Section "Full Probe Initialization Algorithm": sleeping probes
+near a dynamic object wake, awake probes away from every dynamic object go
+back to sleep).
+
+One building of the city is marked dynamic; a 10x4x6 window of 1 m probes
+sits over the rooftops (open air, so many probes classify as sleeping).
+Classification wakes the sleeping probes inside the building's grown box;
+frame 1 promotes them.  Before frame 3 the scene is replaced by the same
+city with that building moved 4 m along x: the state step puts the probes
+it left to sleep and wakes those it now reaches.  States after every step
+bit for bit, ray records, radiance and texels of every frame."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2009_10796_amd import scenes as S
+from tests.gpu_helpers import compare_records, slots_of, texel_check, within
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def city_with_dynamic_building(shift=None):
+    """The city with the building of the lot [6, 8] x [6, 8] as dynamic
+    object 1; `shift` moves that building (its vertices duplicated and
+    translated, the rest of the scene unchanged)."""
+    w = S.config1(gbuffer=False)
+    sc = w.scene
+    c = sc.vertices[sc.indices].mean(1)
+    m = (c[:, 0] > 6) & (c[:, 0] < 8) & (c[:, 2] > 6) & (c[:, 2] < 8) & (c[:, 1] > 0.02)
+    obj = sc.tri_object.copy()
+    obj[m] = 1
+    if shift is None:
+        return w, dataclasses.replace(sc, tri_object=obj)
+    used = np.unique(sc.indices[m])
+    remap = np.arange(len(sc.vertices))
+    remap[used] = len(sc.vertices) + np.arange(len(used))
+    idx = sc.indices.copy()
+    idx[m] = remap[sc.indices[m]]
+    verts = np.concatenate([sc.vertices, sc.vertices[used] + np.asarray(shift, np.float32)]).astype(np.float32)
+    return w, dataclasses.replace(sc, vertices=verts, indices=idx.astype(np.uint32), tri_object=obj)
+
+
+def test_dynamic_object_wakes_and_releases_probes(torch):
+    import oracle
+    from paper_2009_10796_amd import irf
+    w, scene_a = city_with_dynamic_building()
+    _, scene_b = city_with_dynamic_building((4.0, 0.0, 0.0))
+    w.scene = scene_a
+    w.volumes = [S.VolumeDesc(origin=(3.5, 5.5, 4.5), spacing=(1.0, 1.0, 1.0), counts=(10, 4, 6), rays_per_probe=64)]
+    ctx = irf.build_workload(w)
+    gv = ctx.volumes[0]
+    osc_a, osc_b = oracle.Scene(scene_a), oracle.Scene(scene_b)
+    o = oracle.Volume(w.volumes[0])
+    ctx.classify(w.classify_rotations)
+    oracle.classify(osc_a, [o], w.classify_rotations)
+    gs = gv.states.cpu().numpy()
+    print(f"[dynamic] classified {np.bincount(o.states, minlength=6)}, differ {(gs != o.states).sum()}", flush=True)
+    diff = np.nonzero(gs != o.states)[0]
+    assert len(diff) <= 2
+    if len(diff):
+        gs[diff] = o.states[diff]
+        gv.states.copy_(torch.from_numpy(gs))
+    assert (o.states == S.NEWLY_AWAKE).sum() > 0
+    seen = {}
+    taint = np.zeros(0, np.int64)
+    for f in (1, 2, 3, 4):
+        if f == 3:
+            ctx.set_scene(scene_b)
+        osc = osc_a if f < 3 else osc_b
+        prev = o.states.copy()
+        R = w.frame_rotation(f)
+        ctx.update_probes(R)
+        rec_o = oracle.update_frame(osc, w.lights, [o], R)
+        torch.cuda.synchronize()
+        assert np.array_equal(gv.states.cpu().numpy(), o.states), f
+        for a, b in zip(prev, o.states):
+            if a != b:
+                seen[(int(a), int(b))] = seen.get((int(a), int(b)), 0) + 1
+        rec_g = ctx.ray_records(0)
+        tainted, _, rep = compare_records(rec_g, rec_o, taint)
+        print(f"[dynamic] frame {f}: states {np.bincount(o.states, minlength=6)} {rep}", flush=True)
+        assert rep["unflagged_flips"] == 0
+        ok, _ = within(rec_g["rgb"][~tainted], rec_o["rgb"][~tainted], kappa=rec_o["kappa"][~tainted])
+        assert ok.all(), np.argwhere(~ok)[:5]
+        tp = np.unique(rec_g["probe"][tainted])
+        clean = [q for q in range(gv.n_probes) if q not in set(tp.tolist())]
+        worst, bad = texel_check(gv, o, clean, rec_o, slots_of(rec_g, w.volumes[0].rays_per_probe))
+        print(f"[dynamic] frame {f}: texel worst err/tol {worst:.3f}", flush=True)
+        assert not bad, bad[:5]
+        taint = tp.astype(np.int64)
+    print(f"[dynamic] state transitions over the frames: {seen}", flush=True)
+    assert seen.get((S.NEWLY_AWAKE, S.AWAKE), 0) > 0       # promotion of woken probes
+    assert seen.get((S.AWAKE, S.SLEEPING), 0) > 0          # released after the move
+    assert seen.get((S.SLEEPING, S.AWAKE), 0) > 0          # woken after the move (and promoted in the frame)
+    ctx.close()
