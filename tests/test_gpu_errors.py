@@ -1,0 +1,83 @@
+"""Errors at the C ABI on a live GPU context.
+
+Each rejected call returns its status before anything is enqueued and
+leaves the context as it was: after a series of rejected calls (frames
+before a scene or a volume exists, 33 lights, a non-finite sky, an empty or
+non-finite classification, a non-finite frame rotation, a negative or
+null query batch) the context's classification, two frames and a query
+are bit for bit those of a fresh context that saw no error."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2009_10796_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _expect(irf, status, fn, *args):
+    with pytest.raises(irf.IrfError) as e:
+        fn(*args)
+    assert e.value.status == status, (e.value.status, status)
+
+
+def test_rejected_calls_leave_the_context_usable(torch):
+    from paper_2009_10796_amd import irf
+    w = S.config0()
+    R1 = w.frame_rotation(1)
+    c = irf.Context(0)
+    _expect(irf, irf.E_STATE, c.update_probes, R1)               # no scene
+    c.set_scene(w.scene)
+    _expect(irf, irf.E_STATE, c.update_probes, R1)               # no volume
+    c.set_lights(w.lights)
+    for d in w.volumes:
+        c.create_volume(d)
+    L = w.lights
+    many = S.Lights(L.dir_to_light, L.dir_irradiance, np.tile(np.float32([[4.0, 4.0, 4.0]]), (33, 1)),
+                    np.ones((33, 3), np.float32), L.sky)
+    _expect(irf, irf.E_INVALID, c.set_lights, many)              # 34 lights > 32
+    _expect(irf, irf.E_INVALID, c.set_lights,
+            S.Lights(L.dir_to_light, L.dir_irradiance, L.point_pos, L.point_intensity,
+                     np.float32([np.nan, 0.0, 0.0])))
+    _expect(irf, irf.E_INVALID, c.classify, np.zeros((0, 9), np.float32))
+    bad_r = w.classify_rotations.copy()
+    bad_r[2, 4] = np.inf
+    _expect(irf, irf.E_INVALID, c.classify, bad_r)
+    nan_r = R1.copy().reshape(9)
+    nan_r[0] = np.nan
+    _expect(irf, irf.E_INVALID, c.update_probes, nan_r)
+    lib = irf.load()
+    p = torch.zeros((4, 3), dtype=torch.float32, device="cuda")
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ptr = C.c_void_p(p.data_ptr())
+    assert lib.irf_query_irradiance(c.handle, ptr, ptr, ptr, -1, ptr, s) == irf.E_INVALID
+    assert lib.irf_query_irradiance(c.handle, None, ptr, ptr, 4, ptr, s) == irf.E_INVALID
+    assert lib.irf_query_irradiance(c.handle, ptr, ptr, ptr, 0, None, s) == irf.OK   # empty batch
+    assert lib.irf_last_error()                                   # a detail string is kept
+    # the same work on this context and on a fresh one
+    fresh = irf.build_workload(w)
+    q = w.queries
+    pos, nrm, view = (torch.from_numpy(a).cuda() for a in (q.pos, q.nrm, q.view))
+    res = []
+    for ctx in (c, fresh):
+        ctx.classify(w.classify_rotations)
+        for f in (1, 2):
+            ctx.update_probes(w.frame_rotation(f))
+        e = ctx.query_irradiance(pos, nrm, view)
+        torch.cuda.synchronize()
+        v = ctx.volumes[0]
+        res.append((v.states.cpu().numpy(), v.irradiance.cpu().numpy(), v.distance.cpu().numpy(), e.cpu().numpy()))
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+    assert c.n_lights == fresh.n_lights
+    c.close()
+    fresh.close()
