@@ -120,11 +120,12 @@ def host_cpu() -> dict:
 
 
 # The oracle's full step at one thread, in a child process (OpenMP fixes its
-# thread count at start-up): warm-up frame, then one timed update frame and
-# the G-buffer query.
+# thread count at start-up): warm-up frame, then three timed steps (update
+# frame + G-buffer query), the median reported.
 _ONE_THREAD_STEP = r"""
 import json, sys, time
 sys.path.insert(0, sys.argv[1])
+import numpy as np
 import oracle
 from paper_2009_10796_amd import scenes as S
 w = S.config1()
@@ -133,17 +134,23 @@ ov = [oracle.Volume(d) for d in w.volumes]
 oracle.classify(sc, ov, w.classify_rotations)
 oracle.update_frame(sc, w.lights, ov, w.frame_rotation(1), records=False)
 q = w.queries
-t0 = time.perf_counter()
-oracle.update_frame(sc, w.lights, ov, w.frame_rotation(2), records=False)
-t1 = time.perf_counter()
-oracle.query(ov, q.pos, q.nrm, q.view)
-t2 = time.perf_counter()
-print(json.dumps({"update_ms": 1e3 * (t1 - t0), "query_ms": 1e3 * (t2 - t1)}))
+upd, qry = [], []
+for f in (2, 3, 4):
+    t0 = time.perf_counter()
+    oracle.update_frame(sc, w.lights, ov, w.frame_rotation(f), records=False)
+    t1 = time.perf_counter()
+    oracle.query(ov, q.pos, q.nrm, q.view)
+    t2 = time.perf_counter()
+    upd.append(t1 - t0)
+    qry.append(t2 - t1)
+tot = [a + b for a, b in zip(upd, qry)]
+i = int(np.argsort(tot)[1])
+print(json.dumps({"update_ms": 1e3 * upd[i], "query_ms": 1e3 * qry[i]}))
 """
 
 
 def cpu_one_thread() -> dict:
-    """The same step of the oracle on one host core (one frame)."""
+    """The same step of the oracle on one host core (median of three steps)."""
     import subprocess
     env = dict(os.environ, OMP_NUM_THREADS="1")
     try:
