@@ -149,11 +149,11 @@ __device__ inline int traverse(const SceneGPU& sc, const Ray& ray, float tmax, f
       const int l0 = bits_i(n3.x), l1 = bits_i(n3.y);
       // branch-free step: descend into the nearer child that was hit and
       // push the other one if both were; with neither, pop.  The slot above
-      // the top is always written (the stack has one spare entry).
+      // the top is always written (it exists: see stack_bytes).
       const bool first0 = h0 & (!h1 | (t0 <= t1));
       const int nearc = first0 ? l0 : l1;
       const int farc = first0 ? l1 : l0;
-      const int top = sp < sc.stack_depth ? sp : sc.stack_depth;
+      const int top = sp < sc.stack_depth - 1 ? sp : sc.stack_depth - 1;
       stack[top * stride] = farc;
       sp = top + ((h0 && h1) ? 1 : 0);
       // the pop is read whether or not it is taken (no branch); an empty
@@ -253,8 +253,15 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t n) {
 }
 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+// One column of stack_depth entries per lane.  The depth counts the root as 1
+// and the leaves, which live in their parent's link, so a lane at an inner
+// node of depth k holds at most k - 1 entries and writes at index <= k - 1:
+// indices stay below stack_depth - 1, and the spare write of the branch-free
+// step (and the clamp in the traversal, which never binds) fits in the
+// column.  For the city's depth-20 tree a 128-lane workgroup then takes
+// 10 KiB of LDS: sixteen workgroups, eight waves per SIMD.
 static inline size_t stack_bytes(const SceneGPU& sc) {
-  return sizeof(int) * (size_t)((sc.stack_depth > 0 ? sc.stack_depth : 1) + 1) * kTraceBlock;   // + spare
+  return sizeof(int) * (size_t)(sc.stack_depth > 0 ? sc.stack_depth : 1) * kTraceBlock;
 }
 
 // Whether a shadow ray from front-face hit X toward light l is needed (the
