@@ -1026,18 +1026,30 @@ irf_status irf_graph_capture(irf_ctx* c, void* stream, irf_graph** out) {
     c->prof = prof;
     return fail(IRF_E_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
   }
-  enqueue_frame(c, identity, st);
+  // the capture is always ended, and the graph destroyed on any failure
+  const hipError_t qe = enqueue_frame(c, identity, st);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(st, &graph);
   c->prof = prof;
   if (e != hipSuccess) return fail(IRF_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  if (qe != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(IRF_E_HIP, "capturing the frame: %s", hipGetErrorString(qe));
+  }
+  size_t n = 0;
+  std::vector<hipGraphNode_t> nodes;
+  e = hipGraphGetNodes(graph, nullptr, &n);
+  if (e == hipSuccess && n) {
+    nodes.resize(n);
+    e = hipGraphGetNodes(graph, nodes.data(), &n);
+  }
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(IRF_E_HIP, "hipGraphGetNodes: %s", hipGetErrorString(e));
+  }
   irf_graph* g = new irf_graph();
   g->graph = graph;
   g->ctx = c;
-  size_t n = 0;
-  HIP_TRY(hipGraphGetNodes(graph, nullptr, &n));
-  std::vector<hipGraphNode_t> nodes(n);
-  if (n) HIP_TRY(hipGraphGetNodes(graph, nodes.data(), &n));
   for (auto node : nodes) {
     hipGraphNodeType type;
     if (hipGraphNodeGetType(node, &type) != hipSuccess || type != hipGraphNodeTypeKernel) continue;
