@@ -379,7 +379,7 @@ def main():
                          "scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "the library runs on one GPU; runs on several GPUs are not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -39,7 +39,7 @@ typedef enum {
   IRF_E_NOMEM = 2,       /* device or host allocation failed */
   IRF_E_HIP = 3,         /* a HIP runtime call failed (message has details) */
   IRF_E_STATE = 4,       /* call not valid now (e.g. update before bind) */
-  IRF_E_UNSUPPORTED = 5  /* valid request this build does not implement */
+  IRF_E_UNSUPPORTED = 5  /* valid request the library does not implement */
 } irf_status;
 
 /* Probe states (Section "Probe States"). */
