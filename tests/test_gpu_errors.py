@@ -2,9 +2,10 @@
 
 Each rejected call returns its status before anything is enqueued and
 leaves the context as it was: after a series of rejected calls (frames
-before a scene or a volume exists, 33 lights, a non-finite sky, an empty or
+before a scene or a volume exists, 34 lights, a non-finite sky, an empty or
 non-finite classification, a non-finite frame rotation, a negative or
-null query batch) the context's classification, two frames and a query
+null query batch, query tensors of the wrong type, layout, device or
+shape) the context's classification, two frames and a query
 are bit for bit those of a fresh context that saw no error."""
 import ctypes as C
 
@@ -63,6 +64,11 @@ def test_rejected_calls_leave_the_context_usable(torch):
     assert lib.irf_query_irradiance(c.handle, None, ptr, ptr, 4, ptr, s) == irf.E_INVALID
     assert lib.irf_query_irradiance(c.handle, ptr, ptr, ptr, 0, None, s) == irf.OK   # empty batch
     assert lib.irf_last_error()                                   # a detail string is kept
+    # the binding checks query tensors before calling the library
+    good = torch.zeros((8, 3), dtype=torch.float32, device="cuda")
+    for bad in (good.double(), torch.zeros((3, 8), dtype=torch.float32, device="cuda").t(), good.cpu(),
+                torch.zeros((8, 4), dtype=torch.float32, device="cuda")):
+        _expect(irf, irf.E_INVALID, c.query_irradiance, bad, good, good)
     # the same work on this context and on a fresh one
     fresh = irf.build_workload(w)
     q = w.queries
