@@ -186,7 +186,8 @@ struct FrameBegin {
   ObjectBoxes ob;
   FrameScratch fs;
   int32_t dir_blocks;    // workgroups of ray directions per volume
-  int32_t weight_rows;   // blend weight rows per volume (0: no matrix-core volume)
+  int32_t weight_rows;   // workgroups of blend weight rows per volume (0: no matrix-core volume)
+  int32_t row_waves;     // waves per weight row (the largest ray count over 64, rounded up)
   int32_t compact;       // 1: the last workgroup steps the states and packs the active list
   int32_t total_probes;  // probes of every volume
 };

@@ -180,41 +180,50 @@ __device__ __forceinline__ bool row_direction(int row, float3& n) {
   return true;
 }
 
-// One weight row of volume v over all rays (ray directions recomputed here:
-// the same function of (ray, rotation) as the direction table).
-__device__ void weight_row(const FrameBegin& a, int v, int row) {
+// Weight rows of volume v over all rays (ray directions recomputed here:
+// the same function of (ray, rotation) as the direction table).  A workgroup
+// holds 16 / row_waves rows, each on row_waves consecutive waves, so short
+// rows (few rays) share a workgroup instead of leaving most of it idle.
+__device__ void weight_rows(const FrameBegin& a, int v, int block) {
   __shared__ float part[kBeginBlock / 64];
   const VolumeGPU& V = a.vs.v[v];
   if (V.blend == IRF_BLEND_F32_VALU) return;
   const FrameScratch& fs = a.fs;
   const int N = V.rays;
+  const int per_row = a.row_waves * 64;                 // lanes of one row
+  const int rows_here = kBeginBlock / per_row;          // rows of this workgroup
+  const int sub = threadIdx.x / per_row;
+  const int row = block * rows_here + sub;
+  const bool live = sub < rows_here && row < kRows;
   float3 n = f3(0.0f, 0.0f, 0.0f);
-  const bool real = row_direction(row, n);
+  const bool real = live && row_direction(row, n);
   float sum = 0.0f;
   char* base = (char*)fs.weights + V.weight_base;
-  for (int k = threadIdx.x; k < N; k += kBeginBlock) {
-    float w = 0.0f;
-    if (real) {
-      const float3 o = sf_direction(k, N, a.p.R);
-      const float c = fmaf(n.x, o.x, fmaf(n.y, o.y, n.z * o.z));
-      w = c > 0.0f ? (row < kIrrRows ? c : pow_weight(c, V)) : 0.0f;
-    }
-    w = round_to(w, V.blend);
-    sum += w;
-    if (V.blend == IRF_BLEND_F32) {
-      ((float*)base)[(size_t)k * kRows + row] = w;               // [k][row]
-    } else if (V.blend == IRF_BLEND_BF16) {
-      ((__bf16*)base)[(size_t)row * N + k] = (__bf16)w;          // [row][k]
-    } else {
-      ((_Float16*)base)[(size_t)row * N + k] = (_Float16)w;
+  if (live) {
+    for (int k = threadIdx.x - sub * per_row; k < N; k += per_row) {
+      float w = 0.0f;
+      if (real) {
+        const float3 o = sf_direction(k, N, a.p.R);
+        const float c = fmaf(n.x, o.x, fmaf(n.y, o.y, n.z * o.z));
+        w = c > 0.0f ? (row < kIrrRows ? c : pow_weight(c, V)) : 0.0f;
+      }
+      w = round_to(w, V.blend);
+      sum += w;
+      if (V.blend == IRF_BLEND_F32) {
+        ((float*)base)[(size_t)k * kRows + row] = w;               // [k][row]
+      } else if (V.blend == IRF_BLEND_BF16) {
+        ((__bf16*)base)[(size_t)row * N + k] = (__bf16)w;          // [row][k]
+      } else {
+        ((_Float16*)base)[(size_t)row * N + k] = (_Float16)w;
+      }
     }
   }
   for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = sum;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (live && threadIdx.x == sub * per_row) {
     float t = 0.0f;
-    for (int w = 0; w < kBeginBlock / 64; w++) t += part[w];
+    for (int w = 0; w < a.row_waves; w++) t += part[sub * a.row_waves + w];
     fs.inv_row_sum[v * kRows + row] = t > 0.0f ? 1.0f / t : 0.0f;
   }
 }
@@ -233,7 +242,7 @@ __global__ __launch_bounds__(kBeginBlock) void k_frame_begin(FrameBegin a) {
     const float3 w = sf_direction(r, V.rays, a.p.R);
     a.fs.omega[V.omega_base + r] = make_float4(w.x, w.y, w.z, 0.0f);
   } else if (x < a.dir_blocks + a.weight_rows) {
-    weight_row(a, v, x - a.dir_blocks);
+    weight_rows(a, v, x - a.dir_blocks);
   } else if (v == 0 && a.compact) {
     compact_small(a);
   }
@@ -334,7 +343,9 @@ FrameBegin make_frame_begin(const FrameParams& p, const VolumeSet& vs, ObjectBox
     P += vs.v[v].n_probes;
   }
   a.dir_blocks = (maxr + kBeginBlock - 1) / kBeginBlock;
-  a.weight_rows = weights ? kRows : 0;
+  a.row_waves = (maxr + 63) / 64 > 0 ? (maxr + 63) / 64 : 1;      // <= 16: at most 1024 rays
+  const int rows_per_block = (kBeginBlock / 64) / a.row_waves;
+  a.weight_rows = weights ? (kRows + rows_per_block - 1) / rows_per_block : 0;
   a.total_probes = P;
   a.compact = P <= kSmallProbes ? 1 : 0;
   return a;
