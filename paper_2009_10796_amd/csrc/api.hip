@@ -95,9 +95,6 @@ struct irf_ctx {
   DevBuf<uint8_t> vis;
   DevBuf<float4> rays;
   DevBuf<float4> shadow_tasks;
-  DevBuf<int32_t> wave_tasks;
-  DevBuf<int64_t> wave_offset;
-  DevBuf<int32_t> batch_wave;
   DevBuf<unsigned long long> stats;
   DevBuf<char> weights;
   DevBuf<float> inv_row_sum;
@@ -251,10 +248,8 @@ irf_status ensure_scratch(irf_ctx* c) {
   if ((s = c->hits.reserve((size_t)R)) != IRF_OK) return s;
   if ((s = c->vis.reserve((size_t)R * (size_t)(nl > 0 ? nl : 1))) != IRF_OK) return s;
   if ((s = c->rays.reserve((size_t)R)) != IRF_OK) return s;
-  if ((s = c->shadow_tasks.reserve((size_t)((R + 63) / 64 * 64) * (size_t)(nl > 0 ? nl : 1))) != IRF_OK) return s;
-  if ((s = c->wave_tasks.reserve((size_t)((R + 63) / 64))) != IRF_OK) return s;
-  if ((s = c->wave_offset.reserve((size_t)((R + 63) / 64 + 1))) != IRF_OK) return s;
-  if ((s = c->batch_wave.reserve((size_t)((R + 63) / 64) * (size_t)(nl > 0 ? nl : 1))) != IRF_OK) return s;
+  if ((s = c->shadow_tasks.reserve((size_t)(kTaskRegions * task_region_cap(R, nl > 0 ? nl : 1)))) != IRF_OK)
+    return s;
   if ((s = c->stats.reserve(8)) != IRF_OK) return s;
   if (c->diff) {
     int64_t off = 0;
@@ -289,9 +284,6 @@ FrameScratch scratch_view(const irf_ctx* c) {
   f.vis = c->vis.p;
   f.rays = c->rays.p;
   f.shadow_tasks = c->shadow_tasks.p;
-  f.wave_tasks = c->wave_tasks.p;
-  f.wave_offset = c->wave_offset.p;
-  f.batch_wave = c->batch_wave.p;
   f.grad_rays = c->grad_rays.p;
   f.probe_pos = c->probe_pos.p;
   f.weights = c->weights.p;
@@ -387,7 +379,6 @@ hipError_t enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st, hipE
   }
   { ProfScope p(c, "trace", st); launch_trace(vs, sc, fs, c->tune.trace_blocks, st); }
   if (nl > 0) {
-    { ProfScope p(c, "scan_tasks", st); launch_scan_tasks(vs, fs, st); }
     { ProfScope p(c, "shadow", st); launch_shadow(vs, sc, nl, fs, c->tune.shadow_blocks, st); }
   }
   { ProfScope p(c, "shade", st); launch_shade(vs, sc, fs, c->tune.shade_blocks, st); }
@@ -495,9 +486,6 @@ void irf_destroy(irf_ctx* c) {
   c->vis.release();
   c->rays.release();
   c->shadow_tasks.release();
-  c->wave_tasks.release();
-  c->wave_offset.release();
-  c->batch_wave.release();
   c->stats.release();
   c->specular.release();
   c->saved.release();

@@ -107,11 +107,25 @@ struct ObjectBoxes {
   int32_t n;
 };
 
+// Shadow tasks are queued in kTaskRegions regions of the task array, a
+// source wave's region chosen by its index, so that waves reserving their
+// runs at the same time add to different counters (one shared counter
+// serialises every wave of the trace on one address).  One region per lane
+// of a wave.
+constexpr int kTaskRegions = 64;
+
+// Tasks one region can hold: its share of the source waves of 64 rays, up
+// to 64 * n_lights tasks each.
+__host__ __device__ inline int64_t task_region_cap(int64_t max_rays, int n_lights) {
+  const int64_t waves = (max_rays + 63) / 64;
+  return (waves + kTaskRegions - 1) / kTaskRegions * 64 * (int64_t)n_lights;
+}
+
 // Per-frame counters written by the compaction kernel.
 struct FrameCounters {
-  int32_t slot_base[IRF_MAX_VOLUMES + 1];  // active probes of volume v: [slot_base[v], slot_base[v+1])
-  int64_t ray_base[IRF_MAX_VOLUMES + 1];   // rays of volume v: [ray_base[v], ray_base[v+1])
-  int64_t shadow_total;                    // shadow rays queued this frame
+  int32_t slot_base[IRF_MAX_VOLUMES + 1];   // active probes of volume v: [slot_base[v], slot_base[v+1])
+  int64_t ray_base[IRF_MAX_VOLUMES + 1];    // rays of volume v: [ray_base[v], ray_base[v+1])
+  uint64_t task_count[kTaskRegions];        // shadow rays queued in each task region this frame
 };
 
 // Scene on the device.
@@ -153,13 +167,9 @@ struct FrameScratch {
   HitRec* hits;             // [max_rays]
   uint8_t* vis;             // [n_lights][max_rays]
   float4* rays;             // [max_rays] rgb + distance (float32 path)
-  float4* shadow_tasks;     // [max_rays * n_lights]: per source wave of 64 rays, a slice of
-                            // 64 * n_lights tasks, light-major: the shadow origin and, in w,
-                            // the bits of (ray id << 5 | light)
-  int32_t* wave_tasks;      // [max_rays / 64] number of tasks in each slice
-  int64_t* wave_offset;     // [max_rays / 64 + 1] exclusive prefix sum of wave_tasks, then the total
-  int32_t* batch_wave;      // [max_rays * n_lights / 64] slice holding the first task of each
-                            // batch of 64 consecutive tasks
+  float4* shadow_tasks;     // [kTaskRegions][task_region_cap]: one contiguous run per source
+                            // wave of 64 rays in its region, light-major; the shadow origin
+                            // and, in w, the bits of (ray id << 5 | light)
   float4* grad_rays;        // [max_rays] adjoint: dLoss/d(ray radiance)
   float4* probe_pos;        // [max_slots] position of each active probe this frame (by slot),
                             // w = 1 for a Newly state (blended with no hysteresis), else 0
@@ -196,7 +206,6 @@ FrameBegin make_frame_begin(const FrameParams& p, const VolumeSet& vs, ObjectBox
 void launch_frame_begin(const FrameBegin& a, hipStream_t s);
 const void* frame_begin_kernel();
 void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s);
-void launch_scan_tasks(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
 void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, hipStream_t s);
 void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s);
 void launch_blend(const VolumeSet& vs, FrameScratch fs, hipStream_t s);

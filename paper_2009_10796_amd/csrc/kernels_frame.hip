@@ -93,7 +93,7 @@ __device__ __forceinline__ void write_counters(const VolumeSet& vs, const FrameS
   }
   C->slot_base[vs.n] = slot_base[vs.n];
   C->ray_base[vs.n] = rays;
-  C->shadow_total = 0;
+  for (int r = 0; r < kTaskRegions; r++) C->task_count[r] = 0;
 }
 
 // Inclusive prefix sum over the workgroup (kBeginBlock threads); `total`

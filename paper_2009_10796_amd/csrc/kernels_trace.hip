@@ -285,12 +285,14 @@ __device__ __forceinline__ bool shadow_ray(const LightSet& L, int l, float3 X, f
 
 // Nearest hit of every active probe ray, stored with the hit triangle's
 // normal and material for the hit shading.  Front-face hits also queue their
-// shadow rays in the slice of their wave (light-major, so the tasks of one
-// light from one probe stay contiguous) and clear their visibility bytes.
-// No atomics: each wave owns its slice and writes its own count.  The grid
-// strides over the rays of all volumes (persistent when the grid is smaller
-// than the ray count); the stride is a multiple of 64, so a wave always holds
-// 64 consecutive rays.
+// shadow rays: each wave counts its tasks, reserves one contiguous run of
+// its task region with a single atomic add on the region's counter, and
+// writes them light-major (the tasks of one light from one probe stay
+// contiguous).  Where a wave's run lands depends on timing, what a task
+// computes does not.  Every ray clears its visibility bytes.  The grid strides over
+// the rays of all volumes (persistent when the grid is smaller than the ray
+// count); the stride is a multiple of 64, so a wave always holds 64
+// consecutive rays.
 // The work index walks each probe's rays in the volume's coherent order
 // (compact cones of the pattern, one per wave); results are stored by ray id.
 __device__ __forceinline__ void trace_one(const VolumeSet& vs, const SceneGPU& sc, const LightSet& L,
@@ -327,24 +329,40 @@ __device__ __forceinline__ void trace_one(const VolumeSet& vs, const SceneGPU& s
     X = f3(fmaf(h.t, w3.x, o.x), fmaf(h.t, w3.y, o.y), fmaf(h.t, w3.z, o.z));
   }
   const int lane = threadIdx.x & 63;
-  const int64_t wave = work >> 6;
-  float4* slice = fs.shadow_tasks + wave * 64 * nl;
+  uint32_t need_bits = 0;
   int n = 0;
   for (int l = 0; l < nl; l++) {
     fs.vis[(int64_t)l * fs.max_rays + id] = 0;
     bool need = false;
-    float3 Xs, dl;
     if (front) {
+      float3 Xs, dl;
       float tmax;
       need = shadow_ray(L, l, X, ng, Xs, dl, tmax);
     }
-    unsigned long long m = __ballot(need);
-    if (need)
-      slice[n + __popcll(m & ((1ull << lane) - 1ull))] =
-          make_float4(Xs.x, Xs.y, Xs.z, __uint_as_float((uint32_t)(id << 5) | (uint32_t)l));
-    n += __popcll(m);
+    need_bits |= (need ? 1u : 0u) << l;
+    n += __popcll(__ballot(need));
   }
-  if (lane == __ffsll((long long)__ballot(1)) - 1) fs.wave_tasks[wave] = n;
+  if (n == 0) return;
+  const int leader = __ffsll((long long)__ballot(1)) - 1;
+  unsigned long long base = 0;
+  const int64_t region = (work >> 6) & (kTaskRegions - 1);
+  if (lane == leader)
+    base = atomicAdd((unsigned long long*)&fs.counters->task_count[region], (unsigned long long)n);
+  base = __shfl(base, leader);
+  float4* run = fs.shadow_tasks + region * task_region_cap(fs.max_rays, nl) + (int64_t)base;
+  int at = 0;
+  for (int l = 0; l < nl; l++) {
+    const bool need = (need_bits >> l) & 1u;
+    const unsigned long long m = __ballot(need);
+    if (need) {
+      float3 Xs, dl;
+      float tmax;
+      shadow_ray(L, l, X, ng, Xs, dl, tmax);
+      run[at + __popcll(m & ((1ull << lane) - 1ull))] =
+          make_float4(Xs.x, Xs.y, Xs.z, __uint_as_float((uint32_t)(id << 5) | (uint32_t)l));
+    }
+    at += __popcll(m);
+  }
 }
 
 __global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeSet vs, SceneGPU sc, FrameScratch fs) {
@@ -356,82 +374,43 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeSet vs, SceneGPU sc
     trace_one(vs, sc, L, fs, C, work);
 }
 
-// Exclusive prefix sum of the per-wave task counts (one workgroup), with the
-// total as a sentinel after the last wave, and for every batch of 64
-// consecutive tasks the slice that holds its first task.  Tiles of
-// 4 x kScanBlock counts: each thread reads four consecutive counts with one
-// 16-byte load (coalesced across the wave), the workgroup scans the thread
-// sums, and a running carry joins the tiles.
-constexpr int kScanBlock = 1024;
-__global__ __launch_bounds__(kScanBlock) void k_scan_tasks(VolumeSet vs, FrameScratch fs) {
-  __shared__ int64_t wave_sum[kScanBlock / 64];
-  FrameCounters* C = fs.counters;
-  const int64_t waves = (C->ray_base[vs.n] + 63) / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int64_t carry = 0;
-  for (int64_t tile = 0; tile < waves; tile += 4 * kScanBlock) {
-    const int64_t i0 = tile + 4 * (int64_t)threadIdx.x;
-    int32_t c[4];
-    if (i0 + 3 < waves) {
-      const int4 v = *(const int4*)(fs.wave_tasks + i0);
-      c[0] = v.x;
-      c[1] = v.y;
-      c[2] = v.z;
-      c[3] = v.w;
-    } else {
+// The shadow tasks in one dense order, region after region.  Lane r of the
+// wave returns the number of tasks in the regions below r, `total` all of
+// them.  Every lane of the wave must be active.
+static_assert(kTaskRegions == 64, "one task region per lane");
+__device__ __forceinline__ int64_t tasks_before_region(const FrameCounters& C, int64_t& total) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)C.task_count[lane];
+  int64_t incl = c;
 #pragma unroll
-      for (int j = 0; j < 4; j++) c[j] = i0 + j < waves ? fs.wave_tasks[i0 + j] : 0;
-    }
-    const int64_t sum = (int64_t)c[0] + c[1] + c[2] + c[3];
-    // inclusive scan within the wave, then across the waves' totals
-    int64_t incl = sum;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int64_t y = __shfl_up(incl, off);
-      if (lane >= off) incl += y;
-    }
-    if (lane == 63) wave_sum[wave] = incl;
-    __syncthreads();
-    int64_t before = 0, total = 0;
-    for (int w = 0; w < kScanBlock / 64; w++) {
-      const int64_t t = wave_sum[w];
-      before += w < wave ? t : 0;
-      total += t;
-    }
-    __syncthreads();   // wave_sum is rewritten by the next tile
-    int64_t run = carry + before + incl - sum;
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      if (i0 + j >= waves) break;
-      fs.wave_offset[i0 + j] = run;
-      for (int64_t t = (run + 63) & ~63ll; t < run + c[j]; t += 64) fs.batch_wave[t >> 6] = (int32_t)(i0 + j);
-      run += c[j];
-    }
-    carry += total;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
   }
-  if (threadIdx.x == 0) {
-    C->shadow_total = carry;
-    fs.wave_offset[waves] = carry;
-  }
+  total = __shfl(incl, 63);
+  return incl - c;
 }
 
-// Any-hit shadow rays over the dense task index space: task k lives in the
-// slice of the last wave whose offset is <= k, found from the slice of the
-// first task of k's batch of 64.  Grid-stride over all tasks.
+// Index in the task array of task k of the dense order (k < total): the last
+// region starting at or before k (an empty region starts where the next does
+// and is passed over), by bisection over the lanes' `before`.  Every lane of
+// the wave must be active.
+__device__ __forceinline__ int64_t task_index(int64_t before, int64_t k, int64_t cap) {
+  int r = 0;
+#pragma unroll
+  for (int step = kTaskRegions / 2; step > 0; step >>= 1)
+    if (__shfl(before, r + step) <= k) r += step;
+  return r * cap + (k - __shfl(before, r));
+}
+
+// Any-hit shadow rays over the dense task order.  Grid-stride over all
+// tasks, a wave at a time (the index search needs every lane).
 template <typename CNT>
 __device__ __forceinline__ void shadow_one(const VolumeSet& vs, const SceneGPU& sc, const LightSet& L,
-                                           const FrameScratch& fs, const FrameCounters& C, int64_t k, CNT* cnt) {
-  const int nl = L.n_dir + L.n_point;
-  int64_t src = fs.batch_wave[k >> 6];
-  int64_t off = fs.wave_offset[src], next = fs.wave_offset[src + 1];
-  while (next <= k) {
-    src++;
-    off = next;
-    next = fs.wave_offset[src + 1];
-  }
+                                           const FrameScratch& fs, int64_t slot, CNT* cnt) {
   // the task carries the shadow origin computed at the hit, so the ray needs
   // no other load
-  const float4 task = fs.shadow_tasks[src * 64 * nl + (k - off)];
+  const float4 task = fs.shadow_tasks[slot];
   const uint32_t word = __float_as_uint(task.w);
   const int64_t id = word >> 5;
   const int l = word & 31;
@@ -463,9 +442,16 @@ __device__ __forceinline__ void shadow_one(const VolumeSet& vs, const SceneGPU& 
 __global__ __launch_bounds__(kTraceBlock) void k_shadow(VolumeSet vs, SceneGPU sc, FrameScratch fs) {
   const FrameCounters& C = *fs.counters;
   const LightSet& L = fs.params->L;
-  const int64_t total = C.shadow_total;
-  for (int64_t k = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x; k < total; k += (int64_t)gridDim.x * kTraceBlock)
-    shadow_one<NoCount>(vs, sc, L, fs, C, k, nullptr);
+  int64_t total;
+  const int64_t before = tasks_before_region(C, total);
+  const int64_t cap = task_region_cap(fs.max_rays, L.n_dir + L.n_point);
+  const int lane = threadIdx.x & 63;
+  for (int64_t k0 = (int64_t)blockIdx.x * kTraceBlock + (threadIdx.x - lane); k0 < total;
+       k0 += (int64_t)gridDim.x * kTraceBlock) {
+    const int64_t k = k0 + lane;
+    const int64_t slot = task_index(before, k < total ? k : total - 1, cap);
+    if (k < total) shadow_one<NoCount>(vs, sc, L, fs, slot, nullptr);
+  }
 }
 
 // Radiance and distance carried by each probe ray (backface rule of the
@@ -875,9 +861,15 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_count(VolumeSet vs, Scene
 __global__ __launch_bounds__(kTraceBlock) void k_shadow_count(VolumeSet vs, SceneGPU sc, FrameScratch fs,
                                                               unsigned long long* out) {
   const FrameCounters& C = *fs.counters;
-  int64_t k = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
+  const LightSet& L = fs.params->L;
+  int64_t total;
+  const int64_t before = tasks_before_region(C, total);
+  const int64_t k = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
   Count cnt;
-  if (k < C.shadow_total) shadow_one<Count>(vs, sc, fs.params->L, fs, C, k, &cnt);
+  if (total > 0) {
+    const int64_t slot = task_index(before, k < total ? k : total - 1, task_region_cap(fs.max_rays, L.n_dir + L.n_point));
+    if (k < total) shadow_one<Count>(vs, sc, L, fs, slot, &cnt);
+  }
   add_block(&out[2], cnt.nodes);
   add_block(&out[3], cnt.tris);
 }
@@ -908,7 +900,8 @@ __global__ void k_frame_stats(VolumeSet vs, SceneGPU sc, FrameScratch fs, unsign
       if (dot(f3(w.x, w.y, w.z), tri_normal(sc, h.tri)) <= 0.0f) front++;
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) tasks = (unsigned long long)C.shadow_total;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    for (int r = 0; r < kTaskRegions; r++) tasks += (unsigned long long)C.task_count[r];
   atomicAdd(&out[0], tasks);
   atomicAdd(&out[1], front);
 }
@@ -957,10 +950,6 @@ static inline unsigned grid_for(int64_t items, int grid) {
 void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s) {
   if (fs.max_rays == 0) return;
   irf_launch(k_trace, dim3(grid_for(fs.max_rays, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs);
-}
-
-void launch_scan_tasks(const VolumeSet& vs, FrameScratch fs, hipStream_t s) {
-  irf_launch(k_scan_tasks, dim3(1), dim3(kScanBlock), 0, s, vs, fs);
 }
 
 void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, hipStream_t s) {
