@@ -270,8 +270,12 @@ irf_status irf_query_irradiance(irf_ctx* ctx, const float* pos, const float* nrm
 /* Launch shapes of the frame's main kernels: the number of workgroups of
    the persistent probe-ray traversal, shadow-ray traversal, hit shading and
    matrix-core blend; each strides over the work of all volumes.  0 selects
-   one workgroup per work unit of the largest possible frame.  Values are
-   normally chosen by the autotuner (paper_2009_10796_amd/autotune.py). */
+   one workgroup per work unit of the largest possible frame.  A new context
+   starts at 0 except for the shadow rays: 16 workgroups per compute unit,
+   what stays resident at once at eight waves per SIMD, each lane looping
+   over the frame's tasks, instead of a workgroup for every shadow ray the
+   largest frame could queue (most of them empty).  Values are normally
+   chosen by the autotuner (paper_2009_10796_amd/autotune.py). */
 typedef struct {
   int32_t trace_blocks;
   int32_t shadow_blocks;

@@ -459,6 +459,9 @@ irf_status irf_create(int32_t hip_device, irf_ctx** out) {
   irf_ctx* c = new (std::nothrow) irf_ctx();
   if (!c) return fail(IRF_E_NOMEM, "context allocation failed");
   c->device = hip_device;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
+    c->tune.shadow_blocks = 16 * cus;
   memset(&c->lights, 0, sizeof(c->lights));
   for (int v = 0; v < IRF_MAX_VOLUMES; v++) c->bound[v] = false;
   *out = c;
