@@ -8,10 +8,15 @@
   frame start's workgroup.  Records and texels against the FP64 oracle, for
   the float32 and the float16 matrix-core blends.
 * The largest light count (32: the sun and 31 point lights): light index 31
-  in the five light bits of a shadow task, every wave slice 64 x 32 tasks
-  wide, the hit shading's visibility bytes gathered in four groups of
-  eight.  Records (visibility bits of all 32 lights), radiance and texels
-  against the oracle."""
+  in the five light bits of a shadow task, a source wave's run of tasks up
+  to 64 x 32 wide in its task region, the hit shading's visibility bytes
+  gathered in four groups of eight.  Records (visibility bits of all 32
+  lights), radiance and texels against the oracle.
+* Lights but no shadow ray: a frame with shadow tasks in its task regions,
+  then the scene replaced by an empty one, so the next frame's rays all miss
+  and every region stays empty: that frame queues no task (its counters
+  start again from zero), every ray carries the sky, no visibility bit is
+  set."""
 import numpy as np
 import pytest
 
@@ -173,4 +178,25 @@ def test_largest_light_count(torch):
         assert not bad, bad[:5]
         taint = tp.astype(np.int64)
     assert last_light_seen > 0          # the 32nd light reached some hits
+    ctx.close()
+
+
+def test_lights_but_no_shadow_ray(torch):
+    from paper_2009_10796_amd import irf
+    w = S.config0()
+    ctx = irf.build_workload(w)
+    ctx.classify(w.classify_rotations)
+    ctx.update_probes(w.frame_rotation(1))
+    s1 = ctx.frame_stats()
+    assert s1["shadow_rays"] > 0 and s1["front_hits"] > 0
+    ctx.set_scene(S.empty_scene())
+    ctx.update_probes(w.frame_rotation(2))
+    s2 = ctx.frame_stats()
+    torch.cuda.synchronize()
+    print(f"[no shadow ray] frame 1 {s1}, frame 2 {s2}", flush=True)
+    assert s2["probe_rays"] > 0 and s2["front_hits"] == 0 and s2["shadow_rays"] == 0
+    rec = ctx.ray_records(0)
+    assert 0 < len(rec) <= s2["probe_rays"]
+    assert np.all(rec["tri"] < 0) and np.all(rec["vis"] == 0)
+    assert np.array_equal(rec["rgb"], np.broadcast_to(w.lights.sky.astype(np.float32), rec["rgb"].shape))
     ctx.close()
