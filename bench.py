@@ -9,7 +9,10 @@ with hysteresis and border texels, state promotion) followed by the query of
 the full 1920x1080 G-buffer.  Inputs are synthetic and seeded; everything
 is resident on the GPU before timing starts.
 
-Prints one JSON line (see the design notes for the fields).
+Prints one JSON line: the metric and its value (ms per city step), the
+dominant kernel's roofline (algorithmic bytes or flops over its measured
+duration, with DRAM traffic from committed counter figures while the kernel
+sources match them), the oracle's CPU time, and the sections' figures.
 """
 import argparse
 import json
