@@ -10,7 +10,7 @@
  *   "Probe States"                 -> states, full initialization algorithm
  *   "Multiple Probe Volumes"       -> cascade blending
  * Readings where the paper is silent follow the published base method
- * (DDGI, Majercik et al. 2019); each is noted at the function that takes it.
+ * (DDGI, Majercik et al. 2019); the GPU path takes the same readings.
  *
  * Plain, unblocked loops: every function follows the definition it cites.
  */
