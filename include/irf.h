@@ -254,7 +254,9 @@ irf_status irf_update_probes(irf_ctx* ctx, const float* rotation, void* stream);
    before the blend -- state step, rays, traversal, shadow rays, hit shading,
    which only read the atlases -- may then run beside those queries: an
    engine's probe trace for the next frame overlapping its shading of the
-   current one.  The caller orders its next queries after this frame (an
+   current one.  When the scene has dynamic objects the state step can put
+   Awake probes to sleep, which changes what a query samples, so then the
+   whole frame is ordered after the event.  The caller orders its next queries after this frame (an
    event recorded on `stream` after this call).  IRF_E_HIP if waiting on the
    event fails.  Async. */
 irf_status irf_update_probes_after(irf_ctx* ctx, const float* rotation, void* stream, void* atlas_event);

@@ -364,9 +364,18 @@ hipError_t enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st, hipE
   fp.L = c->lights;
   bool any_mma = false, any_valu = false;
   for (int v = 0; v < c->n_vol; v++) (c->vol[v].blend == IRF_BLEND_F32_VALU ? any_valu : any_mma) = true;
+  // With dynamic objects in the scene the state step rewrites probe states
+  // (an Awake probe away from every object goes to sleep), which the queries
+  // read: then the whole frame waits, not only its atlas writes.
+  const ObjectBoxes boxes = boxes_view(c);
+  if (atlas_wait && boxes.n > 0) {
+    hipError_t e = hipStreamWaitEvent(st, atlas_wait, 0);
+    if (e != hipSuccess) return e;
+    atlas_wait = nullptr;
+  }
   {
     ProfScope p(c, "frame_begin", st);
-    launch_frame_begin(make_frame_begin(fp, vs, boxes_view(c), fs, any_mma), st);
+    launch_frame_begin(make_frame_begin(fp, vs, boxes, fs, any_mma), st);
   }
   if (c->diff) {
     // the frame's inputs for the adjoint: atlases and the stepped states
