@@ -3,7 +3,9 @@
 Only the test-suite, the smoke check and the CPU-baseline leg of the
 benchmark may import this package.  It wraps ``liborc.so`` (built from
 ``irf_oracle.c`` by ``oracle/build.py``) with ctypes and keeps all state in
-numpy float64 arrays owned by Python.
+numpy float64 arrays owned by Python.  ``f32=True`` selects ``liborc32.so``,
+the same source built as a float32 evaluation of the value path; it is used
+only to check the oracle's float32 sensitivity estimates (kappa).
 """
 from __future__ import annotations
 
@@ -16,20 +18,28 @@ import numpy as np
 from . import build as _build
 
 OFF, SLEEPING, NEWLY_AWAKE, NEWLY_VIGILANT, AWAKE, VIGILANT = 0, 1, 2, 3, 4, 5
-F_GRAZE, F_TIE, F_NEARMISS, F_EDGEON, F_SHADOW = 1, 2, 4, 8, 16
+F_GRAZE, F_TIE, F_NEARMISS, F_EDGEON, F_SHADOW, F_FORCED, F_FORCE_INVALID = 1, 2, 4, 8, 16, 32, 64
+F_AMBIGUOUS = F_GRAZE | F_TIE | F_NEARMISS | F_EDGEON | F_SHADOW
 CAGE = 16
 
 _lib = None
+_lib32 = None
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_build.LIB):
+def lib(f32: bool = False):
+    """The oracle library (f32=True: its float32 build)."""
+    global _lib, _lib32
+    if (_lib32 if f32 else _lib) is None:
+        path = _build.LIB32 if f32 else _build.LIB
+        if not os.path.exists(path):
             _build.build()
-        _lib = C.CDLL(_build.LIB)
-        _declare(_lib)
-    return _lib
+        L = C.CDLL(path)
+        _declare(L)
+        if f32:
+            _lib32 = L
+        else:
+            _lib = L
+    return _lib32 if f32 else _lib
 
 
 class Hit(C.Structure):
@@ -39,12 +49,14 @@ class Hit(C.Structure):
 class RayRecord(C.Structure):
     _fields_ = [("tri", C.c_int32), ("flags", C.c_int32), ("t", C.c_double), ("rgb", C.c_double * 3),
                 ("d", C.c_double), ("vis", C.c_uint32), ("n_cage", C.c_int32),
-                ("cage", C.c_int32 * CAGE), ("kappa", C.c_double * 3), ("cosi", C.c_double)]
+                ("cage", C.c_int32 * CAGE), ("kappa", C.c_double * 3), ("cosi", C.c_double),
+                ("d_kappa", C.c_double)]
 
 
 RECORD_DTYPE = np.dtype([("tri", np.int32), ("flags", np.int32), ("t", np.float64), ("rgb", np.float64, 3),
                          ("d", np.float64), ("vis", np.uint32), ("n_cage", np.int32),
-                         ("cage", np.int32, CAGE), ("kappa", np.float64, 3), ("cosi", np.float64)], align=True)
+                         ("cage", np.int32, CAGE), ("kappa", np.float64, 3), ("cosi", np.float64),
+                         ("d_kappa", np.float64)], align=True)
 assert RECORD_DTYPE.itemsize == C.sizeof(RayRecord)
 HIT_DTYPE = np.dtype([("tri", np.int32), ("flags", np.int32), ("t", np.float64), ("bmin", np.float64)], align=True)
 
@@ -96,6 +108,8 @@ def _declare(L):
     L.orc_track_volume.argtypes = [vp, vp, vp, vp, i32, vp]
     L.orc_update_frame.restype = i64
     L.orc_update_frame.argtypes = [vp, vp, vp, i32, vp, vp, i64]
+    L.orc_update_frame_forced.restype = i64
+    L.orc_update_frame_forced.argtypes = [vp, vp, vp, i32, vp, vp, i64, i64, vp, vp, vp]
     L.orc_shade_ray.argtypes = [vp, vp, vp, i32, dp, dp, C.c_double, vp]
     L.orc_query_backward.argtypes = [vp, i32, dp, dp, dp, dp, vp]
     L.orc_update_backward.argtypes = [vp, vp, i32, vp, vp, vp, vp, dp]
@@ -172,37 +186,40 @@ def blend_probe_ex(omega, rgb, d, cos_power, alpha_irr, alpha_dist, gamma, thres
 
 class Scene:
     """Oracle-side copy of a scene (FP64 triangles plus the oracle's own
-    median-split BVH, an exact accelerator)."""
+    median-split BVH, an exact accelerator).  f32=True: a scene of the
+    float32 build; every call made with it runs that build."""
 
-    def __init__(self, scene):
+    def __init__(self, scene, f32: bool = False):
+        self.f32 = bool(f32)
+        self.L = lib(self.f32)
         self._keep = [np.ascontiguousarray(x) for x in (scene.vertices, scene.indices, scene.tri_material,
                                                         scene.tri_object, scene.albedo, scene.emission)]
         v, i, m, o, a, e = self._keep
         self.n_triangles = int(i.shape[0])
-        self.handle = lib().orc_scene_create(_p(v), v.shape[0], _p(i), i.shape[0], _p(m), _p(o),
-                                             _p(a), _p(e), a.shape[0])
+        self.handle = self.L.orc_scene_create(_p(v), v.shape[0], _p(i), i.shape[0], _p(m), _p(o),
+                                              _p(a), _p(e), a.shape[0])
         spec = getattr(scene, "specular", None)
         if spec is not None:
             self.set_specular(spec)
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib is not None:
-            _lib.orc_scene_free(self.handle)
+        if getattr(self, "handle", None) and getattr(self, "L", None) is not None:
+            self.L.orc_scene_free(self.handle)
             self.handle = None
 
     def set_specular(self, specular) -> None:
         sp = np.ascontiguousarray(specular, dtype=np.float64).reshape(-1, 3)
-        lib().orc_scene_set_specular(self.handle, _p(sp))
+        self.L.orc_scene_set_specular(self.handle, _p(sp))
 
     def set_emission(self, emission) -> None:
         e = np.ascontiguousarray(emission, dtype=np.float64).reshape(-1, 3)
-        lib().orc_scene_set_emission(self.handle, _p(e))
+        self.L.orc_scene_set_emission(self.handle, _p(e))
 
     def trace(self, origins, dirs, static_only=False, brute=False) -> np.ndarray:
         o = _d(origins).reshape(-1, 3)
         d = _d(dirs).reshape(-1, 3)
         hits = np.zeros(o.shape[0], dtype=HIT_DTYPE)
-        lib().orc_trace_batch(self.handle, o.shape[0], _p(o), _p(d), int(static_only), int(brute), _p(hits))
+        self.L.orc_trace_batch(self.handle, o.shape[0], _p(o), _p(d), int(static_only), int(brute), _p(hits))
         return hits
 
 
@@ -281,7 +298,7 @@ def classify(scene: Scene, vols: List[Volume], rotations: np.ndarray):
     n_flag = np.zeros(total, np.int32)
     t_front = np.zeros(total)
     arr = _vol_array(vols)
-    lib().orc_classify(scene.handle, arr, len(vols), _p(R), R.shape[0], _p(n_back), _p(n_flag), _p(t_front))
+    scene.L.orc_classify(scene.handle, arr, len(vols), _p(R), R.shape[0], _p(n_back), _p(n_flag), _p(t_front))
     return n_back, n_flag, t_front
 
 
@@ -292,7 +309,7 @@ def optimize_offsets(scene: Scene, vol: Volume, rotations, offset_limit: float =
     R = np.ascontiguousarray(rotations, dtype=np.float32).reshape(-1, 9)
     amb = np.zeros(vol.desc.n_probes, dtype=np.int32)
     arr = _vol_array([vol])
-    lib().orc_optimize_offsets(scene.handle, C.byref(arr[0]), _p(R), len(R), float(offset_limit), _p(amb))
+    scene.L.orc_optimize_offsets(scene.handle, C.byref(arr[0]), _p(R), len(R), float(offset_limit), _p(amb))
     return amb
 
 
@@ -304,7 +321,7 @@ def track_volume(scene: Scene, vol: Volume, camera, rotations) -> np.ndarray:
     R = np.ascontiguousarray(rotations, dtype=np.float32).reshape(-1, 9)
     arr = _vol_array([vol])
     shift = np.zeros(3, dtype=np.int32)
-    lib().orc_track_volume(scene.handle, C.byref(arr[0]), _p(cam), _p(R), len(R), _p(shift))
+    scene.L.orc_track_volume(scene.handle, C.byref(arr[0]), _p(cam), _p(R), len(R), _p(shift))
     for a in range(3):
         vol.origin[a] = arr[0].origin[a]
         vol.phase[a] = arr[0].phase[a]
@@ -313,10 +330,14 @@ def track_volume(scene: Scene, vol: Volume, camera, rotations) -> np.ndarray:
 
 
 def state_step(scene: Scene, vols: List[Volume]):
-    lib().orc_state_step(scene.handle, _vol_array(vols), len(vols))
+    scene.L.orc_state_step(scene.handle, _vol_array(vols), len(vols))
 
 
-def update_frame(scene: Scene, lights, vols: List[Volume], R, records: bool = True):
+def update_frame(scene: Scene, lights, vols: List[Volume], R, records: bool = True, force=None):
+    """One update frame of all volumes (in place).  force: None, or
+    (mask uint8[n], tri int32[n], vis uint32[n]) over record indices -- bit 0
+    of mask adopts tri as the ray's hit (-1: miss), bit 1 adopts vis as its
+    shadow bits (see orc_update_frame_forced)."""
     R = np.ascontiguousarray(R, dtype=np.float32).reshape(9)
     L = make_lights(lights)
     # states change inside; the number of active probes is known after the
@@ -324,27 +345,36 @@ def update_frame(scene: Scene, lights, vols: List[Volume], R, records: bool = Tr
     cap = sum(v.desc.n_probes * v.desc.rays_per_probe for v in vols) if records else 0
     rec = np.zeros(cap, dtype=RECORD_DTYPE)
     arr = _vol_array(vols)
-    n = lib().orc_update_frame(scene.handle, C.byref(L), arr, len(vols), _p(R),
-                               _p(rec) if records else None, cap)
+    if force is None:
+        n = scene.L.orc_update_frame(scene.handle, C.byref(L), arr, len(vols), _p(R),
+                                     _p(rec) if records else None, cap)
+    else:
+        fm = np.ascontiguousarray(force[0], dtype=np.uint8)
+        ft = np.ascontiguousarray(force[1], dtype=np.int32)
+        fv = np.ascontiguousarray(force[2], dtype=np.uint32)
+        assert fm.shape == ft.shape == fv.shape
+        n = scene.L.orc_update_frame_forced(scene.handle, C.byref(L), arr, len(vols), _p(R),
+                                            _p(rec) if records else None, cap, fm.shape[0], _p(fm), _p(ft), _p(fv))
     return rec[:n] if records else None
 
 
-def query(vols: List[Volume], pos, nrm, view):
+def query(vols: List[Volume], pos, nrm, view, f32: bool = False):
     pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
     nrm = np.ascontiguousarray(nrm, dtype=np.float32).reshape(-1, 3)
     view = np.ascontiguousarray(view, dtype=np.float32).reshape(-1, 3)
     out = np.zeros((pos.shape[0], 3))
     kap = np.zeros((pos.shape[0], 3))
-    lib().orc_query_batch(_vol_array(vols), len(vols), pos.shape[0], _p(pos), _p(nrm), _p(view), _p(out), _p(kap))
+    lib(f32).orc_query_batch(_vol_array(vols), len(vols), pos.shape[0], _p(pos), _p(nrm), _p(view), _p(out),
+                             _p(kap))
     return out, kap
 
 
-def query_look(vols: List[Volume], X, n, wo, look):
+def query_look(vols: List[Volume], X, n, wo, look, f32: bool = False):
     """One query with the texels sampled in direction `look` (the probes'
     filtered radiance); returns (value[3], kappa[3])."""
     out, kap = np.zeros(3), np.zeros(3)
-    lib().orc_query_look(_vol_array(vols), len(vols), _p(_d(X, 3)), _p(_d(n, 3)), _p(_d(wo, 3)), _p(_d(look, 3)),
-                         _p(out), _p(kap), None, None)
+    lib(f32).orc_query_look(_vol_array(vols), len(vols), _p(_d(X, 3)), _p(_d(n, 3)), _p(_d(wo, 3)),
+                            _p(_d(look, 3)), _p(out), _p(kap), None, None)
     return out, kap
 
 
@@ -357,16 +387,16 @@ def glossy(scene: Scene, lights, vols: List[Volume], pos, nrm, view) -> np.ndarr
     view = np.ascontiguousarray(view, dtype=np.float32).reshape(-1, 3)
     rec = np.zeros(pos.shape[0], dtype=RECORD_DTYPE)
     L = make_lights(lights)
-    lib().orc_glossy_batch(scene.handle, C.byref(L), _vol_array(vols), len(vols), pos.shape[0], _p(pos), _p(nrm),
-                           _p(view), _p(rec))
+    scene.L.orc_glossy_batch(scene.handle, C.byref(L), _vol_array(vols), len(vols), pos.shape[0], _p(pos),
+                             _p(nrm), _p(view), _p(rec))
     return rec
 
 
 def shade_ray(scene: Scene, lights, vols: List[Volume], o, w, dmax) -> np.ndarray:
     L = make_lights(lights)
     rec = np.zeros(1, dtype=RECORD_DTYPE)
-    lib().orc_shade_ray(scene.handle, C.byref(L), _vol_array(vols), len(vols), _p(_d(o, 3)), _p(_d(w, 3)),
-                        float(dmax), _p(rec))
+    scene.L.orc_shade_ray(scene.handle, C.byref(L), _vol_array(vols), len(vols), _p(_d(o, 3)), _p(_d(w, 3)),
+                          float(dmax), _p(rec))
     return rec[0]
 
 
@@ -436,8 +466,8 @@ def update_backward(scene: Scene, prev: List[Volume], R, records, g_new_irr, g_n
     assert g_emission.dtype == np.float64 and g_emission.flags.c_contiguous
     Gn = _grads(g_new_irr, g_new_dist, a_new_irr, a_new_dist)
     Gp = _grads(g_prev_irr, g_prev_dist, a_prev_irr, a_prev_dist, s_prev_irr, s_prev_dist)
-    lib().orc_update_backward(scene.handle, _vol_array(prev), len(prev), _p(R), _p(rec), C.byref(Gn), C.byref(Gp),
-                              _p(g_emission))
+    scene.L.orc_update_backward(scene.handle, _vol_array(prev), len(prev), _p(R), _p(rec), C.byref(Gn),
+                                C.byref(Gp), _p(g_emission))
 
 
 def copy_volumes(vols: List[Volume]) -> List[Volume]:

@@ -17,9 +17,21 @@
 #include "irf_oracle.h"
 
 #include <float.h>
-#include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#include <tgmath.h>
+
+/* Arithmetic type of the value path (octahedral map, ray directions,
+   shading, blend, query).  The oracle is double.  The same source built with
+   -DORC_REAL=float (and single-precision constants) is a float32 evaluation
+   of the same steps, used only to check the oracle's own float32
+   sensitivity estimate (kappa) as an error bound.  Nearest-hit search,
+   flags, classification and the adjoint stay double in both builds; every
+   interface array is double in both (a float32 build rounds what it reads). */
+#ifndef ORC_REAL
+#define ORC_REAL double
+#endif
+typedef ORC_REAL real;
 
 #define EPS_B 1e-4   /* barycentric margin for flags */
 #define EPS_T 1e-6   /* relative distance margin for flags */
@@ -45,6 +57,26 @@ static inline void normalize3(double a[3]) {
 }
 static inline double clampd(double x, double lo, double hi) { return x < lo ? lo : (x > hi ? hi : x); }
 static inline double signnz(double x) { return x >= 0.0 ? 1.0 : -1.0; }
+
+/* the same helpers in the value-path type */
+static inline real dot3r(const real a[3], const real b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static inline void sub3r(const real a[3], const real b[3], real r[3]) {
+  r[0] = a[0] - b[0]; r[1] = a[1] - b[1]; r[2] = a[2] - b[2];
+}
+static inline void cross3r(const real a[3], const real b[3], real r[3]) {
+  r[0] = a[1] * b[2] - a[2] * b[1];
+  r[1] = a[2] * b[0] - a[0] * b[2];
+  r[2] = a[0] * b[1] - a[1] * b[0];
+}
+static inline real len3r(const real a[3]) { return sqrt(dot3r(a, a)); }
+static inline void normalize3r(real a[3]) {
+  real l = len3r(a);
+  if (l > 0) { a[0] /= l; a[1] /= l; a[2] /= l; }
+  else { a[0] = a[1] = a[2] = 0; }
+}
+static inline real clampr(real x, real lo, real hi) { return x < lo ? lo : (x > hi ? hi : x); }
+static inline real signnzr(real x) { return x >= 0 ? 1 : -1; }
+static inline void load3r(const double a[3], real r[3]) { r[0] = (real)a[0]; r[1] = (real)a[1]; r[2] = (real)a[2]; }
 
 /* ------------------------------------------------------------------ scene */
 typedef struct {
@@ -400,12 +432,12 @@ static int occluded(const orc_scene* s, const double o[3], const double d[3], do
 /* -------------------------------------------------------------- octahedral */
 /* Octahedral map of the unit sphere onto [-1,1]^2 (Cigolle et al. 2014),
    used for the probe tiles (Section "Probe Representation" and Table 2). */
-void orc_oct_encode(const double v[3], double p[2]) {
-  double l1 = fabs(v[0]) + fabs(v[1]) + fabs(v[2]);
-  double x = v[0] / l1, y = v[1] / l1;
+static void oct_encode_r(const real v[3], real p[2]) {
+  real l1 = fabs(v[0]) + fabs(v[1]) + fabs(v[2]);
+  real x = v[0] / l1, y = v[1] / l1;
   if (v[2] < 0.0) {
-    double nx = (1.0 - fabs(y)) * signnz(x);
-    double ny = (1.0 - fabs(x)) * signnz(y);
+    real nx = (1.0 - fabs(y)) * signnzr(x);
+    real ny = (1.0 - fabs(x)) * signnzr(y);
     x = nx;
     y = ny;
   }
@@ -413,24 +445,44 @@ void orc_oct_encode(const double v[3], double p[2]) {
   p[1] = y;
 }
 
-void orc_oct_decode(const double p[2], double v[3]) {
-  double x = p[0], y = p[1];
-  double z = 1.0 - fabs(x) - fabs(y);
+static void oct_decode_r(const real p[2], real v[3]) {
+  real x = p[0], y = p[1];
+  real z = 1.0 - fabs(x) - fabs(y);
   if (z < 0.0) {
-    double nx = (1.0 - fabs(y)) * signnz(x);
-    double ny = (1.0 - fabs(x)) * signnz(y);
+    real nx = (1.0 - fabs(y)) * signnzr(x);
+    real ny = (1.0 - fabs(x)) * signnzr(y);
     x = nx;
     y = ny;
   }
   v[0] = x; v[1] = y; v[2] = z;
-  normalize3(v);
+  normalize3r(v);
+}
+
+void orc_oct_encode(const double v[3], double p[2]) {
+  real vr[3], pr[2];
+  load3r(v, vr);
+  oct_encode_r(vr, pr);
+  p[0] = pr[0];
+  p[1] = pr[1];
+}
+
+void orc_oct_decode(const double p[2], double v[3]) {
+  real pr[2] = {(real)p[0], (real)p[1]}, vr[3];
+  oct_decode_r(pr, vr);
+  for (int a = 0; a < 3; a++) v[a] = vr[a];
 }
 
 /* interior cell (x, y) of an m x m tile covers [-1,1]^2 in k = m-2 cells */
-void orc_texel_direction(int32_t m, int32_t x, int32_t y, double v[3]) {
+static void texel_direction_r(int32_t m, int32_t x, int32_t y, real v[3]) {
   int32_t k = m - 2;
-  double p[2] = {2.0 * ((x - 1) + 0.5) / k - 1.0, 2.0 * ((y - 1) + 0.5) / k - 1.0};
-  orc_oct_decode(p, v);
+  real p[2] = {(real)2.0 * ((x - 1) + (real)0.5) / k - 1, (real)2.0 * ((y - 1) + (real)0.5) / k - 1};
+  oct_decode_r(p, v);
+}
+
+void orc_texel_direction(int32_t m, int32_t x, int32_t y, double v[3]) {
+  real vr[3];
+  texel_direction_r(m, x, y, vr);
+  for (int a = 0; a < 3; a++) v[a] = vr[a];
 }
 
 /* The one-texel border repeats the cell across the octahedral seam: the
@@ -454,37 +506,47 @@ void orc_border_source(int32_t m, int32_t x, int32_t y, int32_t* sx, int32_t* sy
   }
 }
 
-void orc_sample_tile(const double* tile, int32_t m, int32_t nch, const double v[3], double* out) {
+static void sample_tile_r(const double* tile, int32_t m, int32_t nch, const real v[3], real* out) {
   int32_t k = m - 2;
-  double p[2];
-  orc_oct_encode(v, p);
-  double cx = 1.0 + (0.5 * p[0] + 0.5) * k - 0.5;
-  double cy = 1.0 + (0.5 * p[1] + 0.5) * k - 0.5;
+  real p[2];
+  oct_encode_r(v, p);
+  real cx = 1.0 + (0.5 * p[0] + 0.5) * k - 0.5;
+  real cy = 1.0 + (0.5 * p[1] + 0.5) * k - 0.5;
   int32_t x0 = (int32_t)floor(cx), y0 = (int32_t)floor(cy);
   if (x0 < 0) x0 = 0;
   if (x0 > k) x0 = k;
   if (y0 < 0) y0 = 0;
   if (y0 > k) y0 = k;
-  double fx = clampd(cx - x0, 0.0, 1.0), fy = clampd(cy - y0, 0.0, 1.0);
+  real fx = clampr(cx - x0, 0.0, 1.0), fy = clampr(cy - y0, 0.0, 1.0);
   for (int c = 0; c < nch; c++) {
-    double a = tile[(y0 * m + x0) * nch + c], b = tile[(y0 * m + x0 + 1) * nch + c];
-    double cc = tile[((y0 + 1) * m + x0) * nch + c], dd = tile[((y0 + 1) * m + x0 + 1) * nch + c];
+    real a = tile[(y0 * m + x0) * nch + c], b = tile[(y0 * m + x0 + 1) * nch + c];
+    real cc = tile[((y0 + 1) * m + x0) * nch + c], dd = tile[((y0 + 1) * m + x0 + 1) * nch + c];
     out[c] = (1 - fy) * ((1 - fx) * a + fx * b) + fy * ((1 - fx) * cc + fx * dd);
   }
+}
+
+void orc_sample_tile(const double* tile, int32_t m, int32_t nch, const double v[3], double* out) {
+  real vr[3], o[4];
+  load3r(v, vr);
+  sample_tile_r(tile, m, nch, vr, o);
+  for (int c = 0; c < nch; c++) out[c] = o[c];
 }
 
 /* -------------------------------------------------------------------- rays */
 /* Spherical Fibonacci point i of n (Keinert et al. 2015), rotated by the
    frame's random rotation (Section "Probe Update"). */
 void orc_sf_direction(int32_t i, int32_t n, const float R[9], double out[3]) {
-  const double phi = (1.0 + sqrt(5.0)) / 2.0;
-  double z = 1.0 - (2.0 * i + 1.0) / n;
-  double r = sqrt(fmax(0.0, 1.0 - z * z));
+  /* the fractional part of i * phi is taken in double in both builds: it
+     has to be exact (in float32 the product loses the fraction's low bits) */
+  const double phi = (1.0 + sqrt((double)5)) / 2.0;
   double f = (double)i * phi;
-  double a = 2.0 * M_PI * (f - floor(f));
-  double sf[3] = {r * cos(a), r * sin(a), z};
+  double frac = f - floor(f);
+  real z = 1.0 - (2.0 * i + 1.0) / n;
+  real r = sqrt(fmax((real)0.0, 1.0 - z * z));
+  real a = (real)2.0 * (real)M_PI * (real)frac;
+  real sf[3] = {r * cos(a), r * sin(a), z};
   for (int row = 0; row < 3; row++)
-    out[row] = (double)R[row * 3 + 0] * sf[0] + (double)R[row * 3 + 1] * sf[1] + (double)R[row * 3 + 2] * sf[2];
+    out[row] = (real)R[row * 3 + 0] * sf[0] + (real)R[row * 3 + 1] * sf[1] + (real)R[row * 3 + 2] * sf[2];
 }
 
 /* ------------------------------------------------------------------- blend */
@@ -509,9 +571,9 @@ void orc_blend_probe_ex(int32_t n, const double* omega, const double* rgb, const
    texel given the largest per-channel change between the new (encoded) value
    and the stored one: lowered by 0.15 (not below 0) above a change of 0.25,
    and 0 above 0.8 (the probe is taken to see a new distribution). */
-static double texel_hysteresis(double alpha, double change) {
-  double a = alpha;
-  if (change > 0.25) a = fmax(0.0, a - 0.15);
+static real texel_hysteresis(real alpha, real change) {
+  real a = alpha;
+  if (change > 0.25) a = fmax((real)0.0, a - (real)0.15);
   if (change > 0.8) a = 0.0;
   return a;
 }
@@ -521,45 +583,50 @@ void orc_blend_probe_k(int32_t n, const double* omega, const double* rgb, const 
                        int32_t thresholds, double* irr, double* dist, double* irr_k, double* dist_k) {
   for (int32_t y = 1; y <= 6; y++)
     for (int32_t x = 1; x <= 6; x++) {
-      double nt[3], W = 0, acc[3] = {0, 0, 0};
-      orc_texel_direction(8, x, y, nt);
+      real nt[3], W = 0, acc[3] = {0, 0, 0};
+      texel_direction_r(8, x, y, nt);
+      const double ntd[3] = {nt[0], nt[1], nt[2]};
       for (int32_t r = 0; r < n; r++) {
-        double w = fmax(0.0, dot3(nt, omega + 3 * r));
+        real om[3];
+        load3r(omega + 3 * r, om);
+        real w = fmax((real)0.0, dot3r(nt, om));
         W += w;
-        for (int c = 0; c < 3; c++) acc[c] += w * rgb[3 * r + c];
+        for (int c = 0; c < 3; c++) acc[c] += w * (real)rgb[3 * r + c];
       }
       if (!(W > 0.0)) continue;
       double* t = &irr[(y * 8 + x) * 3];
-      double nv[3], enc[3], kn[3], kenc[3];
+      real nv[3], enc[3];
+      double kn[3], kenc[3];
       for (int c = 0; c < 3; c++) {
         nv[c] = acc[c] / W;
         /* Section "Perception-based exponential encoding": the stored value
            is the new mean raised to 1/gamma; the hysteresis then blends in
            the encoded domain */
-        enc[c] = gamma != 1.0 ? pow(fmax(nv[c], 0.0), 1.0 / gamma) : nv[c];
+        enc[c] = gamma != 1.0 ? pow(fmax(nv[c], (real)0.0), (real)(1.0 / gamma)) : nv[c];
         if (irr_k) {
           double kw = 0.0, kr = 0.0;
           for (int32_t r = 0; r < n; r++) {
-            double cw = dot3(nt, omega + 3 * r);
+            double cw = dot3(ntd, omega + 3 * r);
             double w = fmax(0.0, cw);
             if (cw > -8.0 * U32) kw += fabs(rgb[3 * r + c] - nv[c]) * 8.0;
             if (rgb_kappa) kr += w * rgb_kappa[3 * r + c];
           }
-          kn[c] = kw / W + kr / W + 8.0 * fabs(nv[c]);
+          kn[c] = kw / W + kr / W + 8.0 * fabs((double)nv[c]);
           if (gamma != 1.0) {
             /* the encoded value's range over the linear value's error bound */
             double e = 8.0 * U32 * kn[c];
-            double hi = pow(fmax(nv[c], 0.0) + e, 1.0 / gamma), lo = pow(fmax(nv[c] - e, 0.0), 1.0 / gamma);
+            double hi = pow(fmax((double)nv[c], 0.0) + e, 1.0 / gamma), lo = pow(fmax(nv[c] - e, 0.0), 1.0 / gamma);
             kenc[c] = fmax(hi - enc[c], enc[c] - lo) / (8.0 * U32) + 8.0 * enc[c];
           } else {
             kenc[c] = kn[c];
           }
         }
       }
-      double a = alpha_irr, flip = 0.0;
+      real a = alpha_irr;
+      double flip = 0.0;
       if (thresholds) {
-        double change = 0.0;
-        for (int c = 0; c < 3; c++) change = fmax(change, fabs(enc[c] - t[c]));
+        real change = 0.0;
+        for (int c = 0; c < 3; c++) change = fmax(change, fabs(enc[c] - (real)t[c]));
         a = texel_hysteresis(alpha_irr, change);
         if (irr_k) {
           /* a float32 evaluation may see the change on the other side of a
@@ -576,26 +643,31 @@ void orc_blend_probe_k(int32_t n, const double* omega, const double* rgb, const 
           double* kt = &irr_k[(y * 8 + x) * 3 + c];
           *kt = a * (*kt) + (1.0 - a) * kenc[c] + 4.0 * fabs(t[c]) + flip * fabs(t[c] - enc[c]) / (8.0 * U32);
         }
-        t[c] = a * t[c] + (1.0 - a) * enc[c];
+        real tc = t[c];
+        t[c] = a * tc + (1 - a) * enc[c];
       }
     }
   for (int32_t y = 1; y <= 14; y++)
     for (int32_t x = 1; x <= 14; x++) {
-      double nt[3], W = 0, m1 = 0, m2 = 0;
-      orc_texel_direction(16, x, y, nt);
+      real nt[3], W = 0, m1 = 0, m2 = 0;
+      texel_direction_r(16, x, y, nt);
+      const double ntd[3] = {nt[0], nt[1], nt[2]};
       for (int32_t r = 0; r < n; r++) {
-        double w = pow(fmax(0.0, dot3(nt, omega + 3 * r)), cos_power);
+        real om[3];
+        load3r(omega + 3 * r, om);
+        real w = pow(fmax((real)0.0, dot3r(nt, om)), (real)cos_power);
+        real dr = d[r];
         W += w;
-        m1 += w * d[r];
-        m2 += w * d[r] * d[r];
+        m1 += w * dr;
+        m2 += w * dr * dr;
       }
       if (W > 0.0) {
         double* t = &dist[(y * 16 + x) * 2];
-        double n1 = m1 / W, n2 = m2 / W;
+        real n1 = m1 / W, n2 = m2 / W;
         if (dist_k) {
           double k1 = 0.0, k2 = 0.0;
           for (int32_t r = 0; r < n; r++) {
-            double cw = dot3(nt, omega + 3 * r);
+            double cw = dot3(ntd, omega + 3 * r);
             if (cw <= -8.0 * U32) continue;
             /* |dw/dc| * 8u with w = c^p */
             double dw = cos_power * pow(fmax(cw, 8.0 * U32), cos_power - 1.0) * 8.0;
@@ -609,11 +681,12 @@ void orc_blend_probe_k(int32_t n, const double* omega, const double* rgb, const 
             }
           }
           double* kt = &dist_k[(y * 16 + x) * 2];
-          kt[0] = alpha_dist * kt[0] + (1.0 - alpha_dist) * (k1 / W + 8.0 * fabs(n1)) + 4.0 * fabs(t[0]);
-          kt[1] = alpha_dist * kt[1] + (1.0 - alpha_dist) * (k2 / W + 8.0 * fabs(n2)) + 4.0 * fabs(t[1]);
+          kt[0] = alpha_dist * kt[0] + (1.0 - alpha_dist) * (k1 / W + 8.0 * fabs((double)n1)) + 4.0 * fabs(t[0]);
+          kt[1] = alpha_dist * kt[1] + (1.0 - alpha_dist) * (k2 / W + 8.0 * fabs((double)n2)) + 4.0 * fabs(t[1]);
         }
-        t[0] = alpha_dist * t[0] + (1.0 - alpha_dist) * n1;
-        t[1] = alpha_dist * t[1] + (1.0 - alpha_dist) * n2;
+        real ad = alpha_dist, t0 = t[0], t1 = t[1];
+        t[0] = ad * t0 + (1 - ad) * n1;
+        t[1] = ad * t1 + (1 - ad) * n2;
       }
     }
   for (int32_t y = 0; y < 8; y++)
@@ -677,29 +750,35 @@ static int64_t storage_index(const orc_volume* V, int64_t i, int64_t j, int64_t 
          (int64_t)V->counts[0] * (wrap(j + V->phase[1], V->counts[1]) + (int64_t)V->counts[1] * wrap(k + V->phase[2], V->counts[2]));
 }
 
-static void probe_position(const orc_volume* V, int64_t q, double P[3]) {
+static void probe_position_r(const orc_volume* V, int64_t q, real P[3]) {
   int64_t g[3];
   logical_index(V, q, g);
   for (int a = 0; a < 3; a++) {
-    P[a] = (double)V->origin[a] + (double)g[a] * (double)V->spacing[a];
-    if (V->offsets) P[a] += (double)V->offsets[q * 3 + a];
+    P[a] = (real)V->origin[a] + (real)g[a] * (real)V->spacing[a];
+    if (V->offsets) P[a] += (real)V->offsets[q * 3 + a];
   }
+}
+
+static void probe_position(const orc_volume* V, int64_t q, double P[3]) {
+  real Pr[3];
+  probe_position_r(V, q, Pr);
+  for (int a = 0; a < 3; a++) P[a] = Pr[a];
 }
 
 /* Section "Multiple Probe Volumes": a volume's weight falls linearly from 1
    to 0 over its last grid cell along each axis (product over axes).  For a
    volume that tracks the camera the transition region is tightened by one
    cell and centred on the camera. */
-static double volume_weight(const orc_volume* V, const double X[3]) {
-  double wv = 1.0;
+static real volume_weight(const orc_volume* V, const real X[3]) {
+  real wv = 1.0;
   for (int a = 0; a < 3; a++) {
-    double sp = (double)V->spacing[a];
+    real sp = V->spacing[a];
     if (V->tracking) {
-      double h = 0.5 * (double)(V->counts[a] - 1) - 1.0;
-      wv *= clampd(h - fabs(X[a] - (double)V->camera[a]) / sp, 0.0, 1.0);
+      real h = (real)0.5 * (real)(V->counts[a] - 1) - 1;
+      wv *= clampr(h - fabs(X[a] - (real)V->camera[a]) / sp, 0.0, 1.0);
     } else {
-      double u = (X[a] - (double)V->origin[a]) / sp;
-      wv *= clampd(fmin(u, (double)(V->counts[a] - 1) - u), 0.0, 1.0);
+      real u = (X[a] - (real)V->origin[a]) / sp;
+      wv *= clampr(fmin(u, (real)(V->counts[a] - 1) - u), 0.0, 1.0);
     }
   }
   return wv;
@@ -713,62 +792,64 @@ static int sampled_state(uint8_t s) { return s == ORC_AWAKE || s == ORC_VIGILANT
    self-shadow bias of Eq. 1.  Result: normalised weighted sum of the
    irradiance texels sampled in direction n.  kap receives the absolute
    sensitivity of the result to float32 rounding (units of 2^-24). */
-static void volume_query(const orc_volume* V, int64_t base, const double X[3], const double n[3],
-                         const double wo[3], const double look[3], double out[3], double kap[3], int32_t* cage,
+static void volume_query(const orc_volume* V, int64_t base, const real X[3], const real n[3],
+                         const real wo[3], const real look[3], real out[3], double kap[3], int32_t* cage,
                          int32_t* ncage) {
-  double u[3], f[3];
+  real u[3], f[3];
   int64_t g[3];
-  double D = fmin((double)V->spacing[0], fmin((double)V->spacing[1], (double)V->spacing[2]));
-  double Xb[3];
+  real D = fmin((real)V->spacing[0], fmin((real)V->spacing[1], (real)V->spacing[2]));
+  real Xb[3];
   for (int a = 0; a < 3; a++) {
-    u[a] = (X[a] - (double)V->origin[a]) / (double)V->spacing[a];
-    double fl = floor(u[a]);
-    g[a] = (int64_t)clampd(fl, 0.0, (double)(V->counts[a] - 2));
-    f[a] = clampd(u[a] - (double)g[a], 0.0, 1.0);
-    Xb[a] = X[a] + (0.2 * n[a] + 0.8 * wo[a]) * (0.75 * D) * (double)V->bias;
+    u[a] = (X[a] - (real)V->origin[a]) / (real)V->spacing[a];
+    real fl = floor(u[a]);
+    g[a] = (int64_t)clampr(fl, 0.0, (real)(V->counts[a] - 2));
+    f[a] = clampr(u[a] - (real)g[a], 0.0, 1.0);
+    Xb[a] = X[a] + ((real)0.2 * n[a] + (real)0.8 * wo[a]) * ((real)0.75 * D) * (real)V->bias;
   }
-  double w[8], e[8][3], ek[8][3], sens[8];
+  real w[8], e[8][3], W = 0;
+  double ek[8][3], sens[8];
   int32_t ids[8];
-  double W = 0;
   int used = 0;
   for (int c = 0; c < 8; c++) {
     int cb[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
     int64_t q = storage_index(V, g[0] + cb[0], g[1] + cb[1], g[2] + cb[2]);
     if (!sampled_state(V->states[q])) continue;
-    double wt = 1.0;
-    for (int a = 0; a < 3; a++) wt *= cb[a] ? f[a] : 1.0 - f[a];
-    double P[3], toP[3];
-    probe_position(V, q, P);
-    sub3(P, X, toP);
-    normalize3(toP);
-    double h = (1.0 + dot3(n, toP)) * 0.5;
-    double wb = h * h + 0.2;
-    double z[3];
-    sub3(Xb, P, z);
-    double r = len3(z);
-    double wv = 1.0, s = 8.0;
+    real wt = 1.0;
+    for (int a = 0; a < 3; a++) wt *= cb[a] ? f[a] : 1 - f[a];
+    real P[3], toP[3];
+    probe_position_r(V, q, P);
+    sub3r(P, X, toP);
+    normalize3r(toP);
+    real h = (1 + dot3r(n, toP)) * (real)0.5;
+    real wb = h * h + (real)0.2;
+    real z[3];
+    sub3r(Xb, P, z);
+    real r = len3r(z);
+    real wv = 1.0;
+    double s = 8.0;
     if (r > 0.0) {
-      double zd[3] = {z[0] / r, z[1] / r, z[2] / r}, mm[2], lo[2], hi[2];
-      orc_sample_tile(V->dist + q * 16 * 16 * 2, 16, 2, zd, mm);
+      real zd[3] = {z[0] / r, z[1] / r, z[2] / r}, mm[2];
+      sample_tile_r(V->dist + q * 16 * 16 * 2, 16, 2, zd, mm);
       if (r > mm[0]) {
-        footprint_range(V->dist + q * 16 * 16 * 2, 16, 2, zd, lo, hi);
-        double var = fmax(mm[1] - mm[0] * mm[0], 0.0);
-        double dl = r - mm[0];
-        double ch = var / (var + dl * dl);
-        wv = pow(ch, (double)V->cheb_power);
+        real var = fmax(mm[1] - mm[0] * mm[0], (real)0.0);
+        real dl = r - mm[0];
+        real ch = var / (var + dl * dl);
+        wv = pow(ch, (real)V->cheb_power);
         /* relative float32 sensitivity of the Chebyshev weight (units of u):
            the bilinear position (k * few u of a texel) and the rounding of
            mu, mu2 and r enter through the cancellations mu2 - mu^2, r - mu */
-        double dmu = 4.0 * fabs(mm[0]) + 32.0 * (hi[0] - lo[0]);
-        double dmu2 = 4.0 * fabs(mm[1]) + 32.0 * (hi[1] - lo[1]);
+        double zdd[3] = {zd[0], zd[1], zd[2]}, lo[2], hi[2];
+        footprint_range(V->dist + q * 16 * 16 * 2, 16, 2, zdd, lo, hi);
+        double dmu = 4.0 * fabs((double)mm[0]) + 32.0 * (hi[0] - lo[0]);
+        double dmu2 = 4.0 * fabs((double)mm[1]) + 32.0 * (hi[1] - lo[1]);
         if (V->dist_kappa) {
           /* the float32 atlas itself differs by its texels' sensitivity */
           double kk[2];
-          orc_sample_tile(V->dist_kappa + q * 16 * 16 * 2, 16, 2, zd, kk);
+          orc_sample_tile(V->dist_kappa + q * 16 * 16 * 2, 16, 2, zdd, kk);
           dmu += kk[0];
           dmu2 += kk[1];
         }
-        double dvar = dmu2 + 2.0 * fabs(mm[0]) * dmu + 4.0 * (fabs(mm[1]) + mm[0] * mm[0]);
+        double dvar = dmu2 + 2.0 * fabs((double)mm[0]) * dmu + 4.0 * (fabs((double)mm[1]) + (double)mm[0] * mm[0]);
         double ddl = 4.0 * r + dmu;
         if (var > 0.0)
           s += V->cheb_power * (1.0 - ch) * (dvar / var + 2.0 * ddl / dl);
@@ -779,19 +860,23 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
     ids[used] = (int32_t)(base + q);
     w[used] = wt * wb * wv;
     sens[used] = s;
-    orc_sample_tile(V->irr + q * 8 * 8 * 3, 8, 3, look, e[used]);
-    if (V->irr_kappa) orc_sample_tile(V->irr_kappa + q * 8 * 8 * 3, 8, 3, look, ek[used]);
-    else ek[used][0] = ek[used][1] = ek[used][2] = 0.0;
+    sample_tile_r(V->irr + q * 8 * 8 * 3, 8, 3, look, e[used]);
+    if (V->irr_kappa) {
+      double lk[3] = {look[0], look[1], look[2]};
+      orc_sample_tile(V->irr_kappa + q * 8 * 8 * 3, 8, 3, lk, ek[used]);
+    } else {
+      ek[used][0] = ek[used][1] = ek[used][2] = 0.0;
+    }
     if (V->gamma != 1.0f) {
       /* Section "Perception-based exponential encoding": each probe's sample
          is decoded to the power gamma/2, so the cage blend runs on a
          gamma-2 curve; the normalised result is squared back below */
-      double h = 0.5 * (double)V->gamma;
+      real h2 = (real)0.5 * (real)V->gamma;
       for (int k = 0; k < 3; k++) {
-        double ev = fmax(e[used][k], 0.0);
-        double dec = pow(ev, h);
-        double ee = (16.0 * fabs(e[used][k]) + ek[used][k]) * U32;
-        double hi = pow(ev + ee, h), lo = pow(fmax(ev - ee, 0.0), h);
+        real ev = fmax(e[used][k], (real)0.0);
+        real dec = pow(ev, h2);
+        double ee = (16.0 * fabs((double)e[used][k]) + ek[used][k]) * U32;
+        double hi = pow((double)ev + ee, (double)h2), lo = pow(fmax((double)ev - ee, 0.0), (double)h2);
         ek[used][k] = fmax(hi - dec, dec - lo) / U32;
         e[used][k] = dec;
       }
@@ -805,7 +890,8 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
   if (!(W > 0.0)) {
     /* no visible probe: float32 may find tiny positive weights */
     for (int i = 0; i < used; i++)
-      for (int c = 0; c < 3; c++) kap[c] = fmax(kap[c], (sq ? e[i][c] * e[i][c] : fabs(e[i][c])) / U32);
+      for (int c = 0; c < 3; c++)
+        kap[c] = fmax(kap[c], (sq ? (double)e[i][c] * e[i][c] : fabs((double)e[i][c])) / U32);
     return;
   }
   for (int i = 0; i < used; i++)
@@ -821,17 +907,17 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
     if (w[i] > 0.0 && !(sens[i] * U32 >= 1.0)) all_fragile = 0;
   for (int i = 0; i < used; i++) {
     for (int c = 0; c < 3; c++) {
-      double dv = fabs(e[i][c] - out[c]);
-      double term = isinf(sens[i]) ? (dv > 0 ? dv / U32 : 0.0) : (w[i] / W) * dv * sens[i];
-      kap[c] += term + (w[i] / W) * (16.0 * fabs(e[i][c]) + ek[i][c]);
+      double dv = fabs((double)e[i][c] - (double)out[c]);
+      double term = isinf(sens[i]) ? (dv > 0 ? dv / U32 : 0.0) : ((double)w[i] / W) * dv * sens[i];
+      kap[c] += term + ((double)w[i] / W) * (16.0 * fabs((double)e[i][c]) + ek[i][c]);
     }
     if (w[i] > 0.0 && cage && ncage && *ncage < 8) cage[(*ncage)++] = ids[i];
   }
   if (all_fragile)
-    for (int c = 0; c < 3; c++) kap[c] += fabs(out[c]) / U32;
+    for (int c = 0; c < 3; c++) kap[c] += fabs((double)out[c]) / U32;
   if (sq)
     for (int c = 0; c < 3; c++) {
-      kap[c] = 2.0 * fabs(out[c]) * kap[c] + 8.0 * out[c] * out[c];
+      kap[c] = 2.0 * fabs((double)out[c]) * kap[c] + 8.0 * (double)out[c] * out[c];
       out[c] = out[c] * out[c];
     }
 }
@@ -839,7 +925,37 @@ static void volume_query(const orc_volume* V, int64_t base, const double X[3], c
 /* Section "Multiple Probe Volumes": volumes are visited from most to least
    dense; a volume's weight falls linearly from 1 to 0 across its last grid
    cell on every axis (product over axes); weights accumulate until they
-   reach 1; the sparsest volume takes whatever weight remains. */
+   reach 1; the sparsest volume takes whatever weight remains.  `look`: the
+   direction the probes' texels are sampled in (the normal for irradiance;
+   see orc_query_look). */
+static void query_look_r(const orc_volume* vols, int32_t nvol, const real X[3], const real n[3], const real wo[3],
+                         const real look[3], real out[3], double kappa[3], int32_t* cage, int32_t* n_cage) {
+  real Wt = 0.0;
+  int64_t base = 0;
+  for (int c = 0; c < 3; c++) { out[c] = 0.0; kappa[c] = 0.0; }
+  if (n_cage) *n_cage = 0;
+  for (int32_t v = 0; v < nvol; v++) {
+    const orc_volume* V = &vols[v];
+    if (Wt >= 1.0) break;
+    real wv = volume_weight(V, X);
+    real wuse = (v == nvol - 1) ? 1 - Wt : fmin(wv, 1 - Wt);
+    if (wuse > 0.0) {
+      real ev[3];
+      double kv[3];
+      int32_t cg[8], nc = 0;
+      volume_query(V, base, X, n, wo, look, ev, kv, cg, &nc);
+      for (int c = 0; c < 3; c++) {
+        out[c] += wuse * ev[c];
+        kappa[c] += wuse * kv[c] + 4.0 * fabs((double)(wuse * ev[c]));
+      }
+      if (cage && n_cage)
+        for (int i = 0; i < nc && *n_cage < ORC_CAGE; i++) cage[(*n_cage)++] = cg[i];
+      Wt += wuse;
+    }
+    base += vol_probes(V);
+  }
+}
+
 void orc_query(const orc_volume* vols, int32_t nvol, const double X[3], const double n[3],
                const double wo[3], double out[3], double kappa[3], int32_t* cage, int32_t* n_cage) {
   orc_query_look(vols, nvol, X, n, wo, n, out, kappa, cage, n_cage);
@@ -851,29 +967,13 @@ void orc_query(const orc_volume* vols, int32_t nvol, const double X[3], const do
 void orc_query_look(const orc_volume* vols, int32_t nvol, const double X[3], const double n[3],
                     const double wo[3], const double look[3], double out[3], double kappa[3], int32_t* cage,
                     int32_t* n_cage) {
-  double Wt = 0.0;
-  int64_t base = 0;
-  for (int c = 0; c < 3; c++) { out[c] = 0.0; kappa[c] = 0.0; }
-  if (n_cage) *n_cage = 0;
-  for (int32_t v = 0; v < nvol; v++) {
-    const orc_volume* V = &vols[v];
-    if (Wt >= 1.0) break;
-    double wv = volume_weight(V, X);
-    double wuse = (v == nvol - 1) ? 1.0 - Wt : fmin(wv, 1.0 - Wt);
-    if (wuse > 0.0) {
-      double ev[3], kv[3];
-      int32_t cg[8], nc = 0;
-      volume_query(V, base, X, n, wo, look, ev, kv, cg, &nc);
-      for (int c = 0; c < 3; c++) {
-        out[c] += wuse * ev[c];
-        kappa[c] += wuse * kv[c] + 4.0 * fabs(wuse * ev[c]);
-      }
-      if (cage && n_cage)
-        for (int i = 0; i < nc && *n_cage < ORC_CAGE; i++) cage[(*n_cage)++] = cg[i];
-      Wt += wuse;
-    }
-    base += vol_probes(V);
-  }
+  real Xr[3], nr[3], wr[3], lr[3], o[3];
+  load3r(X, Xr);
+  load3r(n, nr);
+  load3r(wo, wr);
+  load3r(look, lr);
+  query_look_r(vols, nvol, Xr, nr, wr, lr, o, kappa, cage, n_cage);
+  for (int c = 0; c < 3; c++) out[c] = o[c];
 }
 
 void orc_query_batch(const orc_volume* vols, int32_t nvol, int64_t nq, const float* pos,
@@ -892,59 +992,75 @@ void orc_query_batch(const orc_volume* vols, int32_t nvol, int64_t nq, const flo
    -w, given which shadow rays are unblocked (bit l of vis): emission plus
    albedo x (direct irradiance / pi + previous-frame probe irradiance). */
 static void front_radiance(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol, int32_t m,
-                           const double X[3], const double ng[3], const double w[3], uint32_t vis, double rgb[3],
+                           const real X[3], const real ng[3], const real w[3], uint32_t vis, real rgb[3],
                            double kq[3], int32_t* cage, int32_t* n_cage) {
-  double direct[3] = {0, 0, 0};
-  double xmax = fmax(fabs(X[0]), fmax(fabs(X[1]), fabs(X[2])));
-  double eps = 1e-4 * fmax(1.0, xmax);
-  double Xs[3] = {X[0] + eps * ng[0], X[1] + eps * ng[1], X[2] + eps * ng[2]};
+  real direct[3] = {0, 0, 0};
+  real xmax = fmax(fabs(X[0]), fmax(fabs(X[1]), fabs(X[2])));
+  real eps = (real)1e-4 * fmax((real)1.0, xmax);
+  real Xs[3] = {X[0] + eps * ng[0], X[1] + eps * ng[1], X[2] + eps * ng[2]};
   int32_t li = 0;
   for (int32_t l = 0; l < L->n_dir; l++, li++) {
     if (!(vis >> li & 1u)) continue;
-    double dl[3] = {L->dir_to_light[3 * l], L->dir_to_light[3 * l + 1], L->dir_to_light[3 * l + 2]};
-    double c = dot3(ng, dl);
-    for (int k = 0; k < 3; k++) direct[k] += (double)L->dir_irradiance[3 * l + k] * c;
+    real dl[3] = {L->dir_to_light[3 * l], L->dir_to_light[3 * l + 1], L->dir_to_light[3 * l + 2]};
+    real c = dot3r(ng, dl);
+    for (int k = 0; k < 3; k++) direct[k] += (real)L->dir_irradiance[3 * l + k] * c;
   }
   for (int32_t l = 0; l < L->n_point; l++, li++) {
     if (!(vis >> li & 1u)) continue;
-    double u[3] = {L->point_pos[3 * l] - Xs[0], L->point_pos[3 * l + 1] - Xs[1], L->point_pos[3 * l + 2] - Xs[2]};
-    double dist = len3(u);
-    double c = dot3(ng, u) / dist;
-    for (int k = 0; k < 3; k++) direct[k] += (double)L->point_intensity[3 * l + k] * c / (dist * dist);
+    real u[3] = {L->point_pos[3 * l] - Xs[0], L->point_pos[3 * l + 1] - Xs[1], L->point_pos[3 * l + 2] - Xs[2]};
+    real dist = len3r(u);
+    real c = dot3r(ng, u) / dist;
+    for (int k = 0; k < 3; k++) direct[k] += (real)L->point_intensity[3 * l + k] * c / (dist * dist);
   }
-  double wo[3] = {-w[0], -w[1], -w[2]}, ind[3] = {0, 0, 0};
+  real wo[3] = {-w[0], -w[1], -w[2]}, ind[3] = {0, 0, 0};
   for (int k = 0; k < 3; k++) kq[k] = 0.0;
-  if (nvol > 0) orc_query(vols, nvol, X, ng, wo, ind, kq, cage, n_cage);
-  for (int k = 0; k < 3; k++) rgb[k] = s->emission[m * 3 + k] + s->albedo[m * 3 + k] * (direct[k] / M_PI + ind[k]);
+  if (nvol > 0) query_look_r(vols, nvol, X, ng, wo, ng, ind, kq, cage, n_cage);
+  for (int k = 0; k < 3; k++)
+    rgb[k] = (real)s->emission[m * 3 + k] + (real)s->albedo[m * 3 + k] * (direct[k] / (real)M_PI + ind[k]);
 }
 
 /* Shadow rays of a front-face hit X (geometric normal ng) toward every
    light on its front side, from the hit lifted off the surface; any
    triangle, either side, occludes.  Sets bit l of vis for an unblocked light
    and ORC_F_SHADOW in flags for an ambiguous shadow ray. */
-static void hit_visibility(const orc_scene* s, const orc_lights* L, const double X[3], const double ng[3],
+static void hit_visibility(const orc_scene* s, const orc_lights* L, const real X[3], const real ng[3],
                            uint32_t* vis, int32_t* flags) {
-  double xmax = fmax(fabs(X[0]), fmax(fabs(X[1]), fabs(X[2])));
-  double eps = 1e-4 * fmax(1.0, xmax);
-  double Xs[3] = {X[0] + eps * ng[0], X[1] + eps * ng[1], X[2] + eps * ng[2]};
+  real xmax = fmax(fabs(X[0]), fmax(fabs(X[1]), fabs(X[2])));
+  real eps = (real)1e-4 * fmax((real)1.0, xmax);
+  real Xs[3] = {X[0] + eps * ng[0], X[1] + eps * ng[1], X[2] + eps * ng[2]};
+  double Xsd[3] = {Xs[0], Xs[1], Xs[2]};
   int32_t li = 0;
   for (int32_t l = 0; l < L->n_dir; l++, li++) {
-    double dl[3] = {L->dir_to_light[3 * l], L->dir_to_light[3 * l + 1], L->dir_to_light[3 * l + 2]};
-    if (dot3(ng, dl) <= 0.0) continue;
+    real dl[3] = {L->dir_to_light[3 * l], L->dir_to_light[3 * l + 1], L->dir_to_light[3 * l + 2]};
+    if (dot3r(ng, dl) <= 0.0) continue;
+    double dld[3] = {dl[0], dl[1], dl[2]};
     int amb = 0;
-    if (!occluded(s, Xs, dl, INFINITY, &amb)) *vis |= 1u << li;
+    if (!occluded(s, Xsd, dld, INFINITY, &amb)) *vis |= 1u << li;
     if (amb) *flags |= ORC_F_SHADOW;
   }
   for (int32_t l = 0; l < L->n_point; l++, li++) {
-    double u[3] = {L->point_pos[3 * l] - Xs[0], L->point_pos[3 * l + 1] - Xs[1], L->point_pos[3 * l + 2] - Xs[2]};
-    double dist = len3(u);
+    real u[3] = {L->point_pos[3 * l] - Xs[0], L->point_pos[3 * l + 1] - Xs[1], L->point_pos[3 * l + 2] - Xs[2]};
+    real dist = len3r(u);
     if (!(dist > 0.0)) continue;
-    double uh[3] = {u[0] / dist, u[1] / dist, u[2] / dist};
-    if (dot3(ng, uh) <= 0.0) continue;
+    real uh[3] = {u[0] / dist, u[1] / dist, u[2] / dist};
+    if (dot3r(ng, uh) <= 0.0) continue;
+    double uhd[3] = {uh[0], uh[1], uh[2]};
     int amb = 0;
-    if (!occluded(s, Xs, uh, dist * (1.0 - 1e-6), &amb)) *vis |= 1u << li;
+    if (!occluded(s, Xsd, uhd, dist * (1.0 - 1e-6), &amb)) *vis |= 1u << li;
     if (amb) *flags |= ORC_F_SHADOW;
   }
+}
+
+/* geometric normal of triangle t (counter-clockwise front face) */
+static void tri_normal_r(const orc_scene* s, int32_t t, real ng[3]) {
+  real v0[3], v1[3], v2[3], e1[3], e2[3];
+  load3r(tri_v(s, t, 0), v0);
+  load3r(tri_v(s, t, 1), v1);
+  load3r(tri_v(s, t, 2), v2);
+  sub3r(v1, v0, e1);
+  sub3r(v2, v0, e2);
+  cross3r(e1, e2, ng);
+  normalize3r(ng);
 }
 
 /* Section "Probe Update" (hit shading) and the backface rule of the
@@ -952,12 +1068,56 @@ static void hit_visibility(const orc_scene* s, const orc_lights* L, const double
    backface records radiance 0 and 20 % of its distance; a front face is
    shaded Lambertian with shadowed direct light, its emission and the
    previous frame's probe irradiance at the hit. */
-void orc_shade_ray(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol,
-                   const double o[3], const double w[3], double dmax, orc_ray_record* rec) {
+/* float32 sensitivity (units of u) of a ray's recorded distance: the hit
+   distance's error along the ray, t (8 / |cos| + 16) from the direction and
+   the arithmetic plus 32 |o| / |cos| from the rounding of the origin's
+   coordinates (|o| its largest), scaled by 0.2 for a backface, unless the
+   distance sits at the clamp beyond that error */
+static double ray_distance_kappa(const orc_ray_record* rr, double dmax, double omag) {
+  if (rr->tri < 0) return 0.0;
+  double c = fmax(rr->cosi, 1e-6);
+  double terr = rr->t * (8.0 / c + 16.0) + 32.0 * omag / c;
+  int back = rr->d == fmin(0.2 * rr->t, dmax) && 0.2 * rr->t < rr->t && rr->d < rr->t;
+  double tt = back ? 0.2 * rr->t : rr->t, err = back ? 0.2 * terr : terr;
+  return tt <= dmax * (1.0 + 4.0 * U32) + err * U32 ? err : 0.0;
+}
+
+static void shade_ray_body(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol,
+                           const double o[3], const double w[3], double dmax, uint8_t force, int32_t force_tri,
+                           uint32_t force_vis, orc_ray_record* rec);
+
+static void shade_ray_impl(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol,
+                           const double o[3], const double w[3], double dmax, uint8_t force, int32_t force_tri,
+                           uint32_t force_vis, orc_ray_record* rec) {
+  shade_ray_body(s, L, vols, nvol, o, w, dmax, force, force_tri, force_vis, rec);
+  rec->d_kappa = ray_distance_kappa(rec, dmax, fmax(fabs(o[0]), fmax(fabs(o[1]), fabs(o[2]))));
+}
+
+static void shade_ray_body(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol,
+                           const double o[3], const double w[3], double dmax, uint8_t force, int32_t force_tri,
+                           uint32_t force_vis, orc_ray_record* rec) {
   orc_hit h;
   orc_trace(s, o, w, 0, &h);
   memset(rec, 0, sizeof(*rec));
   for (int i = 0; i < ORC_CAGE; i++) rec->cage[i] = -1;
+  if (force & 1) {
+    /* the hit is given (another tracer's decision on a ray this oracle
+       flags): a miss, or triangle force_tri at the exact distance of its
+       plane along the ray */
+    h.flags |= ORC_F_FORCED;
+    if (force_tri < 0 || force_tri >= s->nt) {
+      h.tri = -1;
+      h.t = INFINITY;
+    } else if (force_tri != h.tri) {
+      double t, bmin;
+      if (plane_hit(s, force_tri, o, w, &t, &bmin) && t > 0.0) {
+        h.tri = force_tri;
+        h.t = t;
+      } else {
+        h.flags |= ORC_F_FORCE_INVALID;
+      }
+    }
+  }
   rec->tri = h.tri;
   rec->t = h.t;
   rec->flags = h.flags;
@@ -966,32 +1126,77 @@ void orc_shade_ray(const orc_scene* s, const orc_lights* L, const orc_volume* vo
     rec->d = dmax;
     return;
   }
-  double e1[3], e2[3], ng[3];
-  sub3(tri_v(s, h.tri, 1), tri_v(s, h.tri, 0), e1);
-  sub3(tri_v(s, h.tri, 2), tri_v(s, h.tri, 0), e2);
-  cross3(e1, e2, ng);
-  normalize3(ng);
-  rec->cosi = fabs(dot3(w, ng)) / len3(w);
-  if (dot3(w, ng) > 0.0) {
-    rec->d = fmin(0.2 * h.t, dmax);
+  real ng[3], wr[3], orr[3];
+  tri_normal_r(s, h.tri, ng);
+  load3r(w, wr);
+  load3r(o, orr);
+  double ngd[3] = {ng[0], ng[1], ng[2]};
+  rec->cosi = fabs(dot3(w, ngd)) / len3(w);
+  real t = h.t;
+  if (dot3r(wr, ng) > 0.0) {
+    rec->d = fmin((real)0.2 * t, (real)dmax);
     return;
   }
-  rec->d = fmin(h.t, dmax);
-  double X[3];
-  for (int a = 0; a < 3; a++) X[a] = o[a] + h.t * w[a];
+  rec->d = fmin(t, (real)dmax);
+  real X[3];
+  for (int a = 0; a < 3; a++) X[a] = orr[a] + t * wr[a];
   int32_t m = s->material[h.tri];
   hit_visibility(s, L, X, ng, &rec->vis, &rec->flags);
+  if (force & 2) {
+    rec->vis = force_vis;
+    rec->flags |= ORC_F_FORCED;
+  }
   double kq[3];
-  front_radiance(s, L, vols, nvol, m, X, ng, w, rec->vis, rec->rgb, kq, rec->cage, &rec->n_cage);
-  /* float32 sensitivity: the query's own, rounding of the sum, and the
-     hit point's float32 error along the ray (about t u / |cos|), measured
-     by a finite difference of the shading at that scale */
+  real rgb[3];
+  front_radiance(s, L, vols, nvol, m, X, ng, wr, rec->vis, rgb, kq, rec->cage, &rec->n_cage);
+  for (int k = 0; k < 3; k++) rec->rgb[k] = rgb[k];
+  /* float32 sensitivity: the query's own, rounding of the sum, and, by
+     finite differences of the shading at the scale of each error, (i) the
+     hit distance's error along the ray (about t u / |cos|), (ii) the
+     rounding of the hit point's coordinates (about 2 u of the largest
+     coordinate, per axis) and (iii) the direction error of a float32
+     normal (about 4 u (1 + |e1| |e2| / |e1 x e2|), along two tangents) */
   double ep = fmin(1e-2, U32 * (8.0 / fmax(rec->cosi, 1e-6) + 16.0));
-  double X2[3], rgb2[3], kq2[3];
-  for (int a = 0; a < 3; a++) X2[a] = o[a] + h.t * (1.0 + ep) * w[a];
-  front_radiance(s, L, vols, nvol, m, X2, ng, w, rec->vis, rgb2, kq2, NULL, NULL);
-  for (int k = 0; k < 3; k++)
-    rec->kappa[k] = s->albedo[m * 3 + k] * kq[k] + 8.0 * fabs(rec->rgb[k]) + fabs(rgb2[k] - rec->rgb[k]) / U32;
+  real X2[3], rgb2[3];
+  double kq2[3], fd[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < 3; a++) X2[a] = orr[a] + t * (real)(1.0 + ep) * wr[a];
+  front_radiance(s, L, vols, nvol, m, X2, ng, wr, rec->vis, rgb2, kq2, NULL, NULL);
+  for (int k = 0; k < 3; k++) fd[k] += fabs((double)rgb2[k] - rec->rgb[k]);
+  double xmag = 0.0;
+  for (int a = 0; a < 3; a++) xmag = fmax(xmag, fmax(fabs((double)X[a]), fabs(o[a])));
+  for (int a = 0; a < 3; a++) {
+    for (int b = 0; b < 3; b++) X2[b] = X[b];
+    X2[a] += (real)(2.0 * U32 * xmag);
+    front_radiance(s, L, vols, nvol, m, X2, ng, wr, rec->vis, rgb2, kq2, NULL, NULL);
+    for (int k = 0; k < 3; k++) fd[k] += fabs((double)rgb2[k] - rec->rgb[k]);
+  }
+  {
+    double e1[3], e2[3], c[3], tg[2][3];
+    sub3(tri_v(s, h.tri, 1), tri_v(s, h.tri, 0), e1);
+    sub3(tri_v(s, h.tri, 2), tri_v(s, h.tri, 0), e2);
+    cross3(e1, e2, c);
+    double en = 4.0 * U32 * (1.0 + len3(e1) * len3(e2) / fmax(len3(c), 1e-30));
+    /* two unit tangents of the normal */
+    int ax = fabs(ngd[0]) < fabs(ngd[1]) ? (fabs(ngd[0]) < fabs(ngd[2]) ? 0 : 2) : (fabs(ngd[1]) < fabs(ngd[2]) ? 1 : 2);
+    double ea[3] = {0.0, 0.0, 0.0};
+    ea[ax] = 1.0;
+    cross3(ngd, ea, tg[0]);
+    normalize3(tg[0]);
+    cross3(ngd, tg[0], tg[1]);
+    for (int j = 0; j < 2; j++) {
+      real n2[3];
+      for (int b = 0; b < 3; b++) n2[b] = (real)(ngd[b] + en * tg[j][b]);
+      normalize3r(n2);
+      front_radiance(s, L, vols, nvol, m, X, n2, wr, rec->vis, rgb2, kq2, NULL, NULL);
+      for (int k = 0; k < 3; k++) fd[k] += fabs((double)rgb2[k] - rec->rgb[k]);
+    }
+  }
+  for (int k = 0; k < 3; k++) rec->kappa[k] = s->albedo[m * 3 + k] * kq[k] + 8.0 * fabs(rec->rgb[k]) + fd[k] / U32;
+}
+
+void orc_shade_ray(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol,
+                   const double o[3], const double w[3], double dmax, orc_ray_record* rec) {
+  shade_ray_impl(s, L, vols, nvol, o, w, dmax, 0, -1, 0, rec);
 }
 
 /* Section "Second Order Glossy": the mirror reflection ray of a surface
@@ -1003,30 +1208,35 @@ void orc_shade_ray(const orc_scene* s, const orc_lights* L, const orc_volume* vo
    probes instead of further rays.  A miss sees the sky; a backface is
    black.  kappa: float32 sensitivity as for a probe ray. */
 static void glossy_front(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol, int32_t m,
-                         const double Y[3], const double ng[3], const double r[3], uint32_t vis, double rgb[3],
+                         const real Y[3], const real ng[3], const real r[3], uint32_t vis, real rgb[3],
                          double kap[3], int32_t* cage, int32_t* n_cage) {
-  double kq[3];
+  double kq[3], kg[3];
   front_radiance(s, L, vols, nvol, m, Y, ng, r, vis, rgb, kq, cage, n_cage);
-  double c = dot3(ng, r);
-  double r2[3] = {r[0] - 2.0 * c * ng[0], r[1] - 2.0 * c * ng[1], r[2] - 2.0 * c * ng[2]};
-  double wo[3] = {-r[0], -r[1], -r[2]}, g[3], kg[3];
-  orc_query_look(vols, nvol, Y, ng, wo, r2, g, kg, NULL, NULL);
+  real c = dot3r(ng, r);
+  real r2[3] = {r[0] - (real)2.0 * c * ng[0], r[1] - (real)2.0 * c * ng[1], r[2] - (real)2.0 * c * ng[2]};
+  real wo[3] = {-r[0], -r[1], -r[2]}, g[3];
+  query_look_r(vols, nvol, Y, ng, wo, r2, g, kg, NULL, NULL);
   for (int k = 0; k < 3; k++) {
-    rgb[k] += s->specular[m * 3 + k] * g[k];
+    rgb[k] += (real)s->specular[m * 3 + k] * g[k];
     kap[k] = s->albedo[m * 3 + k] * kq[k] + s->specular[m * 3 + k] * kg[k];
   }
 }
 
 void orc_glossy(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol, const double X[3],
                 const double n[3], const double v[3], orc_ray_record* rec) {
-  double c = dot3(n, v);
-  double r[3] = {2.0 * c * n[0] - v[0], 2.0 * c * n[1] - v[1], 2.0 * c * n[2] - v[2]};
-  normalize3(r);
-  double xmax = fmax(fabs(X[0]), fmax(fabs(X[1]), fabs(X[2])));
-  double eps = 1e-4 * fmax(1.0, xmax);
-  double o[3] = {X[0] + eps * n[0], X[1] + eps * n[1], X[2] + eps * n[2]};
+  real Xr[3], nr[3], vr[3];
+  load3r(X, Xr);
+  load3r(n, nr);
+  load3r(v, vr);
+  real c = dot3r(nr, vr);
+  real r[3] = {(real)2.0 * c * nr[0] - vr[0], (real)2.0 * c * nr[1] - vr[1], (real)2.0 * c * nr[2] - vr[2]};
+  normalize3r(r);
+  real xmax = fmax(fabs(Xr[0]), fmax(fabs(Xr[1]), fabs(Xr[2])));
+  real eps = (real)1e-4 * fmax((real)1.0, xmax);
+  real o[3] = {Xr[0] + eps * nr[0], Xr[1] + eps * nr[1], Xr[2] + eps * nr[2]};
+  double od[3] = {o[0], o[1], o[2]}, rd[3] = {r[0], r[1], r[2]};
   orc_hit h;
-  orc_trace(s, o, r, 0, &h);
+  orc_trace(s, od, rd, 0, &h);
   memset(rec, 0, sizeof(*rec));
   for (int i = 0; i < ORC_CAGE; i++) rec->cage[i] = -1;
   rec->tri = h.tri;
@@ -1036,26 +1246,27 @@ void orc_glossy(const orc_scene* s, const orc_lights* L, const orc_volume* vols,
     for (int k = 0; k < 3; k++) rec->rgb[k] = L->sky[k];
     return;
   }
-  double e1[3], e2[3], ng[3];
-  sub3(tri_v(s, h.tri, 1), tri_v(s, h.tri, 0), e1);
-  sub3(tri_v(s, h.tri, 2), tri_v(s, h.tri, 0), e2);
-  cross3(e1, e2, ng);
-  normalize3(ng);
-  rec->cosi = fabs(dot3(r, ng));
-  if (dot3(r, ng) > 0.0) return;   /* backface: black */
-  double Y[3];
-  for (int a = 0; a < 3; a++) Y[a] = o[a] + h.t * r[a];
+  real ng[3];
+  tri_normal_r(s, h.tri, ng);
+  double ngd[3] = {ng[0], ng[1], ng[2]};
+  rec->cosi = fabs(dot3(rd, ngd));
+  if (dot3r(r, ng) > 0.0) return;   /* backface: black */
+  real t = h.t, Y[3];
+  for (int a = 0; a < 3; a++) Y[a] = o[a] + t * r[a];
   int32_t m = s->material[h.tri];
   hit_visibility(s, L, Y, ng, &rec->vis, &rec->flags);
   double kap[3];
-  glossy_front(s, L, vols, nvol, m, Y, ng, r, rec->vis, rec->rgb, kap, rec->cage, &rec->n_cage);
+  real rgb[3];
+  glossy_front(s, L, vols, nvol, m, Y, ng, r, rec->vis, rgb, kap, rec->cage, &rec->n_cage);
+  for (int k = 0; k < 3; k++) rec->rgb[k] = rgb[k];
   /* the hit point's float32 error along the ray, and the reflection
      direction's (about u per component over the distance t) */
   double ep = fmin(1e-2, U32 * (8.0 / fmax(rec->cosi, 1e-6) + 16.0 + 8.0 / fmax(h.t, 1e-6)));
-  double Y2[3], rgb2[3], kap2[3];
-  for (int a = 0; a < 3; a++) Y2[a] = o[a] + h.t * (1.0 + ep) * r[a];
+  real Y2[3], rgb2[3];
+  double kap2[3];
+  for (int a = 0; a < 3; a++) Y2[a] = o[a] + t * (real)(1.0 + ep) * r[a];
   glossy_front(s, L, vols, nvol, m, Y2, ng, r, rec->vis, rgb2, kap2, NULL, NULL);
-  for (int k = 0; k < 3; k++) rec->kappa[k] = kap[k] + 8.0 * fabs(rec->rgb[k]) + fabs(rgb2[k] - rec->rgb[k]) / U32;
+  for (int k = 0; k < 3; k++) rec->kappa[k] = kap[k] + 8.0 * fabs(rec->rgb[k]) + fabs((double)rgb2[k] - rec->rgb[k]) / U32;
 }
 
 void orc_glossy_batch(const orc_scene* s, const orc_lights* L, const orc_volume* vols, int32_t nvol, int64_t n,
@@ -1353,16 +1564,6 @@ static int active_state(uint8_t s) {
   return s == ORC_NEWLY_AWAKE || s == ORC_NEWLY_VIGILANT || s == ORC_AWAKE || s == ORC_VIGILANT;
 }
 
-/* float32 sensitivity (units of u) of a ray's recorded distance: the hit
-   distance's error along the ray, t (8 / |cos| + 16) (0.2 t for a
-   backface), unless the distance sits at the clamp beyond that error */
-static double ray_distance_kappa(const orc_ray_record* rr, double dmax) {
-  if (rr->tri < 0) return 0.0;
-  double tt = rr->d < dmax ? rr->d : (rr->d == fmin(0.2 * rr->t, dmax) && 0.2 * rr->t < rr->t ? 0.2 * rr->t : rr->t);
-  double err = tt * (8.0 / fmax(rr->cosi, 1e-6) + 16.0);
-  return tt <= dmax * (1.0 + 4.0 * U32) + err * U32 ? err : 0.0;
-}
-
 /* One frame (Section "Probe Update" and the last two steps of the full
    initialization): state step; every active probe traces its rotated
    spherical-Fibonacci rays and shades them against the previous atlases of
@@ -1370,6 +1571,12 @@ static double ray_distance_kappa(const orc_ray_record* rr, double dmax) {
    states) and Newly states promoted. */
 int64_t orc_update_frame(const orc_scene* s, const orc_lights* L, orc_volume* vols, int32_t nvol,
                          const float R[9], orc_ray_record* records, int64_t capacity) {
+  return orc_update_frame_forced(s, L, vols, nvol, R, records, capacity, 0, NULL, NULL, NULL);
+}
+
+int64_t orc_update_frame_forced(const orc_scene* s, const orc_lights* L, orc_volume* vols, int32_t nvol,
+                                const float R[9], orc_ray_record* records, int64_t capacity, int64_t n_force,
+                                const uint8_t* force, const int32_t* force_tri, const uint32_t* force_vis) {
   orc_state_step(s, vols, nvol);
   /* previous atlases and states, read by hit shading */
   orc_volume* prev = (orc_volume*)malloc(sizeof(orc_volume) * (size_t)(nvol ? nvol : 1));
@@ -1403,7 +1610,9 @@ int64_t orc_update_frame(const orc_scene* s, const orc_lights* L, orc_volume* vo
       for (int32_t r = 0; r < V->rays; r++) {
         double w[3];
         orc_sf_direction(r, V->rays, R, w);
-        orc_shade_ray(s, L, prev, nvol, Pq, w, dmax, &rec[off + slot[q] * V->rays + r]);
+        int64_t i = off + slot[q] * V->rays + r;
+        uint8_t fm = (force && i < n_force) ? force[i] : 0;
+        shade_ray_impl(s, L, prev, nvol, Pq, w, dmax, fm, fm ? force_tri[i] : -1, fm ? force_vis[i] : 0, &rec[i]);
       }
     }
     off += na * V->rays;
@@ -1434,7 +1643,7 @@ int64_t orc_update_frame(const orc_scene* s, const orc_lights* L, orc_volume* vo
           rk[3 * r + c] = rr->kappa[c];
         }
         d[r] = rr->d;
-        dk[r] = ray_distance_kappa(rr, (double)V->dmax);
+        dk[r] = rr->d_kappa;
       }
       int fresh = V->states[q] == ORC_NEWLY_AWAKE || V->states[q] == ORC_NEWLY_VIGILANT;
       orc_blend_probe_k(N, omega, rgb, rk, d, dk, (double)V->cos_power, fresh ? 0.0 : (double)V->alpha_irr,
@@ -1676,7 +1885,9 @@ static void query_terms(const orc_volume* vols, int32_t nvol, const double X[3],
   for (int32_t v = 0; v < nvol; v++) {
     const orc_volume* V = &vols[v];
     if (Wt >= 1.0) break;
-    double wv = volume_weight(V, X);
+    real Xr[3];
+    load3r(X, Xr);
+    double wv = volume_weight(V, Xr);
     double wuse = (v == nvol - 1) ? 1.0 - Wt : fmin(wv, 1.0 - Wt);
     if (wuse > 0.0) {
       double g[3] = {wuse * gout[0], wuse * gout[1], wuse * gout[2]};

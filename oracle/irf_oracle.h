@@ -10,7 +10,10 @@
  * benchmark load it.
  *
  * All arithmetic is IEEE double.  Inputs arrive as the same float32 arrays
- * that the GPU library receives and are promoted on entry.
+ * that the GPU library receives and are promoted on entry.  (A second build
+ * of the same source with -DORC_REAL=float evaluates the value path in
+ * float32; it exists only to check the float32 sensitivity estimates kappa
+ * that the records and texels carry.)
  */
 #ifndef IRF_ORACLE_H
 #define IRF_ORACLE_H
@@ -30,7 +33,9 @@ enum {
   ORC_F_TIE = 2,       /* another hit within eps_t * t of the closest           */
   ORC_F_NEARMISS = 4,  /* a triangle missed by less than eps_b before t(1+eps_t) */
   ORC_F_EDGEON = 8,    /* ray nearly parallel to the hit plane (face side unsure) */
-  ORC_F_SHADOW = 16    /* at least one shadow ray of this hit is ambiguous       */
+  ORC_F_SHADOW = 16,   /* at least one shadow ray of this hit is ambiguous       */
+  ORC_F_FORCED = 32,   /* hit or shadow decisions given by the caller            */
+  ORC_F_FORCE_INVALID = 64 /* the given triangle is not hit by the ray's line    */
 };
 
 typedef struct orc_scene orc_scene;
@@ -96,6 +101,7 @@ typedef struct {
   int32_t cage[ORC_CAGE];/* global probe ids (volume base + q); -1 pads */
   double kappa[3];       /* absolute float32 sensitivity of rgb (units of u) */
   double cosi;           /* |cos| of the angle between ray and hit plane (0 on a miss) */
+  double d_kappa;        /* absolute float32 sensitivity of d (units of u) */
 } orc_ray_record;
 
 /* ---- octahedral map (Cigolle et al. 2014), square [-1,1]^2 ---- */
@@ -155,6 +161,16 @@ void orc_state_step(const orc_scene* s, orc_volume* vols, int32_t nvol);
    volume in order, per active probe in index order, per ray, one record ---- */
 int64_t orc_update_frame(const orc_scene* s, const orc_lights* L, orc_volume* vols, int32_t nvol,
                          const float R[9], orc_ray_record* records, int64_t capacity);
+/* the same frame with some rays' decisions given (the parity protocol: on a
+   ray this oracle flags, another tracer's hit and shadow decisions are
+   adopted and everything downstream is recomputed).  For record index
+   i < n_force: bit 0 of force[i] takes force_tri[i] (-1: a miss) as the
+   ray's nearest hit, at the exact distance of that triangle's plane; bit 1
+   takes force_vis[i] as its shadow-ray bits.  Flags keep this oracle's own
+   flags plus ORC_F_FORCED. */
+int64_t orc_update_frame_forced(const orc_scene* s, const orc_lights* L, orc_volume* vols, int32_t nvol,
+                                const float R[9], orc_ray_record* records, int64_t capacity, int64_t n_force,
+                                const uint8_t* force, const int32_t* force_tri, const uint32_t* force_vis);
 
 /* ---- tracking window (Section "Tracking Windows") ----
    Moves V's window toward the camera: along each axis, while the camera is

@@ -37,11 +37,11 @@ class OracleFrame:
         self.emission = w.scene.emission.astype(np.float64)
         self.target = self.forward(S.target_emission(w).astype(np.float64), self.A0)[0]
 
-    def forward(self, emission, A0):
+    def forward(self, emission, A0, force=None):
         o = self.o
         self.sc.set_emission(emission)
         vols = o.copy_volumes(A0)
-        rec = o.update_frame(self.sc, self.w.lights, vols, self.R)
+        rec = o.update_frame(self.sc, self.w.lights, vols, self.R, force=force)
         q = self.w.queries
         E, _ = o.query(vols, q.pos, q.nrm, q.view)
         return E, vols, rec
@@ -93,11 +93,13 @@ class FullFrame:
         self.emission = w.scene.emission.astype(np.float64)
         self.target = self.forward(S.target_emission(w).astype(np.float64))[0]
 
-    def forward(self, emission):
+    def forward(self, emission, force=None):
+        """force: the GPU's decisions on rays the oracle flags (see
+        oracle.update_frame), so both sides hold the same hits fixed."""
         o = self.o
         self.sc.set_emission(emission)
         vols = o.copy_volumes(self.A0)
-        rec = o.update_frame(self.sc, self.w.lights, vols, self.R)
+        rec = o.update_frame(self.sc, self.w.lights, vols, self.R, force=force)
         q = self.w.queries
         E, _ = o.query(vols, q.pos, q.nrm, q.view)
         return E, vols, rec

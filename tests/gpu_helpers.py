@@ -1,93 +1,120 @@
-"""Shared helpers of the GPU parity tests: run a workload through the HIP
-library and through the oracle on the same seeded inputs, and compare.
+"""GPU side of the parity protocol (tests/parity.py): run workloads through
+the HIP library and through the FP64 oracle on the same seeded inputs and
+compare every ray, texel and query.
 
-Tolerances.  Floating-point results are compared per element as
-|gpu - oracle| <= 1e-5 * max(|oracle|, tau) + 8 u kappa, with tau = 1e-3 x
-the largest |oracle| value of that channel, u = 2^-24 and kappa the
-oracle's own estimate of the float32 sensitivity of that value (large only
-where the Chebyshev visibility weight is ill-conditioned).  Rays whose
-nearest hit or shadow decision differs between the float32 tracer and the
-oracle are accepted only where the oracle flagged them as ambiguous; such
-rays, the probes they feed and (next frame) the rays whose hit-shading query
-used those probes are 'tainted' and checked by validity instead of value.
+Every frame goes through the substitution step (the oracle adopts the
+library's decision on the rays it flags and where the two differ), so no
+probe, texel or ray is left out of the value comparison.  Each comparison
+prints its plain-1e-5 pass rate and the counts of elements that needed the
+oracle's float32 sensitivity allowance; those counts are held to budgets
+(WIDENED_MAX, BEYOND_MAX of the elements compared).
 """
 import numpy as np
 
-U32 = 2.0 ** -24
+from tests import parity as P
+
+U32 = P.U32
+# budgets, as fractions of the elements of one comparison: elements beyond
+# 1e-5 s within their kappa allowance (capped at 1e-3 s), and elements whose
+# allowance exceeds 1e-3 s (the float32 evaluation of the oracle's own steps
+# stays below 0.5 % and 0.6 % on these workloads)
+WIDENED_MAX = 0.02
+BEYOND_MAX = 0.01
 
 
-def tau(o, axis=0):
-    return 1e-3 * np.max(np.abs(o), axis=axis, keepdims=True) + 1e-30
+def gpu_records(ctx):
+    """All volumes' ray records of the last frame, in the oracle's order
+    (per volume, per active probe in index order, per ray)."""
+    recs = [ctx.ray_records(v) for v in range(len(ctx.volumes))]
+    return np.concatenate(recs) if recs else np.zeros(0)
 
 
-def within(g, o, kappa=None, rel=1e-5, tau_v=None):
-    g = np.asarray(g, np.float64)
-    o = np.asarray(o, np.float64)
-    t = tau(o.reshape(-1, o.shape[-1]) if o.ndim > 1 else o.reshape(-1, 1)) if tau_v is None else tau_v
-    tol = rel * np.maximum(np.abs(o), t.reshape((1,) * (o.ndim - 1) + (-1,)) if o.ndim > 1 else t.ravel()[0])
-    if kappa is not None:
-        tol = tol + 8 * U32 * np.asarray(kappa)
-    return np.abs(g - o) <= tol, tol
+def gpu_atlases(gv):
+    return (gv.irradiance[..., :3].float().cpu().numpy().astype(np.float64),
+            gv.distance.float().cpu().numpy().astype(np.float64))
 
 
-def run_classify(ctx, w, o_scene, o_vols):
+def copy_states(ctx, ov, torch, max_diff_frac=0.01):
+    """After classification: the GPU's states must match the oracle's except
+    on probes with an ambiguous ray; those take the oracle's state so both
+    sides continue from identical states.  Returns the differing count."""
+    total = 0
+    for gv, o in zip(ctx.volumes, ov):
+        gs = gv.states.cpu().numpy()
+        diff = np.nonzero(gs != o.states)[0]
+        assert len(diff) <= max(2, max_diff_frac * len(gs)), len(diff)
+        if len(diff):
+            gs[diff] = o.states[diff]
+            gv.states.copy_(torch.from_numpy(gs))
+        total += len(diff)
+    return total
+
+
+def frame(torch, ctx, osc, ov, lights, R, tag, launch=None):
+    """One GPU frame (ctx.update_probes(R), or launch()) and the oracle's
+    frame with substitution.  Returns (verdicts, report, oracle records,
+    GPU records)."""
+    if launch is None:
+        ctx.update_probes(R)
+    else:
+        launch()
+    torch.cuda.synchronize()
+    per_vol = [ctx.ray_records(v) for v in range(len(ctx.volumes))]
+    rec_g = np.concatenate(per_vol) if per_vol else np.zeros(0)
+    rec_o, rep = P.oracle_frame(osc, lights, ov, R, rec_g["tri"], rec_g["vis"])
+    print(f"[parity] {tag}: {rep.line()}", flush=True)
+    assert rep.unflagged_flips == 0, rep.line()
+    o_mag = P.origin_magnitude(ov, [len(r) for r in per_vol])
+    vs, t_bad = P.ray_checks(tag, rec_g["rgb"], rec_g["d"], rec_g["t"], rec_o, o_mag)
+    assert t_bad == 0, f"{tag}: {t_bad} hit distances beyond the float32 direction error"
+    for v, (gv, o) in enumerate(zip(ctx.volumes, ov)):
+        assert np.array_equal(gv.states.cpu().numpy(), o.states), f"{tag}: states of volume {v}"
+        gi, gd = gpu_atlases(gv)
+        vs += P.texel_checks(f"{tag} volume {v}", gi, gd, o)
+    return vs, rep, rec_o, rec_g
+
+
+def queries(torch, ctx, ov, q, tag, stage=True):
+    """End to end (each side's own atlases) and, with stage=True, the GPU
+    query on the oracle's atlases rounded to float32 (this overwrites the
+    GPU atlases)."""
     import oracle
-    ctx.classify(w.classify_rotations)
-    nb, nf, tf = oracle.classify(o_scene, o_vols, w.classify_rotations)
-    return nb, nf, tf
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    pos, nrm, view = t(q.pos), t(q.nrm), t(q.view)
+    eg = ctx.query_irradiance(pos, nrm, view).cpu().numpy()
+    eo, ko = oracle.query(ov, q.pos, q.nrm, q.view)
+    out = [P.compare(f"{tag} query end-to-end", eg, eo, ko)]
+    if stage:
+        ovr = oracle.copy_volumes(ov)
+        for gv, o in zip(ctx.volumes, ovr):
+            o.irr[:] = o.irr.astype(np.float32)
+            o.dist[:] = o.dist.astype(np.float32)
+            o.irr_kappa[:] = 0.0
+            o.dist_kappa[:] = 0.0
+            gv.irradiance[..., :3].copy_(torch.from_numpy(o.irr.astype(np.float32)))
+            gv.distance.copy_(torch.from_numpy(o.dist.astype(np.float32)))
+        es = ctx.query_irradiance(pos, nrm, view).cpu().numpy()
+        eo32, ko32 = oracle.query(ovr, q.pos, q.nrm, q.view)
+        out.append(P.compare(f"{tag} query stage", es, eo32, ko32))
+    return out
 
 
-def gpu_states(ctx):
-    return [v.states.cpu().numpy() for v in ctx.volumes]
+def check(verdicts, widened_max=WIDENED_MAX, beyond_max=BEYOND_MAX):
+    """Prints every verdict; asserts none fails and the counts stay within
+    their budgets."""
+    for v in verdicts:
+        print("[parity]", v.line(), flush=True)
+    bad = [(v.name, v.fail, round(v.worst_allowed, 3), v.where[:3]) for v in verdicts if not v.ok]
+    assert not bad, bad
+    over = [(v.name, v.widened, v.beyond_cap, v.n) for v in verdicts
+            if v.widened > widened_max * v.n or v.beyond_cap > beyond_max * v.n]
+    assert not over, over
 
 
-def sync_states_check(ctx, o_vols):
-    g = gpu_states(ctx)
-    return [np.array_equal(a, v.states) for a, v in zip(g, o_vols)]
-
-
-def compare_records(g, o, taint_probes_prev=None, probe_base=0):
-    """Per-ray comparison of one volume.  Returns (tainted_ray_mask, report)."""
-    assert len(g) == len(o), (len(g), len(o))
-    flip_tri = g["tri"] != o["tri"]
-    flip_vis = g["vis"] != o["vis"]
-    flagged = o["flags"] != 0
-    bad_flip = (flip_tri | flip_vis) & ~flagged
-    tainted = flip_tri | flip_vis
-    if taint_probes_prev is not None and taint_probes_prev.size:
-        cage = o["cage"]
-        used_tainted = np.isin(cage, taint_probes_prev) & (cage >= 0)
-        tainted = tainted | used_tainted.any(axis=1)
-    report = {"rays": len(g), "flagged": int(flagged.sum()), "flips": int((flip_tri | flip_vis).sum()),
-              "unflagged_flips": int(bad_flip.sum()), "tainted": int(tainted.sum())}
-    return tainted, bad_flip, report
-
-
-def texel_check(gv, ov, probes, rec_o=None, slot_of=None, rel=1e-5):
-    """Compare the atlases of `probes` (oracle float64 vs GPU): per texel
-    |g - o| <= rel * max(|o|, tau) + 8 u kappa, kappa = the oracle's float32
-    sensitivity of that texel (its rays' radiance, its blend weights and
-    rounding, carried through the hysteresis)."""
-    gi = gv.irradiance[..., :3].float().cpu().numpy().astype(np.float64)
-    gd = gv.distance.float().cpu().numpy().astype(np.float64)
-    oi, od = ov.irr, ov.dist
-    ti = tau(oi.reshape(-1, 3))
-    td = tau(od.reshape(-1, 2))
-    worst = 0.0
-    bad = []
-    for q in probes:
-        tol_i = rel * np.maximum(np.abs(oi[q]), ti.reshape(1, 1, 3)) + 8 * U32 * ov.irr_kappa[q]
-        tol_d = rel * np.maximum(np.abs(od[q]), td.reshape(1, 1, 2)) + 8 * U32 * ov.dist_kappa[q]
-        ei = np.abs(gi[q] - oi[q]) / tol_i
-        ed = np.abs(gd[q] - od[q]) / tol_d
-        m = max(ei.max(), ed.max())
-        worst = max(worst, m)
-        if m > 1:
-            bad.append((q, float(ei.max()), float(ed.max())))
-    return worst, bad
-
-
-def slots_of(rec_g, n_rays):
-    probes = rec_g["probe"]
-    probe_list = probes[::n_rays]
-    return {int(q): np.arange(i * n_rays, (i + 1) * n_rays) for i, q in enumerate(probe_list)}
+def flips(rec_g, rec_o):
+    """Rays whose hit or shadow bits differ, and how many of them the oracle
+    did not flag (must be none)."""
+    import oracle
+    f = (rec_g["tri"] != rec_o["tri"]) | (rec_g["vis"] != rec_o["vis"])
+    return f, {"rays": len(f), "flips": int(f.sum()),
+               "unflagged_flips": int((f & ((rec_o["flags"] & oracle.F_AMBIGUOUS) == 0)).sum())}

@@ -1,20 +1,31 @@
 """Blend variants on the GPU against the FP64 oracle.
 
 * f32_valu: the vector-ALU blend (one workgroup per probe) must meet the same
-  1e-5 parity bar as the float32 matrix-core blend used by default.
+  parity bar as the float32 matrix-core blend used by default.
 * bf16 / f16 inputs on the matrix cores with float32 accumulation and float32
-  normalisation, atlases stored in float32 or float16: the error against the
-  oracle is measured per atlas channel and bounded a priori by the input
-  rounding (u = 2^-9 for bf16, 2^-11 for f16), the float16 storage rounding
-  and its growth through the hysteresis.
+  normalisation, atlases stored in float32 or float16: the relative error
+  against the oracle (floor tau = 1e-3 of the channel's largest value) is
+  measured per atlas channel -- irradiance R, G, B, mean distance mu and
+  mean squared distance mu2 -- after the second frame, as max and p99, and
+  held to its a-priori bound: the input rounding u_in (2^-8 for bf16, 2^-11
+  for f16) of the weights and of the ray values moves a normalised weighted
+  mean by at most u_in of the largest value plus u_in of the value spread
+  (<= 4 u_in relative at the floor), float16 storage adds its rounding
+  (2^-11, twice: the frame-1 and the frame-2 texel).  The mode claimed to
+  meet the precision gate of 1e-3 relative irradiance error (f16 inputs,
+  float32 atlases) is asserted at 1e-3; bf16 inputs do not meet it (their
+  8-bit significand on the weights and values alone allows ~4e-3).
 """
 import numpy as np
 import pytest
 
 from paper_2009_10796_amd import scenes as S
-from tests.gpu_helpers import compare_records, slots_of, tau, texel_check
+from tests import gpu_helpers as G
+from tests import parity as P
 
 pytestmark = pytest.mark.gpu
+
+CHANNELS = ("E.R", "E.G", "E.B", "mu", "mu2")
 
 
 @pytest.fixture(scope="module")
@@ -25,7 +36,9 @@ def torch():
     return torch
 
 
-def _run_pair(torch, w, frames=(1, 2)):
+def _run(torch, w, frames=(1, 2)):
+    """Frames through the parity protocol (substitution on flagged rays);
+    returns the context, the oracle volumes and the last frame's verdicts."""
     import oracle
     from paper_2009_10796_amd import irf
     ctx = irf.build_workload(w)
@@ -33,52 +46,35 @@ def _run_pair(torch, w, frames=(1, 2)):
     ov = [oracle.Volume(d) for d in w.volumes]
     ctx.classify(w.classify_rotations)
     oracle.classify(osc, ov, w.classify_rotations)
-    gs = ctx.volumes[0].states.cpu().numpy()
-    diff = np.nonzero(gs != ov[0].states)[0]
-    if len(diff):
-        gs[diff] = ov[0].states[diff]
-        ctx.volumes[0].states.copy_(torch.from_numpy(gs))
-    taint = np.zeros(0, np.int64)
+    G.copy_states(ctx, ov, torch)
+    verdicts = []
     for f in frames:
-        R = w.frame_rotation(f)
-        ctx.update_probes(R)
-        rec_o = oracle.update_frame(osc, w.lights, ov, R)
-        torch.cuda.synchronize()
-        rec_g = ctx.ray_records(0)
-        tainted, bad, rep = compare_records(rec_g, rec_o, taint)
-        assert rep["unflagged_flips"] == 0
-        taint = np.unique(rec_g["probe"][tainted]).astype(np.int64)
-    ctx.last_records = (rec_g, rec_o)
-    return ctx, ov, taint
+        vs, _, _, _ = G.frame(torch, ctx, osc, ov, w.lights, w.frame_rotation(f), f"blend {w.volumes[0].blend} frame {f}")
+        verdicts += vs
+    return ctx, ov, verdicts
 
 
-def _errors(ctx, ov, taint):
-    g_irr = ctx.volumes[0].irradiance[..., :3].float().cpu().numpy().astype(np.float64)
-    g_dist = ctx.volumes[0].distance.float().cpu().numpy().astype(np.float64)
-    keep = np.ones(len(g_irr), bool)
-    keep[taint] = False
+def channel_errors(ctx, ov):
+    """Per channel (E.R, E.G, E.B, mu, mu2): (max, p99) of |g - o| / max(|o|, tau)."""
+    gi, gd = G.gpu_atlases(ctx.volumes[0])
     out = {}
-    for name, g, o in (("irradiance", g_irr, ov[0].irr), ("distance", g_dist, ov[0].dist)):
-        t = tau(o.reshape(-1, o.shape[-1])).reshape(1, 1, 1, -1)
-        rel = np.abs(g - o) / np.maximum(np.abs(o), t)
-        rel = rel[keep]
-        out[name] = (float(rel.max()), float(np.quantile(rel, 0.99)))
+    for names, g, o in ((CHANNELS[:3], gi, ov[0].irr), (CHANNELS[3:], gd, ov[0].dist)):
+        rel = np.abs(g - o) / np.maximum(np.abs(o), P.channel_tau(o))
+        for c, name in enumerate(names):
+            r = rel[..., c].ravel()
+            out[name] = (float(r.max()), float(np.quantile(r, 0.99)))
     return out
 
 
 @pytest.mark.parametrize("mode", ["f32_valu", "f32"])
 def test_f32_blend_parity_room(torch, mode):
-    """Both float32 blends meet the parity bar of the main test (1e-5 with the
-    oracle's float32 sensitivity of the rays that feed each texel)."""
+    """Both float32 blends meet the parity bar of the main test."""
     w = S.config0()
     for d in w.volumes:
         d.blend = mode
-    ctx, ov, taint = _run_pair(torch, w)
-    rec_g, rec_o = ctx.last_records
-    clean = [q for q in range(ctx.volumes[0].n_probes) if q not in set(taint.tolist())]
-    worst, bad = texel_check(ctx.volumes[0], ov[0], clean, rec_o, slots_of(rec_g, w.volumes[0].rays_per_probe))
-    print(f"[blend] {mode} room: texel worst err/tol {worst:.3f}; plain errors {_errors(ctx, ov, taint)}", flush=True)
-    assert not bad, bad[:5]
+    ctx, ov, verdicts = _run(torch, w)
+    G.check(verdicts)
+    print(f"[blend] {mode} room: per-channel (max, p99) {channel_errors(ctx, ov)}", flush=True)
     ctx.close()
 
 
@@ -89,15 +85,16 @@ def test_low_precision_blend_error_city(torch, mode, atlas16):
     for d in w.volumes:
         d.blend = mode
         d.atlas_f16 = atlas16
-    ctx, ov, taint = _run_pair(torch, w)
-    e = _errors(ctx, ov, taint)
-    print(f"[blend] city mode={mode} atlas_f16={atlas16}: (max, p99) relative error {e}", flush=True)
-    # a-priori bounds (relative, floor tau): input rounding u_in on radiance and
-    # weights (the weighted mean moves by at most ~2 u_in of the value spread),
-    # plus float16 storage (u = 2^-11) amplified at most 1/(1-alpha) ... but
-    # frame 2 adds only one blend step: u16 * (1 + alpha) suffices here
+    ctx, ov, _ = _run(torch, w)
+    e = channel_errors(ctx, ov)
+    print(f"[blend] city mode={mode} atlas_f16={atlas16}: per-channel (max, p99) relative error "
+          + ", ".join(f"{k} ({a:.2e}, {b:.2e})" for k, (a, b) in e.items()), flush=True)
     u_in = {"bf16": 2.0 ** -8, "f16": 2.0 ** -11, "f32": 2.0 ** -23}[mode]
-    u_st = 2.0 ** -11 * 2 if atlas16 else 0.0
-    bound = 4 * u_in + u_st + 1e-5
-    assert e["irradiance"][1] <= bound, (e, bound)
+    u_st = 2 * 2.0 ** -11 if atlas16 else 0.0
+    bound_max = 4 * u_in + u_st + 1e-5
+    bound_p99 = 2 * u_in + u_st + 1e-5
+    for k, (mx, p99) in e.items():
+        assert mx <= bound_max and p99 <= bound_p99, (k, mx, p99, bound_max, bound_p99)
+    if mode == "f16" and not atlas16:
+        assert max(e[c][0] for c in CHANNELS[:3]) <= 1e-3, e    # the precision gate
     ctx.close()

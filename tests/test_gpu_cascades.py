@@ -10,20 +10,17 @@ which blend the cascades (Section "Multiple Probe Volumes").
 The same checks on four cascades of 16x8x16 probes (8,192 probes, 32 rays):
 above 4,096 probes the frame start compacts the active probes in two
 passes (per-workgroup counts, then a scatter) instead of one workgroup.
-Frames 1 and 2 exercise that path completely (state steps, active lists and
-counters of every volume, hits, shading from the previous atlases, texels).
-A third frame is left out there: five of its 15,904 rays in the densest
-cascade -- probes 0.14 m from a wall, where the Chebyshev variance is a
-near-cancellation of the two blended moments -- exceed the oracle's
-first-order float32 sensitivity bound by 5-14 % (every other ray stays
-below 0.6 of it); the GPU's values there are the same before and after the
-recent query changes, so this is a limit of the bound, not of the path.
+Its third frame holds hits 0.016 m above the densest cascade's bottom probe
+layer, where that cascade's blend weight is a small difference of float32
+coordinates (~27 m) and so carries ~1e-4 relative error: the oracle's
+float32 sensitivity takes the rounding of the hit point's coordinates into
+account.
 """
 import numpy as np
 import pytest
 
 from paper_2009_10796_amd import scenes as S
-from tests.gpu_helpers import compare_records, slots_of, tau, texel_check, within
+from tests import gpu_helpers as G
 
 pytestmark = pytest.mark.gpu
 
@@ -50,7 +47,7 @@ def test_two_pass_compaction_parity(torch):
     total = sum(d.n_probes for d in w.volumes)
     print(f"[cascade] {total} probes in {len(w.volumes)} volumes", flush=True)
     assert total > 4096
-    _cascades_parity(torch, w, frames=(1, 2))
+    _cascades_parity(torch, w)
 
 
 def _cascades_parity(torch, w, frames=(1, 2, 3)):
@@ -61,57 +58,16 @@ def _cascades_parity(torch, w, frames=(1, 2, 3)):
     ov = [oracle.Volume(d) for d in w.volumes]
     ctx.classify(w.classify_rotations)
     oracle.classify(osc, ov, w.classify_rotations)
-    for v, (gv, o) in enumerate(zip(ctx.volumes, ov)):
-        gs = gv.states.cpu().numpy()
-        print(f"[cascade] volume {v} states {np.bincount(o.states, minlength=6)} differ={(gs != o.states).sum()}",
-              flush=True)
-        diff = np.nonzero(gs != o.states)[0]
-        assert len(diff) <= max(2, 0.01 * len(gs))
-        if len(diff):
-            gs[diff] = o.states[diff]
-            gv.states.copy_(torch.from_numpy(gs))
-    taints = [np.zeros(0, np.int64) for _ in ov]
-    bases = np.cumsum([0] + [d.n_probes for d in w.volumes])
+    for v, o in enumerate(ov):
+        print(f"[cascade] volume {v} states {np.bincount(o.states, minlength=6)}", flush=True)
+    print(f"[cascade] classification differs on {G.copy_states(ctx, ov, torch)} probes", flush=True)
+    verdicts = []
     for f in frames:
         L = S.sun_for_frame(f)
         ctx.set_lights(L)
-        R = w.frame_rotation(f)
-        ctx.update_probes(R)
-        rec_o_all = oracle.update_frame(osc, L, ov, R)
-        torch.cuda.synchronize()
-        off = 0
-        new_taint_global = []
-        for v, gv in enumerate(ctx.volumes):
-            rec_g = ctx.ray_records(v)
-            rec_o = rec_o_all[off: off + len(rec_g)]
-            off += len(rec_g)
-            assert np.array_equal(gv.states.cpu().numpy(), ov[v].states)
-            prev_global = np.concatenate(taints) if len(taints) else np.zeros(0, np.int64)
-            tainted, bad, rep = compare_records(rec_g, rec_o, prev_global)
-            print(f"[cascade] frame {f} volume {v}: {rep}", flush=True)
-            assert rep["unflagged_flips"] == 0
-            clean = ~tainted
-            ok, _ = within(rec_g["rgb"][clean], rec_o["rgb"][clean], kappa=rec_o["kappa"][clean])
-            assert ok.all(), np.argwhere(~ok)[:5]
-            tp = np.unique(rec_g["probe"][tainted])
-            cp = [q for q in range(gv.n_probes) if q not in set(tp.tolist())]
-            worst, badt = texel_check(gv, ov[v], cp, rec_o, slots_of(rec_g, w.volumes[v].rays_per_probe))
-            print(f"[cascade] frame {f} volume {v}: texel worst err/tol {worst:.3f}", flush=True)
-            assert not badt, badt[:5]
-            new_taint_global.append(tp.astype(np.int64) + bases[v])
-        assert off == len(rec_o_all)
-        taints = new_taint_global
-    # queries at surface points: cascade blend; stage parity on the oracle atlases
-    q = S.surface_points(w.scene, 20000, 3)
-    for gv, o in zip(ctx.volumes, ov):
-        gv.irradiance[..., :3].copy_(torch.from_numpy(o.irr.astype(np.float32)))
-        gv.distance.copy_(torch.from_numpy(o.dist.astype(np.float32)))
-        o.irr[:] = o.irr.astype(np.float32)
-        o.dist[:] = o.dist.astype(np.float32)
-    e = ctx.query_irradiance(torch.from_numpy(q.pos).cuda(), torch.from_numpy(q.nrm).cuda(),
-                             torch.from_numpy(q.view).cuda()).cpu().numpy()
-    eo, ko = oracle.query(ov, q.pos, q.nrm, q.view)
-    ok, _ = within(e, eo, kappa=ko)
-    print(f"[cascade] query stage: fail={int((~ok).any(1).sum())} of {len(e)}", flush=True)
-    assert ok.all()
+        vs, _, _, _ = G.frame(torch, ctx, osc, ov, L, w.frame_rotation(f), f"cascade frame {f}")
+        verdicts += vs
+    # queries at surface points: cascade blend, end to end and on the oracle's atlases
+    verdicts += G.queries(torch, ctx, ov, S.surface_points(w.scene, 20000, 3), "cascade")
+    G.check(verdicts)
     ctx.close()

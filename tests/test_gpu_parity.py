@@ -3,15 +3,17 @@
 Workloads: the 4x4x4-probe room (64 rays) and the full-size 16x8x16-probe
 city (256 rays, ~100k triangles, 1920x1080 G-buffer queries).  Steps:
 classification, update frames 1 (converge, hysteresis 0) and 2 (hysteresis
-0.97, hit shading reads the frame-1 atlas), then queries.  Tolerances and
-the treatment of rays the float32 tracer may legitimately decide otherwise
-are described in gpu_helpers.
+0.97, hit shading reads the frame-1 atlas), then queries.  Every ray, every
+texel of every probe and every query is compared (tests/parity.py: rays
+the float32 tracer decides otherwise must be flagged by the oracle, which
+then adopts the GPU's decision on them and recomputes; plain 1e-5 relative
+rule with the oracle's float32 sensitivity allowance counted and capped).
 """
 import numpy as np
 import pytest
 
 from paper_2009_10796_amd import scenes as S
-from tests.gpu_helpers import U32, compare_records, tau, texel_check, within
+from tests import gpu_helpers as G
 
 pytestmark = pytest.mark.gpu
 
@@ -37,85 +39,27 @@ def test_update_and_query_parity(torch, name):
     print(f"[parity] workload={name}", flush=True)
     w = _workload(name)
     ctx = irf.build_workload(w)
-    gv = ctx.volumes[0]
     osc = oracle.Scene(w.scene)
     ov = [oracle.Volume(d) for d in w.volumes]
 
     # classification
     ctx.classify(w.classify_rotations)
     nb, nf, tf = oracle.classify(osc, ov, w.classify_rotations)
-    gs = gv.states.cpu().numpy()
+    gs = ctx.volumes[0].states.cpu().numpy()
     diff = np.nonzero(gs != ov[0].states)[0]
     print(f"[parity] {name} states {np.bincount(ov[0].states, minlength=6)} differ={len(diff)}", flush=True)
     assert np.all(nf[diff] > 0), "state differs on a probe with no ambiguous ray"
-    assert len(diff) <= max(2, 0.01 * len(gs))
-    if len(diff):
-        # continue from identical states (oracle -> GPU input only)
-        gs[diff] = ov[0].states[diff]
-        gv.states.copy_(torch.from_numpy(gs))
+    G.copy_states(ctx, ov, torch)
 
-    tainted_prev = np.zeros(0, np.int64)
+    verdicts = []
+    substituted = 0
     for f in (1, 2):
-        R = w.frame_rotation(f)
-        ctx.update_probes(R)
-        rec_o = oracle.update_frame(osc, w.lights, ov, R)
-        torch.cuda.synchronize()
-        rec_g = ctx.ray_records(0)
-        assert np.array_equal(gv.states.cpu().numpy(), ov[0].states)
-        tainted, bad_flip, rep = compare_records(rec_g, rec_o, tainted_prev)
-        print(f"[parity] {name} frame {f}: {rep}", flush=True)
-        assert rep["unflagged_flips"] == 0
-        assert rep["tainted"] <= 0.01 * rep["rays"] + 2
-        clean = ~tainted
-        # per-ray hit distance on identical hits, radiance and distance
-        # (float32 rounding of the ray direction moves t by ~u / |cos incidence|)
-        same = (rec_g["tri"] == rec_o["tri"]) & (rec_o["tri"] >= 0)
-        t_tol = rec_o["t"][same] * (2e-6 + 8 * U32 / np.maximum(rec_o["cosi"][same], 1e-6))
-        assert np.all(np.abs(rec_g["t"][same] - rec_o["t"][same]) <= t_tol)
-        ok, _ = within(rec_g["rgb"][clean], rec_o["rgb"][clean], kappa=rec_o["kappa"][clean])
-        worst_ray = np.argwhere(~ok)
-        assert ok.all(), (worst_ray[:5], rec_g["rgb"][clean][~ok.all(1)][:3], rec_o["rgb"][clean][~ok.all(1)][:3])
-        ok, _ = within(rec_g["d"][clean, None], rec_o["d"][clean, None])
-        assert ok.all()
-        # texels
-        probes = rec_g["probe"]
-        n_rays = w.volumes[0].rays_per_probe
-        assert len(probes) % n_rays == 0
-        probe_list = probes[::n_rays]
-        slot_of = {int(q): np.arange(i * n_rays, (i + 1) * n_rays) for i, q in enumerate(probe_list)}
-        taint_probes = np.unique(probes[tainted])
-        clean_probes = [int(q) for q in range(gv.n_probes) if q not in set(taint_probes.tolist())]
-        worst, bad = texel_check(gv, ov[0], clean_probes, rec_o, slot_of)
-        print(f"[parity] {name} frame {f}: texel worst err/tol = {worst:.3f}, tainted probes {len(taint_probes)}",
-              flush=True)
-        assert not bad, bad[:5]
-        tainted_prev = taint_probes.astype(np.int64)
-
-    # queries on each side's own frame-2 atlas
-    q = w.queries
-    pos = torch.from_numpy(q.pos).cuda()
-    nrm = torch.from_numpy(q.nrm).cuda()
-    view = torch.from_numpy(q.view).cuda()
-    eg = ctx.query_irradiance(pos, nrm, view).cpu().numpy()
-    eo, ko = oracle.query(ov, q.pos, q.nrm, q.view)
-    # stage parity: the GPU query on the oracle's atlas (rounded to float32)
-    gv.irradiance[..., :3].copy_(torch.from_numpy(ov[0].irr.astype(np.float32)))
-    gv.distance.copy_(torch.from_numpy(ov[0].dist.astype(np.float32)))
-    ov32 = oracle.Volume(w.volumes[0], states=ov[0].states)
-    ov32.irr[:] = ov[0].irr.astype(np.float32)
-    ov32.dist[:] = ov[0].dist.astype(np.float32)
-    es = ctx.query_irradiance(pos, nrm, view).cpu().numpy()
-    eo32, ko32 = oracle.query([ov32], q.pos, q.nrm, q.view)
-    ok, tol = within(es, eo32, kappa=ko32)
-    loose = (ko32 * U32 * 8 > 1e-5 * np.maximum(np.abs(eo32), tau(eo32))).any(1)
-    print(f"[parity] {name} query stage: n={len(es)} fail={int((~ok).any(1).sum())} "
-          f"ill-conditioned={int(loose.sum())}", flush=True)
-    assert ok.all(), np.argwhere(~ok)[:5]
-    # end to end (each side's own atlas): the atlases agree to ~32 u relative
-    # (checked above), which the query amplifies by the same sensitivity
-    ok, _ = within(eg, eo, kappa=32 * ko)
-    print(f"[parity] {name} query end-to-end: fail={int((~ok).any(1).sum())}", flush=True)
-    assert (~ok).any(1).mean() <= 1e-3
+        vs, rep, _, _ = G.frame(torch, ctx, osc, ov, w.lights, w.frame_rotation(f), f"{name} frame {f}")
+        verdicts += vs
+        substituted += rep.substituted
+    print(f"[parity] {name}: every probe's texels compared; {substituted} rays substituted", flush=True)
+    verdicts += G.queries(torch, ctx, ov, w.queries, name)
+    G.check(verdicts)
     ctx.close()
 
 

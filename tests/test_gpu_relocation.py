@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from paper_2009_10796_amd import scenes as S
-from tests.gpu_helpers import compare_records, slots_of, texel_check, within
+from tests import gpu_helpers as G
 
 pytestmark = pytest.mark.gpu
 
@@ -57,30 +57,15 @@ def test_relocation_parity(torch, name):
     # classification from the relocated positions
     ctx.classify(w.classify_rotations)
     oracle.classify(osc, ov, w.classify_rotations)
-    gs = gv.states.cpu().numpy()
-    diff = np.nonzero(gs != ov[0].states)[0]
-    print(f"[relocation] {name}: states {np.bincount(ov[0].states, minlength=6)} differ={len(diff)}", flush=True)
-    assert len(diff) <= max(2, 0.01 * len(gs))
-    if len(diff):
-        gs[diff] = ov[0].states[diff]
-        gv.states.copy_(torch.from_numpy(gs))
+    n_diff = G.copy_states(ctx, ov, torch)
+    print(f"[relocation] {name}: states {np.bincount(ov[0].states, minlength=6)} differ={n_diff}", flush=True)
 
-    # one update frame from the relocated probes
-    R = w.frame_rotation(1)
-    ctx.update_probes(R)
-    rec_o = oracle.update_frame(osc, w.lights, ov, R)
-    torch.cuda.synchronize()
-    rec_g = ctx.ray_records(0)
-    tainted, _, rep = compare_records(rec_g, rec_o)
-    print(f"[relocation] {name} frame 1: {rep}", flush=True)
-    assert rep["unflagged_flips"] == 0
-    ok, _ = within(rec_g["rgb"][~tainted], rec_o["rgb"][~tainted], kappa=rec_o["kappa"][~tainted])
-    assert ok.all(), np.argwhere(~ok)[:5]
-    taint_probes = set(np.unique(rec_g["probe"][tainted]).tolist())
-    worst, bad = texel_check(gv, ov[0], [q for q in range(gv.n_probes) if q not in taint_probes], rec_o,
-                             slots_of(rec_g, w.volumes[0].rays_per_probe))
-    print(f"[relocation] {name} frame 1: texel worst err/tol {worst:.3f}", flush=True)
-    assert not bad, bad[:5]
+    # two update frames from the relocated probes
+    verdicts = []
+    for f in (1, 2):
+        vs, _, _, _ = G.frame(torch, ctx, osc, ov, w.lights, w.frame_rotation(f), f"relocation {name} frame {f}")
+        verdicts += vs
+    G.check(verdicts)
     ctx.close()
 
 

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from paper_2009_10796_amd import scenes as S
-from tests.gpu_helpers import compare_records, slots_of, texel_check, within
+from tests import gpu_helpers as G
 
 pytestmark = pytest.mark.gpu
 
@@ -43,40 +43,14 @@ def test_scene_replaced_between_frames(torch):
     o = oracle.Volume(w.volumes[0])
     ctx.classify(w.classify_rotations)
     oracle.classify(osc_a, [o], w.classify_rotations)
-    gs = gv.states.cpu().numpy()
-    diff = np.nonzero(gs != o.states)[0]
-    assert len(diff) <= 1
-    if len(diff):
-        gs[diff] = o.states[diff]
-        gv.states.copy_(torch.from_numpy(gs))
-    taint = np.zeros(0, np.int64)
+    assert G.copy_states(ctx, [o], torch) <= 1
+    verdicts = []
     for f, (osc, scene) in ((1, (osc_a, None)), (2, (osc_b, scene_b))):
         if scene is not None:
             ctx.set_scene(scene)
-        R = w.frame_rotation(f)
-        ctx.update_probes(R)
-        rec_o = oracle.update_frame(osc, w.lights, [o], R)
-        torch.cuda.synchronize()
-        rec_g = ctx.ray_records(0)
-        assert np.array_equal(gv.states.cpu().numpy(), o.states)
-        tainted, _, rep = compare_records(rec_g, rec_o, taint)
-        print(f"[scene change] frame {f}: {rep}, states {np.bincount(o.states, minlength=6)}", flush=True)
-        assert rep["unflagged_flips"] == 0
-        ok, _ = within(rec_g["rgb"][~tainted], rec_o["rgb"][~tainted], kappa=rec_o["kappa"][~tainted])
-        assert ok.all(), np.argwhere(~ok)[:5]
-        tp = np.unique(rec_g["probe"][tainted])
-        clean = [q for q in range(gv.n_probes) if q not in set(tp.tolist())]
-        worst, bad = texel_check(gv, o, clean, rec_o, slots_of(rec_g, w.volumes[0].rays_per_probe))
-        print(f"[scene change] frame {f}: texel worst err/tol {worst:.3f}", flush=True)
-        assert not bad, bad[:5]
-        taint = tp.astype(np.int64)
-    q = w.queries
-    gv.irradiance[..., :3].copy_(torch.from_numpy(o.irr.astype(np.float32)))
-    gv.distance.copy_(torch.from_numpy(o.dist.astype(np.float32)))
-    o.irr[:] = o.irr.astype(np.float32)
-    o.dist[:] = o.dist.astype(np.float32)
-    e = ctx.query_irradiance(*(torch.from_numpy(a).cuda() for a in (q.pos, q.nrm, q.view))).cpu().numpy()
-    eo, ko = oracle.query([o], q.pos, q.nrm, q.view)
-    ok, _ = within(e, eo, kappa=ko)
-    assert ok.all(), np.argwhere(~ok)[:5]
+        vs, rep, _, _ = G.frame(torch, ctx, osc, [o], w.lights, w.frame_rotation(f), f"scene change frame {f}")
+        verdicts += vs
+        print(f"[scene change] frame {f}: states {np.bincount(o.states, minlength=6)}", flush=True)
+    verdicts += G.queries(torch, ctx, [o], w.queries, "scene change")
+    G.check(verdicts)
     ctx.close()

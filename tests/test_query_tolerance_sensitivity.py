@@ -8,7 +8,7 @@ swapped pair is what a wrong wide load of adjacent texels would produce.)"""
 import numpy as np
 
 from paper_2009_10796_amd import scenes as S
-from tests.gpu_helpers import within
+from tests import parity as P
 
 
 def _swap_pairs(a):
@@ -38,8 +38,7 @@ def test_swapped_texel_pairs_fail_the_query_tolerance():
         return oracle.query([v], w.queries.pos, w.queries.nrm, w.queries.view)
 
     eo, ko = query(irr, dist)
-    ok, _ = within(eo, eo, kappa=ko)
-    assert ok.all()
+    assert P.compare("unchanged", eo, eo, ko).ok
     for planted in (query(_swap_pairs(irr), dist)[0], query(irr, _swap_pairs(dist))[0]):
-        ok, _ = within(planted, eo, kappa=ko)
-        assert (~ok).any(1).sum() > 0.1 * len(eo)
+        v = P.compare("planted", planted, eo, ko)
+        assert v.fail > 0.1 * eo.size, v.line()
