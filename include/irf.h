@@ -248,6 +248,26 @@ irf_status irf_optimize_probes(irf_ctx* ctx, const float* rotations, int32_t ite
    states), border texels, promotion of Newly states.  Async. */
 irf_status irf_update_probes(irf_ctx* ctx, const float* rotation, void* stream);
 
+/* The same frame for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   it calls no hipMalloc, hipFree or other allocating routine.  Its frame
+   scratch (parameters, active list, ray directions, weight rows, hit
+   records, shadow-task queues, visibility bytes, ray radiance) is carved
+   from one static device array of IRF_NOALLOC_SCRATCH_BYTES that each GPU
+   the library runs on holds until the process ends, shared by every
+   context and call on that GPU; it keeps the last call's contents (each
+   frame writes what it reads).  Calls that overlap on one GPU (two streams,
+   two threads) race on it: order them.  A frame whose scratch (the sizes
+   irf_update_probes would allocate for the bound volumes and lights) exceeds
+   the array, or a differentiable context (irf_set_differentiable), returns
+   IRF_E_UNSUPPORTED before any launch.  Results (atlases, states) are those
+   of irf_update_probes bit for bit; the frame's rays run in index order
+   (the per-volume coherent trace order is a library allocation), and
+   irf_ray_records / irf_frame_stats do not see this frame (IRF_E_STATE until
+   the next irf_update_probes).  Async. */
+#define IRF_NOALLOC_SCRATCH_BYTES (128ll << 20)
+irf_status irf_update_probes_noalloc(irf_ctx* ctx, const float* rotation, void* stream);
+
 /* The same frame, with its atlas writes (the blend) ordered after
    `atlas_event` (a hipEvent_t the caller recorded, typically after the
    previous frame's queries on another stream; NULL: none).  Everything

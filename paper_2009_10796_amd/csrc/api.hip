@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -354,9 +355,8 @@ irf_status launched() {
 
 // One update frame, asynchronously on `st` (also what a graph captures); the
 // blend waits for `atlas_wait` when given.
-hipError_t enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st, hipEvent_t atlas_wait = nullptr) {
-  VolumeSet vs = volume_view(c);
-  FrameScratch fs = scratch_view(c);
+hipError_t enqueue_frame_on(irf_ctx* c, const float* rotation, hipStream_t st, hipEvent_t atlas_wait,
+                            const VolumeSet& vs, const FrameScratch& fs) {
   SceneGPU sc = scene_view(c);
   const int nl = c->lights.n_dir + c->lights.n_point;
   FrameParams fp;
@@ -404,6 +404,73 @@ hipError_t enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st, hipE
     launch_blend_mma(vs, fs, c->tune.blend_blocks, st);
   }
   return hipSuccess;
+}
+
+hipError_t enqueue_frame(irf_ctx* c, const float* rotation, hipStream_t st, hipEvent_t atlas_wait = nullptr) {
+  return enqueue_frame_on(c, rotation, st, atlas_wait, volume_view(c), scratch_view(c));
+}
+
+// ---- the allocation-free frame (irf_update_probes_noalloc)
+//
+// Its scratch is this file-scope array: each GPU the library runs on holds
+// its own copy (IRF_NOALLOC_SCRATCH_BYTES) until the process ends.  On the
+// host the array's name is only a stand-in, so host code uses the device
+// address that hipGetSymbolAddress gives once per device (g_noalloc_ptr),
+// never the name.
+static __device__ __align__(256) char g_noalloc_scratch[IRF_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+// Once per device, with that device current: the device address of the array.
+irf_status noalloc_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(IRF_E_UNSUPPORTED, "device %d beyond %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return IRF_OK;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_noalloc_scratch));
+  if (e != hipSuccess || !p)
+    return fail(IRF_E_HIP, "hipGetSymbolAddress(no-alloc scratch) failed: %s", hipGetErrorString(e));
+  g_noalloc_ptr[device] = p;
+  return IRF_OK;
+}
+
+// The frame's scratch carved from `base` (null: sizes only) with the sizes
+// ensure_scratch gives the context's own buffers; returns the bytes used.
+int64_t noalloc_layout(const irf_ctx* c, char* base, FrameScratch* fs) {
+  const int64_t P = total_probes(c), R = total_rays(c);
+  const int nl = c->lights.n_dir + c->lights.n_point;
+  int64_t om = 0, nb = 0, wbytes = 0;
+  for (int v = 0; v < c->n_vol; v++) {
+    om += c->vol[v].rays;
+    nb += (c->vol[v].n_probes + 1023) / 1024;
+    wbytes += 256ll * c->vol[v].rays * 4;
+  }
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) -> char* {
+    char* q = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return q;
+  };
+  FrameScratch f;
+  memset(&f, 0, sizeof(f));
+  f.params = (FrameParams*)take(sizeof(FrameParams));
+  f.active = (int32_t*)take(sizeof(int32_t) * P);
+  f.probe_pos = (float4*)take(sizeof(float4) * (P > 0 ? P : 1));
+  f.block_active = (int32_t*)take(sizeof(int32_t) * (nb > 0 ? nb : 1));
+  f.counters = (FrameCounters*)take(sizeof(FrameCounters));
+  f.omega = (float4*)take(sizeof(float4) * om);
+  f.hits = (HitRec*)take(sizeof(HitRec) * R);
+  f.vis = (uint8_t*)take(R * (int64_t)(nl > 0 ? nl : 1));
+  f.rays = (float4*)take(sizeof(float4) * R);
+  f.shadow_tasks = (float4*)take(sizeof(float4) * kTaskRegions * task_region_cap(R, nl > 0 ? nl : 1));
+  f.weights = take(wbytes > 0 ? wbytes : 16);
+  f.inv_row_sum = (float*)take(sizeof(float) * 256 * (c->n_vol > 0 ? c->n_vol : 1));
+  f.max_rays = R;
+  f.max_slots = (int32_t)P;
+  if (fs) *fs = f;
+  return off;
 }
 
 // Hash of everything a captured frame bakes into its nodes.
@@ -465,6 +532,8 @@ irf_status irf_create(int32_t hip_device, irf_ctx** out) {
   if (e != hipSuccess || n <= 0) return fail(IRF_E_HIP, "no HIP device available");
   if (hip_device < 0 || hip_device >= n) return fail(IRF_E_INVALID, "device %d out of range [0, %d)", hip_device, n);
   HIP_TRY(hipSetDevice(hip_device));
+  irf_status ns = noalloc_setup(hip_device);
+  if (ns != IRF_OK) return ns;
   irf_ctx* c = new (std::nothrow) irf_ctx();
   if (!c) return fail(IRF_E_NOMEM, "context allocation failed");
   c->device = hip_device;
@@ -914,6 +983,38 @@ irf_status irf_update_probes_after(irf_ctx* c, const float* rotation, void* stre
 
 irf_status irf_update_probes(irf_ctx* c, const float* rotation, void* stream) {
   return irf_update_probes_after(c, rotation, stream, nullptr);
+}
+
+irf_status irf_update_probes_noalloc(irf_ctx* c, const float* rotation, void* stream) {
+  if (!c || !rotation) return fail(IRF_E_INVALID, "NULL argument");
+  for (int i = 0; i < 9; i++)
+    if (!std::isfinite(rotation[i])) return fail(IRF_E_INVALID, "rotation is not finite");
+  irf_status s = check_ready(c);
+  if (s != IRF_OK) return s;
+  if (c->diff)
+    return fail(IRF_E_UNSUPPORTED, "the no-alloc frame does not save a differentiable frame's inputs");
+  const int64_t need = noalloc_layout(c, nullptr, nullptr);
+  if (need > IRF_NOALLOC_SCRATCH_BYTES)
+    return fail(IRF_E_UNSUPPORTED, "the frame needs %lld bytes of scratch; the no-alloc scratch holds %lld",
+                (long long)need, (long long)IRF_NOALLOC_SCRATCH_BYTES);
+  if ((s = set_device(c)) != IRF_OK) return s;
+  void* base = c->device >= 0 && c->device < kMaxDevices ? g_noalloc_ptr[c->device] : nullptr;
+  if (!base) return fail(IRF_E_STATE, "no-alloc scratch not set up on device %d", c->device);
+  FrameScratch fs;
+  noalloc_layout(c, (char*)base, &fs);
+  // the coherent ray order is a library-owned table: traced in index order
+  // here (only the lane a ray runs on changes, no result)
+  VolumeSet vs = volume_view(c);
+  for (int v = 0; v < vs.n; v++) vs.v[v].order = nullptr;
+  const bool prof = c->prof;
+  c->prof = false;   // kernel timing would create events
+  hipError_t e = enqueue_frame_on(c, rotation, (hipStream_t)stream, nullptr, vs, fs);
+  c->prof = prof;
+  if (e != hipSuccess) return fail(IRF_E_HIP, "enqueueing the frame: %s", hipGetErrorString(e));
+  // the context's own scratch does not hold this frame: no records or stats
+  c->frame_done = false;
+  c->diff_frame = false;
+  return launched();
 }
 
 irf_status irf_query_irradiance(irf_ctx* c, const float* pos, const float* nrm, const float* view, int64_t n,

@@ -84,6 +84,7 @@ SIGNATURES = {
     "irf_classify": (C.c_int, [_vp, _vp, _i32, _vp]),
     "irf_update_probes": (C.c_int, [_vp, _vp, _vp]),
     "irf_update_probes_after": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "irf_update_probes_noalloc": (C.c_int, [_vp, _vp, _vp]),
     "irf_query_irradiance": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp]),
     "irf_ray_records": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(_i64), _vp]),
     "irf_frame_stats": (C.c_int, [_vp, C.POINTER(_i64 * 4), _vp]),
@@ -299,6 +300,13 @@ class Context:
         else:
             _check(load().irf_update_probes_after(self.handle, _ptr(R), _stream(self.torch),
                                                   C.c_void_p(after.cuda_event)))
+        self.frames += 1
+
+    def update_probes_noalloc(self, rotation) -> None:
+        """One update frame that allocates nothing (its scratch is the
+        library's static per-GPU array; see irf_update_probes_noalloc)."""
+        R = _np(rotation, np.float32).reshape(9)
+        _check(load().irf_update_probes_noalloc(self.handle, _ptr(R), _stream(self.torch)))
         self.frames += 1
 
     def query_irradiance(self, pos, nrm, view, out=None):
