@@ -296,13 +296,20 @@ irf_status irf_query_irradiance(irf_ctx* ctx, const float* pos, const float* nrm
    starts at 0 except for the shadow rays: 16 workgroups per compute unit,
    what stays resident at once at eight waves per SIMD, each lane looping
    over the frame's tasks, instead of a workgroup for every shadow ray the
-   largest frame could queue (most of them empty).  Values are normally
-   chosen by the autotuner (paper_2009_10796_amd/autotune.py). */
+   largest frame could queue (most of them empty).  shadow_refill selects
+   how the shadow rays are spread over lanes: 0 in batches of 64 tasks (a
+   wave moves on when the longest ray of its batch ends); n in [1, 64] a
+   fixed range of tasks per wave whose lanes take the range's next task
+   whenever at least n of them are idle.  Results do not depend on any of
+   these.  Values are normally chosen by the autotuner
+   (paper_2009_10796_amd/autotune.py).  IRF_E_INVALID for negative values or
+   shadow_refill above 64. */
 typedef struct {
   int32_t trace_blocks;
   int32_t shadow_blocks;
   int32_t shade_blocks;
   int32_t blend_blocks;
+  int32_t shadow_refill;
 } irf_tuning;
 irf_status irf_set_tuning(irf_ctx* ctx, const irf_tuning* tuning);
 irf_status irf_get_tuning(const irf_ctx* ctx, irf_tuning* tuning);

@@ -2,10 +2,12 @@
 
 For each persistent kernel of the update (probe-ray traversal, shadow-ray
 traversal, hit shading, matrix-core blend) it times a set of grid sizes
-(multiples of the compute-unit count, plus 0 = one workgroup per work unit)
-on the live workload, with the library's own kernel timing, and keeps the
-fastest.  The choice is returned as a dict, can be saved as JSON and applied
-to another context with ``apply``.  Tuning runs real frames: call it during
+(multiples of the compute-unit count, plus 0 = one workgroup per work unit),
+and for the shadow rays how their tasks are spread over lanes (batches of
+64, or per-wave ranges with lane refill at an idle-lane threshold), on the
+live workload with the library's own kernel timing, and keeps the fastest.
+The choice is returned as a dict, can be saved as JSON and applied to
+another context with ``apply``.  Tuning runs real frames: call it during
 warm-up.
 """
 from __future__ import annotations
@@ -14,11 +16,17 @@ import json
 import os
 from typing import Dict, Iterable, Optional
 
-KNOBS = (("trace_blocks", "trace"), ("shadow_blocks", "shadow"), ("shade_blocks", "shade"),
-         ("blend_blocks", "blend_mma"))
+SHADOW = ("shadow", "shadow_refill")   # the kernel the shadow rays run on, by refill mode
+KNOBS = (("trace_blocks", ("trace",)), ("shadow_refill", SHADOW), ("shadow_blocks", SHADOW),
+         ("shade_blocks", ("shade",)), ("blend_blocks", ("blend_mma",)))
 
 
-def candidates(cu: int) -> list:
+def candidates(cu: int, knob: str = "trace_blocks") -> list:
+    """Values tried for one knob: grid sizes (0 = one workgroup per work
+    unit, else multiples of the compute-unit count), or for the shadow rays'
+    lane refill the idle-lane threshold (0 = batches of 64)."""
+    if knob == "shadow_refill":
+        return [0, 4, 8, 16, 32]
     return [0] + [cu * k for k in (1, 2, 4, 8, 16)]
 
 
@@ -33,9 +41,9 @@ def autotune(ctx, rotations: Iterable, frames_per_candidate: int = 3, cu: Option
     rot = iter(rotations)
     chosen = {}
     report = {}
-    for knob, kernel in KNOBS:
+    for knob, kernels in KNOBS:
         times = {}
-        for c in candidates(cu):
+        for c in candidates(cu, knob):
             ctx.set_tuning(**{knob: c})
             step(next(rot))                       # settle
             torch.cuda.synchronize()
@@ -46,10 +54,10 @@ def autotune(ctx, rotations: Iterable, frames_per_candidate: int = 3, cu: Option
             torch.cuda.synchronize()
             prof = ctx.profile_read(reset=True)
             ctx.profile(False)
-            if kernel not in prof:
+            ran = [prof[k] for k in kernels if k in prof]
+            if not ran:
                 break
-            n, ms = prof[kernel]
-            times[c] = ms / n
+            times[c] = sum(ms for _, ms in ran) / max(n for n, _ in ran)
         if times:
             best = min(times, key=times.get)
             ctx.set_tuning(**{knob: best})

@@ -104,7 +104,7 @@ struct irf_ctx {
   DevBuf<unsigned long long> reloc_keys;
   bool frame_done = false;
   bool diff_frame = false;   // the last frame saved its inputs for the adjoint
-  Tuning tune = {0, 0, 0, 0};
+  Tuning tune = {0, 0, 0, 0, 0};
   // adjoint: the frame's input atlases and states, saved by each update
   bool diff = false;
   DevBuf<char> saved;
@@ -289,7 +289,6 @@ FrameScratch scratch_view(const irf_ctx* c) {
   f.probe_pos = c->probe_pos.p;
   f.weights = c->weights.p;
   f.inv_row_sum = c->inv_row_sum.p;
-  f.rays_lp = nullptr;
   f.max_rays = total_rays(c);
   f.max_slots = (int32_t)total_probes(c);
   return f;
@@ -388,7 +387,8 @@ hipError_t enqueue_frame_on(irf_ctx* c, const float* rotation, hipStream_t st, h
   }
   { ProfScope p(c, "trace", st); launch_trace(vs, sc, fs, c->tune.trace_blocks, st); }
   if (nl > 0) {
-    { ProfScope p(c, "shadow", st); launch_shadow(vs, sc, nl, fs, c->tune.shadow_blocks, st); }
+    ProfScope p(c, c->tune.shadow_refill > 0 ? "shadow_refill" : "shadow", st);
+    launch_shadow(vs, sc, nl, fs, c->tune.shadow_blocks, c->tune.shadow_refill, st);
   }
   { ProfScope p(c, "shade", st); launch_shade(vs, sc, fs, c->tune.shade_blocks, st); }
   if (atlas_wait) {
@@ -1094,10 +1094,13 @@ irf_status irf_set_tuning(irf_ctx* c, const irf_tuning* t) {
   if (!c || !t) return fail(IRF_E_INVALID, "NULL argument");
   if (t->trace_blocks < 0 || t->shadow_blocks < 0 || t->shade_blocks < 0 || t->blend_blocks < 0)
     return fail(IRF_E_INVALID, "tuning values must be >= 0");
+  if (t->shadow_refill < 0 || t->shadow_refill > 64)
+    return fail(IRF_E_INVALID, "shadow_refill must be in [0, 64]");
   c->tune.trace_blocks = t->trace_blocks;
   c->tune.shadow_blocks = t->shadow_blocks;
   c->tune.shade_blocks = t->shade_blocks;
   c->tune.blend_blocks = t->blend_blocks;
+  c->tune.shadow_refill = t->shadow_refill;
   return IRF_OK;
 }
 
@@ -1107,6 +1110,7 @@ irf_status irf_get_tuning(const irf_ctx* c, irf_tuning* t) {
   t->shadow_blocks = c->tune.shadow_blocks;
   t->shade_blocks = c->tune.shade_blocks;
   t->blend_blocks = c->tune.blend_blocks;
+  t->shadow_refill = c->tune.shadow_refill;
   return IRF_OK;
 }
 

@@ -98,6 +98,7 @@ struct Tuning {
   int32_t shadow_blocks;
   int32_t shade_blocks;
   int32_t blend_blocks;
+  int32_t shadow_refill;   // 0: shadow rays in batches of 64; n > 0: lane refill at n idle lanes
 };
 
 // Dynamic-object boxes (state step and classification wake rule).
@@ -175,7 +176,6 @@ struct FrameScratch {
                             // w = 1 for a Newly state (blended with no hysteresis), else 0
   void* weights;            // per volume: 256 weight rows x rays (float32 [k][row] or 16-bit [row][k])
   float* inv_row_sum;       // [n_volumes][256] 1 / sum of the stored weights of each row (0 = none)
-  void* rays_lp;            // [max_rays] 4 x bf16/f16 (matrix-core path)
   int64_t max_rays;
   int32_t max_slots;
 };
@@ -206,7 +206,8 @@ FrameBegin make_frame_begin(const FrameParams& p, const VolumeSet& vs, ObjectBox
 void launch_frame_begin(const FrameBegin& a, hipStream_t s);
 const void* frame_begin_kernel();
 void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s);
-void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, hipStream_t s);
+void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, int refill,
+                   hipStream_t s);
 void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s);
 void launch_blend(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
 void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, int grid, hipStream_t s);

@@ -170,17 +170,18 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
     for (int e = threadIdx.x; e < kPB * (kpad - kn); e += kBlendMmaBlock) {
       const int p = e / (kpad - kn), k = kn + e % (kpad - kn);
 #pragma unroll
-      for (int c = 0; c < 6; c++) store_b<MODE>(lds, k, 8 * c + p, 0.0f);
+      for (int c = 0; c < 6; c++)
+        if (c != 3) store_b<MODE>(lds, k, 8 * c + p, 0.0f);
     }
     for (int e = threadIdx.x; e < kPB * kn; e += kBlendMmaBlock) {
       int p = e / kn, k = e - p * kn;
       float4 r = p < np ? rays[(int64_t)p * N + kc + k] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      // columns: R of probe p at p, G at 8 + p, B at 16 + p (zeros at 24 + p),
-      // so one lane of the epilogue holds R and B of a texel and G is 8 lanes up
+      // columns: R of probe p at p, G at 8 + p, B at 16 + p (24..31 stay
+      // zero from the kernel's start), so one lane of the epilogue holds R and
+      // B of a texel and G is 8 lanes up
       store_b<MODE>(lds, k, p, r.x);
       store_b<MODE>(lds, k, 8 + p, r.y);
       store_b<MODE>(lds, k, 16 + p, r.z);
-      store_b<MODE>(lds, k, 24 + p, 0.0f);
       store_b<MODE>(lds, k, 32 + p, r.w);
       store_b<MODE>(lds, k, 40 + p, r.w * r.w);
     }
@@ -287,7 +288,11 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
 }
 
 // Persistent over work items (probe block x row split) of every volume whose
-// blend mode is MODE.
+// blend mode is MODE.  Workgroups are dispatched to the 8 XCDs round robin
+// (XCD = workgroup id mod 8) and the grid is a multiple of 8, so item wi runs
+// on XCD wi mod 8; item wi is split (wi / 8) mod kRSplit of probe block
+// (wi / (8 kRSplit)) * 8 + wi mod 8, which puts the kRSplit items of a block --
+// the same rays staged kRSplit times -- on one XCD, and on one L2.
 template <int MODE>
 __global__ __launch_bounds__(kBlendMmaBlock) void k_blend_mma(VolumeSet vs, FrameScratch fs) {
   constexpr int LDS_BYTES = MODE == IRF_BLEND_F32 ? kKC * kBfStride * 4 : 48 * kBtStride * 2;
@@ -295,18 +300,24 @@ __global__ __launch_bounds__(kBlendMmaBlock) void k_blend_mma(VolumeSet vs, Fram
   __shared__ int s_q[kPB];
   __shared__ bool s_fresh[kPB];
   const FrameCounters& C = *fs.counters;
-  int item_base[IRF_MAX_VOLUMES + 1];
-  item_base[0] = 0;
+  int block_base[IRF_MAX_VOLUMES + 1];
+  block_base[0] = 0;
   for (int v = 0; v < vs.n; v++) {
     int count = vs.v[v].blend == MODE ? C.slot_base[v + 1] - C.slot_base[v] : 0;
-    item_base[v + 1] = item_base[v] + (count + kPB - 1) / kPB * kRSplit;
+    block_base[v + 1] = block_base[v] + (count + kPB - 1) / kPB;
   }
-  for (int wi = blockIdx.x; wi < item_base[vs.n]; wi += gridDim.x) {
+  // B columns 24..31 (the irradiance tiles' unused half) are zero for the
+  // whole kernel; the staging never writes them
+  for (int e = threadIdx.x; e < kKC * 8; e += kBlendMmaBlock) store_b<MODE>(lds, e / 8, 24 + e % 8, 0.0f);
+  const int blocks = block_base[vs.n];
+  const int items = (blocks + 7) / 8 * 8 * kRSplit;
+  for (int wi = blockIdx.x; wi < items; wi += gridDim.x) {
+    const int b = (wi / (8 * kRSplit)) * 8 + (wi & 7);
+    if (b >= blocks) continue;
     int v = 0;
-    while (v + 1 < vs.n && wi >= item_base[v + 1]) v++;
-    const int local = wi - item_base[v];
+    while (v + 1 < vs.n && b >= block_base[v + 1]) v++;
     __syncthreads();   // the previous item's epilogue has finished with s_q / s_fresh
-    blend_item<MODE>(vs, fs, C, v, local / kRSplit, local % kRSplit, lds, s_q, s_fresh);
+    blend_item<MODE>(vs, fs, C, v, b - block_base[v], (wi / 8) % kRSplit, lds, s_q, s_fresh);
   }
 }
 
@@ -318,7 +329,11 @@ void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, int grid, hipStream_
     if (vs.v[v].blend <= IRF_BLEND_F16) mode_present[vs.v[v].blend] = true;
   }
   if (full == 0) return;
-  const unsigned g = (unsigned)(grid > 0 && grid < full ? grid : full);
+  // items of probe blocks rounded up to groups of 8 (see k_blend_mma); a grid
+  // that is a multiple of 8 keeps each block's row splits on one XCD
+  full = (full + 8 * kRSplit - 1) / (8 * kRSplit) * (8 * kRSplit);
+  const int want = grid > 0 && grid < full ? grid : full;
+  const unsigned g = (unsigned)((want + 7) / 8 * 8);
   if (mode_present[IRF_BLEND_F32])
     irf_launch(k_blend_mma<IRF_BLEND_F32>, dim3(g), dim3(kBlendMmaBlock), 0, s, vs, fs);
   if (mode_present[IRF_BLEND_BF16])

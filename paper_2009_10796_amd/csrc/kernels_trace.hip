@@ -454,6 +454,117 @@ __global__ __launch_bounds__(kTraceBlock) void k_shadow(VolumeSet vs, SceneGPU s
   }
 }
 
+// Any-hit shadow rays with lane refill.  Each wave owns one contiguous range
+// of the dense task order, fixed by its index (no atomics); a lane whose ray
+// has ended takes the range's next task at the next refill, so the wave's
+// lanes stay busy until its range runs out, instead of waiting at every
+// batch of 64 for the longest ray of the batch (after the persistent
+// while-while traversal with replacement of terminated rays, Aila and Laine
+// 2009).  A refill runs when at least `refill` lanes are idle (every lane
+// of the wave takes part in it: the task index search reads other lanes).
+// Each pass of the loop takes every active lane through its inner nodes to
+// the next leaf (or the end), then that leaf's triangles.
+__global__ __launch_bounds__(kTraceBlock) void k_shadow_refill(VolumeSet vs, SceneGPU sc, FrameScratch fs,
+                                                               int refill) {
+  const FrameCounters& C = *fs.counters;
+  const LightSet& L = fs.params->L;
+  int64_t total;
+  const int64_t before = tasks_before_region(C, total);
+  const int64_t cap = task_region_cap(fs.max_rays, L.n_dir + L.n_point);
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (kTraceBlock / 64);
+  const int64_t wave = (int64_t)blockIdx.x * (kTraceBlock / 64) + (threadIdx.x >> 6);
+  const int64_t per = (total + waves - 1) / waves;
+  int64_t next = wave * per;                  // the range's next task (same on every lane)
+  const int64_t end = min(total, next + per);
+  int* stack = dyn_stack + threadIdx.x;
+  const int stride = kTraceBlock;
+  bool active = false;
+  Ray ray;
+  float tmax = 0.0f;
+  int node = 0, sp = 0;
+  int64_t out = 0;                            // visibility byte of the lane's task
+  while (true) {
+    const unsigned long long idle = __ballot(!active);
+    const int n_idle = __popcll(idle);
+    if (next < end && (n_idle >= refill || n_idle == 64)) {
+      const int rank = __popcll(idle & ((1ull << lane) - 1ull));
+      const int64_t k = next + rank;
+      const bool take = !active && k < end;
+      const int64_t slot = task_index(before, take ? k : next, cap);
+      if (take) {
+        const float4 task = fs.shadow_tasks[slot];
+        const uint32_t word = __float_as_uint(task.w);
+        const int l = word & 31;
+        const float3 Xs = f3(task.x, task.y, task.z);
+        out = (int64_t)l * fs.max_rays + (int64_t)(word >> 5);
+        if (l < L.n_dir) {
+          ray = make_ray(Xs, f3(L.dir[l][0], L.dir[l][1], L.dir[l][2]));
+          tmax = INFINITY;
+        } else {
+          // a point light's segment from the light (as in k_shadow)
+          const int p = l - L.n_dir;
+          const float3 P = f3(L.pos[p][0], L.pos[p][1], L.pos[p][2]);
+          const float3 u = P - Xs;
+          const float dist = length(u);
+          const float3 dl = (1.0f / dist) * u;
+          tmax = dist;
+          ray = make_ray(P, f3(-dl.x, -dl.y, -dl.z));
+        }
+        node = sc.n_nodes > 0 ? 0 : kTraversalDone;
+        sp = 0;
+        active = true;
+      }
+      next += min((int64_t)n_idle, end - next);
+    }
+    if (__ballot(active) == 0) break;        // the range is used up (a refill of 64 idle lanes takes a task)
+    if (!active) continue;
+    // inner nodes to the next leaf (the step of traverse<>)
+    while (node >= 0) {
+      const float4* np = sc.nodes + (size_t)node * 4;
+      float4 n0 = np[0], n1 = np[1], n2 = np[2], n3 = np[3];
+      float t0, t1;
+      const bool h0 = box_hit(ray, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tmax, t0);
+      const bool h1 = box_hit(ray, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tmax, t1);
+      const int l0 = bits_i(n3.x), l1 = bits_i(n3.y);
+      const bool first0 = h0 & (!h1 | (t0 <= t1));
+      const int nearc = first0 ? l0 : l1;
+      const int farc = first0 ? l1 : l0;
+      const int top = sp < sc.stack_depth - 1 ? sp : sc.stack_depth - 1;
+      stack[top * stride] = farc;
+      sp = top + ((h0 && h1) ? 1 : 0);
+      const int below = sp > 0 ? sp - 1 : 0;
+      const int popped = stack[below * stride];
+      const bool any = h0 || h1;
+      node = any ? nearc : (sp == 0 ? kTraversalDone : popped);
+      sp = any ? sp : below;
+    }
+    bool done = node == kTraversalDone, hit = false;
+    if (!done) {
+      const int code = ~node;
+      const int first = code >> 3, count = (code & 7) + 1;
+      for (int i = first; i < first + count; i++) {
+        const float4* tp = sc.tris + (size_t)i * 3;
+        float t;
+        if (tri_hit(ray, tp[0], tp[1], tp[2], tmax, t)) {
+          hit = true;
+          break;
+        }
+      }
+      if (hit || sp == 0) {
+        done = true;
+      } else {
+        sp--;
+        node = stack[sp * stride];
+      }
+    }
+    if (done) {
+      if (!hit) fs.vis[out] = 1;
+      active = false;
+    }
+  }
+}
+
 // Radiance and distance carried by each probe ray (backface rule of the
 // self-shadow-bias section: radiance 0, distance shortened by 80 %).
 __device__ __forceinline__ void shade_one(const VolumeSet& vs, const SceneGPU& sc, const LightSet& L,
@@ -952,10 +1063,14 @@ void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, h
   irf_launch(k_trace, dim3(grid_for(fs.max_rays, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs);
 }
 
-void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, hipStream_t s) {
+void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, int refill,
+                   hipStream_t s) {
   if (fs.max_rays == 0 || n_lights == 0) return;
   int64_t cap = (fs.max_rays + 63) / 64 * 64 * n_lights;
-  irf_launch(k_shadow, dim3(grid_for(cap, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs);
+  if (refill > 0)
+    irf_launch(k_shadow_refill, dim3(grid_for(cap, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs, refill);
+  else
+    irf_launch(k_shadow, dim3(grid_for(cap, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs);
 }
 
 void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s) {

@@ -36,18 +36,28 @@ def test_persistent_grids_match_default(torch):
     B = irf.build_workload(w)
     # tiny persistent grids: every workgroup loops over many work items
     B.set_tuning(trace_blocks=7, shadow_blocks=5, shade_blocks=3, blend_blocks=2)
-    for c in (A, B):
+    # shadow rays by lane refill: per-wave task ranges, refilled at 1, 13 or
+    # 64 idle lanes, on grids from one wave's worth to many
+    Cs = []
+    for refill, grid in ((1, 3), (13, 64), (64, 0)):
+        c = irf.build_workload(w)
+        c.set_tuning(shadow_refill=refill, shadow_blocks=grid)
+        Cs.append(c)
+    for c in (A, B, *Cs):
         c.classify(w.classify_rotations)
     for f in (1, 2, 3):
         L = S.sun_for_frame(f)
         R = w.frame_rotation(f)
-        for c in (A, B):
+        for c in (A, B, *Cs):
             c.set_lights(L)
             c.update_probes(R)
         torch.cuda.synchronize()
-        assert _same(_snapshot(A), _snapshot(B)), f
-    A.close()
-    B.close()
+        a = _snapshot(A)
+        assert _same(a, _snapshot(B)), f
+        for c in Cs:
+            assert _same(a, _snapshot(c)), (f, c.get_tuning())
+    for c in (A, B, *Cs):
+        c.close()
 
 
 @pytest.mark.parametrize("size", ["1024 probes", "8192 probes"])
@@ -100,7 +110,7 @@ def test_autotuner_keeps_results(torch):
         c.classify(w.classify_rotations)
         c.set_lights(S.sun_for_frame(0))
     chosen = autotune.autotune(B, S.rotations(3, 200, start_frame=100), frames_per_candidate=1)
-    assert set(chosen) == {"trace_blocks", "shadow_blocks", "shade_blocks", "blend_blocks"}
+    assert set(chosen) == {"trace_blocks", "shadow_refill", "shadow_blocks", "shade_blocks", "blend_blocks"}
     # after tuning, the same frames from the same state agree with the default launch shapes
     for c in (A, B):
         for v in c.volumes:
