@@ -43,9 +43,11 @@ COUNTER_FILES = {"city": os.path.join(ROOT, "profiles", "city-16x8x16-256rays_co
                  "terrain": os.path.join(ROOT, "profiles", "terrain-4x32x16x32-192rays_counters.md")}
 # kernel symbol -> bench key (longer names first: k_shadow_refill before k_shadow)
 KERNEL_KEYS = (("k_shadow_refill", "shadow_refill"), ("k_shadow_count", "shadow_count"), ("k_shadow", "shadow"),
-               ("k_trace_count", "trace_count"), ("k_trace", "trace"), ("k_shade_backward", "shade_backward"),
+               ("k_trace_count", "trace_count"), ("k_trace", "trace"), ("k_shade_terms", "shade_terms"),
                ("k_shade", "shade"), ("k_blend_mma", "blend_mma"), ("k_blend_f32", "blend_valu"),
-               ("k_blend_backward", "blend_backward"), ("k_query_backward", "query_backward"), ("k_query", "query"),
+               ("k_blend_backward", "blend_backward"), ("k_query_terms", "query_terms"), ("k_query", "query"),
+               ("k_gather_pieces", "gather_pieces"), ("k_finish_pieces", "finish_pieces"),
+               ("k_piece_offsets", "piece_offsets"), ("k_blend_norms", "blend_norms"), ("k_segments", "segments"),
                ("k_frame_begin", "frame_begin"), ("k_state_count", "state_count"),
                ("k_state_scatter", "state_scatter"), ("k_glossy", "glossy"))
 # the sources of the frame and query kernels: a change to any of them voids
@@ -695,7 +697,7 @@ def main():
     nrm = torch.from_numpy(q.nrm).cuda()
     view = torch.from_numpy(q.view).cuda()
     out = torch.empty_like(pos)
-    R = S.rotations(w.config, 1 + args.warmup + 3 * args.steps, start_frame=1)
+    R = S.rotations(w.config, 1 + 2 * max(1, args.warmup) + 3 * args.steps, start_frame=1)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
     print(f"[bench] setup {setup_s:.1f}s, {w.scene.n_triangles} triangles, {q.n} queries", file=sys.stderr, flush=True)
@@ -713,6 +715,10 @@ def main():
     torch.cuda.synchronize()
     with torch.cuda.stream(s):
         graph = ctx.capture_frame(s)
+        for _ in range(max(1, args.warmup)):     # replays warm up like the eager steps
+            graph.launch(R[f])
+            ctx.query_irradiance(pos, nrm, view, out)
+            f += 1
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with torch.cuda.stream(s):

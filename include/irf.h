@@ -342,12 +342,21 @@ irf_status irf_set_differentiable(irf_ctx* ctx, int32_t enable);
 /* Replaces the materials' emitted radiance from a device array [n_materials][3]. */
 irf_status irf_set_emission(irf_ctx* ctx, const float* emission, void* stream);
 /* dLoss/d(atlases) of irf_query_irradiance at the same points given
-   grad_out = dLoss/dE [n][3] (device); reads the current atlases. */
+   grad_out = dLoss/dE [n][3] (device); reads the current atlases.  Adds
+   (+=) into grad_irr[v] / grad_dist[v] (device, the layout of the volume's
+   atlases).  Each texel's terms are summed in point order without atomics,
+   so the result is the same bit for bit from call to call; the terms go
+   through library memory (about 0.25 GB, allocated on the first call) in
+   batches of 2^22 / (8 x volumes) points. */
 irf_status irf_query_backward(irf_ctx* ctx, const float* pos, const float* nrm, const float* view, int64_t n,
                               const float* grad_out, float* const* grad_irr, float* const* grad_dist, void* stream);
 /* Backward of the last update frame: from dLoss/d(output atlases) to
-   dLoss/d(input atlases) and dLoss/d(emission) [n_materials][3].  The blend
-   is differentiated with float32 weights whatever the forward blend mode. */
+   dLoss/d(input atlases) and dLoss/d(emission) [n_materials][3], all added
+   (+=) into the caller's device arrays.  The blend is differentiated with
+   float32 weights whatever the forward blend mode.  Gradients are summed in
+   a fixed order (texels: ray order; emitters: ray order per material), so
+   they are the same bit for bit from call to call.  Reads the frame's ray
+   count back to the host (synchronizes `stream`). */
 irf_status irf_update_backward(irf_ctx* ctx, float* const* grad_new_irr, float* const* grad_new_dist,
                                float* const* grad_prev_irr, float* const* grad_prev_dist, float* grad_emission,
                                void* stream);

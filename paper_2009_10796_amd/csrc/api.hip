@@ -111,6 +111,7 @@ struct irf_ctx {
   int64_t saved_irr[IRF_MAX_VOLUMES], saved_dist[IRF_MAX_VOLUMES], saved_states[IRF_MAX_VOLUMES];
   DevBuf<float4> grad_rays;
   DevBuf<float4> probe_pos;
+  DevBuf<char> adj;        // the adjoint's term buffers, segments and sort storage
   // kernel timing
   bool prof = false;
   struct ProfRec {
@@ -572,6 +573,7 @@ void irf_destroy(irf_ctx* c) {
   c->saved.release();
   c->grad_rays.release();
   c->probe_pos.release();
+  c->adj.release();
   c->weights.release();
   c->inv_row_sum.release();
   c->class_back.release();
@@ -1176,6 +1178,15 @@ irf_status irf_graph_capture(irf_ctx* c, void* stream, irf_graph** out) {
     delete g;
     return fail(IRF_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
   }
+  // the executable graph goes to the device now: otherwise its first launch
+  // pays the upload (about 0.8 ms for the city frame, measured)
+  e = hipGraphUpload(g->exec, st);
+  if (e != hipSuccess) {
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(graph);
+    delete g;
+    return fail(IRF_E_HIP, "hipGraphUpload: %s", hipGetErrorString(e));
+  }
   g->signature = frame_signature(c);
   *out = g;
   return IRF_OK;
@@ -1257,6 +1268,50 @@ static irf_status grad_set(const irf_ctx* c, float* const* irr, float* const* di
   return IRF_OK;
 }
 
+// Terms of one batch of the adjoint's gradient sums: 2^22 (168 MB of terms,
+// 48 MB of keys and sorted order); a frame's rays or a query's points go through
+// in batches of that many terms.
+constexpr int64_t kAdjTerms = 1ll << 22;
+
+static irf_status adjoint_scratch(irf_ctx* c, AdjointScratch& A) {
+  int64_t K = c->n_materials > 0 ? c->n_materials : 0;
+  for (int v = 0; v < c->n_vol; v++) K += c->vol[v].n_probes;
+  if (K < 1) K = 1;
+  const int64_t slots = adjoint_partial_slots(kAdjTerms);
+  const size_t sort_bytes = adjoint_sort_bytes(kAdjTerms);
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t T4 = up(4 * (size_t)kAdjTerms), K4 = up(4 * (size_t)(K + 1));
+  const size_t sizes[] = {up(40 * (size_t)kAdjTerms), T4, T4, T4, K4, K4, K4, K4,
+                          up(adjoint_slot_bytes() * (size_t)slots),
+                          up(sizeof(float) * (size_t)adjoint_norms_per_volume() * IRF_MAX_VOLUMES), up(sort_bytes)};
+  constexpr int kParts = sizeof(sizes) / sizeof(sizes[0]);
+  size_t total = 0;
+  for (size_t b : sizes) total += b;
+  irf_status s = c->adj.reserve(total);
+  if (s != IRF_OK) return s;
+  char* q = c->adj.p;
+  void* part[kParts];
+  for (int i = 0; i < kParts; i++) {
+    part[i] = q;
+    q += sizes[i];
+  }
+  A.terms = part[0];
+  A.keys[0] = (uint32_t*)part[1];
+  A.keys[1] = (uint32_t*)part[2];
+  A.idx = (uint32_t*)part[3];
+  A.seg_start = (uint32_t*)part[4];
+  A.seg_end = (uint32_t*)part[5];
+  A.offs = (uint32_t*)part[6];
+  A.poffs = (uint32_t*)part[7];
+  A.partial = (float*)part[8];
+  A.norms = (float*)part[9];
+  A.sort_temp = part[10];
+  A.sort_bytes = sort_bytes;
+  A.max_terms = kAdjTerms;
+  A.max_partial = slots;
+  return IRF_OK;
+}
+
 irf_status irf_query_backward(irf_ctx* c, const float* pos, const float* nrm, const float* view, int64_t n,
                               const float* grad_out, float* const* grad_irr, float* const* grad_dist, void* stream) {
   if (!c) return fail(IRF_E_INVALID, "ctx is NULL");
@@ -1268,7 +1323,9 @@ irf_status irf_query_backward(irf_ctx* c, const float* pos, const float* nrm, co
   GradSet G;
   if ((s = grad_set(c, grad_irr, grad_dist, G)) != IRF_OK) return s;
   if ((s = set_device(c)) != IRF_OK) return s;
-  launch_query_backward(volume_view(c), pos, nrm, view, n, grad_out, G, (hipStream_t)stream);
+  AdjointScratch A;
+  if ((s = adjoint_scratch(c, A)) != IRF_OK) return s;
+  HIP_TRY(launch_query_backward(volume_view(c), pos, nrm, view, n, grad_out, G, A, (hipStream_t)stream));
   return launched();
 }
 
@@ -1287,7 +1344,15 @@ irf_status irf_update_backward(irf_ctx* c, float* const* g_new_irr, float* const
     prev.v[v].dist = c->saved.p + c->saved_dist[v];
     prev.v[v].states = (uint8_t*)(c->saved.p + c->saved_states[v]);
   }
-  launch_update_backward(prev, scene_view(c), scratch_view(c), Gn, Gp, g_emission, (hipStream_t)stream);
+  AdjointScratch A;
+  if ((s = adjoint_scratch(c, A)) != IRF_OK) return s;
+  // the frame's ray count bounds the batches (most probes of a sparse frame
+  // trace nothing)
+  FrameCounters fc;
+  HIP_TRY(hipMemcpyAsync(&fc, c->counters.p, sizeof(fc), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  HIP_TRY(launch_update_backward(prev, scene_view(c), scratch_view(c), Gn, Gp, g_emission, c->n_materials,
+                                 fc.ray_base[c->n_vol], A, (hipStream_t)stream));
   return launched();
 }
 

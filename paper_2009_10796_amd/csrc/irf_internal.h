@@ -229,10 +229,36 @@ void launch_traversal_stats(const VolumeSet& vs, SceneGPU sc, int n_lights, Fram
 struct GradSet;
 void launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t s);
 void launch_set_emission(const float* src, float4* dst, int m, hipStream_t s);
-void launch_query_backward(const VolumeSet& vs, const float* pos, const float* nrm, const float* view, int64_t n,
-                           const float* gout, const GradSet& G, hipStream_t s);
-void launch_update_backward(const VolumeSet& prev, SceneGPU sc, FrameScratch fs, const GradSet& Gnew,
-                            const GradSet& Gprev, float* g_emission, hipStream_t s);
+// Scratch of the adjoint's fixed-order gradient sums (library-owned): the
+// terms of one batch of query points or rays with their keys (before and
+// after the sort) and sorted order, segment bounds and piece offsets over keys
+// (probes, then materials), the stored sums of long segments, the blend's
+// per-volume normalisers and the sort's temporary storage.
+struct AdjointScratch {
+  void* terms;             // [max_terms] query terms (40 bytes each)
+  uint32_t* keys[2];       // [max_terms] before and after the sort
+  uint32_t* idx;           // [max_terms] sorted order (term positions)
+  uint32_t* seg_start;     // [max_keys]
+  uint32_t* seg_end;       // [max_keys]
+  uint32_t* offs;          // [max_keys + 1]
+  uint32_t* poffs;         // [max_keys + 1]
+  float* partial;          // [max_partial] stored piece sums
+  float* norms;            // [volumes][adjoint_norms_per_volume()]
+  void* sort_temp;
+  size_t sort_bytes;
+  int64_t max_terms;
+  int64_t max_partial;
+};
+size_t adjoint_sort_bytes(int64_t max_pairs);
+int64_t adjoint_partial_slots(int64_t max_terms);
+size_t adjoint_slot_bytes();
+int adjoint_norms_per_volume();
+hipError_t launch_query_backward(const VolumeSet& vs, const float* pos, const float* nrm, const float* view,
+                                 int64_t n, const float* gout, const GradSet& G, const AdjointScratch& A,
+                                 hipStream_t s);
+hipError_t launch_update_backward(const VolumeSet& prev, SceneGPU sc, FrameScratch fs, const GradSet& Gnew,
+                                  const GradSet& Gprev, float* g_emission, int n_materials, int64_t n_rays,
+                                  const AdjointScratch& A, hipStream_t s);
 void launch_glossy(const VolumeSet& vs, SceneGPU sc, const LightSet& L, const float* pos, const float* nrm,
                    const float* view, int64_t n, float* out, irf_ray_record* rec, hipStream_t s);
 void launch_frame_stats(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, unsigned long long* out, hipStream_t s);

@@ -3,36 +3,99 @@
 // smooth function of emitter radiance and input texels, up to the clamp of
 // the Chebyshev variance at zero).
 //
-//  k_query_backward   dLoss/d(texels) of E(X, n, w_o) for a batch of points
+//  query terms        the reverse pass of one query E(X, n, w_o) as one term
+//                     per probe of each cage it read: the gradient of that
+//                     probe's irradiance sample and of its (mu, mu2) sample,
+//                     with the two bilinear footprints they spread over
 //  k_blend_backward   per probe: folds border gradients into their source
 //                     texels, passes alpha * gradient to the input texels
 //                     (all of it for probes that were not updated) and the
 //                     transposed normalised weights to every ray's radiance
-//  k_shade_backward   per ray: radiance gradient to the hit's emitter and,
-//                     through albedo, to the previous-frame query at the hit
+//  k_shade_terms      per ray: the query terms of the previous-frame query at
+//                     its hit (through albedo) and its emitter's share
 //
-// Gradient atlases have the layout of the atlases (irradiance [P][8][8][4],
-// distance [P][16][16][2], float32) and accumulate with atomic adds.
+// Gradients are summed without atomics, in a fixed order: the terms of a
+// batch (points or rays, in index order) are sorted by probe with a stable
+// radix sort (so a probe's terms stay in point order), and one workgroup per
+// probe adds its terms texel by texel in that order; emitter shares are
+// sorted by material and summed per material in ray order.  Results are the
+// same bit for bit from run to run.  Gradient atlases have the layout of the
+// atlases (irradiance [P][8][8][4], distance [P][16][16][2], float32) and
+// accumulate (+=).
 #include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
 
 #include "device_common.h"
 
 namespace irf {
 
-template <int M>
-__device__ __forceinline__ void scatter_bilinear(float* tile, int nch, int stride, float3 v, const float* g) {
-  int x0, y0;
-  float fx, fy;
-  tile_footprint<M>(v, x0, y0, fx, fy);
-  const float bw[4] = {(1.0f - fx) * (1.0f - fy), fx * (1.0f - fy), (1.0f - fx) * fy, fx * fy};
-  const int idx[4] = {y0 * M + x0, y0 * M + x0 + 1, (y0 + 1) * M + x0, (y0 + 1) * M + x0 + 1};
-  for (int t = 0; t < 4; t++)
-    for (int c = 0; c < nch; c++) atomicAdd(&tile[idx[t] * stride + c], bw[t] * g[c]);
+// One probe's share of a query's reverse pass: the gradient of its
+// irradiance sample (RGB) over the bilinear footprint at (ix, iy) with
+// fractions (ifx, ify), and of its (mu, mu2) sample over the footprint at
+// (dx, dy), (dfx, dfy).
+struct Term {
+  float ge[3];
+  float gd[2];
+  float ifx, ify, dfx, dfy;
+  uint32_t fp;   // ix | iy << 8 | dx << 16 | dy << 24
+};
+static_assert(sizeof(Term) == 40, "ten words");
+
+// One corner probe of a cage query: its trilinear x backface weight (wtb),
+// full weight (ww, with the Chebyshev factor when r > mu), irradiance sample
+// and distance sample.
+struct Corner {
+  bool ok;      // the probe is sampled
+  bool cheb;    // the Chebyshev factor applies
+  int q;
+  float wtb, ww, r;
+  float2 mm;
+  float3 zd, e;
+};
+
+__device__ __forceinline__ Corner corner_eval(const VolumeGPU& V, int c, const int* gi, const float* f, float3 X,
+                                              float3 Xb, float3 n) {
+  Corner k;
+  const int cb0 = c & 1, cb1 = (c >> 1) & 1, cb2 = (c >> 2) & 1;
+  k.q = storage_index(V, gi[0] + cb0, gi[1] + cb1, gi[2] + cb2);
+  k.ok = sampled_state(V.states[k.q]);
+  k.cheb = false;
+  if (!k.ok) return k;
+  const float wt = (cb0 ? f[0] : 1.0f - f[0]) * (cb1 ? f[1] : 1.0f - f[1]) * (cb2 ? f[2] : 1.0f - f[2]);
+  const float3 P = probe_position(V, k.q);
+  const float3 toP = normalize_or_zero(P - X);
+  const float h = (1.0f + dot(n, toP)) * 0.5f;
+  k.wtb = wt * fmaf(h, h, 0.2f);
+  k.ww = k.wtb;
+  const float3 z = Xb - P;
+  k.r = length(z);
+  if (k.r > 0.0f) {
+    k.zd = (1.0f / k.r) * z;
+    k.mm = sample_distance(V, k.q, k.zd);
+    if (k.r > k.mm.x) {
+      const float var = fmaxf(fmaf(-k.mm.x, k.mm.x, k.mm.y), 0.0f);
+      const float dl = k.r - k.mm.x;
+      const float ch = var / fmaf(dl, dl, var);
+      float p = ch;
+      for (int j = 1; j < V.cheb_power; j++) p *= ch;
+      k.ww *= p;
+      k.cheb = true;
+    }
+  }
+  k.e = sample_irradiance(V, k.q, n);
+  return k;
 }
 
-// Reverse pass of one volume's cage query (forward: volume_query).
-__device__ inline void volume_query_backward(const VolumeGPU& V, float3 X, float3 n, float3 wo, float3 g, float* gI,
-                                             float* gD) {
+// Terms of one volume's cage query (forward: volume_query) with upstream
+// gradient g: corner c's term in t[c], key[c] its global probe id (`none`
+// for a corner without a sampled probe).  Two passes over the corners (the
+// weight sum, then the terms) recompute each corner instead of holding all
+// eight in registers.
+__device__ inline void volume_query_terms(const VolumeGPU& V, float3 X, float3 n, float3 wo, float3 g, Term* t,
+                                          uint32_t* key, uint32_t none) {
   float u[3] = {(X.x - V.origin[0]) * V.inv_spacing[0], (X.y - V.origin[1]) * V.inv_spacing[1],
                 (X.z - V.origin[2]) * V.inv_spacing[2]};
   int gi[3];
@@ -45,95 +108,296 @@ __device__ inline void volume_query_backward(const VolumeGPU& V, float3 X, float
   float sb = 0.75f * D * V.bias;
   float3 Xb = f3(fmaf(fmaf(0.2f, n.x, 0.8f * wo.x), sb, X.x), fmaf(fmaf(0.2f, n.y, 0.8f * wo.y), sb, X.y),
                  fmaf(fmaf(0.2f, n.z, 0.8f * wo.z), sb, X.z));
-  // first pass: weights and the normalised result
-  float w[8], wtb[8], r8[8];
-  float3 e[8], zd[8];
-  float2 mm[8];
-  int qs[8];
-  bool cheb[8];
-  int used = 0;
   float W = 0.0f;
   float3 E = f3(0.0f, 0.0f, 0.0f);
   for (int c = 0; c < 8; c++) {
-    int cb0 = c & 1, cb1 = (c >> 1) & 1, cb2 = (c >> 2) & 1;
-    int q = storage_index(V, gi[0] + cb0, gi[1] + cb1, gi[2] + cb2);
-    if (!sampled_state(V.states[q])) continue;
-    float wt = (cb0 ? f[0] : 1.0f - f[0]) * (cb1 ? f[1] : 1.0f - f[1]) * (cb2 ? f[2] : 1.0f - f[2]);
-    float3 P = probe_position(V, q);
-    float3 toP = normalize_or_zero(P - X);
-    float h = (1.0f + dot(n, toP)) * 0.5f;
-    float ww = wt * fmaf(h, h, 0.2f);
-    wtb[used] = ww;
-    float3 z = Xb - P;
-    float r = length(z);
-    cheb[used] = false;
-    if (r > 0.0f) {
-      zd[used] = (1.0f / r) * z;
-      mm[used] = sample_distance(V, q, zd[used]);
-      if (r > mm[used].x) {
-        float var = fmaxf(fmaf(-mm[used].x, mm[used].x, mm[used].y), 0.0f);
-        float dl = r - mm[used].x;
-        float ch = var / fmaf(dl, dl, var);
-        float p = ch;
-        for (int k = 1; k < V.cheb_power; k++) p *= ch;
-        ww *= p;
-        cheb[used] = true;
-      }
-    }
-    r8[used] = r;
-    qs[used] = q;
-    w[used] = ww;
-    e[used] = sample_irradiance(V, q, n);
-    E = E + ww * e[used];
-    W += ww;
-    used++;
+    const Corner k = corner_eval(V, c, gi, f, X, Xb, n);
+    if (!k.ok) continue;
+    E = E + k.ww * k.e;
+    W += k.ww;
   }
-  if (!(W > 0.0f)) return;
+  if (!(W > 0.0f)) {
+    for (int c = 0; c < 8; c++) key[c] = none;
+    return;
+  }
   const float iW = 1.0f / W;
   E = iW * E;
-  for (int i = 0; i < used; i++) {
-    const float ge[3] = {g.x * w[i] * iW, g.y * w[i] * iW, g.z * w[i] * iW};
-    scatter_bilinear<kIrrTile>(gI + (size_t)qs[i] * kIrrTexels * 4, 3, 4, n, ge);
-    if (!cheb[i]) continue;
-    const float gw = (g.x * (e[i].x - E.x) + g.y * (e[i].y - E.y) + g.z * (e[i].z - E.z)) * iW;
-    const float mu = mm[i].x, mu2 = mm[i].y;
-    const float raw = fmaf(-mu, mu, mu2);
-    const float var = fmaxf(raw, 0.0f);
-    const float dl = r8[i] - mu;
-    const float den = fmaf(dl, dl, var);
-    const float ch = var / den;
-    const float dch_dvar = dl * dl / (den * den);
-    const float dch_ddl = -2.0f * dl * var / (den * den);
-    const float dvar_dmu = raw > 0.0f ? -2.0f * mu : 0.0f, dvar_dmu2 = raw > 0.0f ? 1.0f : 0.0f;
-    float dwv = (float)V.cheb_power;
-    for (int k = 1; k < V.cheb_power; k++) dwv *= ch;
-    const float gwv = gw * wtb[i] * dwv;
-    const float gd[2] = {gwv * (dch_dvar * dvar_dmu - dch_ddl), gwv * dch_dvar * dvar_dmu2};
-    scatter_bilinear<kDistTile>(gD + (size_t)qs[i] * kDistTexels * 2, 2, 2, zd[i], gd);
+  int ix, iy;
+  float ifx, ify;
+  tile_footprint<kIrrTile>(n, ix, iy, ifx, ify);
+  for (int c = 0; c < 8; c++) {
+    const Corner k = corner_eval(V, c, gi, f, X, Xb, n);
+    if (!k.ok) {
+      key[c] = none;
+      continue;
+    }
+    Term T;
+    T.ge[0] = g.x * k.ww * iW;
+    T.ge[1] = g.y * k.ww * iW;
+    T.ge[2] = g.z * k.ww * iW;
+    T.gd[0] = T.gd[1] = 0.0f;
+    T.ifx = ifx;
+    T.ify = ify;
+    int dx = 0, dy = 0;
+    float dfx = 0.0f, dfy = 0.0f;
+    if (k.cheb) {
+      const float gw = (g.x * (k.e.x - E.x) + g.y * (k.e.y - E.y) + g.z * (k.e.z - E.z)) * iW;
+      const float mu = k.mm.x, mu2 = k.mm.y;
+      const float raw = fmaf(-mu, mu, mu2);
+      const float var = fmaxf(raw, 0.0f);
+      const float dl = k.r - mu;
+      const float den = fmaf(dl, dl, var);
+      const float ch = var / den;
+      const float dch_dvar = dl * dl / (den * den);
+      const float dch_ddl = -2.0f * dl * var / (den * den);
+      const float dvar_dmu = raw > 0.0f ? -2.0f * mu : 0.0f, dvar_dmu2 = raw > 0.0f ? 1.0f : 0.0f;
+      float dwv = (float)V.cheb_power;
+      for (int j = 1; j < V.cheb_power; j++) dwv *= ch;
+      const float gwv = gw * k.wtb * dwv;
+      T.gd[0] = gwv * (dch_dvar * dvar_dmu - dch_ddl);
+      T.gd[1] = gwv * dch_dvar * dvar_dmu2;
+      tile_footprint<kDistTile>(k.zd, dx, dy, dfx, dfy);
+    }
+    T.dfx = dfx;
+    T.dfy = dfy;
+    T.fp = (uint32_t)ix | (uint32_t)iy << 8 | (uint32_t)dx << 16 | (uint32_t)dy << 24;
+    t[c] = T;
+    key[c] = (uint32_t)(V.probe_base + k.q);
   }
 }
 
-__device__ inline void query_backward(const VolumeSet& vs, const GradSet& G, float3 X, float3 n, float3 wo, float3 g) {
+// Terms of the query over all volumes (8 slots per volume, in volume order),
+// each volume's share of the upstream gradient as its weight in the forward
+// cascade blend.
+__device__ inline void query_terms(const VolumeSet& vs, float3 X, float3 n, float3 wo, float3 g, Term* t,
+                                   uint32_t* key, uint32_t none) {
   float Wt = 0.0f;
   for (int v = 0; v < vs.n; v++) {
-    if (Wt >= 1.0f) break;
     const VolumeGPU& V = vs.v[v];
-    float wv = volume_weight(V, X);
-    float wuse = (v == vs.n - 1) ? 1.0f - Wt : fminf(wv, 1.0f - Wt);
+    float wuse = 0.0f;
+    if (Wt < 1.0f) {
+      float wv = volume_weight(V, X);
+      wuse = (v == vs.n - 1) ? 1.0f - Wt : fminf(wv, 1.0f - Wt);
+    }
     if (wuse > 0.0f) {
-      volume_query_backward(V, X, n, wo, wuse * g, G.irr[v], G.dist[v]);
+      volume_query_terms(V, X, n, wo, wuse * g, t + 8 * v, key + 8 * v, none);
       Wt += wuse;
+    } else {
+      for (int i = 0; i < 8; i++) key[8 * v + i] = none;
     }
   }
 }
 
-__global__ void k_query_backward(VolumeSet vs, const float* pos, const float* nrm, const float* view, int64_t n,
-                                 const float* gout, GradSet G) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+// Query terms of points [i0, i0 + n): point i's at (i - i0) * 8 * vs.n.
+__global__ void k_query_terms(VolumeSet vs, const float* pos, const float* nrm, const float* view, int64_t i0,
+                              int64_t n, const float* gout, Term* terms, uint32_t* keys, uint32_t none) {
+  const int per = 8 * vs.n;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = i0 + j;
     float3 X = f3(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]);
     float3 N = f3(nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]);
     float3 Wo = f3(view[3 * i], view[3 * i + 1], view[3 * i + 2]);
-    query_backward(vs, G, X, N, Wo, f3(gout[3 * i], gout[3 * i + 1], gout[3 * i + 2]));
+    query_terms(vs, X, N, Wo, f3(gout[3 * i], gout[3 * i + 1], gout[3 * i + 2]), terms + j * per, keys + j * per,
+                none);
+  }
+}
+
+__global__ void k_fill_words(uint32_t* p, uint32_t value, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+// Segments of a sorted key array: keys below `none` get [start, end).
+__global__ void k_segments(const uint32_t* keys, int64_t n, uint32_t none, uint32_t* start, uint32_t* end) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t k = keys[i];
+    if (k >= none) continue;
+    if (i == 0 || keys[i - 1] != k) start[k] = (uint32_t)i;
+    if (i == n - 1 || keys[i + 1] != k) end[k] = (uint32_t)(i + 1);
+  }
+}
+
+// Pieces: each segment (a probe's or a material's terms, in sorted order)
+// is cut into pieces of kPieceTerms consecutive terms.  A piece is summed by
+// one workgroup in a fixed order; a segment of one piece adds its sum to the
+// gradient directly, a longer one stores its pieces' sums and k_finish_pieces
+// adds them in piece order.  The cut depends only on the sorted terms, so the
+// result is the same from run to run, and no workgroup sums more than
+// kPieceTerms terms however the terms crowd onto a few probes.
+constexpr int kPieceTerms = 1024;
+constexpr int kPieceWaves = 4;
+constexpr int kWaveTerms = kPieceTerms / kPieceWaves;
+constexpr int kSlotFloats = 3 * kIrrTexels + 2 * kDistTexels;   // one probe's texel gradients (RGB, mu mu2)
+static_assert(kIrrTexels == 64 && kDistTexels == 256 && kWaveTerms % 64 == 0, "one lane: one irradiance texel, "
+              "a column of four distance texels");
+
+__device__ __forceinline__ uint32_t pieces_of(const uint32_t* start, const uint32_t* end, uint32_t k) {
+  const uint32_t a = start[k], b = end[k];
+  return b > a ? (b - a + kPieceTerms - 1) / kPieceTerms : 0u;
+}
+
+// offs[k]: the first piece of segment k (offs[K] = all pieces); poffs[k]: its
+// first stored sum (segments of two or more pieces only).  One workgroup:
+// contiguous runs of segments per thread, then a scan over threads.
+__global__ __launch_bounds__(1024) void k_piece_offsets(const uint32_t* start, const uint32_t* end, uint32_t K,
+                                                       uint32_t* offs, uint32_t* poffs) {
+  __shared__ uint32_t s1[1024], s2[1024];
+  const uint32_t t = threadIdx.x, per = (K + 1023) / 1024;
+  const uint32_t k0 = min(K, t * per), k1 = min(K, k0 + per);
+  uint32_t a1 = 0, a2 = 0;
+  for (uint32_t k = k0; k < k1; k++) {
+    const uint32_t n = pieces_of(start, end, k);
+    a1 += n;
+    a2 += n > 1 ? n : 0u;
+  }
+  s1[t] = a1;
+  s2[t] = a2;
+  for (uint32_t off = 1; off < 1024; off <<= 1) {
+    __syncthreads();
+    const uint32_t v1 = t >= off ? s1[t - off] : 0u, v2 = t >= off ? s2[t - off] : 0u;
+    __syncthreads();
+    s1[t] += v1;
+    s2[t] += v2;
+  }
+  uint32_t b1 = s1[t] - a1, b2 = s2[t] - a2;
+  for (uint32_t k = k0; k < k1; k++) {
+    const uint32_t n = pieces_of(start, end, k);
+    offs[k] = b1;
+    poffs[k] = b2;
+    b1 += n;
+    b2 += n > 1 ? n : 0u;
+  }
+  if (t == 1023) {
+    offs[K] = s1[1023];
+    poffs[K] = s2[1023];
+  }
+}
+
+// Index of a probe's texel gradient value s (0 .. kSlotFloats-1) in the
+// gradient atlases: irradiance texel s / 3 channel s % 3, then distance
+// texel (s - 192) / 2 channel (s - 192) % 2.
+__device__ __forceinline__ float* slot_target(const GradSet& G, int v, int q, int s) {
+  if (s < 3 * kIrrTexels) return G.irr[v] + ((size_t)q * kIrrTexels + s / 3) * 4 + s % 3;
+  s -= 3 * kIrrTexels;
+  return G.dist[v] + ((size_t)q * kDistTexels + s / 2) * 2 + s % 2;
+}
+
+__device__ __forceinline__ float corner_weight(int x, int x0, float f) {
+  return x == x0 ? 1.0f - f : (x == x0 + 1 ? f : 0.0f);
+}
+
+// One workgroup per piece (the grid bounds the number of pieces; the rest
+// return).  Probe pieces: wave w takes the piece's batches of 64 terms w,
+// w + 4, w + 8, ... in order, through LDS; lane l accumulates irradiance
+// texel l and distance texels (l % 16, 4 (l / 16) .. + 3); the four waves'
+// sums are added in wave order.  Material pieces: thread t sums terms t,
+// t + 256, ... then a fixed tree over threads.  Keys: [0, P) probes,
+// [P, K) materials.
+__global__ __launch_bounds__(256) void k_gather_pieces(VolumeSet vs, uint32_t P, uint32_t K, const Term* terms,
+                                                       const uint32_t* idx, const uint32_t* start,
+                                                       const uint32_t* end, const uint32_t* offs,
+                                                       const uint32_t* poffs, float* partial, uint32_t max_partial,
+                                                       GradSet G, float* g_emission) {
+  __shared__ Term s_t[kPieceWaves][64];
+  __shared__ float s_red[kPieceWaves * kSlotFloats];
+  const uint32_t w = blockIdx.x;
+  if (w >= offs[K]) return;
+  uint32_t lo = 0, hi = K - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  const uint32_t k = lo, j = w - offs[k], n = offs[k + 1] - offs[k];
+  const uint32_t a = start[k] + j * kPieceTerms, b = min(end[k], a + kPieceTerms);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  float* out = nullptr;   // stored sums of a segment of several pieces
+  if (n > 1) {
+    const uint32_t slot = poffs[k] + j;
+    if (slot >= max_partial) return;
+    out = partial + (size_t)slot * kSlotFloats;
+  }
+  if (k >= P) {
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    for (uint32_t i = a + t; i < b; i += 256) {
+      const Term& T = terms[idx[i]];
+      for (int c = 0; c < 3; c++) acc[c] += T.ge[c];
+    }
+    for (int c = 0; c < 3; c++) s_red[c * 256 + t] = acc[c];
+    for (int half = 128; half > 0; half >>= 1) {
+      __syncthreads();
+      if (t < half)
+        for (int c = 0; c < 3; c++) s_red[c * 256 + t] += s_red[c * 256 + t + half];
+    }
+    if (t < 3) {
+      if (out) out[t] = s_red[t * 256];
+      else g_emission[3 * (k - P) + t] += s_red[t * 256];
+    }
+    return;
+  }
+  const int xi = lane % kIrrTile, yi = lane / kIrrTile, xd = lane % kDistTile, yd0 = 4 * (lane / kDistTile);
+  float ai[3] = {0.0f, 0.0f, 0.0f}, ad[4][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}};
+  for (int batch = 0; batch < kWaveTerms / 64; batch++) {
+    const uint32_t b0 = a + (uint32_t)(batch * kPieceWaves + wave) * 64;
+    const int cnt = b0 < b ? (int)min(64u, b - b0) : 0;
+    __syncthreads();
+    if (lane < cnt) s_t[wave][lane] = terms[idx[b0 + lane]];
+    __syncthreads();
+    for (int i = 0; i < cnt; i++) {
+      const Term& T = s_t[wave][i];
+      const int ix = T.fp & 255, iy = (T.fp >> 8) & 255;
+      const float wb = corner_weight(xi, ix, T.ifx) * corner_weight(yi, iy, T.ify);
+      for (int c = 0; c < 3; c++) ai[c] = fmaf(wb, T.ge[c], ai[c]);
+      if (T.gd[0] != 0.0f || T.gd[1] != 0.0f) {
+        const int dx = (T.fp >> 16) & 255, dy = T.fp >> 24;
+        const float wx = corner_weight(xd, dx, T.dfx);
+        for (int r = 0; r < 4; r++) {
+          const float wd = wx * corner_weight(yd0 + r, dy, T.dfy);
+          ad[r][0] = fmaf(wd, T.gd[0], ad[r][0]);
+          ad[r][1] = fmaf(wd, T.gd[1], ad[r][1]);
+        }
+      }
+    }
+  }
+  float* red = s_red + wave * kSlotFloats;
+  for (int c = 0; c < 3; c++) red[lane * 3 + c] = ai[c];
+  for (int r = 0; r < 4; r++)
+    for (int c = 0; c < 2; c++) red[3 * kIrrTexels + ((yd0 + r) * kDistTile + xd) * 2 + c] = ad[r][c];
+  __syncthreads();
+  int v = 0;
+  while (v + 1 < vs.n && (int)k >= vs.v[v + 1].probe_base) v++;
+  const int q = (int)k - vs.v[v].probe_base;
+  for (int s = t; s < kSlotFloats; s += 256) {
+    float sum = s_red[s];
+    for (int wv = 1; wv < kPieceWaves; wv++) sum += s_red[wv * kSlotFloats + s];
+    if (out) out[s] = sum;
+    else *slot_target(G, v, q, s) += sum;
+  }
+}
+
+// Segments of two or more pieces: their stored sums added in piece order.
+__global__ __launch_bounds__(256) void k_finish_pieces(VolumeSet vs, uint32_t P, uint32_t K, const uint32_t* offs,
+                                                       const uint32_t* poffs, const float* partial,
+                                                       uint32_t max_partial, GradSet G, float* g_emission) {
+  const uint32_t k = blockIdx.x;
+  const uint32_t n = offs[k + 1] - offs[k], p0 = poffs[k];
+  if (n < 2 || p0 + n > max_partial) return;
+  const int t = threadIdx.x;
+  if (k >= P) {
+    if (t < 3) {
+      float sum = 0.0f;
+      for (uint32_t j = 0; j < n; j++) sum += partial[(size_t)(p0 + j) * kSlotFloats + t];
+      g_emission[3 * (k - P) + t] += sum;
+    }
+    return;
+  }
+  int v = 0;
+  while (v + 1 < vs.n && (int)k >= vs.v[v + 1].probe_base) v++;
+  const int q = (int)k - vs.v[v].probe_base;
+  for (int s = t; s < kSlotFloats; s += 256) {
+    float sum = 0.0f;
+    for (uint32_t j = 0; j < n; j++) sum += partial[(size_t)(p0 + j) * kSlotFloats + s];
+    *slot_target(G, v, q, s) += sum;
   }
 }
 
@@ -160,13 +424,44 @@ __device__ __forceinline__ float folded(const float* g, int stride, int c, int x
 }
 
 constexpr int kBwdBlock = 256;
+constexpr int kNormsPerVolume = 36 + 196;   // interior irradiance texels, interior distance texels
+
+// Per volume: the inverse of each interior texel's weight sum over the
+// frame's rays (0 for an empty sum), irradiance texels first.  Every probe of
+// a volume traces the same rotated directions, so one row per volume.  One
+// workgroup per (texel, volume): thread t sums rays t, t + 256, ..., then a
+// fixed tree over lanes and waves.
+__global__ __launch_bounds__(kBwdBlock) void k_blend_norms(VolumeSet prev, FrameScratch fs, float* norms) {
+  __shared__ float s_part[kBwdBlock / 64];
+  const int row = blockIdx.x, v = blockIdx.y, t = threadIdx.x;
+  const VolumeGPU& V = prev.v[v];
+  const float4* om = fs.omega + V.omega_base;
+  const bool irr = row < 36;
+  const float3 nt = irr ? texel_direction<kIrrTile>(row % 6 + 1, row / 6 + 1)
+                        : texel_direction<kDistTile>((row - 36) % 14 + 1, (row - 36) / 14 + 1);
+  float W = 0.0f;
+  for (int r = t; r < V.rays; r += kBwdBlock) {
+    const float4 o = om[r];
+    const float c = fmaf(nt.x, o.x, fmaf(nt.y, o.y, nt.z * o.z));
+    if (c > 0.0f) W += irr ? c : pow_weight(c, V);
+  }
+  for (int off = 32; off > 0; off >>= 1) W += __shfl_down(W, off);
+  if ((t & 63) == 0) s_part[t >> 6] = W;
+  __syncthreads();
+  if (t == 0) {
+    float sum = s_part[0];
+    for (int w = 1; w < kBwdBlock / 64; w++) sum += s_part[w];
+    norms[(size_t)v * kNormsPerVolume + row] = sum > 0.0f ? 1.0f / sum : 0.0f;
+  }
+}
 
 // One workgroup per probe of every volume.  prev: the frame's input atlases
 // and the states after its state step.
-__global__ __launch_bounds__(kBwdBlock) void k_blend_backward(VolumeSet prev, FrameScratch fs, GradSet Gnew,
-                                                              GradSet Gprev) {
+__global__ __launch_bounds__(kBwdBlock) void k_blend_backward(VolumeSet prev, FrameScratch fs, const float* norms,
+                                                              GradSet Gnew, GradSet Gprev) {
   __shared__ float s_g[36][3];
   __shared__ float s_iW[36];
+  __shared__ float3 s_nt[36];
   const FrameCounters& C = *fs.counters;
   int gq = blockIdx.x;
   int v = 0;
@@ -189,33 +484,23 @@ __global__ __launch_bounds__(kBwdBlock) void k_blend_backward(VolumeSet prev, Fr
   const float ai = fresh ? 0.0f : V.alpha_irr, ad = fresh ? 0.0f : V.alpha_dist;
   const int N = V.rays;
   const float4* om = fs.omega + V.omega_base;
+  const float* nv = norms + (size_t)v * kNormsPerVolume;
   const int t = threadIdx.x;
   if (t < 36) {
     const int x = t % 6 + 1, y = t / 6 + 1;
-    float3 nt = texel_direction<kIrrTile>(x, y);
-    float W = 0.0f;
-    for (int r = 0; r < N; r++) {
-      float4 o = om[r];
-      W += fmaxf(0.0f, fmaf(nt.x, o.x, fmaf(nt.y, o.y, nt.z * o.z)));
-    }
-    s_iW[t] = W > 0.0f ? 1.0f / W : 0.0f;
+    s_nt[t] = texel_direction<kIrrTile>(x, y);
+    const float iW = nv[t];
+    s_iW[t] = iW;
     for (int c = 0; c < 3; c++) {
       float g = folded<kIrrTile>(gi, 4, c, x, y);
       s_g[t][c] = g;
-      pi[(y * kIrrTile + x) * 4 + c] += (W > 0.0f ? ai : 1.0f) * g;
+      pi[(y * kIrrTile + x) * 4 + c] += (iW > 0.0f ? ai : 1.0f) * g;
     }
   }
   if (t < 196) {
     const int x = t % 14 + 1, y = t / 14 + 1;
-    float3 nt = texel_direction<kDistTile>(x, y);
-    // a zero weight sum keeps the texel (same float32 weights as the forward)
-    float W = 0.0f;
-    for (int r = 0; r < N; r++) {
-      float4 o = om[r];
-      float c = fmaf(nt.x, o.x, fmaf(nt.y, o.y, nt.z * o.z));
-      if (c > 0.0f) W += pow_weight(c, V);
-    }
-    const bool any = W > 0.0f;
+    // a zero weight sum keeps the texel
+    const bool any = nv[36 + t] > 0.0f;
     for (int c = 0; c < 2; c++) pd[(y * kDistTile + x) * 2 + c] += (any ? ad : 1.0f) * folded<kDistTile>(gd, 2, c, x, y);
   }
   __syncthreads();
@@ -230,8 +515,9 @@ __global__ __launch_bounds__(kBwdBlock) void k_blend_backward(VolumeSet prev, Fr
   for (int r = t; r < N; r += kBwdBlock) {
     float4 o = om[r];
     float3 acc = f3(0.0f, 0.0f, 0.0f);
+#pragma unroll 4
     for (int k = 0; k < 36; k++) {
-      float3 nt = texel_direction<kIrrTile>(k % 6 + 1, k / 6 + 1);
+      const float3 nt = s_nt[k];
       float w = fmaxf(0.0f, fmaf(nt.x, o.x, fmaf(nt.y, o.y, nt.z * o.z))) * s_iW[k];
       acc = acc + w * f3(s_g[k][0], s_g[k][1], s_g[k][2]);
     }
@@ -245,13 +531,22 @@ __device__ __forceinline__ int64_t ray_volume(const VolumeSet& vs, const FrameCo
   return v;
 }
 
-// Per ray of the frame: emitter gradient and the previous-frame query at the
-// hit (front faces only; misses and backfaces carry constants).
-__global__ void k_shade_backward(VolumeSet prev, SceneGPU sc, FrameScratch fs, GradSet Gprev, float* g_emission) {
+// Rays [r0, r0 + n) of the frame (front faces only; misses and backfaces
+// carry constants), 8 prev.n + 1 slots per ray at (r - r0) * (8 prev.n + 1):
+// the terms of the previous-frame query at the hit, with upstream albedo x
+// the ray's radiance gradient, then its emitter record (key P + material,
+// ge = the radiance gradient).  Keys of empty slots: `none`.
+__global__ void k_shade_terms(VolumeSet prev, SceneGPU sc, FrameScratch fs, int64_t r0, int64_t n, Term* terms,
+                              uint32_t* keys, uint32_t P, uint32_t none) {
   const FrameCounters& C = *fs.counters;
   const int64_t total = C.ray_base[prev.n];
-  for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < total;
-       id += (int64_t)gridDim.x * blockDim.x) {
+  const int per = 8 * prev.n + 1;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    Term* tj = terms + j * per;
+    uint32_t* kj = keys + j * per;
+    for (int k = 0; k < per; k++) kj[k] = none;
+    const int64_t id = r0 + j;
+    if (id >= total) continue;
     HitRec h = fs.hits[id];
     if (h.tri < 0) continue;
     const int v = (int)ray_volume(prev, C, id);
@@ -267,13 +562,16 @@ __global__ void k_shade_backward(VolumeSet prev, SceneGPU sc, FrameScratch fs, G
     if (dot(w, ng) > 0.0f) continue;
     float4 g = fs.grad_rays[id];
     const int m = __float_as_int(c.w);
-    atomicAdd(&g_emission[3 * m + 0], g.x);
-    atomicAdd(&g_emission[3 * m + 1], g.y);
-    atomicAdd(&g_emission[3 * m + 2], g.z);
+    Term E = {};
+    E.ge[0] = g.x;
+    E.ge[1] = g.y;
+    E.ge[2] = g.z;
+    tj[per - 1] = E;
+    kj[per - 1] = P + (uint32_t)m;
     float4 al = sc.albedo[m];
     float3 o = probe_position(V, q);
     float3 X = f3(fmaf(h.t, w.x, o.x), fmaf(h.t, w.y, o.y), fmaf(h.t, w.z, o.z));
-    query_backward(prev, Gprev, X, ng, f3(-w.x, -w.y, -w.z), f3(al.x * g.x, al.y * g.y, al.z * g.z));
+    query_terms(prev, X, ng, f3(-w.x, -w.y, -w.z), f3(al.x * g.x, al.y * g.y, al.z * g.z), tj, kj, none);
   }
 }
 
@@ -304,25 +602,99 @@ void launch_set_emission(const float* src, float4* dst, int m, hipStream_t s) {
   irf_launch(k_set_emission, dim3((m + 255) / 256), dim3(256), 0, s, src, dst, m);
 }
 
-void launch_query_backward(const VolumeSet& vs, const float* pos, const float* nrm, const float* view, int64_t n,
-                           const float* gout, const GradSet& G, hipStream_t s) {
-  if (n == 0) return;
-  int64_t blocks = (n + 255) / 256;
-  irf_launch(k_query_backward, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, vs, pos, nrm,
-                     view, n, gout, G);
+static inline unsigned grid_of(int64_t n, int block) {
+  const int64_t b = (n + block - 1) / block;
+  return (unsigned)(b < 65536 ? (b > 0 ? b : 1) : 65536);
 }
 
-void launch_update_backward(const VolumeSet& prev, SceneGPU sc, FrameScratch fs, const GradSet& Gnew,
-                            const GradSet& Gprev, float* g_emission, hipStream_t s) {
-  int P = 0;
-  for (int v = 0; v < prev.n; v++) P += prev.v[v].n_probes;
-  if (P == 0) return;
-  irf_launch(k_blend_backward, dim3(P), dim3(kBwdBlock), 0, s, prev, fs, Gnew, Gprev);
-  if (fs.max_rays > 0) {
-    int64_t blocks = (fs.max_rays + 255) / 256;
-    irf_launch(k_shade_backward, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, prev, sc,
-                       fs, Gprev, g_emission);
+// Bits that hold keys 0 .. none.
+static inline unsigned key_bits(uint32_t none) {
+  unsigned b = 1;
+  while (b < 32 && (1ull << b) <= none) b++;
+  return b;
+}
+
+// Onesweep radix sort at every size above one block (rocPRIM's merge-sort
+// path for mid sizes is several times slower on these key widths).
+using SortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                              rocprim::default_config, 0>;
+
+size_t adjoint_sort_bytes(int64_t max_pairs) {
+  size_t bytes = 0;
+  (void)rocprim::radix_sort_pairs<SortConfig>(nullptr, bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                              rocprim::counting_iterator<uint32_t>(0u), (uint32_t*)nullptr,
+                                              (unsigned)max_pairs, 0u, 32u);
+  return bytes;
+}
+
+int64_t adjoint_partial_slots(int64_t max_terms) { return 2 * (max_terms / kPieceTerms) + 2; }
+size_t adjoint_slot_bytes() { return sizeof(float) * kSlotFloats; }
+int adjoint_norms_per_volume() { return kNormsPerVolume; }
+
+// Sorts the batch's nt terms by key (segments 0 .. K-1; `none` = K for empty
+// slots) and adds each segment's terms into its probe's texels (keys below
+// P) or its material's emission gradient (P .. K-1).
+static hipError_t gather_batch(const VolumeSet& vs, const AdjointScratch& A, int64_t nt, uint32_t P, uint32_t K,
+                               const GradSet& G, float* g_emission, hipStream_t s) {
+  size_t bytes = A.sort_bytes;
+  hipError_t e = rocprim::radix_sort_pairs<SortConfig>(A.sort_temp, bytes, (const uint32_t*)A.keys[0], A.keys[1],
+                                                       rocprim::counting_iterator<uint32_t>(0u), A.idx, (unsigned)nt,
+                                                       0u, key_bits(K), s);
+  if (e != hipSuccess) return e;
+  irf_launch(k_fill_words, dim3(grid_of(K, 256)), dim3(256), 0, s, A.seg_start, 0u, (int64_t)K);
+  irf_launch(k_fill_words, dim3(grid_of(K, 256)), dim3(256), 0, s, A.seg_end, 0u, (int64_t)K);
+  irf_launch(k_segments, dim3(grid_of(nt, 256)), dim3(256), 0, s, (const uint32_t*)A.keys[1], nt, K, A.seg_start,
+             A.seg_end);
+  irf_launch(k_piece_offsets, dim3(1), dim3(1024), 0, s, (const uint32_t*)A.seg_start, (const uint32_t*)A.seg_end, K,
+             A.offs, A.poffs);
+  const int64_t grid = (nt + kPieceTerms - 1) / kPieceTerms + K;
+  irf_launch(k_gather_pieces, dim3((unsigned)grid), dim3(256), 0, s, vs, P, K, (const Term*)A.terms,
+             (const uint32_t*)A.idx, (const uint32_t*)A.seg_start, (const uint32_t*)A.seg_end,
+             (const uint32_t*)A.offs, (const uint32_t*)A.poffs, A.partial, (uint32_t)A.max_partial, G, g_emission);
+  irf_launch(k_finish_pieces, dim3(K), dim3(256), 0, s, vs, P, K, (const uint32_t*)A.offs, (const uint32_t*)A.poffs,
+             (const float*)A.partial, (uint32_t)A.max_partial, G, g_emission);
+  return hipSuccess;
+}
+
+hipError_t launch_query_backward(const VolumeSet& vs, const float* pos, const float* nrm, const float* view,
+                                 int64_t n, const float* gout, const GradSet& G, const AdjointScratch& A,
+                                 hipStream_t s) {
+  uint32_t P = 0;
+  for (int v = 0; v < vs.n; v++) P += (uint32_t)vs.v[v].n_probes;
+  const int per = 8 * vs.n;
+  const int64_t chunk = A.max_terms / per;
+  if (n == 0 || P == 0 || chunk == 0) return hipSuccess;
+  for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+    const int64_t m = n - i0 < chunk ? n - i0 : chunk;
+    irf_launch(k_query_terms, dim3(grid_of(m, 256)), dim3(256), 0, s, vs, pos, nrm, view, i0, m, gout,
+               (Term*)A.terms, A.keys[0], P);
+    hipError_t e = gather_batch(vs, A, m * per, P, P, G, nullptr, s);
+    if (e != hipSuccess) return e;
   }
+  return hipSuccess;
+}
+
+hipError_t launch_update_backward(const VolumeSet& prev, SceneGPU sc, FrameScratch fs, const GradSet& Gnew,
+                                  const GradSet& Gprev, float* g_emission, int n_materials, int64_t n_rays,
+                                  const AdjointScratch& A, hipStream_t s) {
+  uint32_t P = 0;
+  for (int v = 0; v < prev.n; v++) P += (uint32_t)prev.v[v].n_probes;
+  if (P == 0) return hipSuccess;
+  irf_launch(k_blend_norms, dim3(kNormsPerVolume, prev.n), dim3(kBwdBlock), 0, s, prev, fs, A.norms);
+  irf_launch(k_blend_backward, dim3(P), dim3(kBwdBlock), 0, s, prev, fs, (const float*)A.norms, Gnew, Gprev);
+  const int per = 8 * prev.n + 1;
+  const int64_t chunk = A.max_terms / per;
+  if (n_rays > fs.max_rays) n_rays = fs.max_rays;
+  if (n_rays <= 0 || chunk == 0) return hipSuccess;
+  const uint32_t K = P + (uint32_t)n_materials;
+  for (int64_t r0 = 0; r0 < n_rays; r0 += chunk) {
+    const int64_t m = n_rays - r0 < chunk ? n_rays - r0 : chunk;
+    irf_launch(k_shade_terms, dim3(grid_of(m, 256)), dim3(256), 0, s, prev, sc, fs, r0, m, (Term*)A.terms, A.keys[0],
+               P, K);
+    hipError_t e = gather_batch(prev, A, m * per, P, K, Gprev, g_emission, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace irf
