@@ -30,7 +30,7 @@ typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
 constexpr int kPB = 8;            // probes per workgroup
 constexpr int kRSplit = 4;        // workgroups per probe block (row tiles split)
-constexpr int kTilesPerWave = 16 / (4 * kRSplit);   // 16 row tiles over kRSplit workgroups of 4 waves
+static_assert(kRSplit * 4 == 16, "one row tile per wave: 16 row tiles over kRSplit workgroups of 4 waves");
 constexpr int kKC = 256;          // rays per LDS chunk
 constexpr int kBlendMmaBlock = 256;
 constexpr int kBfStride = 49;     // float32 B tile: [k][48 + 1]
@@ -144,38 +144,88 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
     s_fresh[threadIdx.x] = real && fs.probe_pos[gslot].w != 0.0f;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // this wave's row tiles: the workgroup owns tiles rt = split, split + kRSplit, ...
-  // (16 / kRSplit of 16) and wave w takes the w-th, (w+4)-th, ... of those
-  int rt_list[kTilesPerWave];
-#pragma unroll
-  for (int i = 0; i < kTilesPerWave; i++) rt_list[i] = split + kRSplit * (wave + 4 * i);
-  v4f acc[kTilesPerWave][2];
-#pragma unroll
-  for (int i = 0; i < kTilesPerWave; i++)
-#pragma unroll
-    for (int j = 0; j < 2; j++) acc[i][j] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  // this wave's row tile: the workgroup owns tiles split, split + kRSplit, ...
+  // and wave w takes the w-th of those
+  const int rt = split + kRSplit * wave;
+  const bool irr_tile = rt < 3;
   const float4* rays = fs.rays + C.ray_base[v] + (int64_t)slot0 * N;
   typedef Mma<MODE> M;
   constexpr int kRound = M::KB * M::KSTEP;   // rays per round of A fragments
-  static_assert(kKC % kRound == 0, "whole rounds per chunk");
+  constexpr int kRounds = kKC / kRound;      // rounds per chunk
+  constexpr int kStage = kPB * kKC / kBlendMmaBlock;   // rays each thread stages per chunk
+  static_assert(kKC % kRound == 0 && (kPB * kKC) % kBlendMmaBlock == 0, "whole rounds and stages per chunk");
   const char* wbase = (const char*)fs.weights + V.weight_base;
+  // Every global read that does not depend on another is issued up front, so
+  // that one memory latency, not four, precedes the products: the wave's A
+  // fragments and this thread's rays for the chunk (registers until the LDS
+  // is free), the rows' reciprocal sums; then, once the probe slots are
+  // known, the epilogue's old texels.
+  typename M::A a[kRounds * M::KB];
+  float4 rv[kStage];
+  auto issue = [&](int kc) {
+    const int kn = min(kKC, N - kc);
+    const int rounds = (kn + kRound - 1) / kRound;
+#pragma unroll
+    for (int r0 = 0; r0 < kRounds; r0++)
+      if (r0 < rounds)
+#pragma unroll
+        for (int j = 0; j < M::KB; j++)
+          a[r0 * M::KB + j] = M::load_a(wbase, rt, kc + r0 * kRound + j * M::KSTEP, N, lane);
+#pragma unroll
+    for (int i = 0; i < kStage; i++) {
+      const int e = (int)threadIdx.x + i * kBlendMmaBlock;
+      const int p = e / kn, k = e - p * kn;
+      rv[i] = e < kPB * kn && p < np ? rays[(int64_t)p * N + kc + k] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  };
+  issue(0);
+  const float* inv = fs.inv_row_sum + v * kRows;
+  float sc[4];
+#pragma unroll
+  for (int r = 0; r < 4; r++) sc[r] = inv[rt * 16 + 4 * (lane / 16) + r];
+  __syncthreads();   // s_q / s_fresh
+  // old texels: irradiance lanes p < 8 hold rows 4 (lane / 16) + r of probe
+  // p; distance lanes channel c of probe p for the same rows
+  float3 old_irr[4];
+  float old_dist[4];
+  {
+    const int p = lane % 16;
+    const int pd = p < 8 ? p : p - 8, cd = p < 8 ? 0 : 1;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int row = rt * 16 + 4 * (lane / 16) + r;
+      old_irr[r] = f3(0.0f, 0.0f, 0.0f);
+      old_dist[r] = 0.0f;
+      if (irr_tile) {
+        if (p < np && row < 36) old_irr[r] = load_irr(V, s_q[p] * kIrrTexels + (row / 6 + 1) * kIrrTile + row % 6 + 1);
+      } else {
+        const int rr = row - kIrrRows;
+        if (pd < np && rr < 196) old_dist[r] = load_ch(V, false, s_q[pd], rr % 14 + 1, rr / 14 + 1, cd);
+      }
+    }
+  }
+  v4f acc[2] = {v4f{0.0f, 0.0f, 0.0f, 0.0f}, v4f{0.0f, 0.0f, 0.0f, 0.0f}};
   for (int kc = 0; kc < N; kc += kKC) {
+    if (kc > 0) issue(kc);
     const int kn = min(kKC, N - kc);
     // the products run over whole rounds with no per-step guard (a guarded
     // step splits the accumulator chain into basic blocks); rays from kn to
     // the round's end are zero in B
     const int rounds = (kn + kRound - 1) / kRound;
     const int kpad = rounds * kRound;
-    __syncthreads();
+    __syncthreads();   // the previous chunk's products are done with the LDS
     for (int e = threadIdx.x; e < kPB * (kpad - kn); e += kBlendMmaBlock) {
       const int p = e / (kpad - kn), k = kn + e % (kpad - kn);
 #pragma unroll
       for (int c = 0; c < 6; c++)
         if (c != 3) store_b<MODE>(lds, k, 8 * c + p, 0.0f);
     }
-    for (int e = threadIdx.x; e < kPB * kn; e += kBlendMmaBlock) {
-      int p = e / kn, k = e - p * kn;
-      float4 r = p < np ? rays[(int64_t)p * N + kc + k] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int i = 0; i < kStage; i++) {
+      const int e = (int)threadIdx.x + i * kBlendMmaBlock;
+      if (e >= kPB * kn) continue;
+      const int p = e / kn, k = e - p * kn;
+      const float4 r = rv[i];
       // columns: R of probe p at p, G at 8 + p, B at 16 + p (24..31 stay
       // zero from the kernel's start), so one lane of the epilogue holds R and
       // B of a texel and G is 8 lanes up
@@ -186,60 +236,46 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
       store_b<MODE>(lds, k, 40 + p, r.w * r.w);
     }
     __syncthreads();
+    if (irr_tile) {
+      // irradiance rows: two column tiles (R, G | B, 0), chains interleaved
 #pragma unroll
-    for (int i = 0; i < kTilesPerWave; i++) {
-      const int rt = rt_list[i];
-      if (rt < 3) {
-        // irradiance rows: two column tiles (R, G | B, 0), chains interleaved
-        for (int r0 = 0; r0 < rounds; r0++) {
-          const int k0 = r0 * kRound;
-          typename M::A a[M::KB];
-#pragma unroll
-          for (int j = 0; j < M::KB; j++) a[j] = M::load_a(wbase, rt, kc + k0 + j * M::KSTEP, N, lane);
+      for (int r0 = 0; r0 < kRounds; r0++)
+        if (r0 < rounds)
 #pragma unroll
           for (int j = 0; j < M::KB; j++) {
-            acc[i][0] = M::mma(a[j], M::load_b(lds, 0, k0 + j * M::KSTEP, lane), acc[i][0]);
-            acc[i][1] = M::mma(a[j], M::load_b(lds, 16, k0 + j * M::KSTEP, lane), acc[i][1]);
+            const int k = r0 * kRound + j * M::KSTEP;
+            acc[0] = M::mma(a[r0 * M::KB + j], M::load_b(lds, 0, k, lane), acc[0]);
+            acc[1] = M::mma(a[r0 * M::KB + j], M::load_b(lds, 16, k, lane), acc[1]);
           }
-        }
-      } else {
-        // distance rows: one column tile (d, d^2)
-        for (int r0 = 0; r0 < rounds; r0++) {
-          const int k0 = r0 * kRound;
-          typename M::A a[M::KB];
+    } else {
+      // distance rows: one column tile (d, d^2)
 #pragma unroll
-          for (int j = 0; j < M::KB; j++) a[j] = M::load_a(wbase, rt, kc + k0 + j * M::KSTEP, N, lane);
+      for (int r0 = 0; r0 < kRounds; r0++)
+        if (r0 < rounds)
 #pragma unroll
           for (int j = 0; j < M::KB; j++)
-            acc[i][0] = M::mma(a[j], M::load_b(lds, 32, k0 + j * M::KSTEP, lane), acc[i][0]);
-        }
-      }
+            acc[0] = M::mma(a[r0 * M::KB + j], M::load_b(lds, 32, r0 * kRound + j * M::KSTEP, lane), acc[0]);
     }
   }
   // epilogue: lane holds rows rt*16 + 4*(lane/16) + r, column col_base + lane%16
-  const float* inv = fs.inv_row_sum + v * kRows;
+  if (irr_tile) {
+    // irradiance rows: lane%16 = p < 8 holds R (tile 0) and B (tile 1) of
+    // probe p; G comes from 8 lanes up.  The whole texel is updated at once
+    // (encoding, per-texel hysteresis) by that lane.
+    const int p = lane % 16;
+    float gch[4];
 #pragma unroll
-  for (int i = 0; i < kTilesPerWave; i++) {
-    const int rt = rt_list[i];
-    if (rt < 3) {
-      // irradiance rows: lane%16 = p < 8 holds R (tile 0) and B (tile 1) of
-      // probe p; G comes from 8 lanes up.  The whole texel is updated at once
-      // (encoding, per-texel hysteresis) by that lane.
-      const int p = lane % 16;
-      float gch[4];
-#pragma unroll
-      for (int r = 0; r < 4; r++) gch[r] = __shfl_down(acc[i][0][r], 8, 16);
-      if (p >= 8 || p >= np) continue;
+    for (int r = 0; r < 4; r++) gch[r] = __shfl_down(acc[0][r], 8, 16);
+    if (p < 8 && p < np) {
       const int q = s_q[p];
       const float a = s_fresh[p] ? 0.0f : V.alpha_irr;
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int row = rt * 16 + 4 * (lane / 16) + r;
-        const float sc = inv[row];
-        if (sc == 0.0f) continue;   // padding row, or no ray with positive weight: keep the texel
+        if (sc[r] == 0.0f) continue;   // padding row, or no ray with positive weight: keep the texel
         const int x = row % 6 + 1, y = row / 6 + 1;
-        const float3 old = load_irr(V, q * kIrrTexels + y * kIrrTile + x);
-        const float3 val = irr_texel_update(V, a, old, f3(acc[i][0][r] * sc, gch[r] * sc, acc[i][1][r] * sc));
+        const float3 val =
+            irr_texel_update(V, a, old_irr[r], f3(acc[0][r] * sc[r], gch[r] * sc[r], acc[1][r] * sc[r]));
         store_irr4(V, q, x, y, val);
         if (y == 1) store_irr4(V, q, 7 - x, 0, val);
         if (y == 6) store_irr4(V, q, 7 - x, 7, val);
@@ -250,33 +286,33 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
         if (x == 6 && y == 1) store_irr4(V, q, 0, 7, val);
         if (x == 1 && y == 1) store_irr4(V, q, 7, 7, val);
       }
-      continue;
     }
+  } else {
     // distance rows: one column tile, d of probe p at 32 + p, d^2 at 40 + p
     const int col = 32 + lane % 16;
     const int p = col - 32 < 8 ? col - 32 : col - 40;
     const int c = col - 32 < 8 ? 0 : 1;
-    if (p >= np) continue;
-    const int q = s_q[p];
-    const float a = s_fresh[p] ? 0.0f : V.alpha_dist;
+    if (p < np) {
+      const int q = s_q[p];
+      const float a = s_fresh[p] ? 0.0f : V.alpha_dist;
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-      const int row = rt * 16 + 4 * (lane / 16) + r;
-      const float sc = inv[row];
-      if (sc == 0.0f) continue;
-      const float nv = acc[i][0][r] * sc;
-      const int rr = row - kIrrRows;
-      const int x = rr % 14 + 1, y = rr / 14 + 1;
-      const float val = a * load_ch(V, false, q, x, y, c) + (1.0f - a) * nv;
-      store_dist(V, q, x, y, c, val);
-      if (y == 1) store_dist(V, q, 15 - x, 0, c, val);
-      if (y == 14) store_dist(V, q, 15 - x, 15, c, val);
-      if (x == 1) store_dist(V, q, 0, 15 - y, c, val);
-      if (x == 14) store_dist(V, q, 15, 15 - y, c, val);
-      if (x == 14 && y == 14) store_dist(V, q, 0, 0, c, val);
-      if (x == 1 && y == 14) store_dist(V, q, 15, 0, c, val);
-      if (x == 14 && y == 1) store_dist(V, q, 0, 15, c, val);
-      if (x == 1 && y == 1) store_dist(V, q, 15, 15, c, val);
+      for (int r = 0; r < 4; r++) {
+        const int row = rt * 16 + 4 * (lane / 16) + r;
+        if (sc[r] == 0.0f) continue;
+        const float nv = acc[0][r] * sc[r];
+        const int rr = row - kIrrRows;
+        const int x = rr % 14 + 1, y = rr / 14 + 1;
+        const float val = a * old_dist[r] + (1.0f - a) * nv;
+        store_dist(V, q, x, y, c, val);
+        if (y == 1) store_dist(V, q, 15 - x, 0, c, val);
+        if (y == 14) store_dist(V, q, 15 - x, 15, c, val);
+        if (x == 1) store_dist(V, q, 0, 15 - y, c, val);
+        if (x == 14) store_dist(V, q, 15, 15 - y, c, val);
+        if (x == 14 && y == 14) store_dist(V, q, 0, 0, c, val);
+        if (x == 1 && y == 14) store_dist(V, q, 15, 0, c, val);
+        if (x == 14 && y == 1) store_dist(V, q, 0, 15, c, val);
+        if (x == 1 && y == 1) store_dist(V, q, 15, 15, c, val);
+      }
     }
   }
   // Newly states are promoted once blended (the Newly flag of this frame is
