@@ -33,6 +33,9 @@ def lib(f32: bool = False):
         path = _build.LIB32 if f32 else _build.LIB
         if not os.path.exists(path):
             _build.build()
+        if not _build.stamp_ok(path):
+            raise RuntimeError(f"{path} was not built from the oracle's sources beside it: rebuild it with "
+                               "`python oracle/build.py`")
         L = C.CDLL(path)
         _declare(L)
         if f32:

@@ -17,6 +17,26 @@ FLAGS = [
 ]
 
 
+STAMP = LIB + ".sha256"
+
+
+def source_hash() -> str:
+    """sha256 over every source and header the library is built from, and the
+    compiler command; written beside the library by build() and compared by
+    the loader, so that a library built from other sources is refused."""
+    import glob
+    import hashlib
+    h = hashlib.sha256(" ".join([HIPCC] + FLAGS + SOURCES).encode())
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    files = [os.path.join(CSRC, s) for s in SOURCES] + sorted(glob.glob(os.path.join(CSRC, "*.h")))
+    files += sorted(glob.glob(os.path.join(inc, "*.h")))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     cmd = [HIPCC] + FLAGS + ["-x", "hip"] + srcs + ["-o", LIB]
@@ -29,6 +49,8 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed")
     if verbose and err.strip():
         sys.stderr.write(err + "\n")
+    with open(STAMP, "w") as f:
+        f.write(source_hash() + "\n")
     return LIB
 
 

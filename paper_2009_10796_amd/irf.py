@@ -112,12 +112,19 @@ _lib = None
 
 
 def load() -> C.CDLL:
-    """Loads libirf.so (building it first only if it is absent)."""
+    """Loads libirf.so (building it first only if it is absent).  A library
+    built from other sources than the ones beside it (its build stamp does
+    not match them) is refused: rebuild it."""
     global _lib
     if _lib is None:
+        from . import build as _build
         if not os.path.exists(LIB_PATH):
-            from . import build as _build
             _build.build()
+        stamp = open(_build.STAMP).read().strip() if os.path.exists(_build.STAMP) else None
+        if stamp != _build.source_hash():
+            raise RuntimeError(f"{LIB_PATH} was not built from the sources beside it "
+                               f"({'no build stamp' if stamp is None else 'sources changed since'}): rebuild it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
         lib = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(lib, name)

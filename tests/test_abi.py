@@ -103,3 +103,19 @@ def test_tracking_volume_needs_five_probes_per_axis():
     assert e.value.status == irf.E_INVALID
     d.counts = (5, 5, 6)
     irf.validate_volume_desc(d)
+
+
+def test_library_built_from_other_sources_is_refused(monkeypatch):
+    """The loaders compare each library's build stamp with the sources beside
+    it and refuse a library built from other sources."""
+    import oracle
+    from oracle import build as obuild
+    from paper_2009_10796_amd import build as lbuild
+    monkeypatch.setattr(irf, "_lib", None)
+    monkeypatch.setattr(lbuild, "source_hash", lambda: "0" * 64)
+    with pytest.raises(RuntimeError, match="not built from the sources"):
+        irf.load()
+    monkeypatch.setattr(oracle, "_lib", None)
+    monkeypatch.setattr(obuild, "source_hash", lambda extra: "0" * 64)
+    with pytest.raises(RuntimeError, match="not built from the oracle's sources"):
+        oracle.lib()
