@@ -300,16 +300,21 @@ irf_status irf_query_irradiance(irf_ctx* ctx, const float* pos, const float* nrm
    how the shadow rays are spread over lanes: 0 in batches of 64 tasks (a
    wave moves on when the longest ray of its batch ends); n in [1, 64] a
    fixed range of tasks per wave whose lanes take the range's next task
-   whenever at least n of them are idle.  Results do not depend on any of
-   these.  Values are normally chosen by the autotuner
-   (paper_2009_10796_amd/autotune.py).  IRF_E_INVALID for negative values or
-   shadow_refill above 64. */
+   whenever at least n of them are idle.  blend_rsplit is the blend's tile
+   shape: how many workgroups share one block of 8 probes (1, 2 or 4; 0
+   selects 4), each taking 16 / rsplit of the 16 row tiles of the weight
+   matrix, so the block's rays are staged rsplit times and each wave
+   multiplies 4 / rsplit row tiles.  Results do not depend on any of these.
+   Values are normally chosen by the autotuner
+   (paper_2009_10796_amd/autotune.py).  IRF_E_INVALID for negative values,
+   shadow_refill above 64 or blend_rsplit not in {0, 1, 2, 4}. */
 typedef struct {
   int32_t trace_blocks;
   int32_t shadow_blocks;
   int32_t shade_blocks;
   int32_t blend_blocks;
   int32_t shadow_refill;
+  int32_t blend_rsplit;
 } irf_tuning;
 irf_status irf_set_tuning(irf_ctx* ctx, const irf_tuning* tuning);
 irf_status irf_get_tuning(const irf_ctx* ctx, irf_tuning* tuning);

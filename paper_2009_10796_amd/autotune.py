@@ -3,8 +3,9 @@
 For each persistent kernel of the update (probe-ray traversal, shadow-ray
 traversal, hit shading, matrix-core blend) it times a set of grid sizes
 (multiples of the compute-unit count, plus 0 = one workgroup per work unit),
-and for the shadow rays how their tasks are spread over lanes (batches of
-64, or per-wave ranges with lane refill at an idle-lane threshold), on the
+for the shadow rays how their tasks are spread over lanes (batches of 64, or
+per-wave ranges with lane refill at an idle-lane threshold), and for the
+blend its tile shape (1, 2 or 4 workgroups per block of 8 probes), on the
 live workload with the library's own kernel timing, and keeps the fastest.
 The choice is returned as a dict, can be saved as JSON and applied to
 another context with ``apply``.  Tuning runs real frames: call it during
@@ -18,7 +19,7 @@ from typing import Dict, Iterable, Optional
 
 SHADOW = ("shadow", "shadow_refill")   # the kernel the shadow rays run on, by refill mode
 KNOBS = (("trace_blocks", ("trace",)), ("shadow_refill", SHADOW), ("shadow_blocks", SHADOW),
-         ("shade_blocks", ("shade",)), ("blend_blocks", ("blend_mma",)))
+         ("shade_blocks", ("shade",)), ("blend_rsplit", ("blend_mma",)), ("blend_blocks", ("blend_mma",)))
 
 
 def candidates(cu: int, knob: str = "trace_blocks") -> list:
@@ -27,6 +28,8 @@ def candidates(cu: int, knob: str = "trace_blocks") -> list:
     lane refill the idle-lane threshold (0 = batches of 64)."""
     if knob == "shadow_refill":
         return [0, 4, 8, 16, 32]
+    if knob == "blend_rsplit":
+        return [4, 2, 1]
     return [0] + [cu * k for k in (1, 2, 4, 8, 16)]
 
 

@@ -104,7 +104,7 @@ struct irf_ctx {
   DevBuf<unsigned long long> reloc_keys;
   bool frame_done = false;
   bool diff_frame = false;   // the last frame saved its inputs for the adjoint
-  Tuning tune = {0, 0, 0, 0, 0};
+  Tuning tune = {0, 0, 0, 0, 0, 0};
   // adjoint: the frame's input atlases and states, saved by each update
   bool diff = false;
   DevBuf<char> saved;
@@ -402,7 +402,7 @@ hipError_t enqueue_frame_on(irf_ctx* c, const float* rotation, hipStream_t st, h
   }
   if (any_mma) {
     ProfScope p(c, "blend_mma", st);
-    launch_blend_mma(vs, fs, c->tune.blend_blocks, st);
+    launch_blend_mma(vs, fs, c->tune.blend_blocks, c->tune.blend_rsplit, st);
   }
   return hipSuccess;
 }
@@ -1098,11 +1098,14 @@ irf_status irf_set_tuning(irf_ctx* c, const irf_tuning* t) {
     return fail(IRF_E_INVALID, "tuning values must be >= 0");
   if (t->shadow_refill < 0 || t->shadow_refill > 64)
     return fail(IRF_E_INVALID, "shadow_refill must be in [0, 64]");
+  if (t->blend_rsplit != 0 && t->blend_rsplit != 1 && t->blend_rsplit != 2 && t->blend_rsplit != 4)
+    return fail(IRF_E_INVALID, "blend_rsplit must be 0, 1, 2 or 4");
   c->tune.trace_blocks = t->trace_blocks;
   c->tune.shadow_blocks = t->shadow_blocks;
   c->tune.shade_blocks = t->shade_blocks;
   c->tune.blend_blocks = t->blend_blocks;
   c->tune.shadow_refill = t->shadow_refill;
+  c->tune.blend_rsplit = t->blend_rsplit;
   return IRF_OK;
 }
 
@@ -1113,6 +1116,7 @@ irf_status irf_get_tuning(const irf_ctx* c, irf_tuning* t) {
   t->shade_blocks = c->tune.shade_blocks;
   t->blend_blocks = c->tune.blend_blocks;
   t->shadow_refill = c->tune.shadow_refill;
+  t->blend_rsplit = c->tune.blend_rsplit;
   return IRF_OK;
 }
 

@@ -260,11 +260,14 @@ __device__ __forceinline__ float texel_alpha(const VolumeGPU& V, float alpha, fl
 }
 
 // The new stored irradiance texel (Eq. U in the stored encoding) from the
-// stored one and the new normalised mean.
+// stored one and the new normalised mean.  The blend is written as one
+// fused multiply-add over a rounded product, so that every kernel (and every
+// tile shape) that inlines it rounds the same way.
 __device__ __forceinline__ float3 irr_texel_update(const VolumeGPU& V, float alpha, float3 old, float3 mean) {
   float3 e = f3(encode_irr(V, mean.x), encode_irr(V, mean.y), encode_irr(V, mean.z));
   float a = texel_alpha(V, alpha, e, old);
-  return f3(a * old.x + (1.0f - a) * e.x, a * old.y + (1.0f - a) * e.y, a * old.z + (1.0f - a) * e.z);
+  const float b = 1.0f - a;
+  return f3(fmaf(a, old.x, b * e.x), fmaf(a, old.y, b * e.y), fmaf(a, old.z, b * e.z));
 }
 
 template <bool F16>

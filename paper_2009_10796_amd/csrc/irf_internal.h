@@ -99,6 +99,7 @@ struct Tuning {
   int32_t shade_blocks;
   int32_t blend_blocks;
   int32_t shadow_refill;   // 0: shadow rays in batches of 64; n > 0: lane refill at n idle lanes
+  int32_t blend_rsplit;    // workgroups per probe block of the blend: 1, 2 or 4 (0: 4)
 };
 
 // Dynamic-object boxes (state step and classification wake rule).
@@ -210,7 +211,7 @@ void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch 
                    hipStream_t s);
 void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s);
 void launch_blend(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
-void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, int grid, hipStream_t s);
+void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, int grid, int rsplit, hipStream_t s);
 void launch_query(const VolumeSet& vs, const float* pos, const float* nrm, const float* view, int64_t n,
                   float* out, hipStream_t s);
 void launch_relocate(const VolumeSet& vs, SceneGPU sc, const float* rotation, float limit, int32_t* back,

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kBlendBlock) void k_blend_f32(VolumeSet vs, FrameSc
       int idx = q * kDistTexels + y * kDistTile + x;
       float2 old = load_dist(V, idx);
       float n1 = m1 / W, n2 = m2 / W;
-      float2 val = make_float2(a * old.x + (1.0f - a) * n1, a * old.y + (1.0f - a) * n2);
+      float2 val = make_float2(fmaf(a, old.x, (1.0f - a) * n1), fmaf(a, old.y, (1.0f - a) * n2));
       store_with_border<kDistTile>(x, y, [&](int xx, int yy) {
         int j = q * kDistTexels + yy * kDistTile + xx;
         if (V.atlas_f16) {

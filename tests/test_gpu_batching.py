@@ -37,11 +37,12 @@ def test_persistent_grids_match_default(torch):
     # tiny persistent grids: every workgroup loops over many work items
     B.set_tuning(trace_blocks=7, shadow_blocks=5, shade_blocks=3, blend_blocks=2)
     # shadow rays by lane refill: per-wave task ranges, refilled at 1, 13 or
-    # 64 idle lanes, on grids from one wave's worth to many
+    # 64 idle lanes, on grids from one wave's worth to many; the blend's tile
+    # shapes (1 or 2 workgroups per block of 8 probes, on tiny and default grids)
     Cs = []
-    for refill, grid in ((1, 3), (13, 64), (64, 0)):
+    for refill, grid, rsplit, bgrid in ((1, 3, 1, 0), (13, 64, 2, 5), (64, 0, 1, 3)):
         c = irf.build_workload(w)
-        c.set_tuning(shadow_refill=refill, shadow_blocks=grid)
+        c.set_tuning(shadow_refill=refill, shadow_blocks=grid, blend_rsplit=rsplit, blend_blocks=bgrid)
         Cs.append(c)
     for c in (A, B, *Cs):
         c.classify(w.classify_rotations)
@@ -110,7 +111,8 @@ def test_autotuner_keeps_results(torch):
         c.classify(w.classify_rotations)
         c.set_lights(S.sun_for_frame(0))
     chosen = autotune.autotune(B, S.rotations(3, 200, start_frame=100), frames_per_candidate=1)
-    assert set(chosen) == {"trace_blocks", "shadow_refill", "shadow_blocks", "shade_blocks", "blend_blocks"}
+    assert set(chosen) == {"trace_blocks", "shadow_refill", "shadow_blocks", "shade_blocks", "blend_rsplit",
+                           "blend_blocks"}
     # after tuning, the same frames from the same state agree with the default launch shapes
     for c in (A, B):
         for v in c.volumes:

@@ -98,3 +98,29 @@ def test_low_precision_blend_error_city(torch, mode, atlas16):
     if mode == "f16" and not atlas16:
         assert max(e[c][0] for c in CHANNELS[:3]) <= 1e-3, e    # the precision gate
     ctx.close()
+
+
+@pytest.mark.parametrize("mode", ["f32", "bf16", "f16"])
+def test_blend_tile_shapes_are_bit_exact(torch, mode):
+    """The blend's tile shape (1, 2 or 4 workgroups per block of 8 probes)
+    changes which workgroup multiplies a row tile, not the order of its
+    products: atlases and states after two city frames are the same bits."""
+    from paper_2009_10796_amd import irf
+    w = S.config1(gbuffer=False)
+    for d in w.volumes:
+        d.blend = mode
+    out = {}
+    for rsplit in (4, 2, 1):
+        ctx = irf.build_workload(w)
+        ctx.set_tuning(blend_rsplit=rsplit)
+        ctx.classify(w.classify_rotations)
+        for f in (1, 2):
+            ctx.update_probes(w.frame_rotation(f))
+        torch.cuda.synchronize()
+        out[rsplit] = [(v.irradiance.cpu().numpy().copy(), v.distance.cpu().numpy().copy(),
+                        v.states.cpu().numpy().copy()) for v in ctx.volumes]
+        ctx.close()
+    for rsplit in (2, 1):
+        for a, b in zip(out[4], out[rsplit]):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y), (mode, rsplit)
