@@ -35,13 +35,15 @@ def candidates(cu: int, knob: str = "trace_blocks") -> list:
 
 def autotune(ctx, rotations: Iterable, frames_per_candidate: int = 3, cu: Optional[int] = None,
              step=None) -> Dict[str, int]:
-    """Tunes ctx in place.  `rotations` supplies one rotation per frame run;
-    `step(R)` runs one frame (default: ctx.update_probes)."""
+    """Tunes ctx in place.  `rotations` supplies the frames' rotations (used
+    in turn, from the start again when they run out); `step(R)` runs one
+    frame (default: ctx.update_probes)."""
+    import itertools
     torch = ctx.torch
     if cu is None:
         cu = torch.cuda.get_device_properties(ctx.device).multi_processor_count
     step = step or ctx.update_probes
-    rot = iter(rotations)
+    rot = itertools.cycle(list(rotations))
     chosen = {}
     report = {}
     for knob, kernels in KNOBS:
