@@ -17,6 +17,8 @@ compared as |g - o| <= 1e-5 a + s (+ 1e-7 of the array's largest |o|).  s is
 large exactly where the Chebyshev factor is ill-conditioned (variance near
 zero with r close to mu), as for the forward parity.
 """
+from types import SimpleNamespace
+
 import numpy as np
 import pytest
 
@@ -355,4 +357,101 @@ def test_backward_is_deterministic(torch, frame):
     for r in runs[1:]:
         for a, b in zip(runs[0], r):
             assert torch.equal(a, b)
+    ctx.close()
+
+
+def test_cascade_backward_matches_oracle(torch):
+    """Two cascaded volumes (Section "Multiple Probe Volumes"): a 6x4x6 volume
+    at 1 m inside a 6x4x6 volume at 2.5 m, 64 rays each, in the city with 64
+    emitters; 2,000 surface points spread over the inner volume, its
+    fall-off band and the outer volume alone, so each query's gradient splits
+    between the volumes by the cascade weights.  Frame 1 (oracle, rounded to
+    float32) is A0; frame 2 is differentiated.  Query backward on the
+    oracle's A1 and frame backward from the oracle's upstream gradient are
+    compared per volume; rays the GPU decided otherwise are substituted in
+    the oracle's frame (parity protocol), so both hold the same hits."""
+    import oracle
+    from paper_2009_10796_amd import irf
+    from tests import parity as P
+    w = S.config4(n_points=20000)
+    w.volumes = [S.VolumeDesc(origin=(5.5, 0.5, 5.5), spacing=(1.0, 1.0, 1.0), counts=(6, 4, 6), rays_per_probe=64),
+                 S.VolumeDesc(origin=(1.5, 0.5, 1.5), spacing=(2.5, 2.5, 2.5), counts=(6, 4, 6), rays_per_probe=64)]
+    q = w.queries
+    sel = np.all((q.pos >= [4.5, 0.0, 4.5]) & (q.pos <= [11.5, 4.5, 11.5]), axis=1)
+    q = S.Queries(q.pos[sel][:2000], q.nrm[sel][:2000], q.view[sel][:2000])
+    assert len(q.pos) == 2000
+    osc = oracle.Scene(w.scene)
+    A0 = [oracle.Volume(d) for d in w.volumes]
+    oracle.classify(osc, A0, w.classify_rotations)
+    oracle.update_frame(osc, w.lights, A0, w.frame_rotation(1), records=False)
+    for v in A0:
+        v.irr[:] = v.irr.astype(np.float32)
+        v.dist[:] = v.dist.astype(np.float32)
+        v.irr_kappa[:] = 0.0
+        v.dist_kappa[:] = 0.0
+    ctx = irf.build_workload(w)
+    dev = ctx.device
+    _load_a0(torch, ctx, SimpleNamespace(A0=A0))
+    ctx.set_differentiable(True)
+    R = w.frame_rotation(2)
+    ctx.update_probes(R)
+    torch.cuda.synchronize()
+    rec_g = np.concatenate([ctx.ray_records(v) for v in range(2)])
+    A1 = oracle.copy_volumes(A0)
+    rec_o, rep = P.oracle_frame(osc, w.lights, A1, R, rec_g["tri"], rec_g["vis"])
+    print(f"[adjoint-cascade] frame: {rep.line()}", flush=True)
+    assert rep.unflagged_flips == 0
+    # query backward on the oracle's A1 rounded to float32
+    for o in A1:
+        o.irr[:] = o.irr.astype(np.float32)
+        o.dist[:] = o.dist.astype(np.float32)
+        o.irr_kappa[:] = 0.0
+        o.dist_kappa[:] = 0.0
+    gE = S.Stream(955, 1).uniform(3 * len(q.pos), -1.0, 1.0).reshape(-1, 3).astype(np.float32)
+    g1i, g1d = _zeros(A1)
+    a1i, a1d = _zeros(A1)
+    s1i, s1d = _zeros(A1)
+    oracle.query_backward(A1, q.pos, q.nrm, q.view, gE.astype(np.float64), g1i, g1d, a1i, a1d, s1i, s1d)
+    saved = [(gv.irradiance.clone(), gv.distance.clone()) for gv in ctx.volumes]
+    for gv, o in zip(ctx.volumes, A1):
+        gv.irradiance[..., :3].copy_(torch.from_numpy(o.irr.astype(np.float32)))
+        gv.distance.copy_(torch.from_numpy(o.dist.astype(np.float32)))
+    pos, nrm, view = (torch.from_numpy(a).to(dev) for a in (q.pos, q.nrm, q.view))
+    Gi, Gd = _gpu_zeros(torch, ctx)
+    ctx.query_backward(pos, nrm, view, torch.from_numpy(gE).to(dev), Gi, Gd)
+    torch.cuda.synchronize()
+    for v in range(2):
+        assert np.abs(g1i[v]).max() > 0 and np.abs(g1d[v]).max() > 0, v    # both volumes take gradient
+        assert _close(Gi[v].cpu().numpy()[..., :3], g1i[v], a1i[v], s1i[v], name=f"cascade query dE/dirr v{v}")
+        assert _close(Gd[v].cpu().numpy(), g1d[v], a1d[v], s1d[v], name=f"cascade query dE/ddist v{v}")
+    for gv, (a, b) in zip(ctx.volumes, saved):
+        gv.irradiance.copy_(a)
+        gv.distance.copy_(b)
+    # frame backward from the oracle's upstream (float32)
+    g1i = [g.astype(np.float32).astype(np.float64) for g in g1i]
+    g1d = [g.astype(np.float32).astype(np.float64) for g in g1d]
+    prev = oracle.copy_volumes(A0)
+    oracle.state_step(osc, prev)
+    g0i, g0d = _zeros(prev)
+    a0i, a0d = _zeros(prev)
+    s0i, s0d = _zeros(prev)
+    ge_o = np.zeros_like(w.scene.emission, dtype=np.float64)
+    osc.set_emission(w.scene.emission.astype(np.float64))
+    oracle.update_backward(osc, prev, R, rec_o, g1i, g1d, g0i, g0d, ge_o, a_prev_irr=a0i, a_prev_dist=a0d,
+                           s_prev_irr=s0i, s_prev_dist=s0d)
+    Ui, Ud = [], []
+    for gv, a, b in zip(ctx.volumes, g1i, g1d):
+        t = torch.zeros(gv.irradiance.shape, dtype=torch.float32)
+        t[..., :3] = torch.from_numpy(a.astype(np.float32))
+        Ui.append(t.to(dev))
+        Ud.append(torch.from_numpy(b.astype(np.float32)).to(dev))
+    P0i, P0d = _gpu_zeros(torch, ctx)
+    ge = torch.zeros((w.scene.emission.shape[0], 3), dtype=torch.float32, device=dev)
+    ctx.update_backward(Ui, Ud, P0i, P0d, ge)
+    torch.cuda.synchronize()
+    assert np.abs(ge_o).max() > 0
+    assert _close(ge.cpu().numpy(), ge_o, name="cascade dL/demission")
+    for v in range(2):
+        assert _close(P0i[v].cpu().numpy()[..., :3], g0i[v], a0i[v], s0i[v], name=f"cascade dL/dirr0 v{v}")
+        assert _close(P0d[v].cpu().numpy(), g0d[v], a0d[v], s0d[v], name=f"cascade dL/ddist0 v{v}")
     ctx.close()
