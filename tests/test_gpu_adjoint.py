@@ -455,3 +455,86 @@ def test_cascade_backward_matches_oracle(torch):
         assert _close(P0i[v].cpu().numpy()[..., :3], g0i[v], a0i[v], s0i[v], name=f"cascade dL/dirr0 v{v}")
         assert _close(P0d[v].cpu().numpy(), g0d[v], a0d[v], s0d[v], name=f"cascade dL/ddist0 v{v}")
     ctx.close()
+
+
+def test_batched_backward_matches_oracle(torch):
+    """The adjoint's batches: the reduced terrain cascades (four 8x4x8
+    volumes) with 1,024 rays per probe trace 344,064 rays in the
+    differentiated frame, and 300,000 surface points are queried, so both
+    backward passes run in three batches of 2^22 terms (33 per ray, 32 per
+    point).  Every texel and emitter gradient is compared with the oracle's
+    adjoint."""
+    import oracle
+    from paper_2009_10796_amd import irf
+    from tests import parity as P
+    w = S.config3(grid_vertices=97, size=48.0, n_buildings=12, cascade_counts=(8, 4, 8),
+                  spacings=(1.0, 2.0, 4.0, 8.0), rays=1024, center_height=3.0)
+    q = S.surface_points(w.scene, 300000, 7)
+    osc = oracle.Scene(w.scene)
+    A0 = [oracle.Volume(d) for d in w.volumes]
+    oracle.classify(osc, A0, w.classify_rotations)
+    oracle.update_frame(osc, S.sun_for_frame(1), A0, w.frame_rotation(1), records=False)
+    for v in A0:
+        v.irr[:] = v.irr.astype(np.float32)
+        v.dist[:] = v.dist.astype(np.float32)
+        v.irr_kappa[:] = 0.0
+        v.dist_kappa[:] = 0.0
+    ctx = irf.build_workload(w)
+    dev = ctx.device
+    _load_a0(torch, ctx, SimpleNamespace(A0=A0))
+    L2, R = S.sun_for_frame(2), w.frame_rotation(2)
+    ctx.set_lights(L2)
+    ctx.set_differentiable(True)
+    ctx.update_probes(R)
+    torch.cuda.synchronize()
+    rec_g = np.concatenate([ctx.ray_records(v) for v in range(len(w.volumes))])
+    assert len(rec_g) > 2 * (1 << 22) // 33, len(rec_g)           # three batches of rays
+    A1 = oracle.copy_volumes(A0)
+    rec_o, rep = P.oracle_frame(osc, L2, A1, R, rec_g["tri"], rec_g["vis"])
+    print(f"[adjoint-batched] frame: {rep.line()}", flush=True)
+    assert rep.unflagged_flips == 0
+    for o in A1:
+        o.irr[:] = o.irr.astype(np.float32)
+        o.dist[:] = o.dist.astype(np.float32)
+        o.irr_kappa[:] = 0.0
+        o.dist_kappa[:] = 0.0
+    gE = S.Stream(956, 1).uniform(3 * len(q.pos), -1.0, 1.0).reshape(-1, 3).astype(np.float32)
+    g1i, g1d = _zeros(A1)
+    a1i, a1d = _zeros(A1)
+    s1i, s1d = _zeros(A1)
+    oracle.query_backward(A1, q.pos, q.nrm, q.view, gE.astype(np.float64), g1i, g1d, a1i, a1d, s1i, s1d)
+    for gv, o in zip(ctx.volumes, A1):
+        gv.irradiance[..., :3].copy_(torch.from_numpy(o.irr.astype(np.float32)))
+        gv.distance.copy_(torch.from_numpy(o.dist.astype(np.float32)))
+    pos, nrm, view = (torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev) for a in (q.pos, q.nrm, q.view))
+    Gi, Gd = _gpu_zeros(torch, ctx)
+    ctx.query_backward(pos, nrm, view, torch.from_numpy(gE).to(dev), Gi, Gd)
+    torch.cuda.synchronize()
+    for v in range(len(w.volumes)):
+        assert _close(Gi[v].cpu().numpy()[..., :3], g1i[v], a1i[v], s1i[v], name=f"batched query dE/dirr v{v}")
+        assert _close(Gd[v].cpu().numpy(), g1d[v], a1d[v], s1d[v], name=f"batched query dE/ddist v{v}")
+    g1i = [g.astype(np.float32).astype(np.float64) for g in g1i]
+    g1d = [g.astype(np.float32).astype(np.float64) for g in g1d]
+    prev = oracle.copy_volumes(A0)
+    oracle.state_step(osc, prev)
+    g0i, g0d = _zeros(prev)
+    a0i, a0d = _zeros(prev)
+    s0i, s0d = _zeros(prev)
+    ge_o = np.zeros_like(w.scene.emission, dtype=np.float64)
+    oracle.update_backward(osc, prev, R, rec_o, g1i, g1d, g0i, g0d, ge_o, a_prev_irr=a0i, a_prev_dist=a0d,
+                           s_prev_irr=s0i, s_prev_dist=s0d)
+    Ui, Ud = [], []
+    for gv, a, b in zip(ctx.volumes, g1i, g1d):
+        t = torch.zeros(gv.irradiance.shape, dtype=torch.float32)
+        t[..., :3] = torch.from_numpy(a.astype(np.float32))
+        Ui.append(t.to(dev))
+        Ud.append(torch.from_numpy(b.astype(np.float32)).to(dev))
+    P0i, P0d = _gpu_zeros(torch, ctx)
+    ge = torch.zeros((w.scene.emission.shape[0], 3), dtype=torch.float32, device=dev)
+    ctx.update_backward(Ui, Ud, P0i, P0d, ge)
+    torch.cuda.synchronize()
+    assert _close(ge.cpu().numpy(), ge_o, name="batched dL/demission")
+    for v in range(len(w.volumes)):
+        assert _close(P0i[v].cpu().numpy()[..., :3], g0i[v], a0i[v], s0i[v], name=f"batched dL/dirr0 v{v}")
+        assert _close(P0d[v].cpu().numpy(), g0d[v], a0d[v], s0d[v], name=f"batched dL/ddist0 v{v}")
+    ctx.close()
