@@ -313,6 +313,10 @@ __global__ __launch_bounds__(256) void k_gather_pieces(VolumeSet vs, uint32_t P,
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   float* out = nullptr;   // stored sums of a segment of several pieces
   if (n > 1) {
+    // a segment of n > 1 pieces has more than kPieceTerms terms, so its n <
+    // 2 len / kPieceTerms and all stored pieces of a batch number below
+    // 2 x batch terms / kPieceTerms = max_partial; the test keeps the write
+    // inside the buffer regardless
     const uint32_t slot = poffs[k] + j;
     if (slot >= max_partial) return;
     out = partial + (size_t)slot * kSlotFloats;
