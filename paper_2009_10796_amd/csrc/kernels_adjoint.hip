@@ -12,14 +12,15 @@
 //                     (all of it for probes that were not updated) and the
 //                     transposed normalised weights to every ray's radiance
 //  k_shade_terms      per ray: the query terms of the previous-frame query at
-//                     its hit (through albedo) and its emitter's share
+//                     its hit (through albedo) and its emitter record
 //
-// Gradients are summed without atomics, in a fixed order: the terms of a
-// batch (points or rays, in index order) are sorted by probe with a stable
-// radix sort (so a probe's terms stay in point order), and one workgroup per
-// probe adds its terms texel by texel in that order; emitter shares are
-// sorted by material and summed per material in ray order.  Results are the
-// same bit for bit from run to run.  Gradient atlases have the layout of the
+// Gradients are summed without atomics, in a fixed order: the terms and
+// emitter records of a batch (points or rays, in index order) are sorted by
+// key -- probe, then material -- with a stable radix sort (so a key's terms
+// stay in point or ray order); each key's run is cut into pieces of 1,024
+// terms, each piece summed by one workgroup in a fixed order, and a run of
+// several pieces adds its pieces' sums in piece order.  Results are the same
+// bit for bit from run to run.  Gradient atlases have the layout of the
 // atlases (irradiance [P][8][8][4], distance [P][16][16][2], float32) and
 // accumulate (+=).
 #include <hip/hip_runtime.h>
