@@ -45,6 +45,101 @@ struct Term {
 };
 static_assert(sizeof(Term) == 40, "ten words");
 
+// ---- the terms in FP64
+//
+// The reverse pass re-evaluates each query's intermediate values in double
+// precision from the frame's float32 inputs (points, normals, texels, probe
+// grid, ray directions and hit triangles): the Chebyshev factor and its
+// derivatives turn on r - mu and mu2 - mu^2, which cancel, so float32
+// intermediates would move the gradient of an ill-conditioned probe far more
+// than its value.  The gradient is then that of the exact forward at the
+// same float32 inputs, to float32 rounding of each term and of the sums.
+
+struct D3 {
+  double x, y, z;
+};
+__device__ __forceinline__ D3 d3(double x, double y, double z) { return {x, y, z}; }
+__device__ __forceinline__ D3 d3f(float3 v) { return {(double)v.x, (double)v.y, (double)v.z}; }
+__device__ __forceinline__ D3 operator+(D3 a, D3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ D3 operator-(D3 a, D3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ D3 operator*(double s, D3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ double dotd(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ D3 crossd(D3 a, D3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ D3 normalized(D3 a) {
+  const double l = sqrt(dotd(a, a));
+  return l > 0.0 ? (1.0 / l) * a : d3(0.0, 0.0, 0.0);
+}
+
+// Bilinear footprint of direction v in an M x M tile (octahedral map, the
+// interior k = M - 2 cells, taps at floor(c) and floor(c) + 1).
+template <int M>
+__device__ __forceinline__ void footprint_d(D3 v, int& x0, int& y0, double& fx, double& fy) {
+  constexpr int k = M - 2;
+  const double l1 = fabs(v.x) + fabs(v.y) + fabs(v.z);
+  double x = v.x / l1, y = v.y / l1;
+  if (v.z < 0.0) {
+    const double nx = (1.0 - fabs(y)) * (x >= 0.0 ? 1.0 : -1.0);
+    const double ny = (1.0 - fabs(x)) * (y >= 0.0 ? 1.0 : -1.0);
+    x = nx;
+    y = ny;
+  }
+  const double cx = (0.5 * x + 0.5) * k + 0.5, cy = (0.5 * y + 0.5) * k + 0.5;
+  x0 = min(max((int)floor(cx), 0), k);
+  y0 = min(max((int)floor(cy), 0), k);
+  fx = fmin(fmax(cx - (double)x0, 0.0), 1.0);
+  fy = fmin(fmax(cy - (double)y0, 0.0), 1.0);
+}
+
+__device__ __forceinline__ D3 irr_texel_d(const VolumeGPU& V, int idx) {
+  const float4 t = ((const float4*)V.irr)[idx];
+  return d3(t.x, t.y, t.z);
+}
+
+__device__ __forceinline__ D3 position_d(const VolumeGPU& V, int q) {
+  int g[3];
+  logical_index(V, q, g);
+  D3 P = d3((double)V.origin[0] + (double)g[0] * (double)V.spacing[0],
+            (double)V.origin[1] + (double)g[1] * (double)V.spacing[1],
+            (double)V.origin[2] + (double)g[2] * (double)V.spacing[2]);
+  if (V.offsets) P = P + d3(V.offsets[3 * q], V.offsets[3 * q + 1], V.offsets[3 * q + 2]);
+  return P;
+}
+
+// Direction of ray i of an n-ray spherical-Fibonacci pattern under the
+// frame's rotation R, in double (frac(i * golden ratio) from the 0.64
+// fixed-point golden ratio, exact).
+__device__ __forceinline__ D3 sf_direction_d(int i, int n, const float* R) {
+  const uint64_t fr = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+  const double f = (double)(fr >> 11) * 0x1p-53;
+  const double z = 1.0 - (2.0 * i + 1.0) / n;
+  const double r = sqrt(fmax(0.0, 1.0 - z * z));
+  double sn, cs;
+  sincospi(2.0 * f, &sn, &cs);
+  const D3 p = d3(r * cs, r * sn, z);
+  return d3((double)R[0] * p.x + (double)R[1] * p.y + (double)R[2] * p.z,
+            (double)R[3] * p.x + (double)R[4] * p.y + (double)R[5] * p.z,
+            (double)R[6] * p.x + (double)R[7] * p.y + (double)R[8] * p.z);
+}
+
+// Section "Multiple Probe Volumes" cascade weight of X (non-tracking and
+// tracking volumes), in double.
+__device__ __forceinline__ double volume_weight_d(const VolumeGPU& V, D3 X) {
+  const double Xa[3] = {X.x, X.y, X.z};
+  double wv = 1.0;
+  for (int a = 0; a < 3; a++) {
+    if (V.tracking) {
+      const double h = 0.5 * (double)(V.counts[a] - 1) - 1.0;
+      wv *= fmin(fmax(h - fabs(Xa[a] - (double)V.camera[a]) / (double)V.spacing[a], 0.0), 1.0);
+    } else {
+      const double u = (Xa[a] - (double)V.origin[a]) / (double)V.spacing[a];
+      wv *= fmin(fmax(fmin(u, (double)(V.counts[a] - 1) - u), 0.0), 1.0);
+    }
+  }
+  return wv;
+}
+
 // One corner probe of a cage query: its trilinear x backface weight (wtb),
 // full weight (ww, with the Chebyshev factor when r > mu), irradiance sample
 // and distance sample.
@@ -52,41 +147,50 @@ struct Corner {
   bool ok;      // the probe is sampled
   bool cheb;    // the Chebyshev factor applies
   int q;
-  float wtb, ww, r;
-  float2 mm;
-  float3 zd, e;
+  double wtb, ww, r, mu, mu2;
+  D3 zd, e;
 };
 
-__device__ __forceinline__ Corner corner_eval(const VolumeGPU& V, int c, const int* gi, const float* f, float3 X,
-                                              float3 Xb, float3 n) {
+__device__ __forceinline__ Corner corner_eval(const VolumeGPU& V, int c, const int* gi, const double* f, D3 X, D3 Xb,
+                                              D3 n, int ix, int iy, double ifx, double ify) {
   Corner k;
   const int cb0 = c & 1, cb1 = (c >> 1) & 1, cb2 = (c >> 2) & 1;
   k.q = storage_index(V, gi[0] + cb0, gi[1] + cb1, gi[2] + cb2);
   k.ok = sampled_state(V.states[k.q]);
   k.cheb = false;
   if (!k.ok) return k;
-  const float wt = (cb0 ? f[0] : 1.0f - f[0]) * (cb1 ? f[1] : 1.0f - f[1]) * (cb2 ? f[2] : 1.0f - f[2]);
-  const float3 P = probe_position(V, k.q);
-  const float3 toP = normalize_or_zero(P - X);
-  const float h = (1.0f + dot(n, toP)) * 0.5f;
-  k.wtb = wt * fmaf(h, h, 0.2f);
+  const double wt = (cb0 ? f[0] : 1.0 - f[0]) * (cb1 ? f[1] : 1.0 - f[1]) * (cb2 ? f[2] : 1.0 - f[2]);
+  const D3 P = position_d(V, k.q);
+  const D3 toP = normalized(P - X);
+  const double h = (1.0 + dotd(n, toP)) * 0.5;
+  k.wtb = wt * (h * h + 0.2);
   k.ww = k.wtb;
-  const float3 z = Xb - P;
-  k.r = length(z);
-  if (k.r > 0.0f) {
-    k.zd = (1.0f / k.r) * z;
-    k.mm = sample_distance(V, k.q, k.zd);
-    if (k.r > k.mm.x) {
-      const float var = fmaxf(fmaf(-k.mm.x, k.mm.x, k.mm.y), 0.0f);
-      const float dl = k.r - k.mm.x;
-      const float ch = var / fmaf(dl, dl, var);
-      float p = ch;
+  const D3 z = Xb - P;
+  k.r = sqrt(dotd(z, z));
+  if (k.r > 0.0) {
+    k.zd = (1.0 / k.r) * z;
+    int x0, y0;
+    double fx, fy;
+    footprint_d<kDistTile>(k.zd, x0, y0, fx, fy);
+    const float2* t = (const float2*)V.dist + (size_t)k.q * kDistTexels + y0 * kDistTile + x0;
+    const float2 ta = t[0], tc = t[1], td = t[kDistTile], te = t[kDistTile + 1];
+    k.mu = (1.0 - fy) * ((1.0 - fx) * ta.x + fx * tc.x) + fy * ((1.0 - fx) * td.x + fx * te.x);
+    k.mu2 = (1.0 - fy) * ((1.0 - fx) * ta.y + fx * tc.y) + fy * ((1.0 - fx) * td.y + fx * te.y);
+    if (k.r > k.mu) {
+      const double var = fmax(k.mu2 - k.mu * k.mu, 0.0);
+      const double dl = k.r - k.mu;
+      const double den = var + dl * dl;
+      const double ch = den > 0.0 ? var / den : 0.0;
+      double p = ch;
       for (int j = 1; j < V.cheb_power; j++) p *= ch;
       k.ww *= p;
       k.cheb = true;
     }
   }
-  k.e = sample_irradiance(V, k.q, n);
+  const int b = k.q * kIrrTexels + iy * kIrrTile + ix;
+  const D3 ea = irr_texel_d(V, b), ec = irr_texel_d(V, b + 1);
+  const D3 ed = irr_texel_d(V, b + kIrrTile), ee = irr_texel_d(V, b + kIrrTile + 1);
+  k.e = (1.0 - ify) * ((1.0 - ifx) * ea + ifx * ec) + ify * ((1.0 - ifx) * ed + ifx * ee);
   return k;
 }
 
@@ -95,72 +199,70 @@ __device__ __forceinline__ Corner corner_eval(const VolumeGPU& V, int c, const i
 // for a corner without a sampled probe).  Two passes over the corners (the
 // weight sum, then the terms) recompute each corner instead of holding all
 // eight in registers.
-__device__ inline void volume_query_terms(const VolumeGPU& V, float3 X, float3 n, float3 wo, float3 g, Term* t,
-                                          uint32_t* key, uint32_t none) {
-  float u[3] = {(X.x - V.origin[0]) * V.inv_spacing[0], (X.y - V.origin[1]) * V.inv_spacing[1],
-                (X.z - V.origin[2]) * V.inv_spacing[2]};
+__device__ inline void volume_query_terms(const VolumeGPU& V, D3 X, D3 n, D3 wo, D3 g, Term* t, uint32_t* key,
+                                          uint32_t none) {
+  const double Xa[3] = {X.x, X.y, X.z};
   int gi[3];
-  float f[3];
+  double f[3];
   for (int a = 0; a < 3; a++) {
-    gi[a] = (int)clampf(floorf(u[a]), 0.0f, (float)(V.counts[a] - 2));
-    f[a] = clampf(u[a] - (float)gi[a], 0.0f, 1.0f);
+    const double u = (Xa[a] - (double)V.origin[a]) / (double)V.spacing[a];
+    gi[a] = (int)fmin(fmax(floor(u), 0.0), (double)(V.counts[a] - 2));
+    f[a] = fmin(fmax(u - (double)gi[a], 0.0), 1.0);
   }
-  float D = fminf(V.spacing[0], fminf(V.spacing[1], V.spacing[2]));
-  float sb = 0.75f * D * V.bias;
-  float3 Xb = f3(fmaf(fmaf(0.2f, n.x, 0.8f * wo.x), sb, X.x), fmaf(fmaf(0.2f, n.y, 0.8f * wo.y), sb, X.y),
-                 fmaf(fmaf(0.2f, n.z, 0.8f * wo.z), sb, X.z));
-  float W = 0.0f;
-  float3 E = f3(0.0f, 0.0f, 0.0f);
+  const double D = fmin((double)V.spacing[0], fmin((double)V.spacing[1], (double)V.spacing[2]));
+  const double sb = 0.75 * D * (double)V.bias;
+  const D3 Xb = X + sb * (0.2 * n + 0.8 * wo);
+  int ix, iy;
+  double ifx, ify;
+  footprint_d<kIrrTile>(n, ix, iy, ifx, ify);
+  double W = 0.0;
+  D3 E = d3(0.0, 0.0, 0.0);
   for (int c = 0; c < 8; c++) {
-    const Corner k = corner_eval(V, c, gi, f, X, Xb, n);
+    const Corner k = corner_eval(V, c, gi, f, X, Xb, n, ix, iy, ifx, ify);
     if (!k.ok) continue;
     E = E + k.ww * k.e;
     W += k.ww;
   }
-  if (!(W > 0.0f)) {
+  if (!(W > 0.0)) {
     for (int c = 0; c < 8; c++) key[c] = none;
     return;
   }
-  const float iW = 1.0f / W;
+  const double iW = 1.0 / W;
   E = iW * E;
-  int ix, iy;
-  float ifx, ify;
-  tile_footprint<kIrrTile>(n, ix, iy, ifx, ify);
   for (int c = 0; c < 8; c++) {
-    const Corner k = corner_eval(V, c, gi, f, X, Xb, n);
+    const Corner k = corner_eval(V, c, gi, f, X, Xb, n, ix, iy, ifx, ify);
     if (!k.ok) {
       key[c] = none;
       continue;
     }
     Term T;
-    T.ge[0] = g.x * k.ww * iW;
-    T.ge[1] = g.y * k.ww * iW;
-    T.ge[2] = g.z * k.ww * iW;
+    T.ge[0] = (float)(g.x * k.ww * iW);
+    T.ge[1] = (float)(g.y * k.ww * iW);
+    T.ge[2] = (float)(g.z * k.ww * iW);
     T.gd[0] = T.gd[1] = 0.0f;
-    T.ifx = ifx;
-    T.ify = ify;
+    T.ifx = (float)ifx;
+    T.ify = (float)ify;
     int dx = 0, dy = 0;
-    float dfx = 0.0f, dfy = 0.0f;
+    double dfx = 0.0, dfy = 0.0;
     if (k.cheb) {
-      const float gw = (g.x * (k.e.x - E.x) + g.y * (k.e.y - E.y) + g.z * (k.e.z - E.z)) * iW;
-      const float mu = k.mm.x, mu2 = k.mm.y;
-      const float raw = fmaf(-mu, mu, mu2);
-      const float var = fmaxf(raw, 0.0f);
-      const float dl = k.r - mu;
-      const float den = fmaf(dl, dl, var);
-      const float ch = var / den;
-      const float dch_dvar = dl * dl / (den * den);
-      const float dch_ddl = -2.0f * dl * var / (den * den);
-      const float dvar_dmu = raw > 0.0f ? -2.0f * mu : 0.0f, dvar_dmu2 = raw > 0.0f ? 1.0f : 0.0f;
-      float dwv = (float)V.cheb_power;
+      const double gw = dotd(g, k.e - E) * iW;
+      const double raw = k.mu2 - k.mu * k.mu;
+      const double var = fmax(raw, 0.0);
+      const double dl = k.r - k.mu;
+      const double den = var + dl * dl;
+      const double ch = var / den;
+      const double dch_dvar = dl * dl / (den * den);
+      const double dch_ddl = -2.0 * dl * var / (den * den);
+      const double dvar_dmu = raw > 0.0 ? -2.0 * k.mu : 0.0, dvar_dmu2 = raw > 0.0 ? 1.0 : 0.0;
+      double dwv = (double)V.cheb_power;
       for (int j = 1; j < V.cheb_power; j++) dwv *= ch;
-      const float gwv = gw * k.wtb * dwv;
-      T.gd[0] = gwv * (dch_dvar * dvar_dmu - dch_ddl);
-      T.gd[1] = gwv * dch_dvar * dvar_dmu2;
-      tile_footprint<kDistTile>(k.zd, dx, dy, dfx, dfy);
+      const double gwv = gw * k.wtb * dwv;
+      T.gd[0] = (float)(gwv * (dch_dvar * dvar_dmu - dch_ddl));
+      T.gd[1] = (float)(gwv * dch_dvar * dvar_dmu2);
+      footprint_d<kDistTile>(k.zd, dx, dy, dfx, dfy);
     }
-    T.dfx = dfx;
-    T.dfy = dfy;
+    T.dfx = (float)dfx;
+    T.dfy = (float)dfy;
     T.fp = (uint32_t)ix | (uint32_t)iy << 8 | (uint32_t)dx << 16 | (uint32_t)dy << 24;
     t[c] = T;
     key[c] = (uint32_t)(V.probe_base + k.q);
@@ -170,17 +272,17 @@ __device__ inline void volume_query_terms(const VolumeGPU& V, float3 X, float3 n
 // Terms of the query over all volumes (8 slots per volume, in volume order),
 // each volume's share of the upstream gradient as its weight in the forward
 // cascade blend.
-__device__ inline void query_terms(const VolumeSet& vs, float3 X, float3 n, float3 wo, float3 g, Term* t,
-                                   uint32_t* key, uint32_t none) {
-  float Wt = 0.0f;
+__device__ inline void query_terms(const VolumeSet& vs, D3 X, D3 n, D3 wo, D3 g, Term* t, uint32_t* key,
+                                   uint32_t none) {
+  double Wt = 0.0;
   for (int v = 0; v < vs.n; v++) {
     const VolumeGPU& V = vs.v[v];
-    float wuse = 0.0f;
-    if (Wt < 1.0f) {
-      float wv = volume_weight(V, X);
-      wuse = (v == vs.n - 1) ? 1.0f - Wt : fminf(wv, 1.0f - Wt);
+    double wuse = 0.0;
+    if (Wt < 1.0) {
+      const double wv = volume_weight_d(V, X);
+      wuse = (v == vs.n - 1) ? 1.0 - Wt : fmin(wv, 1.0 - Wt);
     }
-    if (wuse > 0.0f) {
+    if (wuse > 0.0) {
       volume_query_terms(V, X, n, wo, wuse * g, t + 8 * v, key + 8 * v, none);
       Wt += wuse;
     } else {
@@ -190,15 +292,15 @@ __device__ inline void query_terms(const VolumeSet& vs, float3 X, float3 n, floa
 }
 
 // Query terms of points [i0, i0 + n): point i's at (i - i0) * 8 * vs.n.
-__global__ void k_query_terms(VolumeSet vs, const float* pos, const float* nrm, const float* view, int64_t i0,
+__global__ __launch_bounds__(256) void k_query_terms(VolumeSet vs, const float* pos, const float* nrm, const float* view, int64_t i0,
                               int64_t n, const float* gout, Term* terms, uint32_t* keys, uint32_t none) {
   const int per = 8 * vs.n;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = i0 + j;
-    float3 X = f3(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]);
-    float3 N = f3(nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]);
-    float3 Wo = f3(view[3 * i], view[3 * i + 1], view[3 * i + 2]);
-    query_terms(vs, X, N, Wo, f3(gout[3 * i], gout[3 * i + 1], gout[3 * i + 2]), terms + j * per, keys + j * per,
+    const D3 X = d3(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]);
+    const D3 N = d3(nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]);
+    const D3 Wo = d3(view[3 * i], view[3 * i + 1], view[3 * i + 2]);
+    query_terms(vs, X, N, Wo, d3(gout[3 * i], gout[3 * i + 1], gout[3 * i + 2]), terms + j * per, keys + j * per,
                 none);
   }
 }
@@ -541,7 +643,7 @@ __device__ __forceinline__ int64_t ray_volume(const VolumeSet& vs, const FrameCo
 // the terms of the previous-frame query at the hit, with upstream albedo x
 // the ray's radiance gradient, then its emitter record (key P + material,
 // ge = the radiance gradient).  Keys of empty slots: `none`.
-__global__ void k_shade_terms(VolumeSet prev, SceneGPU sc, FrameScratch fs, int64_t r0, int64_t n, Term* terms,
+__global__ __launch_bounds__(256) void k_shade_terms(VolumeSet prev, SceneGPU sc, FrameScratch fs, int64_t r0, int64_t n, Term* terms,
                               uint32_t* keys, uint32_t P, uint32_t none) {
   const FrameCounters& C = *fs.counters;
   const int64_t total = C.ray_base[prev.n];
@@ -573,10 +675,17 @@ __global__ void k_shade_terms(VolumeSet prev, SceneGPU sc, FrameScratch fs, int6
     E.ge[2] = g.z;
     tj[per - 1] = E;
     kj[per - 1] = P + (uint32_t)m;
-    float4 al = sc.albedo[m];
-    float3 o = probe_position(V, q);
-    float3 X = f3(fmaf(h.t, w.x, o.x), fmaf(h.t, w.y, o.y), fmaf(h.t, w.z, o.z));
-    query_terms(prev, X, ng, f3(-w.x, -w.y, -w.z), f3(al.x * g.x, al.y * g.y, al.z * g.z), tj, kj, none);
+    const float4 al = sc.albedo[m];
+    // the hit in double: the ray (probe position, direction) and its
+    // distance to the hit triangle's plane
+    const D3 o = position_d(V, q);
+    const D3 wd = sf_direction_d(r, V.rays, fs.params->R);
+    const D3 va = d3(a.x, a.y, a.z), vb = d3(b.x, b.y, b.z), vc = d3(c.x, c.y, c.z);
+    const D3 nn = crossd(vb - va, vc - va);
+    const double td = dotd(va - o, nn) / dotd(wd, nn);
+    const D3 X = o + td * wd;
+    query_terms(prev, X, normalized(nn), d3(-wd.x, -wd.y, -wd.z),
+                d3((double)al.x * g.x, (double)al.y * g.y, (double)al.z * g.z), tj, kj, none);
   }
 }
 

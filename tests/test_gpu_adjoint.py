@@ -7,8 +7,9 @@ one frame from A0 to A1 queried at surface points).  The GPU starts from the
 oracle's A0 and probe states, rounded to float32 (oracle -> GPU input only).
 
 Tolerance.  Each gradient element is a sum of terms (an upstream gradient
-times float32 coefficients: normalised blend and query weights and their
-Chebyshev derivatives), accumulated in a fixed order (point or ray order per
+times the normalised blend and query weights and their Chebyshev
+derivatives; the query terms are evaluated in FP64 from the float32 inputs
+and stored in float32), accumulated in a fixed order (point or ray order per
 texel), so that a second run gives the same bits.  The
 oracle reports per element the sum of the terms' magnitudes (a) and how far
 the terms move when the float32 inputs of each query (sampled moments, r,
