@@ -5,8 +5,12 @@ A step is one pass of the whole hot path over the 16x8x16-probe city (256
 rays per probe, ~100k triangles, 8 point lights, 32 emissive quads): the
 per-frame update (state step and compaction, ray directions, nearest-hit
 traversal, shadow rays, hit shading with the previous frame's probes, blend
-with hysteresis and border texels, state promotion) followed by the query of
-the full 1920x1080 G-buffer.  Inputs are synthetic and seeded; everything
+with hysteresis and border texels, state promotion) and the query of the
+full 1920x1080 G-buffer against its result.  The timed steps answer each
+frame's queries inside the next frame's probe-ray trace launch
+(irf_update_probes_query), which gives the same frames and the same query
+results as running each frame and then its queries (that schedule is timed
+too, `serial_ms_per_step`).  Inputs are synthetic and seeded; everything
 is resident on the GPU before timing starts.
 
 Prints one JSON line: the metric and its value (ms per city step), the
@@ -43,7 +47,7 @@ COUNTER_FILES = {"city": os.path.join(ROOT, "profiles", "city-16x8x16-256rays_co
                  "terrain": os.path.join(ROOT, "profiles", "terrain-4x32x16x32-192rays_counters.md")}
 # kernel symbol -> bench key (longer names first: k_shadow_refill before k_shadow)
 KERNEL_KEYS = (("k_shadow_refill", "shadow_refill"), ("k_shadow_count", "shadow_count"), ("k_shadow", "shadow"),
-               ("k_trace_count", "trace_count"), ("k_trace", "trace"), ("k_shade_terms", "shade_terms"),
+               ("k_trace_count", "trace_count"), ("k_trace_query", "trace_query"), ("k_trace", "trace"), ("k_shade_terms", "shade_terms"),
                ("k_shade", "shade"), ("k_blend_mma", "blend_mma"), ("k_blend_f32", "blend_valu"),
                ("k_blend_backward", "blend_backward"), ("k_query_terms", "query_terms"), ("k_query", "query"),
                ("k_gather_pieces", "gather_pieces"), ("k_finish_pieces", "finish_pieces"),
@@ -697,7 +701,7 @@ def main():
     nrm = torch.from_numpy(q.nrm).cuda()
     view = torch.from_numpy(q.view).cuda()
     out = torch.empty_like(pos)
-    R = S.rotations(w.config, 1 + 2 * max(1, args.warmup) + 3 * args.steps, start_frame=1)
+    R = S.rotations(w.config, 1 + 3 * max(2, args.warmup) + 6 * args.steps, start_frame=1)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
     print(f"[bench] setup {setup_s:.1f}s, {w.scene.n_triangles} triangles, {q.n} queries", file=sys.stderr, flush=True)
@@ -731,7 +735,8 @@ def main():
     graph.close()
     graph_ms = 1e3 * (t1 - t0) / args.steps
 
-    # timed (the value): the same steps with eager launches, no instrumentation
+    # the same steps with eager launches, no instrumentation: serial (each
+    # frame, then its query) ...
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -739,24 +744,55 @@ def main():
         ctx.query_irradiance(pos, nrm, view, out)
         f += 1
     torch.cuda.synchronize()
-    ms_step = 1e3 * (time.perf_counter() - t0) / args.steps
-    print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step (graph replay {graph_ms:.3f})", file=sys.stderr,
-          flush=True)
+    serial_ms = 1e3 * (time.perf_counter() - t0) / args.steps
 
-    # per-kernel times: a separate pass with the library's kernel timing
-    ctx.profile(True)
-    ctx.profile_read(reset=True)
-    for _ in range(args.steps):
+    def fused_steps(k):
+        # k frames and k queries with the same results as the serial steps:
+        # the query of frame i runs inside frame i+1's trace launch
+        # (irf_update_probes_query), the last one on its own
+        nonlocal f
         ctx.update_probes(R[f])
-        ctx.query_irradiance(pos, nrm, view, out)
         f += 1
+        for _ in range(k - 1):
+            ctx.update_probes_query(R[f], pos, nrm, view, out)
+            f += 1
+        ctx.query_irradiance(pos, nrm, view, out)
+
+    # ... and (the value) fused: the same frames and queries, each query
+    # answered inside the next frame's trace launch
+    fused_steps(max(2, args.warmup))
     torch.cuda.synchronize()
-    prof = ctx.profile_read(reset=True)
-    ctx.profile(False)
+    t0 = time.perf_counter()
+    fused_steps(args.steps)
+    torch.cuda.synchronize()
+    ms_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step (serial {serial_ms:.3f}, graph replay "
+          f"{graph_ms:.3f})", file=sys.stderr, flush=True)
+
+    # per-kernel times: separate passes with the library's kernel timing,
+    # serial (the update's and the query's own kernels) and fused
+    def profiled(run):
+        ctx.profile(True)
+        ctx.profile_read(reset=True)
+        run()
+        torch.cuda.synchronize()
+        pr = ctx.profile_read(reset=True)
+        ctx.profile(False)
+        return {k: {"launches": n, "avg_us": round(1e3 * ms / max(1, n), 2)} for k, (n, ms) in pr.items()}
+
+    def serial_steps():
+        nonlocal f
+        for _ in range(args.steps):
+            ctx.update_probes(R[f])
+            ctx.query_irradiance(pos, nrm, view, out)
+            f += 1
+
+    kern = profiled(serial_steps)
+    kern_fused = profiled(lambda: fused_steps(args.steps))
     stats = ctx.frame_stats()
 
-    kern = {k: {"launches": n, "avg_us": round(1e3 * ms / max(1, n), 2)} for k, (n, ms) in prof.items()}
-    upd = [k for k in kern if k != "query"]
+    kern["trace_query"] = kern_fused["trace_query"]
+    upd = [k for k in kern if k not in ("query", "trace_query")]
     update_ms = sum(kern[k]["avg_us"] for k in upd) / 1e3
     query_ms = kern["query"]["avg_us"] / 1e3
     prim, shad = stats["probe_rays"], stats["shadow_rays"]
@@ -786,9 +822,13 @@ def main():
                   + shad * RAY_IO_BYTES) if sk in kern else {},
         bk: {"algorithmic_flops_per_launch": blend_flops,
              "fp32_matrix_frac": round(blend_flops / (kern[bk]["avg_us"] * 1e-6) / 1e12 / FP32_PEAK_TFLOPS, 4)},
+        "trace_query": fetch("trace_query", trav["probe_nodes"] * NODE_BYTES + trav["probe_tris"] * TRI_BYTES
+                             + prim * RAY_IO_BYTES + qbytes),
     }
     rooflines = {k: binding_roofline(k, kern[k]["avg_us"], counters, extra.get(k)) for k in kern}
-    dominant = max(kern, key=lambda k: kern[k]["avg_us"])
+    # the dominant kernel of the timed (fused) step
+    step_kernels = [k for k in kern if k not in ("trace", "query")]
+    dominant = max(step_kernels, key=lambda k: kern[k]["avg_us"])
     roof = rooflines[dominant]
     line = {
         "metric": METRIC,
@@ -806,7 +846,8 @@ def main():
         "config": {"workload": w.name, "probes": int(w.volumes[0].n_probes), "active_probes": int(stats["active_probes"]),
                    "rays_per_probe": int(w.volumes[0].rays_per_probe), "triangles": int(w.scene.n_triangles),
                    "point_lights": 8, "queries": int(q.n), "blend": "f32", "atlas": "f32",
-                   "launch": "eager"},
+                   "launch": "eager, each frame's G-buffer query inside the next frame's trace launch"},
+        "serial_ms_per_step": round(serial_ms, 4),
         "graph_ms_per_step": round(graph_ms, 4),
         "update_ms": round(update_ms, 4),
         "query_ms": round(query_ms, 4),
@@ -816,6 +857,7 @@ def main():
                         "total_update": round((prim + shad) / (update_ms * 1e-3) / 1e9, 3)},
         "queries_per_s": round(q.n / (query_ms * 1e-3), 1),
         "kernels_us": kern,
+        "step_kernels": step_kernels,
         "dominant_kernel": dominant,
         "traversal": {k: int(v) for k, v in trav.items()},
         "kernel_rooflines": rooflines,

@@ -289,6 +289,27 @@ irf_status irf_update_probes_after(irf_ctx* ctx, const float* rotation, void* st
 irf_status irf_query_irradiance(irf_ctx* ctx, const float* pos, const float* nrm, const float* view,
                                 int64_t n, float* out_rgb, void* stream);
 
+/* One update frame (irf_update_probes) that also answers n irradiance
+   queries (irf_query_irradiance: same arrays, layouts and units) against the
+   atlases and probe states as they stood before this frame, i.e. the result
+   of the previous frame.  `out_rgb` receives exactly what
+   irf_query_irradiance on the same stream just before irf_update_probes
+   would have written, and the frame's results are those of
+   irf_update_probes; only the schedule differs.  The queries run inside the
+   frame's probe-ray trace launch (the trace reads no atlas and no probe
+   state, and writes neither): the trace's waves wait on dependent node
+   fetches and leave issue slots that the queries' arithmetic fills
+   (Section "Probe Query" for what a query computes, Section "Probe Update"
+   for the frame).
+   A renderer that shades frame f with the probes of update f issues
+   update f+1 together with the queries of frame f.  When the scene has
+   dynamic objects the frame's state step can rewrite the states a query
+   reads, so the queries then run first, as their own launch.  n = 0 is a
+   plain frame; n < 0, a NULL rotation or (with n > 0) a NULL array:
+   IRF_E_INVALID before any launch.  Async. */
+irf_status irf_update_probes_query(irf_ctx* ctx, const float* rotation, const float* pos, const float* nrm,
+                                   const float* view, int64_t n, float* out_rgb, void* stream);
+
 /* Launch shapes of the frame's main kernels: the number of workgroups of
    the persistent probe-ray traversal, shadow-ray traversal, hit shading and
    matrix-core blend; each strides over the work of all volumes.  0 selects

@@ -354,9 +354,12 @@ irf_status launched() {
 }
 
 // One update frame, asynchronously on `st` (also what a graph captures); the
-// blend waits for `atlas_wait` when given.
+// blend waits for `atlas_wait` when given.  With a query batch `qb` the
+// queries see the atlases and states as they stood before the frame: they run
+// inside the probe-ray trace launch, or first, on their own, when the state
+// step can rewrite the states they read.
 hipError_t enqueue_frame_on(irf_ctx* c, const float* rotation, hipStream_t st, hipEvent_t atlas_wait,
-                            const VolumeSet& vs, const FrameScratch& fs) {
+                            const VolumeSet& vs, const FrameScratch& fs, const QueryBatch* qb = nullptr) {
   SceneGPU sc = scene_view(c);
   const int nl = c->lights.n_dir + c->lights.n_point;
   FrameParams fp;
@@ -373,6 +376,11 @@ hipError_t enqueue_frame_on(irf_ctx* c, const float* rotation, hipStream_t st, h
     if (e != hipSuccess) return e;
     atlas_wait = nullptr;
   }
+  const bool fused = qb && qb->n > 0 && boxes.n == 0;
+  if (qb && qb->n > 0 && !fused) {
+    ProfScope p(c, "query", st);
+    launch_query(vs, qb->pos, qb->nrm, qb->view, qb->n, qb->out, st);
+  }
   {
     ProfScope p(c, "frame_begin", st);
     launch_frame_begin(make_frame_begin(fp, vs, boxes, fs, any_mma), st);
@@ -386,7 +394,13 @@ hipError_t enqueue_frame_on(irf_ctx* c, const float* rotation, hipStream_t st, h
       launch_copy(c->saved.p + c->saved_states[v], c->vol[v].states, P, st);
     }
   }
-  { ProfScope p(c, "trace", st); launch_trace(vs, sc, fs, c->tune.trace_blocks, st); }
+  if (fused) {
+    ProfScope p(c, "trace_query", st);
+    launch_trace_query(vs, sc, fs, c->tune.trace_blocks, *qb, st);
+  } else {
+    ProfScope p(c, "trace", st);
+    launch_trace(vs, sc, fs, c->tune.trace_blocks, st);
+  }
   if (nl > 0) {
     ProfScope p(c, c->tune.shadow_refill > 0 ? "shadow_refill" : "shadow", st);
     launch_shadow(vs, sc, nl, fs, c->tune.shadow_blocks, c->tune.shadow_refill, st);
@@ -985,6 +999,25 @@ irf_status irf_update_probes_after(irf_ctx* c, const float* rotation, void* stre
 
 irf_status irf_update_probes(irf_ctx* c, const float* rotation, void* stream) {
   return irf_update_probes_after(c, rotation, stream, nullptr);
+}
+
+irf_status irf_update_probes_query(irf_ctx* c, const float* rotation, const float* pos, const float* nrm,
+                                   const float* view, int64_t n, float* out, void* stream) {
+  if (!c || !rotation) return fail(IRF_E_INVALID, "NULL argument");
+  if (n < 0) return fail(IRF_E_INVALID, "n < 0");
+  if (n > 0 && (!pos || !nrm || !view || !out)) return fail(IRF_E_INVALID, "NULL array");
+  for (int i = 0; i < 9; i++)
+    if (!std::isfinite(rotation[i])) return fail(IRF_E_INVALID, "rotation is not finite");
+  irf_status s = check_ready(c);
+  if (s != IRF_OK) return s;
+  if ((s = set_device(c)) != IRF_OK) return s;
+  if ((s = ensure_scratch(c)) != IRF_OK) return s;
+  const QueryBatch qb = {pos, nrm, view, out, n};
+  hipError_t e = enqueue_frame_on(c, rotation, (hipStream_t)stream, nullptr, volume_view(c), scratch_view(c), &qb);
+  if (e != hipSuccess) return fail(IRF_E_HIP, "enqueueing the frame: %s", hipGetErrorString(e));
+  c->frame_done = true;
+  c->diff_frame = c->diff;
+  return launched();
 }
 
 irf_status irf_update_probes_noalloc(irf_ctx* c, const float* rotation, void* stream) {

@@ -468,4 +468,17 @@ __device__ __forceinline__ float3 query_irradiance(const VolumeSet& vs, float3 X
   return query_look(vs, X, n, wo, n);
 }
 
+// Query point i of a batch (position, normal and view direction packed xyz).
+__device__ __forceinline__ void query_point(const VolumeSet& vs, const float* __restrict__ pos,
+                                            const float* __restrict__ nrm, const float* __restrict__ view, int64_t i,
+                                            float* __restrict__ out) {
+  const float3 X = f3(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]);
+  const float3 N = f3(nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]);
+  const float3 Wo = f3(view[3 * i], view[3 * i + 1], view[3 * i + 2]);
+  const float3 E = query_irradiance(vs, X, N, Wo);
+  out[3 * i] = E.x;
+  out[3 * i + 1] = E.y;
+  out[3 * i + 2] = E.z;
+}
+
 }  // namespace irf

@@ -207,6 +207,17 @@ FrameBegin make_frame_begin(const FrameParams& p, const VolumeSet& vs, ObjectBox
 void launch_frame_begin(const FrameBegin& a, hipStream_t s);
 const void* frame_begin_kernel();
 void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s);
+// A batch of irradiance queries (points packed xyz, float32, device memory).
+struct QueryBatch {
+  const float* pos;
+  const float* nrm;
+  const float* view;
+  float* out;
+  int64_t n;
+};
+// The probe-ray trace with a query batch answered in the same launch.
+void launch_trace_query(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, const QueryBatch& q,
+                        hipStream_t s);
 void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, int refill,
                    hipStream_t s);
 void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s);

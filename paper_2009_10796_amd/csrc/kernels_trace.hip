@@ -374,6 +374,28 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(VolumeSet vs, SceneGPU sc
     trace_one(vs, sc, L, fs, C, work);
 }
 
+// The probe-ray trace of a frame with a batch of irradiance queries answered
+// in the same launch, against the atlases and states the previous frame left
+// (the trace reads no atlas and writes none, nor any probe state): blocks
+// [0, trace_blocks) trace as k_trace does, striding over the rays; the rest
+// take one query point per lane, in order.  The trace's waves wait on
+// dependent node fetches, and the queries' arithmetic fills the issue slots
+// they leave.
+__global__ __launch_bounds__(kTraceBlock) void k_trace_query(VolumeSet vs, SceneGPU sc, FrameScratch fs,
+                                                            int trace_blocks, QueryBatch q) {
+  if ((int)blockIdx.x < trace_blocks) {
+    const FrameCounters& C = *fs.counters;
+    const LightSet& L = fs.params->L;
+    const int64_t total = C.ray_base[vs.n];
+    for (int64_t work = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x; work < total;
+         work += (int64_t)trace_blocks * kTraceBlock)
+      trace_one(vs, sc, L, fs, C, work);
+  } else {
+    const int64_t i = (int64_t)(blockIdx.x - trace_blocks) * kTraceBlock + threadIdx.x;
+    if (i < q.n) query_point(vs, q.pos, q.nrm, q.view, i, q.out);
+  }
+}
+
 // The shadow tasks in one dense order, region after region.  Lane r of the
 // wave returns the number of tasks in the regions below r, `total` all of
 // them.  Every lane of the wave must be active.
@@ -1061,6 +1083,14 @@ static inline unsigned grid_for(int64_t items, int grid) {
 void launch_trace(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s) {
   if (fs.max_rays == 0) return;
   irf_launch(k_trace, dim3(grid_for(fs.max_rays, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs);
+}
+
+void launch_trace_query(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, const QueryBatch& q,
+                        hipStream_t s) {
+  if (q.n == 0) return launch_trace(vs, sc, fs, grid, s);
+  const unsigned tb = fs.max_rays > 0 ? grid_for(fs.max_rays, grid) : 0;
+  const unsigned qb = blocks_for(q.n, kTraceBlock);
+  irf_launch(k_trace_query, dim3(tb + qb), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs, (int)tb, q);
 }
 
 void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, int refill,

@@ -135,15 +135,8 @@ constexpr int kQueryBlock = 256;
 __global__ __launch_bounds__(kQueryBlock) void k_query(VolumeSet vs, const float* __restrict__ pos,
                                                       const float* __restrict__ nrm, const float* __restrict__ view,
                                                       int64_t n, float* __restrict__ out) {
-  int64_t i = (int64_t)blockIdx.x * kQueryBlock + threadIdx.x;
-  if (i >= n) return;
-  float3 X = f3(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]);
-  float3 N = f3(nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]);
-  float3 Wo = f3(view[3 * i], view[3 * i + 1], view[3 * i + 2]);
-  float3 E = query_irradiance(vs, X, N, Wo);
-  out[3 * i] = E.x;
-  out[3 * i + 1] = E.y;
-  out[3 * i + 2] = E.z;
+  const int64_t i = (int64_t)blockIdx.x * kQueryBlock + threadIdx.x;
+  if (i < n) query_point(vs, pos, nrm, view, i, out);
 }
 
 // ---- launches

@@ -86,6 +86,7 @@ SIGNATURES = {
     "irf_update_probes_after": (C.c_int, [_vp, _vp, _vp, _vp]),
     "irf_update_probes_noalloc": (C.c_int, [_vp, _vp, _vp]),
     "irf_query_irradiance": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp]),
+    "irf_update_probes_query": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp]),
     "irf_ray_records": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(_i64), _vp]),
     "irf_frame_stats": (C.c_int, [_vp, C.POINTER(_i64 * 4), _vp]),
     "irf_traversal_stats": (C.c_int, [_vp, C.POINTER(_i64 * 4), _vp]),
@@ -316,7 +317,7 @@ class Context:
         _check(load().irf_update_probes_noalloc(self.handle, _ptr(R), _stream(self.torch)))
         self.frames += 1
 
-    def query_irradiance(self, pos, nrm, view, out=None):
+    def _query_args(self, pos, nrm, view, out):
         torch = self.torch
         n = int(pos.shape[0])
         for t in (pos, nrm, view):
@@ -324,6 +325,24 @@ class Context:
                 raise IrfError(E_INVALID, "query inputs must be contiguous float32 CUDA tensors of shape [n, 3]")
         if out is None:
             out = torch.empty((n, 3), dtype=torch.float32, device=pos.device)
+        elif out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous() or tuple(out.shape) != (n, 3):
+            raise IrfError(E_INVALID, "the query output must be a contiguous float32 CUDA tensor of shape [n, 3]")
+        return n, out
+
+    def update_probes_query(self, rotation, pos, nrm, view, out=None):
+        """One update frame that also answers the queries against the atlases
+        the previous frame left (inside the frame's trace launch); returns
+        `out`, equal to query_irradiance() called before update_probes()."""
+        n, out = self._query_args(pos, nrm, view, out)
+        R = _np(rotation, np.float32).reshape(9)
+        _check(load().irf_update_probes_query(self.handle, _ptr(R), C.c_void_p(pos.data_ptr()),
+                                              C.c_void_p(nrm.data_ptr()), C.c_void_p(view.data_ptr()), n,
+                                              C.c_void_p(out.data_ptr()), _stream(self.torch)))
+        self.frames += 1
+        return out
+
+    def query_irradiance(self, pos, nrm, view, out=None):
+        n, out = self._query_args(pos, nrm, view, out)
         _check(load().irf_query_irradiance(self.handle, C.c_void_p(pos.data_ptr()), C.c_void_p(nrm.data_ptr()),
                                            C.c_void_p(view.data_ptr()), n, C.c_void_p(out.data_ptr()),
                                            _stream(self.torch)))

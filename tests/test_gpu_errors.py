@@ -4,8 +4,8 @@ Each rejected call returns its status before anything is enqueued and
 leaves the context as it was: after a series of rejected calls (frames
 before a scene or a volume exists, 34 lights, a non-finite sky, an empty or
 non-finite classification, a non-finite frame rotation, a negative or
-null query batch, query tensors of the wrong type, layout, device or
-shape) the context's classification, two frames and a query
+null query batch, also for the frame that answers one, query tensors of
+the wrong type, layout, device or shape) the context's classification, two frames and a query
 are bit for bit those of a fresh context that saw no error."""
 import ctypes as C
 
@@ -68,6 +68,16 @@ def test_rejected_calls_leave_the_context_usable(torch):
     assert lib.irf_query_irradiance(c.handle, None, ptr, ptr, 4, ptr, s) == irf.E_INVALID
     assert lib.irf_query_irradiance(c.handle, ptr, ptr, ptr, 0, None, s) == irf.OK   # empty batch
     assert lib.irf_last_error()                                   # a detail string is kept
+    # the frame that also answers a query batch checks the batch before any launch
+    R = np.ascontiguousarray(R1, np.float32).reshape(9)
+    Rp = R.ctypes.data_as(C.c_void_p)
+    assert lib.irf_update_probes_query(c.handle, Rp, ptr, ptr, ptr, -1, ptr, s) == irf.E_INVALID
+    assert lib.irf_update_probes_query(c.handle, Rp, ptr, None, ptr, 4, ptr, s) == irf.E_INVALID
+    assert lib.irf_update_probes_query(c.handle, Rp, ptr, ptr, ptr, 4, None, s) == irf.E_INVALID
+    assert lib.irf_update_probes_query(c.handle, None, ptr, ptr, ptr, 4, ptr, s) == irf.E_INVALID
+    nan32 = np.ascontiguousarray(nan_r, np.float32)
+    nan_p = nan32.ctypes.data_as(C.c_void_p)
+    assert lib.irf_update_probes_query(c.handle, nan_p, ptr, ptr, ptr, 4, ptr, s) == irf.E_INVALID
     # the binding checks query tensors before calling the library
     good = torch.zeros((8, 3), dtype=torch.float32, device="cuda")
     for bad in (good.double(), torch.zeros((3, 8), dtype=torch.float32, device="cuda").t(), good.cpu(),

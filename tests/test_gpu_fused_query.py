@@ -1,0 +1,94 @@
+"""The frame that also answers a query batch (irf_update_probes_query).
+
+Its queries must equal, bit for bit, irf_query_irradiance called just
+before irf_update_probes on the same stream (the atlases and states the
+previous frame left), and its frame the plain frame: checked on the city
+(a 480x270 G-buffer; the queries inside the probe-ray trace launch, also
+with a persistent trace grid), on the room, and on the city with a dynamic
+building, whose state step can put probes to sleep before the queries would
+see them (there the queries run first, as their own launch), over frames
+that move the building."""
+import numpy as np
+import pytest
+
+from paper_2009_10796_amd import scenes as S
+from tests.test_gpu_dynamic_states import city_with_dynamic_building
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _tensors(torch, q):
+    return [torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda() for a in (q.pos, q.nrm, q.view)]
+
+
+def _same_atlases(A, B):
+    return all(np.array_equal(va.irradiance.cpu().numpy(), vb.irradiance.cpu().numpy())
+               and np.array_equal(va.distance.cpu().numpy(), vb.distance.cpu().numpy())
+               and np.array_equal(va.states.cpu().numpy(), vb.states.cpu().numpy())
+               for va, vb in zip(A.volumes, B.volumes))
+
+
+def _run(torch, w, frames, tunings=(None,), scene_at=None):
+    """Context A: query, then the frame; context B: the fused call.  Returns
+    per frame whether queries and atlases agree bit for bit."""
+    from paper_2009_10796_amd import irf
+    pos, nrm, view = _tensors(torch, w.queries)
+    A, B = irf.build_workload(w), irf.build_workload(w)
+    for c in (A, B):
+        c.classify(w.classify_rotations)
+        c.update_probes(w.frame_rotation(1))
+    ea, eb = torch.empty_like(pos), torch.empty_like(pos)
+    out = []
+    for i, f in enumerate(frames):
+        if scene_at and f in scene_at:
+            for c in (A, B):
+                c.set_scene(scene_at[f])
+        t = tunings[i % len(tunings)]
+        if t:
+            B.set_tuning(**t)
+        A.query_irradiance(pos, nrm, view, ea)
+        A.update_probes(w.frame_rotation(f))
+        eb.fill_(float("nan"))
+        B.update_probes_query(w.frame_rotation(f), pos, nrm, view, eb)
+        torch.cuda.synchronize()
+        q_same = torch.equal(ea, eb)
+        a_same = _same_atlases(A, B)
+        print(f"[fused] {w.name} frame {f} tuning {t}: queries equal {q_same}, frame equal {a_same}", flush=True)
+        out.append((q_same, a_same))
+    # n = 0: a plain frame
+    A.update_probes(w.frame_rotation(99))
+    B.update_probes_query(w.frame_rotation(99), pos[:0], nrm[:0], view[:0])
+    torch.cuda.synchronize()
+    out.append((True, _same_atlases(A, B)))
+    A.close()
+    B.close()
+    return out
+
+
+def test_fused_queries_match_query_then_frame_on_the_city(torch):
+    w = S.config1(width=480, height=270)
+    res = _run(torch, w, (2, 3, 4), tunings=(None, {"trace_blocks": 37}, {"trace_blocks": 0}))
+    assert all(q and a for q, a in res), res
+
+
+def test_fused_queries_match_query_then_frame_on_the_room(torch):
+    res = _run(torch, S.config0(), (2, 3))
+    assert all(q and a for q, a in res), res
+
+
+def test_dynamic_scene_queries_run_before_the_state_step(torch):
+    w, scene_a = city_with_dynamic_building()
+    _, scene_b = city_with_dynamic_building((4.0, 0.0, 0.0))
+    w.scene = scene_a
+    w.volumes = [S.VolumeDesc(origin=(3.5, 5.5, 4.5), spacing=(1.0, 1.0, 1.0), counts=(10, 4, 6), rays_per_probe=64)]
+    w.queries = S.config1(width=320, height=180).queries
+    res = _run(torch, w, (2, 3, 4), scene_at={3: scene_b})
+    assert all(q and a for q, a in res), res
