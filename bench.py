@@ -7,8 +7,8 @@ per-frame update (state step and compaction, ray directions, nearest-hit
 traversal, shadow rays, hit shading with the previous frame's probes, blend
 with hysteresis and border texels, state promotion) and the query of the
 full 1920x1080 G-buffer against its result.  The timed steps answer each
-frame's queries inside the next frame's probe-ray trace launch
-(irf_update_probes_query), which gives the same frames and the same query
+frame's queries inside the next frame's probe-ray trace and shadow-ray
+launches (irf_update_probes_query), which gives the same frames and the same query
 results as running each frame and then its queries (that schedule is timed
 too, `serial_ms_per_step`).  Inputs are synthetic and seeded; everything
 is resident on the GPU before timing starts.
@@ -46,7 +46,8 @@ NODE_BYTES, TRI_BYTES, RAY_IO_BYTES = 64, 48, 32
 COUNTER_FILES = {"city": os.path.join(ROOT, "profiles", "city-16x8x16-256rays_counters.md"),
                  "terrain": os.path.join(ROOT, "profiles", "terrain-4x32x16x32-192rays_counters.md")}
 # kernel symbol -> bench key (longer names first: k_shadow_refill before k_shadow)
-KERNEL_KEYS = (("k_shadow_refill", "shadow_refill"), ("k_shadow_count", "shadow_count"), ("k_shadow", "shadow"),
+KERNEL_KEYS = (("k_shadow_refill", "shadow_refill"), ("k_shadow_count", "shadow_count"),
+               ("k_shadow_query", "shadow_query"), ("k_shadow", "shadow"),
                ("k_trace_count", "trace_count"), ("k_trace_query", "trace_query"), ("k_trace", "trace"), ("k_shade_terms", "shade_terms"),
                ("k_shade", "shade"), ("k_blend_mma", "blend_mma"), ("k_blend_f32", "blend_valu"),
                ("k_blend_backward", "blend_backward"), ("k_query_terms", "query_terms"), ("k_query", "query"),
@@ -791,8 +792,12 @@ def main():
     kern_fused = profiled(lambda: fused_steps(args.steps))
     stats = ctx.frame_stats()
 
-    kern["trace_query"] = kern_fused["trace_query"]
-    upd = [k for k in kern if k not in ("query", "trace_query")]
+    # the fused steps' own launches (the plain first frame and the last
+    # query run once per pass)
+    step_kernels = sorted(k for k, e in kern_fused.items() if e["launches"] >= args.steps - 1)
+    for k in step_kernels:
+        kern.setdefault(k, kern_fused[k])
+    upd = [k for k in kern if k not in ("query", "trace_query", "shadow_query")]
     update_ms = sum(kern[k]["avg_us"] for k in upd) / 1e3
     query_ms = kern["query"]["avg_us"] / 1e3
     prim, shad = stats["probe_rays"], stats["shadow_rays"]
@@ -822,12 +827,17 @@ def main():
                   + shad * RAY_IO_BYTES) if sk in kern else {},
         bk: {"algorithmic_flops_per_launch": blend_flops,
              "fp32_matrix_frac": round(blend_flops / (kern[bk]["avg_us"] * 1e-6) / 1e12 / FP32_PEAK_TFLOPS, 4)},
-        "trace_query": fetch("trace_query", trav["probe_nodes"] * NODE_BYTES + trav["probe_tris"] * TRI_BYTES
-                             + prim * RAY_IO_BYTES + qbytes),
     }
+    # the fused launches: each traversal's own fetches and its share of the queries'
+    share = ctx.get_tuning()["query_shadow"] / 1000.0
+    if "trace_query" in kern:
+        extra["trace_query"] = fetch("trace_query", trav["probe_nodes"] * NODE_BYTES + trav["probe_tris"] * TRI_BYTES
+                                     + prim * RAY_IO_BYTES + (1.0 - share) * qbytes)
+    if "shadow_query" in kern:
+        extra["shadow_query"] = fetch("shadow_query", trav["shadow_nodes"] * NODE_BYTES + trav["shadow_tris"]
+                                      * TRI_BYTES + shad * RAY_IO_BYTES + share * qbytes)
     rooflines = {k: binding_roofline(k, kern[k]["avg_us"], counters, extra.get(k)) for k in kern}
     # the dominant kernel of the timed (fused) step
-    step_kernels = [k for k in kern if k not in ("trace", "query")]
     dominant = max(step_kernels, key=lambda k: kern[k]["avg_us"])
     roof = rooflines[dominant]
     line = {
@@ -843,10 +853,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
+        "query_shadow": ctx.get_tuning()["query_shadow"],
         "config": {"workload": w.name, "probes": int(w.volumes[0].n_probes), "active_probes": int(stats["active_probes"]),
                    "rays_per_probe": int(w.volumes[0].rays_per_probe), "triangles": int(w.scene.n_triangles),
                    "point_lights": 8, "queries": int(q.n), "blend": "f32", "atlas": "f32",
-                   "launch": "eager, each frame's G-buffer query inside the next frame's trace launch"},
+                   "launch": "eager, each frame's G-buffer query inside the next frame's trace and shadow "
+                             "launches"},
         "serial_ms_per_step": round(serial_ms, 4),
         "graph_ms_per_step": round(graph_ms, 4),
         "update_ms": round(update_ms, 4),

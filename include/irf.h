@@ -296,11 +296,12 @@ irf_status irf_query_irradiance(irf_ctx* ctx, const float* pos, const float* nrm
    irf_query_irradiance on the same stream just before irf_update_probes
    would have written, and the frame's results are those of
    irf_update_probes; only the schedule differs.  The queries run inside the
-   frame's probe-ray trace launch (the trace reads no atlas and no probe
-   state, and writes neither): the trace's waves wait on dependent node
-   fetches and leave issue slots that the queries' arithmetic fills
-   (Section "Probe Query" for what a query computes, Section "Probe Update"
-   for the frame).
+   frame's probe-ray trace and shadow-ray launches, split by the tuning's
+   query_shadow (neither traversal reads an atlas or a probe state, nor
+   writes one): the traversals' waves wait on dependent node fetches and
+   leave issue slots that the queries' arithmetic fills (Section "Probe
+   Query" for what a query computes, Section "Probe Update" for the
+   frame).
    A renderer that shades frame f with the probes of update f issues
    update f+1 together with the queries of frame f.  When the scene has
    dynamic objects the frame's state step can rewrite the states a query
@@ -325,10 +326,15 @@ irf_status irf_update_probes_query(irf_ctx* ctx, const float* rotation, const fl
    shape: how many workgroups share one block of 8 probes (1, 2 or 4; 0
    selects 4), each taking 16 / rsplit of the 16 row tiles of the weight
    matrix, so the block's rays are staged rsplit times and each wave
-   multiplies 4 / rsplit row tiles.  Results do not depend on any of these.
-   Values are normally chosen by the autotuner
+   multiplies 4 / rsplit row tiles.  query_shadow splits the query batch of
+   irf_update_probes_query: per mille of its points answered in the
+   shadow-ray launch (batched shadow rays only; with shadow_refill > 0, or
+   no lights, all of them run in the probe-ray trace launch), the rest in
+   the trace launch (a new context: 500).  Results do not depend on any of
+   these.  The launch shapes are normally chosen by the autotuner
    (paper_2009_10796_amd/autotune.py).  IRF_E_INVALID for negative values,
-   shadow_refill above 64 or blend_rsplit not in {0, 1, 2, 4}. */
+   shadow_refill above 64, blend_rsplit not in {0, 1, 2, 4} or query_shadow
+   above 1000. */
 typedef struct {
   int32_t trace_blocks;
   int32_t shadow_blocks;
@@ -336,6 +342,7 @@ typedef struct {
   int32_t blend_blocks;
   int32_t shadow_refill;
   int32_t blend_rsplit;
+  int32_t query_shadow;
 } irf_tuning;
 irf_status irf_set_tuning(irf_ctx* ctx, const irf_tuning* tuning);
 irf_status irf_get_tuning(const irf_ctx* ctx, irf_tuning* tuning);

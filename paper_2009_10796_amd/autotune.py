@@ -4,7 +4,8 @@ For each persistent kernel of the update (probe-ray traversal, shadow-ray
 traversal, hit shading, matrix-core blend) it times a set of grid sizes
 (multiples of the compute-unit count, plus 0 = one workgroup per work unit),
 for the shadow rays how their tasks are spread over lanes (batches of 64, or
-per-wave ranges with lane refill at an idle-lane threshold), and for the
+per-wave ranges with lane refill at an idle-lane threshold), for frames that
+answer a query batch the batch's share in the shadow launch, and for the
 blend its tile shape (1, 2 or 4 workgroups per block of 8 probes), on the
 live workload with the library's own kernel timing, and keeps the fastest.
 The choice is returned as a dict, can be saved as JSON and applied to
@@ -17,13 +18,19 @@ import json
 import os
 from typing import Dict, Iterable, Optional
 
-SHADOW = ("shadow", "shadow_refill")   # the kernel the shadow rays run on, by refill mode
+# the kernels a stage runs on: the shadow rays by refill mode, and the
+# traversals with a share of a query batch when the frames are
+# irf_update_probes_query frames
+TRACE = ("trace", "trace_query")
+SHADOW = ("shadow", "shadow_refill", "shadow_query")
 # knobs in the order they are tuned (one at a time, the others held); the
 # blend's grid is tuned again after its tile shape, since the best grid
-# depends on the shape
-KNOBS = (("trace_blocks", ("trace",)), ("shadow_refill", SHADOW), ("shadow_blocks", SHADOW),
-         ("shade_blocks", ("shade",)), ("blend_blocks", ("blend_mma",)), ("blend_rsplit", ("blend_mma",)),
-         ("blend_blocks", ("blend_mma",)))
+# depends on the shape.  query_shadow (the query batch's share in the shadow
+# launch) is timed over both traversals and tuned only on frames that answer
+# queries.
+KNOBS = (("trace_blocks", TRACE), ("shadow_refill", SHADOW), ("query_shadow", TRACE + SHADOW),
+         ("shadow_blocks", SHADOW), ("shade_blocks", ("shade",)), ("blend_blocks", ("blend_mma",)),
+         ("blend_rsplit", ("blend_mma",)), ("blend_blocks", ("blend_mma",)))
 
 
 def candidates(cu: int, knob: str = "trace_blocks") -> list:
@@ -34,6 +41,8 @@ def candidates(cu: int, knob: str = "trace_blocks") -> list:
         return [0, 4, 8, 16, 32]
     if knob == "blend_rsplit":
         return [4, 2, 1]
+    if knob == "query_shadow":
+        return [0, 250, 500, 750]
     return [0] + [cu * k for k in (1, 2, 4, 8, 16)]
 
 
@@ -41,7 +50,8 @@ def autotune(ctx, rotations: Iterable, frames_per_candidate: int = 3, cu: Option
              step=None) -> Dict[str, int]:
     """Tunes ctx in place.  `rotations` supplies the frames' rotations (used
     in turn, from the start again when they run out); `step(R)` runs one
-    frame (default: ctx.update_probes)."""
+    frame (default: ctx.update_probes; a step that calls
+    ctx.update_probes_query also tunes the query batch's split)."""
     import itertools
     torch = ctx.torch
     if cu is None:
@@ -64,7 +74,7 @@ def autotune(ctx, rotations: Iterable, frames_per_candidate: int = 3, cu: Option
             prof = ctx.profile_read(reset=True)
             ctx.profile(False)
             ran = [prof[k] for k in kernels if k in prof]
-            if not ran:
+            if not ran or (knob == "query_shadow" and "trace_query" not in prof):
                 break
             times[c] = sum(ms for _, ms in ran) / max(n for n, _ in ran)
         if times:

@@ -104,7 +104,7 @@ struct irf_ctx {
   DevBuf<unsigned long long> reloc_keys;
   bool frame_done = false;
   bool diff_frame = false;   // the last frame saved its inputs for the adjoint
-  Tuning tune = {0, 0, 0, 0, 0, 0};
+  Tuning tune = {0, 0, 0, 0, 0, 0, 500};
   // adjoint: the frame's input atlases and states, saved by each update
   bool diff = false;
   DevBuf<char> saved;
@@ -394,14 +394,28 @@ hipError_t enqueue_frame_on(irf_ctx* c, const float* rotation, hipStream_t st, h
       launch_copy(c->saved.p + c->saved_states[v], c->vol[v].states, P, st);
     }
   }
+  // the fused batch: a share in the shadow launch (batched shadow rays only),
+  // the rest in the trace launch
+  QueryBatch q_trace = {}, q_shadow = {};
+  if (fused) {
+    const int64_t ns = nl > 0 && c->tune.shadow_refill == 0 ? qb->n * c->tune.query_shadow / 1000 : 0;
+    q_trace = *qb;
+    q_trace.n = qb->n - ns;
+    q_shadow = *qb;
+    q_shadow.first = qb->first + q_trace.n;
+    q_shadow.n = ns;
+  }
   if (fused) {
     ProfScope p(c, "trace_query", st);
-    launch_trace_query(vs, sc, fs, c->tune.trace_blocks, *qb, st);
+    launch_trace_query(vs, sc, fs, c->tune.trace_blocks, q_trace, st);
   } else {
     ProfScope p(c, "trace", st);
     launch_trace(vs, sc, fs, c->tune.trace_blocks, st);
   }
-  if (nl > 0) {
+  if (q_shadow.n > 0) {
+    ProfScope p(c, "shadow_query", st);
+    launch_shadow_query(vs, sc, nl, fs, c->tune.shadow_blocks, q_shadow, st);
+  } else if (nl > 0) {
     ProfScope p(c, c->tune.shadow_refill > 0 ? "shadow_refill" : "shadow", st);
     launch_shadow(vs, sc, nl, fs, c->tune.shadow_blocks, c->tune.shadow_refill, st);
   }
@@ -1012,7 +1026,7 @@ irf_status irf_update_probes_query(irf_ctx* c, const float* rotation, const floa
   if (s != IRF_OK) return s;
   if ((s = set_device(c)) != IRF_OK) return s;
   if ((s = ensure_scratch(c)) != IRF_OK) return s;
-  const QueryBatch qb = {pos, nrm, view, out, n};
+  const QueryBatch qb = {pos, nrm, view, out, 0, n};
   hipError_t e = enqueue_frame_on(c, rotation, (hipStream_t)stream, nullptr, volume_view(c), scratch_view(c), &qb);
   if (e != hipSuccess) return fail(IRF_E_HIP, "enqueueing the frame: %s", hipGetErrorString(e));
   c->frame_done = true;
@@ -1133,12 +1147,14 @@ irf_status irf_set_tuning(irf_ctx* c, const irf_tuning* t) {
     return fail(IRF_E_INVALID, "shadow_refill must be in [0, 64]");
   if (t->blend_rsplit != 0 && t->blend_rsplit != 1 && t->blend_rsplit != 2 && t->blend_rsplit != 4)
     return fail(IRF_E_INVALID, "blend_rsplit must be 0, 1, 2 or 4");
+  if (t->query_shadow < 0 || t->query_shadow > 1000) return fail(IRF_E_INVALID, "query_shadow must be in [0, 1000]");
   c->tune.trace_blocks = t->trace_blocks;
   c->tune.shadow_blocks = t->shadow_blocks;
   c->tune.shade_blocks = t->shade_blocks;
   c->tune.blend_blocks = t->blend_blocks;
   c->tune.shadow_refill = t->shadow_refill;
   c->tune.blend_rsplit = t->blend_rsplit;
+  c->tune.query_shadow = t->query_shadow;
   return IRF_OK;
 }
 
@@ -1150,6 +1166,7 @@ irf_status irf_get_tuning(const irf_ctx* c, irf_tuning* t) {
   t->blend_blocks = c->tune.blend_blocks;
   t->shadow_refill = c->tune.shadow_refill;
   t->blend_rsplit = c->tune.blend_rsplit;
+  t->query_shadow = c->tune.query_shadow;
   return IRF_OK;
 }
 

@@ -166,9 +166,13 @@ __device__ __forceinline__ int logical_of(int s, int phase, int n) {
   return x < 0 ? x + n : x;
 }
 
+// Probe index x + nx (y + ny z) of the storage slots: every partial product
+// is below the volume's probe count (at most 2^22), so 24-bit multiplies
+// (full rate) are exact.
 __device__ __forceinline__ int storage_index(const VolumeGPU& V, int i, int j, int k) {
-  return slot_of(i, V.phase[0], V.counts[0]) +
-         V.counts[0] * (slot_of(j, V.phase[1], V.counts[1]) + V.counts[1] * slot_of(k, V.phase[2], V.counts[2]));
+  const uint32_t yz = (uint32_t)slot_of(j, V.phase[1], V.counts[1]) +
+                      __umul24((uint32_t)V.counts[1], (uint32_t)slot_of(k, V.phase[2], V.counts[2]));
+  return (int)((uint32_t)slot_of(i, V.phase[0], V.counts[0]) + __umul24((uint32_t)V.counts[0], yz));
 }
 
 __device__ __forceinline__ void logical_index(const VolumeGPU& V, int q, int g[3]) {
@@ -360,10 +364,21 @@ __device__ __forceinline__ float3 volume_query_t(const VolumeGPU& V, float3 X, f
   float ifx, ify;
   tile_footprint_fast<kIrrTile>(look, ix, iy, ifx, ify);
   const int irr_off = iy * kIrrTile + ix;
+  // the cage's storage slots, two per axis, and its eight probe indices
+  int sx[2], sy[2], sz[2];
+#pragma unroll
+  for (int b = 0; b < 2; b++) {
+    sx[b] = slot_of(g[0] + b, V.phase[0], V.counts[0]);
+    sy[b] = slot_of(g[1] + b, V.phase[1], V.counts[1]);
+    sz[b] = slot_of(g[2] + b, V.phase[2], V.counts[2]);
+  }
   int q[8];
   bool use[8];
 #pragma unroll
-  for (int c = 0; c < 8; c++) q[c] = storage_index(V, g[0] + (c & 1), g[1] + ((c >> 1) & 1), g[2] + ((c >> 2) & 1));
+  for (int c = 0; c < 8; c++) {
+    const uint32_t yz = (uint32_t)sy[(c >> 1) & 1] + __umul24((uint32_t)V.counts[1], (uint32_t)sz[c >> 2]);
+    q[c] = (int)((uint32_t)sx[c & 1] + __umul24((uint32_t)V.counts[0], yz));
+  }
 #pragma unroll
   for (int c = 0; c < 8; c++) use[c] = sampled_state(V.states[q[c]]);
   float3 acc = f3(0.0f, 0.0f, 0.0f);

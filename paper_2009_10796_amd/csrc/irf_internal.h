@@ -100,6 +100,7 @@ struct Tuning {
   int32_t blend_blocks;
   int32_t shadow_refill;   // 0: shadow rays in batches of 64; n > 0: lane refill at n idle lanes
   int32_t blend_rsplit;    // workgroups per probe block of the blend: 1, 2 or 4 (0: 4)
+  int32_t query_shadow;    // irf_update_probes_query: per mille of its batch answered in the shadow launch
 };
 
 // Dynamic-object boxes (state step and classification wake rule).
@@ -213,8 +214,12 @@ struct QueryBatch {
   const float* nrm;
   const float* view;
   float* out;
+  int64_t first;   // points [first, first + n) of the arrays
   int64_t n;
 };
+// The shadow rays (batched form) with a query batch answered in the same launch.
+void launch_shadow_query(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid,
+                         const QueryBatch& q, hipStream_t s);
 // The probe-ray trace with a query batch answered in the same launch.
 void launch_trace_query(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, const QueryBatch& q,
                         hipStream_t s);

@@ -392,7 +392,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_query(VolumeSet vs, Scene
       trace_one(vs, sc, L, fs, C, work);
   } else {
     const int64_t i = (int64_t)(blockIdx.x - trace_blocks) * kTraceBlock + threadIdx.x;
-    if (i < q.n) query_point(vs, q.pos, q.nrm, q.view, i, q.out);
+    if (i < q.n) query_point(vs, q.pos, q.nrm, q.view, q.first + i, q.out);
   }
 }
 
@@ -473,6 +473,29 @@ __global__ __launch_bounds__(kTraceBlock) void k_shadow(VolumeSet vs, SceneGPU s
     const int64_t k = k0 + lane;
     const int64_t slot = task_index(before, k < total ? k : total - 1, cap);
     if (k < total) shadow_one<NoCount>(vs, sc, L, fs, slot, nullptr);
+  }
+}
+
+// k_shadow with a share of a query batch in the same launch (blocks past
+// shadow_blocks take one point per lane): the shadow rays read no atlas.
+__global__ __launch_bounds__(kTraceBlock) void k_shadow_query(VolumeSet vs, SceneGPU sc, FrameScratch fs,
+                                                             int shadow_blocks, QueryBatch q) {
+  if ((int)blockIdx.x < shadow_blocks) {
+    const FrameCounters& C = *fs.counters;
+    const LightSet& L = fs.params->L;
+    int64_t total;
+    const int64_t before = tasks_before_region(C, total);
+    const int64_t cap = task_region_cap(fs.max_rays, L.n_dir + L.n_point);
+    const int lane = threadIdx.x & 63;
+    for (int64_t k0 = (int64_t)blockIdx.x * kTraceBlock + (threadIdx.x - lane); k0 < total;
+         k0 += (int64_t)shadow_blocks * kTraceBlock) {
+      const int64_t k = k0 + lane;
+      const int64_t slot = task_index(before, k < total ? k : total - 1, cap);
+      if (k < total) shadow_one<NoCount>(vs, sc, L, fs, slot, nullptr);
+    }
+  } else {
+    const int64_t i = (int64_t)(blockIdx.x - shadow_blocks) * kTraceBlock + threadIdx.x;
+    if (i < q.n) query_point(vs, q.pos, q.nrm, q.view, q.first + i, q.out);
   }
 }
 
@@ -1101,6 +1124,15 @@ void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch 
     irf_launch(k_shadow_refill, dim3(grid_for(cap, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs, refill);
   else
     irf_launch(k_shadow, dim3(grid_for(cap, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs);
+}
+
+void launch_shadow_query(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid,
+                         const QueryBatch& q, hipStream_t s) {
+  if (q.n == 0) return launch_shadow(vs, sc, n_lights, fs, grid, 0, s);
+  const int64_t cap = (fs.max_rays + 63) / 64 * 64 * n_lights;
+  const unsigned sb = fs.max_rays > 0 && n_lights > 0 ? grid_for(cap, grid) : 0;
+  const unsigned qb = blocks_for(q.n, kTraceBlock);
+  irf_launch(k_shadow_query, dim3(sb + qb), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs, (int)sb, q);
 }
 
 void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s) {

@@ -58,7 +58,8 @@ class BufferSizes(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("trace_blocks", C.c_int32), ("shadow_blocks", C.c_int32), ("shade_blocks", C.c_int32),
-                ("blend_blocks", C.c_int32), ("shadow_refill", C.c_int32), ("blend_rsplit", C.c_int32)]
+                ("blend_blocks", C.c_int32), ("shadow_refill", C.c_int32), ("blend_rsplit", C.c_int32),
+                ("query_shadow", C.c_int32)]
 
 
 class KernelTime(C.Structure):

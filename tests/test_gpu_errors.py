@@ -59,6 +59,8 @@ def test_rejected_calls_leave_the_context_usable(torch):
     _expect(irf, irf.E_INVALID, lambda: c.set_tuning(blend_rsplit=3))   # tile shapes 1, 2, 4 (0 = 4)
     _expect(irf, irf.E_INVALID, lambda: c.set_tuning(shadow_refill=65))
     _expect(irf, irf.E_INVALID, lambda: c.set_tuning(trace_blocks=-1))
+    _expect(irf, irf.E_INVALID, lambda: c.set_tuning(query_shadow=1001))
+    _expect(irf, irf.E_INVALID, lambda: c.set_tuning(query_shadow=-1))
     assert c.get_tuning()["blend_rsplit"] == 0 and c.get_tuning()["trace_blocks"] == 0
     lib = irf.load()
     p = torch.zeros((4, 3), dtype=torch.float32, device="cuda")

@@ -3,8 +3,10 @@
 Its queries must equal, bit for bit, irf_query_irradiance called just
 before irf_update_probes on the same stream (the atlases and states the
 previous frame left), and its frame the plain frame: checked on the city
-(a 480x270 G-buffer; the queries inside the probe-ray trace launch, also
-with a persistent trace grid), on the room, and on the city with a dynamic
+(a 480x270 G-buffer; the queries split between the probe-ray trace and
+the shadow-ray launches in several proportions, on persistent and full
+grids, and all in the trace launch when the shadow rays use lane refill),
+on the room, and on the city with a dynamic
 building, whose state step can put probes to sleep before the queries would
 see them (there the queries run first, as their own launch), over frames
 that move the building."""
@@ -75,7 +77,10 @@ def _run(torch, w, frames, tunings=(None,), scene_at=None):
 
 def test_fused_queries_match_query_then_frame_on_the_city(torch):
     w = S.config1(width=480, height=270)
-    res = _run(torch, w, (2, 3, 4), tunings=(None, {"trace_blocks": 37}, {"trace_blocks": 0}))
+    res = _run(torch, w, (2, 3, 4, 5, 6, 7),
+               tunings=(None, {"trace_blocks": 37, "query_shadow": 0}, {"trace_blocks": 0, "query_shadow": 1000},
+                        {"query_shadow": 333, "shadow_blocks": 5}, {"query_shadow": 500, "shadow_refill": 8},
+                        {"query_shadow": 500, "shadow_blocks": 0, "shadow_refill": 0}))
     assert all(q and a for q, a in res), res
 
 
@@ -92,3 +97,35 @@ def test_dynamic_scene_queries_run_before_the_state_step(torch):
     w.queries = S.config1(width=320, height=180).queries
     res = _run(torch, w, (2, 3, 4), scene_at={3: scene_b})
     assert all(q and a for q, a in res), res
+
+
+def test_autotuner_on_fused_frames_keeps_results(torch):
+    from paper_2009_10796_amd import irf, autotune
+    w = S.config1(width=320, height=180)
+    pos, nrm, view = _tensors(torch, w.queries)
+    A, B = irf.build_workload(w), irf.build_workload(w)
+    for c in (A, B):
+        c.classify(w.classify_rotations)
+    eb = torch.empty_like(pos)
+    chosen = autotune.autotune(B, [w.frame_rotation(50 + i) for i in range(6)], frames_per_candidate=2,
+                               step=lambda R: B.update_probes_query(R, pos, nrm, view, eb))
+    print(f"[fused] autotuned {chosen}", flush=True)
+    assert "query_shadow" in chosen and chosen["query_shadow"] in (0, 250, 500, 750)
+    # the tuned context from the same state as the default one: same results
+    for c in (A, B):
+        for v in c.volumes:
+            v.irradiance.zero_()
+            v.distance.zero_()
+    for va, vb in zip(A.volumes, B.volumes):
+        va.states.copy_(vb.states)
+    for c in (A, B):
+        c.update_probes(w.frame_rotation(1))
+    ea = torch.empty_like(pos)
+    for f in (2, 3):
+        A.query_irradiance(pos, nrm, view, ea)
+        A.update_probes(w.frame_rotation(f))
+        B.update_probes_query(w.frame_rotation(f), pos, nrm, view, eb)
+        torch.cuda.synchronize()
+        assert torch.equal(ea, eb) and _same_atlases(A, B), f
+    A.close()
+    B.close()
