@@ -313,7 +313,11 @@ irf_status irf_update_probes_query(irf_ctx* ctx, const float* rotation, const fl
 
 /* Launch shapes of the frame's main kernels: the number of workgroups of
    the persistent probe-ray traversal, shadow-ray traversal, hit shading and
-   matrix-core blend; each strides over the work of all volumes.  0 selects
+   matrix-core blend; each strides over the work of all volumes.  With the
+   shadow rays in batches (shadow_refill = 0) the hit shading's indirect
+   term (the previous frame's irradiance at each hit, which needs the hit
+   alone) runs in the shadow-ray launch, on shade_blocks workgroups of its
+   own, and the shading launch adds the direct light.  0 selects
    one workgroup per work unit of the largest possible frame.  A new context
    starts at 0 except for the shadow rays: 16 workgroups per compute unit,
    what stays resident at once at eight waves per SIMD, each lane looping

@@ -396,9 +396,13 @@ hipError_t enqueue_frame_on(irf_ctx* c, const float* rotation, hipStream_t st, h
   }
   // the fused batch: a share in the shadow launch (batched shadow rays only),
   // the rest in the trace launch
+  // the batched shadow rays share their launch with the hit shading's
+  // indirect terms (and a share of the queries); with lane refill, or no
+  // light, the hit shading queries the indirect terms itself
+  const bool stage = nl > 0 && c->tune.shadow_refill == 0;
   QueryBatch q_trace = {}, q_shadow = {};
   if (fused) {
-    const int64_t ns = nl > 0 && c->tune.shadow_refill == 0 ? qb->n * c->tune.query_shadow / 1000 : 0;
+    const int64_t ns = stage ? qb->n * c->tune.query_shadow / 1000 : 0;
     q_trace = *qb;
     q_trace.n = qb->n - ns;
     q_shadow = *qb;
@@ -412,14 +416,14 @@ hipError_t enqueue_frame_on(irf_ctx* c, const float* rotation, hipStream_t st, h
     ProfScope p(c, "trace", st);
     launch_trace(vs, sc, fs, c->tune.trace_blocks, st);
   }
-  if (q_shadow.n > 0) {
-    ProfScope p(c, "shadow_query", st);
-    launch_shadow_query(vs, sc, nl, fs, c->tune.shadow_blocks, q_shadow, st);
+  if (stage) {
+    ProfScope p(c, q_shadow.n > 0 ? "shadow_query" : "shadow", st);
+    launch_shadow_stage(vs, sc, nl, fs, c->tune.shadow_blocks, c->tune.shade_blocks, q_shadow, st);
   } else if (nl > 0) {
-    ProfScope p(c, c->tune.shadow_refill > 0 ? "shadow_refill" : "shadow", st);
+    ProfScope p(c, "shadow_refill", st);
     launch_shadow(vs, sc, nl, fs, c->tune.shadow_blocks, c->tune.shadow_refill, st);
   }
-  { ProfScope p(c, "shade", st); launch_shade(vs, sc, fs, c->tune.shade_blocks, st); }
+  { ProfScope p(c, "shade", st); launch_shade(vs, sc, fs, c->tune.shade_blocks, stage, st); }
   if (atlas_wait) {
     hipError_t e = hipStreamWaitEvent(st, atlas_wait, 0);
     if (e != hipSuccess) return e;

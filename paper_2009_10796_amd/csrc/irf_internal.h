@@ -217,15 +217,19 @@ struct QueryBatch {
   int64_t first;   // points [first, first + n) of the arrays
   int64_t n;
 };
-// The shadow rays (batched form) with a query batch answered in the same launch.
-void launch_shadow_query(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid,
+// The shadow rays in batches of 64 (grid), the indirect term of every
+// front-face hit (hit_grid: the hit shading's grid) and a query batch (may be
+// empty), one launch.
+void launch_shadow_stage(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, int hit_grid,
                          const QueryBatch& q, hipStream_t s);
 // The probe-ray trace with a query batch answered in the same launch.
 void launch_trace_query(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, const QueryBatch& q,
                         hipStream_t s);
+// The shadow rays with lane refill (k_shadow_refill, threshold `refill`).
 void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, int refill,
                    hipStream_t s);
-void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s);
+// The hit shading; indirect_done: launch_shadow_stage computed the indirect terms.
+void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, bool indirect_done, hipStream_t s);
 void launch_blend(const VolumeSet& vs, FrameScratch fs, hipStream_t s);
 void launch_blend_mma(const VolumeSet& vs, FrameScratch fs, int grid, int rsplit, hipStream_t s);
 void launch_query(const VolumeSet& vs, const float* pos, const float* nrm, const float* view, int64_t n,

@@ -461,43 +461,6 @@ __device__ __forceinline__ void shadow_one(const VolumeSet& vs, const SceneGPU& 
   if (!cnt && hit < 0) fs.vis[(int64_t)l * fs.max_rays + id] = 1;
 }
 
-__global__ __launch_bounds__(kTraceBlock) void k_shadow(VolumeSet vs, SceneGPU sc, FrameScratch fs) {
-  const FrameCounters& C = *fs.counters;
-  const LightSet& L = fs.params->L;
-  int64_t total;
-  const int64_t before = tasks_before_region(C, total);
-  const int64_t cap = task_region_cap(fs.max_rays, L.n_dir + L.n_point);
-  const int lane = threadIdx.x & 63;
-  for (int64_t k0 = (int64_t)blockIdx.x * kTraceBlock + (threadIdx.x - lane); k0 < total;
-       k0 += (int64_t)gridDim.x * kTraceBlock) {
-    const int64_t k = k0 + lane;
-    const int64_t slot = task_index(before, k < total ? k : total - 1, cap);
-    if (k < total) shadow_one<NoCount>(vs, sc, L, fs, slot, nullptr);
-  }
-}
-
-// k_shadow with a share of a query batch in the same launch (blocks past
-// shadow_blocks take one point per lane): the shadow rays read no atlas.
-__global__ __launch_bounds__(kTraceBlock) void k_shadow_query(VolumeSet vs, SceneGPU sc, FrameScratch fs,
-                                                             int shadow_blocks, QueryBatch q) {
-  if ((int)blockIdx.x < shadow_blocks) {
-    const FrameCounters& C = *fs.counters;
-    const LightSet& L = fs.params->L;
-    int64_t total;
-    const int64_t before = tasks_before_region(C, total);
-    const int64_t cap = task_region_cap(fs.max_rays, L.n_dir + L.n_point);
-    const int lane = threadIdx.x & 63;
-    for (int64_t k0 = (int64_t)blockIdx.x * kTraceBlock + (threadIdx.x - lane); k0 < total;
-         k0 += (int64_t)shadow_blocks * kTraceBlock) {
-      const int64_t k = k0 + lane;
-      const int64_t slot = task_index(before, k < total ? k : total - 1, cap);
-      if (k < total) shadow_one<NoCount>(vs, sc, L, fs, slot, nullptr);
-    }
-  } else {
-    const int64_t i = (int64_t)(blockIdx.x - shadow_blocks) * kTraceBlock + threadIdx.x;
-    if (i < q.n) query_point(vs, q.pos, q.nrm, q.view, q.first + i, q.out);
-  }
-}
 
 // Any-hit shadow rays with lane refill.  Each wave owns one contiguous range
 // of the dense task order, fixed by its index (no atomics); a lane whose ray
@@ -612,6 +575,39 @@ __global__ __launch_bounds__(kTraceBlock) void k_shadow_refill(VolumeSet vs, Sce
 
 // Radiance and distance carried by each probe ray (backface rule of the
 // self-shadow-bias section: radiance 0, distance shortened by 80 %).
+// A probe ray's front-face hit: the hit point, its normal and the ray
+// direction (false for a miss or a backface).
+__device__ __forceinline__ bool front_hit(const VolumeSet& vs, const FrameScratch& fs, const FrameCounters& C,
+                                          int64_t id, const HitRec& h, float3& X, float3& ng, float3& w) {
+  if (h.tri < 0) return false;
+  const RaySlot s = locate_ray(vs, C, fs.active, id);
+  const VolumeGPU& V = vs.v[s.v];
+  const float3 o = slot_position(fs, s);
+  const float4 w4 = fs.omega[V.omega_base + s.r];
+  w = f3(w4.x, w4.y, w4.z);
+  ng = f3(h.n[0], h.n[1], h.n[2]);
+  if (dot(w, ng) > 0.0f) return false;
+  X = f3(fmaf(h.t, w.x, o.x), fmaf(h.t, w.y, o.y), fmaf(h.t, w.z, o.z));
+  return true;
+}
+
+// The indirect term of a front-face hit's shading: the previous frame's
+// irradiance at the hit, queried from all volumes; it needs the hit alone,
+// not the shadow rays, so it runs in the shadow-ray launch and waits in the
+// ray's radiance slot for shade_one.
+__device__ __forceinline__ void shade_indirect_one(const VolumeSet& vs, const FrameScratch& fs,
+                                                   const FrameCounters& C, int64_t id) {
+  const HitRec h = fs.hits[id];
+  float3 X, ng, w;
+  if (!front_hit(vs, fs, C, id, h, X, ng, w)) return;
+  const float3 ind = query_irradiance(vs, X, ng, f3(-w.x, -w.y, -w.z));
+  fs.rays[id] = make_float4(ind.x, ind.y, ind.z, 0.0f);
+}
+
+// The hit shading of one probe ray.  IND: the indirect term is already in
+// the ray's radiance slot (shade_indirect_one ran); otherwise it is queried
+// here.
+template <bool IND>
 __device__ __forceinline__ void shade_one(const VolumeSet& vs, const SceneGPU& sc, const LightSet& L,
                                           const FrameScratch& fs, const FrameCounters& C, int64_t id) {
   HitRec h = fs.hits[id];
@@ -658,7 +654,13 @@ __device__ __forceinline__ void shade_one(const VolumeSet& vs, const SceneGPU& s
           direct = direct + k * f3(L.irr[l][0], L.irr[l][1], L.irr[l][2]);
         }
       }
-      float3 ind = query_irradiance(vs, X, ng, f3(-w.x, -w.y, -w.z));
+      float3 ind;
+      if (IND) {
+        const float4 r = fs.rays[id];
+        ind = f3(r.x, r.y, r.z);
+      } else {
+        ind = query_irradiance(vs, X, ng, f3(-w.x, -w.y, -w.z));
+      }
       float4 al = sc.albedo[h.mat], em = sc.emission[h.mat];
       const float inv_pi = 0.318309886183790672f;
       out = make_float4(fmaf(al.x, fmaf(direct.x, inv_pi, ind.x), em.x), fmaf(al.y, fmaf(direct.y, inv_pi, ind.y), em.y),
@@ -674,7 +676,63 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade(VolumeSet vs, SceneGPU sc
   const int64_t total = C.ray_base[vs.n];
   for (int64_t id = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x; id < total;
        id += (int64_t)gridDim.x * kTraceBlock)
-    shade_one(vs, sc, L, fs, C, id);
+    shade_one<false>(vs, sc, L, fs, C, id);
+}
+
+// The hit shading after the shadow-ray launch computed the indirect terms.
+__global__ __launch_bounds__(kTraceBlock) void k_shade_direct(VolumeSet vs, SceneGPU sc, FrameScratch fs) {
+  const FrameCounters& C = *fs.counters;
+  const LightSet& L = fs.params->L;
+  const int64_t total = C.ray_base[vs.n];
+  for (int64_t id = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x; id < total;
+       id += (int64_t)gridDim.x * kTraceBlock)
+    shade_one<true>(vs, sc, L, fs, C, id);
+}
+
+// The shadow-ray launch (batched form): blocks [0, shadow_blocks) take the
+// shadow tasks, 64 consecutive ones per wave, striding over the dense task
+// order; the next hit_blocks stride over the probe rays and compute the
+// indirect term of each front-face hit (shade_indirect_one: it reads the
+// hit and the atlases, not the shadow rays); the rest, in k_shadow_query,
+// take one point per lane of a share of a query batch against the atlases
+// the previous frame left.  The shadow rays and the queries read no atlas
+// that this frame writes; their blocks come first, so they are resident from
+// the start and the others fill the issue slots their traversal leaves.
+__device__ __forceinline__ void shadow_stage(const VolumeSet& vs, const SceneGPU& sc, const FrameScratch& fs,
+                                             int shadow_blocks, int hit_blocks, const QueryBatch& q) {
+  const FrameCounters& C = *fs.counters;
+  const int b = (int)blockIdx.x;
+  if (b < shadow_blocks) {
+    const LightSet& L = fs.params->L;
+    int64_t total;
+    const int64_t before = tasks_before_region(C, total);
+    const int64_t cap = task_region_cap(fs.max_rays, L.n_dir + L.n_point);
+    const int lane = threadIdx.x & 63;
+    for (int64_t k0 = (int64_t)b * kTraceBlock + (threadIdx.x - lane); k0 < total;
+         k0 += (int64_t)shadow_blocks * kTraceBlock) {
+      const int64_t k = k0 + lane;
+      const int64_t slot = task_index(before, k < total ? k : total - 1, cap);
+      if (k < total) shadow_one<NoCount>(vs, sc, L, fs, slot, nullptr);
+    }
+  } else if (b < shadow_blocks + hit_blocks) {
+    const int64_t total = C.ray_base[vs.n];
+    for (int64_t id = (int64_t)(b - shadow_blocks) * kTraceBlock + threadIdx.x; id < total;
+         id += (int64_t)hit_blocks * kTraceBlock)
+      shade_indirect_one(vs, fs, C, id);
+  } else {
+    const int64_t i = (int64_t)(b - shadow_blocks - hit_blocks) * kTraceBlock + threadIdx.x;
+    if (i < q.n) query_point(vs, q.pos, q.nrm, q.view, q.first + i, q.out);
+  }
+}
+
+__global__ __launch_bounds__(kTraceBlock) void k_shadow(VolumeSet vs, SceneGPU sc, FrameScratch fs, int shadow_blocks,
+                                                        int hit_blocks) {
+  shadow_stage(vs, sc, fs, shadow_blocks, hit_blocks, QueryBatch{});
+}
+
+__global__ __launch_bounds__(kTraceBlock) void k_shadow_query(VolumeSet vs, SceneGPU sc, FrameScratch fs,
+                                                             int shadow_blocks, int hit_blocks, QueryBatch q) {
+  shadow_stage(vs, sc, fs, shadow_blocks, hit_blocks, q);
 }
 
 // ---- classification (Section "Full Probe Initialization Algorithm")
@@ -1120,24 +1178,30 @@ void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch 
                    hipStream_t s) {
   if (fs.max_rays == 0 || n_lights == 0) return;
   int64_t cap = (fs.max_rays + 63) / 64 * 64 * n_lights;
-  if (refill > 0)
-    irf_launch(k_shadow_refill, dim3(grid_for(cap, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs, refill);
-  else
-    irf_launch(k_shadow, dim3(grid_for(cap, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs);
+  irf_launch(k_shadow_refill, dim3(grid_for(cap, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs,
+             refill > 0 ? refill : 64);
 }
 
-void launch_shadow_query(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid,
+void launch_shadow_stage(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, int hit_grid,
                          const QueryBatch& q, hipStream_t s) {
-  if (q.n == 0) return launch_shadow(vs, sc, n_lights, fs, grid, 0, s);
   const int64_t cap = (fs.max_rays + 63) / 64 * 64 * n_lights;
   const unsigned sb = fs.max_rays > 0 && n_lights > 0 ? grid_for(cap, grid) : 0;
+  const unsigned hb = fs.max_rays > 0 ? grid_for(fs.max_rays, hit_grid) : 0;
   const unsigned qb = blocks_for(q.n, kTraceBlock);
-  irf_launch(k_shadow_query, dim3(sb + qb), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs, (int)sb, q);
+  if (sb + hb + qb == 0) return;
+  if (q.n > 0)
+    irf_launch(k_shadow_query, dim3(sb + hb + qb), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs, (int)sb,
+               (int)hb, q);
+  else
+    irf_launch(k_shadow, dim3(sb + hb), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs, (int)sb, (int)hb);
 }
 
-void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, hipStream_t s) {
+void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, bool indirect_done, hipStream_t s) {
   if (fs.max_rays == 0) return;
-  irf_launch(k_shade, dim3(grid_for(fs.max_rays, grid)), dim3(kTraceBlock), 0, s, vs, sc, fs);
+  if (indirect_done)
+    irf_launch(k_shade_direct, dim3(grid_for(fs.max_rays, grid)), dim3(kTraceBlock), 0, s, vs, sc, fs);
+  else
+    irf_launch(k_shade, dim3(grid_for(fs.max_rays, grid)), dim3(kTraceBlock), 0, s, vs, sc, fs);
 }
 
 void launch_classify(const VolumeSet& vs, SceneGPU sc, ObjectBoxes boxes, const float* rotations, int K,
