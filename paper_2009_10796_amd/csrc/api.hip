@@ -396,9 +396,9 @@ hipError_t enqueue_frame_on(irf_ctx* c, const float* rotation, hipStream_t st, h
   }
   // the fused batch: a share in the shadow launch (batched shadow rays only),
   // the rest in the trace launch
-  // the batched shadow rays share their launch with the hit shading's
-  // indirect terms (and a share of the queries); with lane refill, or no
-  // light, the hit shading queries the indirect terms itself
+  // the shadow rays share their launch with the hit shading's indirect
+  // terms (and, in batches, a share of the queries); with no light the hit
+  // shading queries the indirect terms itself
   const bool stage = nl > 0 && c->tune.shadow_refill == 0;
   QueryBatch q_trace = {}, q_shadow = {};
   if (fused) {
@@ -421,9 +421,9 @@ hipError_t enqueue_frame_on(irf_ctx* c, const float* rotation, hipStream_t st, h
     launch_shadow_stage(vs, sc, nl, fs, c->tune.shadow_blocks, c->tune.shade_blocks, q_shadow, st);
   } else if (nl > 0) {
     ProfScope p(c, "shadow_refill", st);
-    launch_shadow(vs, sc, nl, fs, c->tune.shadow_blocks, c->tune.shadow_refill, st);
+    launch_shadow(vs, sc, nl, fs, c->tune.shadow_blocks, c->tune.shade_blocks, c->tune.shadow_refill, st);
   }
-  { ProfScope p(c, "shade", st); launch_shade(vs, sc, fs, c->tune.shade_blocks, stage, st); }
+  { ProfScope p(c, "shade", st); launch_shade(vs, sc, fs, c->tune.shade_blocks, nl > 0, st); }
   if (atlas_wait) {
     hipError_t e = hipStreamWaitEvent(st, atlas_wait, 0);
     if (e != hipSuccess) return e;

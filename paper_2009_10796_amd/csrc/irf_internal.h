@@ -225,9 +225,10 @@ void launch_shadow_stage(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameSc
 // The probe-ray trace with a query batch answered in the same launch.
 void launch_trace_query(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, const QueryBatch& q,
                         hipStream_t s);
-// The shadow rays with lane refill (k_shadow_refill, threshold `refill`).
-void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, int refill,
-                   hipStream_t s);
+// The shadow rays with lane refill (k_shadow_refill, threshold `refill`) and
+// the indirect term of every front-face hit (hit_grid), one launch.
+void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, int hit_grid,
+                   int refill, hipStream_t s);
 // The hit shading; indirect_done: launch_shadow_stage computed the indirect terms.
 void launch_shade(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int grid, bool indirect_done, hipStream_t s);
 void launch_blend(const VolumeSet& vs, FrameScratch fs, hipStream_t s);

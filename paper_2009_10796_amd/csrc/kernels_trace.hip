@@ -472,15 +472,17 @@ __device__ __forceinline__ void shadow_one(const VolumeSet& vs, const SceneGPU& 
 // of the wave takes part in it: the task index search reads other lanes).
 // Each pass of the loop takes every active lane through its inner nodes to
 // the next leaf (or the end), then that leaf's triangles.
-__global__ __launch_bounds__(kTraceBlock) void k_shadow_refill(VolumeSet vs, SceneGPU sc, FrameScratch fs,
-                                                               int refill) {
+// The ranges belong to the waves of the launch's first `shadow_blocks`
+// workgroups (k_shadow_refill below).
+__device__ __forceinline__ void refill_shadow_rays(const VolumeSet& vs, const SceneGPU& sc, const FrameScratch& fs,
+                                                   int refill, int shadow_blocks) {
   const FrameCounters& C = *fs.counters;
   const LightSet& L = fs.params->L;
   int64_t total;
   const int64_t before = tasks_before_region(C, total);
   const int64_t cap = task_region_cap(fs.max_rays, L.n_dir + L.n_point);
   const int lane = threadIdx.x & 63;
-  const int64_t waves = (int64_t)gridDim.x * (kTraceBlock / 64);
+  const int64_t waves = (int64_t)shadow_blocks * (kTraceBlock / 64);
   const int64_t wave = (int64_t)blockIdx.x * (kTraceBlock / 64) + (threadIdx.x >> 6);
   const int64_t per = (total + waves - 1) / waves;
   int64_t next = wave * per;                  // the range's next task (same on every lane)
@@ -573,8 +575,6 @@ __global__ __launch_bounds__(kTraceBlock) void k_shadow_refill(VolumeSet vs, Sce
   }
 }
 
-// Radiance and distance carried by each probe ray (backface rule of the
-// self-shadow-bias section: radiance 0, distance shortened by 80 %).
 // A probe ray's front-face hit: the hit point, its normal and the ray
 // direction (false for a miss or a backface).
 __device__ __forceinline__ bool front_hit(const VolumeSet& vs, const FrameScratch& fs, const FrameCounters& C,
@@ -604,9 +604,10 @@ __device__ __forceinline__ void shade_indirect_one(const VolumeSet& vs, const Fr
   fs.rays[id] = make_float4(ind.x, ind.y, ind.z, 0.0f);
 }
 
-// The hit shading of one probe ray.  IND: the indirect term is already in
-// the ray's radiance slot (shade_indirect_one ran); otherwise it is queried
-// here.
+// Radiance and distance carried by each probe ray (backface rule of the
+// self-shadow-bias section: radiance 0, distance shortened by 80 %).  IND:
+// the indirect term of a front-face hit is already in the ray's radiance
+// slot (shade_indirect_one ran); otherwise it is queried here.
 template <bool IND>
 __device__ __forceinline__ void shade_one(const VolumeSet& vs, const SceneGPU& sc, const LightSet& L,
                                           const FrameScratch& fs, const FrameCounters& C, int64_t id) {
@@ -733,6 +734,23 @@ __global__ __launch_bounds__(kTraceBlock) void k_shadow(VolumeSet vs, SceneGPU s
 __global__ __launch_bounds__(kTraceBlock) void k_shadow_query(VolumeSet vs, SceneGPU sc, FrameScratch fs,
                                                              int shadow_blocks, int hit_blocks, QueryBatch q) {
   shadow_stage(vs, sc, fs, shadow_blocks, hit_blocks, q);
+}
+
+// The shadow rays with lane refill (refill_shadow_rays) on the first
+// shadow_blocks workgroups and the hit shading's indirect terms on the next
+// hit_blocks, as in shadow_stage.
+__global__ __launch_bounds__(kTraceBlock) void k_shadow_refill(VolumeSet vs, SceneGPU sc, FrameScratch fs, int refill,
+                                                               int shadow_blocks, int hit_blocks) {
+  const int b = (int)blockIdx.x;
+  if (b < shadow_blocks) {
+    refill_shadow_rays(vs, sc, fs, refill, shadow_blocks);
+  } else {
+    const FrameCounters& C = *fs.counters;
+    const int64_t total = C.ray_base[vs.n];
+    for (int64_t id = (int64_t)(b - shadow_blocks) * kTraceBlock + threadIdx.x; id < total;
+         id += (int64_t)hit_blocks * kTraceBlock)
+      shade_indirect_one(vs, fs, C, id);
+  }
 }
 
 // ---- classification (Section "Full Probe Initialization Algorithm")
@@ -1174,12 +1192,13 @@ void launch_trace_query(const VolumeSet& vs, SceneGPU sc, FrameScratch fs, int g
   irf_launch(k_trace_query, dim3(tb + qb), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs, (int)tb, q);
 }
 
-void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, int refill,
-                   hipStream_t s) {
+void launch_shadow(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, int hit_grid,
+                   int refill, hipStream_t s) {
   if (fs.max_rays == 0 || n_lights == 0) return;
-  int64_t cap = (fs.max_rays + 63) / 64 * 64 * n_lights;
-  irf_launch(k_shadow_refill, dim3(grid_for(cap, grid)), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs,
-             refill > 0 ? refill : 64);
+  const int64_t cap = (fs.max_rays + 63) / 64 * 64 * n_lights;
+  const unsigned sb = grid_for(cap, grid), hb = grid_for(fs.max_rays, hit_grid);
+  irf_launch(k_shadow_refill, dim3(sb + hb), dim3(kTraceBlock), stack_bytes(sc), s, vs, sc, fs,
+             refill > 0 ? refill : 64, (int)sb, (int)hb);
 }
 
 void launch_shadow_stage(const VolumeSet& vs, SceneGPU sc, int n_lights, FrameScratch fs, int grid, int hit_grid,
