@@ -45,11 +45,14 @@ VALU_PEAK_GINSTR = SIMDS * CLOCK_GHZ / 4.0
 NODE_BYTES, TRI_BYTES, RAY_IO_BYTES = 64, 48, 32
 COUNTER_FILES = {"city": os.path.join(ROOT, "profiles", "city-16x8x16-256rays_counters.md"),
                  "terrain": os.path.join(ROOT, "profiles", "terrain-4x32x16x32-192rays_counters.md")}
-# kernel symbol -> bench key (longer names first: k_shadow_refill before k_shadow)
+# kernel symbol -> bench key (longer names first: k_shadow_refill before
+# k_shadow).  The hit shading runs as k_shade_direct when the shadow-ray
+# launch computed the indirect terms (every frame with lights), else k_shade:
+# one key, since a frame runs one of them
 KERNEL_KEYS = (("k_shadow_refill", "shadow_refill"), ("k_shadow_count", "shadow_count"),
                ("k_shadow_query", "shadow_query"), ("k_shadow", "shadow"),
                ("k_trace_count", "trace_count"), ("k_trace_query", "trace_query"), ("k_trace", "trace"), ("k_shade_terms", "shade_terms"),
-               ("k_shade", "shade"), ("k_blend_mma", "blend_mma"), ("k_blend_f32", "blend_valu"),
+               ("k_shade_direct", "shade"), ("k_shade", "shade"), ("k_blend_mma", "blend_mma"), ("k_blend_f32", "blend_valu"),
                ("k_blend_backward", "blend_backward"), ("k_query_terms", "query_terms"), ("k_query", "query"),
                ("k_gather_pieces", "gather_pieces"), ("k_finish_pieces", "finish_pieces"),
                ("k_piece_offsets", "piece_offsets"), ("k_blend_norms", "blend_norms"), ("k_segments", "segments"),
