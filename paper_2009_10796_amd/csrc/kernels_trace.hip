@@ -461,7 +461,6 @@ __device__ __forceinline__ void shadow_one(const VolumeSet& vs, const SceneGPU& 
   if (!cnt && hit < 0) fs.vis[(int64_t)l * fs.max_rays + id] = 1;
 }
 
-
 // Any-hit shadow rays with lane refill.  Each wave owns one contiguous range
 // of the dense task order, fixed by its index (no atomics); a lane whose ray
 // has ended takes the range's next task at the next refill, so the wave's
