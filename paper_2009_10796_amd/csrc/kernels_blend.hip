@@ -29,16 +29,15 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
 constexpr int kPB = 8;            // probes per workgroup
-// Rays per LDS chunk: 64 for float32 inputs (a 12.25 KiB B tile, so a
-// compute unit holds many items at once: on the terrain cascades the blend
-// took 130-170 us with 256-ray chunks and 78-95 us with 64), one whole round
-// of A fragments (256 rays) for 16-bit inputs.  The products run over the
-// rays in the same order whatever the chunk, so results do not change.
-template <int MODE>
-constexpr int kKC = MODE == IRF_BLEND_F32 ? 64 : 256;
+// Rays per LDS chunk: 64, a B tile of 12.25 KiB (float32) or 6.75 KiB
+// (16-bit), so a compute unit holds many work items at once.  On the terrain
+// cascades the blend took 130-170 us (float32) and 88-105 us (16-bit) with
+// 256-ray chunks, 78-95 and 51-75 us with 64.  The products run over the rays
+// in the same order whatever the chunk, so results do not change.
+constexpr int kKC = 64;
 constexpr int kBlendMmaBlock = 256;
 constexpr int kBfStride = 49;     // float32 B tile: [k][48 + 1]
-constexpr int kBtStride = 256 + 8;// 16-bit B tile: [col][256 + 8]
+constexpr int kBtStride = 64 + 8; // 16-bit B tile: [col][64 + 8]
 
 template <int MODE>
 struct Mma;
@@ -65,7 +64,7 @@ struct Mma<IRF_BLEND_F32> {
 template <>
 struct Mma<IRF_BLEND_BF16> {
   static constexpr int KSTEP = 32;
-  static constexpr int KB = 8;
+  static constexpr int KB = 2;     // k-steps whose A fragments are loaded together (one 64-ray chunk)
   typedef v8bf A;
   __device__ static A load_a(const char* wbase, int row_tile, int k, int N, int lane) {
     const int kk = min(k + 8 * (lane / 16), N - 8);   // rays past N: any finite weights (their B is zero)
@@ -80,7 +79,7 @@ struct Mma<IRF_BLEND_BF16> {
 template <>
 struct Mma<IRF_BLEND_F16> {
   static constexpr int KSTEP = 32;
-  static constexpr int KB = 8;
+  static constexpr int KB = 2;     // k-steps whose A fragments are loaded together (one 64-ray chunk)
   typedef v8h A;
   __device__ static A load_a(const char* wbase, int row_tile, int k, int N, int lane) {
     const int kk = min(k + 8 * (lane / 16), N - 8);   // rays past N: any finite weights (their B is zero)
@@ -225,10 +224,9 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
   const float4* rays = fs.rays + C.ray_base[v] + (int64_t)slot0 * N;
   typedef Mma<MODE> M;
   constexpr int kRound = M::KB * M::KSTEP;   // rays per round of A fragments
-  constexpr int KC = kKC<MODE>;
-  constexpr int kRounds = KC / kRound;       // rounds per chunk
-  constexpr int kStage = kPB * KC / kBlendMmaBlock;   // rays each thread stages per chunk
-  static_assert(KC % kRound == 0 && (kPB * KC) % kBlendMmaBlock == 0, "whole rounds and stages per chunk");
+  constexpr int kRounds = kKC / kRound;      // rounds per chunk
+  constexpr int kStage = kPB * kKC / kBlendMmaBlock;   // rays each thread stages per chunk
+  static_assert(kKC % kRound == 0 && (kPB * kKC) % kBlendMmaBlock == 0, "whole rounds and stages per chunk");
   const char* wbase = (const char*)fs.weights + V.weight_base;
   // Every global read that does not depend on another is issued up front, so
   // that one memory latency, not four, precedes the products: the first
@@ -239,7 +237,7 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
   typename M::A a[kRounds * M::KB];
   float4 rv[kStage];
   auto load_a = [&](int tile, int kc) {
-    const int kn = min(KC, N - kc);
+    const int kn = min(kKC, N - kc);
     const int rounds = (kn + kRound - 1) / kRound;
 #pragma unroll
     for (int r0 = 0; r0 < kRounds; r0++)
@@ -249,7 +247,7 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
           a[r0 * M::KB + j] = M::load_a(wbase, tile, kc + r0 * kRound + j * M::KSTEP, N, lane);
   };
   auto load_rays = [&](int kc) {
-    const int kn = min(KC, N - kc);
+    const int kn = min(kKC, N - kc);
 #pragma unroll
     for (int i = 0; i < kStage; i++) {
       const int e = (int)threadIdx.x + i * kBlendMmaBlock;
@@ -294,12 +292,12 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
   v4f acc[kTiles][2];
 #pragma unroll
   for (int i = 0; i < kTiles; i++) acc[i][0] = acc[i][1] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int kc = 0; kc < N; kc += KC) {
+  for (int kc = 0; kc < N; kc += kKC) {
     if (kc > 0) {
       load_a(rt[0], kc);
       load_rays(kc);
     }
-    const int kn = min(KC, N - kc);
+    const int kn = min(kKC, N - kc);
     // the products run over whole rounds with no per-step guard (a guarded
     // step splits the accumulator chain into basic blocks); rays from kn to
     // the round's end are zero in B
@@ -373,7 +371,7 @@ __device__ __forceinline__ void blend_item(const VolumeSet& vs, const FrameScrat
 // rays staged RS times -- on one XCD, and on one L2.
 template <int MODE, int RS>
 __global__ __launch_bounds__(kBlendMmaBlock) void k_blend_mma(VolumeSet vs, FrameScratch fs) {
-  constexpr int LDS_BYTES = MODE == IRF_BLEND_F32 ? kKC<MODE> * kBfStride * 4 : 48 * kBtStride * 2;
+  constexpr int LDS_BYTES = MODE == IRF_BLEND_F32 ? kKC * kBfStride * 4 : 48 * kBtStride * 2;
   __shared__ __attribute__((aligned(16))) char lds[LDS_BYTES];
   __shared__ int s_q[kPB];
   __shared__ bool s_fresh[kPB];
@@ -386,7 +384,7 @@ __global__ __launch_bounds__(kBlendMmaBlock) void k_blend_mma(VolumeSet vs, Fram
   }
   // B columns 24..31 (the irradiance tiles' unused half) are zero for the
   // whole kernel; the staging never writes them
-  for (int e = threadIdx.x; e < kKC<MODE> * 8; e += kBlendMmaBlock) store_b<MODE>(lds, e / 8, 24 + e % 8, 0.0f);
+  for (int e = threadIdx.x; e < kKC * 8; e += kBlendMmaBlock) store_b<MODE>(lds, e / 8, 24 + e % 8, 0.0f);
   const int blocks = block_base[vs.n];
   const int items = (blocks + 7) / 8 * 8 * RS;
   for (int wi = blockIdx.x; wi < items; wi += gridDim.x) {
