@@ -297,11 +297,10 @@ irf_status irf_query_irradiance(irf_ctx* ctx, const float* pos, const float* nrm
    would have written, and the frame's results are those of
    irf_update_probes; only the schedule differs.  The queries run inside the
    frame's probe-ray trace and shadow-ray launches, split by the tuning's
-   query_shadow (neither traversal reads an atlas or a probe state, nor
-   writes one): the traversals' waves wait on dependent node fetches and
-   leave issue slots that the queries' arithmetic fills (Section "Probe
-   Query" for what a query computes, Section "Probe Update" for the
-   frame).
+   query_shadow (neither launch writes an atlas or a probe state): the
+   traversals' waves wait on dependent node fetches and leave issue slots
+   that the queries' arithmetic fills (Section "Probe Query" for what a
+   query computes, Section "Probe Update" for the frame).
    A renderer that shades frame f with the probes of update f issues
    update f+1 together with the queries of frame f.  When the scene has
    dynamic objects the frame's state step can rewrite the states a query

@@ -695,9 +695,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_shade_direct(VolumeSet vs, Scen
 // indirect term of each front-face hit (shade_indirect_one: it reads the
 // hit and the atlases, not the shadow rays); the rest, in k_shadow_query,
 // take one point per lane of a share of a query batch against the atlases
-// the previous frame left.  The shadow rays and the queries read no atlas
-// that this frame writes; their blocks come first, so they are resident from
-// the start and the others fill the issue slots their traversal leaves.
+// the previous frame left.  Nothing in this launch writes an atlas or a
+// probe state.  The shadow rays' blocks come first, so they are resident
+// from the start and the others fill the issue slots their traversal leaves.
 __device__ __forceinline__ void shadow_stage(const VolumeSet& vs, const SceneGPU& sc, const FrameScratch& fs,
                                              int shadow_blocks, int hit_blocks, const QueryBatch& q) {
   const FrameCounters& C = *fs.counters;
