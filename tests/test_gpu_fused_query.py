@@ -6,7 +6,7 @@ previous frame left), and its frame the plain frame: checked on the city
 (a 480x270 G-buffer; the queries split between the probe-ray trace and
 the shadow-ray launches in several proportions, on persistent and full
 grids, and all in the trace launch when the shadow rays use lane refill),
-on the room, and on the city with a dynamic
+on the room, on four cascades (also past 4,096 probes), and on the city with a dynamic
 building, whose state step can put probes to sleep before the queries would
 see them (there the queries run first, as their own launch), over frames
 that move the building."""
@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 from paper_2009_10796_amd import scenes as S
+from tests.test_gpu_cascades import small_terrain
 from tests.test_gpu_dynamic_states import city_with_dynamic_building
 
 pytestmark = pytest.mark.gpu
@@ -86,6 +87,18 @@ def test_fused_queries_match_query_then_frame_on_the_city(torch):
 
 def test_fused_queries_match_query_then_frame_on_the_room(torch):
     res = _run(torch, S.config0(), (2, 3))
+    assert all(q and a for q, a in res), res
+
+
+@pytest.mark.parametrize("counts,rays", [((8, 4, 8), 64), ((16, 8, 16), 32)], ids=["1024 probes", "8192 probes"])
+def test_fused_queries_match_on_cascades(torch, counts, rays):
+    # four cascades (the query blends them); 8,192 probes: the frame start's
+    # two-pass compaction; lane refill and batched shadow rays
+    w = small_terrain(cascade_counts=counts, rays=rays)
+    w.queries = S.surface_points(w.scene, 20000, 3)
+    res = _run(torch, w, (2, 3, 4), tunings=({"shadow_refill": 8, "shadow_blocks": 64},
+                                             {"shadow_refill": 0, "query_shadow": 500},
+                                             {"shadow_refill": 0, "query_shadow": 900, "trace_blocks": 11}))
     assert all(q and a for q, a in res), res
 
 
