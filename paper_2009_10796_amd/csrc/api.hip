@@ -356,8 +356,8 @@ irf_status launched() {
 // One update frame, asynchronously on `st` (also what a graph captures); the
 // blend waits for `atlas_wait` when given.  With a query batch `qb` the
 // queries see the atlases and states as they stood before the frame: they run
-// inside the probe-ray trace launch, or first, on their own, when the state
-// step can rewrite the states they read.
+// inside the probe-ray trace and shadow-ray launches, or first, on their own,
+// when the state step can rewrite the states they read.
 hipError_t enqueue_frame_on(irf_ctx* c, const float* rotation, hipStream_t st, hipEvent_t atlas_wait,
                             const VolumeSet& vs, const FrameScratch& fs, const QueryBatch* qb = nullptr) {
   SceneGPU sc = scene_view(c);
@@ -394,22 +394,19 @@ hipError_t enqueue_frame_on(irf_ctx* c, const float* rotation, hipStream_t st, h
       launch_copy(c->saved.p + c->saved_states[v], c->vol[v].states, P, st);
     }
   }
-  // the fused batch: a share in the shadow launch (batched shadow rays only),
-  // the rest in the trace launch
-  // the shadow rays share their launch with the hit shading's indirect
-  // terms (and, in batches, a share of the queries); with no light the hit
-  // shading queries the indirect terms itself
+  // The shadow rays share their launch with the hit shading's indirect terms
+  // and, in batches (`stage`), with the tuning's share of a fused query batch;
+  // the rest of the batch runs in the trace launch.  With no light the hit
+  // shading queries the indirect terms itself.
   const bool stage = nl > 0 && c->tune.shadow_refill == 0;
-  QueryBatch q_trace = {}, q_shadow = {};
+  QueryBatch q_shadow = {};
   if (fused) {
     const int64_t ns = stage ? qb->n * c->tune.query_shadow / 1000 : 0;
-    q_trace = *qb;
+    QueryBatch q_trace = *qb;
     q_trace.n = qb->n - ns;
     q_shadow = *qb;
     q_shadow.first = qb->first + q_trace.n;
     q_shadow.n = ns;
-  }
-  if (fused) {
     ProfScope p(c, "trace_query", st);
     launch_trace_query(vs, sc, fs, c->tune.trace_blocks, q_trace, st);
   } else {
