@@ -51,8 +51,9 @@ COUNTER_FILES = {"city": os.path.join(ROOT, "profiles", "city-16x8x16-256rays_co
 # one key, since a frame runs one of them
 KERNEL_KEYS = (("k_shadow_refill", "shadow_refill"), ("k_shadow_count", "shadow_count"),
                ("k_shadow_query", "shadow_query"), ("k_shadow", "shadow"),
-               ("k_trace_count", "trace_count"), ("k_trace_query", "trace_query"), ("k_trace", "trace"), ("k_shade_terms", "shade_terms"),
-               ("k_shade_direct", "shade"), ("k_shade", "shade"), ("k_blend_mma", "blend_mma"), ("k_blend_f32", "blend_valu"),
+               ("k_trace_count", "trace_count"), ("k_trace_query", "trace_query"), ("k_trace", "trace"),
+               ("k_shade_terms", "shade_terms"), ("k_shade_direct", "shade"), ("k_shade", "shade"),
+               ("k_blend_mma", "blend_mma"), ("k_blend_f32", "blend_valu"),
                ("k_blend_backward", "blend_backward"), ("k_query_terms", "query_terms"), ("k_query", "query"),
                ("k_gather_pieces", "gather_pieces"), ("k_finish_pieces", "finish_pieces"),
                ("k_piece_offsets", "piece_offsets"), ("k_blend_norms", "blend_norms"), ("k_segments", "segments"),
@@ -752,8 +753,8 @@ def main():
 
     def fused_steps(k):
         # k frames and k queries with the same results as the serial steps:
-        # the query of frame i runs inside frame i+1's trace launch
-        # (irf_update_probes_query), the last one on its own
+        # the query of frame i runs inside frame i+1's trace and shadow-ray
+        # launches (irf_update_probes_query), the last one on its own
         nonlocal f
         ctx.update_probes(R[f])
         f += 1
@@ -763,7 +764,7 @@ def main():
         ctx.query_irradiance(pos, nrm, view, out)
 
     # ... and (the value) fused: the same frames and queries, each query
-    # answered inside the next frame's trace launch
+    # answered inside the next frame's traversal launches
     fused_steps(max(2, args.warmup))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
