@@ -163,3 +163,31 @@ def test_lights_but_no_shadow_ray(torch):
     assert np.all(rec["tri"] < 0) and np.all(rec["vis"] == 0)
     assert np.array_equal(rec["rgb"], np.broadcast_to(w.lights.sky.astype(np.float32), rec["rgb"].shape))
     ctx.close()
+
+
+def test_frame_with_no_light(torch):
+    """No directional or point light (the emissive quad and the sky light the
+    room): no shadow-ray launch, so the hit shading queries each front-face
+    hit's indirect term itself (k_shade); rays and texels against the
+    oracle."""
+    import oracle
+    from paper_2009_10796_amd import irf
+    w = S.config0()
+    z = np.zeros((0, 3), np.float32)
+    w.lights = S.Lights(z, z, z, z, w.lights.sky)
+    ctx = irf.build_workload(w)
+    osc = oracle.Scene(w.scene)
+    ov = [oracle.Volume(d) for d in w.volumes]
+    ctx.classify(w.classify_rotations)
+    oracle.classify(osc, ov, w.classify_rotations)
+    assert G.copy_states(ctx, ov, torch) <= 1
+    verdicts = []
+    for f in (1, 2):
+        vs, rep, rec_o, rec_g = G.frame(torch, ctx, osc, ov, w.lights, w.frame_rotation(f), f"edges no light frame {f}")
+        verdicts += vs
+        stats = ctx.frame_stats()
+        print(f"[edges] no light, frame {f}: {stats}", flush=True)
+        assert stats["shadow_rays"] == 0 and stats["front_hits"] > 0
+        assert np.all(rec_g["vis"] == 0)
+    G.check(verdicts)
+    ctx.close()
