@@ -57,8 +57,14 @@ def test_frame_with_no_active_probe(torch):
     stats = ctx.frame_stats()
     assert stats["active_probes"] == 0 and stats["probe_rays"] == 0 and stats["shadow_rays"] == 0
     q = w.queries
-    e = ctx.query_irradiance(*(torch.from_numpy(a).cuda() for a in (q.pos, q.nrm, q.view))).cpu().numpy()
+    qt = [torch.from_numpy(a).cuda() for a in (q.pos, q.nrm, q.view)]
+    e = ctx.query_irradiance(*qt).cpu().numpy()
     assert np.all(e == 0.0)
+    # a frame with no probe ray that answers a query batch: the launches hold
+    # only query work
+    e2 = ctx.update_probes_query(w.frame_rotation(4), *qt).cpu().numpy()
+    assert np.all(e2 == 0.0)
+    assert all(np.array_equal(x, y) for a, b in zip(before, _snapshot(ctx)) for x, y in zip(a, b))
     empty = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
     assert ctx.query_irradiance(empty, empty, empty).shape == (0, 3)
     ctx.close()
