@@ -24,6 +24,7 @@ figures.
 CSVs of one workload into the committed summary that the roofline reads.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -197,6 +198,18 @@ def summary_markdown(workload: str, paths) -> str:
     return "\n".join([*lines, f"Counters per launch (mean over the kernel's dispatches); FETCH_SIZE / WRITE_SIZE "
                       f"(KiB) scaled to bytes by the calibration copy: {d['copy_scale']}.", "", *rows, "",
                       "```json", json.dumps(d, indent=1), "```"])
+
+
+def quiet_gc() -> None:
+    """Python's garbage collector off for the timed work: a full collection
+    of this process (torch and the workloads: ~170k objects) takes ~37 ms on
+    the host, and one landing inside a timed region stalls the GPU's queue
+    for that long.  The objects so far are collected once and frozen, and no
+    automatic collection runs until the bench ends (reference counting still
+    frees everything that is not in a cycle)."""
+    gc.collect()
+    gc.freeze()
+    gc.disable()
 
 
 def binding_roofline(kernel: str, avg_us: float, counters: dict, extra: dict = None) -> dict:
@@ -690,6 +703,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.only:
+        quiet_gc()
         if args.only == "terrain":
             res = terrain_batched(irf, torch, oracle_step=not args.no_cpu_baseline, drift=not args.no_drift,
                                   tuning=json.loads(args.tuning) if args.tuning else None)
@@ -706,10 +720,11 @@ def main():
     nrm = torch.from_numpy(q.nrm).cuda()
     view = torch.from_numpy(q.view).cuda()
     out = torch.empty_like(pos)
-    R = S.rotations(w.config, 1 + 3 * max(2, args.warmup) + 6 * args.steps, start_frame=1)
+    R = S.rotations(w.config, 1 + 4 * max(2, args.warmup) + 7 * args.steps, start_frame=1)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
     print(f"[bench] setup {setup_s:.1f}s, {w.scene.n_triangles} triangles, {q.n} queries", file=sys.stderr, flush=True)
+    quiet_gc()
 
     f = 0
     for _ in range(max(1, args.warmup)):
@@ -739,6 +754,29 @@ def main():
     t1 = time.perf_counter()
     graph.close()
     graph_ms = 1e3 * (t1 - t0) / args.steps
+
+    # the fused steps (below) with the frame that answers the queries
+    # captured as a graph (irf_graph_capture_query)
+    with torch.cuda.stream(s):
+        gq = ctx.capture_frame_query(pos, nrm, view, out, s)
+
+        def graph_fused_steps(k):
+            nonlocal f
+            ctx.update_probes(R[f])
+            f += 1
+            for _ in range(k - 1):
+                gq.launch(R[f])
+                f += 1
+            ctx.query_irradiance(pos, nrm, view, out)
+
+        graph_fused_steps(max(2, args.warmup))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(s):
+        graph_fused_steps(args.steps)
+    torch.cuda.synchronize()
+    graph_fused_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    gq.close()
 
     # the same steps with eager launches, no instrumentation: serial (each
     # frame, then its query) ...
@@ -772,7 +810,7 @@ def main():
     torch.cuda.synchronize()
     ms_step = 1e3 * (time.perf_counter() - t0) / args.steps
     print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step (serial {serial_ms:.3f}, graph replay "
-          f"{graph_ms:.3f})", file=sys.stderr, flush=True)
+          f"{graph_ms:.3f}, fused graph replay {graph_fused_ms:.3f})", file=sys.stderr, flush=True)
 
     # per-kernel times: separate passes with the library's kernel timing,
     # serial (the update's and the query's own kernels) and fused
@@ -865,6 +903,7 @@ def main():
                              "launches"},
         "serial_ms_per_step": round(serial_ms, 4),
         "graph_ms_per_step": round(graph_ms, 4),
+        "graph_fused_ms_per_step": round(graph_fused_ms, 4),
         "update_ms": round(update_ms, 4),
         "query_ms": round(query_ms, 4),
         "rays": {"primary": int(prim), "shadow": int(shad), "total": int(prim + shad)},

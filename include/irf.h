@@ -355,10 +355,19 @@ irf_status irf_get_tuning(const irf_ctx* ctx, irf_tuning* tuning);
    them; irf_graph_launch replays it with a new rotation and the context's
    current lights (the frame's parameters are the argument block of its
    frame-start node, updated before each launch).  A graph stays valid while the scene,
-   volumes, bound buffers, light count and tuning are unchanged; otherwise
-   irf_graph_launch returns IRF_E_STATE and the frame must be captured again. */
+   volumes, bound buffers, light count, dynamic objects and tuning are
+   unchanged; otherwise irf_graph_launch returns IRF_E_STATE and the frame
+   must be captured again. */
 typedef struct irf_graph irf_graph;
 irf_status irf_graph_capture(irf_ctx* ctx, void* stream, irf_graph** out);
+/* The frame of irf_update_probes_query captured the same way: each
+   irf_graph_launch of it is an update frame that also answers the n queries
+   at the device arrays given here (pos, nrm, view, out_rgb: [n][3] float,
+   fixed at capture; the caller may rewrite their contents between launches)
+   against the atlases and states the previous frame left.  Same errors as
+   irf_graph_capture, and IRF_E_INVALID for n < 0 or (n > 0) a NULL array. */
+irf_status irf_graph_capture_query(irf_ctx* ctx, void* stream, const float* pos, const float* nrm,
+                                   const float* view, int64_t n, float* out_rgb, irf_graph** out);
 irf_status irf_graph_launch(irf_ctx* ctx, irf_graph* graph, const float* rotation, void* stream);
 void irf_graph_destroy(irf_graph* graph);
 

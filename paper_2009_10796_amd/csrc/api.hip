@@ -517,6 +517,9 @@ uint64_t frame_signature(const irf_ctx* c) {
   mix(&fs, sizeof(fs));
   mix(&sc, sizeof(sc));
   mix(&c->tune, sizeof(c->tune));
+  // dynamic objects decide where a captured query batch runs
+  const ObjectBoxes ob = boxes_view(c);
+  mix(&ob, sizeof(ob));
   // a differentiable frame also writes the saved inputs
   const void* sv = c->diff ? (const void*)c->saved.p : nullptr;
   mix(&sv, sizeof(sv));
@@ -1171,7 +1174,8 @@ irf_status irf_get_tuning(const irf_ctx* c, irf_tuning* t) {
   return IRF_OK;
 }
 
-irf_status irf_graph_capture(irf_ctx* c, void* stream, irf_graph** out) {
+// The frame (with a query batch when qb is given) captured on `stream`.
+irf_status capture_frame(irf_ctx* c, void* stream, const QueryBatch* qb, irf_graph** out) {
   if (!c || !out) return fail(IRF_E_INVALID, "NULL argument");
   *out = nullptr;
   if (!stream) return fail(IRF_E_INVALID, "capture needs a stream other than the null stream");
@@ -1189,7 +1193,7 @@ irf_status irf_graph_capture(irf_ctx* c, void* stream, irf_graph** out) {
     return fail(IRF_E_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
   }
   // the capture is always ended, and the graph destroyed on any failure
-  const hipError_t qe = enqueue_frame(c, identity, st);
+  const hipError_t qe = enqueue_frame_on(c, identity, st, nullptr, volume_view(c), scratch_view(c), qb);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(st, &graph);
   c->prof = prof;
@@ -1245,6 +1249,20 @@ irf_status irf_graph_capture(irf_ctx* c, void* stream, irf_graph** out) {
   g->signature = frame_signature(c);
   *out = g;
   return IRF_OK;
+}
+
+irf_status irf_graph_capture(irf_ctx* c, void* stream, irf_graph** out) {
+  return capture_frame(c, stream, nullptr, out);
+}
+
+irf_status irf_graph_capture_query(irf_ctx* c, void* stream, const float* pos, const float* nrm, const float* view,
+                                   int64_t n, float* out_rgb, irf_graph** out) {
+  if (!c || !out) return fail(IRF_E_INVALID, "NULL argument");
+  *out = nullptr;
+  if (n < 0) return fail(IRF_E_INVALID, "n < 0");
+  if (n > 0 && (!pos || !nrm || !view || !out_rgb)) return fail(IRF_E_INVALID, "NULL array");
+  const QueryBatch qb = {pos, nrm, view, out_rgb, 0, n};
+  return capture_frame(c, stream, &qb, out);
 }
 
 irf_status irf_graph_launch(irf_ctx* c, irf_graph* g, const float* rotation, void* stream) {

@@ -94,6 +94,7 @@ SIGNATURES = {
     "irf_set_tuning": (C.c_int, [_vp, C.POINTER(Tuning)]),
     "irf_get_tuning": (C.c_int, [_vp, C.POINTER(Tuning)]),
     "irf_graph_capture": (C.c_int, [_vp, _vp, C.POINTER(_vp)]),
+    "irf_graph_capture_query": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _vp, C.POINTER(_vp)]),
     "irf_graph_launch": (C.c_int, [_vp, _vp, _vp, _vp]),
     "irf_graph_destroy": (None, [_vp]),
     "irf_optimize_probes": (C.c_int, [_vp, _vp, _i32, C.c_float, _vp]),
@@ -423,6 +424,20 @@ class Context:
         g = C.c_void_p()
         _check(load().irf_graph_capture(self.handle, C.c_void_p(st.cuda_stream), C.byref(g)))
         return FrameGraph(self, g, st)
+
+    def capture_frame_query(self, pos, nrm, view, out, stream=None) -> "FrameGraph":
+        """Captures the frame of update_probes_query: each launch also writes
+        into `out` the queries at pos/nrm/view (tensors fixed at capture, their
+        contents may change) against the atlases the previous frame left."""
+        n, out = self._query_args(pos, nrm, view, out)
+        st = stream or self.torch.cuda.current_stream()
+        g = C.c_void_p()
+        _check(load().irf_graph_capture_query(self.handle, C.c_void_p(st.cuda_stream), C.c_void_p(pos.data_ptr()),
+                                              C.c_void_p(nrm.data_ptr()), C.c_void_p(view.data_ptr()), n,
+                                              C.c_void_p(out.data_ptr()), C.byref(g)))
+        graph = FrameGraph(self, g, st)
+        graph.tensors = (pos, nrm, view, out)   # kept alive while the graph is
+        return graph
 
     def profile(self, enable: bool = True) -> None:
         _check(load().irf_profile_enable(self.handle, int(enable)))

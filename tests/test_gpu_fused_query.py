@@ -142,3 +142,47 @@ def test_autotuner_on_fused_frames_keeps_results(torch):
         assert torch.equal(ea, eb) and _same_atlases(A, B), f
     A.close()
     B.close()
+
+
+@pytest.mark.parametrize("dynamic", [False, True], ids=["static city", "dynamic building"])
+def test_graph_replayed_fused_frames_match_eager(torch, dynamic):
+    """irf_graph_capture_query: replays (with eager work and synchronizations
+    between them) give the queries and atlases of the eager fused frames, bit
+    for bit; with a dynamic building the captured frame runs the queries
+    first, as its own node."""
+    from paper_2009_10796_amd import irf
+    if dynamic:
+        w, scene = city_with_dynamic_building()
+        w.scene = scene
+        w.volumes = [S.VolumeDesc(origin=(3.5, 5.5, 4.5), spacing=(1.0, 1.0, 1.0), counts=(10, 4, 6),
+                                  rays_per_probe=64)]
+        w.queries = S.config1(width=320, height=180).queries
+    else:
+        w = S.config1(width=320, height=180)
+    pos, nrm, view = _tensors(torch, w.queries)
+    A, B = irf.build_workload(w), irf.build_workload(w)
+    for c in (A, B):
+        c.classify(w.classify_rotations)
+        c.update_probes(w.frame_rotation(1))
+    torch.cuda.synchronize()
+    ea, eb = torch.empty_like(pos), torch.empty_like(pos)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = B.capture_frame_query(pos, nrm, view, eb, s)
+    for f in (2, 3, 4, 5):
+        A.update_probes_query(w.frame_rotation(f), pos, nrm, view, ea)
+        eb.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g.launch(w.frame_rotation(f))
+        torch.cuda.synchronize()
+        # eager work on the graph's context between replays
+        extra = B.query_irradiance(pos, nrm, view)
+        torch.cuda.synchronize()
+        q_same, a_same = torch.equal(ea, eb), _same_atlases(A, B)
+        print(f"[fused graph] dynamic={dynamic} frame {f}: queries equal {q_same}, frame equal {a_same}", flush=True)
+        assert q_same and a_same, f
+        assert torch.isfinite(extra).all()
+    g.close()
+    A.close()
+    B.close()
