@@ -26,6 +26,25 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(irf.SIGNATURES), set(names) ^ set(irf.SIGNATURES)
 
 
+def test_header_is_plain_c_and_links(tmp_path):
+    """The header compiles as C99 with every declaration used, and a C
+    program links against the library (no GPU needed: nothing is called)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    names = _declared()
+    src = tmp_path / "use.c"
+    src.write_text('#include "irf.h"\n#include <stdio.h>\nint main(void) {\n'
+                   + "".join(f'  printf("%p\\n", (void*)&{n});\n' for n in names) + "  return 0;\n}\n")
+    lib = irf.LIB_PATH
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", f"-I{os.path.dirname(HEADER)}", str(src), "-o",
+                        str(tmp_path / "use"), lib, f"-Wl,-rpath,{os.path.dirname(lib)}"],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def test_status_strings_and_version():
     lib = irf.load()
     assert lib.irf_status_str(0) == b"IRF_OK"
