@@ -6,10 +6,11 @@ previous frame left), and its frame the plain frame: checked on the city
 (a 480x270 G-buffer; the queries split between the probe-ray trace and
 the shadow-ray launches in several proportions, on persistent and full
 grids, and all in the trace launch when the shadow rays use lane refill),
-on the room, on four cascades (also past 4,096 probes), and on the city with a dynamic
-building, whose state step can put probes to sleep before the queries would
-see them (there the queries run first, as their own launch), over frames
-that move the building."""
+on the room, on four cascades (also past 4,096 probes), on the city with a
+dynamic building, whose state step can put probes to sleep before the
+queries would see them (there the queries run first, as their own launch),
+over frames that move the building, after autotuning, and as a captured
+graph (irf_graph_capture_query) replayed against the eager frames."""
 import numpy as np
 import pytest
 
