@@ -27,8 +27,10 @@ SHADOW = ("shadow", "shadow_refill", "shadow_query")
 # blend's grid is tuned again after its tile shape, since the best grid
 # depends on the shape.  query_shadow (the query batch's share in the shadow
 # launch) is timed over both traversals and tuned only on frames that answer
-# queries.
-KNOBS = (("trace_blocks", TRACE), ("shadow_refill", SHADOW), ("query_shadow", TRACE + SHADOW),
+# queries.  shadow_refill is timed over both traversals too: with lane
+# refill the shadow launch takes no share of a query batch, so the whole
+# batch moves into the trace launch.
+KNOBS = (("trace_blocks", TRACE), ("shadow_refill", TRACE + SHADOW), ("query_shadow", TRACE + SHADOW),
          ("shadow_blocks", SHADOW), ("shade_blocks", ("shade",)), ("blend_blocks", ("blend_mma",)),
          ("blend_rsplit", ("blend_mma",)), ("blend_blocks", ("blend_mma",)))
 
