@@ -333,8 +333,9 @@ class Context:
 
     def update_probes_query(self, rotation, pos, nrm, view, out=None):
         """One update frame that also answers the queries against the atlases
-        the previous frame left (inside the frame's trace launch); returns
-        `out`, equal to query_irradiance() called before update_probes()."""
+        the previous frame left (inside the frame's probe-ray and shadow-ray
+        launches, split by the tuning's query_shadow); returns `out`, equal
+        to query_irradiance() called before update_probes()."""
         n, out = self._query_args(pos, nrm, view, out)
         R = _np(rotation, np.float32).reshape(9)
         _check(load().irf_update_probes_query(self.handle, _ptr(R), C.c_void_p(pos.data_ptr()),
