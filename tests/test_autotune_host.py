@@ -86,3 +86,23 @@ def test_refill_wins_where_it_is_faster_overall():
     chosen = autotune.autotune(ctx, [None] * 4, frames_per_candidate=2, cu=256, step=ctx.step)
     assert chosen["shadow_refill"] in (4, 8, 16, 32), chosen
     assert "query_shadow" not in chosen      # plain frames do not tune the query split
+
+
+def test_saved_tuning_applies_to_another_context(tmp_path):
+    ctx = ModelCtx(queries=True)
+    chosen = autotune.autotune(ctx, [None] * 4, frames_per_candidate=1, cu=256, step=ctx.step)
+    path = tmp_path / "sub" / "tuning.json"
+    autotune.save(chosen, str(path), "model-city", ctx.tuning_report)
+    loaded = autotune.load(str(path))
+    assert loaded == chosen and all(isinstance(v, int) for v in loaded.values())
+    other = ModelCtx(queries=True)
+    autotune.apply(other, loaded)
+    assert {k: other.t[k] for k in loaded} == chosen
+
+
+def test_knob_candidates():
+    assert autotune.candidates(256, "shadow_refill") == [0, 4, 8, 16, 32]
+    assert autotune.candidates(256, "blend_rsplit") == [4, 2, 1]
+    assert autotune.candidates(256, "query_shadow") == [0, 250, 500, 750]
+    # grids: 0 (one workgroup per work unit) and multiples of the compute units
+    assert autotune.candidates(256, "trace_blocks") == [0, 256, 512, 1024, 2048, 4096]
